@@ -1,0 +1,545 @@
+"""Oracle UniHENN network: the layer algorithms of Sections IV and VI written
+out step by step, over two interchangeable evaluators:
+
+  SlotEval -- plaintext slot vectors in FP64 (Rot = cyclic left shift,
+              Mul(P) = elementwise product).  Pins the layout and planning
+              against a direct FP64 CNN without any encryption.
+  CkksEval -- the CPU CKKS oracle (oracle.ckks).
+
+TEST INFRASTRUCTURE ONLY (tests, smoke check, benchmark CPU-baseline leg).
+
+Every multiplicative stage has one normal form,
+    out = Rescale( sum_t Rot(X_t, r_t) * Encode(w_t * mask_t) )  [+ bias],
+where a "multiply by a mask, then rotate" in the paper is computed as
+"rotate, then multiply by the mask moved to the destination slots" (same
+message, same rotation count).  Rotations by 0 are the identity.
+
+Layout of a feature map (Section IV-B, VI-A): the value (c, y, x) of packed
+sample b sits at slot  b*stride + ch_off[c] + I*(x + W_img*y),  with I the
+interval (product of conv strides and pooling kernels so far) and W_img the
+width of the original input, which every layer keeps as its row pitch.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+# --------------------------------------------------------------------------
+# layout and planning
+# --------------------------------------------------------------------------
+@dataclass
+class Layout:
+    kind: str                 # "map" (C,H,W feature map) or "vec" (flat vector)
+    C: int = 1
+    H: int = 1
+    W: int = 1
+    I: int = 1                # interval
+    W_img: int = 1            # row pitch
+    ch_ct: list = field(default_factory=list)   # ciphertext index of channel c
+    ch_off: list = field(default_factory=list)  # slot offset of channel c
+    prev: str = "input"       # last non-square layer: input / conv / avgpool
+    pending: float = 1.0      # deferred average-pooling factor (Section IV-C)
+    length: int = 0           # vector length for kind == "vec"
+
+
+class PlanError(ValueError):
+    pass
+
+
+def kernel_hw(lay) -> tuple[int, int, int, int]:
+    """(K_h, K_w, S_h, S_w): a 1D convolution has a 1 x K kernel."""
+    if lay.get("dims") == 1:
+        return 1, lay["k"], 1, lay["s"]
+    return lay["k"], lay["k"], lay["s"], lay["s"]
+
+
+def input_layout(inp: dict) -> Layout:
+    C, H, W = inp["c"], inp["h"], inp["w"]
+    # one ciphertext per sample, channels row-major at offset c*H*W (Sec. III-A)
+    return Layout("map", C, H, W, 1, W, [0] * C, [c * H * W for c in range(C)], "input", 1.0)
+
+
+def footprint(inp: dict, layers) -> int:
+    """Slots each packed sample needs (Section VI): the largest extent, over
+    all layers, of the slots that hold the sample's valid values or that a
+    valid output reads; the flatten output C*H*W; the FC width
+    DAT_out * ceil(DAT_in / DAT_out)."""
+    L = input_layout(inp)
+    need = inp["c"] * inp["h"] * inp["w"]
+    for lay in layers:
+        k = lay["kind"]
+        if k == "conv":
+            Kh, K, Sh, S = kernel_hw(lay)
+            if not K >= S >= 1:
+                raise PlanError("Theorem 1 needs K >= S >= 1")
+            Ho, Wo = (L.H - Kh) // Sh + 1, (L.W - K) // S + 1
+            # last slot read by a valid output
+            read = max(L.ch_off) + L.I * ((S * (Wo - 1) + K - 1) + L.W_img * (Sh * (Ho - 1) + Kh - 1)) + 1
+            need = max(need, read)
+            I = L.I * S
+            L = Layout("map", lay["ch_out"], Ho, Wo, I, L.W_img, list(range(lay["ch_out"])),
+                       [0] * lay["ch_out"], "conv", 1.0)
+            need = max(need, I * ((Wo - 1) + L.W_img * (Ho - 1)) + 1)
+        elif k == "avgpool":
+            c = lay["c"]
+            read = max(L.ch_off) + L.I * ((c * (L.W // c) - 1) + L.W_img * (c * (L.H // c) - 1)) + 1
+            need = max(need, read)
+            L = Layout("map", L.C, L.H // c, L.W // c, L.I * c, L.W_img, L.ch_ct, L.ch_off, "avgpool", 1.0)
+        elif k == "flatten":
+            need = max(need, L.C * L.H * L.W)
+            L = Layout("vec", length=L.C * L.H * L.W)
+        elif k == "fc":
+            D = lay["dout"]
+            need = max(need, D * math.ceil(lay["din"] / D))
+            L = Layout("vec", length=D)
+    return need
+
+
+def check_packing(inp: dict, layers, n_slots: int, samples: int, stride: int) -> int:
+    fp = footprint(inp, layers)
+    if samples == 1:
+        if fp > n_slots:
+            raise PlanError("model does not fit the slots")
+        return n_slots
+    if stride < fp or samples * stride > n_slots:
+        raise PlanError(f"stride {stride} < footprint {fp} or {samples} samples exceed {n_slots} slots")
+    return stride
+
+
+def shapes(inp: dict, layers):
+    """(C,H,W) or (len,) after each layer."""
+    C, H, W = inp["c"], inp["h"], inp["w"]
+    out = []
+    flat = None
+    for lay in layers:
+        k = lay["kind"]
+        if k == "conv":
+            Kh, K, Sh, S = kernel_hw(lay)
+            C, H, W = lay["ch_out"], (H - Kh) // Sh + 1, (W - K) // S + 1
+        elif k == "avgpool":
+            H, W = H // lay["c"], W // lay["c"]
+        elif k == "flatten":
+            flat = C * H * W
+        elif k == "fc":
+            flat = lay["dout"]
+        out.append((C, H, W) if flat is None else (flat,))
+    return out
+
+
+def network_depth(inp: dict, layers) -> int:
+    d = 0
+    prev, I, pending = "input", 1, 1.0
+    H = inp["h"]
+    for lay in layers:
+        k = lay["kind"]
+        if k == "conv":
+            d += 1
+            Kh, K, Sh, S = kernel_hw(lay)
+            prev, I, pending = "conv", I * S, 1.0
+            H = (H - Kh) // Sh + 1
+        elif k == "square":
+            d += 1
+            pending *= pending
+        elif k == "avgpool":
+            prev, I = "avgpool", I * lay["c"]
+            pending /= lay["c"] ** 2
+            H = H // lay["c"]
+        elif k == "flatten":
+            d += int(prev == "avgpool" or I > 1 or pending != 1.0)
+            d += int(H > 1)
+        elif k == "fc":
+            d += 1
+    return d
+
+
+# --------------------------------------------------------------------------
+# FP64 reference CNN (valid convolutions, no padding)
+# --------------------------------------------------------------------------
+def cnn_fp64(x: np.ndarray, layers, params) -> np.ndarray:
+    """Direct FP64 forward pass of one input x of shape (C, H, W)."""
+    a = np.asarray(x, dtype=np.float64)
+    for lay, p in zip(layers, params):
+        k = lay["kind"]
+        if k == "conv":
+            w, b = p
+            Kh, K, Sh, S = kernel_hw(lay)
+            C, H, W = a.shape
+            Ho, Wo = (H - Kh) // Sh + 1, (W - K) // S + 1
+            out = np.zeros((w.shape[0], Ho, Wo))
+            for o in range(w.shape[0]):
+                for y in range(Ho):
+                    for xx in range(Wo):
+                        out[o, y, xx] = np.sum(w[o] * a[:, Sh * y:Sh * y + Kh, S * xx:S * xx + K]) + b[o]
+            a = out
+        elif k == "square":
+            a = a * a
+        elif k == "avgpool":
+            c = lay["c"]
+            C, H, W = a.shape
+            Ho, Wo = H // c, W // c
+            a = a[:, :Ho * c, :Wo * c].reshape(C, Ho, c, Wo, c).mean(axis=(2, 4))
+        elif k == "flatten":
+            a = a.reshape(-1)
+        elif k == "fc":
+            w, b = p
+            a = w @ a.reshape(-1) + b
+    return a
+
+
+# --------------------------------------------------------------------------
+# evaluators
+# --------------------------------------------------------------------------
+class OpCount:
+    def __init__(self):
+        self.rot = 0
+        self.mac = 0
+        self.rescale = 0
+        self.relin = 0
+
+    def as_dict(self):
+        return {"rot": self.rot, "mac": self.mac, "rescale": self.rescale, "relin": self.relin}
+
+
+class SlotEval:
+    """FP64 slot vectors; masks and weights applied exactly, no rescale."""
+
+    def __init__(self, n_slots: int):
+        self.n_slots = n_slots
+        self.count = OpCount()
+
+    def rot(self, x, r):
+        if r % self.n_slots == 0:
+            return x
+        self.count.rot += 1
+        return np.roll(x, -r)
+
+    def mac_rescale(self, srcs, terms_per_out):
+        """terms_per_out[o] = list of (src_index, weight, mask_vector)."""
+        outs = []
+        for terms in terms_per_out:
+            acc = np.zeros(self.n_slots)
+            for t, w, m in terms:
+                acc = acc + srcs[t] * (w * m)
+                self.count.mac += 1
+            self.count.rescale += 1
+            outs.append(acc)
+        return outs
+
+    def add_plain(self, x, vec):
+        return x + vec
+
+    def add(self, a, b):
+        return a + b
+
+    def square(self, x):
+        self.count.relin += 1
+        self.count.rescale += 1
+        return x * x
+
+
+class CkksEval:
+    """The CPU CKKS oracle.  keys: {r mod N/2: loaded key}, rlk: loaded key."""
+
+    def __init__(self, ck, keys: dict, rlk):
+        self.ck = ck
+        self.n_slots = ck.slots
+        self.keys = keys
+        self.rlk = rlk
+        self.count = OpCount()
+
+    def rot(self, x, r):
+        r = r % self.n_slots
+        if r == 0:
+            return x
+        if r not in self.keys:
+            raise KeyError(f"no rotation key for {r}")
+        self.count.rot += 1
+        return self.ck.rotate(x, r, self.keys[r])
+
+    def mac_rescale(self, srcs, terms_per_out):
+        ck = self.ck
+        nl = srcs[0].nl
+        scale = srcs[0].scale
+        for s in srcs:
+            if s.nl != nl or s.scale != scale:
+                raise ValueError("MAC terms must share level and scale")
+        outs = []
+        chunk = 4
+        for o0 in range(0, len(terms_per_out), chunk):
+            block = terms_per_out[o0:o0 + chunk]
+            pts = []
+            for terms in block:
+                row = [None] * len(srcs)
+                # group this output's terms by mask so each mask is transformed once
+                bymask = {}
+                for t, w, m in terms:
+                    bymask.setdefault(id(m), (m, []))[1].append((t, w))
+                for _, (m, tw) in bymask.items():
+                    enc = ck.encode_scaled(m, [w for _, w in tw], ck.delta, nl)
+                    for (t, _), p in zip(tw, enc):
+                        if row[t] is not None:
+                            raise ValueError("duplicate term")
+                        row[t] = p
+                self.count.mac += len(terms)
+                pts.append(row)
+            accs = ck.mac_matrix(srcs, pts)
+            for a in accs:
+                from oracle.ckks import Ciphertext
+                self.count.rescale += 1
+                outs.append(ck.rescale(Ciphertext(a, scale * ck.delta)))
+        return outs
+
+    def add_plain(self, x, vec):
+        pt = self.ck.encode(vec, x.scale, x.nl)
+        return self.ck.add_plain(x, pt)
+
+    def add(self, a, b):
+        return self.ck.add(a, b)
+
+    def square(self, x):
+        self.count.relin += 1
+        self.count.rescale += 1
+        return self.ck.rescale(self.ck.square_relin(x, self.rlk))
+
+
+# --------------------------------------------------------------------------
+# the layers
+# --------------------------------------------------------------------------
+class Net:
+    """Plan + evaluation of a UniHENN network on one ciphertext of packed
+    samples (or one FP64 slot vector)."""
+
+    def __init__(self, inp: dict, layers, params, n_slots: int, samples: int = 1, stride: int = 0):
+        self.inp = inp
+        self.layers = layers
+        self.params = params
+        self.n_slots = n_slots
+        self.samples = samples
+        self.stride = check_packing(inp, layers, n_slots, samples, stride if samples > 1 else n_slots)
+        self.depth = network_depth(inp, layers)
+
+    # slot vector helper: ones at the given in-sample positions of every sample
+    def _mask(self, positions) -> np.ndarray:
+        m = np.zeros(self.n_slots)
+        pos = np.asarray(sorted(set(int(p) for p in positions)), dtype=np.int64)
+        for b in range(self.samples):
+            m[b * self.stride + pos] = 1.0
+        return m
+
+    def _vec(self, values_at: dict) -> np.ndarray:
+        v = np.zeros(self.n_slots)
+        for b in range(self.samples):
+            for p, val in values_at.items():
+                v[b * self.stride + p] = val
+        return v
+
+    def input_vector(self, xs: np.ndarray) -> np.ndarray:
+        """Client-side packing (Section III-B): sample b's row-major (C,H,W)
+        data starts at slot b*stride."""
+        v = np.zeros(self.n_slots)
+        for b, x in enumerate(xs):
+            flat = np.asarray(x, dtype=np.float64).reshape(-1)
+            v[b * self.stride: b * self.stride + flat.size] = flat
+        return v
+
+    def rotation_set(self) -> list[int]:
+        """Distinct non-zero rotation amounts (mod N/2) the evaluation uses."""
+        rec = _RotRecorder(self.n_slots)
+        self.run(rec, [np.zeros(self.n_slots)])
+        return sorted(rec.seen)
+
+    def run(self, ev, cts):
+        L = input_layout(self.inp)
+        xs = list(cts)
+        for lay, p in zip(self.layers, self.params):
+            k = lay["kind"]
+            if k == "conv":
+                xs, L = self._conv(ev, xs, L, lay, p)
+            elif k == "square":
+                xs = [ev.square(x) for x in xs]
+                L.pending = L.pending * L.pending
+            elif k == "avgpool":
+                xs, L = self._avgpool(ev, xs, L, lay)
+            elif k == "flatten":
+                xs, L = self._flatten(ev, xs, L)
+            elif k == "fc":
+                xs, L = self._fc(ev, xs, L, lay, p)
+            else:
+                raise PlanError(k)
+        self.out_layout = L
+        return xs
+
+    # Algorithm 1 ----------------------------------------------------------
+    def _conv(self, ev, xs, L, lay, p):
+        w, b = p
+        Kh, K, Sh, S = kernel_hw(lay)
+        ci, co = lay["ch_in"], lay["ch_out"]
+        if ci != L.C:
+            raise PlanError("channel mismatch")
+        if not K >= S >= 1:
+            raise PlanError("Theorem 1 needs K >= S >= 1")
+        Ho, Wo = (L.H - Kh) // Sh + 1, (L.W - K) // S + 1
+        I_out = L.I * S
+        # first loop: C_rot(i,j,k) = Rot(C_in(i), I_in (k + W_img j)) (+ channel offset)
+        rots, src_index = [], {}
+        for i in range(ci):
+            for j in range(Kh):
+                for kk in range(K):
+                    key = (L.ch_ct[i], L.ch_off[i] + L.I * (kk + L.W_img * j))
+                    if key not in src_index:
+                        src_index[key] = len(rots)
+                        rots.append(ev.rot(xs[key[0]], key[1]))
+        # structured kernel vector: the weight on the valid output slots
+        m_out = self._mask([I_out * (x + L.W_img * y) for y in range(Ho) for x in range(Wo)])
+        wp = w * L.pending
+        terms = []
+        for o in range(co):
+            t = []
+            for i in range(ci):
+                for j in range(Kh):
+                    for kk in range(K):
+                        key = (L.ch_ct[i], L.ch_off[i] + L.I * (kk + L.W_img * j))
+                        t.append((src_index[key], float(wp[o, i, j, kk]), m_out))
+            terms.append(t)
+        outs = ev.mac_rescale(rots, terms)
+        outs = [ev.add_plain(outs[o], float(b[o]) * m_out) for o in range(co)]
+        L2 = Layout("map", co, Ho, Wo, I_out, L.W_img, list(range(co)), [0] * co, "conv", 1.0)
+        return outs, L2
+
+    # Section IV-C -----------------------------------------------------------
+    def _avgpool(self, ev, xs, L, lay):
+        c = lay["c"]
+        amounts = [L.I * (dx + L.W_img * dy) for dy in range(c) for dx in range(c)]
+        outs = []
+        for x in xs:
+            acc = None
+            for r in amounts:
+                t = ev.rot(x, r)
+                acc = t if acc is None else ev.add(acc, t)
+            outs.append(acc)
+        L2 = Layout("map", L.C, L.H // c, L.W // c, L.I * c, L.W_img, L.ch_ct, L.ch_off, "avgpool",
+                    L.pending / (c * c))
+        return outs, L2
+
+    # Section IV-E -----------------------------------------------------------
+    def _flatten(self, ev, xs, L):
+        if len(set(L.ch_ct)) != L.C or any(L.ch_off):
+            raise PlanError("flatten expects one ciphertext per channel")
+        S, Wi, Hi, Wimg = L.I, L.W, L.H, L.W_img
+        ys = list(xs)
+        # step A: remove the row interval / invalid data
+        if L.prev == "avgpool":
+            # term x: Rot(X, x(S-1)) * (pending at slot S W_img y + x)
+            rots_all = [[ev.rot(X, x * (S - 1)) for x in range(Wi)] for X in ys]
+            masks = [self._mask([S * Wimg * y + x for y in range(Hi)]) for x in range(Wi)]
+            ys = []
+            for R in rots_all:
+                ys.extend(ev.mac_rescale(R, [[(x, L.pending, masks[x]) for x in range(Wi)]]))
+        elif S > 1:
+            G = math.ceil(Wi / S)
+            masks = [self._mask([S * Wimg * y + g * S + m for y in range(Hi) for m in range(S) if g * S + m < Wi])
+                     for g in range(G)]
+            out = []
+            for X in ys:
+                T = None
+                for m in range(S):
+                    t = ev.rot(X, m * (S - 1))
+                    T = t if T is None else ev.add(T, t)
+                R = [ev.rot(T, g * S * (S - 1)) for g in range(G)]
+                out.extend(ev.mac_rescale(R, [[(g, L.pending, masks[g]) for g in range(G)]]))
+            ys = out
+        elif L.pending != 1.0:
+            m = self._mask([Wimg * y + x for y in range(Hi) for x in range(Wi)])
+            ys = [ev.mac_rescale([X], [[(0, L.pending, m)]])[0] for X in ys]
+        # now (y, x) sits at S W_img y + x
+        # step B: remove the column interval
+        if Hi > 1:
+            masks = [self._mask([y * Wi + x for x in range(Wi)]) for y in range(Hi)]
+            out = []
+            for X in ys:
+                R = [ev.rot(X, y * (Wimg * S - Wi)) for y in range(Hi)]
+                out.extend(ev.mac_rescale(R, [[(y, 1.0, masks[y]) for y in range(Hi)]]))
+            ys = out
+        # step C: pack channel o at o * H * W (right rotation)
+        acc = None
+        for o, X in enumerate(ys):
+            t = ev.rot(X, -o * Wi * Hi)
+            acc = t if acc is None else ev.add(acc, t)
+        return [acc], Layout("vec", length=L.C * Hi * Wi)
+
+    # Algorithm 2 -------------------------------------------------------------
+    def _fc(self, ev, xs, L, lay, p):
+        w, b = p
+        din, D = lay["din"], lay["dout"]
+        if L.kind != "vec" or L.length != din:
+            raise PlanError("FC input size mismatch")
+        wp = w * L.pending
+        Wvec = D * math.ceil(din / D)
+        X = xs[0]
+        srcs, terms = [], []
+        for o in range(D):
+            mrot = np.zeros(Wvec)
+            for q in range(Wvec):
+                col = (q + o) % Wvec
+                mrot[q] = wp[q % D, col] if col < din else 0.0
+            v1 = self._vec({q: mrot[q] for q in range(Wvec - o)})
+            srcs.append(ev.rot(X, o))
+            terms.append((len(srcs) - 1, 1.0, v1))
+            if o >= 1:
+                v2 = self._vec({q: mrot[q] for q in range(Wvec - o, Wvec)})
+                srcs.append(ev.rot(X, o - Wvec))
+                terms.append((len(srcs) - 1, 1.0, v2))
+        csum = ev.mac_rescale(srcs, [terms])[0]
+        acc = None
+        for i in range(math.ceil(din / D)):
+            t = ev.rot(csum, i * D)
+            acc = t if acc is None else ev.add(acc, t)
+        acc = ev.add_plain(acc, self._vec({q: float(b[q]) for q in range(D)}))
+        return [acc], Layout("vec", length=D)
+
+    # read-out -----------------------------------------------------------------
+    def output_positions(self) -> list[list[int]]:
+        """Per sample, the slots of the network output in FP64-CNN order."""
+        L = self.out_layout
+        res = []
+        for b in range(self.samples):
+            base = b * self.stride
+            if L.kind == "vec":
+                res.append([base + q for q in range(L.length)])
+            else:
+                pos = []
+                for c in range(L.C):
+                    for y in range(L.H):
+                        for x in range(L.W):
+                            pos.append((c, base + L.ch_off[c] + L.I * (x + L.W_img * y)))
+                res.append(pos)
+        return res
+
+
+class _RotRecorder(SlotEval):
+    def __init__(self, n_slots):
+        super().__init__(n_slots)
+        self.seen = set()
+
+    def rot(self, x, r):
+        r = r % self.n_slots
+        if r:
+            self.seen.add(r)
+        return super().rot(x, r)
+
+
+def read_outputs(net: Net, values_per_ct: list) -> np.ndarray:
+    """Gather network outputs from decoded slot vectors (one per output
+    ciphertext) into [samples][...] FP64-CNN order."""
+    L = net.out_layout
+    pos = net.output_positions()
+    out = []
+    for b in range(net.samples):
+        if L.kind == "vec":
+            out.append(np.array([values_per_ct[0][p] for p in pos[b]]))
+        else:
+            out.append(np.array([values_per_ct[L.ch_ct[c]][p] for c, p in pos[b]]))
+    return np.array(out)

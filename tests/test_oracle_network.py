@@ -1,0 +1,157 @@
+"""Oracle network: layer algorithms (Algorithms 1 and 2, average pooling,
+flatten) checked against a direct FP64 CNN, without encryption (slot
+simulation) and with encryption (CPU CKKS oracle).  No GPU."""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle.network import (Net, PlanError, SlotEval, check_packing, cnn_fp64, footprint, network_depth,
+                            read_outputs, shapes)
+from oracle.run import OracleSession, build_net, decrypt_outputs, reference_outputs, run_encrypted
+
+
+def _slot_run(name, samples=None, stride=None):
+    cfg = W.config(name)
+    n_slots = 2 ** (cfg["log_n"] - 1)
+    params = W.gen_params(cfg["layers"])
+    S = cfg["samples_per_ct"] if samples is None else samples
+    st = cfg["sample_stride"] if stride is None else stride
+    xs = W.gen_inputs(cfg["input"], S)
+    net = Net(cfg["input"], cfg["layers"], params, n_slots, S, st)
+    ev = SlotEval(n_slots)
+    outs = net.run(ev, [net.input_vector(xs)])
+    got = read_outputs(net, outs)
+    ref = np.array([cnn_fp64(x, cfg["layers"], params).reshape(-1) for x in xs])
+    return got, ref, ev.count.as_dict(), net
+
+
+@pytest.mark.parametrize("name", list(W.CONFIGS))
+def test_slot_simulation_matches_fp64_cnn(name):
+    got, ref, _, _ = _slot_run(name)
+    assert got.shape == ref.shape
+    assert np.abs(got - ref).max() < 1e-12
+
+
+def test_lenet1_operation_counts():
+    """Exact primitive counts of Algorithms 1 and 2, pooling and flatten for
+    LeNet-1: conv rotations CH_in K^2 minus the zero shifts, conv products
+    CH_in CH_out K^2, pooling c^2 - 1 rotations per channel, flatten W_in +
+    H_in products and rotations per channel plus CH - 1 packing rotations,
+    FC 2 DAT_out - 1 products and 2 (DAT_out - 1) + ceil(DAT_in / DAT_out) - 1
+    rotations."""
+    _, _, cnt, net = _slot_run("lenet1")
+    conv_rot = (1 * 25 - 1) + (4 * 25 - 4)
+    conv_mac = 1 * 4 * 25 + 4 * 12 * 25
+    pool_rot = 3 * 4 + 3 * 12
+    flat_rot = 12 * (3 + 3) + 11
+    flat_mac = 12 * (4 + 4)
+    fc_rot = 2 * 9 + math.ceil(192 / 10) - 1
+    fc_mac = 2 * 10 - 1
+    assert cnt["rot"] == conv_rot + pool_rot + flat_rot + fc_rot == 288
+    assert cnt["mac"] == conv_mac + flat_mac + fc_mac == 1415
+    assert cnt["relin"] == 4 + 12
+    assert cnt["rescale"] == 4 + 4 + 12 + 12 + 12 + 12 + 1 == 57
+    assert len(net.rotation_set()) == 81
+
+
+@pytest.mark.parametrize("name,expect", [("conv1", 2), ("lenet1", 7), ("cnn1d", 6), ("cifar_cnn", 7)])
+def test_depth(name, expect):
+    cfg = W.config(name)
+    assert network_depth(cfg["input"], cfg["layers"]) == expect
+
+
+def test_theorem1_conv_does_not_grow():
+    """H_img >= H_out(i) * prod_{j<=i} S_j whenever K >= S >= 1 (Theorem 1 and
+    its corollary for widths), over random conv stacks."""
+    rng = np.random.default_rng(3)
+    for _ in range(200):
+        H = int(rng.integers(8, 64))
+        h, prod = H, 1
+        for _ in range(int(rng.integers(1, 4))):
+            K = int(rng.integers(1, 6))
+            S = int(rng.integers(1, K + 1))
+            if h < K:
+                break
+            h = (h - K) // S + 1
+            prod *= S
+            assert H >= h * prod
+
+
+def test_stride_larger_than_kernel_rejected():
+    inp = {"c": 1, "h": 28, "w": 28, "dist": "uniform01"}
+    with pytest.raises(PlanError):
+        footprint(inp, [{"kind": "conv", "ch_in": 1, "ch_out": 1, "k": 2, "s": 3}])
+
+
+def test_cnn1d_packing_as_written_overflows():
+    """32 sequences at stride 128 cannot hold the 944-slot flatten output or
+    the 945-slot FC width; 8 at stride 1024 fit."""
+    cfg = W.config("cnn1d")
+    assert footprint(cfg["input"], cfg["layers"]) == 945
+    with pytest.raises(PlanError):
+        check_packing(cfg["input"], cfg["layers"], 8192, 32, 128)
+    assert check_packing(cfg["input"], cfg["layers"], 8192, 8, 1024) == 1024
+
+
+def test_packed_equals_single_slot_sim():
+    got10, ref10, _, _ = _slot_run("lenet1_batched")
+    got1, ref1, _, _ = _slot_run("lenet1", samples=1)
+    assert np.abs(got10[0] - got1[0]).max() < 1e-12
+    assert np.abs(got10 - ref10).max() < 1e-12
+
+
+def test_shapes_lenet1():
+    cfg = W.config("lenet1")
+    assert shapes(cfg["input"], cfg["layers"])[-2:] == [(192,), (10,)]
+
+
+# ---------------------------------------------------------------- encrypted
+def test_encrypted_conv1_config():
+    cfg = W.config("conv1")
+    sess = OracleSession(cfg)
+    net = build_net(cfg, sess.ck.slots)
+    xs = W.gen_inputs(cfg["input"], 1)
+    _, outs, ev = run_encrypted(sess, net, xs)
+    assert ev.count.as_dict() == {"rot": 24, "mac": 100, "rescale": 8, "relin": 4}
+    got = decrypt_outputs(sess, net, outs)
+    assert all(o.nl == 1 for o in outs)
+    assert np.abs(got - reference_outputs(net, xs)).max() < 1e-3
+
+
+def test_encrypted_packing_isolation():
+    """Five images packed at stride 784 decrypt to the same outputs as each
+    image alone (conv + square at N = 2^13)."""
+    cfg = W.config("conv1")
+    sess = OracleSession(cfg)
+    cfgp = dict(cfg, samples_per_ct=5, sample_stride=784)
+    netp = build_net(cfgp, sess.ck.slots)
+    xs = W.gen_inputs(cfg["input"], 5)
+    _, outs, _ = run_encrypted(sess, netp, xs)
+    packed = decrypt_outputs(sess, netp, outs)
+    ref = reference_outputs(netp, xs)
+    assert np.abs(packed - ref).max() < 1e-3
+    net1 = build_net(cfg, sess.ck.slots)
+    _, outs1, _ = run_encrypted(sess, net1, xs[2:3])
+    single = decrypt_outputs(sess, net1, outs1)
+    assert np.abs(packed[2] - single[0]).max() < 1e-3
+
+
+@pytest.mark.slow
+def test_encrypted_lenet1_small_ring():
+    """LeNet-1 shape end to end at N = 2^11 (1024 slots hold the 784-slot
+    footprint) with the same 60 + 7 x 40 + 60 chain: 7 levels consumed,
+    logits within 1e-3 of FP64."""
+    cfg = W.config("lenet1")
+    cfg["log_n"] = 11
+    sess = OracleSession(cfg)
+    net = build_net(cfg, sess.ck.slots)
+    xs = W.gen_inputs(cfg["input"], 1)
+    _, outs, ev = run_encrypted(sess, net, xs)
+    assert outs[0].nl == 1
+    assert ev.count.rescale == 57
+    got = decrypt_outputs(sess, net, outs)
+    assert np.abs(got - reference_outputs(net, xs)).max() < 1e-3

@@ -1,0 +1,291 @@
+"""Pins of the CPU oracle against things other than itself: number theory,
+schoolbook products, exact big-integer CRT and rounding, a decimal evaluation
+of the encoding sum, slot-level invariants and the paper's printed facts.
+No GPU."""
+from __future__ import annotations
+
+import json
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle.ckks import OracleCKKS, gen_primes
+from tests import bigint_ref as R
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    ring = W.TINY_RINGS["n16"]
+    ck = OracleCKKS(ring["log_n"], ring["prime_bits"], ring["special_bits"], ring["log_scale"])
+    ck.keygen(W.SEED_KEYS)
+    return ck
+
+
+@pytest.fixture(scope="module")
+def mid():
+    ring = W.TINY_RINGS["n1024"]
+    ck = OracleCKKS(ring["log_n"], ring["prime_bits"], ring["special_bits"], ring["log_scale"])
+    ck.keygen(W.SEED_KEYS)
+    return ck
+
+
+# ---------------------------------------------------------------- primes
+@pytest.mark.parametrize("name", ["conv1", "lenet1", "cifar_cnn"])
+def test_prime_chain(name):
+    cfg = W.config(name)
+    bits = cfg["prime_bits"] + [cfg["special_bits"]]
+    ps = gen_primes(cfg["log_n"], bits)
+    two_n = 2 << cfg["log_n"]
+    assert len(set(ps)) == len(ps)
+    for i, (p, b) in enumerate(zip(ps, bits)):
+        assert p.bit_length() == b and p % two_n == 1 and R.is_prime(p)
+        # largest: every candidate above it that is = 1 mod 2N is composite or used earlier
+        c = p + two_n
+        while c < (1 << b):
+            assert (not R.is_prime(c)) or c in ps[:i]
+            c += two_n
+
+
+def test_prime_chain_survey_values():
+    """Cross-check with the chain computed independently when the work was
+    surveyed (same selection rule)."""
+    assert gen_primes(13, [60, 40, 40, 60]) == [1152921504606830593, 1099511480321, 1099510890497,
+                                                1152921504606748673]
+    assert gen_primes(14, [60] + [40] * 7 + [60])[-1] == 1152921504606683137
+
+
+# ---------------------------------------------------------------- ring arithmetic
+def test_poly_mul_schoolbook(tiny):
+    rng = np.random.default_rng(5)
+    N = tiny.n
+    for mi, q in enumerate(tiny.primes + [tiny.special]):
+        a = [int(x) for x in rng.integers(0, q, N, dtype=np.uint64)]
+        b = [int(x) for x in rng.integers(0, q, N, dtype=np.uint64)]
+        out = np.zeros(N, dtype=np.uint64)
+        from oracle.ckks import lib, _p64
+        lib().or_poly_mul(tiny.ctx, mi, _p64(np.array(a, dtype=np.uint64)), _p64(np.array(b, dtype=np.uint64)),
+                          _p64(out))
+        assert [int(x) for x in out] == R.negacyclic(a, b, N, q)
+
+
+def test_automorphism_substitution(tiny):
+    rng = np.random.default_rng(6)
+    N = tiny.n
+    a = np.stack([rng.integers(0, q, N, dtype=np.uint64) for q in tiny.primes])
+    for r in [1, 2, 3, -1]:
+        g = tiny.galois_elt(r)
+        assert g == pow(5, r % (N // 2), 2 * N)
+        out = tiny.automorphism(a, g)
+        for i, q in enumerate(tiny.primes):
+            assert [int(x) for x in out[i]] == R.substitute([int(x) for x in a[i]], g, N, q)
+
+
+# ---------------------------------------------------------------- encoding
+def test_encode_matches_decimal_closed_form(tiny):
+    """Rounded integers equal round-half-away of the 60-digit decimal value."""
+    rng = np.random.default_rng(7)
+    N = tiny.n
+    z = rng.uniform(-1, 1, N // 2)
+    scale = 2.0 ** 30
+    pt = tiny.encode(z, scale, len(tiny.primes))
+    exact = R.encode_exact(z, N, scale)
+    hi, lo = tiny.real_transform(z)
+    for j in range(N):
+        v = R.round_half_away(exact[j])
+        for i, q in enumerate(tiny.primes):
+            assert int(pt[i, j]) == v % q
+        # the binary128 transform agrees with the decimal one far below 1/2 ulp of the scaled value
+        assert abs(float(exact[j] / int(scale) - R.Decimal(hi[j]) - R.Decimal(lo[j]))) < 1e-28
+
+
+def test_encode_scaled_is_encode_of_product(tiny):
+    rng = np.random.default_rng(8)
+    z = np.zeros(tiny.slots)
+    z[[0, 3, 5]] = 1.0
+    ws = rng.normal(0, 0.1, 5)
+    batch = tiny.encode_scaled(z, ws, 2.0 ** 30, 2)
+    for w, pt in zip(ws, batch):
+        assert np.array_equal(pt, tiny.encode(w * z, 2.0 ** 30, 2))
+
+
+def test_decode_encode_roundtrip(mid):
+    z = W.gen_slots(mid.slots, 1, seed=9)[0]
+    pt = mid.encode(z, mid.delta, 2)
+    back = mid.decode(pt, mid.delta)
+    assert np.abs(back - z).max() < 1e-9
+
+
+def test_encode_rotation_equivariance(mid):
+    """Encode(roll(z, -r)) == tau_{5^r}(Encode(z)), bit for bit."""
+    z = W.gen_slots(mid.slots, 1, seed=10)[0]
+    pt = mid.encode(z, mid.delta, 3)
+    for r in [1, 7, mid.slots // 4, -3]:
+        assert np.array_equal(mid.encode(np.roll(z, -r), mid.delta, 3), mid.automorphism(pt, mid.galois_elt(r)))
+
+
+# ---------------------------------------------------------------- encryption
+def test_encrypt_decrypt(mid):
+    z = W.gen_slots(mid.slots, 1, seed=11)[0]
+    ct = mid.encrypt(z, 12)
+    assert np.abs(mid.decrypt(ct) - z).max() < 1e-7
+
+
+# ---------------------------------------------------------------- key switching
+def _ks_bruteforce(ck, d, key, nl):
+    """round((sum_j centered(d mod q_j) * evk_j) / P) mod q_i, on integers."""
+    N = ck.n
+    mods = ck.primes[:nl] + [ck.special]
+    key_limbs = list(range(nl)) + [key.shape[2] - 1]
+    out = np.zeros((2, nl, N), dtype=np.uint64)
+    for c in range(2):
+        U = [0] * N
+        for j in range(nl):
+            dj = [R.centered(int(x), ck.primes[j]) for x in d[j]]
+            ev = [R.crt([int(key[j, c, li, t]) for li in key_limbs], mods)[0] for t in range(N)]
+            prod = R.negacyclic(dj, ev, N)
+            U = [u + p for u, p in zip(U, prod)]
+        M = 1
+        for m in mods:
+            M *= m
+        for t in range(N):
+            v = R.round_div(U[t] % M, ck.special)
+            for i in range(nl):
+                out[c, i, t] = v % ck.primes[i]
+    return out
+
+
+def test_keyswitch_bruteforce(tiny):
+    rng = np.random.default_rng(13)
+    key = tiny.rotation_key(1)
+    h = tiny.load_key(key)
+    for nl in [3, 2]:
+        d = np.stack([rng.integers(0, q, tiny.n, dtype=np.uint64) for q in tiny.primes[:nl]])
+        assert np.array_equal(tiny.keyswitch(d, h), _ks_bruteforce(tiny, d, key, nl))
+
+
+def test_rescale_bruteforce(tiny):
+    rng = np.random.default_rng(14)
+    from oracle.ckks import Ciphertext
+    for nl in [3, 2]:
+        data = np.stack([np.stack([rng.integers(0, q, tiny.n, dtype=np.uint64) for q in tiny.primes[:nl]])
+                         for _ in range(2)])
+        out = tiny.rescale(Ciphertext(data, 1.0)).data
+        ql = tiny.primes[nl - 1]
+        for c in range(2):
+            for t in range(tiny.n):
+                x, _ = R.crt([int(data[c, i, t]) for i in range(nl)], tiny.primes[:nl])
+                v = R.round_div(x, ql)
+                for i in range(nl - 1):
+                    assert int(out[c, i, t]) == v % tiny.primes[i]
+
+
+def test_keyswitch_noise_bound(mid):
+    """KS(d) decrypts to d * t plus an error below N sum_j (q_j/2) 19 / P + N."""
+    rng = np.random.default_rng(15)
+    r = 5
+    key = mid.load_key(mid.rotation_key(r))
+    nl = len(mid.primes)
+    d = np.stack([rng.integers(0, q, mid.n, dtype=np.uint64) for q in mid.primes])
+    ks = mid.keyswitch(d, key)
+    from oracle.ckks import Ciphertext
+    m = mid.decrypt_residues(Ciphertext(ks, 1.0))
+    # expected d * tau_g(s), limb by limb
+    g = mid.galois_elt(r)
+    s = [int(x) for x in mid.sk.s]
+    ts = R.substitute(s, g, mid.n, 1 << 80)
+    ts = [x - (1 << 80) if x > (1 << 79) else x for x in ts]
+    bound = mid.n * sum(q / 2 for q in mid.primes) * 19 / mid.special + mid.n
+    worst = 0
+    for i in range(1):  # limb 0 only: q_0 is 60-bit and holds the error
+        q = mid.primes[i]
+        exp = R.negacyclic([int(x) for x in d[i]], ts, mid.n, q)
+        err = max(abs(R.centered(int(a) - b, q)) for a, b in zip(m[i], exp))
+        worst = max(worst, err)
+    assert worst <= bound
+
+
+def test_rotation_decrypts_to_left_roll(mid):
+    z = W.gen_slots(mid.slots, 1, seed=16)[0]
+    ct = mid.encrypt(z, 17)
+    for r in [1, 5, -3, mid.slots // 4]:
+        k = mid.load_key(mid.rotation_key(r))
+        out = mid.decrypt(mid.rotate(ct, r, k))
+        assert np.abs(out - np.roll(z, -r)).max() < 1e-6
+
+
+def test_hoisted_equals_plain(mid):
+    z = W.gen_slots(mid.slots, 1, seed=18)[0]
+    ct = mid.limb_drop(mid.encrypt(z, 19), 3)
+    rs = [1, 28, -4, 100]
+    keys = [mid.load_key(mid.rotation_key(r)) for r in rs]
+    hs = mid.rotate_hoisted(ct, rs, keys)
+    for r, k, h in zip(rs, keys, hs):
+        assert np.array_equal(h.data, mid.rotate(ct, r, k).data)
+
+
+def test_square_relin_rescale(mid):
+    z = W.gen_slots(mid.slots, 1, seed=20)[0]
+    ct = mid.encrypt(z, 21)
+    rlk = mid.load_key(mid.relin_key())
+    sq = mid.rescale(mid.square_relin(ct, rlk))
+    assert sq.nl == len(mid.primes) - 1
+    assert np.abs(mid.decrypt(sq) - z * z).max() < 1e-6
+
+
+def test_mac_schoolbook(tiny):
+    rng = np.random.default_rng(22)
+    nl = 2
+    from oracle.ckks import Ciphertext
+    cts = [Ciphertext(np.stack([np.stack([rng.integers(0, q, tiny.n, dtype=np.uint64) for q in tiny.primes[:nl]])
+                                for _ in range(2)]), 1.0) for _ in range(3)]
+    pts = [[np.stack([rng.integers(0, q, tiny.n, dtype=np.uint64) for q in tiny.primes[:nl]]) for _ in range(3)]
+           for _ in range(2)]
+    pts[1][2] = None
+    accs = tiny.mac_matrix(cts, pts)
+    for o in range(2):
+        for c in range(2):
+            for i, q in enumerate(tiny.primes[:nl]):
+                exp = [0] * tiny.n
+                for t in range(3):
+                    if pts[o][t] is None:
+                        continue
+                    p = R.negacyclic([int(x) for x in pts[o][t][i]], [int(x) for x in cts[t].data[c, i]], tiny.n, q)
+                    exp = [(a + b) % q for a, b in zip(exp, p)]
+                assert [int(x) for x in accs[o][c, i]] == exp
+
+
+# ---------------------------------------------------------------- paper facts
+def test_paper_facts():
+    facts = json.load(open(os.path.join(GOLD, "paper_facts.json")))
+    from oracle.network import network_depth, Net, SlotEval
+    # Table of M2 (LeNet-1): per-layer #Mult and total 7
+    cfg = W.config("lenet1")
+    per = facts["lenet1_mults"]
+    layers = cfg["layers"]
+    acc = 0
+    for i, lay in enumerate(layers):
+        d = network_depth(cfg["input"], layers[: i + 1])
+        assert d - acc == per[i]["mult"], (i, lay)
+        acc = d
+    assert acc == facts["lenet1_total_mults"]
+    # FC 64 -> 10: the first loop of Algorithm 2 runs DAT_out = 10 times, not 64
+    fc = facts["fc_64_10"]
+    ev = SlotEval(4096)
+    inp = {"c": 1, "h": 1, "w": fc["din"], "dist": "normal"}
+    lays = [W.FLATTEN, {"kind": "fc", "din": fc["din"], "dout": fc["dout"]}]
+    net = Net(inp, lays, W.gen_params(lays), 4096)
+    net.run(ev, [np.zeros(4096)])
+    D = fc["dout"]
+    assert ev.count.mac == 2 * D - 1            # the loop body's two products, V2 empty at o = 0
+    assert ev.count.mac // 2 + 1 == fc["loop_iterations"]
+    # packing example: input i is shifted right by (i - 1) * 800 slots
+    ex = facts["packing_800"]
+    inp = {"c": 1, "h": 1, "w": 784, "dist": "uniform01"}
+    net = Net(inp, [], [], 8192, samples=3, stride=ex["stride"])
+    v = net.input_vector(np.ones((3, 1, 1, 784)))
+    for i in range(1, 4):
+        assert v[(i - 1) * ex["stride"]] == 1.0 and v[(i - 1) * ex["stride"] + 784] == 0.0
