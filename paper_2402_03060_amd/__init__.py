@@ -1,0 +1,327 @@
+"""Python binding of libunihenn (include/unihenn.h): argument marshalling only.
+
+Every computation runs in the HIP library; torch provides device memory
+(int64 tensors reinterpreted as uint64 residues) and streams.  The binding
+refuses to run without the built library: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch  # imported first so the library binds to torch's HIP runtime
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libunihenn.so")
+
+OK, EINVAL, ELEVEL, ESCALE, ENOKEY, ESLOTS, ENOMEM, EDEVICE = 0, -1, -2, -3, -4, -5, -6, -7
+LAYER_CONV, LAYER_SQUARE, LAYER_AVGPOOL, LAYER_FLATTEN, LAYER_FC = 1, 2, 3, 4, 5
+EVAL_PLAIN, EVAL_HOISTED = 0, 1
+KERNEL_FAMILIES = ["ntt_fwd", "ntt_inv", "modup", "ks_inner", "moddown", "rescale", "mac", "automorphism",
+                   "tensor", "add", "encode", "other"]
+
+
+class UnihennError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"unihenn error {code}: {msg}")
+        self.code = code
+
+
+class CT(C.Structure):
+    _fields_ = [("data", C.c_void_p), ("n_limbs", C.c_uint32), ("batch", C.c_uint32), ("scale", C.c_double)]
+
+
+class EVK(C.Structure):
+    _fields_ = [("data", C.c_void_p), ("n_data", C.c_uint32)]
+
+
+class LAYER(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("ch_in", C.c_uint32), ("ch_out", C.c_uint32), ("k", C.c_uint32),
+                ("s", C.c_uint32), ("dims", C.c_uint32), ("weights", C.POINTER(C.c_double)),
+                ("bias", C.POINTER(C.c_double))]
+
+
+class INPUT(C.Structure):
+    _fields_ = [("c", C.c_uint32), ("h", C.c_uint32), ("w", C.c_uint32), ("samples", C.c_uint32),
+                ("stride", C.c_uint32)]
+
+
+# name -> (restype, argtypes); every symbol declared in include/unihenn.h
+_vp, _u32, _i32, _u64, _d, _sz = C.c_void_p, C.c_uint32, C.c_int32, C.c_uint64, C.c_double, C.c_size_t
+_P = C.POINTER
+SIGNATURES = {
+    "unihenn_last_error": (C.c_char_p, []),
+    "unihenn_ctx_create": (C.c_int, [_u32, _P(_u32), _u32, _u32, _d, _P(_vp)]),
+    "unihenn_ctx_destroy": (C.c_int, [_vp]),
+    "unihenn_ctx_primes": (C.c_int, [_vp, _P(_u64)]),
+    "unihenn_to_ntt": (C.c_int, [_vp, _vp, _u32, _u32, _vp]),
+    "unihenn_from_ntt": (C.c_int, [_vp, _vp, _u32, _u32, _vp]),
+    "unihenn_import_evk": (C.c_int, [_vp, _vp, _u32, _vp, _vp]),
+    "unihenn_encode": (C.c_int, [_vp, _P(_d), _u32, _d, _u32, C.c_int, _vp, _vp]),
+    "unihenn_import_pt": (C.c_int, [_vp, _vp, _u32, C.c_int, _vp, _vp]),
+    "unihenn_export_pt": (C.c_int, [_vp, _vp, _u32, C.c_int, _vp, _vp]),
+    "unihenn_ks_workspace_size": (_sz, [_vp, _u32, _u32]),
+    "unihenn_rotate": (C.c_int, [_vp, _P(CT), _i32, _P(EVK), _P(CT), _vp, _sz, _vp]),
+    "unihenn_rotate_hoisted": (C.c_int, [_vp, _P(CT), _P(_i32), _u32, _P(EVK), _P(CT), _vp, _sz, _vp]),
+    "unihenn_mul_plain_acc": (C.c_int, [_vp, _P(CT), _P(_vp), _u32, C.c_int, _P(CT), _vp]),
+    "unihenn_rescale": (C.c_int, [_vp, _P(CT), _P(CT), _vp, _sz, _vp]),
+    "unihenn_square_relin": (C.c_int, [_vp, _P(CT), _P(EVK), _P(CT), _vp, _sz, _vp]),
+    "unihenn_add": (C.c_int, [_vp, _P(CT), _P(CT), _P(CT), _vp]),
+    "unihenn_add_plain": (C.c_int, [_vp, _P(CT), _vp, _P(CT), _vp]),
+    "unihenn_mod_drop": (C.c_int, [_vp, _P(CT), _u32, _P(CT), _vp]),
+    "unihenn_net_create": (C.c_int, [_vp, _P(INPUT), _P(LAYER), _u32, _u32, _P(_vp)]),
+    "unihenn_net_destroy": (C.c_int, [_vp]),
+    "unihenn_net_info": (C.c_int, [_vp, _P(_u32), _P(_u32), _P(_u32), _P(_u32)]),
+    "unihenn_net_rotations": (C.c_int, [_vp, _P(_i32)]),
+    "unihenn_net_bind_keys": (C.c_int, [_vp, _P(_i32), _P(EVK), _u32, _P(EVK)]),
+    "unihenn_net_set_mode": (C.c_int, [_vp, C.c_int]),
+    "unihenn_conv": (C.c_int, [_vp, _vp, _u32, _P(CT), _u32, _P(CT), _P(_u32), _vp]),
+    "unihenn_eval_network": (C.c_int, [_vp, _vp, _P(CT), _P(CT), _vp]),
+    "unihenn_net_output_slots": (C.c_int, [_vp, _P(_u64), _P(_u32)]),
+    "unihenn_keygen_secret": (C.c_int, [_vp, _u64, _vp, _vp]),
+    "unihenn_gen_switch_key": (C.c_int, [_vp, _vp, _u64, _i32, C.c_int, _vp, _vp]),
+    "unihenn_encrypt_sk": (C.c_int, [_vp, _vp, _vp, _u64, _P(CT), _vp]),
+    "unihenn_decrypt_slots": (C.c_int, [_vp, _vp, _P(CT), _P(_u32), _u32, _P(_d), _vp]),
+    "unihenn_stats_enable": (C.c_int, [C.c_int]),
+    "unihenn_stats_reset": (C.c_int, []),
+    "unihenn_stats_get": (C.c_int, [C.c_int, _P(_u64), _P(_d), _P(_d)]),
+    "unihenn_kernel_family_name": (C.c_char_p, [C.c_int]),
+}
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2402_03060_amd/build.py "
+                               "(there is no fallback path)")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name, None)
+            if f is None:
+                continue  # reported by missing_symbols()
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def missing_symbols() -> list[str]:
+    L = lib()
+    return [n for n in SIGNATURES if getattr(L, n, None) is None]
+
+
+def _check(rc: int):
+    if rc != OK:
+        raise UnihennError(rc, lib().unihenn_last_error().decode())
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def device_u64(a: np.ndarray, device="cuda") -> torch.Tensor:
+    """uint64 numpy array -> int64 device tensor with the same bits."""
+    return torch.from_numpy(np.ascontiguousarray(a).view(np.int64)).to(device)
+
+
+def host_u64(t: torch.Tensor) -> np.ndarray:
+    return t.detach().cpu().numpy().view(np.uint64)
+
+
+class Ciphertext:
+    """A batch of device ciphertexts [batch][2][n_limbs][N] (NTT form)."""
+
+    def __init__(self, data: torch.Tensor, scale: float):
+        assert data.dtype == torch.int64 and data.is_cuda and data.is_contiguous() and data.dim() == 4
+        self.data = data
+        self.scale = float(scale)
+
+    @property
+    def batch(self):
+        return self.data.shape[0]
+
+    @property
+    def n_limbs(self):
+        return self.data.shape[2]
+
+    def desc(self) -> CT:
+        return CT(self.data.data_ptr(), self.n_limbs, self.batch, self.scale)
+
+
+class Context:
+    def __init__(self, log_n: int, prime_bits, special_bits: int, scale: float):
+        self.log_n = log_n
+        self.n = 1 << log_n
+        self.slots = self.n // 2
+        self.n_data = len(prime_bits)
+        self.scale = float(scale)
+        bits = (C.c_uint32 * len(prime_bits))(*prime_bits)
+        h = C.c_void_p()
+        _check(lib().unihenn_ctx_create(log_n, bits, len(prime_bits), special_bits, float(scale), C.byref(h)))
+        self.h = h
+        out = (C.c_uint64 * (self.n_data + 1))()
+        _check(lib().unihenn_ctx_primes(self.h, out))
+        self.primes = [int(x) for x in out[: self.n_data]]
+        self.special = int(out[self.n_data])
+
+    def close(self):
+        if self.h:
+            lib().unihenn_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- allocation helpers (torch) ----
+    def empty_ct(self, batch: int, n_limbs: int, scale: float = 0.0) -> Ciphertext:
+        return Ciphertext(torch.empty((batch, 2, n_limbs, self.n), dtype=torch.int64, device="cuda"), scale)
+
+    def workspace(self, n_limbs: int, batch: int) -> torch.Tensor:
+        nbytes = lib().unihenn_ks_workspace_size(self.h, n_limbs, batch)
+        return torch.empty(max(nbytes // 8, 1), dtype=torch.int64, device="cuda")
+
+    # ---- conversions ----
+    def to_ntt(self, t: torch.Tensor, n_limbs: int, n_polys: int, stream=None):
+        _check(lib().unihenn_to_ntt(self.h, t.data_ptr(), n_limbs, n_polys, _stream(stream)))
+
+    def from_ntt(self, t: torch.Tensor, n_limbs: int, n_polys: int, stream=None):
+        _check(lib().unihenn_from_ntt(self.h, t.data_ptr(), n_limbs, n_polys, _stream(stream)))
+
+    def import_ct(self, coeff: np.ndarray, scale: float) -> Ciphertext:
+        """coeff: uint64 [batch][2][n_limbs][N] or [2][n_limbs][N] (coefficient form)."""
+        if coeff.ndim == 3:
+            coeff = coeff[None]
+        t = device_u64(coeff)
+        self.to_ntt(t, coeff.shape[2], coeff.shape[0] * 2)
+        return Ciphertext(t, scale)
+
+    def export_ct(self, ct: Ciphertext) -> np.ndarray:
+        t = ct.data.clone()
+        self.from_ntt(t, ct.n_limbs, ct.batch * 2)
+        torch.cuda.synchronize()
+        return host_u64(t)
+
+    def import_evk(self, coeff: np.ndarray) -> torch.Tensor:
+        t = device_u64(coeff)
+        _check(lib().unihenn_import_evk(self.h, t.data_ptr(), coeff.shape[0], t.data_ptr(), _stream()))
+        return t
+
+    def evk(self, t: torch.Tensor) -> EVK:
+        return EVK(t.data_ptr(), self.n_data)
+
+    def encode(self, z, scale: float, n_limbs: int, mont: bool = True) -> torch.Tensor:
+        z = np.ascontiguousarray(np.asarray(z, dtype=np.float64))
+        out = torch.empty((n_limbs, self.n), dtype=torch.int64, device="cuda")
+        _check(lib().unihenn_encode(self.h, z.ctypes.data_as(C.POINTER(C.c_double)), len(z), float(scale), n_limbs,
+                                    int(mont), out.data_ptr(), _stream()))
+        return out
+
+    def import_pt(self, coeff: np.ndarray, mont: bool = True) -> torch.Tensor:
+        t = device_u64(coeff)
+        _check(lib().unihenn_import_pt(self.h, t.data_ptr(), coeff.shape[0], int(mont), t.data_ptr(), _stream()))
+        return t
+
+    def export_pt(self, pt: torch.Tensor, mont: bool = True) -> np.ndarray:
+        out = torch.empty_like(pt)
+        _check(lib().unihenn_export_pt(self.h, pt.data_ptr(), pt.shape[0], int(mont), out.data_ptr(), _stream()))
+        torch.cuda.synchronize()
+        return host_u64(out)
+
+    # ---- primitives ----
+    def rotate(self, ct: Ciphertext, steps: int, key: torch.Tensor | None, ws: torch.Tensor) -> Ciphertext:
+        out = self.empty_ct(ct.batch, ct.n_limbs)
+        o = out.desc()
+        k = self.evk(key) if key is not None else None
+        _check(lib().unihenn_rotate(self.h, C.byref(ct.desc()), int(steps), C.byref(k) if k else None, C.byref(o),
+                                    ws.data_ptr(), ws.numel() * 8, _stream()))
+        out.scale = o.scale
+        return out
+
+    def rotate_hoisted(self, ct: Ciphertext, steps, keys, ws: torch.Tensor) -> list[Ciphertext]:
+        steps = list(steps)
+        outs = [self.empty_ct(ct.batch, ct.n_limbs) for _ in steps]
+        od = (CT * len(steps))(*[o.desc() for o in outs])
+        kd = (EVK * len(steps))(*[self.evk(k) if k is not None else EVK(None, self.n_data) for k in keys])
+        sa = (C.c_int32 * len(steps))(*steps)
+        _check(lib().unihenn_rotate_hoisted(self.h, C.byref(ct.desc()), sa, len(steps), kd, od, ws.data_ptr(),
+                                            ws.numel() * 8, _stream()))
+        for o, d in zip(outs, od):
+            o.scale = d.scale
+        return outs
+
+    def mul_plain_acc(self, cts: list[Ciphertext], pts: list[torch.Tensor], acc: Ciphertext | None = None,
+                      overwrite: bool = True) -> Ciphertext:
+        if acc is None:
+            acc = self.empty_ct(cts[0].batch, cts[0].n_limbs)
+        cd = (CT * len(cts))(*[c.desc() for c in cts])
+        pd = (C.c_void_p * len(pts))(*[p.data_ptr() for p in pts])
+        a = acc.desc()
+        _check(lib().unihenn_mul_plain_acc(self.h, cd, pd, len(cts), int(overwrite), C.byref(a), _stream()))
+        acc.scale = a.scale
+        return acc
+
+    def rescale(self, ct: Ciphertext, ws: torch.Tensor) -> Ciphertext:
+        out = self.empty_ct(ct.batch, ct.n_limbs - 1)
+        o = out.desc()
+        _check(lib().unihenn_rescale(self.h, C.byref(ct.desc()), C.byref(o), ws.data_ptr(), ws.numel() * 8,
+                                     _stream()))
+        out.scale = o.scale
+        return out
+
+    def square_relin(self, ct: Ciphertext, rlk: torch.Tensor, ws: torch.Tensor) -> Ciphertext:
+        out = self.empty_ct(ct.batch, ct.n_limbs)
+        o = out.desc()
+        _check(lib().unihenn_square_relin(self.h, C.byref(ct.desc()), C.byref(self.evk(rlk)), C.byref(o),
+                                          ws.data_ptr(), ws.numel() * 8, _stream()))
+        out.scale = o.scale
+        return out
+
+    def add(self, a: Ciphertext, b: Ciphertext) -> Ciphertext:
+        out = self.empty_ct(a.batch, a.n_limbs)
+        o = out.desc()
+        _check(lib().unihenn_add(self.h, C.byref(a.desc()), C.byref(b.desc()), C.byref(o), _stream()))
+        out.scale = o.scale
+        return out
+
+    def add_plain(self, a: Ciphertext, pt: torch.Tensor) -> Ciphertext:
+        out = self.empty_ct(a.batch, a.n_limbs)
+        o = out.desc()
+        _check(lib().unihenn_add_plain(self.h, C.byref(a.desc()), pt.data_ptr(), C.byref(o), _stream()))
+        out.scale = o.scale
+        return out
+
+    def mod_drop(self, a: Ciphertext, n_limbs: int) -> Ciphertext:
+        out = self.empty_ct(a.batch, n_limbs)
+        o = out.desc()
+        _check(lib().unihenn_mod_drop(self.h, C.byref(a.desc()), n_limbs, C.byref(o), _stream()))
+        out.scale = o.scale
+        return out
+
+
+def stats_enable(on: bool = True):
+    _check(lib().unihenn_stats_enable(int(on)))
+
+
+def stats_reset():
+    _check(lib().unihenn_stats_reset())
+
+
+def stats() -> dict:
+    """{family: (launches, total_ms, algorithmic_bytes)}"""
+    out = {}
+    for i, name in enumerate(KERNEL_FAMILIES):
+        n = C.c_uint64()
+        ms = C.c_double()
+        by = C.c_double()
+        _check(lib().unihenn_stats_get(i, C.byref(n), C.byref(ms), C.byref(by)))
+        out[name] = (int(n.value), float(ms.value), float(by.value))
+    return out

@@ -1,0 +1,106 @@
+// Internal structures shared by the library's translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <stdint.h>
+#include <string>
+#include <vector>
+
+#include "../../include/unihenn.h"
+#include "modarith.h"
+
+#define UH_MAX_MODULI 24
+
+// Device-side view of the context, passed by value to kernels.
+struct DevCtx {
+    int log_n;
+    int n;                 // ring degree N
+    int n_data;            // data primes q_0..q_{L}
+    int p_index;           // index of the special prime P (= n_data)
+    const Modulus* mod;    // [n_data + 1]
+    const u64* tw;         // forward twiddles  [n_mod][N]: psi^brev(k)
+    const u64* tw_sh;      // Shoup companions
+    const u64* itw;        // inverse twiddles  [n_mod][N]: psi^-brev(k)
+    const u64* itw_sh;
+};
+
+struct unihenn_ctx {
+    int log_n = 0;
+    int n = 0;
+    int n_data = 0;
+    double scale = 0;
+    std::vector<u64> primes;          // data primes then P
+    std::vector<Modulus> host_mod;
+    // small constant tables on the host (read by launchers)
+    std::vector<u64> q_mod;           // [a][b] = q_a mod q_b   (n_mod x n_mod)
+    std::vector<u64> inv_last;        // [l][i] = q_l^-1 mod q_i (Shoup pair interleaved)
+    std::vector<u64> p_inv;           // [i] = P^-1 mod q_i (value, shoup)
+    // device memory
+    Modulus* d_mod = nullptr;
+    u64* d_tw = nullptr;              // 4 tables of n_mod * N
+    u64* d_qmod = nullptr;            // q_mod on device
+    u64* d_inv_last = nullptr;
+    u64* d_p_inv = nullptr;
+    uint32_t* d_galois_e = nullptr;   // 5^k mod 2N, k < N/2
+    double* d_cos = nullptr;          // cos(pi t / N) as double-double, t < 2N: [2N][2]
+    int device = 0;
+    DevCtx dev;
+};
+
+// error reporting (thread-local message)
+int uh_fail(int code, const std::string& msg);
+#define UH_CHECK_HIP(expr)                                                                \
+    do {                                                                                  \
+        hipError_t _e = (expr);                                                           \
+        if (_e != hipSuccess) return uh_fail(UNIHENN_EDEVICE, std::string(#expr) + ": " + \
+                                             hipGetErrorString(_e));                     \
+    } while (0)
+
+// -------------------------------------------------------------------------
+// row -> modulus mapping for batched transforms and elementwise kernels
+// -------------------------------------------------------------------------
+// Rows are N-word polynomials laid out back to back.  Row r uses modulus
+//   PERIODIC: mods[r % period]
+//   MODUP:    r = j * n + s (digit j, slot s < n): target t = s < j ? s : s+1,
+//             and t == n means the special prime (mods[n]); mods[] lists the
+//             moduli of q_0..q_{n-1}, P.
+struct RowMap {
+    int kind;          // 0 periodic, 1 modup
+    int period;        // periodic: period; modup: n
+    int mods[UH_MAX_MODULI];
+};
+
+__host__ __device__ __forceinline__ int rowmap_mod(const RowMap& m, int r)
+{
+    if (m.kind == 0) return m.mods[r % m.period];
+    int n = m.period;
+    int j = (r / n) % n, s = r % n;
+    int t = s < j ? s : s + 1;
+    return m.mods[t];
+}
+
+RowMap rowmap_ct(int n_limbs);                       // rows [..][n_limbs]: mod = limb
+RowMap rowmap_list(const std::vector<int>& mods);    // periodic over a list
+RowMap rowmap_modup(int n_limbs, int p_index);
+
+// -------------------------------------------------------------------------
+// launchers (all asynchronous on `stream`)
+// -------------------------------------------------------------------------
+void launch_ntt_fwd(const unihenn_ctx* c, u64* data, int n_rows, const RowMap& map, hipStream_t s);
+void launch_ntt_inv(const unihenn_ctx* c, u64* data, int n_rows, const RowMap& map, hipStream_t s);
+
+// kernel timing hooks (per kernel family), see unihenn_stats_*
+enum KernelFamily {
+    KF_NTT_FWD = 0, KF_NTT_INV, KF_MODUP, KF_KS_INNER, KF_MODDOWN, KF_RESCALE, KF_MAC, KF_AUTO,
+    KF_TENSOR, KF_ADD, KF_ENCODE, KF_OTHER, KF_COUNT
+};
+struct LaunchTimer {
+    LaunchTimer(KernelFamily f, double bytes, hipStream_t s);
+    ~LaunchTimer();
+    KernelFamily fam;
+    double bytes;
+    hipStream_t stream;
+    hipEvent_t ev0, ev1;
+    bool on;
+};
+void stats_collect();

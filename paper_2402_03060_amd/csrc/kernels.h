@@ -1,0 +1,53 @@
+// Launchers of the elementwise kernels (kernels.hip) and the NTT (ntt.hip).
+#pragma once
+#include "internal.h"
+
+#define UH_MAC_MAX_TERMS 32
+
+// up to UH_MAC_MAX_TERMS (ciphertext batch, plaintext) pairs, passed by value
+struct MacTerms {
+    const u64* ct[UH_MAC_MAX_TERMS];  // [B][2][nl][N]
+    const u64* pt[UH_MAC_MAX_TERMS];  // [nl][N], Montgomery form
+};
+
+void launch_automorphism(const unihenn_ctx* c, u64* out, const u64* in, int rows, u32 g, hipStream_t s);
+void launch_modup(const unihenn_ctx* c, u64* out, const u64* dcoef, int batch, int nl, hipStream_t s);
+void launch_ks_inner(const unihenn_ctx* c, u64* U, u64* Up, const u64* dntt, int d_stride, const u64* modup,
+                     const u64* key, int nd, int batch, int nl, u32 g, hipStream_t s);
+void launch_lift_last(const unihenn_ctx* c, u64* out, const u64* src, int n_src_rows, int nl, int src_mod,
+                      KernelFamily fam, hipStream_t s);
+void launch_sub_scale(const unihenn_ctx* c, u64* out, const u64* x, int x_limbs, const u64* r, const u64* inv,
+                      int n_polys, int nl, const u64* add0, const u64* add1, int add_stride, KernelFamily fam,
+                      hipStream_t s);
+void launch_gather_rows(const unihenn_ctx* c, u64* dst, const u64* src, int rows, int per, int src_stride, int off,
+                        hipStream_t s);
+void launch_mac(const unihenn_ctx* c, u64* acc, const MacTerms& terms, int n_terms, int nl, int batch, int accumulate,
+                hipStream_t s);
+void launch_tensor_square(const unihenn_ctx* c, u64* d0, u64* d1, u64* d2, const u64* ct, int batch, int nl,
+                          hipStream_t s);
+void launch_add(const unihenn_ctx* c, u64* out, const u64* a, const u64* b, int rows, int nl, hipStream_t s);
+void launch_add_plain(const unihenn_ctx* c, u64* out, const u64* a, const u64* pt, int batch, int nl, hipStream_t s);
+void launch_mont_convert(const unihenn_ctx* c, u64* data, int rows, const RowMap& map, int to_mont, hipStream_t s);
+
+// Galois element of a left rotation by `steps` slots: 5^(steps mod N/2) mod 2N
+u32 galois_elt(const unihenn_ctx* c, long steps);
+
+// ---- key switching core (evaluator.hip) ----
+// Workspace rows (of N words) needed by the evaluator for `batch` ciphertexts at nl limbs.
+size_t ks_ws_rows(int nl, int batch);
+struct KsWs {
+    u64* dcoef;   // [B][nl]       digits in coefficient form
+    u64* modup;   // [B][nl][nl]   digits extended to the other moduli (NTT form)
+    u64* U;       // [B][2][nl]    inner product, data limbs
+    u64* Up;      // [B][2]        inner product, special-prime limb
+    u64* R;       // [B][2][nl]    lifted special-prime limb
+    u64* aux;     // [B][3][nl]    automorphism / tensor temporaries
+};
+KsWs ks_ws_carve(u64* base, int nl, int batch, int n);
+// ModUp of d (NTT form, row (b, j) at d + (b * d_stride + j) * N)
+void ks_modup(const unihenn_ctx* c, const u64* d, int d_stride, int batch, int nl, KsWs& ws, hipStream_t s);
+// out[B][2][nl] = KS(tau_g(d)) after ks_modup(d), plus add0 on c = 0 and add1
+// on c = 1 (rows (b, i) at add + (b * add_stride + i) * N)
+void ks_finish(const unihenn_ctx* c, const u64* d, int d_stride, const u64* key, int nd, int batch, int nl, u32 g,
+               u64* out, const u64* add0, const u64* add1, int add_stride, KsWs& ws, hipStream_t s);
+void rescale_core(const unihenn_ctx* c, const u64* in, int batch, int nl, u64* out, KsWs& ws, hipStream_t s);

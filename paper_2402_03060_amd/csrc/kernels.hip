@@ -1,0 +1,345 @@
+// Elementwise kernels of the key-switching, rescaling and multiply-accumulate
+// path.  Every kernel is memory-streaming over limb rows of N words; threads
+// map to consecutive coefficients so each wavefront touches 512 contiguous
+// bytes of a row.
+#include "kernels.h"
+
+namespace {
+
+constexpr int EW_THREADS = 256;
+
+__device__ __forceinline__ u32 brev_bits(u32 x, int bits) { return __brev(x) >> (32 - bits); }
+
+// NTT-form automorphism: entry k of tau_g(a) is entry perm(k) of a, where
+// 2 brev(perm(k)) + 1 = g (2 brev(k) + 1) mod 2N.
+__device__ __forceinline__ u32 auto_perm(u32 k, u32 g, int log_n)
+{
+    u32 e = (u32)(((u64)g * (2u * brev_bits(k, log_n) + 1u)) & ((2u << log_n) - 1u));
+    return brev_bits((e - 1u) >> 1, log_n);
+}
+
+__global__ void k_automorphism(u64* __restrict__ out, const u64* __restrict__ in, int log_n, u32 g)
+{
+    const int n = 1 << log_n;
+    const u32 k = blockIdx.x * EW_THREADS + threadIdx.x;
+    if (k >= (u32)n) return;
+    const size_t row = blockIdx.y;
+    out[row * n + k] = in[row * n + auto_perm(k, g, log_n)];
+}
+
+// digits of the ModUp: out[b][j][s] = centered([d]_{q_j}) mod q_t, t = s < j ? s : s+1 (t = n: P)
+__global__ void k_modup(u64* __restrict__ out, const u64* __restrict__ dcoef, DevCtx ctx, const u64* __restrict__ qmod,
+                        int nl, int n_mod)
+{
+    const int n = ctx.n;
+    const int k = blockIdx.x * EW_THREADS + threadIdx.x;
+    if (k >= n) return;
+    const int r = blockIdx.y;  // (b * nl + j) * nl + s
+    const int s = r % nl, j = (r / nl) % nl, b = r / (nl * nl);
+    const int t = s < j ? s : s + 1;
+    const int tm = t == nl ? ctx.p_index : t;
+    const Modulus mt = ctx.mod[tm];
+    const u64 x = dcoef[((size_t)b * nl + j) * n + k];
+    out[(size_t)r * n + k] = centered_lift(x, ctx.mod[j].half, qmod[(size_t)j * n_mod + tm], mt.q, mt.ratio);
+}
+
+// U_c[t] = sum_j D_j[t] (*) evk_{j,c}[t] over t in {q_0..q_{nl-1}, P}.  D_j[j]
+// is limb j of the NTT-form input itself; the other targets come from the
+// ModUp rows.  With g != 1 the digits are read through the automorphism
+// permutation (hoisted rotation).  The thread keeps its 2 nl key words in
+// registers and loops over the batch.
+template <int MAXL>
+__global__ void __launch_bounds__(EW_THREADS) k_ks_inner(u64* __restrict__ U, u64* __restrict__ Up,
+                                                         const u64* __restrict__ dntt, int d_stride,
+                                                         const u64* __restrict__ modup, const u64* __restrict__ key,
+                                                         DevCtx ctx, int nl, int nd, int batch, u32 g)
+{
+    const int n = ctx.n;
+    const int k = blockIdx.x * EW_THREADS + threadIdx.x;
+    if (k >= n) return;
+    const int t = blockIdx.y;  // 0..nl
+    const int tm = t == nl ? ctx.p_index : t;
+    const int klimb = t == nl ? nd : t;
+    const Modulus M = ctx.mod[tm];
+    const u32 src = g == 1 ? (u32)k : auto_perm((u32)k, g, ctx.log_n);
+    u64 k0[MAXL], k1[MAXL];
+#pragma unroll
+    for (int j = 0; j < MAXL; ++j) {
+        if (j < nl) {
+            k0[j] = key[(((size_t)j * 2 + 0) * (nd + 1) + klimb) * n + k];
+            k1[j] = key[(((size_t)j * 2 + 1) * (nd + 1) + klimb) * n + k];
+        }
+    }
+    for (int b = 0; b < batch; ++b) {
+        u64 a0 = 0, a1 = 0;
+#pragma unroll
+        for (int j = 0; j < MAXL; ++j) {
+            if (j < nl) {
+                u64 d;
+                if (t == j) {
+                    d = dntt[((size_t)b * d_stride + j) * n + src];
+                } else {
+                    const int s = t < j ? t : t - 1;
+                    d = modup[(((size_t)b * nl + j) * nl + s) * n + src];
+                }
+                a0 = add_mod(a0, mont_mul(d, k0[j], M.q, M.qinv_neg), M.q);
+                a1 = add_mod(a1, mont_mul(d, k1[j], M.q, M.qinv_neg), M.q);
+            }
+        }
+        if (t < nl) {
+            U[(((size_t)b * 2 + 0) * nl + t) * n + k] = a0;
+            U[(((size_t)b * 2 + 1) * nl + t) * n + k] = a1;
+        } else {
+            Up[((size_t)b * 2 + 0) * n + k] = a0;
+            Up[((size_t)b * 2 + 1) * n + k] = a1;
+        }
+    }
+}
+
+// out[row = p * nl + i] = centered(src[p]) mod q_i, src rows in the modulus
+// src_mod (P for ModDown, q_l for rescale)
+__global__ void k_lift_last(u64* __restrict__ out, const u64* __restrict__ src, DevCtx ctx,
+                            const u64* __restrict__ qmod, int n_mod, int nl, int src_mod)
+{
+    const int n = ctx.n;
+    const int k = blockIdx.x * EW_THREADS + threadIdx.x;
+    if (k >= n) return;
+    const int r = blockIdx.y;
+    const int i = r % nl, p = r / nl;
+    const Modulus mi = ctx.mod[i];
+    out[(size_t)r * n + k] = centered_lift(src[(size_t)p * n + k], ctx.mod[src_mod].half,
+                                           qmod[(size_t)src_mod * n_mod + i], mi.q, mi.ratio);
+}
+
+// out[p][i] = (x[p][i] - r[p][i]) * inv_i (+ add_c[b][i]),  p = b * 2 + c,
+// x rows have stride x_limbs per polynomial, out and r have nl.
+__global__ void k_sub_scale(u64* __restrict__ out, const u64* __restrict__ x, int x_limbs, const u64* __restrict__ r,
+                            const u64* __restrict__ inv, DevCtx ctx, int nl, const u64* __restrict__ add0,
+                            const u64* __restrict__ add1, int add_stride)
+{
+    const int n = ctx.n;
+    const int k = blockIdx.x * EW_THREADS + threadIdx.x;
+    if (k >= n) return;
+    const int row = blockIdx.y;
+    const int i = row % nl, p = row / nl;
+    const int b = p >> 1, c = p & 1;
+    const u64 q = ctx.mod[i].q;
+    u64 v = sub_mod(x[((size_t)p * x_limbs + i) * n + k], r[(size_t)row * n + k], q);
+    v = mul_shoup(v, inv[2 * i], inv[2 * i + 1], q);
+    const u64* add = c == 0 ? add0 : add1;
+    if (add) v = add_mod(v, add[((size_t)b * add_stride + i) * n + k], q);
+    out[(size_t)row * n + k] = v;
+}
+
+// dst row r <- src row (r / per) * src_stride + r % per + off
+__global__ void k_gather_rows(u64* __restrict__ dst, const u64* __restrict__ src, int n, int per, int src_stride,
+                              int off)
+{
+    const int k = blockIdx.x * EW_THREADS + threadIdx.x;
+    if (k >= n) return;
+    const int r = blockIdx.y;
+    const size_t sr = (size_t)(r / per) * src_stride + r % per + off;
+    dst[(size_t)r * n + k] = src[sr * n + k];
+}
+
+template <int BCH>
+__global__ void __launch_bounds__(EW_THREADS) k_mac(u64* __restrict__ acc, MacTerms terms, int n_terms, DevCtx ctx,
+                                                    int nl, int batch, int accumulate)
+{
+    const int n = ctx.n;
+    const int k = blockIdx.x * EW_THREADS + threadIdx.x;
+    if (k >= n) return;
+    const int i = blockIdx.y;
+    const int b0 = blockIdx.z * BCH;
+    const Modulus M = ctx.mod[i];
+    u64 a[2 * BCH];
+#pragma unroll
+    for (int u = 0; u < 2 * BCH; ++u) a[u] = 0;
+    if (accumulate) {
+#pragma unroll
+        for (int u = 0; u < 2 * BCH; ++u) {
+            const int b = b0 + u / 2, c = u & 1;
+            if (b < batch) a[u] = acc[(((size_t)b * 2 + c) * nl + i) * n + k];
+        }
+    }
+    for (int t = 0; t < n_terms; ++t) {
+        const u64 p = terms.pt[t][(size_t)i * n + k];
+        const u64* ct = terms.ct[t];
+#pragma unroll
+        for (int u = 0; u < 2 * BCH; ++u) {
+            const int b = b0 + u / 2, c = u & 1;
+            if (b < batch) {
+                const u64 v = ct[(((size_t)b * 2 + c) * nl + i) * n + k];
+                a[u] = add_mod(a[u], mont_mul(p, v, M.q, M.qinv_neg), M.q);
+            }
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < 2 * BCH; ++u) {
+        const int b = b0 + u / 2, c = u & 1;
+        if (b < batch) acc[(((size_t)b * 2 + c) * nl + i) * n + k] = a[u];
+    }
+}
+
+// (c0, c1) -> d0 = c0^2, d1 = 2 c0 c1, d2 = c1^2, each [B][nl][N]
+__global__ void k_tensor_square(u64* __restrict__ d0, u64* __restrict__ d1, u64* __restrict__ d2,
+                                const u64* __restrict__ ct, DevCtx ctx, int nl)
+{
+    const int n = ctx.n;
+    const int k = blockIdx.x * EW_THREADS + threadIdx.x;
+    if (k >= n) return;
+    const int r = blockIdx.y;  // b * nl + i
+    const int i = r % nl, b = r / nl;
+    const Modulus M = ctx.mod[i];
+    const u64 c0 = ct[(((size_t)b * 2 + 0) * nl + i) * n + k];
+    const u64 c1 = ct[(((size_t)b * 2 + 1) * nl + i) * n + k];
+    // x y = mont(mont(x, y), 2^128 mod q)
+    const u64 s00 = mont_mul(mont_mul(c0, c0, M.q, M.qinv_neg), M.r2, M.q, M.qinv_neg);
+    const u64 s01 = mont_mul(mont_mul(c0, c1, M.q, M.qinv_neg), M.r2, M.q, M.qinv_neg);
+    const u64 s11 = mont_mul(mont_mul(c1, c1, M.q, M.qinv_neg), M.r2, M.q, M.qinv_neg);
+    d0[(size_t)r * n + k] = s00;
+    d1[(size_t)r * n + k] = add_mod(s01, s01, M.q);
+    d2[(size_t)r * n + k] = s11;
+}
+
+// out = a + b over rows with modulus = row % nl
+__global__ void k_add(u64* __restrict__ out, const u64* __restrict__ a, const u64* __restrict__ b, DevCtx ctx, int nl)
+{
+    const int n = ctx.n;
+    const int k = blockIdx.x * EW_THREADS + threadIdx.x;
+    if (k >= n) return;
+    const size_t r = blockIdx.y;
+    const u64 q = ctx.mod[r % nl].q;
+    out[r * n + k] = add_mod(a[r * n + k], b[r * n + k], q);
+}
+
+// c0 of every ciphertext += pt ([nl][N]); c1 copied when out != a
+__global__ void k_add_plain(u64* __restrict__ out, const u64* __restrict__ a, const u64* __restrict__ pt, DevCtx ctx,
+                            int nl)
+{
+    const int n = ctx.n;
+    const int k = blockIdx.x * EW_THREADS + threadIdx.x;
+    if (k >= n) return;
+    const int r = blockIdx.y;  // (b * 2 + c) * nl + i
+    const int i = r % nl, c = (r / nl) & 1;
+    const u64 q = ctx.mod[i].q;
+    u64 v = a[(size_t)r * n + k];
+    if (c == 0) v = add_mod(v, pt[(size_t)i * n + k], q);
+    out[(size_t)r * n + k] = v;
+}
+
+// x -> x 2^64 mod q (to_mont) or x 2^-64 mod q (from_mont), modulus by row map
+__global__ void k_mont_convert(u64* __restrict__ data, DevCtx ctx, RowMap map, int to_mont)
+{
+    const int n = ctx.n;
+    const int k = blockIdx.x * EW_THREADS + threadIdx.x;
+    if (k >= n) return;
+    const size_t r = blockIdx.y;
+    const Modulus M = ctx.mod[rowmap_mod(map, (int)r)];
+    const u64 x = data[r * n + k];
+    data[r * n + k] = mont_mul(x, to_mont ? M.r2 : 1, M.q, M.qinv_neg);
+}
+
+inline dim3 grid_rows(int n, int rows, int z = 1) { return dim3((n + EW_THREADS - 1) / EW_THREADS, rows, z); }
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+void launch_automorphism(const unihenn_ctx* c, u64* out, const u64* in, int rows, u32 g, hipStream_t s)
+{
+    if (rows <= 0) return;
+    LaunchTimer tm(KF_AUTO, 16.0 * c->n * rows, s);
+    k_automorphism<<<grid_rows(c->n, rows), EW_THREADS, 0, s>>>(out, in, c->log_n, g);
+}
+
+void launch_modup(const unihenn_ctx* c, u64* out, const u64* dcoef, int batch, int nl, hipStream_t s)
+{
+    int rows = batch * nl * nl;
+    LaunchTimer tm(KF_MODUP, 8.0 * c->n * (batch * nl + rows), s);
+    k_modup<<<grid_rows(c->n, rows), EW_THREADS, 0, s>>>(out, dcoef, c->dev, c->d_qmod, nl,
+                                                         (int)c->primes.size());
+}
+
+void launch_ks_inner(const unihenn_ctx* c, u64* U, u64* Up, const u64* dntt, int d_stride, const u64* modup,
+                     const u64* key, int nd, int batch, int nl, u32 g, hipStream_t s)
+{
+    // algorithmic bytes: key limbs (2 nl (nl+1)), digits (nl (nl+1) per ct), output 2 (nl+1) per ct
+    double rows = 2.0 * nl * (nl + 1) + (double)batch * (nl * (nl + 1) + 2 * (nl + 1));
+    LaunchTimer tm(KF_KS_INNER, 8.0 * c->n * rows, s);
+    dim3 g3 = grid_rows(c->n, nl + 1);
+    if (nl <= 4)
+        k_ks_inner<4><<<g3, EW_THREADS, 0, s>>>(U, Up, dntt, d_stride, modup, key, c->dev, nl, nd, batch, g);
+    else if (nl <= 8)
+        k_ks_inner<8><<<g3, EW_THREADS, 0, s>>>(U, Up, dntt, d_stride, modup, key, c->dev, nl, nd, batch, g);
+    else if (nl <= 12)
+        k_ks_inner<12><<<g3, EW_THREADS, 0, s>>>(U, Up, dntt, d_stride, modup, key, c->dev, nl, nd, batch, g);
+    else
+        k_ks_inner<UH_MAX_MODULI><<<g3, EW_THREADS, 0, s>>>(U, Up, dntt, d_stride, modup, key, c->dev, nl, nd, batch, g);
+}
+
+void launch_lift_last(const unihenn_ctx* c, u64* out, const u64* src, int n_src_rows, int nl, int src_mod,
+                      KernelFamily fam, hipStream_t s)
+{
+    int rows = n_src_rows * nl;
+    LaunchTimer tm(fam, 8.0 * c->n * (n_src_rows + rows), s);
+    k_lift_last<<<grid_rows(c->n, rows), EW_THREADS, 0, s>>>(out, src, c->dev, c->d_qmod, (int)c->primes.size(), nl,
+                                                             src_mod);
+}
+
+void launch_sub_scale(const unihenn_ctx* c, u64* out, const u64* x, int x_limbs, const u64* r, const u64* inv,
+                      int n_polys, int nl, const u64* add0, const u64* add1, int add_stride, KernelFamily fam,
+                      hipStream_t s)
+{
+    int rows = n_polys * nl;
+    LaunchTimer tm(fam, 8.0 * c->n * rows * (3 + (add0 ? 0.5 : 0) + (add1 ? 0.5 : 0)), s);
+    k_sub_scale<<<grid_rows(c->n, rows), EW_THREADS, 0, s>>>(out, x, x_limbs, r, inv, c->dev, nl, add0, add1, add_stride);
+}
+
+void launch_gather_rows(const unihenn_ctx* c, u64* dst, const u64* src, int rows, int per, int src_stride, int off,
+                        hipStream_t s)
+{
+    if (rows <= 0) return;
+    LaunchTimer tm(KF_OTHER, 16.0 * c->n * rows, s);
+    k_gather_rows<<<grid_rows(c->n, rows), EW_THREADS, 0, s>>>(dst, src, c->n, per, src_stride, off);
+}
+
+void launch_mac(const unihenn_ctx* c, u64* acc, const MacTerms& terms, int n_terms, int nl, int batch, int accumulate,
+                hipStream_t s)
+{
+    // algorithmic bytes: plaintexts once, ciphertexts once, acc written (and read when accumulating)
+    double rows = (double)n_terms * nl + (double)n_terms * batch * 2 * nl + (1 + accumulate) * batch * 2.0 * nl;
+    LaunchTimer tm(KF_MAC, 8.0 * c->n * rows, s);
+    if (batch >= 4) {
+        k_mac<4><<<grid_rows(c->n, nl, (batch + 3) / 4), EW_THREADS, 0, s>>>(acc, terms, n_terms, c->dev, nl, batch,
+                                                                             accumulate);
+    } else {
+        k_mac<1><<<grid_rows(c->n, nl, batch), EW_THREADS, 0, s>>>(acc, terms, n_terms, c->dev, nl, batch,
+                                                                   accumulate);
+    }
+}
+
+void launch_tensor_square(const unihenn_ctx* c, u64* d0, u64* d1, u64* d2, const u64* ct, int batch, int nl,
+                          hipStream_t s)
+{
+    LaunchTimer tm(KF_TENSOR, 8.0 * c->n * batch * nl * 5, s);
+    k_tensor_square<<<grid_rows(c->n, batch * nl), EW_THREADS, 0, s>>>(d0, d1, d2, ct, c->dev, nl);
+}
+
+void launch_add(const unihenn_ctx* c, u64* out, const u64* a, const u64* b, int rows, int nl, hipStream_t s)
+{
+    LaunchTimer tm(KF_ADD, 24.0 * c->n * rows, s);
+    k_add<<<grid_rows(c->n, rows), EW_THREADS, 0, s>>>(out, a, b, c->dev, nl);
+}
+
+void launch_add_plain(const unihenn_ctx* c, u64* out, const u64* a, const u64* pt, int batch, int nl, hipStream_t s)
+{
+    LaunchTimer tm(KF_ADD, 8.0 * c->n * (batch * 4.0 * nl + nl), s);
+    k_add_plain<<<grid_rows(c->n, batch * 2 * nl), EW_THREADS, 0, s>>>(out, a, pt, c->dev, nl);
+}
+
+void launch_mont_convert(const unihenn_ctx* c, u64* data, int rows, const RowMap& map, int to_mont, hipStream_t s)
+{
+    if (rows <= 0) return;
+    LaunchTimer tm(KF_OTHER, 16.0 * c->n * rows, s);
+    k_mont_convert<<<grid_rows(c->n, rows), EW_THREADS, 0, s>>>(data, c->dev, map, to_mont);
+}

@@ -1,0 +1,87 @@
+// Modular arithmetic on 64-bit residues for primes q < 2^61, built from the
+// 32-bit integer ALUs of CDNA4 (the compiler lowers each 64x64 product to
+// v_mad_u64_u32 / v_mul_hi_u32 sequences).
+//
+//   mul_shoup   x * w mod q for a fixed w with w' = floor(w 2^64 / q)
+//               (Shoup's method): result in [0, 2q) for any 64-bit x.
+//   mont_mul    a * b * 2^-64 mod q (Montgomery, R = 2^64): used where one
+//               operand is stored pre-multiplied by R (keys, plaintexts).
+//   reduce64    x mod q for any 64-bit x, with r = floor(2^64 / q).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+typedef uint64_t u64;
+typedef uint32_t u32;
+typedef int64_t i64;
+
+// Per-prime constants, resident in device memory.
+struct Modulus {
+    u64 q;
+    u64 ratio;     // floor(2^64 / q)
+    u64 qinv_neg;  // -q^-1 mod 2^64
+    u64 r2;        // 2^128 mod q  (mont_mul(x, r2) = x * 2^64 mod q)
+    u64 half;      // (q - 1) / 2
+    u64 n_inv;     // N^-1 mod q
+    u64 n_inv_sh;  // Shoup companion of n_inv
+    u64 pad;
+};
+
+__host__ __device__ __forceinline__ u64 umulhi64(u64 a, u64 b)
+{
+#ifdef __HIP_DEVICE_COMPILE__
+    return __umul64hi(a, b);
+#else
+    return (u64)(((unsigned __int128)a * b) >> 64);
+#endif
+}
+
+__host__ __device__ __forceinline__ u64 add_mod(u64 a, u64 b, u64 q)
+{
+    u64 s = a + b;
+    return s >= q ? s - q : s;
+}
+
+__host__ __device__ __forceinline__ u64 sub_mod(u64 a, u64 b, u64 q)
+{
+    return a >= b ? a - b : a + q - b;
+}
+
+__host__ __device__ __forceinline__ u64 csub(u64 a, u64 q) { return a >= q ? a - q : a; }
+
+// [0, 2q) result
+__host__ __device__ __forceinline__ u64 mul_shoup_lazy(u64 x, u64 w, u64 w_sh, u64 q)
+{
+    u64 qh = umulhi64(x, w_sh);
+    return x * w - qh * q;
+}
+
+__host__ __device__ __forceinline__ u64 mul_shoup(u64 x, u64 w, u64 w_sh, u64 q)
+{
+    return csub(mul_shoup_lazy(x, w, w_sh, q), q);
+}
+
+// a, b < q: returns a b 2^-64 mod q in [0, q)
+__host__ __device__ __forceinline__ u64 mont_mul(u64 a, u64 b, u64 q, u64 qinv_neg)
+{
+    u64 lo = a * b;
+    u64 hi = umulhi64(a, b);
+    u64 m = lo * qinv_neg;
+    u64 u = hi + umulhi64(m, q) + (lo != 0);
+    return csub(u, q);
+}
+
+// any 64-bit x -> x mod q
+__host__ __device__ __forceinline__ u64 reduce64(u64 x, u64 q, u64 ratio)
+{
+    u64 qh = umulhi64(x, ratio);
+    return csub(x - qh * q, q);
+}
+
+// x is a residue mod p (odd); lift it to the centered range (-p/2, p/2) and
+// reduce that integer mod q.  p_mod_q = p mod q.
+__host__ __device__ __forceinline__ u64 centered_lift(u64 x, u64 p_half, u64 p_mod_q, u64 q, u64 ratio)
+{
+    u64 r = reduce64(x, q, ratio);
+    return x > p_half ? sub_mod(r, p_mod_q, q) : r;
+}

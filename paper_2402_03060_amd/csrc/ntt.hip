@@ -1,0 +1,199 @@
+// Negacyclic NTT / inverse NTT of batched limb rows.
+//
+// Forward: Cooley-Tukey butterflies with the 2N-th root psi merged into the
+// twiddles (stage s uses psi^brev(2^s + i)), output in bit-reversed order,
+// so that entry k holds a(psi^(2 brev(k) + 1)).  Inverse: Gentleman-Sande
+// butterflies with psi^-brev(.), then the factor N^-1.  Values stay lazily
+// reduced (forward in [0, 4q), inverse in [0, 2q)) and are made canonical
+// at the end; q < 2^61 keeps every intermediate below 2^64.
+//
+// The log N stages are split into two passes over LDS tiles:
+//   column pass  stages [0, L1): 2^L1-point transforms of elements strided by
+//                N / 2^L1; a tile holds COLS consecutive columns so every
+//                global row access is COLS contiguous words;
+//   row pass     stages [L1, log N): contiguous 2^(log N - L1)-point blocks.
+// Each tile is TILE words (16 KiB) of LDS; 256 threads, one butterfly per
+// thread per four-butterfly slice of a stage.
+#include "internal.h"
+
+namespace {
+
+constexpr int TILE = 2048;
+constexpr int NTT_THREADS = 256;
+
+struct PassGeom {
+    int log_r;    // log2 of the sub-transform size
+    int cols;     // sub-transforms per tile
+    int sigma0;   // first global stage of the pass
+    bool strided; // column pass
+};
+
+__device__ __forceinline__ int lds_index(bool strided, int u, int c, int cols, int r)
+{
+    return strided ? u * cols + c : c * r + u;
+}
+
+template <bool STRIDED, bool LAST>
+__global__ void __launch_bounds__(NTT_THREADS) k_ntt_fwd(u64* __restrict__ data, DevCtx ctx, RowMap map,
+                                                         int log_r, int cols, int sigma0)
+{
+    __shared__ u64 s[TILE];
+    const int n = ctx.n, log_n = ctx.log_n;
+    const int r = 1 << log_r;
+    const int row = blockIdx.y;
+    const int mi = rowmap_mod(map, row);
+    const u64 q = ctx.mod[mi].q, q2 = 2 * q;
+    const u64* tw = ctx.tw + (size_t)mi * n;
+    const u64* tw_sh = ctx.tw_sh + (size_t)mi * n;
+    u64* a = data + (size_t)row * n;
+    const int tid = threadIdx.x;
+    const int elems = r * cols;
+    const int col0 = blockIdx.x * cols;  // first column (strided) or first block (contiguous)
+    const int stride = n >> log_r;
+
+    for (int e = tid; e < elems; e += NTT_THREADS) {
+        if (STRIDED) {
+            int c = e % cols, u = e / cols;
+            s[e] = a[col0 + c + (size_t)u * stride];
+        } else {
+            s[e] = a[(size_t)col0 * r + e];
+        }
+    }
+    __syncthreads();
+    for (int tau = 0; tau < log_r; ++tau) {
+        const int sigma = sigma0 + tau;
+        const int hb = log_r - tau - 1;  // half-size bit
+        const int t = 1 << hb;
+        for (int b = tid; b < elems / 2; b += NTT_THREADS) {
+            int c, p;
+            if (STRIDED) { c = b % cols; p = b / cols; }
+            else { c = b / (r / 2); p = b % (r / 2); }
+            const int u = ((p >> hb) << (hb + 1)) | (p & (t - 1));
+            const int j = STRIDED ? (col0 + c) + u * stride : (col0 + c) * r + u;  // global index
+            const int ti = (1 << sigma) + (j >> (log_n - sigma));
+            const int i0 = lds_index(STRIDED, u, c, cols, r), i1 = lds_index(STRIDED, u + t, c, cols, r);
+            u64 U = s[i0];
+            U = U >= q2 ? U - q2 : U;
+            const u64 V = mul_shoup_lazy(s[i1], tw[ti], tw_sh[ti], q);
+            s[i0] = U + V;
+            s[i1] = U - V + q2;
+        }
+        __syncthreads();
+    }
+    for (int e = tid; e < elems; e += NTT_THREADS) {
+        u64 v = s[e];
+        if (LAST) {
+            v = v >= q2 ? v - q2 : v;
+            v = v >= q ? v - q : v;
+        }
+        if (STRIDED) {
+            int c = e % cols, u = e / cols;
+            a[col0 + c + (size_t)u * stride] = v;
+        } else {
+            a[(size_t)col0 * r + e] = v;
+        }
+    }
+}
+
+template <bool STRIDED, bool LAST>
+__global__ void __launch_bounds__(NTT_THREADS) k_ntt_inv(u64* __restrict__ data, DevCtx ctx, RowMap map,
+                                                         int log_r, int cols, int sigma0)
+{
+    __shared__ u64 s[TILE];
+    const int n = ctx.n, log_n = ctx.log_n;
+    const int r = 1 << log_r;
+    const int row = blockIdx.y;
+    const int mi = rowmap_mod(map, row);
+    const Modulus M = ctx.mod[mi];
+    const u64 q = M.q, q2 = 2 * q;
+    const u64* tw = ctx.itw + (size_t)mi * n;
+    const u64* tw_sh = ctx.itw_sh + (size_t)mi * n;
+    u64* a = data + (size_t)row * n;
+    const int tid = threadIdx.x;
+    const int elems = r * cols;
+    const int col0 = blockIdx.x * cols;
+    const int stride = n >> log_r;
+
+    for (int e = tid; e < elems; e += NTT_THREADS) {
+        if (STRIDED) {
+            int c = e % cols, u = e / cols;
+            s[e] = a[col0 + c + (size_t)u * stride];
+        } else {
+            s[e] = a[(size_t)col0 * r + e];
+        }
+    }
+    __syncthreads();
+    for (int tau = log_r - 1; tau >= 0; --tau) {
+        const int sigma = sigma0 + tau;
+        const int hb = log_r - tau - 1;
+        const int t = 1 << hb;
+        for (int b = tid; b < elems / 2; b += NTT_THREADS) {
+            int c, p;
+            if (STRIDED) { c = b % cols; p = b / cols; }
+            else { c = b / (r / 2); p = b % (r / 2); }
+            const int u = ((p >> hb) << (hb + 1)) | (p & (t - 1));
+            const int j = STRIDED ? (col0 + c) + u * stride : (col0 + c) * r + u;
+            const int ti = (1 << sigma) + (j >> (log_n - sigma));
+            const int i0 = lds_index(STRIDED, u, c, cols, r), i1 = lds_index(STRIDED, u + t, c, cols, r);
+            const u64 U = s[i0], V = s[i1];
+            u64 x = U + V;
+            s[i0] = x >= q2 ? x - q2 : x;
+            s[i1] = mul_shoup_lazy(U - V + q2, tw[ti], tw_sh[ti], q);
+        }
+        __syncthreads();
+    }
+    for (int e = tid; e < elems; e += NTT_THREADS) {
+        u64 v = s[e];
+        if (LAST) v = mul_shoup(v, M.n_inv, M.n_inv_sh, q);
+        if (STRIDED) {
+            int c = e % cols, u = e / cols;
+            a[col0 + c + (size_t)u * stride] = v;
+        } else {
+            a[(size_t)col0 * r + e] = v;
+        }
+    }
+}
+
+void split(int log_n, int* l1, int* l2)
+{
+    *l1 = log_n / 2;
+    *l2 = log_n - *l1;
+}
+
+int tile_cols(int log_r, int log_n)
+{
+    int r = 1 << log_r;
+    int cols = TILE / r;
+    int avail = 1 << (log_n - log_r);
+    return cols < avail ? cols : avail;
+}
+
+}  // namespace
+
+void launch_ntt_fwd(const unihenn_ctx* c, u64* data, int n_rows, const RowMap& map, hipStream_t st)
+{
+    if (n_rows <= 0) return;
+    int l1, l2;
+    split(c->log_n, &l1, &l2);
+    LaunchTimer tm(KF_NTT_FWD, 16.0 * c->n * n_rows, st);
+    int cols1 = tile_cols(l1, c->log_n);
+    dim3 g1((1 << (c->log_n - l1)) / cols1, n_rows);
+    k_ntt_fwd<true, false><<<g1, NTT_THREADS, 0, st>>>(data, c->dev, map, l1, cols1, 0);
+    int cols2 = tile_cols(l2, c->log_n);
+    dim3 g2((1 << (c->log_n - l2)) / cols2, n_rows);
+    k_ntt_fwd<false, true><<<g2, NTT_THREADS, 0, st>>>(data, c->dev, map, l2, cols2, l1);
+}
+
+void launch_ntt_inv(const unihenn_ctx* c, u64* data, int n_rows, const RowMap& map, hipStream_t st)
+{
+    if (n_rows <= 0) return;
+    int l1, l2;
+    split(c->log_n, &l1, &l2);
+    LaunchTimer tm(KF_NTT_INV, 16.0 * c->n * n_rows, st);
+    int cols2 = tile_cols(l2, c->log_n);
+    dim3 g2((1 << (c->log_n - l2)) / cols2, n_rows);
+    k_ntt_inv<false, false><<<g2, NTT_THREADS, 0, st>>>(data, c->dev, map, l2, cols2, l1);
+    int cols1 = tile_cols(l1, c->log_n);
+    dim3 g1((1 << (c->log_n - l1)) / cols1, n_rows);
+    k_ntt_inv<true, true><<<g1, NTT_THREADS, 0, st>>>(data, c->dev, map, l1, cols1, 0);
+}

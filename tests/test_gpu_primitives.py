@@ -1,0 +1,146 @@
+"""GPU parity of the CKKS primitives against the CPU oracle: every output is
+compared in coefficient form, residue by residue (bit-exact)."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import workloads as W
+from tests.gpu_util import gpu_ctx_for, ocat, oracle_ring, random_ct
+
+pytestmark = pytest.mark.gpu
+
+RINGS = {
+    "n16": W.TINY_RINGS["n16"],
+    "n1024": W.TINY_RINGS["n1024"],
+    "n8192": {"log_n": 13, "prime_bits": [60, 40, 40], "special_bits": 60, "log_scale": 40},
+}
+
+
+@pytest.fixture(scope="module", params=list(RINGS))
+def pair(request):
+    ring = RINGS[request.param]
+    ck = oracle_ring(ring)
+    ctx = gpu_ctx_for(ck, ring)
+    return ck, ctx, ring
+
+
+@pytest.mark.parametrize("log_n", [4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15])
+def test_ntt_roundtrip_all_sizes(log_n):
+    import torch
+    from paper_2402_03060_amd import Context, device_u64, host_u64
+    bits = [60, 40, 40]
+    ctx = Context(log_n, bits, 60, 2.0 ** 40)
+    rng = np.random.default_rng(log_n)
+    a = np.stack([np.stack([rng.integers(0, q, ctx.n, dtype=np.uint64) for q in ctx.primes]) for _ in range(3)])
+    t = device_u64(a)
+    ctx.to_ntt(t, 3, 3)
+    ntt = host_u64(t.clone())
+    ctx.from_ntt(t, 3, 3)
+    torch.cuda.synchronize()
+    assert np.array_equal(host_u64(t), a)
+    for i, q in enumerate(ctx.primes):
+        assert int(ntt[:, i].max()) < q  # canonical residues
+
+
+def test_mac_parity(pair):
+    ck, ctx, _ = pair
+    nl = len(ck.primes)
+    cts = [random_ct(ck, nl, 100 + t)[0] for t in range(3)]
+    pts = [np.stack([np.random.default_rng(200 + t).integers(0, q, ck.n, dtype=np.uint64) for q in ck.primes])
+           for t in range(3)]
+    exp = ck.mac_matrix([ocat(c) for c in cts], [pts])[0]
+    g = ctx.mul_plain_acc([ctx.import_ct(c, 1.0) for c in cts], [ctx.import_pt(p) for p in pts])
+    assert np.array_equal(ctx.export_ct(g)[0], exp)
+
+
+@pytest.mark.parametrize("steps", [1, 3, -2, 5])
+def test_rotate_parity(pair, steps):
+    ck, ctx, _ = pair
+    z = W.gen_slots(ck.slots, 1, seed=31)[0]
+    ct = ck.encrypt(z, 32)
+    key = ck.rotation_key(steps)
+    hk = ck.load_key(key)
+    gkey = ctx.import_evk(key)
+    for nl in sorted({len(ck.primes), 2}):
+        oct_ = ck.limb_drop(ct, nl)
+        exp = ck.rotate(oct_, steps, hk)
+        ws = ctx.workspace(nl, 1)
+        got = ctx.rotate(ctx.import_ct(oct_.data, oct_.scale), steps, gkey, ws)
+        assert np.array_equal(ctx.export_ct(got)[0], exp.data)
+
+
+def test_rotate_hoisted_parity(pair):
+    ck, ctx, _ = pair
+    z = W.gen_slots(ck.slots, 1, seed=33)[0]
+    ct = ck.encrypt(z, 34)
+    rs = [1, 2, -1, 0]
+    keys = {r: ck.rotation_key(r) for r in rs if r}
+    gct = ctx.import_ct(ct.data, ct.scale)
+    ws = ctx.workspace(len(ck.primes), 1)
+    outs = ctx.rotate_hoisted(gct, rs, [ctx.import_evk(keys[r]) if r else None for r in rs], ws)
+    for r, o in zip(rs, outs):
+        exp = ck.rotate(ct, r, ck.load_key(keys[r])).data if r else ct.data
+        assert np.array_equal(ctx.export_ct(o)[0], exp)
+
+
+def test_rescale_parity(pair):
+    ck, ctx, _ = pair
+    nl = len(ck.primes)
+    a = random_ct(ck, nl, 41, batch=2)
+    ws = ctx.workspace(nl, 2)
+    got = ctx.export_ct(ctx.rescale(ctx.import_ct(a, 1.0), ws))
+    for b in range(2):
+        assert np.array_equal(got[b], ck.rescale(ocat(a[b])).data)
+
+
+def test_square_relin_parity(pair):
+    ck, ctx, _ = pair
+    z = W.gen_slots(ck.slots, 1, seed=35)[0]
+    ct = ck.encrypt(z, 36)
+    rk = ck.relin_key()
+    exp = ck.square_relin(ct, ck.load_key(rk))
+    ws = ctx.workspace(len(ck.primes), 1)
+    got = ctx.square_relin(ctx.import_ct(ct.data, ct.scale), ctx.import_evk(rk), ws)
+    assert np.array_equal(ctx.export_ct(got)[0], exp.data)
+    assert got.scale == exp.scale
+
+
+def test_add_and_add_plain_parity(pair):
+    ck, ctx, _ = pair
+    nl = len(ck.primes)
+    a, b = random_ct(ck, nl, 51)[0], random_ct(ck, nl, 52)[0]
+    got = ctx.export_ct(ctx.add(ctx.import_ct(a, 1.0), ctx.import_ct(b, 1.0)))[0]
+    assert np.array_equal(got, ck.add(ocat(a), ocat(b)).data)
+    pt = np.stack([np.random.default_rng(53).integers(0, q, ck.n, dtype=np.uint64) for q in ck.primes])
+    got = ctx.export_ct(ctx.add_plain(ctx.import_ct(a, 1.0), ctx.import_pt(pt, mont=False)))[0]
+    assert np.array_equal(got, ck.add_plain(ocat(a), pt).data)
+
+
+@pytest.mark.parametrize("kind", ["dense", "mask", "bias_scale"])
+def test_encode_parity(pair, kind):
+    ck, ctx, _ = pair
+    nl = len(ck.primes)
+    rng = np.random.default_rng(61)
+    if kind == "dense":
+        z, scale = rng.uniform(-1, 1, ck.slots), ck.delta
+    elif kind == "mask":
+        z = np.zeros(ck.slots)
+        z[rng.choice(ck.slots, size=max(1, ck.slots // 7), replace=False)] = rng.normal(0, 0.1)
+        scale = ck.delta
+    else:
+        z = np.zeros(ck.slots)
+        z[: max(1, ck.slots // 3)] = rng.normal(0, 0.01)
+        scale = ck.delta * 1.0000013283  # a non-power-of-two scale, as after a rescale
+    exp = ck.encode(z, scale, nl)
+    for mont in (False, True):
+        got = ctx.export_pt(ctx.encode(z, scale, nl, mont=mont), mont=mont)
+        assert np.array_equal(got, exp)
+
+
+def test_mod_drop(pair):
+    ck, ctx, _ = pair
+    nl = len(ck.primes)
+    a = random_ct(ck, nl, 71, batch=2)
+    got = ctx.export_ct(ctx.mod_drop(ctx.import_ct(a, 1.0), 1))
+    assert np.array_equal(got, a[:, :, :1, :])
