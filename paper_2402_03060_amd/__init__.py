@@ -325,3 +325,130 @@ def stats() -> dict:
         _check(lib().unihenn_stats_get(i, C.byref(n), C.byref(ms), C.byref(by)))
         out[name] = (int(n.value), float(ms.value), float(by.value))
     return out
+
+
+# ---------------------------------------------------------------- client
+def keygen_secret(ctx: Context, seed: int) -> torch.Tensor:
+    sk = torch.empty((ctx.n_data + 1, ctx.n), dtype=torch.int64, device="cuda")
+    _check(lib().unihenn_keygen_secret(ctx.h, seed, sk.data_ptr(), _stream()))
+    return sk
+
+
+def gen_switch_key(ctx: Context, sk: torch.Tensor, seed: int, steps: int = 0, relin: bool = False) -> torch.Tensor:
+    nd = ctx.n_data
+    out = torch.empty((nd, 2, nd + 1, ctx.n), dtype=torch.int64, device="cuda")
+    _check(lib().unihenn_gen_switch_key(ctx.h, sk.data_ptr(), seed, int(steps), int(relin), out.data_ptr(), _stream()))
+    return out
+
+
+def encrypt_sk(ctx: Context, sk: torch.Tensor, pts: torch.Tensor, seed: int, scale: float) -> Ciphertext:
+    """pts: [batch][n_limbs][N] plain-form plaintexts (encode with mont=False)."""
+    B, nl = pts.shape[0], pts.shape[1]
+    ct = ctx.empty_ct(B, nl, scale)
+    d = ct.desc()
+    _check(lib().unihenn_encrypt_sk(ctx.h, sk.data_ptr(), pts.data_ptr(), seed, C.byref(d), _stream()))
+    return ct
+
+
+def decrypt_slots(ctx: Context, sk: torch.Tensor, ct: Ciphertext, slots) -> np.ndarray:
+    slots = np.ascontiguousarray(np.asarray(slots, dtype=np.uint32))
+    out = np.zeros((ct.batch, len(slots)), dtype=np.float64)
+    _check(lib().unihenn_decrypt_slots(ctx.h, sk.data_ptr(), C.byref(ct.desc()),
+                                       slots.ctypes.data_as(C.POINTER(C.c_uint32)), len(slots),
+                                       out.ctypes.data_as(C.POINTER(C.c_double)), _stream()))
+    return out
+
+
+# ---------------------------------------------------------------- network
+_KIND = {"conv": LAYER_CONV, "square": LAYER_SQUARE, "avgpool": LAYER_AVGPOOL, "flatten": LAYER_FLATTEN,
+         "fc": LAYER_FC}
+
+
+class Net:
+    """A planned network with its plaintexts encoded on the device."""
+
+    def __init__(self, ctx: Context, inp: dict, layers, params, samples: int = 1, stride: int = 0,
+                 max_batch: int = 1):
+        self.ctx = ctx
+        self._keep = []
+        arr = (LAYER * len(layers))()
+        for i, (L, p) in enumerate(zip(layers, params)):
+            d = arr[i]
+            d.kind = _KIND[L["kind"]]
+            if L["kind"] == "conv":
+                d.ch_in, d.ch_out, d.k, d.s, d.dims = L["ch_in"], L["ch_out"], L["k"], L["s"], L.get("dims", 2)
+            elif L["kind"] == "avgpool":
+                d.k = L["c"]
+            elif L["kind"] == "fc":
+                d.ch_in, d.ch_out = L["din"], L["dout"]
+            if p is not None:
+                w = np.ascontiguousarray(p[0], dtype=np.float64)
+                b = np.ascontiguousarray(p[1], dtype=np.float64)
+                self._keep += [w, b]
+                d.weights = w.ctypes.data_as(C.POINTER(C.c_double))
+                d.bias = b.ctypes.data_as(C.POINTER(C.c_double))
+        ind = INPUT(inp["c"], inp["h"], inp["w"], samples, stride)
+        h = C.c_void_p()
+        _check(lib().unihenn_net_create(ctx.h, C.byref(ind), arr, len(layers), max_batch, C.byref(h)))
+        self.h = h
+        self.samples = samples
+        self.max_batch = max_batch
+        dep, nrot, nout, inl = C.c_uint32(), C.c_uint32(), C.c_uint32(), C.c_uint32()
+        _check(lib().unihenn_net_info(h, C.byref(dep), C.byref(nrot), C.byref(nout), C.byref(inl)))
+        self.depth, self.n_rot, self.n_out, self.in_limbs = dep.value, nrot.value, nout.value, inl.value
+        self._bound = None
+
+    def close(self):
+        if self.h:
+            lib().unihenn_net_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def rotations(self) -> list[int]:
+        a = (C.c_int32 * max(self.n_rot, 1))()
+        _check(lib().unihenn_net_rotations(self.h, a))
+        return [int(x) for x in a[: self.n_rot]]
+
+    def bind_keys(self, keys: dict, rlk: torch.Tensor | None):
+        steps = sorted(keys)
+        sa = (C.c_int32 * max(len(steps), 1))(*steps)
+        ka = (EVK * max(len(steps), 1))(*[self.ctx.evk(keys[s]) for s in steps])
+        r = self.ctx.evk(rlk) if rlk is not None else None
+        _check(lib().unihenn_net_bind_keys(self.h, sa, ka, len(steps), C.byref(r) if r is not None else None))
+        self._bound = (keys, rlk)  # the library keeps raw pointers
+
+    def set_mode(self, mode: int):
+        _check(lib().unihenn_net_set_mode(self.h, mode))
+
+    def output_slots(self) -> np.ndarray:
+        nv = C.c_uint32()
+        _check(lib().unihenn_net_output_slots(self.h, None, C.byref(nv)))
+        pos = np.zeros(self.samples * nv.value, dtype=np.uint64)
+        _check(lib().unihenn_net_output_slots(self.h, pos.ctypes.data_as(C.POINTER(C.c_uint64)), None))
+        return pos.reshape(self.samples, nv.value)
+
+    def alloc_outputs(self, batch: int) -> list[Ciphertext]:
+        return [self.ctx.empty_ct(batch, 1) for _ in range(self.n_out)]
+
+    def eval(self, ct: Ciphertext, outs: list[Ciphertext] | None = None, stream=None) -> list[Ciphertext]:
+        outs = self.alloc_outputs(ct.batch) if outs is None else outs
+        od = (CT * self.n_out)(*[o.desc() for o in outs])
+        _check(lib().unihenn_eval_network(self.ctx.h, self.h, C.byref(ct.desc()), od, _stream(stream)))
+        for o, d in zip(outs, od):
+            o.scale = d.scale
+        return outs
+
+    def conv(self, layer: int, ins: list[Ciphertext], n_out: int, out_limbs: int):
+        outs = [self.ctx.empty_ct(ins[0].batch, out_limbs) for _ in range(n_out)]
+        ia = (CT * len(ins))(*[c.desc() for c in ins])
+        od = (CT * n_out)(*[o.desc() for o in outs])
+        interval = C.c_uint32()
+        _check(lib().unihenn_conv(self.ctx.h, self.h, layer, ia, len(ins), od, C.byref(interval), _stream()))
+        for o, d in zip(outs, od):
+            o.scale = d.scale
+        return outs, interval.value

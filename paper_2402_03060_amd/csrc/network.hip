@@ -1,0 +1,1025 @@
+// UniHENN network: planning on the host, then a straight-line program of
+// rotations, multiply-accumulates, rescales, additions and squares executed
+// on one stream.
+//
+// Layout of a feature map (Sections III-A, IV-B, VI-A): the value (c, y, x)
+// of packed sample b sits at slot  b*stride + ch_off[c] + I*(x + W_img*y),
+// with I the product of the conv strides and pooling kernels so far and W_img
+// the width of the input, kept as the row pitch by every layer.
+//
+// Every multiplicative stage is  Rescale( sum_t Rot(X_t, r_t) * pt_t ), where
+// pt_t = Encode(w_t * mask_t) puts the scalar on the destination slots.  The
+// paper's "multiply by a mask, then rotate" steps of the flatten layer are
+// computed as "rotate, then multiply by the mask moved to the destination":
+// the message and the rotation count are the same, and all rotations of one
+// source become consecutive, so they can share one digit decomposition.
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+
+int encode_scaled_batch(const unihenn_ctx* c, const double* z, int n_slots, const double* w, int n_w, double scale,
+                        int nl, int mont, u64* out, hipStream_t s);
+
+namespace {
+
+enum StepKind { ST_DROP, ST_ROT, ST_MAC, ST_RESCALE, ST_ADD, ST_ADD_PLAIN, ST_SQUARE };
+
+struct VReg {
+    int nl;
+    double scale;
+    int phys = -1;
+};
+
+struct Term {
+    int src;
+    size_t pt;  // word offset of the plaintext in the arena
+};
+
+struct Step {
+    StepKind kind;
+    int dst = -1, a = -1, b = -1;
+    int rot = 0;
+    bool acc = false;
+    std::vector<Term> terms;
+    size_t pt = 0;
+};
+
+struct PtRequest {
+    std::vector<double> z;
+    std::vector<double> w;
+    double scale;
+    int nl;
+    int mont;
+    size_t offset;
+};
+
+struct LayerRecord {
+    int kind;
+    size_t step_begin, step_end;
+    std::vector<int> in_regs, out_regs;
+    int interval_out = 0;
+};
+
+struct Layout {
+    bool vec = false;
+    int C = 1, H = 1, W = 1, I = 1, W_img = 1;
+    std::vector<int> ch_reg, ch_off;  // register and slot offset of channel c
+    int prev = 0;                      // 0 input, 1 conv, 2 avgpool (last non-square layer)
+    double pending = 1.0;              // deferred pooling factor (Section IV-C)
+    int length = 0;
+};
+
+struct KernelGeom {
+    int kh, kw, sh, sw;
+};
+
+KernelGeom geom(const unihenn_layer& L)
+{
+    if (L.dims == 1) return {1, (int)L.k, 1, (int)L.s};
+    return {(int)L.k, (int)L.k, (int)L.s, (int)L.s};
+}
+
+}  // namespace
+
+struct unihenn_net {
+    const unihenn_ctx* ctx = nullptr;
+    int n_slots = 0, samples = 1, stride = 0, depth = 0, in_limbs = 0, max_batch = 1;
+    std::vector<VReg> regs;
+    std::vector<Step> steps;
+    std::vector<LayerRecord> layers;
+    std::vector<int> rotations;
+    std::vector<int> out_regs;
+    std::vector<uint64_t> out_slots;
+    int n_values = 0;
+    int input_reg = -1;
+    std::vector<PtRequest> requests;
+    size_t pt_words = 0;
+    // device
+    u64* pt_arena = nullptr;
+    u64* reg_arena = nullptr;
+    std::vector<size_t> phys_off;
+    u64* ws = nullptr;
+    int ws_nl = 0;
+    std::map<int, const u64*> keys;
+    const u64* rlk = nullptr;
+    int mode = UNIHENN_EVAL_PLAIN;
+};
+
+namespace {
+
+// ---------------------------------------------------------------- planning
+struct Planner {
+    unihenn_net* net;
+    const unihenn_ctx* c;
+    double delta;
+    std::map<int, int> rotset;
+    std::string err;
+    int err_code = 0;
+
+    int fail(int code, const std::string& m)
+    {
+        if (!err_code) { err_code = code; err = m; }
+        return -1;
+    }
+
+    int newreg(int nl, double scale)
+    {
+        net->regs.push_back({nl, scale, -1});
+        return (int)net->regs.size() - 1;
+    }
+
+    int norm_rot(long r) const
+    {
+        long h = net->n_slots;
+        return (int)(((r % h) + h) % h);
+    }
+
+    int rot(int src, long r)
+    {
+        int rr = norm_rot(r);
+        if (rr == 0) return src;
+        int d = newreg(net->regs[src].nl, net->regs[src].scale);
+        Step s;
+        s.kind = ST_ROT;
+        s.dst = d;
+        s.a = src;
+        s.rot = rr;
+        net->steps.push_back(s);
+        rotset[rr] = 1;
+        return d;
+    }
+
+    int add(int a, int b)
+    {
+        if (net->regs[a].nl != net->regs[b].nl || net->regs[a].scale != net->regs[b].scale)
+            return fail(UNIHENN_ESCALE, "addition of ciphertexts at different levels or scales");
+        int d = newreg(net->regs[a].nl, net->regs[a].scale);
+        Step s;
+        s.kind = ST_ADD;
+        s.dst = d;
+        s.a = a;
+        s.b = b;
+        net->steps.push_back(s);
+        return d;
+    }
+
+    // request plaintexts Encode(w_t * z) at `scale` and nl limbs; returns the
+    // offset of the first (the others follow, nl * N words apart)
+    size_t request(const std::vector<double>& z, const std::vector<double>& w, double scale, int nl, int mont)
+    {
+        PtRequest r{z, w, scale, nl, mont, net->pt_words};
+        net->pt_words += w.size() * (size_t)nl * c->n;
+        net->requests.push_back(std::move(r));
+        return net->requests.back().offset;
+    }
+
+    std::vector<double> mask(const std::vector<long>& pos, double value = 1.0) const
+    {
+        std::vector<double> z(net->n_slots, 0.0);
+        for (int b = 0; b < net->samples; ++b)
+            for (long p : pos) z[(size_t)b * net->stride + p] = value;
+        return z;
+    }
+
+    // out = Rescale(sum_t pts[t] (*) srcs[t]); one MAC step then one rescale
+    int mac_rescale(const std::vector<Term>& terms)
+    {
+        if (terms.empty()) return fail(UNIHENN_EINVAL, "empty sum");
+        const VReg r0 = net->regs[terms[0].src];
+        for (const Term& t : terms)
+            if (net->regs[t.src].nl != r0.nl || net->regs[t.src].scale != r0.scale)
+                return fail(UNIHENN_ESCALE, "multiply-accumulate terms at different levels or scales");
+        if (r0.nl < 2) return fail(UNIHENN_ELEVEL, "level exhausted");
+        int acc = newreg(r0.nl, r0.scale * delta);
+        Step s;
+        s.kind = ST_MAC;
+        s.dst = acc;
+        s.terms = terms;
+        net->steps.push_back(s);
+        return rescale(acc);
+    }
+
+    int rescale(int a)
+    {
+        const VReg r = net->regs[a];
+        if (r.nl < 2) return fail(UNIHENN_ELEVEL, "level exhausted");
+        int d = newreg(r.nl - 1, r.scale / (double)c->primes[r.nl - 1]);
+        Step s;
+        s.kind = ST_RESCALE;
+        s.dst = d;
+        s.a = a;
+        net->steps.push_back(s);
+        return d;
+    }
+
+    int add_plain_vec(int a, const std::vector<double>& z)
+    {
+        const VReg r = net->regs[a];
+        double one = 1.0;
+        size_t off = request(z, std::vector<double>(1, one), r.scale, r.nl, 0);
+        int d = newreg(r.nl, r.scale);
+        Step s;
+        s.kind = ST_ADD_PLAIN;
+        s.dst = d;
+        s.a = a;
+        s.pt = off;
+        net->steps.push_back(s);
+        return d;
+    }
+
+    int square(int a)
+    {
+        const VReg r = net->regs[a];
+        if (r.nl < 2) return fail(UNIHENN_ELEVEL, "level exhausted");
+        const double s2 = r.scale * r.scale;
+        int d = newreg(r.nl - 1, s2 / (double)c->primes[r.nl - 1]);
+        Step s;
+        s.kind = ST_SQUARE;
+        s.dst = d;
+        s.a = a;
+        net->steps.push_back(s);
+        return d;
+    }
+
+    // Algorithm 1 -----------------------------------------------------------
+    int conv(Layout& L, const unihenn_layer& ly)
+    {
+        const KernelGeom g = geom(ly);
+        const int ci = (int)ly.ch_in, co = (int)ly.ch_out;
+        if (L.vec || ci != L.C) return fail(UNIHENN_EINVAL, "conv input channels do not match");
+        if (!(g.kw >= g.sw && g.sw >= 1 && g.kh >= g.sh && g.sh >= 1))
+            return fail(UNIHENN_EINVAL, "conv needs kernel >= stride >= 1 (Theorem 1)");
+        if (L.H < g.kh || L.W < g.kw) return fail(UNIHENN_EINVAL, "conv kernel larger than its input");
+        if (!ly.weights || !ly.bias) return fail(UNIHENN_EINVAL, "conv without weights or bias");
+        const int Ho = (L.H - g.kh) / g.sh + 1, Wo = (L.W - g.kw) / g.sw + 1;
+        const int I_out = L.I * g.sw;
+        std::vector<long> pos;
+        for (int y = 0; y < Ho; ++y)
+            for (int x = 0; x < Wo; ++x) pos.push_back((long)I_out * (x + (long)L.W_img * y));
+        const std::vector<double> m_out = mask(pos);
+        const int nl = net->regs[L.ch_reg[0]].nl;
+        const double s_in = net->regs[L.ch_reg[0]].scale;
+        auto weight = [&](int o, int i, int j, int k) {
+            return ly.weights[(((size_t)o * ci + i) * g.kh + j) * g.kw + k] * L.pending;
+        };
+        auto amount = [&](int i, int j, int k) { return (long)L.ch_off[i] + (long)L.I * (k + (long)L.W_img * j); };
+        bool one_ct = true;
+        for (int i = 1; i < ci; ++i) one_ct &= L.ch_reg[i] == L.ch_reg[0];
+        one_ct &= ci > 1;
+
+        std::vector<int> acc(co, -1);
+        // plaintexts: per output, every (i, j, k) weight on the valid output slots
+        std::vector<std::vector<size_t>> pt(co);
+        for (int o = 0; o < co; ++o) {
+            std::vector<double> w;
+            for (int i = 0; i < ci; ++i)
+                for (int j = 0; j < g.kh; ++j)
+                    for (int k = 0; k < g.kw; ++k) w.push_back(weight(o, i, j, k));
+            size_t off = request(m_out, w, delta, nl, 1);
+            for (size_t t = 0; t < w.size(); ++t) pt[o].push_back(off + t * (size_t)nl * c->n);
+        }
+        const int kk = g.kh * g.kw;
+        auto emit_macs = [&](int i_begin, int i_end, const std::vector<int>& rot_regs, bool accumulate) {
+            for (int o = 0; o < co; ++o) {
+                std::vector<Term> terms;
+                for (int i = i_begin; i < i_end; ++i)
+                    for (int t = 0; t < kk; ++t) terms.push_back({rot_regs[(i - i_begin) * kk + t], pt[o][(size_t)i * kk + t]});
+                if (acc[o] < 0) acc[o] = newreg(nl, s_in * delta);
+                Step s;
+                s.kind = ST_MAC;
+                s.dst = acc[o];
+                s.terms = terms;
+                s.acc = accumulate;
+                net->steps.push_back(s);
+            }
+        };
+        for (int i = 0; i < ci; ++i)
+            if (net->regs[L.ch_reg[i]].nl != nl || net->regs[L.ch_reg[i]].scale != s_in)
+                return fail(UNIHENN_ESCALE, "conv inputs at different levels or scales");
+        if (nl < 2) return fail(UNIHENN_ELEVEL, "level exhausted");
+        if (one_ct) {
+            // all channels in one ciphertext: every rotation first, then the sums
+            std::map<long, int> seen;
+            std::vector<int> rr;
+            for (int i = 0; i < ci; ++i)
+                for (int j = 0; j < g.kh; ++j)
+                    for (int k = 0; k < g.kw; ++k) {
+                        long r = norm_rot(amount(i, j, k));
+                        auto it = seen.find(r);
+                        int reg = it != seen.end() ? it->second : rot(L.ch_reg[0], r);
+                        seen[r] = reg;
+                        rr.push_back(reg);
+                    }
+            emit_macs(0, ci, rr, false);
+        } else {
+            // one input channel at a time: its K^2 rotations, then every output accumulates
+            for (int i = 0; i < ci; ++i) {
+                std::map<long, int> seen;
+                std::vector<int> rr;
+                for (int j = 0; j < g.kh; ++j)
+                    for (int k = 0; k < g.kw; ++k) {
+                        long r = norm_rot(amount(i, j, k));
+                        auto it = seen.find(r);
+                        int reg = it != seen.end() ? it->second : rot(L.ch_reg[i], r);
+                        seen[r] = reg;
+                        rr.push_back(reg);
+                    }
+                emit_macs(i, i + 1, rr, i > 0);
+            }
+        }
+        Layout out;
+        out.C = co;
+        out.H = Ho;
+        out.W = Wo;
+        out.I = I_out;
+        out.W_img = L.W_img;
+        out.prev = 1;
+        out.pending = 1.0;
+        for (int o = 0; o < co; ++o) {
+            int r = rescale(acc[o]);
+            if (r < 0) return -1;
+            std::vector<double> bz = mask(pos, ly.bias[o]);
+            int d = add_plain_vec(r, bz);
+            out.ch_reg.push_back(d);
+            out.ch_off.push_back(0);
+        }
+        L = out;
+        return 0;
+    }
+
+    // Section IV-C ----------------------------------------------------------
+    int avgpool(Layout& L, const unihenn_layer& ly)
+    {
+        const int cc = (int)ly.k;
+        if (L.vec || cc < 1 || L.H < cc || L.W < cc) return fail(UNIHENN_EINVAL, "bad pooling shape");
+        std::map<int, int> mapped;
+        for (int reg : L.ch_reg) {
+            if (mapped.count(reg)) continue;
+            int acc = -1;
+            for (int dy = 0; dy < cc; ++dy)
+                for (int dx = 0; dx < cc; ++dx) {
+                    int t = rot(reg, (long)L.I * (dx + (long)L.W_img * dy));
+                    acc = acc < 0 ? t : add(acc, t);
+                    if (acc < 0) return -1;
+                }
+            mapped[reg] = acc;
+        }
+        for (int& reg : L.ch_reg) reg = mapped[reg];
+        L.H /= cc;
+        L.W /= cc;
+        L.I *= cc;
+        L.prev = 2;
+        L.pending /= (double)(cc * cc);
+        return 0;
+    }
+
+    int square_layer(Layout& L)
+    {
+        std::map<int, int> mapped;
+        if (L.vec) {
+            int d = square(L.ch_reg[0]);
+            if (d < 0) return -1;
+            L.ch_reg[0] = d;
+        } else {
+            for (int& reg : L.ch_reg) {
+                if (!mapped.count(reg)) {
+                    int d = square(reg);
+                    if (d < 0) return -1;
+                    mapped[reg] = d;
+                }
+                reg = mapped[reg];
+            }
+        }
+        L.pending *= L.pending;
+        return 0;
+    }
+
+    // Section IV-E ----------------------------------------------------------
+    int flatten(Layout& L)
+    {
+        if (L.vec) return fail(UNIHENN_EINVAL, "flatten of a vector");
+        for (int c0 = 0; c0 < L.C; ++c0)
+            for (int c1 = c0 + 1; c1 < L.C; ++c1)
+                if (L.ch_reg[c0] == L.ch_reg[c1]) return fail(UNIHENN_EINVAL, "flatten needs one ciphertext per channel");
+        for (int off : L.ch_off)
+            if (off) return fail(UNIHENN_EINVAL, "flatten needs channels at offset 0");
+        const int S = L.I, Wi = L.W, Hi = L.H, Wimg = L.W_img;
+        std::vector<int> ys = L.ch_reg;
+        const int nl = net->regs[ys[0]].nl;
+        if (L.prev == 2) {
+            // invalid values between the pooled ones: one mask per column x
+            std::vector<size_t> pts;
+            for (int x = 0; x < Wi; ++x) {
+                std::vector<long> pos;
+                for (int y = 0; y < Hi; ++y) pos.push_back((long)S * Wimg * y + x);
+                pts.push_back(request(mask(pos), std::vector<double>(1, L.pending), delta, nl, 1));
+            }
+            for (int& X : ys) {
+                std::vector<Term> terms;
+                for (int x = 0; x < Wi; ++x) terms.push_back({rot(X, (long)x * (S - 1)), pts[x]});
+                X = mac_rescale(terms);
+                if (X < 0) return -1;
+            }
+        } else if (S > 1) {
+            // zeros between the values: S shifted copies summed, then one mask per group of S columns
+            const int G = (Wi + S - 1) / S;
+            std::vector<size_t> pts;
+            for (int gq = 0; gq < G; ++gq) {
+                std::vector<long> pos;
+                for (int y = 0; y < Hi; ++y)
+                    for (int m = 0; m < S; ++m)
+                        if (gq * S + m < Wi) pos.push_back((long)S * Wimg * y + (long)gq * S + m);
+                pts.push_back(request(mask(pos), std::vector<double>(1, L.pending), delta, nl, 1));
+            }
+            for (int& X : ys) {
+                int T = -1;
+                for (int m = 0; m < S; ++m) {
+                    int t = rot(X, (long)m * (S - 1));
+                    T = T < 0 ? t : add(T, t);
+                    if (T < 0) return -1;
+                }
+                std::vector<Term> terms;
+                for (int gq = 0; gq < G; ++gq) terms.push_back({rot(T, (long)gq * S * (S - 1)), pts[gq]});
+                X = mac_rescale(terms);
+                if (X < 0) return -1;
+            }
+        } else if (L.pending != 1.0) {
+            std::vector<long> pos;
+            for (int y = 0; y < Hi; ++y)
+                for (int x = 0; x < Wi; ++x) pos.push_back((long)Wimg * y + x);
+            size_t pt = request(mask(pos), std::vector<double>(1, L.pending), delta, nl, 1);
+            for (int& X : ys) {
+                X = mac_rescale({{X, pt}});
+                if (X < 0) return -1;
+            }
+        }
+        // (y, x) now sits at S W_img y + x; remove the column interval
+        if (Hi > 1) {
+            const int nl2 = net->regs[ys[0]].nl;
+            std::vector<size_t> pts;
+            for (int y = 0; y < Hi; ++y) {
+                std::vector<long> pos;
+                for (int x = 0; x < Wi; ++x) pos.push_back((long)y * Wi + x);
+                pts.push_back(request(mask(pos), std::vector<double>(1, 1.0), delta, nl2, 1));
+            }
+            for (int& X : ys) {
+                std::vector<Term> terms;
+                for (int y = 0; y < Hi; ++y) terms.push_back({rot(X, (long)y * ((long)Wimg * S - Wi)), pts[y]});
+                X = mac_rescale(terms);
+                if (X < 0) return -1;
+            }
+        }
+        // pack: channel o shifted right by o H W
+        int acc = -1;
+        for (int o = 0; o < (int)ys.size(); ++o) {
+            int t = rot(ys[o], -(long)o * Wi * Hi);
+            acc = acc < 0 ? t : add(acc, t);
+            if (acc < 0) return -1;
+        }
+        Layout out;
+        out.vec = true;
+        out.length = L.C * Hi * Wi;
+        out.ch_reg = {acc};
+        out.ch_off = {0};
+        L = out;
+        return 0;
+    }
+
+    // Algorithm 2 -----------------------------------------------------------
+    int fc(Layout& L, const unihenn_layer& ly)
+    {
+        const int din = (int)ly.ch_in, D = (int)ly.ch_out;
+        if (!L.vec || L.length != din) return fail(UNIHENN_EINVAL, "FC input size does not match");
+        if (!ly.weights || !ly.bias || D < 1) return fail(UNIHENN_EINVAL, "FC without weights or bias");
+        const int reps = (din + D - 1) / D;
+        const int Wvec = D * reps;
+        const int X = L.ch_reg[0];
+        const int nl = net->regs[X].nl;
+        std::vector<Term> terms;
+        for (int o = 0; o < D; ++o) {
+            std::vector<double> mrot(Wvec);
+            for (int p = 0; p < Wvec; ++p) {
+                int col = (p + o) % Wvec;
+                mrot[p] = col < din ? ly.weights[(size_t)(p % D) * din + col] * L.pending : 0.0;
+            }
+            std::vector<double> v1(net->n_slots, 0.0), v2(net->n_slots, 0.0);
+            for (int b = 0; b < net->samples; ++b)
+                for (int p = 0; p < Wvec; ++p) (p < Wvec - o ? v1 : v2)[(size_t)b * net->stride + p] = mrot[p];
+            terms.push_back({rot(X, o), request(v1, std::vector<double>(1, 1.0), delta, nl, 1)});
+            if (o >= 1) terms.push_back({rot(X, (long)o - Wvec), request(v2, std::vector<double>(1, 1.0), delta, nl, 1)});
+        }
+        int csum = mac_rescale(terms);
+        if (csum < 0) return -1;
+        int acc = -1;
+        for (int i = 0; i < reps; ++i) {
+            int t = rot(csum, (long)i * D);
+            acc = acc < 0 ? t : add(acc, t);
+            if (acc < 0) return -1;
+        }
+        std::vector<long> pos;
+        for (int p = 0; p < D; ++p) pos.push_back(p);
+        std::vector<double> bz(net->n_slots, 0.0);
+        for (int b = 0; b < net->samples; ++b)
+            for (int p = 0; p < D; ++p) bz[(size_t)b * net->stride + p] = ly.bias[p];
+        int out = add_plain_vec(acc, bz);
+        Layout o;
+        o.vec = true;
+        o.length = D;
+        o.ch_reg = {out};
+        o.ch_off = {0};
+        L = o;
+        return 0;
+    }
+};
+
+// Slots one packed sample needs (Section VI): the largest extent of the
+// slots holding its valid values or read by a valid output, the flatten
+// output C H W, and the FC width DAT_out ceil(DAT_in / DAT_out).
+int footprint(const unihenn_input& in, const unihenn_layer* ls, int n, long* out)
+{
+    long need = (long)in.c * in.h * in.w;
+    int C = (int)in.c, H = (int)in.h, W = (int)in.w, I = 1, Wimg = (int)in.w;
+    long max_off = (long)(in.c - 1) * in.h * in.w;
+    bool vec = false;
+    for (int l = 0; l < n; ++l) {
+        const unihenn_layer& L = ls[l];
+        if (L.kind == UNIHENN_LAYER_CONV) {
+            KernelGeom g = geom(L);
+            if (vec || H < g.kh || W < g.kw || g.sw < 1 || g.sh < 1) return UNIHENN_EINVAL;
+            int Ho = (H - g.kh) / g.sh + 1, Wo = (W - g.kw) / g.sw + 1;
+            need = std::max(need, max_off + (long)I * ((g.sw * (Wo - 1) + g.kw - 1) +
+                                                       (long)Wimg * (g.sh * (Ho - 1) + g.kh - 1)) + 1);
+            I *= g.sw;
+            C = (int)L.ch_out;
+            H = Ho;
+            W = Wo;
+            max_off = 0;
+            need = std::max(need, (long)I * ((Wo - 1) + (long)Wimg * (Ho - 1)) + 1);
+        } else if (L.kind == UNIHENN_LAYER_AVGPOOL) {
+            int cc = (int)L.k;
+            if (vec || cc < 1 || H < cc || W < cc) return UNIHENN_EINVAL;
+            need = std::max(need, max_off + (long)I * ((cc * (W / cc) - 1) + (long)Wimg * (cc * (H / cc) - 1)) + 1);
+            H /= cc;
+            W /= cc;
+            I *= cc;
+        } else if (L.kind == UNIHENN_LAYER_FLATTEN) {
+            need = std::max(need, (long)C * H * W);
+            vec = true;
+        } else if (L.kind == UNIHENN_LAYER_FC) {
+            long D = L.ch_out;
+            if (D < 1) return UNIHENN_EINVAL;
+            need = std::max(need, D * ((L.ch_in + D - 1) / D));
+        }
+    }
+    *out = need;
+    return UNIHENN_OK;
+}
+
+// multiplicative depth: conv 1, square 1, FC 1, flatten
+// [after pooling, or interval > 1, or a pending factor] + [H > 1]
+int count_depth(const unihenn_input& in, const unihenn_layer* ls, int n)
+{
+    int d = 0, prev = 0, I = 1, H = (int)in.h;
+    double pending = 1.0;
+    for (int l = 0; l < n; ++l) {
+        const unihenn_layer& L = ls[l];
+        switch (L.kind) {
+        case UNIHENN_LAYER_CONV: {
+            KernelGeom g = geom(L);
+            d += 1;
+            prev = 1;
+            I *= g.sw;
+            pending = 1.0;
+            H = (H - g.kh) / g.sh + 1;
+            break;
+        }
+        case UNIHENN_LAYER_SQUARE: d += 1; pending *= pending; break;
+        case UNIHENN_LAYER_AVGPOOL: prev = 2; I *= (int)L.k; pending /= (double)(L.k * L.k); H /= (int)L.k; break;
+        case UNIHENN_LAYER_FLATTEN: d += (prev == 2 || I > 1 || pending != 1.0) + (H > 1); break;
+        case UNIHENN_LAYER_FC: d += 1; break;
+        default: return -1;
+        }
+    }
+    return d;
+}
+
+// register allocation: buffers by limb count, reused after a value's last use
+void allocate(unihenn_net* net, std::vector<int>& phys_nl)
+{
+    const int nr = (int)net->regs.size();
+    std::vector<int> last(nr, -1), def(nr, -1);
+    auto use = [&](int r, int s) { if (r >= 0) last[r] = std::max(last[r], s); };
+    for (int s = 0; s < (int)net->steps.size(); ++s) {
+        const Step& st = net->steps[s];
+        use(st.a, s);
+        use(st.b, s);
+        for (const Term& t : st.terms) use(t.src, s);
+        if (st.acc) use(st.dst, s);
+        if (st.dst >= 0 && def[st.dst] < 0) def[st.dst] = s;
+        use(st.dst, s);
+    }
+    for (int r : net->out_regs) last[r] = (int)net->steps.size();
+    std::map<int, std::vector<int>> free_by_nl;
+    std::vector<std::vector<int>> dying(net->steps.size() + 1);
+    for (int r = 0; r < nr; ++r)
+        if (last[r] >= 0 && last[r] < (int)net->steps.size()) dying[last[r]].push_back(r);
+    for (int s = 0; s < (int)net->steps.size(); ++s) {
+        int d = net->steps[s].dst;
+        if (d >= 0 && def[d] == s && net->regs[d].phys < 0) {
+            auto& fl = free_by_nl[net->regs[d].nl];
+            if (!fl.empty()) {
+                net->regs[d].phys = fl.back();
+                fl.pop_back();
+            } else {
+                net->regs[d].phys = (int)phys_nl.size();
+                phys_nl.push_back(net->regs[d].nl);
+            }
+        }
+        for (int r : dying[s])
+            if (net->regs[r].phys >= 0) free_by_nl[net->regs[r].nl].push_back(net->regs[r].phys);
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- C ABI
+extern "C" int unihenn_net_destroy(unihenn_net* net)
+{
+    if (!net) return UNIHENN_OK;
+    hipFree(net->pt_arena);
+    hipFree(net->reg_arena);
+    hipFree(net->ws);
+    delete net;
+    return UNIHENN_OK;
+}
+
+extern "C" int unihenn_net_create(const unihenn_ctx* c, const unihenn_input* in, const unihenn_layer* layers,
+                                  uint32_t n_layers, uint32_t max_batch, unihenn_net** out)
+{
+    if (!c || !in || !out || (n_layers && !layers)) return uh_fail(UNIHENN_EINVAL, "null argument");
+    if (in->c < 1 || in->h < 1 || in->w < 1 || in->samples < 1 || max_batch < 1)
+        return uh_fail(UNIHENN_EINVAL, "empty input shape, sample count or batch");
+    for (uint32_t l = 0; l < n_layers; ++l)
+        if (layers[l].kind < UNIHENN_LAYER_CONV || layers[l].kind > UNIHENN_LAYER_FC)
+            return uh_fail(UNIHENN_EINVAL, "unknown layer kind");
+    unihenn_net* net = new unihenn_net();
+    net->ctx = c;
+    net->n_slots = c->n / 2;
+    net->samples = (int)in->samples;
+    net->max_batch = (int)max_batch;
+    long fp = 0;
+    if (footprint(*in, layers, (int)n_layers, &fp)) {
+        delete net;
+        return uh_fail(UNIHENN_EINVAL, "layer shapes do not chain");
+    }
+    if (in->samples == 1) {
+        net->stride = net->n_slots;
+        if (fp > net->n_slots) {
+            delete net;
+            return uh_fail(UNIHENN_ESLOTS, "the model's footprint exceeds the slots");
+        }
+    } else {
+        net->stride = (int)in->stride;
+        if ((long)in->stride < fp || (long)in->samples * in->stride > net->n_slots) {
+            delete net;
+            return uh_fail(UNIHENN_ESLOTS, "sample stride " + std::to_string(in->stride) + " below the footprint " +
+                                               std::to_string(fp) + " or samples exceed the slots");
+        }
+    }
+    net->depth = count_depth(*in, layers, (int)n_layers);
+    net->in_limbs = net->depth + 1;
+    if (net->depth < 0 || net->in_limbs > c->n_data) {
+        delete net;
+        return uh_fail(UNIHENN_ELEVEL, "the network needs " + std::to_string(net->in_limbs) + " limbs, the chain has " +
+                                           std::to_string(c->n_data));
+    }
+
+    Planner P{net, c, c->scale, {}, "", 0};
+    net->input_reg = P.newreg(net->in_limbs, c->scale);
+    {
+        Step s;
+        s.kind = ST_DROP;
+        s.dst = net->input_reg;
+        net->steps.push_back(s);
+    }
+    Layout L;
+    L.C = (int)in->c;
+    L.H = (int)in->h;
+    L.W = (int)in->w;
+    L.I = 1;
+    L.W_img = (int)in->w;
+    for (uint32_t ch = 0; ch < in->c; ++ch) {
+        L.ch_reg.push_back(net->input_reg);
+        L.ch_off.push_back((int)(ch * in->h * in->w));
+    }
+    for (uint32_t l = 0; l < n_layers; ++l) {
+        LayerRecord rec;
+        rec.kind = layers[l].kind;
+        rec.step_begin = net->steps.size();
+        rec.in_regs = L.ch_reg;
+        int rc = 0;
+        switch (layers[l].kind) {
+        case UNIHENN_LAYER_CONV: rc = P.conv(L, layers[l]); break;
+        case UNIHENN_LAYER_SQUARE: rc = P.square_layer(L); break;
+        case UNIHENN_LAYER_AVGPOOL: rc = P.avgpool(L, layers[l]); break;
+        case UNIHENN_LAYER_FLATTEN: rc = P.flatten(L); break;
+        case UNIHENN_LAYER_FC: rc = P.fc(L, layers[l]); break;
+        }
+        if (rc < 0 || P.err_code) {
+            int code = P.err_code ? P.err_code : UNIHENN_EINVAL;
+            std::string m = P.err;
+            delete net;
+            return uh_fail(code, "layer " + std::to_string(l) + ": " + m);
+        }
+        rec.step_end = net->steps.size();
+        rec.out_regs = L.ch_reg;
+        rec.interval_out = L.I;
+        net->layers.push_back(rec);
+    }
+    // outputs: distinct registers in channel order
+    for (int r : L.ch_reg)
+        if (std::find(net->out_regs.begin(), net->out_regs.end(), r) == net->out_regs.end()) net->out_regs.push_back(r);
+    for (int b = 0; b < net->samples; ++b) {
+        long base = (long)b * net->stride;
+        if (L.vec) {
+            for (int v = 0; v < L.length; ++v) net->out_slots.push_back((uint64_t)(base + v));
+        } else {
+            for (int ch = 0; ch < L.C; ++ch) {
+                uint64_t idx = std::find(net->out_regs.begin(), net->out_regs.end(), L.ch_reg[ch]) - net->out_regs.begin();
+                for (int y = 0; y < L.H; ++y)
+                    for (int x = 0; x < L.W; ++x)
+                        net->out_slots.push_back((idx << 32) | (uint64_t)(base + L.ch_off[ch] + (long)L.I * (x + (long)L.W_img * y)));
+            }
+        }
+    }
+    net->n_values = L.vec ? L.length : L.C * L.H * L.W;
+    for (auto& kv : P.rotset) net->rotations.push_back(kv.first);
+    for (int r : net->out_regs)
+        if (net->regs[r].nl != 1) {
+            unihenn_net_destroy(net);
+            return uh_fail(UNIHENN_ELEVEL, "output not at one limb");
+        }
+
+    // device memory: plaintexts, registers, workspace
+    std::vector<int> phys_nl;
+    allocate(net, phys_nl);
+    size_t reg_words = 0;
+    for (int nl : phys_nl) {
+        net->phys_off.push_back(reg_words);
+        reg_words += (size_t)max_batch * 2 * nl * c->n;
+    }
+    net->ws_nl = net->in_limbs;
+    size_t ws_words = ks_ws_rows(net->ws_nl, (int)max_batch) * c->n;
+    if (hipMalloc(&net->pt_arena, sizeof(u64) * std::max<size_t>(net->pt_words, 1)) != hipSuccess ||
+        hipMalloc(&net->reg_arena, sizeof(u64) * std::max<size_t>(reg_words, 1)) != hipSuccess ||
+        hipMalloc(&net->ws, sizeof(u64) * ws_words) != hipSuccess) {
+        unihenn_net_destroy(net);
+        return uh_fail(UNIHENN_ENOMEM, "network buffers");
+    }
+    for (const PtRequest& r : net->requests) {
+        int rc = encode_scaled_batch(c, r.z.data(), (int)r.z.size(), r.w.data(), (int)r.w.size(), r.scale, r.nl,
+                                     r.mont, net->pt_arena + r.offset, nullptr);
+        if (rc) {
+            unihenn_net_destroy(net);
+            return rc;
+        }
+    }
+    net->requests.clear();
+    net->requests.shrink_to_fit();
+    *out = net;
+    return UNIHENN_OK;
+}
+
+extern "C" int unihenn_net_info(const unihenn_net* net, uint32_t* depth, uint32_t* n_rotations, uint32_t* n_outputs,
+                                uint32_t* input_limbs)
+{
+    if (!net) return uh_fail(UNIHENN_EINVAL, "null net");
+    if (depth) *depth = (uint32_t)net->depth;
+    if (n_rotations) *n_rotations = (uint32_t)net->rotations.size();
+    if (n_outputs) *n_outputs = (uint32_t)net->out_regs.size();
+    if (input_limbs) *input_limbs = (uint32_t)net->in_limbs;
+    return UNIHENN_OK;
+}
+
+extern "C" int unihenn_net_rotations(const unihenn_net* net, int32_t* steps)
+{
+    if (!net || !steps) return uh_fail(UNIHENN_EINVAL, "null argument");
+    for (size_t i = 0; i < net->rotations.size(); ++i) steps[i] = net->rotations[i];
+    return UNIHENN_OK;
+}
+
+extern "C" int unihenn_net_output_slots(const unihenn_net* net, uint64_t* positions, uint32_t* n_values)
+{
+    if (!net) return uh_fail(UNIHENN_EINVAL, "null net");
+    if (n_values) *n_values = (uint32_t)net->n_values;
+    if (positions) std::copy(net->out_slots.begin(), net->out_slots.end(), positions);
+    return UNIHENN_OK;
+}
+
+extern "C" int unihenn_net_bind_keys(unihenn_net* net, const int32_t* steps, const unihenn_evk* gks, uint32_t n,
+                                     const unihenn_evk* rlk)
+{
+    if (!net || (n && (!steps || !gks))) return uh_fail(UNIHENN_EINVAL, "null argument");
+    const unihenn_ctx* c = net->ctx;
+    std::map<int, const u64*> k;
+    for (uint32_t i = 0; i < n; ++i) {
+        if (!gks[i].data || (int)gks[i].n_data != c->n_data) return uh_fail(UNIHENN_EINVAL, "bad rotation key");
+        long h = net->n_slots;
+        k[(int)(((steps[i] % h) + h) % h)] = gks[i].data;
+    }
+    for (int r : net->rotations)
+        if (!k.count(r)) return uh_fail(UNIHENN_ENOKEY, "no key for rotation " + std::to_string(r));
+    bool needs_rlk = false;
+    for (const Step& s : net->steps) needs_rlk |= s.kind == ST_SQUARE;
+    if (needs_rlk && (!rlk || !rlk->data || (int)rlk->n_data != c->n_data))
+        return uh_fail(UNIHENN_ENOKEY, "no relinearisation key");
+    net->keys = k;
+    net->rlk = rlk ? rlk->data : nullptr;
+    return UNIHENN_OK;
+}
+
+extern "C" int unihenn_net_set_mode(unihenn_net* net, int mode)
+{
+    if (!net || (mode != UNIHENN_EVAL_PLAIN && mode != UNIHENN_EVAL_HOISTED))
+        return uh_fail(UNIHENN_EINVAL, "bad mode");
+    net->mode = mode;
+    return UNIHENN_OK;
+}
+
+// ---------------------------------------------------------------- execution
+namespace {
+
+struct Exec {
+    unihenn_net* net;
+    const unihenn_ctx* c;
+    int B;
+    hipStream_t s;
+    std::map<int, u64*> bound;  // registers bound to caller buffers
+    int modup_owner = -1;       // register whose digits the workspace holds
+    const u64* ext_in = nullptr;
+    int ext_in_limbs = 0;
+
+    u64* reg(int r)
+    {
+        auto it = bound.find(r);
+        if (it != bound.end()) return it->second;
+        return net->reg_arena + net->phys_off[net->regs[r].phys];
+    }
+
+    int run(size_t begin, size_t end)
+    {
+        const size_t rn = (size_t)c->n;
+        for (size_t si = begin; si < end; ++si) {
+            const Step& st = net->steps[si];
+            const int nl = net->regs[st.dst].nl;
+            KsWs w = ks_ws_carve(net->ws, nl, B, c->n);
+            switch (st.kind) {
+            case ST_DROP:
+                launch_gather_rows(c, reg(st.dst), ext_in, B * 2 * nl, nl, ext_in_limbs, 0, s);
+                break;
+            case ST_ROT: {
+                const u64* key = net->keys.at(st.rot);
+                const u32 g = galois_elt(c, st.rot);
+                const u64* src = reg(st.a);
+                if (net->mode == UNIHENN_EVAL_HOISTED) {
+                    if (modup_owner != st.a) {
+                        ks_modup(c, src + (size_t)nl * rn, 2 * nl, B, nl, w, s);
+                        modup_owner = st.a;
+                    }
+                    launch_automorphism(c, w.aux, src, B * 2 * nl, g, s);
+                    ks_finish(c, src + (size_t)nl * rn, 2 * nl, key, c->n_data, B, nl, g, reg(st.dst), w.aux, nullptr,
+                              2 * nl, w, s);
+                } else {
+                    launch_automorphism(c, w.aux, src, B * 2 * nl, g, s);
+                    ks_modup(c, w.aux + (size_t)nl * rn, 2 * nl, B, nl, w, s);
+                    ks_finish(c, w.aux + (size_t)nl * rn, 2 * nl, key, c->n_data, B, nl, 1, reg(st.dst), w.aux,
+                              nullptr, 2 * nl, w, s);
+                    modup_owner = -1;
+                }
+                break;
+            }
+            case ST_MAC: {
+                const size_t nt = st.terms.size();
+                for (size_t t0 = 0; t0 < nt; t0 += UH_MAC_MAX_TERMS) {
+                    MacTerms mt;
+                    int k = (int)std::min<size_t>(UH_MAC_MAX_TERMS, nt - t0);
+                    for (int t = 0; t < k; ++t) {
+                        mt.ct[t] = reg(st.terms[t0 + t].src);
+                        mt.pt[t] = net->pt_arena + st.terms[t0 + t].pt;
+                    }
+                    launch_mac(c, reg(st.dst), mt, k, nl, B, (st.acc || t0 > 0) ? 1 : 0, s);
+                }
+                break;
+            }
+            case ST_RESCALE: {
+                const int nla = net->regs[st.a].nl;
+                KsWs wa = ks_ws_carve(net->ws, nla, B, c->n);
+                rescale_core(c, reg(st.a), B, nla, reg(st.dst), wa, s);
+                break;
+            }
+            case ST_ADD:
+                launch_add(c, reg(st.dst), reg(st.a), reg(st.b), B * 2 * nl, nl, s);
+                break;
+            case ST_ADD_PLAIN:
+                launch_add_plain(c, reg(st.dst), reg(st.a), net->pt_arena + st.pt, B, nl, s);
+                break;
+            case ST_SQUARE: {
+                const int nla = net->regs[st.a].nl;
+                KsWs wa = ks_ws_carve(net->ws, nla, B, c->n);
+                u64* d0 = wa.aux;
+                u64* d1 = wa.aux + (size_t)B * nla * rn;
+                u64* d2 = wa.aux + (size_t)2 * B * nla * rn;
+                launch_tensor_square(c, d0, d1, d2, reg(st.a), B, nla, s);
+                ks_modup(c, d2, nla, B, nla, wa, s);
+                // the relinearised product goes to the (then dead) ModUp rows
+                u64* tmp = wa.modup;
+                ks_finish(c, d2, nla, net->rlk, c->n_data, B, nla, 1, tmp, d0, d1, nla, wa, s);
+                rescale_core(c, tmp, B, nla, reg(st.dst), wa, s);
+                modup_owner = -1;
+                break;
+            }
+            }
+        }
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return uh_fail(UNIHENN_EDEVICE, std::string("launch: ") + hipGetErrorString(e));
+        return UNIHENN_OK;
+    }
+};
+
+int check_keys(const unihenn_net* net)
+{
+    if (net->keys.size() < net->rotations.size()) return uh_fail(UNIHENN_ENOKEY, "keys not bound");
+    for (const Step& s : net->steps)
+        if (s.kind == ST_SQUARE && !net->rlk) return uh_fail(UNIHENN_ENOKEY, "relinearisation key not bound");
+    return UNIHENN_OK;
+}
+
+}  // namespace
+
+extern "C" int unihenn_eval_network(const unihenn_ctx* c, unihenn_net* net, const unihenn_ct* in, unihenn_ct* out,
+                                    void* stream)
+{
+    if (!c || !net || !in || !in->data || !out) return uh_fail(UNIHENN_EINVAL, "null argument");
+    if (net->ctx != c) return uh_fail(UNIHENN_EINVAL, "net made for another context");
+    if (in->batch < 1 || (int)in->batch > net->max_batch) return uh_fail(UNIHENN_EINVAL, "batch exceeds max_batch");
+    if ((int)in->n_limbs < net->in_limbs) return uh_fail(UNIHENN_ELEVEL, "input has fewer limbs than the depth needs");
+    if ((int)in->n_limbs > c->n_data) return uh_fail(UNIHENN_ELEVEL, "bad input limb count");
+    if (in->scale != c->scale) return uh_fail(UNIHENN_ESCALE, "input scale differs from the encoding scale");
+    int rc = check_keys(net);
+    if (rc) return rc;
+    for (size_t i = 0; i < net->out_regs.size(); ++i)
+        if (!out[i].data) return uh_fail(UNIHENN_EINVAL, "null output buffer");
+    Exec ex{net, c, (int)in->batch, (hipStream_t)stream, {}, -1, in->data, (int)in->n_limbs};
+    for (size_t i = 0; i < net->out_regs.size(); ++i) ex.bound[net->out_regs[i]] = out[i].data;
+    rc = ex.run(0, net->steps.size());
+    if (rc) return rc;
+    for (size_t i = 0; i < net->out_regs.size(); ++i) {
+        out[i].n_limbs = 1;
+        out[i].batch = in->batch;
+        out[i].scale = net->regs[net->out_regs[i]].scale;
+    }
+    return UNIHENN_OK;
+}
+
+extern "C" int unihenn_conv(const unihenn_ctx* c, unihenn_net* net, uint32_t layer, const unihenn_ct* in,
+                            uint32_t n_in, unihenn_ct* out, uint32_t* interval_out, void* stream)
+{
+    if (!c || !net || !in || !out) return uh_fail(UNIHENN_EINVAL, "null argument");
+    if (layer >= net->layers.size() || net->layers[layer].kind != UNIHENN_LAYER_CONV)
+        return uh_fail(UNIHENN_EINVAL, "layer is not a convolution");
+    const LayerRecord& L = net->layers[layer];
+    std::vector<int> uniq;
+    for (int r : L.in_regs)
+        if (std::find(uniq.begin(), uniq.end(), r) == uniq.end()) uniq.push_back(r);
+    if (n_in != uniq.size()) return uh_fail(UNIHENN_EINVAL, "expected " + std::to_string(uniq.size()) + " inputs");
+    const int B = (int)in[0].batch;
+    if (B < 1 || B > net->max_batch) return uh_fail(UNIHENN_EINVAL, "batch exceeds max_batch");
+    for (uint32_t i = 0; i < n_in; ++i) {
+        const VReg& r = net->regs[uniq[i]];
+        if (!in[i].data || (int)in[i].n_limbs != r.nl || (int)in[i].batch != B)
+            return uh_fail(UNIHENN_ELEVEL, "input " + std::to_string(i) + " not at the layer's level");
+        if (in[i].scale != r.scale) return uh_fail(UNIHENN_ESCALE, "input scale differs from the plan");
+    }
+    int rc = check_keys(net);
+    if (rc) return rc;
+    Exec ex{net, c, B, (hipStream_t)stream, {}, -1, nullptr, 0};
+    for (uint32_t i = 0; i < n_in; ++i) ex.bound[uniq[i]] = in[i].data;
+    for (size_t o = 0; o < L.out_regs.size(); ++o) {
+        if (!out[o].data) return uh_fail(UNIHENN_EINVAL, "null output buffer");
+        ex.bound[L.out_regs[o]] = out[o].data;
+    }
+    rc = ex.run(L.step_begin, L.step_end);
+    if (rc) return rc;
+    for (size_t o = 0; o < L.out_regs.size(); ++o) {
+        const VReg& r = net->regs[L.out_regs[o]];
+        out[o].n_limbs = (uint32_t)r.nl;
+        out[o].batch = (uint32_t)B;
+        out[o].scale = r.scale;
+    }
+    if (interval_out) *interval_out = (uint32_t)L.interval_out;
+    return UNIHENN_OK;
+}

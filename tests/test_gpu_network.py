@@ -1,0 +1,174 @@
+"""GPU network parity: whole networks and single conv layers evaluated by the
+HIP library on keys and ciphertexts made by the CPU oracle (client role),
+compared with the oracle's evaluation residue by residue; and the product's
+own client end to end against the FP64 CNN."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle.network import input_layout, read_outputs
+from oracle.run import OracleSession, build_net, reference_outputs, run_encrypted
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu_net(P, ctx, cfg, sess, net_oracle, batch=1):
+    net = P.Net(ctx, cfg["input"], cfg["layers"], net_oracle.params, samples=cfg["samples_per_ct"],
+                stride=cfg["sample_stride"], max_batch=batch)
+    assert net.depth == net_oracle.depth
+    assert sorted(net.rotations()) == net_oracle.rotation_set()
+    keys = {r: ctx.import_evk(sess.key_coeff[r]) for r in net.rotations()}
+    rlk = ctx.import_evk(sess.rlk_coeff)
+    net.bind_keys(keys, rlk)
+    return net
+
+
+def _ctx(P, cfg):
+    return P.Context(cfg["log_n"], cfg["prime_bits"], cfg["special_bits"], 2.0 ** cfg["log_scale"])
+
+
+def _run_parity(cfg, n_cts=1, seeds=(W.SEED_ENCRYPT,)):
+    import paper_2402_03060_amd as P
+    sess = OracleSession(cfg)
+    onet = build_net(cfg, sess.ck.slots)
+    xs_all = W.gen_inputs(cfg["input"], cfg["samples_per_ct"] * n_cts)
+    expected, cts = [], []
+    for b in range(n_cts):
+        xs = xs_all[b * cfg["samples_per_ct"]:(b + 1) * cfg["samples_per_ct"]]
+        ct, outs, _ = run_encrypted(sess, onet, xs, enc_seed=seeds[b % len(seeds)] + b)
+        expected.append([o.data for o in outs])
+        cts.append(ct)
+    ctx = _ctx(P, cfg)
+    assert ctx.primes == sess.ck.primes
+    gnet = _gpu_net(P, ctx, cfg, sess, onet, batch=n_cts)
+    gin = ctx.import_ct(np.stack([c.data for c in cts]), cts[0].scale)
+    results = {}
+    for mode in (P.EVAL_PLAIN, P.EVAL_HOISTED):
+        gnet.set_mode(mode)
+        outs = gnet.eval(gin)
+        got = [ctx.export_ct(o) for o in outs]
+        for b in range(n_cts):
+            for k in range(len(outs)):
+                assert np.array_equal(got[k][b], expected[b][k]), (mode, b, k)
+        results[mode] = got
+    return sess, onet, gnet, ctx, xs_all
+
+
+def test_conv1_config_bit_exact():
+    """One conv layer (4 filters 5x5) + square at N = 2^13: the full-size
+    single-layer workload."""
+    _run_parity(W.config("conv1"))
+
+
+def test_lenet1_small_ring_bit_exact():
+    """Every layer kind (conv, square, pool, flatten after pooling, FC) at N = 2^11."""
+    cfg = W.config("lenet1")
+    cfg["log_n"] = 11
+    _run_parity(cfg)
+
+
+def test_lenet1_packed_batch_bit_exact():
+    """Two images per ciphertext at stride 784 and two ciphertexts per launch."""
+    cfg = W.config("lenet1_batched")
+    cfg["log_n"] = 12
+    cfg["samples_per_ct"] = 2
+    _run_parity(cfg, n_cts=2)
+
+
+def test_cnn1d_small_ring_bit_exact():
+    """1D convolutions with stride 2 and the row-interval flatten at N = 2^12,
+    two sequences at stride 1024."""
+    cfg = W.config("cnn1d")
+    cfg["log_n"] = 12
+    cfg["samples_per_ct"] = 2
+    _run_parity(cfg)
+
+
+def test_conv_layer_entry_point():
+    """unihenn_conv (Algorithm 1 alone) on the LeNet-1 second conv at N = 2^11."""
+    import paper_2402_03060_amd as P
+    from oracle.network import CkksEval, Layout
+    cfg = W.config("lenet1")
+    cfg["log_n"] = 11
+    sess = OracleSession(cfg)
+    onet = build_net(cfg, sess.ck.slots)
+    sess.ensure_keys(onet.rotation_set())
+    ck = sess.ck
+    ev = CkksEval(ck, sess.key_handle, sess.rlk)
+    # four input channels at the level and scale conv2 sees in the network
+    xs = W.gen_slots(ck.slots, 4, seed=81, lo=0, hi=0.5)
+    nl = onet.depth + 1 - 2
+    cts = [ck.limb_drop(ck.encrypt(x, 90 + i), nl) for i, x in enumerate(xs)]
+    ctx = _ctx(P, cfg)
+    gnet = _gpu_net(P, ctx, cfg, sess, onet)
+    # the plan's scale for conv2's input: conv1 (MAC, rescale), square (rescale), pool
+    s = ck.delta * ck.delta / ck.primes[nl + 1]
+    s = s * s / ck.primes[nl]
+    cts = [type(c)(c.data, s) for c in cts]
+    L = Layout("map", 4, 12, 12, 2, 28, [0, 1, 2, 3], [0, 0, 0, 0], "avgpool", 0.25)
+    exp, L2 = onet._conv(ev, cts, L, cfg["layers"][3], onet.params[3])
+    gins = [ctx.import_ct(c.data, s) for c in cts]
+    outs, interval = gnet.conv(3, gins, 12, nl - 1)
+    assert interval == L2.I == 2
+    for o in range(12):
+        assert np.array_equal(ctx.export_ct(outs[o])[0], exp[o].data)
+
+
+def test_full_size_rotation_lenet1_ring():
+    """One rotation and one rescale at the LeNet-1 size (N = 2^14, 8 limbs),
+    launch configuration of the benchmark."""
+    import paper_2402_03060_amd as P
+    cfg = W.config("lenet1")
+    sess = OracleSession(cfg)
+    ck = sess.ck
+    z = W.gen_slots(ck.slots, 1, seed=91)[0]
+    ct = ck.encrypt(z, 92)
+    key = ck.rotation_key(28)
+    exp = ck.rotate(ct, 28, ck.load_key(key))
+    ctx = _ctx(P, cfg)
+    ws = ctx.workspace(8, 1)
+    g = ctx.rotate(ctx.import_ct(ct.data, ct.scale), 28, ctx.import_evk(key), ws)
+    assert np.array_equal(ctx.export_ct(g)[0], exp.data)
+    r = ctx.rescale(g, ws)
+    assert np.array_equal(ctx.export_ct(r)[0], ck.rescale(exp).data)
+
+
+@pytest.mark.parametrize("name", ["conv1", "lenet1", "cnn1d"])
+def test_product_client_end_to_end(name):
+    """The library's own client (GPU keygen, encryption, decryption) around
+    the full-size network: outputs within 1e-3 of the FP64 CNN."""
+    import paper_2402_03060_amd as P
+    cfg = W.config(name)
+    ctx = _ctx(P, cfg)
+    params = W.gen_params(cfg["layers"])
+    S = cfg["samples_per_ct"]
+    B = 2
+    net = P.Net(ctx, cfg["input"], cfg["layers"], params, samples=S, stride=cfg["sample_stride"], max_batch=B)
+    sk = P.keygen_secret(ctx, 5)
+    keys = {r: P.gen_switch_key(ctx, sk, 6, steps=r) for r in net.rotations()}
+    rlk = P.gen_switch_key(ctx, sk, 7, relin=True)
+    net.bind_keys(keys, rlk)
+    xs = W.gen_inputs(cfg["input"], S * B)
+    from oracle.network import Net as ONet
+    onet = ONet(cfg["input"], cfg["layers"], params, ctx.slots, S, cfg["sample_stride"])
+    pts = []
+    for b in range(B):
+        v = onet.input_vector(xs[b * S:(b + 1) * S])
+        pts.append(ctx.encode(v, ctx.scale, net.in_limbs, mont=False))
+    import torch
+    ct = P.encrypt_sk(ctx, sk, torch.stack(pts), 8, ctx.scale)
+    net.set_mode(P.EVAL_HOISTED)
+    outs = net.eval(ct)
+    pos = net.output_slots()
+    ref = reference_outputs(onet, xs)
+    for b in range(B):
+        for s in range(S):
+            ids = pos[s] >> np.uint64(32)
+            slots = (pos[s] & np.uint64(0xffffffff)).astype(np.uint32)
+            vals = np.zeros(len(slots))
+            for k in np.unique(ids):
+                sel = ids == k
+                vals[sel] = P.decrypt_slots(ctx, sk, outs[int(k)], slots[sel])[b]
+            assert np.abs(vals - ref[b * S + s]).max() < 1e-3

@@ -1,0 +1,73 @@
+"""The C-ABI library loads without a GPU and exports every function that
+include/unihenn.h declares; the binding declares a signature for each.
+Host-only helpers (no device work) are checked here too."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "unihenn.h")
+LIB = os.path.join(ROOT, "paper_2402_03060_amd", "libunihenn.so")
+
+
+def declared_functions() -> list[str]:
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(unihenn_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_hot_path():
+    names = declared_functions()
+    for required in ["unihenn_encode", "unihenn_rotate", "unihenn_mul_plain_acc", "unihenn_rescale",
+                     "unihenn_conv", "unihenn_eval_network"]:
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    assert os.path.exists(LIB), "build the library first (paper_2402_03060_amd/build.py)"
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_the_header():
+    import paper_2402_03060_amd as P
+    assert sorted(P.SIGNATURES) == declared_functions()
+    assert P.missing_symbols() == []
+
+
+def test_errors_reported_without_device_work():
+    import paper_2402_03060_amd as P
+    L = P.lib()
+    h = ctypes.c_void_p()
+    bits = (ctypes.c_uint32 * 2)(60, 40)
+    assert L.unihenn_ctx_create(3, bits, 2, 60, 2.0 ** 40, ctypes.byref(h)) == P.EINVAL
+    assert b"log_n" in L.unihenn_last_error()
+    assert L.unihenn_stats_get(99, None, None, None) == P.EINVAL
+    assert L.unihenn_kernel_family_name(0) == b"ntt_fwd"
+
+
+def test_double_double_cosine_table():
+    """The library's own cosine table against binary128 values (oracle side)."""
+    from oracle.ckks import OracleCKKS
+    L = ctypes.CDLL(LIB)
+    log_n = 6
+    n = 1 << log_n
+    tab = np.zeros(4 * n)
+    L.unihenn_debug_cos_table(log_n, tab.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    ck = OracleCKKS(log_n, [60, 40], 60)
+    # m_j of a unit vector at slot 0 is (2/N) cos(pi j / N): compare the tables through it
+    z = np.zeros(ck.slots)
+    z[0] = 1.0
+    hi, lo = ck.real_transform(z)
+    for j in range(n):
+        got = (tab[2 * j] + tab[2 * j + 1]) * 2 / n
+        ref = hi[j] + lo[j]
+        assert abs(got - ref) <= 1e-30 + 1e-15 * abs(ref)
+        # double-double residual agrees far below double precision
+        assert abs((tab[2 * j] - hi[j] * n / 2) + (tab[2 * j + 1] - lo[j] * n / 2)) < 1e-28
