@@ -1,0 +1,257 @@
+"""Benchmark: encrypted LeNet-1-shape inference on one MI355X.
+
+Headline (`value`): plain LeNet-1 (Table M2 shape) encrypted inferences per
+second at N = 2^14 with the 60 + 7 x 40-bit chain and a 60-bit special
+prime, scale 2^40, one image per ciphertext, one key switch per rotation,
+evaluated layer by layer (the paper's method as written).  A step is one
+whole encrypted inference; its input ciphertext and the evaluation keys are
+resident in HBM before the timer starts.
+
+Also reported on the same JSON line:
+  batched   - the batched evaluator (ten 28 x 28 images per ciphertext at
+              stride 784, many ciphertexts per launch, hoisted rotations):
+              images/s and its multiple of the plain rate;
+  rotations - rotations/s of a single rotation at the same size;
+  roofline  - the dominant kernel family, timed with HIP events on its launch
+              stream over a replay of the timed steps;
+  cpu_baseline - the CPU oracle (scalar C, one thread) timed on one whole
+              inference of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HBM_PEAK_GBS = 8000.0
+
+
+def _pack(net_input: dict, xs: np.ndarray, n_slots: int, stride: int) -> np.ndarray:
+    """Client-side packing: sample b's row-major (C, H, W) values at slot b * stride."""
+    v = np.zeros(n_slots)
+    for b, x in enumerate(xs):
+        flat = np.asarray(x, dtype=np.float64).reshape(-1)
+        v[b * stride: b * stride + flat.size] = flat
+    return v
+
+
+def setup(P, W, name: str, batch: int, seed: int = 5):
+    import torch
+    cfg = W.config(name)
+    ctx = P.Context(cfg["log_n"], cfg["prime_bits"], cfg["special_bits"], 2.0 ** cfg["log_scale"])
+    params = W.gen_params(cfg["layers"])
+    S, stride = cfg["samples_per_ct"], cfg["sample_stride"]
+    net = P.Net(ctx, cfg["input"], cfg["layers"], params, samples=S, stride=stride, max_batch=batch)
+    sk = P.keygen_secret(ctx, seed)
+    keys = {r: P.gen_switch_key(ctx, sk, seed + 1, steps=r) for r in net.rotations()}
+    rlk = P.gen_switch_key(ctx, sk, seed + 2, relin=True)
+    net.bind_keys(keys, rlk)
+    xs = W.gen_inputs(cfg["input"], S * batch)
+    pts = [ctx.encode(_pack(cfg["input"], xs[b * S:(b + 1) * S], ctx.slots, stride if S > 1 else ctx.slots),
+                      ctx.scale, net.in_limbs, mont=False) for b in range(batch)]
+    ct = P.encrypt_sk(ctx, sk, torch.stack(pts), seed + 3, ctx.scale)
+    torch.cuda.synchronize()
+    return {"cfg": cfg, "ctx": ctx, "net": net, "sk": sk, "keys": keys, "rlk": rlk, "ct": ct, "xs": xs,
+            "params": params, "outs": net.alloc_outputs(batch)}
+
+
+def max_error(P, W, st) -> float:
+    """Decrypt every sample's outputs and compare with a direct FP64 CNN."""
+    cfg, ctx, net = st["cfg"], st["ctx"], st["net"]
+    S, B = cfg["samples_per_ct"], st["ct"].batch
+    pos = net.output_slots()                     # [S][values]: (ciphertext << 32) | slot
+    ids = pos >> np.uint64(32)
+    slots = (pos & np.uint64(0xFFFFFFFF)).astype(np.uint32)
+    got = np.zeros((B,) + pos.shape)
+    for k in np.unique(ids):
+        sel = ids == k
+        vals = P.decrypt_slots(ctx, st["sk"], st["outs"][int(k)], slots[sel])
+        for b in range(B):
+            got[b][sel] = vals[b]
+    err = 0.0
+    for b in range(B):
+        for s in range(S):
+            ref = _fp64_cnn(st["xs"][b * S + s], cfg["layers"], st["params"])
+            err = max(err, float(np.abs(got[b, s] - ref).max()))
+    return err
+
+
+def _fp64_cnn(x, layers, params):
+    """Direct FP64 forward pass (valid convolutions, mean pooling)."""
+    a = np.asarray(x, dtype=np.float64)
+    for L, p in zip(layers, params):
+        k = L["kind"]
+        if k == "conv":
+            w, b = p
+            kh, kw = w.shape[2], w.shape[3]
+            sh = 1 if L.get("dims") == 1 else L["s"]
+            sw = L["s"]
+            C, H, Wd = a.shape
+            Ho, Wo = (H - kh) // sh + 1, (Wd - kw) // sw + 1
+            out = np.zeros((w.shape[0], Ho, Wo))
+            for y in range(Ho):
+                for xx in range(Wo):
+                    patch = a[:, sh * y:sh * y + kh, sw * xx:sw * xx + kw]
+                    out[:, y, xx] = np.tensordot(w, patch, axes=3) + b
+            a = out
+        elif k == "square":
+            a = a * a
+        elif k == "avgpool":
+            c = L["c"]
+            C, H, Wd = a.shape
+            a = a[:, :H // c * c, :Wd // c * c].reshape(C, H // c, c, Wd // c, c).mean(axis=(2, 4))
+        elif k == "flatten":
+            a = a.reshape(-1)
+        elif k == "fc":
+            w, b = p
+            a = w @ a.reshape(-1) + b
+    return a.reshape(-1)
+
+
+def timed(fn, steps: int, warmup: int) -> float:
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def family_stats(P, fn, steps: int) -> dict:
+    import torch
+    torch.cuda.synchronize()
+    P.stats_enable(True)
+    P.stats_reset()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    s = P.stats()
+    P.stats_enable(False)
+    return s
+
+
+def roofline_entry(stats: dict, traffic=None) -> dict:
+    fam = max(stats, key=lambda k: stats[k][1])
+    n, ms, by = stats[fam]
+    avg_s = ms / 1e3 / max(n, 1)
+    achieved = by / max(n, 1) / avg_s / 1e9
+    return {"kernel": fam, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "launches": n, "avg_us": round(avg_s * 1e6, 2), "bytes_per_launch": by / max(n, 1)}
+
+
+def cpu_baseline(W) -> dict:
+    """The oracle (scalar C, one thread) on one whole encrypted LeNet-1
+    inference at the same parameters; keys are made before the timer."""
+    from oracle.run import OracleSession, build_net, run_encrypted
+    cfg = W.config("lenet1")
+    sess = OracleSession(cfg)
+    net = build_net(cfg, sess.ck.slots)
+    sess.ensure_keys(net.rotation_set())
+    xs = W.gen_inputs(cfg["input"], 1)
+    t0 = time.perf_counter()
+    run_encrypted(sess, net, xs)
+    dt = time.perf_counter() - t0
+    return {"value": round(1.0 / dt, 5), "unit": "inferences/s", "cores": 1, "kind": "oracle",
+            "sample": f"one whole LeNet-1 encrypted inference (N=2^14, 8 limbs, 288 rotations), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--batched-cts", type=int, default=128, help="ciphertexts per batched launch (10 images each)")
+    ap.add_argument("--batched-steps", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--only-plain", action="store_true", help="skip every extra measurement (for profiling)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported in this build "
+              "(the path shards by ciphertext with replicated keys; see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2402_03060_amd as P
+    import workloads as W
+
+    print("[bench] setup plain LeNet-1 (N=2^14)", file=sys.stderr, flush=True)
+    st = setup(P, W, "lenet1", batch=1)
+    net, ct, outs = st["net"], st["ct"], st["outs"]
+    net.set_mode(P.EVAL_PLAIN)
+    step = lambda: net.eval(ct, outs)
+    dt = timed(step, args.steps, args.warmup)
+    value = args.steps / dt
+    err = max_error(P, W, st)
+    print(f"[bench] plain: {value:.2f} inf/s, max |err| {err:.2e}", file=sys.stderr, flush=True)
+    res = {
+        "metric": "encrypted LeNet-1-shape inferences/s (plain: one image per ciphertext, one key switch per rotation)",
+        "value": round(value, 3), "unit": "inferences/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(1e3 * dt / args.steps, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u64",
+        "data": "synthetic (seeded: uniform [0,1] 28x28 images, weights N(0,0.1^2), biases N(0,0.01^2))",
+        "config": {"workload": "LeNet-1 shape (Table M2): conv 1->4 K5, sq, pool2, conv 4->12 K5, sq, pool2, "
+                               "flatten, FC 192->10", "log_n": 14, "primes": "60 + 7x40 (+60 special)",
+                   "scale": "2^40", "images_per_ct": 1, "mode": "plain"},
+        "max_abs_err_vs_fp64": err,
+    }
+    if args.only_plain:
+        print(json.dumps(res))
+        return
+
+    stats = family_stats(P, step, args.steps)
+    res["roofline"] = roofline_entry(stats)
+    res["kernel_families_ms_per_step"] = {k: round(v[1] / args.steps, 4) for k, v in stats.items() if v[0]}
+
+    # hoisted evaluation of the same single-image workload
+    net.set_mode(P.EVAL_HOISTED)
+    dth = timed(step, args.steps, 1)
+    res["plain_hoisted_inferences_per_s"] = round(args.steps / dth, 3)
+    net.set_mode(P.EVAL_PLAIN)
+
+    # rotations/s at the same size (one ciphertext, 8 limbs)
+    ctx = st["ctx"]
+    ws = ctx.workspace(8, 1)
+    key = st["keys"][1]
+    full = ctx.empty_ct(1, 8, ctx.scale)
+    full.data.copy_(st["ct"].data)
+    rot = lambda: ctx.rotate(full, 1, key, ws)
+    dtr = timed(rot, 50, 5)
+    res["rotations_per_s"] = round(50 / dtr, 1)
+
+    if not args.no_batched:
+        B = args.batched_cts
+        print(f"[bench] setup batched LeNet-1 ({B} ciphertexts x 10 images)", file=sys.stderr, flush=True)
+        del st, step
+        torch.cuda.empty_cache()
+        sb = setup(P, W, "lenet1_batched", batch=B)
+        nb, ctb, outb = sb["net"], sb["ct"], sb["outs"]
+        nb.set_mode(P.EVAL_HOISTED)
+        stepb = lambda: nb.eval(ctb, outb)
+        dtb = timed(stepb, args.batched_steps, 1)
+        imgs = args.batched_steps * B * 10 / dtb
+        errb = max_error(P, W, sb)
+        res["batched"] = {"images_per_s": round(imgs, 2), "ms_per_launch": round(1e3 * dtb / args.batched_steps, 2),
+                          "images_per_launch": B * 10, "multiple_of_plain": round(imgs / value, 2),
+                          "max_abs_err_vs_fp64": errb}
+        print(f"[bench] batched: {imgs:.1f} img/s ({imgs / value:.1f}x plain), max |err| {errb:.2e}",
+              file=sys.stderr, flush=True)
+
+    if not args.no_cpu_baseline:
+        print("[bench] CPU oracle baseline (one inference)", file=sys.stderr, flush=True)
+        res["cpu_baseline"] = cpu_baseline(W)
+    res["paper_context"] = {"lenet1_seconds": 30.089, "ten_samples_m1_seconds": 16.247,
+                            "hardware": "Intel Xeon Gold 5220 @ 2.2 GHz, SEAL single-threaded, N=2^14, scale 2^32"}
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()
