@@ -51,3 +51,28 @@ void ks_modup(const unihenn_ctx* c, const u64* d, int d_stride, int batch, int n
 void ks_finish(const unihenn_ctx* c, const u64* d, int d_stride, const u64* key, int nd, int batch, int nl, u32 g,
                u64* out, const u64* add0, const u64* add1, int add_stride, KsWs& ws, hipStream_t s);
 void rescale_core(const unihenn_ctx* c, const u64* in, int batch, int nl, u64* out, KsWs& ws, hipStream_t s);
+
+// ---- grouped rotations (several rotations per launch set) ----
+#define UH_GROUP_MAX 32
+struct GroupArgs {
+    int E;                          // rotations in the group
+    const u64* src[UH_GROUP_MAX];   // source ciphertexts [B][2][nl]
+    u64* dst[UH_GROUP_MAX];         // destinations [B][2][nl]
+    const u64* key[UH_GROUP_MAX];   // switching keys (device form)
+    u32 g[UH_GROUP_MAX];            // Galois element of the rotation
+    u32 gin[UH_GROUP_MAX];          // permutation applied when reading digits (hoisted: g, plain: 1)
+    int blk[UH_GROUP_MAX];          // ModUp block holding the element's digits
+    const u64* dsrc[UH_GROUP_MAX];  // per ModUp block: NTT rows (b, j) at dsrc + (b * dstride + j) * N
+    int dstride;
+};
+// ModUp of D polynomials (rows (b, j) at dsrc[d] + (b * dstride + j) * N, NTT
+// form): dcoef [D][B][nl] and modup [D][B][nl][nl]
+void group_modup(const unihenn_ctx* c, int D, const u64* const* dsrc, int dstride, int B, int nl, u64* dcoef,
+                 u64* modup, hipStream_t s);
+// inner product with each element's key, ModDown, and the c0 addend: aux holds
+// tau_g(src) per element ([E][B][2][nl]); with c0_only the c0 rows of aux
+// are computed here (hoisted), otherwise the caller filled aux.
+void group_switch(const unihenn_ctx* c, const GroupArgs& ga, int B, int nl, bool c0_only, const u64* modup, u64* aux,
+                  u64* U, u64* Up, u64* R, hipStream_t s);
+// aux[e] = tau_{g_e}(src_e), both polynomials
+void group_auto_both(const unihenn_ctx* c, const GroupArgs& ga, int B, int nl, u64* aux, hipStream_t s);

@@ -2,6 +2,8 @@
 // path.  Every kernel is memory-streaming over limb rows of N words; threads
 // map to consecutive coefficients so each wavefront touches 512 contiguous
 // bytes of a row.
+#include <cstring>
+
 #include "kernels.h"
 
 namespace {
@@ -342,4 +344,164 @@ void launch_mont_convert(const unihenn_ctx* c, u64* data, int rows, const RowMap
     if (rows <= 0) return;
     LaunchTimer tm(KF_OTHER, 16.0 * c->n * rows, s);
     k_mont_convert<<<grid_rows(c->n, rows), EW_THREADS, 0, s>>>(data, c->dev, map, to_mont);
+}
+
+// ------------------------------------------------------------------ grouped rotations
+namespace {
+
+// aux[e][b][c][i] = tau_{g_e}(src_e)[b][c][i]; c0_only: c = 0 rows only
+__global__ void k_group_auto(u64* __restrict__ aux, GroupArgs ga, int nl, int batch, int log_n, int c0_only)
+{
+    const int n = 1 << log_n;
+    const u32 k = blockIdx.x * EW_THREADS + threadIdx.x;
+    if (k >= (u32)n) return;
+    const int e = blockIdx.z;
+    const int r = blockIdx.y;  // (b * 2 + c) * nl + i  (c0_only: b * nl + i)
+    int b, c, i;
+    if (c0_only) { i = r % nl; b = r / nl; c = 0; }
+    else { i = r % nl; c = (r / nl) & 1; b = r / (2 * nl); }
+    const size_t row = ((size_t)b * 2 + c) * nl + i;
+    aux[((size_t)e * batch * 2 * nl + row) * n + k] = ga.src[e][row * n + auto_perm(k, ga.g[e], log_n)];
+}
+
+// dcoef[blk][b][j] = dsrc_blk rows (b, j)
+__global__ void k_group_gather(u64* __restrict__ dcoef, GroupArgs ga, int nl, int batch, int n)
+{
+    const int k = blockIdx.x * EW_THREADS + threadIdx.x;
+    if (k >= n) return;
+    const int r = blockIdx.y;  // b * nl + j
+    const int blk = blockIdx.z;
+    const int j = r % nl, b = r / nl;
+    dcoef[(((size_t)blk * batch + b) * nl + j) * n + k] = ga.dsrc[blk][((size_t)b * ga.dstride + j) * n + k];
+}
+
+template <int MAXL>
+__global__ void __launch_bounds__(EW_THREADS) k_group_inner(u64* __restrict__ U, u64* __restrict__ Up,
+                                                            const u64* __restrict__ modup, GroupArgs ga, DevCtx ctx,
+                                                            int nl, int nd, int batch)
+{
+    const int n = ctx.n;
+    const int k = blockIdx.x * EW_THREADS + threadIdx.x;
+    if (k >= n) return;
+    const int t = blockIdx.y;  // 0..nl
+    const int e = blockIdx.z;
+    const int tm = t == nl ? ctx.p_index : t;
+    const int klimb = t == nl ? nd : t;
+    const Modulus M = ctx.mod[tm];
+    const u32 g = ga.gin[e];
+    const u32 src = g == 1 ? (u32)k : auto_perm((u32)k, g, ctx.log_n);
+    const u64* __restrict__ key = ga.key[e];
+    const u64* __restrict__ dsrc = ga.dsrc[ga.blk[e]];
+    const int blk = ga.blk[e];
+    u64 k0[MAXL], k1[MAXL];
+#pragma unroll
+    for (int j = 0; j < MAXL; ++j) {
+        if (j < nl) {
+            k0[j] = key[(((size_t)j * 2 + 0) * (nd + 1) + klimb) * n + k];
+            k1[j] = key[(((size_t)j * 2 + 1) * (nd + 1) + klimb) * n + k];
+        }
+    }
+    for (int b = 0; b < batch; ++b) {
+        u64 a0 = 0, a1 = 0;
+#pragma unroll
+        for (int j = 0; j < MAXL; ++j) {
+            if (j < nl) {
+                u64 d;
+                if (t == j) {
+                    d = dsrc[((size_t)b * ga.dstride + j) * n + src];
+                } else {
+                    const int s = t < j ? t : t - 1;
+                    d = modup[((((size_t)blk * batch + b) * nl + j) * nl + s) * n + src];
+                }
+                a0 = add_mod(a0, mont_mul(d, k0[j], M.q, M.qinv_neg), M.q);
+                a1 = add_mod(a1, mont_mul(d, k1[j], M.q, M.qinv_neg), M.q);
+            }
+        }
+        const size_t eb = (size_t)e * batch + b;
+        if (t < nl) {
+            U[((eb * 2 + 0) * nl + t) * n + k] = a0;
+            U[((eb * 2 + 1) * nl + t) * n + k] = a1;
+        } else {
+            Up[(eb * 2 + 0) * n + k] = a0;
+            Up[(eb * 2 + 1) * n + k] = a1;
+        }
+    }
+}
+
+// dst_e[b][c][i] = (U - R) P^-1 (+ aux c0 on c = 0)
+__global__ void k_group_sub_scale(GroupArgs ga, const u64* __restrict__ U, const u64* __restrict__ R,
+                                  const u64* __restrict__ aux, const u64* __restrict__ inv, DevCtx ctx, int nl,
+                                  int batch)
+{
+    const int n = ctx.n;
+    const int k = blockIdx.x * EW_THREADS + threadIdx.x;
+    if (k >= n) return;
+    const int r = blockIdx.y;  // (b * 2 + c) * nl + i
+    const int e = blockIdx.z;
+    const int i = r % nl, c = (r / nl) & 1, b = r / (2 * nl);
+    const u64 q = ctx.mod[i].q;
+    const size_t row = (size_t)e * batch * 2 * nl + r;
+    u64 v = sub_mod(U[row * n + k], R[row * n + k], q);
+    v = mul_shoup(v, inv[2 * i], inv[2 * i + 1], q);
+    if (c == 0) v = add_mod(v, aux[(((size_t)e * batch + b) * 2 * nl + i) * n + k], q);
+    ga.dst[e][(size_t)r * n + k] = v;
+}
+
+}  // namespace
+
+void group_modup(const unihenn_ctx* c, int D, const u64* const* dsrc, int dstride, int B, int nl, u64* dcoef,
+                 u64* modup, hipStream_t s)
+{
+    GroupArgs ga;
+    memset(&ga, 0, sizeof(ga));
+    for (int d = 0; d < D; ++d) ga.dsrc[d] = dsrc[d];
+    ga.dstride = dstride;
+    {
+        LaunchTimer tm(KF_OTHER, 16.0 * c->n * D * B * nl, s);
+        dim3 g3((c->n + EW_THREADS - 1) / EW_THREADS, B * nl, D);
+        k_group_gather<<<g3, EW_THREADS, 0, s>>>(dcoef, ga, nl, B, c->n);
+    }
+    launch_ntt_inv(c, dcoef, D * B * nl, rowmap_ct(nl), s);
+    launch_modup(c, modup, dcoef, D * B, nl, s);
+    launch_ntt_fwd(c, modup, D * B * nl * nl, rowmap_modup(nl, c->n_data), s);
+}
+
+void group_switch(const unihenn_ctx* c, const GroupArgs& ga, int B, int nl, bool c0_only, const u64* modup, u64* aux,
+                  u64* U, u64* Up, u64* R, hipStream_t s)
+{
+    const int E = ga.E;
+    const unsigned gx = (c->n + EW_THREADS - 1) / EW_THREADS;
+    {
+        double rows = (double)E * 2.0 * nl * (nl + 1) + (double)E * B * (nl * (nl + 1) + 2 * (nl + 1));
+        LaunchTimer tm(KF_KS_INNER, 8.0 * c->n * rows, s);
+        dim3 g3(gx, nl + 1, E);
+        if (nl <= 4)
+            k_group_inner<4><<<g3, EW_THREADS, 0, s>>>(U, Up, modup, ga, c->dev, nl, c->n_data, B);
+        else if (nl <= 8)
+            k_group_inner<8><<<g3, EW_THREADS, 0, s>>>(U, Up, modup, ga, c->dev, nl, c->n_data, B);
+        else if (nl <= 12)
+            k_group_inner<12><<<g3, EW_THREADS, 0, s>>>(U, Up, modup, ga, c->dev, nl, c->n_data, B);
+        else
+            k_group_inner<UH_MAX_MODULI><<<g3, EW_THREADS, 0, s>>>(U, Up, modup, ga, c->dev, nl, c->n_data, B);
+    }
+    if (c0_only) {
+        LaunchTimer tm(KF_AUTO, 16.0 * c->n * E * B * nl, s);
+        dim3 g3(gx, B * nl, E);
+        k_group_auto<<<g3, EW_THREADS, 0, s>>>(aux, ga, nl, B, c->log_n, 1);
+    }
+    launch_ntt_inv(c, Up, E * B * 2, rowmap_list({c->n_data}), s);
+    launch_lift_last(c, R, Up, E * B * 2, nl, c->n_data, KF_MODDOWN, s);
+    launch_ntt_fwd(c, R, E * B * 2 * nl, rowmap_ct(nl), s);
+    {
+        LaunchTimer tm(KF_MODDOWN, 8.0 * c->n * E * B * 2 * nl * 3.5, s);
+        dim3 g3(gx, B * 2 * nl, E);
+        k_group_sub_scale<<<g3, EW_THREADS, 0, s>>>(ga, U, R, aux, c->d_p_inv, c->dev, nl, B);
+    }
+}
+
+void group_auto_both(const unihenn_ctx* c, const GroupArgs& ga, int B, int nl, u64* aux, hipStream_t s)
+{
+    LaunchTimer tm(KF_AUTO, 16.0 * c->n * ga.E * B * 2 * nl, s);
+    dim3 g3((c->n + EW_THREADS - 1) / EW_THREADS, B * 2 * nl, ga.E);
+    k_group_auto<<<g3, EW_THREADS, 0, s>>>(aux, ga, nl, B, c->log_n, 0);
 }

@@ -15,6 +15,7 @@
 // source become consecutive, so they can share one digit decomposition.
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <map>
 #include <string>
 #include <vector>
@@ -104,6 +105,7 @@ struct unihenn_net {
     std::vector<size_t> phys_off;
     u64* ws = nullptr;
     int ws_nl = 0;
+    int group_max = 1;       // rotations per grouped key-switch launch set
     std::map<int, const u64*> keys;
     const u64* rlk = nullptr;
     int mode = UNIHENN_EVAL_PLAIN;
@@ -165,6 +167,17 @@ struct Planner {
         s.b = b;
         net->steps.push_back(s);
         return d;
+    }
+
+    // sum of ciphertexts (a chain of additions)
+    int sum(const std::vector<int>& xs)
+    {
+        int acc = -1;
+        for (int x : xs) {
+            acc = acc < 0 ? x : add(acc, x);
+            if (acc < 0) return -1;
+        }
+        return acc;
     }
 
     // request plaintexts Encode(w_t * z) at `scale` and nl limbs; returns the
@@ -359,13 +372,11 @@ struct Planner {
         std::map<int, int> mapped;
         for (int reg : L.ch_reg) {
             if (mapped.count(reg)) continue;
-            int acc = -1;
+            std::vector<int> terms;
             for (int dy = 0; dy < cc; ++dy)
-                for (int dx = 0; dx < cc; ++dx) {
-                    int t = rot(reg, (long)L.I * (dx + (long)L.W_img * dy));
-                    acc = acc < 0 ? t : add(acc, t);
-                    if (acc < 0) return -1;
-                }
+                for (int dx = 0; dx < cc; ++dx) terms.push_back(rot(reg, (long)L.I * (dx + (long)L.W_img * dy)));
+            int acc = sum(terms);
+            if (acc < 0) return -1;
             mapped[reg] = acc;
         }
         for (int& reg : L.ch_reg) reg = mapped[reg];
@@ -436,12 +447,10 @@ struct Planner {
                 pts.push_back(request(mask(pos), std::vector<double>(1, L.pending), delta, nl, 1));
             }
             for (int& X : ys) {
-                int T = -1;
-                for (int m = 0; m < S; ++m) {
-                    int t = rot(X, (long)m * (S - 1));
-                    T = T < 0 ? t : add(T, t);
-                    if (T < 0) return -1;
-                }
+                std::vector<int> shifted;
+                for (int m = 0; m < S; ++m) shifted.push_back(rot(X, (long)m * (S - 1)));
+                int T = sum(shifted);
+                if (T < 0) return -1;
                 std::vector<Term> terms;
                 for (int gq = 0; gq < G; ++gq) terms.push_back({rot(T, (long)gq * S * (S - 1)), pts[gq]});
                 X = mac_rescale(terms);
@@ -474,12 +483,10 @@ struct Planner {
             }
         }
         // pack: channel o shifted right by o H W
-        int acc = -1;
-        for (int o = 0; o < (int)ys.size(); ++o) {
-            int t = rot(ys[o], -(long)o * Wi * Hi);
-            acc = acc < 0 ? t : add(acc, t);
-            if (acc < 0) return -1;
-        }
+        std::vector<int> placed;
+        for (int o = 0; o < (int)ys.size(); ++o) placed.push_back(rot(ys[o], -(long)o * Wi * Hi));
+        int acc = sum(placed);
+        if (acc < 0) return -1;
         Layout out;
         out.vec = true;
         out.length = L.C * Hi * Wi;
@@ -514,12 +521,10 @@ struct Planner {
         }
         int csum = mac_rescale(terms);
         if (csum < 0) return -1;
-        int acc = -1;
-        for (int i = 0; i < reps; ++i) {
-            int t = rot(csum, (long)i * D);
-            acc = acc < 0 ? t : add(acc, t);
-            if (acc < 0) return -1;
-        }
+        std::vector<int> parts;
+        for (int i = 0; i < reps; ++i) parts.push_back(rot(csum, (long)i * D));
+        int acc = sum(parts);
+        if (acc < 0) return -1;
         std::vector<long> pos;
         for (int p = 0; p < D; ++p) pos.push_back(p);
         std::vector<double> bz(net->n_slots, 0.0);
@@ -773,7 +778,10 @@ extern "C" int unihenn_net_create(const unihenn_ctx* c, const unihenn_input* in,
         reg_words += (size_t)max_batch * 2 * nl * c->n;
     }
     net->ws_nl = net->in_limbs;
-    size_t ws_words = ks_ws_rows(net->ws_nl, (int)max_batch) * c->n;
+    net->group_max = std::max(1, std::min(UH_GROUP_MAX, 32 / (int)max_batch));
+    const size_t L0 = (size_t)net->ws_nl, Bm = max_batch, E = (size_t)net->group_max;
+    const size_t group_rows = Bm * (L0 + L0 * L0) + E * Bm * (L0 * L0 + 7 * L0 + 2);
+    size_t ws_words = std::max(ks_ws_rows(net->ws_nl, (int)max_batch), group_rows) * c->n;
     if (hipMalloc(&net->pt_arena, sizeof(u64) * std::max<size_t>(net->pt_words, 1)) != hipSuccess ||
         hipMalloc(&net->reg_arena, sizeof(u64) * std::max<size_t>(reg_words, 1)) != hipSuccess ||
         hipMalloc(&net->ws, sizeof(u64) * ws_words) != hipSuccess) {
@@ -870,6 +878,89 @@ struct Exec {
         return net->reg_arena + net->phys_off[net->regs[r].phys];
     }
 
+    // workspace carve for grouped rotations (fixed offsets at the net's widest level)
+    struct GroupWs {
+        u64 *pdcoef, *pmodup, *aux, *dcoef, *modup, *U, *Up, *R;
+    };
+    GroupWs carve() const
+    {
+        const size_t rn = (size_t)c->n, L0 = (size_t)net->ws_nl, Bm = (size_t)net->max_batch,
+                     E = (size_t)net->group_max;
+        GroupWs w;
+        u64* p = net->ws;
+        w.pdcoef = p; p += Bm * L0 * rn;
+        w.pmodup = p; p += Bm * L0 * L0 * rn;
+        w.aux = p;    p += E * Bm * 2 * L0 * rn;
+        w.dcoef = p;  p += E * Bm * L0 * rn;
+        w.modup = p;  p += E * Bm * L0 * L0 * rn;
+        w.U = p;      p += E * Bm * 2 * L0 * rn;
+        w.Up = p;     p += E * Bm * 2 * rn;
+        w.R = p;
+        return w;
+    }
+
+    void fill(GroupArgs& ga, const std::vector<size_t>& run, size_t from, int count)
+    {
+        memset(&ga, 0, sizeof(ga));
+        ga.E = count;
+        for (int e = 0; e < count; ++e) {
+            const Step& st = net->steps[run[from + e]];
+            ga.src[e] = reg(st.a);
+            ga.dst[e] = reg(st.dst);
+            ga.key[e] = net->keys.at(st.rot);
+            ga.g[e] = galois_elt(c, st.rot);
+        }
+    }
+
+    void rotations(const std::vector<size_t>& run, int nl)
+    {
+        const size_t rn = (size_t)c->n;
+        GroupWs w = carve();
+        const int Emax = net->group_max;
+        if (net->mode == UNIHENN_EVAL_HOISTED) {
+            size_t i = 0;
+            while (i < run.size()) {
+                const int src = net->steps[run[i]].a;
+                size_t j = i;
+                while (j < run.size() && net->steps[run[j]].a == src) ++j;
+                if (modup_owner != src) {
+                    const u64* d = reg(src) + (size_t)nl * rn;
+                    group_modup(c, 1, &d, 2 * nl, B, nl, w.pdcoef, w.pmodup, s);
+                    modup_owner = src;
+                }
+                for (size_t k = i; k < j; k += Emax) {
+                    GroupArgs ga;
+                    fill(ga, run, k, (int)std::min<size_t>(Emax, j - k));
+                    ga.dsrc[0] = reg(src) + (size_t)nl * rn;
+                    ga.dstride = 2 * nl;
+                    for (int e = 0; e < ga.E; ++e) {
+                        ga.blk[e] = 0;
+                        ga.gin[e] = ga.g[e];
+                    }
+                    group_switch(c, ga, B, nl, true, w.pmodup, w.aux, w.U, w.Up, w.R, s);
+                }
+                i = j;
+            }
+        } else {
+            for (size_t k = 0; k < run.size(); k += Emax) {
+                GroupArgs ga;
+                fill(ga, run, k, (int)std::min<size_t>(Emax, run.size() - k));
+                ga.dstride = 2 * nl;
+                std::vector<const u64*> d(ga.E);
+                for (int e = 0; e < ga.E; ++e) {
+                    ga.blk[e] = e;
+                    ga.gin[e] = 1;
+                    ga.dsrc[e] = w.aux + ((size_t)e * B * 2 * nl + nl) * rn;  // c1 of tau(src_e)
+                    d[e] = ga.dsrc[e];
+                }
+                group_auto_both(c, ga, B, nl, w.aux, s);
+                group_modup(c, ga.E, d.data(), 2 * nl, B, nl, w.dcoef, w.modup, s);
+                group_switch(c, ga, B, nl, false, w.modup, w.aux, w.U, w.Up, w.R, s);
+            }
+            modup_owner = -1;
+        }
+    }
+
     int run(size_t begin, size_t end)
     {
         const size_t rn = (size_t)c->n;
@@ -882,24 +973,17 @@ struct Exec {
                 launch_gather_rows(c, reg(st.dst), ext_in, B * 2 * nl, nl, ext_in_limbs, 0, s);
                 break;
             case ST_ROT: {
-                const u64* key = net->keys.at(st.rot);
-                const u32 g = galois_elt(c, st.rot);
-                const u64* src = reg(st.a);
-                if (net->mode == UNIHENN_EVAL_HOISTED) {
-                    if (modup_owner != st.a) {
-                        ks_modup(c, src + (size_t)nl * rn, 2 * nl, B, nl, w, s);
-                        modup_owner = st.a;
-                    }
-                    launch_automorphism(c, w.aux, src, B * 2 * nl, g, s);
-                    ks_finish(c, src + (size_t)nl * rn, 2 * nl, key, c->n_data, B, nl, g, reg(st.dst), w.aux, nullptr,
-                              2 * nl, w, s);
-                } else {
-                    launch_automorphism(c, w.aux, src, B * 2 * nl, g, s);
-                    ks_modup(c, w.aux + (size_t)nl * rn, 2 * nl, B, nl, w, s);
-                    ks_finish(c, w.aux + (size_t)nl * rn, 2 * nl, key, c->n_data, B, nl, 1, reg(st.dst), w.aux,
-                              nullptr, 2 * nl, w, s);
-                    modup_owner = -1;
+                // a run of consecutive rotations at this level, none reading another's result
+                std::vector<size_t> run;
+                size_t sj = si;
+                while (sj < end && net->steps[sj].kind == ST_ROT && net->regs[net->steps[sj].dst].nl == nl) {
+                    bool dep = false;
+                    for (size_t x : run) dep |= net->steps[x].dst == net->steps[sj].a;
+                    if (dep) break;
+                    run.push_back(sj++);
                 }
+                rotations(run, nl);
+                si = sj - 1;
                 break;
             }
             case ST_MAC: {
@@ -919,6 +1003,7 @@ struct Exec {
                 const int nla = net->regs[st.a].nl;
                 KsWs wa = ks_ws_carve(net->ws, nla, B, c->n);
                 rescale_core(c, reg(st.a), B, nla, reg(st.dst), wa, s);
+                modup_owner = -1;
                 break;
             }
             case ST_ADD:

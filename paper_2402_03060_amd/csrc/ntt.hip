@@ -154,6 +154,153 @@ __global__ void __launch_bounds__(NTT_THREADS) k_ntt_inv(u64* __restrict__ data,
     }
 }
 
+
+// Radix-8 register rounds: each thread holds the 8 elements of its
+// sub-transform that differ in three consecutive index bits, applies up to
+// three butterfly stages in registers, and exchanges through LDS once per
+// round (one barrier per three stages).  All index arithmetic is shifts and
+// masks (sub-transform size and tile width are powers of two).
+template <int LOG_R, bool STRIDED, bool INV, bool LAST>
+__global__ void __launch_bounds__(NTT_THREADS) k_ntt_r8(u64* __restrict__ data, DevCtx ctx, RowMap map, int log_cols,
+                                                        int sigma0)
+{
+    constexpr int LOG_G = LOG_R - 3;  // threads per sub-transform: 2^LOG_G
+    constexpr int ROUNDS = (LOG_R + 2) / 3;
+    __shared__ u64 s[TILE];
+    const int n = ctx.n, log_n = ctx.log_n;
+    const int row = blockIdx.y;
+    const int mi = rowmap_mod(map, row);
+    const Modulus M = ctx.mod[mi];
+    const u64 q = M.q, q2 = 2 * q;
+    const u64* __restrict__ tw = (INV ? ctx.itw : ctx.tw) + (size_t)mi * n;
+    const u64* __restrict__ tw_sh = (INV ? ctx.itw_sh : ctx.tw_sh) + (size_t)mi * n;
+    u64* __restrict__ a = data + (size_t)row * n;
+    const int tid = threadIdx.x;
+    const int cmask = (1 << log_cols) - 1;
+    int c, g;
+    if (STRIDED) { c = tid & cmask; g = tid >> log_cols; }
+    else { g = tid & ((1 << LOG_G) - 1); c = tid >> LOG_G; }
+    const int col = (blockIdx.x << log_cols) + c;
+    const int log_stride = log_n - LOG_R;
+    // local index u -> global index, LDS index
+#define GIDX(u) (STRIDED ? col + ((u) << log_stride) : (col << LOG_R) + (u))
+#define LIDX(u) (STRIDED ? ((u) << log_cols) + c : (c << LOG_R) + (u))
+    u64 x[8];
+#pragma unroll
+    for (int rho = 0; rho < ROUNDS; ++rho) {
+        // bits held this round: [lo, lo + 3)
+        const int lo = INV ? (3 * rho < LOG_R - 3 ? 3 * rho : LOG_R - 3)
+                           : (LOG_R - 3 - 3 * rho > 0 ? LOG_R - 3 - 3 * rho : 0);
+        const int umask = (1 << lo) - 1;
+        int ub = ((g >> lo) << (lo + 3)) | (g & umask);
+        if (rho == 0) {
+#pragma unroll
+            for (int m = 0; m < 8; ++m) x[m] = a[GIDX(ub | (m << lo))];
+        } else {
+#pragma unroll
+            for (int m = 0; m < 8; ++m) x[m] = s[LIDX(ub | (m << lo))];
+        }
+        if (!INV) {
+            // stages tau = 3 rho .. : bit b = LOG_R - 1 - tau, from the top bit down
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const int tau = 3 * rho + k;
+                if (tau >= LOG_R) break;
+                const int b = LOG_R - 1 - tau;
+                const int mb = b - lo;
+                const int sigma = sigma0 + tau;
+#pragma unroll
+                for (int m = 0; m < 8; ++m) {
+                    if (m & (1 << mb)) continue;
+                    const int u = ub | (m << lo);
+                    const int ti = (1 << sigma) + (GIDX(u) >> (log_n - sigma));
+                    u64 U = x[m];
+                    U = U >= q2 ? U - q2 : U;
+                    const u64 V = mul_shoup_lazy(x[m | (1 << mb)], tw[ti], tw_sh[ti], q);
+                    x[m] = U + V;
+                    x[m | (1 << mb)] = U - V + q2;
+                }
+            }
+        } else {
+            // stages from the lowest held bit up (tau = LOG_R - 1 - b)
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const int b = 3 * rho + k;
+                if (b >= LOG_R) break;
+                const int mb = b - lo;
+                const int tau = LOG_R - 1 - b;
+                const int sigma = sigma0 + tau;
+#pragma unroll
+                for (int m = 0; m < 8; ++m) {
+                    if (m & (1 << mb)) continue;
+                    const int u = ub | (m << lo);
+                    const int ti = (1 << sigma) + (GIDX(u) >> (log_n - sigma));
+                    const u64 U = x[m], V = x[m | (1 << mb)];
+                    const u64 sum = U + V;
+                    x[m] = sum >= q2 ? sum - q2 : sum;
+                    x[m | (1 << mb)] = mul_shoup_lazy(U - V + q2, tw[ti], tw_sh[ti], q);
+                }
+            }
+        }
+        if (rho + 1 < ROUNDS) {
+#pragma unroll
+            for (int m = 0; m < 8; ++m) s[LIDX(ub | (m << lo))] = x[m];
+            __syncthreads();
+        } else {
+#pragma unroll
+            for (int m = 0; m < 8; ++m) {
+                u64 v = x[m];
+                if (LAST) {
+                    if (INV) {
+                        v = mul_shoup(v, M.n_inv, M.n_inv_sh, q);
+                    } else {
+                        v = v >= q2 ? v - q2 : v;
+                        v = v >= q ? v - q : v;
+                    }
+                }
+                a[GIDX(ub | (m << lo))] = v;
+            }
+        }
+    }
+#undef GIDX
+#undef LIDX
+}
+
+template <int LOG_R>
+void launch_r8(u64* data, const DevCtx& dev, const RowMap& map, int n_rows, int log_n, int sigma0, bool strided,
+               bool inv, bool last, hipStream_t st)
+{
+    const int avail_log = log_n - LOG_R;                 // log2 of sub-transforms per row
+    int log_cols = 11 - LOG_R;                            // TILE = 2^11 words
+    if (log_cols > avail_log) log_cols = avail_log;
+    const int threads = 1 << (LOG_R - 3 + log_cols);
+    dim3 grid(1 << (avail_log - log_cols), n_rows);
+#define L8(S, I, Z) k_ntt_r8<LOG_R, S, I, Z><<<grid, threads, 0, st>>>(data, dev, map, log_cols, sigma0)
+    if (strided) {
+        if (!inv) { if (last) L8(true, false, true); else L8(true, false, false); }
+        else { if (last) L8(true, true, true); else L8(true, true, false); }
+    } else {
+        if (!inv) { if (last) L8(false, false, true); else L8(false, false, false); }
+        else { if (last) L8(false, true, true); else L8(false, true, false); }
+    }
+#undef L8
+}
+
+// dispatch on the sub-transform size; sizes below 8 points use the generic kernel
+bool launch_pass_r8(u64* data, const DevCtx& dev, const RowMap& map, int n_rows, int log_n, int log_r, int sigma0,
+                    bool strided, bool inv, bool last, hipStream_t st)
+{
+    switch (log_r) {
+    case 3: launch_r8<3>(data, dev, map, n_rows, log_n, sigma0, strided, inv, last, st); return true;
+    case 4: launch_r8<4>(data, dev, map, n_rows, log_n, sigma0, strided, inv, last, st); return true;
+    case 5: launch_r8<5>(data, dev, map, n_rows, log_n, sigma0, strided, inv, last, st); return true;
+    case 6: launch_r8<6>(data, dev, map, n_rows, log_n, sigma0, strided, inv, last, st); return true;
+    case 7: launch_r8<7>(data, dev, map, n_rows, log_n, sigma0, strided, inv, last, st); return true;
+    case 8: launch_r8<8>(data, dev, map, n_rows, log_n, sigma0, strided, inv, last, st); return true;
+    default: return false;
+    }
+}
+
 void split(int log_n, int* l1, int* l2)
 {
     *l1 = log_n / 2;
@@ -176,12 +323,16 @@ void launch_ntt_fwd(const unihenn_ctx* c, u64* data, int n_rows, const RowMap& m
     int l1, l2;
     split(c->log_n, &l1, &l2);
     LaunchTimer tm(KF_NTT_FWD, 16.0 * c->n * n_rows, st);
-    int cols1 = tile_cols(l1, c->log_n);
-    dim3 g1((1 << (c->log_n - l1)) / cols1, n_rows);
-    k_ntt_fwd<true, false><<<g1, NTT_THREADS, 0, st>>>(data, c->dev, map, l1, cols1, 0);
-    int cols2 = tile_cols(l2, c->log_n);
-    dim3 g2((1 << (c->log_n - l2)) / cols2, n_rows);
-    k_ntt_fwd<false, true><<<g2, NTT_THREADS, 0, st>>>(data, c->dev, map, l2, cols2, l1);
+    if (!launch_pass_r8(data, c->dev, map, n_rows, c->log_n, l1, 0, true, false, false, st)) {
+        int cols1 = tile_cols(l1, c->log_n);
+        dim3 g1((1 << (c->log_n - l1)) / cols1, n_rows);
+        k_ntt_fwd<true, false><<<g1, NTT_THREADS, 0, st>>>(data, c->dev, map, l1, cols1, 0);
+    }
+    if (!launch_pass_r8(data, c->dev, map, n_rows, c->log_n, l2, l1, false, false, true, st)) {
+        int cols2 = tile_cols(l2, c->log_n);
+        dim3 g2((1 << (c->log_n - l2)) / cols2, n_rows);
+        k_ntt_fwd<false, true><<<g2, NTT_THREADS, 0, st>>>(data, c->dev, map, l2, cols2, l1);
+    }
 }
 
 void launch_ntt_inv(const unihenn_ctx* c, u64* data, int n_rows, const RowMap& map, hipStream_t st)
@@ -190,10 +341,14 @@ void launch_ntt_inv(const unihenn_ctx* c, u64* data, int n_rows, const RowMap& m
     int l1, l2;
     split(c->log_n, &l1, &l2);
     LaunchTimer tm(KF_NTT_INV, 16.0 * c->n * n_rows, st);
-    int cols2 = tile_cols(l2, c->log_n);
-    dim3 g2((1 << (c->log_n - l2)) / cols2, n_rows);
-    k_ntt_inv<false, false><<<g2, NTT_THREADS, 0, st>>>(data, c->dev, map, l2, cols2, l1);
-    int cols1 = tile_cols(l1, c->log_n);
-    dim3 g1((1 << (c->log_n - l1)) / cols1, n_rows);
-    k_ntt_inv<true, true><<<g1, NTT_THREADS, 0, st>>>(data, c->dev, map, l1, cols1, 0);
+    if (!launch_pass_r8(data, c->dev, map, n_rows, c->log_n, l2, l1, false, true, false, st)) {
+        int cols2 = tile_cols(l2, c->log_n);
+        dim3 g2((1 << (c->log_n - l2)) / cols2, n_rows);
+        k_ntt_inv<false, false><<<g2, NTT_THREADS, 0, st>>>(data, c->dev, map, l2, cols2, l1);
+    }
+    if (!launch_pass_r8(data, c->dev, map, n_rows, c->log_n, l1, 0, true, true, true, st)) {
+        int cols1 = tile_cols(l1, c->log_n);
+        dim3 g1((1 << (c->log_n - l1)) / cols1, n_rows);
+        k_ntt_inv<true, true><<<g1, NTT_THREADS, 0, st>>>(data, c->dev, map, l1, cols1, 0);
+    }
 }
