@@ -137,14 +137,60 @@ def family_stats(P, fn, steps: int) -> dict:
     return s
 
 
+# Peak 64-bit modular butterflies per second, from the chip's unit counts:
+# the fp32 vector peak (157.3 TFLOP/s = 256 CUs x 2.4 GHz x 128 lanes x 2)
+# gives 128 full-rate VALU lane-operations per clock per CU, 7.86e13/s.
+# v_mul_lo_u32 / v_mul_hi_u32 issue at 1/4 of that and v_mad_u64_u32 at 1/2
+# (integer rate microbenchmark).  One butterfly on 64-bit words is one Shoup
+# product (6 v_mad_u64_u32 + 4 v_mul_lo_u32) plus about ten full-rate adds,
+# subtracts, compares and selects: 6*2 + 4*4 + 10 = 38 slots.
+VALU_LANE_OPS_PER_S = 256 * 128 * 2.4e9
+BUTTERFLY_SLOTS = 6 * 2 + 4 * 4 + 10
+BUTTERFLY_PEAK = VALU_LANE_OPS_PER_S / BUTTERFLY_SLOTS
+PROFILES = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles")
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per dispatch of `kernel` from the committed rocprofv3 PMC
+    summary, or None when there is none or the kernel source has changed
+    since the counters were taken."""
+    import hashlib
+    path = os.path.join(PROFILES, f"{kernel}_lenet1_plain_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2402_03060_amd", "csrc", "ntt.hip")
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != kv.get("ntt_source_sha256"):
+        return None
+    return {"read_bytes_per_dispatch": float(kv["measured_read_bytes_per_dispatch"]),
+            "write_bytes_per_dispatch": float(kv["measured_write_bytes_per_dispatch"]),
+            "read_over_algorithmic": float(kv["read_over_algorithmic"]),
+            "write_over_algorithmic": float(kv["write_over_algorithmic"]),
+            "source": os.path.basename(path)}
+
+
 def roofline_entry(stats: dict, traffic=None) -> dict:
     fam = max(stats, key=lambda k: stats[k][1])
-    n, ms, by = stats[fam]
-    avg_s = ms / 1e3 / max(n, 1)
-    achieved = by / max(n, 1) / avg_s / 1e9
-    return {"kernel": fam, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "launches": n, "avg_us": round(avg_s * 1e6, 2), "bytes_per_launch": by / max(n, 1)}
+    n, ms, by, ops = stats[fam]
+    n = max(n, 1)
+    avg_s = ms / 1e3 / n
+    out = {"kernel": fam, "launches": n, "avg_us": round(avg_s * 1e6, 3), "traffic": traffic}
+    if ops > 0:
+        achieved = ops / n / avg_s / 1e9
+        peak = BUTTERFLY_PEAK / 1e9
+        out.update({"bound": "alu", "achieved": round(achieved, 2), "peak": round(peak, 1),
+                    "unit": "G butterflies/s", "frac": round(achieved / peak, 4),
+                    "ops_per_launch": ops / n, "bytes_per_launch": by / n,
+                    "hbm_gbs_equivalent": round(by / n / avg_s / 1e9, 1)})
+    else:
+        achieved = by / n / avg_s / 1e9
+        out.update({"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "bytes_per_launch": by / n})
+    return out
 
 
 def cpu_baseline(W) -> dict:
@@ -173,7 +219,18 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--only-plain", action="store_true", help="skip every extra measurement (for profiling)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only copy 256 MiB three times (calibrates the HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        x = torch.ones(32 * 1024 * 1024, dtype=torch.int64, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": x.numel() * 8, "copies": 3}))
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported in this build "
               "(the path shards by ciphertext with replicated keys; see the design notes)", file=sys.stderr)
@@ -186,7 +243,7 @@ def main():
     print("[bench] setup plain LeNet-1 (N=2^14)", file=sys.stderr, flush=True)
     st = setup(P, W, "lenet1", batch=1)
     net, ct, outs = st["net"], st["ct"], st["outs"]
-    net.set_mode(P.EVAL_PLAIN)
+    net.set_mode(P.EVAL_PLAIN | P.EVAL_GRAPH)
     step = lambda: net.eval(ct, outs)
     dt = timed(step, args.steps, args.warmup)
     value = args.steps / dt
@@ -200,7 +257,7 @@ def main():
         "data": "synthetic (seeded: uniform [0,1] 28x28 images, weights N(0,0.1^2), biases N(0,0.01^2))",
         "config": {"workload": "LeNet-1 shape (Table M2): conv 1->4 K5, sq, pool2, conv 4->12 K5, sq, pool2, "
                                "flatten, FC 192->10", "log_n": 14, "primes": "60 + 7x40 (+60 special)",
-                   "scale": "2^40", "images_per_ct": 1, "mode": "plain"},
+                   "scale": "2^40", "images_per_ct": 1, "mode": "plain, replayed as one HIP graph"},
         "max_abs_err_vs_fp64": err,
     }
     if args.only_plain:
@@ -208,14 +265,19 @@ def main():
         return
 
     stats = family_stats(P, step, args.steps)
-    res["roofline"] = roofline_entry(stats)
+    rf = roofline_entry(stats)
+    tr = measured_traffic(rf["kernel"])
+    if tr is not None:
+        rf["traffic"] = round(tr["read_bytes_per_dispatch"] + tr["write_bytes_per_dispatch"])
+        rf["traffic_detail"] = tr
+    res["roofline"] = rf
     res["kernel_families_ms_per_step"] = {k: round(v[1] / args.steps, 4) for k, v in stats.items() if v[0]}
 
     # hoisted evaluation of the same single-image workload
-    net.set_mode(P.EVAL_HOISTED)
+    net.set_mode(P.EVAL_HOISTED | P.EVAL_GRAPH)
     dth = timed(step, args.steps, 1)
     res["plain_hoisted_inferences_per_s"] = round(args.steps / dth, 3)
-    net.set_mode(P.EVAL_PLAIN)
+    net.set_mode(P.EVAL_PLAIN | P.EVAL_GRAPH)
 
     # rotations/s at the same size (one ciphertext, 8 limbs)
     ctx = st["ctx"]
@@ -234,7 +296,7 @@ def main():
         torch.cuda.empty_cache()
         sb = setup(P, W, "lenet1_batched", batch=B)
         nb, ctb, outb = sb["net"], sb["ct"], sb["outs"]
-        nb.set_mode(P.EVAL_HOISTED)
+        nb.set_mode(P.EVAL_HOISTED | P.EVAL_GRAPH)
         stepb = lambda: nb.eval(ctb, outb)
         dtb = timed(stepb, args.batched_steps, 1)
         imgs = args.batched_steps * B * 10 / dtb

@@ -221,10 +221,14 @@ int unihenn_net_rotations(const unihenn_net* net, int32_t* steps);
 int unihenn_net_bind_keys(unihenn_net* net, const int32_t* steps, const unihenn_evk* gks, uint32_t n,
                           const unihenn_evk* rlk);
 
-enum { UNIHENN_EVAL_PLAIN = 0, UNIHENN_EVAL_HOISTED = 1 };
+enum { UNIHENN_EVAL_PLAIN = 0, UNIHENN_EVAL_HOISTED = 1, UNIHENN_EVAL_GRAPH = 2 };
 /* PLAIN: each rotation does its own key switch, layer by layer.  HOISTED:
  * rotations of one ciphertext share the digit decomposition; results are
- * bit-identical. */
+ * bit-identical.  GRAPH may be or-ed into either: unihenn_eval_network then
+ * records its launches once into a HIP graph (per batch size and buffer
+ * set) on a stream of the net's own, and replays it; the caller's stream
+ * is ordered before and after the replay with events.  While kernel timing
+ * (unihenn_stats_enable) is on, launches are issued directly. */
 int unihenn_net_set_mode(unihenn_net* net, int mode);
 
 /* One convolution layer (Algorithm 1) of the net, layer index `layer`:
@@ -273,15 +277,17 @@ int unihenn_decrypt_slots(const unihenn_ctx* ctx, const uint64_t* sk, const unih
 /* Per-kernel-family launch timing with HIP events recorded on the launch
  * stream around each launch (adds a little overhead while on). */
 enum {
-    UNIHENN_KF_NTT_FWD = 0, UNIHENN_KF_NTT_INV, UNIHENN_KF_MODUP, UNIHENN_KF_KS_INNER, UNIHENN_KF_MODDOWN,
-    UNIHENN_KF_RESCALE, UNIHENN_KF_MAC, UNIHENN_KF_AUTO, UNIHENN_KF_TENSOR, UNIHENN_KF_ADD, UNIHENN_KF_ENCODE,
-    UNIHENN_KF_OTHER, UNIHENN_KF_COUNT
+    UNIHENN_KF_NTT_FWD_COL = 0, UNIHENN_KF_NTT_FWD_ROW, UNIHENN_KF_NTT_INV_ROW, UNIHENN_KF_NTT_INV_COL,
+    UNIHENN_KF_MODUP, UNIHENN_KF_KS_INNER, UNIHENN_KF_MODDOWN, UNIHENN_KF_RESCALE, UNIHENN_KF_MAC, UNIHENN_KF_AUTO,
+    UNIHENN_KF_TENSOR, UNIHENN_KF_ADD, UNIHENN_KF_ENCODE, UNIHENN_KF_OTHER, UNIHENN_KF_COUNT
 };
 int unihenn_stats_enable(int on);
 int unihenn_stats_reset(void);
-/* Synchronises the device, then reports launches, total milliseconds and
- * algorithmic bytes (inputs read once + outputs written once) for a family. */
-int unihenn_stats_get(int family, uint64_t* launches, double* total_ms, double* bytes);
+/* Synchronises the device, then reports launches, total milliseconds,
+ * algorithmic bytes (inputs read once + outputs written once) and algorithmic
+ * operations (NTT butterflies; 0 for other families) of a family.  Each NTT
+ * pass is its own family, one kernel dispatch per launch. */
+int unihenn_stats_get(int family, uint64_t* launches, double* total_ms, double* bytes, double* ops);
 const char* unihenn_kernel_family_name(int family);
 
 #ifdef __cplusplus

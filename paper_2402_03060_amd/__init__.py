@@ -17,9 +17,9 @@ LIB_PATH = os.path.join(_HERE, "libunihenn.so")
 
 OK, EINVAL, ELEVEL, ESCALE, ENOKEY, ESLOTS, ENOMEM, EDEVICE = 0, -1, -2, -3, -4, -5, -6, -7
 LAYER_CONV, LAYER_SQUARE, LAYER_AVGPOOL, LAYER_FLATTEN, LAYER_FC = 1, 2, 3, 4, 5
-EVAL_PLAIN, EVAL_HOISTED = 0, 1
-KERNEL_FAMILIES = ["ntt_fwd", "ntt_inv", "modup", "ks_inner", "moddown", "rescale", "mac", "automorphism",
-                   "tensor", "add", "encode", "other"]
+EVAL_PLAIN, EVAL_HOISTED, EVAL_GRAPH = 0, 1, 2
+KERNEL_FAMILIES = ["ntt_fwd_col", "ntt_fwd_row", "ntt_inv_row", "ntt_inv_col", "modup", "ks_inner", "moddown",
+                   "rescale", "mac", "automorphism", "tensor", "add", "encode", "other"]
 
 
 class UnihennError(RuntimeError):
@@ -85,7 +85,7 @@ SIGNATURES = {
     "unihenn_decrypt_slots": (C.c_int, [_vp, _vp, _P(CT), _P(_u32), _u32, _P(_d), _vp]),
     "unihenn_stats_enable": (C.c_int, [C.c_int]),
     "unihenn_stats_reset": (C.c_int, []),
-    "unihenn_stats_get": (C.c_int, [C.c_int, _P(_u64), _P(_d), _P(_d)]),
+    "unihenn_stats_get": (C.c_int, [C.c_int, _P(_u64), _P(_d), _P(_d), _P(_d)]),
     "unihenn_kernel_family_name": (C.c_char_p, [C.c_int]),
 }
 
@@ -316,14 +316,15 @@ def stats_reset():
 
 
 def stats() -> dict:
-    """{family: (launches, total_ms, algorithmic_bytes)}"""
+    """{family: (launches, total_ms, algorithmic_bytes, algorithmic_ops)}"""
     out = {}
     for i, name in enumerate(KERNEL_FAMILIES):
         n = C.c_uint64()
         ms = C.c_double()
         by = C.c_double()
-        _check(lib().unihenn_stats_get(i, C.byref(n), C.byref(ms), C.byref(by)))
-        out[name] = (int(n.value), float(ms.value), float(by.value))
+        op = C.c_double()
+        _check(lib().unihenn_stats_get(i, C.byref(n), C.byref(ms), C.byref(by), C.byref(op)))
+        out[name] = (int(n.value), float(ms.value), float(by.value), float(op.value))
     return out
 
 

@@ -317,7 +317,7 @@ extern "C" int unihenn_ctx_primes(const unihenn_ctx* c, uint64_t* out)
 namespace {
 struct Pending {
     int fam;
-    double bytes;
+    double bytes, ops;
     hipEvent_t a, b;
 };
 std::mutex g_stats_mu;
@@ -326,11 +326,13 @@ std::vector<Pending> g_pending;
 uint64_t g_launches[KF_COUNT];
 double g_ms[KF_COUNT];
 double g_bytes[KF_COUNT];
-const char* g_names[KF_COUNT] = {"ntt_fwd", "ntt_inv", "modup", "ks_inner", "moddown", "rescale",
-                                 "mac", "automorphism", "tensor", "add", "encode", "other"};
+double g_ops[KF_COUNT];
+const char* g_names[KF_COUNT] = {"ntt_fwd_col", "ntt_fwd_row", "ntt_inv_row", "ntt_inv_col", "modup", "ks_inner",
+                                 "moddown", "rescale", "mac", "automorphism", "tensor", "add", "encode", "other"};
 }  // namespace
 
-LaunchTimer::LaunchTimer(KernelFamily f, double b, hipStream_t s) : fam(f), bytes(b), stream(s), on(false)
+LaunchTimer::LaunchTimer(KernelFamily f, double b, hipStream_t s, double o)
+    : fam(f), bytes(b), ops(o), stream(s), on(false)
 {
     if (!g_stats_on) return;
     on = true;
@@ -344,7 +346,7 @@ LaunchTimer::~LaunchTimer()
     if (!on) return;
     hipEventRecord(ev1, stream);
     std::lock_guard<std::mutex> g(g_stats_mu);
-    g_pending.push_back({(int)fam, bytes, ev0, ev1});
+    g_pending.push_back({(int)fam, bytes, ops, ev0, ev1});
     if (g_pending.size() > 8192) {
         // bound the number of live events
         for (auto& p : g_pending) {
@@ -354,6 +356,7 @@ LaunchTimer::~LaunchTimer()
             g_launches[p.fam]++;
             g_ms[p.fam] += ms;
             g_bytes[p.fam] += p.bytes;
+            g_ops[p.fam] += p.ops;
             hipEventDestroy(p.a);
             hipEventDestroy(p.b);
         }
@@ -371,11 +374,14 @@ void stats_collect()
         g_launches[p.fam]++;
         g_ms[p.fam] += ms;
         g_bytes[p.fam] += p.bytes;
+        g_ops[p.fam] += p.ops;
         hipEventDestroy(p.a);
         hipEventDestroy(p.b);
     }
     g_pending.clear();
 }
+
+bool stats_enabled() { return g_stats_on; }
 
 extern "C" int unihenn_stats_enable(int on)
 {
@@ -387,17 +393,18 @@ extern "C" int unihenn_stats_enable(int on)
 extern "C" int unihenn_stats_reset(void)
 {
     stats_collect();
-    for (int i = 0; i < KF_COUNT; ++i) { g_launches[i] = 0; g_ms[i] = 0; g_bytes[i] = 0; }
+    for (int i = 0; i < KF_COUNT; ++i) { g_launches[i] = 0; g_ms[i] = 0; g_bytes[i] = 0; g_ops[i] = 0; }
     return UNIHENN_OK;
 }
 
-extern "C" int unihenn_stats_get(int family, uint64_t* launches, double* total_ms, double* bytes)
+extern "C" int unihenn_stats_get(int family, uint64_t* launches, double* total_ms, double* bytes, double* ops)
 {
     if (family < 0 || family >= KF_COUNT) return uh_fail(UNIHENN_EINVAL, "bad kernel family");
     stats_collect();
     if (launches) *launches = g_launches[family];
     if (total_ms) *total_ms = g_ms[family];
     if (bytes) *bytes = g_bytes[family];
+    if (ops) *ops = g_ops[family];
     return UNIHENN_OK;
 }
 

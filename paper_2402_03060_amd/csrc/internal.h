@@ -91,16 +91,21 @@ void launch_ntt_inv(const unihenn_ctx* c, u64* data, int n_rows, const RowMap& m
 
 // kernel timing hooks (per kernel family), see unihenn_stats_*
 enum KernelFamily {
-    KF_NTT_FWD = 0, KF_NTT_INV, KF_MODUP, KF_KS_INNER, KF_MODDOWN, KF_RESCALE, KF_MAC, KF_AUTO,
-    KF_TENSOR, KF_ADD, KF_ENCODE, KF_OTHER, KF_COUNT
+    KF_NTT_FWD_COL = 0, KF_NTT_FWD_ROW, KF_NTT_INV_ROW, KF_NTT_INV_COL, KF_MODUP, KF_KS_INNER, KF_MODDOWN,
+    KF_RESCALE, KF_MAC, KF_AUTO, KF_TENSOR, KF_ADD, KF_ENCODE, KF_OTHER, KF_COUNT
 };
+// Times one launch (or a group of launches) on its stream with HIP events when
+// timing is on; `bytes` is the algorithmic traffic, `ops` the algorithmic
+// operation count (NTT butterflies) of what it brackets.
 struct LaunchTimer {
-    LaunchTimer(KernelFamily f, double bytes, hipStream_t s);
+    LaunchTimer(KernelFamily f, double bytes, hipStream_t s, double ops = 0.0);
     ~LaunchTimer();
     KernelFamily fam;
     double bytes;
+    double ops;
     hipStream_t stream;
     hipEvent_t ev0, ev1;
     bool on;
 };
 void stats_collect();
+bool stats_enabled();

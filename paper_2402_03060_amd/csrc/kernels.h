@@ -76,3 +76,15 @@ void group_switch(const unihenn_ctx* c, const GroupArgs& ga, int B, int nl, bool
                   u64* U, u64* Up, u64* R, hipStream_t s);
 // aux[e] = tau_{g_e}(src_e), both polynomials
 void group_auto_both(const unihenn_ctx* c, const GroupArgs& ga, int B, int nl, u64* aux, hipStream_t s);
+
+// ---- multiply-accumulate into several outputs at once (convolution) ----
+#define UH_MACM_MAX_OUT 16
+struct MacMulti {
+    u64* acc[UH_MACM_MAX_OUT];          // outputs [B][2][nl]
+    const u64* ct[UH_MAC_MAX_TERMS];    // terms [B][2][nl]
+    const u64* pt_base;                 // plaintext (o, t) at pt_base + ((o * o_stride + t_off + t) * nl) * N
+    int o_stride, t_off;
+};
+// acc[o] (+)= sum_t pt(o, t) (*) ct[t] for o < n_out, t < n_terms
+void launch_mac_multi(const unihenn_ctx* c, const MacMulti& m, int n_out, int n_terms, int nl, int batch,
+                      int accumulate, hipStream_t s);

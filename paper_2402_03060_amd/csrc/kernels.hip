@@ -505,3 +505,67 @@ void group_auto_both(const unihenn_ctx* c, const GroupArgs& ga, int B, int nl, u
     dim3 g3((c->n + EW_THREADS - 1) / EW_THREADS, B * 2 * nl, ga.E);
     k_group_auto<<<g3, EW_THREADS, 0, s>>>(aux, ga, nl, B, c->log_n, 0);
 }
+
+// ------------------------------------------------------------------ multi-output MAC
+namespace {
+template <int BCH>
+__global__ void __launch_bounds__(EW_THREADS) k_mac_multi(MacMulti m, int n_out, int n_terms, DevCtx ctx, int nl,
+                                                          int batch, int accumulate)
+{
+    const int n = ctx.n;
+    const int k = blockIdx.x * EW_THREADS + threadIdx.x;
+    if (k >= n) return;
+    const int i = blockIdx.y;
+    const int b0 = blockIdx.z * BCH;
+    const Modulus M = ctx.mod[i];
+    u64 a[UH_MACM_MAX_OUT][2 * BCH];
+#pragma unroll
+    for (int o = 0; o < UH_MACM_MAX_OUT; ++o)
+#pragma unroll
+        for (int u = 0; u < 2 * BCH; ++u) {
+            const int b = b0 + u / 2, c = u & 1;
+            a[o][u] = (accumulate && o < n_out && b < batch) ? m.acc[o][(((size_t)b * 2 + c) * nl + i) * n + k] : 0;
+        }
+    const size_t row = (size_t)nl * n;
+    for (int t = 0; t < n_terms; ++t) {
+        u64 v[2 * BCH];
+#pragma unroll
+        for (int u = 0; u < 2 * BCH; ++u) {
+            const int b = b0 + u / 2, c = u & 1;
+            v[u] = b < batch ? m.ct[t][(((size_t)b * 2 + c) * nl + i) * n + k] : 0;
+        }
+        const u64* p0 = m.pt_base + (size_t)(m.t_off + t) * row + (size_t)i * n + k;
+#pragma unroll
+        for (int o = 0; o < UH_MACM_MAX_OUT; ++o) {
+            if (o < n_out) {
+                const u64 p = p0[(size_t)o * m.o_stride * row];
+#pragma unroll
+                for (int u = 0; u < 2 * BCH; ++u) a[o][u] = add_mod(a[o][u], mont_mul(p, v[u], M.q, M.qinv_neg), M.q);
+            }
+        }
+    }
+#pragma unroll
+    for (int o = 0; o < UH_MACM_MAX_OUT; ++o)
+#pragma unroll
+        for (int u = 0; u < 2 * BCH; ++u) {
+            const int b = b0 + u / 2, c = u & 1;
+            if (o < n_out && b < batch) m.acc[o][(((size_t)b * 2 + c) * nl + i) * n + k] = a[o][u];
+        }
+}
+}  // namespace
+
+void launch_mac_multi(const unihenn_ctx* c, const MacMulti& m, int n_out, int n_terms, int nl, int batch,
+                      int accumulate, hipStream_t s)
+{
+    // algorithmic bytes: each term ciphertext once, each plaintext once, outputs written (read when accumulating)
+    double rows = (double)n_terms * batch * 2 * nl + (double)n_out * n_terms * nl +
+                  (1.0 + accumulate) * n_out * batch * 2 * nl;
+    LaunchTimer tm(KF_MAC, 8.0 * c->n * rows, s);
+    if (batch >= 2) {
+        dim3 g3((c->n + EW_THREADS - 1) / EW_THREADS, nl, (batch + 1) / 2);
+        k_mac_multi<2><<<g3, EW_THREADS, 0, s>>>(m, n_out, n_terms, c->dev, nl, batch, accumulate);
+    } else {
+        dim3 g3((c->n + EW_THREADS - 1) / EW_THREADS, nl, batch);
+        k_mac_multi<1><<<g3, EW_THREADS, 0, s>>>(m, n_out, n_terms, c->dev, nl, batch, accumulate);
+    }
+}

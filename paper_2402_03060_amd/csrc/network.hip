@@ -27,7 +27,7 @@ int encode_scaled_batch(const unihenn_ctx* c, const double* z, int n_slots, cons
 
 namespace {
 
-enum StepKind { ST_DROP, ST_ROT, ST_MAC, ST_RESCALE, ST_ADD, ST_ADD_PLAIN, ST_SQUARE };
+enum StepKind { ST_DROP, ST_ROT, ST_MAC, ST_MACM, ST_RESCALE, ST_ADD, ST_ADD_PLAIN, ST_SQUARE };
 
 struct VReg {
     int nl;
@@ -47,6 +47,9 @@ struct Step {
     bool acc = false;
     std::vector<Term> terms;
     size_t pt = 0;
+    // ST_MACM: outs[o] (+)= sum_t pt(o, t) (*) srcs[t], pt(o, t) at pt + (o * pt_ostride + pt_toff + t) * nl * N
+    std::vector<int> outs, srcs;
+    int pt_ostride = 0, pt_toff = 0;
 };
 
 struct PtRequest {
@@ -109,6 +112,17 @@ struct unihenn_net {
     std::map<int, const u64*> keys;
     const u64* rlk = nullptr;
     int mode = UNIHENN_EVAL_PLAIN;
+    // captured evaluation (UNIHENN_EVAL_GRAPH)
+    hipStream_t gstream = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    struct {
+        int batch = 0, in_limbs = 0, mode = -1;
+        const u64* in = nullptr;
+        std::vector<u64*> outs;
+        size_t key_version = 0;
+    } gkey;
+    size_t key_version = 0;
 };
 
 namespace {
@@ -296,19 +310,20 @@ struct Planner {
             for (size_t t = 0; t < w.size(); ++t) pt[o].push_back(off + t * (size_t)nl * c->n);
         }
         const int kk = g.kh * g.kw;
+        // one step per input channel: every output accumulates that channel's K^2 products
+        for (int o = 0; o < co; ++o) acc[o] = newreg(nl, s_in * delta);
         auto emit_macs = [&](int i_begin, int i_end, const std::vector<int>& rot_regs, bool accumulate) {
-            for (int o = 0; o < co; ++o) {
-                std::vector<Term> terms;
-                for (int i = i_begin; i < i_end; ++i)
-                    for (int t = 0; t < kk; ++t) terms.push_back({rot_regs[(i - i_begin) * kk + t], pt[o][(size_t)i * kk + t]});
-                if (acc[o] < 0) acc[o] = newreg(nl, s_in * delta);
-                Step s;
-                s.kind = ST_MAC;
-                s.dst = acc[o];
-                s.terms = terms;
-                s.acc = accumulate;
-                net->steps.push_back(s);
-            }
+            Step s;
+            s.kind = ST_MACM;
+            s.outs = acc;
+            s.srcs = rot_regs;
+            s.pt = pt[0][0];
+            s.pt_ostride = ci * kk;
+            s.pt_toff = i_begin * kk;
+            s.acc = accumulate;
+            s.dst = acc[0];
+            (void)i_end;
+            net->steps.push_back(s);
         };
         for (int i = 0; i < ci; ++i)
             if (net->regs[L.ch_reg[i]].nl != nl || net->regs[L.ch_reg[i]].scale != s_in)
@@ -623,9 +638,14 @@ void allocate(unihenn_net* net, std::vector<int>& phys_nl)
         use(st.a, s);
         use(st.b, s);
         for (const Term& t : st.terms) use(t.src, s);
+        for (int r : st.srcs) use(r, s);
         if (st.acc) use(st.dst, s);
         if (st.dst >= 0 && def[st.dst] < 0) def[st.dst] = s;
         use(st.dst, s);
+        for (int r : st.outs) {
+            if (def[r] < 0) def[r] = s;
+            use(r, s);
+        }
     }
     for (int r : net->out_regs) last[r] = (int)net->steps.size();
     std::map<int, std::vector<int>> free_by_nl;
@@ -633,8 +653,10 @@ void allocate(unihenn_net* net, std::vector<int>& phys_nl)
     for (int r = 0; r < nr; ++r)
         if (last[r] >= 0 && last[r] < (int)net->steps.size()) dying[last[r]].push_back(r);
     for (int s = 0; s < (int)net->steps.size(); ++s) {
-        int d = net->steps[s].dst;
-        if (d >= 0 && def[d] == s && net->regs[d].phys < 0) {
+        std::vector<int> defs = net->steps[s].outs;
+        if (net->steps[s].dst >= 0) defs.push_back(net->steps[s].dst);
+        for (int d : defs) {
+            if (def[d] != s || net->regs[d].phys >= 0) continue;
             auto& fl = free_by_nl[net->regs[d].nl];
             if (!fl.empty()) {
                 net->regs[d].phys = fl.back();
@@ -655,6 +677,10 @@ void allocate(unihenn_net* net, std::vector<int>& phys_nl)
 extern "C" int unihenn_net_destroy(unihenn_net* net)
 {
     if (!net) return UNIHENN_OK;
+    if (net->gexec) hipGraphExecDestroy(net->gexec);
+    if (net->ev_in) hipEventDestroy(net->ev_in);
+    if (net->ev_out) hipEventDestroy(net->ev_out);
+    if (net->gstream) hipStreamDestroy(net->gstream);
     hipFree(net->pt_arena);
     hipFree(net->reg_arena);
     hipFree(net->ws);
@@ -847,12 +873,13 @@ extern "C" int unihenn_net_bind_keys(unihenn_net* net, const int32_t* steps, con
         return uh_fail(UNIHENN_ENOKEY, "no relinearisation key");
     net->keys = k;
     net->rlk = rlk ? rlk->data : nullptr;
+    net->key_version++;
     return UNIHENN_OK;
 }
 
 extern "C" int unihenn_net_set_mode(unihenn_net* net, int mode)
 {
-    if (!net || (mode != UNIHENN_EVAL_PLAIN && mode != UNIHENN_EVAL_HOISTED))
+    if (!net || mode < 0 || mode > (UNIHENN_EVAL_HOISTED | UNIHENN_EVAL_GRAPH))
         return uh_fail(UNIHENN_EINVAL, "bad mode");
     net->mode = mode;
     return UNIHENN_OK;
@@ -917,7 +944,7 @@ struct Exec {
         const size_t rn = (size_t)c->n;
         GroupWs w = carve();
         const int Emax = net->group_max;
-        if (net->mode == UNIHENN_EVAL_HOISTED) {
+        if (net->mode & UNIHENN_EVAL_HOISTED) {
             size_t i = 0;
             while (i < run.size()) {
                 const int src = net->steps[run[i]].a;
@@ -999,6 +1026,24 @@ struct Exec {
                 }
                 break;
             }
+            case ST_MACM: {
+                const int O = (int)st.outs.size(), T = (int)st.srcs.size();
+                for (int o0 = 0; o0 < O; o0 += UH_MACM_MAX_OUT) {
+                    const int no = std::min(UH_MACM_MAX_OUT, O - o0);
+                    for (int t0 = 0; t0 < T; t0 += UH_MAC_MAX_TERMS) {
+                        const int nt = std::min(UH_MAC_MAX_TERMS, T - t0);
+                        MacMulti m;
+                        memset(&m, 0, sizeof(m));
+                        for (int o = 0; o < no; ++o) m.acc[o] = reg(st.outs[o0 + o]);
+                        for (int t = 0; t < nt; ++t) m.ct[t] = reg(st.srcs[t0 + t]);
+                        m.pt_base = net->pt_arena + st.pt + (size_t)o0 * st.pt_ostride * nl * c->n;
+                        m.o_stride = st.pt_ostride;
+                        m.t_off = st.pt_toff + t0;
+                        launch_mac_multi(c, m, no, nt, nl, B, (st.acc || t0 > 0) ? 1 : 0, s);
+                    }
+                }
+                break;
+            }
             case ST_RESCALE: {
                 const int nla = net->regs[st.a].nl;
                 KsWs wa = ks_ws_carve(net->ws, nla, B, c->n);
@@ -1058,10 +1103,59 @@ extern "C" int unihenn_eval_network(const unihenn_ctx* c, unihenn_net* net, cons
     if (rc) return rc;
     for (size_t i = 0; i < net->out_regs.size(); ++i)
         if (!out[i].data) return uh_fail(UNIHENN_EINVAL, "null output buffer");
-    Exec ex{net, c, (int)in->batch, (hipStream_t)stream, {}, -1, in->data, (int)in->n_limbs};
-    for (size_t i = 0; i < net->out_regs.size(); ++i) ex.bound[net->out_regs[i]] = out[i].data;
-    rc = ex.run(0, net->steps.size());
-    if (rc) return rc;
+    const bool graph = (net->mode & UNIHENN_EVAL_GRAPH) && !stats_enabled();
+    hipStream_t cs = (hipStream_t)stream;
+    if (!graph) {
+        Exec ex{net, c, (int)in->batch, cs, {}, -1, in->data, (int)in->n_limbs};
+        for (size_t i = 0; i < net->out_regs.size(); ++i) ex.bound[net->out_regs[i]] = out[i].data;
+        rc = ex.run(0, net->steps.size());
+        if (rc) return rc;
+    } else {
+        if (!net->gstream) {
+            UH_CHECK_HIP(hipStreamCreateWithFlags(&net->gstream, hipStreamNonBlocking));
+            UH_CHECK_HIP(hipEventCreateWithFlags(&net->ev_in, hipEventDisableTiming));
+            UH_CHECK_HIP(hipEventCreateWithFlags(&net->ev_out, hipEventDisableTiming));
+        }
+        std::vector<u64*> outs;
+        for (size_t i = 0; i < net->out_regs.size(); ++i) outs.push_back(out[i].data);
+        auto& k = net->gkey;
+        const bool hit = net->gexec && k.batch == (int)in->batch && k.in == in->data && k.in_limbs == (int)in->n_limbs &&
+                         k.outs == outs && k.mode == net->mode && k.key_version == net->key_version;
+        if (!hit) {
+            if (net->gexec) {
+                hipGraphExecDestroy(net->gexec);
+                net->gexec = nullptr;
+            }
+            Exec ex{net, c, (int)in->batch, net->gstream, {}, -1, in->data, (int)in->n_limbs};
+            for (size_t i = 0; i < net->out_regs.size(); ++i) ex.bound[net->out_regs[i]] = out[i].data;
+            UH_CHECK_HIP(hipStreamBeginCapture(net->gstream, hipStreamCaptureModeThreadLocal));
+            int rc2 = ex.run(0, net->steps.size());
+            hipGraph_t graph_obj = nullptr;
+            hipError_t e = hipStreamEndCapture(net->gstream, &graph_obj);
+            if (rc2) {
+                if (graph_obj) hipGraphDestroy(graph_obj);
+                return rc2;
+            }
+            if (e != hipSuccess) return uh_fail(UNIHENN_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+            e = hipGraphInstantiate(&net->gexec, graph_obj, nullptr, nullptr, 0);
+            hipGraphDestroy(graph_obj);
+            if (e != hipSuccess) {
+                net->gexec = nullptr;
+                return uh_fail(UNIHENN_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+            }
+            k.batch = (int)in->batch;
+            k.in = in->data;
+            k.in_limbs = (int)in->n_limbs;
+            k.outs = outs;
+            k.mode = net->mode;
+            k.key_version = net->key_version;
+        }
+        UH_CHECK_HIP(hipEventRecord(net->ev_in, cs));
+        UH_CHECK_HIP(hipStreamWaitEvent(net->gstream, net->ev_in, 0));
+        UH_CHECK_HIP(hipGraphLaunch(net->gexec, net->gstream));
+        UH_CHECK_HIP(hipEventRecord(net->ev_out, net->gstream));
+        UH_CHECK_HIP(hipStreamWaitEvent(cs, net->ev_out, 0));
+    }
     for (size_t i = 0; i < net->out_regs.size(); ++i) {
         out[i].n_limbs = 1;
         out[i].batch = in->batch;

@@ -322,16 +322,22 @@ void launch_ntt_fwd(const unihenn_ctx* c, u64* data, int n_rows, const RowMap& m
     if (n_rows <= 0) return;
     int l1, l2;
     split(c->log_n, &l1, &l2);
-    LaunchTimer tm(KF_NTT_FWD, 16.0 * c->n * n_rows, st);
-    if (!launch_pass_r8(data, c->dev, map, n_rows, c->log_n, l1, 0, true, false, false, st)) {
-        int cols1 = tile_cols(l1, c->log_n);
-        dim3 g1((1 << (c->log_n - l1)) / cols1, n_rows);
-        k_ntt_fwd<true, false><<<g1, NTT_THREADS, 0, st>>>(data, c->dev, map, l1, cols1, 0);
+    const double bytes = 16.0 * c->n * n_rows, half = 0.5 * c->n * n_rows;
+    {
+        LaunchTimer tm(KF_NTT_FWD_COL, bytes, st, half * l1);
+        if (!launch_pass_r8(data, c->dev, map, n_rows, c->log_n, l1, 0, true, false, false, st)) {
+            int cols1 = tile_cols(l1, c->log_n);
+            dim3 g1((1 << (c->log_n - l1)) / cols1, n_rows);
+            k_ntt_fwd<true, false><<<g1, NTT_THREADS, 0, st>>>(data, c->dev, map, l1, cols1, 0);
+        }
     }
-    if (!launch_pass_r8(data, c->dev, map, n_rows, c->log_n, l2, l1, false, false, true, st)) {
-        int cols2 = tile_cols(l2, c->log_n);
-        dim3 g2((1 << (c->log_n - l2)) / cols2, n_rows);
-        k_ntt_fwd<false, true><<<g2, NTT_THREADS, 0, st>>>(data, c->dev, map, l2, cols2, l1);
+    {
+        LaunchTimer tm(KF_NTT_FWD_ROW, bytes, st, half * l2);
+        if (!launch_pass_r8(data, c->dev, map, n_rows, c->log_n, l2, l1, false, false, true, st)) {
+            int cols2 = tile_cols(l2, c->log_n);
+            dim3 g2((1 << (c->log_n - l2)) / cols2, n_rows);
+            k_ntt_fwd<false, true><<<g2, NTT_THREADS, 0, st>>>(data, c->dev, map, l2, cols2, l1);
+        }
     }
 }
 
@@ -340,15 +346,21 @@ void launch_ntt_inv(const unihenn_ctx* c, u64* data, int n_rows, const RowMap& m
     if (n_rows <= 0) return;
     int l1, l2;
     split(c->log_n, &l1, &l2);
-    LaunchTimer tm(KF_NTT_INV, 16.0 * c->n * n_rows, st);
-    if (!launch_pass_r8(data, c->dev, map, n_rows, c->log_n, l2, l1, false, true, false, st)) {
-        int cols2 = tile_cols(l2, c->log_n);
-        dim3 g2((1 << (c->log_n - l2)) / cols2, n_rows);
-        k_ntt_inv<false, false><<<g2, NTT_THREADS, 0, st>>>(data, c->dev, map, l2, cols2, l1);
+    const double bytes = 16.0 * c->n * n_rows, half = 0.5 * c->n * n_rows;
+    {
+        LaunchTimer tm(KF_NTT_INV_ROW, bytes, st, half * l2);
+        if (!launch_pass_r8(data, c->dev, map, n_rows, c->log_n, l2, l1, false, true, false, st)) {
+            int cols2 = tile_cols(l2, c->log_n);
+            dim3 g2((1 << (c->log_n - l2)) / cols2, n_rows);
+            k_ntt_inv<false, false><<<g2, NTT_THREADS, 0, st>>>(data, c->dev, map, l2, cols2, l1);
+        }
     }
-    if (!launch_pass_r8(data, c->dev, map, n_rows, c->log_n, l1, 0, true, true, true, st)) {
-        int cols1 = tile_cols(l1, c->log_n);
-        dim3 g1((1 << (c->log_n - l1)) / cols1, n_rows);
-        k_ntt_inv<true, true><<<g1, NTT_THREADS, 0, st>>>(data, c->dev, map, l1, cols1, 0);
+    {
+        LaunchTimer tm(KF_NTT_INV_COL, bytes, st, half * l1);
+        if (!launch_pass_r8(data, c->dev, map, n_rows, c->log_n, l1, 0, true, true, true, st)) {
+            int cols1 = tile_cols(l1, c->log_n);
+            dim3 g1((1 << (c->log_n - l1)) / cols1, n_rows);
+            k_ntt_inv<true, true><<<g1, NTT_THREADS, 0, st>>>(data, c->dev, map, l1, cols1, 0);
+        }
     }
 }

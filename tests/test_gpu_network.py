@@ -172,3 +172,36 @@ def test_product_client_end_to_end(name):
                 sel = ids == k
                 vals[sel] = P.decrypt_slots(ctx, sk, outs[int(k)], slots[sel])[b]
             assert np.abs(vals - ref[b * S + s]).max() < 1e-3
+
+
+def test_graph_replay_matches_eager():
+    """The captured evaluation, replayed several times with eager evaluations
+    and synchronisations in between, equals the eager result every time."""
+    import torch
+    import paper_2402_03060_amd as P
+    cfg = W.config("lenet1")
+    cfg["log_n"] = 11
+    sess = OracleSession(cfg)
+    onet = build_net(cfg, sess.ck.slots)
+    xs = W.gen_inputs(cfg["input"], 2)
+    cts = [run_encrypted(sess, onet, xs[b:b + 1], enc_seed=200 + b)[0] for b in range(2)]
+    ctx = _ctx(P, cfg)
+    net = _gpu_net(P, ctx, cfg, sess, onet, batch=2)
+    gin = ctx.import_ct(np.stack([c.data for c in cts]), cts[0].scale)
+    other = ctx.import_ct(np.stack([cts[1].data, cts[0].data]), cts[0].scale)
+    for mode in (P.EVAL_PLAIN, P.EVAL_HOISTED):
+        net.set_mode(mode)
+        eager = [ctx.export_ct(o) for o in net.eval(gin)]
+        net.set_mode(mode | P.EVAL_GRAPH)
+        outs = net.alloc_outputs(2)
+        for rep in range(3):
+            net.eval(gin, outs)
+            torch.cuda.synchronize()
+            got = [ctx.export_ct(o) for o in outs]
+            for a, b in zip(got, eager):
+                assert np.array_equal(a, b), (mode, rep)
+            # eager work between replays (different buffers -> direct launches)
+            net.set_mode(mode)
+            swapped = [ctx.export_ct(o) for o in net.eval(other)]
+            assert np.array_equal(swapped[0][0], eager[0][1])
+            net.set_mode(mode | P.EVAL_GRAPH)

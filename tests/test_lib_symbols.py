@@ -48,8 +48,8 @@ def test_errors_reported_without_device_work():
     bits = (ctypes.c_uint32 * 2)(60, 40)
     assert L.unihenn_ctx_create(3, bits, 2, 60, 2.0 ** 40, ctypes.byref(h)) == P.EINVAL
     assert b"log_n" in L.unihenn_last_error()
-    assert L.unihenn_stats_get(99, None, None, None) == P.EINVAL
-    assert L.unihenn_kernel_family_name(0) == b"ntt_fwd"
+    assert L.unihenn_stats_get(99, None, None, None, None) == P.EINVAL
+    assert L.unihenn_kernel_family_name(0) == b"ntt_fwd_col"
 
 
 def test_double_double_cosine_table():
