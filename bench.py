@@ -219,9 +219,34 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--only-plain", action="store_true", help="skip every extra measurement (for profiling)")
+    ap.add_argument("--ntt-probe", type=int, default=0, metavar="ROWS",
+                    help="only time forward+inverse NTTs of ROWS limb rows at N=2^14 (kernel throughput)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 256 MiB three times (calibrates the HBM byte counters)")
     args = ap.parse_args()
+    if args.ntt_probe:
+        import torch
+        import paper_2402_03060_amd as P
+        ctx = P.Context(14, [60] + [40] * 7, 60, 2.0 ** 40)
+        rows = args.ntt_probe - args.ntt_probe % 8
+        t = torch.randint(0, 2 ** 39, (rows // 8, 8, ctx.n), dtype=torch.int64, device="cuda")
+        ref = t.clone()
+        for _ in range(2):
+            ctx.to_ntt(t, 8, rows // 8)
+            ctx.from_ntt(t, 8, rows // 8)
+        torch.cuda.synchronize()
+        reps = args.steps
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            ctx.to_ntt(t, 8, rows // 8)
+            ctx.from_ntt(t, 8, rows // 8)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        bfly = 2 * reps * rows * (ctx.n // 2) * 14
+        print(json.dumps({"ntt_probe_rows": rows, "roundtrips": reps, "seconds": dt,
+                          "butterflies_per_s": bfly / dt, "frac_of_alu_peak": bfly / dt / BUTTERFLY_PEAK,
+                          "roundtrip_exact": bool(torch.equal(t, ref))}))
+        return
     if args.copy_probe:
         import torch
         x = torch.ones(32 * 1024 * 1024, dtype=torch.int64, device="cuda")

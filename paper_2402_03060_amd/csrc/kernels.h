@@ -88,3 +88,31 @@ struct MacMulti {
 // acc[o] (+)= sum_t pt(o, t) (*) ct[t] for o < n_out, t < n_terms
 void launch_mac_multi(const unihenn_ctx* c, const MacMulti& m, int n_out, int n_terms, int nl, int batch,
                       int accumulate, hipStream_t s);
+
+// ---- grouped elementwise steps (independent steps of one kind, one launch) ----
+#define UH_EW_GROUP_MAX 32
+struct EwGroup {
+    int E;
+    u64* out[UH_EW_GROUP_MAX];
+    const u64* a[UH_EW_GROUP_MAX];
+    const u64* b[UH_EW_GROUP_MAX];   // second operand (add) or plaintext (add_plain)
+};
+void launch_group_add(const unihenn_ctx* c, const EwGroup& g, int batch, int nl, bool plain, hipStream_t s);
+// rescale of E ciphertext batches [B][2][nl] -> [B][2][nl-1]; ws holds
+// E * B * 2 * nl rows
+void group_rescale(const unihenn_ctx* c, int E, const u64* const* in, u64* const* out, int batch, int nl, u64* ws,
+                   hipStream_t s);
+// square + relinearise + rescale of E ciphertext batches at nl limbs
+// ([B][2][nl] -> [B][2][nl-1]); ws holds group_square_ws_rows rows
+size_t group_square_ws_rows(int E, int nl, int batch);
+void group_square(const unihenn_ctx* c, int E, const u64* const* in, u64* const* out, const u64* rlk, int batch, int nl,
+                  u64* ws, hipStream_t s);
+// E single-output multiply-accumulates with T terms each (E * T <= 64)
+#define UH_MACG_MAX 64
+struct MacGroup {
+    int E, T;
+    u64* acc[UH_EW_GROUP_MAX];
+    const u64* ct[UH_MACG_MAX];
+    const u64* pt[UH_MACG_MAX];
+};
+void launch_mac_group(const unihenn_ctx* c, const MacGroup& m, int nl, int batch, hipStream_t s);

@@ -3,6 +3,7 @@
 // map to consecutive coefficients so each wavefront touches 512 contiguous
 // bytes of a row.
 #include <cstring>
+#include <vector>
 
 #include "kernels.h"
 
@@ -568,4 +569,216 @@ void launch_mac_multi(const unihenn_ctx* c, const MacMulti& m, int n_out, int n_
         dim3 g3((c->n + EW_THREADS - 1) / EW_THREADS, nl, batch);
         k_mac_multi<1><<<g3, EW_THREADS, 0, s>>>(m, n_out, n_terms, c->dev, nl, batch, accumulate);
     }
+}
+
+// ------------------------------------------------------------------ grouped elementwise steps
+namespace {
+__global__ void k_group_add(EwGroup g, DevCtx ctx, int nl, int plain)
+{
+    const int n = ctx.n;
+    const int k = blockIdx.x * EW_THREADS + threadIdx.x;
+    if (k >= n) return;
+    const int r = blockIdx.y;  // (b * 2 + c) * nl + i
+    const int e = blockIdx.z;
+    const int i = r % nl, c = (r / nl) & 1;
+    const u64 q = ctx.mod[i].q;
+    const u64 x = g.a[e][(size_t)r * n + k];
+    u64 v;
+    if (plain) v = c == 0 ? add_mod(x, g.b[e][(size_t)i * n + k], q) : x;
+    else v = add_mod(x, g.b[e][(size_t)r * n + k], q);
+    g.out[e][(size_t)r * n + k] = v;
+}
+
+// last[e][b][c] <- in_e[b][c][nl-1]
+__global__ void k_group_last(u64* __restrict__ last, EwGroup g, int nl, int n)
+{
+    const int k = blockIdx.x * EW_THREADS + threadIdx.x;
+    if (k >= n) return;
+    const int p = blockIdx.y;  // b * 2 + c
+    const int e = blockIdx.z;
+    last[((size_t)e * gridDim.y + p) * n + k] = g.a[e][((size_t)p * nl + nl - 1) * n + k];
+}
+
+// out_e[p][i] = (in_e[p][i] - r[e][p][i]) * inv_i (+ d0 / d1 addends: relinearisation)
+__global__ void k_group_sub_scale2(EwGroup g, const u64* __restrict__ r, int x_limbs, const u64* __restrict__ inv,
+                                   DevCtx ctx, int nl, int polys)
+{
+    const int n = ctx.n;
+    const int k = blockIdx.x * EW_THREADS + threadIdx.x;
+    if (k >= n) return;
+    const int row = blockIdx.y;  // p * nl + i
+    const int e = blockIdx.z;
+    const int i = row % nl, p = row / nl;
+    const u64 q = ctx.mod[i].q;
+    u64 v = sub_mod(g.a[e][((size_t)p * x_limbs + i) * n + k], r[((size_t)e * polys * nl + row) * n + k], q);
+    v = mul_shoup(v, inv[2 * i], inv[2 * i + 1], q);
+    g.out[e][(size_t)row * n + k] = v;
+}
+
+// relinearised product: out[e][b][c][i] = (U - R) P^-1 + d_c[e][b][i]
+__global__ void k_relin_combine(u64* __restrict__ out, const u64* __restrict__ U, const u64* __restrict__ R,
+                                const u64* __restrict__ d0, const u64* __restrict__ d1, const u64* __restrict__ inv,
+                                DevCtx ctx, int nl)
+{
+    const int n = ctx.n;
+    const int k = blockIdx.x * EW_THREADS + threadIdx.x;
+    if (k >= n) return;
+    const size_t row = blockIdx.y;  // ((e * B + b) * 2 + c) * nl + i
+    const int i = (int)(row % nl);
+    const size_t p = row / nl, eb = p >> 1;
+    const int c = (int)(p & 1);
+    const u64 q = ctx.mod[i].q;
+    u64 v = sub_mod(U[row * n + k], R[row * n + k], q);
+    v = mul_shoup(v, inv[2 * i], inv[2 * i + 1], q);
+    const u64* d = c == 0 ? d0 : d1;
+    v = add_mod(v, d[(eb * nl + i) * n + k], q);
+    out[row * n + k] = v;
+}
+
+// tensor of E ciphertext batches: d0/d1/d2 [E][B][nl]
+__global__ void k_group_tensor(u64* __restrict__ d0, u64* __restrict__ d1, u64* __restrict__ d2, EwGroup g, DevCtx ctx,
+                               int nl, int batch)
+{
+    const int n = ctx.n;
+    const int k = blockIdx.x * EW_THREADS + threadIdx.x;
+    if (k >= n) return;
+    const int r = blockIdx.y;  // b * nl + i
+    const int e = blockIdx.z;
+    const int i = r % nl, b = r / nl;
+    const Modulus M = ctx.mod[i];
+    const u64 c0 = g.a[e][(((size_t)b * 2 + 0) * nl + i) * n + k];
+    const u64 c1 = g.a[e][(((size_t)b * 2 + 1) * nl + i) * n + k];
+    const u64 s00 = mont_mul(mont_mul(c0, c0, M.q, M.qinv_neg), M.r2, M.q, M.qinv_neg);
+    const u64 s01 = mont_mul(mont_mul(c0, c1, M.q, M.qinv_neg), M.r2, M.q, M.qinv_neg);
+    const u64 s11 = mont_mul(mont_mul(c1, c1, M.q, M.qinv_neg), M.r2, M.q, M.qinv_neg);
+    const size_t o = ((size_t)e * batch * nl + r) * n + k;
+    d0[o] = s00;
+    d1[o] = add_mod(s01, s01, M.q);
+    d2[o] = s11;
+}
+
+template <int BCH>
+__global__ void __launch_bounds__(EW_THREADS) k_mac_group(MacGroup m, DevCtx ctx, int nl, int batch)
+{
+    const int n = ctx.n;
+    const int k = blockIdx.x * EW_THREADS + threadIdx.x;
+    if (k >= n) return;
+    const int i = blockIdx.y;
+    const int e = blockIdx.z % m.E;
+    const int b0 = (blockIdx.z / m.E) * BCH;
+    const Modulus M = ctx.mod[i];
+    u64 a[2 * BCH];
+#pragma unroll
+    for (int u = 0; u < 2 * BCH; ++u) a[u] = 0;
+    for (int t = 0; t < m.T; ++t) {
+        const u64 p = m.pt[e * m.T + t][(size_t)i * n + k];
+        const u64* ct = m.ct[e * m.T + t];
+#pragma unroll
+        for (int u = 0; u < 2 * BCH; ++u) {
+            const int b = b0 + u / 2, c = u & 1;
+            if (b < batch) a[u] = add_mod(a[u], mont_mul(p, ct[(((size_t)b * 2 + c) * nl + i) * n + k], M.q, M.qinv_neg), M.q);
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < 2 * BCH; ++u) {
+        const int b = b0 + u / 2, c = u & 1;
+        if (b < batch) m.acc[e][(((size_t)b * 2 + c) * nl + i) * n + k] = a[u];
+    }
+}
+}  // namespace
+
+void launch_group_add(const unihenn_ctx* c, const EwGroup& g, int batch, int nl, bool plain, hipStream_t s)
+{
+    LaunchTimer tm(KF_ADD, 8.0 * c->n * g.E * (batch * 2.0 * nl * (plain ? 2.0 : 3.0) + (plain ? nl : 0)), s);
+    dim3 g3((c->n + EW_THREADS - 1) / EW_THREADS, batch * 2 * nl, g.E);
+    k_group_add<<<g3, EW_THREADS, 0, s>>>(g, c->dev, nl, plain ? 1 : 0);
+}
+
+void group_rescale(const unihenn_ctx* c, int E, const u64* const* in, u64* const* out, int B, int nl, u64* ws,
+                   hipStream_t s)
+{
+    const int l = nl - 1;
+    const size_t rn = (size_t)c->n;
+    EwGroup g;
+    memset(&g, 0, sizeof(g));
+    g.E = E;
+    for (int e = 0; e < E; ++e) {
+        g.a[e] = in[e];
+        g.out[e] = out[e];
+    }
+    u64* last = ws;                               // [E][B][2]
+    u64* R = ws + (size_t)E * B * 2 * rn;         // [E][B][2][l]
+    const unsigned gx = (c->n + EW_THREADS - 1) / EW_THREADS;
+    {
+        LaunchTimer tm(KF_OTHER, 16.0 * c->n * E * B * 2, s);
+        k_group_last<<<dim3(gx, B * 2, E), EW_THREADS, 0, s>>>(last, g, nl, c->n);
+    }
+    launch_ntt_inv(c, last, E * B * 2, rowmap_list({l}), s);
+    launch_lift_last(c, R, last, E * B * 2, l, l, KF_RESCALE, s);
+    launch_ntt_fwd(c, R, E * B * 2 * l, rowmap_ct(l), s);
+    const u64* inv = c->d_inv_last + (size_t)l * c->primes.size() * 2;
+    {
+        LaunchTimer tm(KF_RESCALE, 8.0 * c->n * E * B * 2 * l * 3, s);
+        k_group_sub_scale2<<<dim3(gx, B * 2 * l, E), EW_THREADS, 0, s>>>(g, R, nl, inv, c->dev, l, B * 2);
+    }
+}
+
+size_t group_square_ws_rows(int E, int nl, int batch)
+{
+    // d0, d1, d2 [E][B][nl]; dcoef [E][B][nl]; modup [E][B][nl][nl]; U [E][B][2][nl]; Up [E][B][2];
+    // R [E][B][2][nl]; relinearised [E][B][2][nl]; rescale scratch E*B*2*nl
+    return (size_t)E * batch * (3 * nl + nl + (size_t)nl * nl + 2 * nl + 2 + 2 * nl + 2 * nl + 2 * nl);
+}
+
+void group_square(const unihenn_ctx* c, int E, const u64* const* in, u64* const* out, const u64* rlk, int B, int nl,
+                  u64* ws, hipStream_t s)
+{
+    const size_t rn = (size_t)c->n, EB = (size_t)E * B;
+    u64* d0 = ws;
+    u64* d1 = d0 + EB * nl * rn;
+    u64* d2 = d1 + EB * nl * rn;
+    u64* dcoef = d2 + EB * nl * rn;
+    u64* modup = dcoef + EB * nl * rn;
+    u64* U = modup + EB * nl * nl * rn;
+    u64* Up = U + EB * 2 * nl * rn;
+    u64* R = Up + EB * 2 * rn;
+    u64* rel = R + EB * 2 * nl * rn;
+    u64* scratch = rel + EB * 2 * nl * rn;
+    const unsigned gx = (c->n + EW_THREADS - 1) / EW_THREADS;
+    EwGroup g;
+    memset(&g, 0, sizeof(g));
+    g.E = E;
+    for (int e = 0; e < E; ++e) g.a[e] = in[e];
+    {
+        LaunchTimer tm(KF_TENSOR, 8.0 * c->n * EB * nl * 5, s);
+        k_group_tensor<<<dim3(gx, B * nl, E), EW_THREADS, 0, s>>>(d0, d1, d2, g, c->dev, nl, B);
+    }
+    // ModUp of every d2 (E * B ciphertext-polys as one batch), inner product with the relinearisation key
+    launch_gather_rows(c, dcoef, d2, (int)EB * nl, nl, nl, 0, s);
+    launch_ntt_inv(c, dcoef, (int)EB * nl, rowmap_ct(nl), s);
+    launch_modup(c, modup, dcoef, (int)EB, nl, s);
+    launch_ntt_fwd(c, modup, (int)EB * nl * nl, rowmap_modup(nl, c->n_data), s);
+    launch_ks_inner(c, U, Up, d2, nl, modup, rlk, c->n_data, (int)EB, nl, 1, s);
+    launch_ntt_inv(c, Up, (int)EB * 2, rowmap_list({c->n_data}), s);
+    launch_lift_last(c, R, Up, (int)EB * 2, nl, c->n_data, KF_MODDOWN, s);
+    launch_ntt_fwd(c, R, (int)EB * 2 * nl, rowmap_ct(nl), s);
+    {
+        LaunchTimer tm(KF_MODDOWN, 8.0 * c->n * EB * 2 * nl * 3.5, s);
+        k_relin_combine<<<dim3(gx, (unsigned)(EB * 2 * nl)), EW_THREADS, 0, s>>>(rel, U, R, d0, d1, c->d_p_inv, c->dev,
+                                                                                 nl);
+    }
+    std::vector<const u64*> ins(E);
+    for (int e = 0; e < E; ++e) ins[e] = rel + (size_t)e * B * 2 * nl * rn;
+    group_rescale(c, E, ins.data(), out, B, nl, scratch, s);
+}
+
+void launch_mac_group(const unihenn_ctx* c, const MacGroup& m, int nl, int batch, hipStream_t s)
+{
+    double rows = (double)m.E * m.T * (nl + batch * 2.0 * nl) + m.E * batch * 2.0 * nl;
+    LaunchTimer tm(KF_MAC, 8.0 * c->n * rows, s);
+    const unsigned gx = (c->n + EW_THREADS - 1) / EW_THREADS;
+    if (batch >= 4)
+        k_mac_group<4><<<dim3(gx, nl, m.E * ((batch + 3) / 4)), EW_THREADS, 0, s>>>(m, c->dev, nl, batch);
+    else
+        k_mac_group<1><<<dim3(gx, nl, m.E * batch), EW_THREADS, 0, s>>>(m, c->dev, nl, batch);
 }

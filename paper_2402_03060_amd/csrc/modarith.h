@@ -27,10 +27,16 @@ struct Modulus {
     u64 pad;
 };
 
+// high 64 bits of a 64 x 64 product: four 32 x 32 + 64 multiply-adds
+// (v_mad_u64_u32) whose addends absorb the carries, plus one 64-bit add
 __host__ __device__ __forceinline__ u64 umulhi64(u64 a, u64 b)
 {
 #ifdef __HIP_DEVICE_COMPILE__
-    return __umul64hi(a, b);
+    const u32 a0 = (u32)a, a1 = (u32)(a >> 32), b0 = (u32)b, b1 = (u32)(b >> 32);
+    const u64 p00 = (u64)a0 * b0;
+    const u64 t = (u64)a0 * b1 + (p00 >> 32);
+    const u64 v = (u64)a1 * b0 + (u32)t;
+    return (u64)a1 * b1 + ((t >> 32) + (v >> 32));
 #else
     return (u64)(((unsigned __int128)a * b) >> 64);
 #endif

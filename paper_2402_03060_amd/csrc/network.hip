@@ -15,6 +15,7 @@
 // source become consecutive, so they can share one digit decomposition.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <string>
@@ -649,9 +650,16 @@ void allocate(unihenn_net* net, std::vector<int>& phys_nl)
     }
     for (int r : net->out_regs) last[r] = (int)net->steps.size();
     std::map<int, std::vector<int>> free_by_nl;
+    // The executor issues runs of consecutive steps of one kind as a single
+    // launch set, where every element reads and writes concurrently; a buffer
+    // read anywhere in such a run is therefore released only after the run.
+    const int ns = (int)net->steps.size();
+    std::vector<int> run_end(ns);
+    for (int s = ns - 1; s >= 0; --s)
+        run_end[s] = (s + 1 < ns && net->steps[s + 1].kind == net->steps[s].kind) ? run_end[s + 1] : s;
     std::vector<std::vector<int>> dying(net->steps.size() + 1);
     for (int r = 0; r < nr; ++r)
-        if (last[r] >= 0 && last[r] < (int)net->steps.size()) dying[last[r]].push_back(r);
+        if (last[r] >= 0 && last[r] < (int)net->steps.size()) dying[run_end[last[r]]].push_back(r);
     for (int s = 0; s < (int)net->steps.size(); ++s) {
         std::vector<int> defs = net->steps[s].outs;
         if (net->steps[s].dst >= 0) defs.push_back(net->steps[s].dst);
@@ -668,6 +676,63 @@ void allocate(unihenn_net* net, std::vector<int>& phys_nl)
         }
         for (int r : dying[s])
             if (net->regs[r].phys >= 0) free_by_nl[net->regs[r].nl].push_back(net->regs[r].phys);
+    }
+}
+
+// Within each layer, order the steps by dependency level (independent steps
+// become neighbours) and, inside a level, by kind and source, so that the
+// executor can issue runs of independent steps of one kind together.
+void schedule_layers(unihenn_net* net)
+{
+    auto kind_order = [](StepKind k) {
+        switch (k) {
+        case ST_ROT: return 0;
+        case ST_MACM: return 1;
+        case ST_MAC: return 2;
+        case ST_RESCALE: return 3;
+        case ST_SQUARE: return 4;
+        case ST_ADD_PLAIN: return 5;
+        case ST_ADD: return 6;
+        default: return 7;
+        }
+    };
+    for (LayerRecord& L : net->layers) {
+        const size_t b = L.step_begin, e = L.step_end;
+        if (e - b < 2) continue;
+        std::map<int, size_t> producer;  // register -> step index (in range)
+        std::vector<int> level(e - b, 0);
+        for (size_t i = b; i < e; ++i) {
+            const Step& st = net->steps[i];
+            int lv = 0;
+            auto dep = [&](int r) {
+                auto it = producer.find(r);
+                if (r >= 0 && it != producer.end()) lv = std::max(lv, level[it->second - b] + 1);
+            };
+            dep(st.a);
+            dep(st.b);
+            for (const Term& t : st.terms) dep(t.src);
+            for (int r : st.srcs) dep(r);
+            if (st.acc) {
+                dep(st.dst);
+                for (int r : st.outs) dep(r);
+            }
+            level[i - b] = lv;
+            if (st.dst >= 0) producer[st.dst] = i;
+            for (int r : st.outs) producer[r] = i;
+        }
+        std::vector<size_t> idx(e - b);
+        for (size_t i = 0; i < idx.size(); ++i) idx[i] = b + i;
+        std::stable_sort(idx.begin(), idx.end(), [&](size_t x, size_t y) {
+            const Step &sx = net->steps[x], &sy = net->steps[y];
+            if (level[x - b] != level[y - b]) return level[x - b] < level[y - b];
+            if (kind_order(sx.kind) != kind_order(sy.kind)) return kind_order(sx.kind) < kind_order(sy.kind);
+            if (sx.kind == ST_ROT && sx.a != sy.a) return sx.a < sy.a;
+            return false;
+        });
+        std::vector<Step> sorted;
+        sorted.reserve(idx.size());
+        for (size_t i : idx) sorted.push_back(net->steps[i]);
+        std::copy(sorted.begin(), sorted.end(), net->steps.begin() + b);
     }
 }
 
@@ -795,6 +860,7 @@ extern "C" int unihenn_net_create(const unihenn_ctx* c, const unihenn_input* in,
             return uh_fail(UNIHENN_ELEVEL, "output not at one limb");
         }
 
+    if (max_batch <= 8 && !getenv("UNIHENN_NO_SCHEDULE")) schedule_layers(net);
     // device memory: plaintexts, registers, workspace
     std::vector<int> phys_nl;
     allocate(net, phys_nl);
@@ -807,7 +873,11 @@ extern "C" int unihenn_net_create(const unihenn_ctx* c, const unihenn_input* in,
     net->group_max = std::max(1, std::min(UH_GROUP_MAX, 32 / (int)max_batch));
     const size_t L0 = (size_t)net->ws_nl, Bm = max_batch, E = (size_t)net->group_max;
     const size_t group_rows = Bm * (L0 + L0 * L0) + E * Bm * (L0 * L0 + 7 * L0 + 2);
-    size_t ws_words = std::max(ks_ws_rows(net->ws_nl, (int)max_batch), group_rows) * c->n;
+    const int e_sq = std::max(1, 32 / (int)max_batch), e_rs = std::max(1, std::min(UH_EW_GROUP_MAX, 64 / (int)max_batch));
+    size_t ws_rows = std::max(ks_ws_rows(net->ws_nl, (int)max_batch), group_rows);
+    ws_rows = std::max(ws_rows, group_square_ws_rows(std::min(e_sq, UH_EW_GROUP_MAX), net->ws_nl, (int)max_batch));
+    ws_rows = std::max(ws_rows, (size_t)e_rs * max_batch * 2 * net->ws_nl);
+    size_t ws_words = ws_rows * c->n;
     if (hipMalloc(&net->pt_arena, sizeof(u64) * std::max<size_t>(net->pt_words, 1)) != hipSuccess ||
         hipMalloc(&net->reg_arena, sizeof(u64) * std::max<size_t>(reg_words, 1)) != hipSuccess ||
         hipMalloc(&net->ws, sizeof(u64) * ws_words) != hipSuccess) {
@@ -939,6 +1009,30 @@ struct Exec {
         }
     }
 
+    // consecutive steps from `si` accepted by `ok`, at the same output level,
+    // none reading a result of another; at most max_e steps (and max_e2)
+    template <class F>
+    std::vector<size_t> collect(size_t si, size_t end, int nl, F ok, int max_e, int max_e2)
+    {
+        std::vector<size_t> run;
+        std::vector<int> made;
+        int cap = std::max(1, std::min(max_e, max_e2));
+        static const char* nog = getenv("UNIHENN_NO_GROUP");  // kinds (step enum digits) never grouped
+        if (nog && strchr(nog, '0' + (int)net->steps[si].kind)) cap = 1;
+        for (size_t sj = si; sj < end && (int)run.size() < cap; ++sj) {
+            const Step& x = net->steps[sj];
+            if (!ok(x) || net->regs[x.dst].nl != nl) break;
+            bool dep = false;
+            auto reads = [&](int r) { return r >= 0 && std::find(made.begin(), made.end(), r) != made.end(); };
+            dep |= reads(x.a) || reads(x.b);
+            for (const Term& t : x.terms) dep |= reads(t.src);
+            if (dep) break;
+            run.push_back(sj);
+            made.push_back(x.dst);
+        }
+        return run;
+    }
+
     void rotations(const std::vector<size_t>& run, int nl)
     {
         const size_t rn = (size_t)c->n;
@@ -1014,6 +1108,28 @@ struct Exec {
                 break;
             }
             case ST_MAC: {
+                // a run of independent single-output sums with the same term count
+                std::vector<size_t> run = collect(si, end, nl, [&](const Step& x) {
+                    return x.kind == ST_MAC && !x.acc && x.terms.size() == st.terms.size() &&
+                           x.terms.size() <= UH_MACG_MAX;
+                }, UH_EW_GROUP_MAX, (int)(UH_MACG_MAX / std::max<size_t>(1, st.terms.size())));
+                if (run.size() > 1) {
+                    MacGroup m;
+                    memset(&m, 0, sizeof(m));
+                    m.E = (int)run.size();
+                    m.T = (int)st.terms.size();
+                    for (int e = 0; e < m.E; ++e) {
+                        const Step& x = net->steps[run[e]];
+                        m.acc[e] = reg(x.dst);
+                        for (int t = 0; t < m.T; ++t) {
+                            m.ct[e * m.T + t] = reg(x.terms[t].src);
+                            m.pt[e * m.T + t] = net->pt_arena + x.terms[t].pt;
+                        }
+                    }
+                    launch_mac_group(c, m, nl, B, s);
+                    si = run.back();
+                    break;
+                }
                 const size_t nt = st.terms.size();
                 for (size_t t0 = 0; t0 < nt; t0 += UH_MAC_MAX_TERMS) {
                     MacTerms mt;
@@ -1046,30 +1162,50 @@ struct Exec {
             }
             case ST_RESCALE: {
                 const int nla = net->regs[st.a].nl;
-                KsWs wa = ks_ws_carve(net->ws, nla, B, c->n);
-                rescale_core(c, reg(st.a), B, nla, reg(st.dst), wa, s);
+                std::vector<size_t> run = collect(si, end, nl, [&](const Step& x) { return x.kind == ST_RESCALE; },
+                                                  UH_EW_GROUP_MAX, std::max(1, 64 / B));
+                std::vector<const u64*> ins;
+                std::vector<u64*> outs;
+                for (size_t x : run) {
+                    ins.push_back(reg(net->steps[x].a));
+                    outs.push_back(reg(net->steps[x].dst));
+                }
+                group_rescale(c, (int)run.size(), ins.data(), outs.data(), B, nla, net->ws, s);
                 modup_owner = -1;
+                si = run.back();
                 break;
             }
             case ST_ADD:
-                launch_add(c, reg(st.dst), reg(st.a), reg(st.b), B * 2 * nl, nl, s);
+            case ST_ADD_PLAIN: {
+                const StepKind kind = st.kind;
+                std::vector<size_t> run = collect(si, end, nl, [&](const Step& x) { return x.kind == kind; },
+                                                  UH_EW_GROUP_MAX, UH_EW_GROUP_MAX);
+                EwGroup g;
+                memset(&g, 0, sizeof(g));
+                g.E = (int)run.size();
+                for (int e = 0; e < g.E; ++e) {
+                    const Step& x = net->steps[run[e]];
+                    g.out[e] = reg(x.dst);
+                    g.a[e] = reg(x.a);
+                    g.b[e] = kind == ST_ADD ? reg(x.b) : net->pt_arena + x.pt;
+                }
+                launch_group_add(c, g, B, nl, kind == ST_ADD_PLAIN, s);
+                si = run.back();
                 break;
-            case ST_ADD_PLAIN:
-                launch_add_plain(c, reg(st.dst), reg(st.a), net->pt_arena + st.pt, B, nl, s);
-                break;
+            }
             case ST_SQUARE: {
                 const int nla = net->regs[st.a].nl;
-                KsWs wa = ks_ws_carve(net->ws, nla, B, c->n);
-                u64* d0 = wa.aux;
-                u64* d1 = wa.aux + (size_t)B * nla * rn;
-                u64* d2 = wa.aux + (size_t)2 * B * nla * rn;
-                launch_tensor_square(c, d0, d1, d2, reg(st.a), B, nla, s);
-                ks_modup(c, d2, nla, B, nla, wa, s);
-                // the relinearised product goes to the (then dead) ModUp rows
-                u64* tmp = wa.modup;
-                ks_finish(c, d2, nla, net->rlk, c->n_data, B, nla, 1, tmp, d0, d1, nla, wa, s);
-                rescale_core(c, tmp, B, nla, reg(st.dst), wa, s);
+                std::vector<size_t> run = collect(si, end, nl, [&](const Step& x) { return x.kind == ST_SQUARE; },
+                                                  UH_EW_GROUP_MAX, std::max(1, 32 / B));
+                std::vector<const u64*> ins;
+                std::vector<u64*> outs;
+                for (size_t x : run) {
+                    ins.push_back(reg(net->steps[x].a));
+                    outs.push_back(reg(net->steps[x].dst));
+                }
+                group_square(c, (int)run.size(), ins.data(), outs.data(), net->rlk, B, nla, net->ws, s);
                 modup_owner = -1;
+                si = run.back();
                 break;
             }
             }

@@ -159,14 +159,20 @@ __global__ void __launch_bounds__(NTT_THREADS) k_ntt_inv(u64* __restrict__ data,
 // sub-transform that differ in three consecutive index bits, applies up to
 // three butterfly stages in registers, and exchanges through LDS once per
 // round (one barrier per three stages).  All index arithmetic is shifts and
-// masks (sub-transform size and tile width are powers of two).
+// masks (sub-transform size and tile width are powers of two).  Within a
+// stage the twiddle depends only on the held bits above the butterfly bit,
+// so each distinct twiddle is loaded once per round.  The contiguous pass
+// pads its LDS tile by one word per eight (u + u/8) so that the sixteen
+// lanes serving one sub-transform hit distinct banks in every round.
 template <int LOG_R, bool STRIDED, bool INV, bool LAST>
 __global__ void __launch_bounds__(NTT_THREADS) k_ntt_r8(u64* __restrict__ data, DevCtx ctx, RowMap map, int log_cols,
                                                         int sigma0)
 {
     constexpr int LOG_G = LOG_R - 3;  // threads per sub-transform: 2^LOG_G
     constexpr int ROUNDS = (LOG_R + 2) / 3;
-    __shared__ u64 s[TILE];
+    constexpr int R = 1 << LOG_R;
+    constexpr int RP = R + R / 8;     // padded sub-transform stride (contiguous pass)
+    __shared__ u64 s[TILE + TILE / 8];
     const int n = ctx.n, log_n = ctx.log_n;
     const int row = blockIdx.y;
     const int mi = rowmap_mod(map, row);
@@ -184,7 +190,7 @@ __global__ void __launch_bounds__(NTT_THREADS) k_ntt_r8(u64* __restrict__ data, 
     const int log_stride = log_n - LOG_R;
     // local index u -> global index, LDS index
 #define GIDX(u) (STRIDED ? col + ((u) << log_stride) : (col << LOG_R) + (u))
-#define LIDX(u) (STRIDED ? ((u) << log_cols) + c : (c << LOG_R) + (u))
+#define LIDX(u) (STRIDED ? ((u) << log_cols) + c : c * RP + (u) + ((u) >> 3))
     u64 x[8];
 #pragma unroll
     for (int rho = 0; rho < ROUNDS; ++rho) {
@@ -192,57 +198,59 @@ __global__ void __launch_bounds__(NTT_THREADS) k_ntt_r8(u64* __restrict__ data, 
         const int lo = INV ? (3 * rho < LOG_R - 3 ? 3 * rho : LOG_R - 3)
                            : (LOG_R - 3 - 3 * rho > 0 ? LOG_R - 3 - 3 * rho : 0);
         const int umask = (1 << lo) - 1;
-        int ub = ((g >> lo) << (lo + 3)) | (g & umask);
+        const int ub = ((g >> lo) << (lo + 3)) | (g & umask);
         if (rho == 0) {
+            if (!STRIDED && lo == 0) {
+                const ulonglong2* src = reinterpret_cast<const ulonglong2*>(a + GIDX(ub));
 #pragma unroll
-            for (int m = 0; m < 8; ++m) x[m] = a[GIDX(ub | (m << lo))];
+                for (int h = 0; h < 4; ++h) {
+                    const ulonglong2 v = src[h];
+                    x[2 * h] = v.x;
+                    x[2 * h + 1] = v.y;
+                }
+            } else {
+#pragma unroll
+                for (int m = 0; m < 8; ++m) x[m] = a[GIDX(ub | (m << lo))];
+            }
         } else {
 #pragma unroll
             for (int m = 0; m < 8; ++m) x[m] = s[LIDX(ub | (m << lo))];
         }
-        if (!INV) {
-            // stages tau = 3 rho .. : bit b = LOG_R - 1 - tau, from the top bit down
 #pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                const int tau = 3 * rho + k;
-                if (tau >= LOG_R) break;
-                const int b = LOG_R - 1 - tau;
-                const int mb = b - lo;
-                const int sigma = sigma0 + tau;
+        for (int k = 0; k < 3; ++k) {
+            int b, tau;
+            if (!INV) { tau = 3 * rho + k; b = LOG_R - 1 - tau; }
+            else { b = 3 * rho + k; tau = LOG_R - 1 - b; }
+            if (tau < 0 || tau >= LOG_R || b < lo) continue;
+            const int mb = b - lo;
+            const int sigma = sigma0 + tau;
+            const int shift = log_n - sigma;
+            // groups of held bits above mb share one twiddle
 #pragma unroll
-                for (int m = 0; m < 8; ++m) {
-                    if (m & (1 << mb)) continue;
-                    const int u = ub | (m << lo);
-                    const int ti = (1 << sigma) + (GIDX(u) >> (log_n - sigma));
-                    u64 U = x[m];
-                    U = U >= q2 ? U - q2 : U;
-                    const u64 V = mul_shoup_lazy(x[m | (1 << mb)], tw[ti], tw_sh[ti], q);
-                    x[m] = U + V;
-                    x[m | (1 << mb)] = U - V + q2;
-                }
-            }
-        } else {
-            // stages from the lowest held bit up (tau = LOG_R - 1 - b)
+            for (int hi = 0; hi < (4 >> mb); ++hi) {
+                const int mbase = hi << (mb + 1);
+                const int ti = (1 << sigma) + (GIDX(ub | (mbase << lo)) >> shift);
+                const u64 w = tw[ti], wsh = tw_sh[ti];
 #pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                const int b = 3 * rho + k;
-                if (b >= LOG_R) break;
-                const int mb = b - lo;
-                const int tau = LOG_R - 1 - b;
-                const int sigma = sigma0 + tau;
-#pragma unroll
-                for (int m = 0; m < 8; ++m) {
-                    if (m & (1 << mb)) continue;
-                    const int u = ub | (m << lo);
-                    const int ti = (1 << sigma) + (GIDX(u) >> (log_n - sigma));
-                    const u64 U = x[m], V = x[m | (1 << mb)];
-                    const u64 sum = U + V;
-                    x[m] = sum >= q2 ? sum - q2 : sum;
-                    x[m | (1 << mb)] = mul_shoup_lazy(U - V + q2, tw[ti], tw_sh[ti], q);
+                for (int low = 0; low < (1 << mb); ++low) {
+                    const int m0 = mbase | low, m1 = m0 | (1 << mb);
+                    if (!INV) {
+                        u64 U = x[m0];
+                        U = U >= q2 ? U - q2 : U;
+                        const u64 V = mul_shoup_lazy(x[m1], w, wsh, q);
+                        x[m0] = U + V;
+                        x[m1] = U - V + q2;
+                    } else {
+                        const u64 U = x[m0], V = x[m1];
+                        const u64 sum = U + V;
+                        x[m0] = sum >= q2 ? sum - q2 : sum;
+                        x[m1] = mul_shoup_lazy(U - V + q2, w, wsh, q);
+                    }
                 }
             }
         }
         if (rho + 1 < ROUNDS) {
+            if (rho > 0) __syncthreads();  // every thread has read this round's LDS values
 #pragma unroll
             for (int m = 0; m < 8; ++m) s[LIDX(ub | (m << lo))] = x[m];
             __syncthreads();
@@ -258,7 +266,15 @@ __global__ void __launch_bounds__(NTT_THREADS) k_ntt_r8(u64* __restrict__ data, 
                         v = v >= q ? v - q : v;
                     }
                 }
-                a[GIDX(ub | (m << lo))] = v;
+                x[m] = v;
+            }
+            if (!STRIDED && lo == 0) {
+                ulonglong2* dst = reinterpret_cast<ulonglong2*>(a + GIDX(ub));
+#pragma unroll
+                for (int h = 0; h < 4; ++h) dst[h] = make_ulonglong2(x[2 * h], x[2 * h + 1]);
+            } else {
+#pragma unroll
+                for (int m = 0; m < 8; ++m) a[GIDX(ub | (m << lo))] = x[m];
             }
         }
     }
