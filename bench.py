@@ -209,6 +209,50 @@ def cpu_baseline(W) -> dict:
             "sample": f"one whole LeNet-1 encrypted inference (N=2^14, 8 limbs, 288 rotations), {dt:.1f} s"}
 
 
+SERVE_MODELS = {"conv1": 16, "cnn1d": 8, "cifar_cnn": 4}     # model -> largest batch (ciphertexts)
+SERVE_MIX = {"conv1": 0.5, "cnn1d": 0.3, "cifar_cnn": 0.2}
+SERVE_HBM_BUDGET = 8 << 30                                    # bytes of admitted request ciphertexts
+
+
+def serving_bench(P, W, n_requests: int) -> dict:
+    """Three models of different ring sizes behind the continuous-batching
+    server: saturation throughput (all requests queued at t = 0), then
+    Poisson arrivals (seed 4, mix 50/30/20) at 0.5, 0.8 and 1.0 times it."""
+    import torch
+    from paper_2402_03060_amd.serve import GpuExecutor, Scheduler, poisson_requests, prepare_model, serve
+    print("[bench] setup serving models " + ", ".join(SERVE_MODELS), file=sys.stderr, flush=True)
+    models = {m: prepare_model(P, W, m, b, pool_size=16) for m, b in SERVE_MODELS.items()}
+    ex = GpuExecutor(models)
+    ex.warmup()
+    specs = {m: d["spec"] for m, d in models.items()}
+    payloads = {m: list(range(16)) for m in models}
+    out = {"models": {m: {"log_n": d["cfg"]["log_n"], "max_batch": SERVE_MODELS[m],
+                          "ciphertexts_per_request": 1, "samples_per_ct": d["cfg"]["samples_per_ct"]}
+                      for m, d in models.items()},
+           "mix": SERVE_MIX, "arrival_seed": W.SEED_ARRIVALS, "hbm_budget_bytes": SERVE_HBM_BUDGET,
+           "requests_per_level": n_requests}
+    burst = poisson_requests(SERVE_MIX, 1e9, n_requests, W.SEED_ARRIVALS, payloads)
+    s = serve(Scheduler(specs, SERVE_HBM_BUDGET), ex, burst)
+    torch.cuda.synchronize()
+    sat = s.completed / s.duration
+    out["saturation_requests_per_s"] = round(sat, 2)
+    print(f"[bench] serving saturation {sat:.1f} req/s", file=sys.stderr, flush=True)
+    levels = {}
+    for frac in (0.5, 0.8, 1.0):
+        reqs = poisson_requests(SERVE_MIX, frac * sat, n_requests, W.SEED_ARRIVALS, payloads)
+        s = serve(Scheduler(specs, SERVE_HBM_BUDGET), ex, reqs)
+        torch.cuda.synchronize()
+        summ = s.summary()
+        summ["offered_requests_per_s"] = round(frac * sat, 2)
+        levels[str(frac)] = summ
+        print(f"[bench] serving at {frac:.1f}x: {summ['throughput_per_s']} req/s, p50 {summ['p50_ms']} ms, "
+              f"p99 {summ['p99_ms']} ms", file=sys.stderr, flush=True)
+    out["load_levels"] = levels
+    del ex, models
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -219,6 +263,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--only-plain", action="store_true", help="skip every extra measurement (for profiling)")
+    ap.add_argument("--serve-requests", type=int, default=300,
+                    help="requests per load level of the serving measurement (0 skips it)")
     ap.add_argument("--ntt-probe", type=int, default=0, metavar="ROWS",
                     help="only time forward+inverse NTTs of ROWS limb rows at N=2^14 (kernel throughput)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -331,6 +377,27 @@ def main():
                           "max_abs_err_vs_fp64": errb}
         print(f"[bench] batched: {imgs:.1f} img/s ({imgs / value:.1f}x plain), max |err| {errb:.2e}",
               file=sys.stderr, flush=True)
+
+    if not args.no_batched:
+        del sb, stepb
+        torch.cuda.empty_cache()
+        print("[bench] setup batched 1D CNN (64 ciphertexts x 8 sequences)", file=sys.stderr, flush=True)
+        sc = setup(P, W, "cnn1d", batch=64)
+        nc, ctc, outc = sc["net"], sc["ct"], sc["outs"]
+        nc.set_mode(P.EVAL_HOISTED | P.EVAL_GRAPH)
+        stepc = lambda: nc.eval(ctc, outc)
+        dtc = timed(stepc, args.batched_steps, 1)
+        seqs = args.batched_steps * 64 * 8 / dtc
+        errc = max_error(P, W, sc)
+        res["batched_cnn1d"] = {"sequences_per_s": round(seqs, 2),
+                                "ms_per_launch": round(1e3 * dtc / args.batched_steps, 2),
+                                "sequences_per_launch": 64 * 8, "max_abs_err_vs_fp64": errc}
+        print(f"[bench] batched cnn1d: {seqs:.1f} seq/s, max |err| {errc:.2e}", file=sys.stderr, flush=True)
+        del sc, stepc
+        torch.cuda.empty_cache()
+
+    if args.serve_requests:
+        res["serving"] = serving_bench(P, W, args.serve_requests)
 
     if not args.no_cpu_baseline:
         print("[bench] CPU oracle baseline (one inference)", file=sys.stderr, flush=True)

@@ -179,8 +179,8 @@ extern "C" int unihenn_gen_switch_key(const unihenn_ctx* c, const uint64_t* sk, 
     u64 *t = nullptr, *e = nullptr;
     if (hipMalloc(&t, sizeof(u64) * nb * c->n) != hipSuccess ||
         hipMalloc(&e, sizeof(u64) * (size_t)nd * nb * c->n) != hipSuccess) {
-        hipFree(t);
-        hipFree(e);
+        (void)hipFree(t);
+        (void)hipFree(e);
         return uh_fail(UNIHENN_ENOMEM, "key generation buffers");
     }
     if (relin)
@@ -196,8 +196,8 @@ extern "C" int unihenn_gen_switch_key(const unihenn_ctx* c, const uint64_t* sk, 
                                                                       (int)c->primes.size(), seed ^ (stream_id << 20));
     launch_mont_convert(c, out, nd * 2 * nb, m, 1, s);
     hipError_t err = hipStreamSynchronize(s);
-    hipFree(t);
-    hipFree(e);
+    (void)hipFree(t);
+    (void)hipFree(e);
     if (err != hipSuccess) return uh_fail(UNIHENN_EDEVICE, hipGetErrorString(err));
     return UNIHENN_OK;
 }
@@ -217,7 +217,7 @@ extern "C" int unihenn_encrypt_sk(const unihenn_ctx* c, const uint64_t* sk, cons
     launch_ntt_fwd(c, e, B * nl, m, s);
     k_encrypt_combine<<<grid_rows(c->n, B * nl), CL_THREADS, 0, s>>>(ct->data, e, sk, pts, c->dev, nl, seed);
     hipError_t err = hipStreamSynchronize(s);
-    hipFree(e);
+    (void)hipFree(e);
     if (err != hipSuccess) return uh_fail(UNIHENN_EDEVICE, hipGetErrorString(err));
     return UNIHENN_OK;
 }
@@ -240,20 +240,21 @@ extern "C" int unihenn_decrypt_slots(const unihenn_ctx* c, const uint64_t* sk, c
     double* dv = nullptr;
     if (hipMalloc(&m, sizeof(u64) * (size_t)B * c->n) != hipSuccess || hipMalloc(&de, sizeof(uint32_t) * n_slots) != hipSuccess ||
         hipMalloc(&dv, sizeof(double) * (size_t)B * n_slots) != hipSuccess) {
-        hipFree(m);
-        hipFree(de);
-        hipFree(dv);
+        (void)hipFree(m);
+        (void)hipFree(de);
+        (void)hipFree(dv);
         return uh_fail(UNIHENN_ENOMEM, "decryption buffers");
     }
-    hipMemcpyAsync(de, es.data(), sizeof(uint32_t) * n_slots, hipMemcpyHostToDevice, s);
+    hipError_t cerr = hipMemcpyAsync(de, es.data(), sizeof(uint32_t) * n_slots, hipMemcpyHostToDevice, s);
     k_decrypt_limb0<<<grid_rows(c->n, B), CL_THREADS, 0, s>>>(m, ct->data, sk, c->dev, nl);
     launch_ntt_inv(c, m, B, rowmap_list({0}), s);
     k_decode_slots<<<dim3(n_slots, B), CL_THREADS, 0, s>>>(dv, m, de, (int)n_slots, c->d_cos, c->dev, 1.0 / ct->scale);
-    hipMemcpyAsync(values, dv, sizeof(double) * (size_t)B * n_slots, hipMemcpyDeviceToHost, s);
+    if (cerr == hipSuccess) cerr = hipMemcpyAsync(values, dv, sizeof(double) * (size_t)B * n_slots, hipMemcpyDeviceToHost, s);
     hipError_t err = hipStreamSynchronize(s);
-    hipFree(m);
-    hipFree(de);
-    hipFree(dv);
+    if (err == hipSuccess) err = cerr;
+    (void)hipFree(m);
+    (void)hipFree(de);
+    (void)hipFree(dv);
     if (err != hipSuccess) return uh_fail(UNIHENN_EDEVICE, hipGetErrorString(err));
     return UNIHENN_OK;
 }

@@ -215,7 +215,10 @@ extern "C" int unihenn_ctx_create(uint32_t log_n, const uint32_t* prime_bits, ui
     c->n_data = (int)n_data;
     c->scale = scale;
     c->primes = primes;
-    hipGetDevice(&c->device);
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return uh_fail(UNIHENN_EDEVICE, "no current HIP device");
+    }
     const int n = c->n, nm = (int)primes.size();
 
     std::vector<u64> tw((size_t)4 * nm * n);
@@ -270,14 +273,18 @@ extern "C" int unihenn_ctx_create(uint32_t log_n, const uint32_t* prime_bits, ui
     if (hipMalloc(&c->d_p_inv, sizeof(u64) * c->p_inv.size()) != hipSuccess) return fail("hipMalloc pinv");
     if (hipMalloc(&c->d_galois_e, sizeof(uint32_t) * ge.size()) != hipSuccess) return fail("hipMalloc galois");
     if (hipMalloc(&c->d_cos, sizeof(double) * cs.size()) != hipSuccess) return fail("hipMalloc cos");
-    hipMemcpy(c->d_mod, c->host_mod.data(), sizeof(Modulus) * nm, hipMemcpyHostToDevice);
-    hipMemcpy(c->d_tw, tw.data(), sizeof(u64) * tw.size(), hipMemcpyHostToDevice);
-    hipMemcpy(c->d_qmod, c->q_mod.data(), sizeof(u64) * c->q_mod.size(), hipMemcpyHostToDevice);
-    hipMemcpy(c->d_inv_last, c->inv_last.data(), sizeof(u64) * c->inv_last.size(), hipMemcpyHostToDevice);
-    hipMemcpy(c->d_p_inv, c->p_inv.data(), sizeof(u64) * c->p_inv.size(), hipMemcpyHostToDevice);
-    hipMemcpy(c->d_galois_e, ge.data(), sizeof(uint32_t) * ge.size(), hipMemcpyHostToDevice);
-    if (hipMemcpy(c->d_cos, cs.data(), sizeof(double) * cs.size(), hipMemcpyHostToDevice) != hipSuccess)
-        return fail("upload");
+    hipError_t up = hipMemcpy(c->d_mod, c->host_mod.data(), sizeof(Modulus) * nm, hipMemcpyHostToDevice);
+    if (up == hipSuccess) up = hipMemcpy(c->d_tw, tw.data(), sizeof(u64) * tw.size(), hipMemcpyHostToDevice);
+    if (up == hipSuccess) up = hipMemcpy(c->d_qmod, c->q_mod.data(), sizeof(u64) * c->q_mod.size(), hipMemcpyHostToDevice);
+    if (up == hipSuccess)
+        up = hipMemcpy(c->d_inv_last, c->inv_last.data(), sizeof(u64) * c->inv_last.size(), hipMemcpyHostToDevice);
+    if (up == hipSuccess) up = hipMemcpy(c->d_p_inv, c->p_inv.data(), sizeof(u64) * c->p_inv.size(), hipMemcpyHostToDevice);
+    if (up == hipSuccess) up = hipMemcpy(c->d_galois_e, ge.data(), sizeof(uint32_t) * ge.size(), hipMemcpyHostToDevice);
+    if (up == hipSuccess) up = hipMemcpy(c->d_cos, cs.data(), sizeof(double) * cs.size(), hipMemcpyHostToDevice);
+    if (up != hipSuccess) {
+        unihenn_ctx_destroy(c);
+        return uh_fail(UNIHENN_EDEVICE, std::string("constant upload: ") + hipGetErrorString(up));
+    }
 
     c->dev.log_n = c->log_n;
     c->dev.n = n;
@@ -295,13 +302,13 @@ extern "C" int unihenn_ctx_create(uint32_t log_n, const uint32_t* prime_bits, ui
 extern "C" int unihenn_ctx_destroy(unihenn_ctx* c)
 {
     if (!c) return UNIHENN_OK;
-    hipFree(c->d_mod);
-    hipFree(c->d_tw);
-    hipFree(c->d_qmod);
-    hipFree(c->d_inv_last);
-    hipFree(c->d_p_inv);
-    hipFree(c->d_galois_e);
-    hipFree(c->d_cos);
+    (void)hipFree(c->d_mod);
+    (void)hipFree(c->d_tw);
+    (void)hipFree(c->d_qmod);
+    (void)hipFree(c->d_inv_last);
+    (void)hipFree(c->d_p_inv);
+    (void)hipFree(c->d_galois_e);
+    (void)hipFree(c->d_cos);
     delete c;
     return UNIHENN_OK;
 }
@@ -331,54 +338,47 @@ const char* g_names[KF_COUNT] = {"ntt_fwd_col", "ntt_fwd_row", "ntt_inv_row", "n
                                  "moddown", "rescale", "mac", "automorphism", "tensor", "add", "encode", "other"};
 }  // namespace
 
+// fold finished timer pairs into the per-family totals (g_stats_mu held)
+static void drain_pending_locked()
+{
+    for (auto& p : g_pending) {
+        float ms = 0;
+        if (hipEventSynchronize(p.b) != hipSuccess || hipEventElapsedTime(&ms, p.a, p.b) != hipSuccess) ms = 0;
+        g_launches[p.fam]++;
+        g_ms[p.fam] += ms;
+        g_bytes[p.fam] += p.bytes;
+        g_ops[p.fam] += p.ops;
+        (void)hipEventDestroy(p.a);
+        (void)hipEventDestroy(p.b);
+    }
+    g_pending.clear();
+}
+
 LaunchTimer::LaunchTimer(KernelFamily f, double b, hipStream_t s, double o)
     : fam(f), bytes(b), ops(o), stream(s), on(false)
 {
     if (!g_stats_on) return;
-    on = true;
-    hipEventCreate(&ev0);
-    hipEventCreate(&ev1);
-    hipEventRecord(ev0, s);
+    on = hipEventCreate(&ev0) == hipSuccess;
+    if (on && hipEventCreate(&ev1) != hipSuccess) {
+        (void)hipEventDestroy(ev0);
+        on = false;
+    }
+    if (on) (void)hipEventRecord(ev0, s);
 }
 
 LaunchTimer::~LaunchTimer()
 {
     if (!on) return;
-    hipEventRecord(ev1, stream);
+    (void)hipEventRecord(ev1, stream);
     std::lock_guard<std::mutex> g(g_stats_mu);
     g_pending.push_back({(int)fam, bytes, ops, ev0, ev1});
-    if (g_pending.size() > 8192) {
-        // bound the number of live events
-        for (auto& p : g_pending) {
-            hipEventSynchronize(p.b);
-            float ms = 0;
-            hipEventElapsedTime(&ms, p.a, p.b);
-            g_launches[p.fam]++;
-            g_ms[p.fam] += ms;
-            g_bytes[p.fam] += p.bytes;
-            g_ops[p.fam] += p.ops;
-            hipEventDestroy(p.a);
-            hipEventDestroy(p.b);
-        }
-        g_pending.clear();
-    }
+    if (g_pending.size() > 8192) drain_pending_locked();  // bound the number of live events
 }
 
 void stats_collect()
 {
     std::lock_guard<std::mutex> g(g_stats_mu);
-    for (auto& p : g_pending) {
-        hipEventSynchronize(p.b);
-        float ms = 0;
-        hipEventElapsedTime(&ms, p.a, p.b);
-        g_launches[p.fam]++;
-        g_ms[p.fam] += ms;
-        g_bytes[p.fam] += p.bytes;
-        g_ops[p.fam] += p.ops;
-        hipEventDestroy(p.a);
-        hipEventDestroy(p.b);
-    }
-    g_pending.clear();
+    drain_pending_locked();
 }
 
 bool stats_enabled() { return g_stats_on; }

@@ -81,11 +81,11 @@ struct EncodeJob {
     int* ovf = nullptr;
     ~EncodeJob()
     {
-        hipFree(ek);
-        hipFree(zv);
-        hipFree(m);
-        hipFree(ws);
-        hipFree(ovf);
+        (void)hipFree(ek);
+        (void)hipFree(zv);
+        (void)hipFree(m);
+        (void)hipFree(ws);
+        (void)hipFree(ovf);
     }
 };
 

@@ -113,16 +113,19 @@ struct unihenn_net {
     std::map<int, const u64*> keys;
     const u64* rlk = nullptr;
     int mode = UNIHENN_EVAL_PLAIN;
-    // captured evaluation (UNIHENN_EVAL_GRAPH)
+    // captured evaluations (UNIHENN_EVAL_GRAPH), one per batch size and buffer set
     hipStream_t gstream = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
-    hipGraphExec_t gexec = nullptr;
-    struct {
+    struct GraphEntry {
         int batch = 0, in_limbs = 0, mode = -1;
         const u64* in = nullptr;
         std::vector<u64*> outs;
         size_t key_version = 0;
-    } gkey;
+        hipGraphExec_t exec = nullptr;
+        unsigned long long last_use = 0;
+    };
+    std::vector<GraphEntry> graphs;
+    unsigned long long graph_clock = 0;
     size_t key_version = 0;
 };
 
@@ -742,13 +745,16 @@ void schedule_layers(unihenn_net* net)
 extern "C" int unihenn_net_destroy(unihenn_net* net)
 {
     if (!net) return UNIHENN_OK;
-    if (net->gexec) hipGraphExecDestroy(net->gexec);
-    if (net->ev_in) hipEventDestroy(net->ev_in);
-    if (net->ev_out) hipEventDestroy(net->ev_out);
-    if (net->gstream) hipStreamDestroy(net->gstream);
-    hipFree(net->pt_arena);
-    hipFree(net->reg_arena);
-    hipFree(net->ws);
+    // a replay still in flight reads the arenas: let it finish first
+    if (net->gstream) (void)hipStreamSynchronize(net->gstream);
+    for (auto& g : net->graphs)
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (net->ev_in) (void)hipEventDestroy(net->ev_in);
+    if (net->ev_out) (void)hipEventDestroy(net->ev_out);
+    if (net->gstream) (void)hipStreamDestroy(net->gstream);
+    (void)hipFree(net->pt_arena);
+    (void)hipFree(net->reg_arena);
+    (void)hipFree(net->ws);
     delete net;
     return UNIHENN_OK;
 }
@@ -1254,13 +1260,22 @@ extern "C" int unihenn_eval_network(const unihenn_ctx* c, unihenn_net* net, cons
         }
         std::vector<u64*> outs;
         for (size_t i = 0; i < net->out_regs.size(); ++i) outs.push_back(out[i].data);
-        auto& k = net->gkey;
-        const bool hit = net->gexec && k.batch == (int)in->batch && k.in == in->data && k.in_limbs == (int)in->n_limbs &&
-                         k.outs == outs && k.mode == net->mode && k.key_version == net->key_version;
+        unihenn_net::GraphEntry* hit = nullptr;
+        for (auto& g : net->graphs)
+            if (g.exec && g.batch == (int)in->batch && g.in == in->data && g.in_limbs == (int)in->n_limbs &&
+                g.outs == outs && g.mode == net->mode && g.key_version == net->key_version)
+                hit = &g;
         if (!hit) {
-            if (net->gexec) {
-                hipGraphExecDestroy(net->gexec);
-                net->gexec = nullptr;
+            // capture into a free slot, or replace the least recently used of 16
+            if (net->graphs.size() < 16) {
+                net->graphs.emplace_back();
+                hit = &net->graphs.back();
+            } else {
+                hit = &net->graphs[0];
+                for (auto& g : net->graphs)
+                    if (g.last_use < hit->last_use) hit = &g;
+                if (hit->exec) (void)hipGraphExecDestroy(hit->exec);
+                hit->exec = nullptr;
             }
             Exec ex{net, c, (int)in->batch, net->gstream, {}, -1, in->data, (int)in->n_limbs};
             for (size_t i = 0; i < net->out_regs.size(); ++i) ex.bound[net->out_regs[i]] = out[i].data;
@@ -1269,26 +1284,28 @@ extern "C" int unihenn_eval_network(const unihenn_ctx* c, unihenn_net* net, cons
             hipGraph_t graph_obj = nullptr;
             hipError_t e = hipStreamEndCapture(net->gstream, &graph_obj);
             if (rc2) {
-                if (graph_obj) hipGraphDestroy(graph_obj);
+                if (graph_obj) (void)hipGraphDestroy(graph_obj);
                 return rc2;
             }
             if (e != hipSuccess) return uh_fail(UNIHENN_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
-            e = hipGraphInstantiate(&net->gexec, graph_obj, nullptr, nullptr, 0);
-            hipGraphDestroy(graph_obj);
+            e = hipGraphInstantiate(&hit->exec, graph_obj, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph_obj);
             if (e != hipSuccess) {
-                net->gexec = nullptr;
+                hit->exec = nullptr;
                 return uh_fail(UNIHENN_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
             }
-            k.batch = (int)in->batch;
-            k.in = in->data;
-            k.in_limbs = (int)in->n_limbs;
-            k.outs = outs;
-            k.mode = net->mode;
-            k.key_version = net->key_version;
+            hit->batch = (int)in->batch;
+            hit->in = in->data;
+            hit->in_limbs = (int)in->n_limbs;
+            hit->outs = outs;
+            hit->mode = net->mode;
+            hit->key_version = net->key_version;
         }
+        hit->last_use = ++net->graph_clock;
+        hipGraphExec_t gexec = hit->exec;
         UH_CHECK_HIP(hipEventRecord(net->ev_in, cs));
         UH_CHECK_HIP(hipStreamWaitEvent(net->gstream, net->ev_in, 0));
-        UH_CHECK_HIP(hipGraphLaunch(net->gexec, net->gstream));
+        UH_CHECK_HIP(hipGraphLaunch(gexec, net->gstream));
         UH_CHECK_HIP(hipEventRecord(net->ev_out, net->gstream));
         UH_CHECK_HIP(hipStreamWaitEvent(cs, net->ev_out, 0));
     }

@@ -135,7 +135,7 @@ def test_full_size_rotation_lenet1_ring():
     assert np.array_equal(ctx.export_ct(r)[0], ck.rescale(exp).data)
 
 
-@pytest.mark.parametrize("name", ["conv1", "lenet1", "cnn1d"])
+@pytest.mark.parametrize("name", ["conv1", "lenet1", "cnn1d", "cifar_cnn"])
 def test_product_client_end_to_end(name):
     """The library's own client (GPU keygen, encryption, decryption) around
     the full-size network: outputs within 1e-3 of the FP64 CNN."""
@@ -205,3 +205,35 @@ def test_graph_replay_matches_eager():
             swapped = [ctx.export_ct(o) for o in net.eval(other)]
             assert np.array_equal(swapped[0][0], eager[0][1])
             net.set_mode(mode | P.EVAL_GRAPH)
+
+
+def test_graph_cache_several_shapes():
+    """Graphs captured for two batch sizes and two output sets stay valid
+    while the evaluation alternates between them."""
+    import torch
+    import paper_2402_03060_amd as P
+    cfg = W.config("lenet1")
+    cfg["log_n"] = 11
+    sess = OracleSession(cfg)
+    onet = build_net(cfg, sess.ck.slots)
+    xs = W.gen_inputs(cfg["input"], 3)
+    cts = [run_encrypted(sess, onet, xs[b:b + 1], enc_seed=300 + b)[0] for b in range(3)]
+    ctx = _ctx(P, cfg)
+    net = _gpu_net(P, ctx, cfg, sess, onet, batch=3)
+    gin3 = ctx.import_ct(np.stack([c.data for c in cts]), cts[0].scale)
+    net.set_mode(P.EVAL_HOISTED)
+    eager = [ctx.export_ct(o) for o in net.eval(gin3)]
+    net.set_mode(P.EVAL_HOISTED | P.EVAL_GRAPH)
+    staging = ctx.empty_ct(3, gin3.n_limbs, gin3.scale)
+    outs_a, outs_b = net.alloc_outputs(3), net.alloc_outputs(3)
+    plan = [(3, outs_a), (1, outs_a), (2, outs_b), (3, outs_a), (1, outs_b), (2, outs_b), (3, outs_b)]
+    for rep, (b, outs) in enumerate(plan):
+        perm = [(rep + i) % 3 for i in range(b)]
+        staging.data[:b].copy_(gin3.data[perm])
+        o = [P.Ciphertext(x.data[:b], 0.0) for x in outs]
+        net.eval(P.Ciphertext(staging.data[:b], gin3.scale), o)
+        torch.cuda.synchronize()
+        got = [ctx.export_ct(x) for x in o]
+        for k in range(len(got)):
+            for i, src in enumerate(perm):
+                assert np.array_equal(got[k][i], eager[k][src]), (rep, b, k, i)
