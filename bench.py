@@ -150,12 +150,12 @@ BUTTERFLY_PEAK = VALU_LANE_OPS_PER_S / BUTTERFLY_SLOTS
 PROFILES = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles")
 
 
-def measured_traffic(kernel: str):
-    """HBM bytes per dispatch of `kernel` from the committed rocprofv3 PMC
-    summary, or None when there is none or the kernel source has changed
-    since the counters were taken."""
+def measured_traffic(family: str, workload: str = "lenet1_plain"):
+    """Measured over algorithmic HBM bytes (read, write) of the family's
+    kernel from the committed rocprofv3 PMC summary, or None when there is
+    none or the kernel source has changed since the counters were taken."""
     import hashlib
-    path = os.path.join(PROFILES, f"{kernel}_lenet1_plain_traffic.txt")
+    path = os.path.join(PROFILES, f"{family}_{workload}_traffic.txt")
     if not os.path.exists(path):
         return None
     kv = {}
@@ -163,13 +163,12 @@ def measured_traffic(kernel: str):
         if "=" in line and not line.startswith("#"):
             k, v = line.split("=", 1)
             kv[k.strip()] = v.strip()
-    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2402_03060_amd", "csrc", "ntt.hip")
-    if hashlib.sha256(open(src, "rb").read()).hexdigest() != kv.get("ntt_source_sha256"):
+    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2402_03060_amd", "csrc", kv["source"])
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != kv.get("source_sha256"):
         return None
-    return {"read_bytes_per_dispatch": float(kv["measured_read_bytes_per_dispatch"]),
-            "write_bytes_per_dispatch": float(kv["measured_write_bytes_per_dispatch"]),
-            "read_over_algorithmic": float(kv["read_over_algorithmic"]),
+    return {"read_over_algorithmic": float(kv["read_over_algorithmic"]),
             "write_over_algorithmic": float(kv["write_over_algorithmic"]),
+            "fetch_scale": float(kv["fetch_scale"]), "write_scale": float(kv["write_scale"]),
             "source": os.path.basename(path)}
 
 
@@ -190,6 +189,78 @@ def roofline_entry(stats: dict, traffic=None) -> dict:
         achieved = by / n / avg_s / 1e9
         out.update({"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "bytes_per_launch": by / n})
+    return out
+
+
+def family_table(stats: dict, steps: int) -> dict:
+    """Per kernel family: launches and time per step, achieved HBM rate on
+    its algorithmic bytes and its fraction of 8 TB/s; for NTT passes also the
+    butterfly rate against the derived integer-ALU peak."""
+    out = {}
+    for fam, (n, ms, by, ops) in sorted(stats.items(), key=lambda kv: -kv[1][1]):
+        if not n or ms <= 0:
+            continue
+        sec = ms / 1e3
+        e = {"launches_per_step": round(n / steps, 2), "ms_per_step": round(ms / steps, 4),
+             "avg_us": round(1e6 * sec / n, 2), "gbs": round(by / sec / 1e9, 1),
+             "hbm_frac": round(by / sec / 1e9 / HBM_PEAK_GBS, 4)}
+        if ops > 0:
+            e["g_butterflies_per_s"] = round(ops / sec / 1e9, 1)
+            e["alu_frac"] = round(ops / sec / BUTTERFLY_PEAK, 4)
+        out[fam] = e
+    return out
+
+
+def step_distribution(fn, reps: int = 30, warmup: int = 3) -> dict:
+    """Per-step GPU time from events around each step on the current stream
+    (3 warm-ups, 30 timed repetitions): mean, std, p50, p99 in ms."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in evs:
+        a.record()
+        fn()
+        b.record()
+    torch.cuda.synchronize()
+    t = np.array([a.elapsed_time(b) for a, b in evs])
+    return {"reps": reps, "mean_ms": round(float(t.mean()), 4), "std_ms": round(float(t.std()), 4),
+            "p50_ms": round(float(np.percentile(t, 50)), 4), "p99_ms": round(float(np.percentile(t, 99)), 4)}
+
+
+ROT_SIZES = [(13, 3), (14, 8), (14, 4), (15, 8)]      # (log2 N, data limbs)
+
+
+def rotation_microbench(P, batch: int = 128, hoisted: int = 24) -> dict:
+    """Rotations/s at several ring sizes: one rotation of one ciphertext,
+    `hoisted` rotations of one ciphertext sharing one ModUp, and one rotation
+    of `batch` ciphertexts per launch.  Keys and inputs come from the
+    library's own client and are resident before timing."""
+    import torch
+    out = {}
+    for log_n, nl in ROT_SIZES:
+        ctx = P.Context(log_n, [60] + [40] * (nl - 1), 60, 2.0 ** 40)
+        sk = P.keygen_secret(ctx, 21)
+        steps = list(range(1, hoisted + 1))
+        keys = [P.gen_switch_key(ctx, sk, 22, steps=r) for r in steps]
+        z = np.random.default_rng(23).uniform(-1, 1, ctx.slots)
+        pt = ctx.encode(z, ctx.scale, nl, mont=False)
+        ctb = P.encrypt_sk(ctx, sk, pt[None].expand(batch, nl, ctx.n).contiguous(), 24, ctx.scale)
+        ct1 = P.Ciphertext(ctb.data[:1].clone(), ctx.scale)
+        ws1 = ctx.workspace(nl, 1)
+        dt1 = timed(lambda: ctx.rotate(ct1, 1, keys[0], ws1), 50, 5)
+        wsh = ctx.workspace(nl, hoisted)
+        dth = timed(lambda: ctx.rotate_hoisted(ct1, steps, keys, wsh), 10, 2)
+        wsb = ctx.workspace(nl, batch)
+        dtb = timed(lambda: ctx.rotate(ctb, 1, keys[0], wsb), 5, 1)
+        out[f"N=2^{log_n},limbs={nl}"] = {
+            "single_per_s": round(50 / dt1, 1),
+            f"hoisted{hoisted}_per_s": round(10 * hoisted / dth, 1),
+            f"batched{batch}_per_s": round(5 * batch / dtb, 1),
+            "key_mb": round(nl * 2 * (nl + 1) * ctx.n * 8 / 1e6, 2)}
+        del ctx, sk, keys, ctb, ct1, ws1, wsh, wsb
+        torch.cuda.empty_cache()
     return out
 
 
@@ -263,6 +334,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--only-plain", action="store_true", help="skip every extra measurement (for profiling)")
+    ap.add_argument("--no-rotation-sweep", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=300,
                     help="requests per load level of the serving measurement (0 skips it)")
     ap.add_argument("--ntt-probe", type=int, default=0, metavar="ROWS",
@@ -339,10 +411,13 @@ def main():
     rf = roofline_entry(stats)
     tr = measured_traffic(rf["kernel"])
     if tr is not None:
-        rf["traffic"] = round(tr["read_bytes_per_dispatch"] + tr["write_bytes_per_dispatch"])
+        # algorithmic bytes per launch are half reads, half writes for every NTT pass
+        half = rf["bytes_per_launch"] / 2
+        rf["traffic"] = round(half * tr["read_over_algorithmic"] + half * tr["write_over_algorithmic"])
         rf["traffic_detail"] = tr
     res["roofline"] = rf
-    res["kernel_families_ms_per_step"] = {k: round(v[1] / args.steps, 4) for k, v in stats.items() if v[0]}
+    res["kernel_families"] = family_table(stats, args.steps)
+    res["plain_step_distribution"] = step_distribution(step)
 
     # hoisted evaluation of the same single-image workload
     net.set_mode(P.EVAL_HOISTED | P.EVAL_GRAPH)
@@ -359,6 +434,10 @@ def main():
     rot = lambda: ctx.rotate(full, 1, key, ws)
     dtr = timed(rot, 50, 5)
     res["rotations_per_s"] = round(50 / dtr, 1)
+    if not args.no_rotation_sweep:
+        print("[bench] rotation microbenchmark", file=sys.stderr, flush=True)
+        del ws, full
+        res["rotation_sweep"] = rotation_microbench(P)
 
     if not args.no_batched:
         B = args.batched_cts
@@ -375,6 +454,9 @@ def main():
         res["batched"] = {"images_per_s": round(imgs, 2), "ms_per_launch": round(1e3 * dtb / args.batched_steps, 2),
                           "images_per_launch": B * 10, "multiple_of_plain": round(imgs / value, 2),
                           "max_abs_err_vs_fp64": errb}
+        sbs = family_stats(P, stepb, 1)
+        res["batched"]["kernel_families"] = family_table(sbs, 1)
+        res["batched"]["roofline"] = roofline_entry(sbs)
         print(f"[bench] batched: {imgs:.1f} img/s ({imgs / value:.1f}x plain), max |err| {errb:.2e}",
               file=sys.stderr, flush=True)
 

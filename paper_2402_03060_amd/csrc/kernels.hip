@@ -21,6 +21,33 @@ __device__ __forceinline__ u32 auto_perm(u32 k, u32 g, int log_n)
     return brev_bits((e - 1u) >> 1, log_n);
 }
 
+// Consecutive hardware workgroup ids are dealt to the 8 XCDs in turn (each
+// with its own L2).  For a 1D grid padded to a multiple of 8, hardware id w
+// runs logical workgroup (w mod 8) * (grid / 8) + w / 8, so every XCD holds a
+// contiguous logical range; kernels order their logical index with the
+// dimension whose workgroups share input rows fastest.  Returns -1 for the
+// padding workgroups.
+constexpr int UH_XCDS = 8;
+__device__ __forceinline__ int xcd_logical(int W)
+{
+    const int wp = (int)gridDim.x, w = (int)blockIdx.x;
+    const int L = (w % UH_XCDS) * (wp / UH_XCDS) + w / UH_XCDS;
+    return L < W ? L : -1;
+}
+
+inline unsigned xcd_grid(long W) { return (unsigned)((W + UH_XCDS - 1) / UH_XCDS * UH_XCDS); }
+
+// Key-switch inner products: split the batch into Zb chunks so that a
+// launch has about 8 workgroups per CU; the chunks of one (coefficient
+// chunk, target limb, rotation) share its key rows.
+inline void inner_split(long C, int T, int E, int batch, int* bb, int* zb)
+{
+    int z = 1;
+    while (C * T * E * z < 2048 && z < batch) z *= 2;
+    *bb = (batch + z - 1) / z;
+    *zb = (batch + *bb - 1) / *bb;
+}
+
 __global__ void k_automorphism(u64* __restrict__ out, const u64* __restrict__ in, int log_n, u32 g)
 {
     const int n = 1 << log_n;
@@ -55,12 +82,18 @@ template <int MAXL>
 __global__ void __launch_bounds__(EW_THREADS) k_ks_inner(u64* __restrict__ U, u64* __restrict__ Up,
                                                          const u64* __restrict__ dntt, int d_stride,
                                                          const u64* __restrict__ modup, const u64* __restrict__ key,
-                                                         DevCtx ctx, int nl, int nd, int batch, u32 g)
+                                                         DevCtx ctx, int nl, int nd, int batch, u32 g, int BB, int Zb,
+                                                         int C, int W)
 {
+    const int L = xcd_logical(W);
+    if (L < 0) return;
+    const int zb = L % Zb;
+    const int x = (L / Zb) % C;
+    const int t = L / (Zb * C);  // 0..nl
     const int n = ctx.n;
-    const int k = blockIdx.x * EW_THREADS + threadIdx.x;
+    const int k = x * EW_THREADS + threadIdx.x;
     if (k >= n) return;
-    const int t = blockIdx.y;  // 0..nl
+    const int b_lo = zb * BB, b_hi = min(batch, b_lo + BB);
     const int tm = t == nl ? ctx.p_index : t;
     const int klimb = t == nl ? nd : t;
     const Modulus M = ctx.mod[tm];
@@ -73,7 +106,7 @@ __global__ void __launch_bounds__(EW_THREADS) k_ks_inner(u64* __restrict__ U, u6
             k1[j] = key[(((size_t)j * 2 + 1) * (nd + 1) + klimb) * n + k];
         }
     }
-    for (int b = 0; b < batch; ++b) {
+    for (int b = b_lo; b < b_hi; ++b) {
         u64 a0 = 0, a1 = 0;
 #pragma unroll
         for (int j = 0; j < MAXL; ++j) {
@@ -269,15 +302,18 @@ void launch_ks_inner(const unihenn_ctx* c, u64* U, u64* Up, const u64* dntt, int
     // algorithmic bytes: key limbs (2 nl (nl+1)), digits (nl (nl+1) per ct), output 2 (nl+1) per ct
     double rows = 2.0 * nl * (nl + 1) + (double)batch * (nl * (nl + 1) + 2 * (nl + 1));
     LaunchTimer tm(KF_KS_INNER, 8.0 * c->n * rows, s);
-    dim3 g3 = grid_rows(c->n, nl + 1);
-    if (nl <= 4)
-        k_ks_inner<4><<<g3, EW_THREADS, 0, s>>>(U, Up, dntt, d_stride, modup, key, c->dev, nl, nd, batch, g);
-    else if (nl <= 8)
-        k_ks_inner<8><<<g3, EW_THREADS, 0, s>>>(U, Up, dntt, d_stride, modup, key, c->dev, nl, nd, batch, g);
-    else if (nl <= 12)
-        k_ks_inner<12><<<g3, EW_THREADS, 0, s>>>(U, Up, dntt, d_stride, modup, key, c->dev, nl, nd, batch, g);
-    else
-        k_ks_inner<UH_MAX_MODULI><<<g3, EW_THREADS, 0, s>>>(U, Up, dntt, d_stride, modup, key, c->dev, nl, nd, batch, g);
+    const int C = (c->n + EW_THREADS - 1) / EW_THREADS;
+    int bb, zb;
+    inner_split(C, nl + 1, 1, batch, &bb, &zb);
+    const int W = zb * C * (nl + 1);
+    const unsigned gx = xcd_grid(W);
+#define KSI(M) k_ks_inner<M><<<gx, EW_THREADS, 0, s>>>(U, Up, dntt, d_stride, modup, key, c->dev, nl, nd, batch, g, \
+                                                       bb, zb, C, W)
+    if (nl <= 4) KSI(4);
+    else if (nl <= 8) KSI(8);
+    else if (nl <= 12) KSI(12);
+    else KSI(UH_MAX_MODULI);
+#undef KSI
 }
 
 void launch_lift_last(const unihenn_ctx* c, u64* out, const u64* src, int n_src_rows, int nl, int src_mod,
@@ -379,13 +415,18 @@ __global__ void k_group_gather(u64* __restrict__ dcoef, GroupArgs ga, int nl, in
 template <int MAXL>
 __global__ void __launch_bounds__(EW_THREADS) k_group_inner(u64* __restrict__ U, u64* __restrict__ Up,
                                                             const u64* __restrict__ modup, GroupArgs ga, DevCtx ctx,
-                                                            int nl, int nd, int batch)
+                                                            int nl, int nd, int batch, int BB, int Zb, int C, int W)
 {
+    const int L = xcd_logical(W);
+    if (L < 0) return;
+    const int zb = L % Zb;
+    const int x = (L / Zb) % C;
+    const int t = (L / (Zb * C)) % (nl + 1);  // 0..nl
+    const int e = L / (Zb * C * (nl + 1));
     const int n = ctx.n;
-    const int k = blockIdx.x * EW_THREADS + threadIdx.x;
+    const int k = x * EW_THREADS + threadIdx.x;
     if (k >= n) return;
-    const int t = blockIdx.y;  // 0..nl
-    const int e = blockIdx.z;
+    const int b_lo = zb * BB, b_hi = min(batch, b_lo + BB);
     const int tm = t == nl ? ctx.p_index : t;
     const int klimb = t == nl ? nd : t;
     const Modulus M = ctx.mod[tm];
@@ -402,7 +443,7 @@ __global__ void __launch_bounds__(EW_THREADS) k_group_inner(u64* __restrict__ U,
             k1[j] = key[(((size_t)j * 2 + 1) * (nd + 1) + klimb) * n + k];
         }
     }
-    for (int b = 0; b < batch; ++b) {
+    for (int b = b_lo; b < b_hi; ++b) {
         u64 a0 = 0, a1 = 0;
 #pragma unroll
         for (int j = 0; j < MAXL; ++j) {
@@ -475,15 +516,16 @@ void group_switch(const unihenn_ctx* c, const GroupArgs& ga, int B, int nl, bool
     {
         double rows = (double)E * 2.0 * nl * (nl + 1) + (double)E * B * (nl * (nl + 1) + 2 * (nl + 1));
         LaunchTimer tm(KF_KS_INNER, 8.0 * c->n * rows, s);
-        dim3 g3(gx, nl + 1, E);
-        if (nl <= 4)
-            k_group_inner<4><<<g3, EW_THREADS, 0, s>>>(U, Up, modup, ga, c->dev, nl, c->n_data, B);
-        else if (nl <= 8)
-            k_group_inner<8><<<g3, EW_THREADS, 0, s>>>(U, Up, modup, ga, c->dev, nl, c->n_data, B);
-        else if (nl <= 12)
-            k_group_inner<12><<<g3, EW_THREADS, 0, s>>>(U, Up, modup, ga, c->dev, nl, c->n_data, B);
-        else
-            k_group_inner<UH_MAX_MODULI><<<g3, EW_THREADS, 0, s>>>(U, Up, modup, ga, c->dev, nl, c->n_data, B);
+        int bb, zb;
+        inner_split((long)gx, nl + 1, E, B, &bb, &zb);
+        const int W = zb * (int)gx * (nl + 1) * E;
+        const unsigned gw = xcd_grid(W);
+#define GI(M) k_group_inner<M><<<gw, EW_THREADS, 0, s>>>(U, Up, modup, ga, c->dev, nl, c->n_data, B, bb, zb, (int)gx, W)
+        if (nl <= 4) GI(4);
+        else if (nl <= 8) GI(8);
+        else if (nl <= 12) GI(12);
+        else GI(UH_MAX_MODULI);
+#undef GI
     }
     if (c0_only) {
         LaunchTimer tm(KF_AUTO, 16.0 * c->n * E * B * nl, s);
@@ -508,24 +550,42 @@ void group_auto_both(const unihenn_ctx* c, const GroupArgs& ga, int B, int nl, u
 }
 
 // ------------------------------------------------------------------ multi-output MAC
+// acc[o][b] (+)= sum_t pt(o, t) (*) ct[t][b] for every coefficient k and limb i:
+// per (i, k) a small product of an n_out x n_terms plaintext matrix and an
+// n_terms x 2B ciphertext matrix.  A thread owns OPT outputs x BCH batch
+// entries (2 OPT BCH accumulators) of one (i, k); the output groups g and
+// batch chunks z that share a (k-chunk, limb) read the same ciphertext rows
+// (across g) and the same plaintext rows (across z).
+//
+// Workgroup numbering is XCD-aware: consecutive hardware workgroup ids go to
+// the 8 XCDs in turn, so hardware id w runs logical workgroup
+// (w mod 8) * (W / 8) + w / 8.  Each XCD then holds a contiguous logical range
+// in which (g, z) vary fastest, and the rows shared across g and z are
+// re-read from that XCD's L2 rather than from HBM.
 namespace {
-template <int BCH>
+template <int OPT, int BCH>
 __global__ void __launch_bounds__(EW_THREADS) k_mac_multi(MacMulti m, int n_out, int n_terms, DevCtx ctx, int nl,
-                                                          int batch, int accumulate)
+                                                          int batch, int accumulate, int G, int Z, int C, int W)
 {
+    const int L = xcd_logical(W);
+    if (L < 0) return;
+    const int g = L % G;
+    const int z = (L / G) % Z;
+    const int x = (L / (G * Z)) % C;
+    const int i = L / (G * Z * C);
     const int n = ctx.n;
-    const int k = blockIdx.x * EW_THREADS + threadIdx.x;
+    const int k = x * EW_THREADS + threadIdx.x;
     if (k >= n) return;
-    const int i = blockIdx.y;
-    const int b0 = blockIdx.z * BCH;
+    const int o0 = g * OPT, b0 = z * BCH;
     const Modulus M = ctx.mod[i];
-    u64 a[UH_MACM_MAX_OUT][2 * BCH];
+    u64 a[OPT][2 * BCH];
 #pragma unroll
-    for (int o = 0; o < UH_MACM_MAX_OUT; ++o)
+    for (int o = 0; o < OPT; ++o)
 #pragma unroll
         for (int u = 0; u < 2 * BCH; ++u) {
             const int b = b0 + u / 2, c = u & 1;
-            a[o][u] = (accumulate && o < n_out && b < batch) ? m.acc[o][(((size_t)b * 2 + c) * nl + i) * n + k] : 0;
+            a[o][u] = (accumulate && o0 + o < n_out && b < batch)
+                          ? m.acc[o0 + o][(((size_t)b * 2 + c) * nl + i) * n + k] : 0;
         }
     const size_t row = (size_t)nl * n;
     for (int t = 0; t < n_terms; ++t) {
@@ -537,23 +597,45 @@ __global__ void __launch_bounds__(EW_THREADS) k_mac_multi(MacMulti m, int n_out,
         }
         const u64* p0 = m.pt_base + (size_t)(m.t_off + t) * row + (size_t)i * n + k;
 #pragma unroll
-        for (int o = 0; o < UH_MACM_MAX_OUT; ++o) {
-            if (o < n_out) {
-                const u64 p = p0[(size_t)o * m.o_stride * row];
+        for (int o = 0; o < OPT; ++o) {
+            if (o0 + o < n_out) {
+                const u64 p = p0[(size_t)(o0 + o) * m.o_stride * row];
 #pragma unroll
                 for (int u = 0; u < 2 * BCH; ++u) a[o][u] = add_mod(a[o][u], mont_mul(p, v[u], M.q, M.qinv_neg), M.q);
             }
         }
     }
 #pragma unroll
-    for (int o = 0; o < UH_MACM_MAX_OUT; ++o)
+    for (int o = 0; o < OPT; ++o)
 #pragma unroll
         for (int u = 0; u < 2 * BCH; ++u) {
             const int b = b0 + u / 2, c = u & 1;
-            if (o < n_out && b < batch) m.acc[o][(((size_t)b * 2 + c) * nl + i) * n + k] = a[o][u];
+            if (o0 + o < n_out && b < batch) m.acc[o0 + o][(((size_t)b * 2 + c) * nl + i) * n + k] = a[o][u];
         }
 }
+
+template <int OPT, int BCH>
+void launch_mm(const MacMulti& m, int n_out, int n_terms, DevCtx dev, int nl, int batch, int accumulate, int G,
+               int Z, int C, hipStream_t s)
+{
+    const int W = G * Z * C * nl;
+    k_mac_multi<OPT, BCH><<<xcd_grid(W), EW_THREADS, 0, s>>>(m, n_out, n_terms, dev, nl, batch, accumulate, G, Z, C, W);
+}
 }  // namespace
+
+// Outputs per thread and batch entries per thread: at most 32 accumulators,
+// and enough workgroups (about 8 per CU) to keep the memory system busy.
+void mac_multi_shape(int n_out, int nl, int batch, int n, int* opt, int* bch)
+{
+    const int b = batch >= 4 ? 4 : (batch >= 2 ? 2 : 1);
+    int o = 16 / b;
+    const long C = (n + EW_THREADS - 1) / EW_THREADS;
+    const long Z = (batch + b - 1) / b;
+    while (o > 1 && (long)((n_out + o - 1) / o) * Z * C * nl < 2048) o /= 2;
+    while (o > 1 && o / 2 >= n_out) o /= 2;
+    *opt = o;
+    *bch = b;
+}
 
 void launch_mac_multi(const unihenn_ctx* c, const MacMulti& m, int n_out, int n_terms, int nl, int batch,
                       int accumulate, hipStream_t s)
@@ -562,13 +644,25 @@ void launch_mac_multi(const unihenn_ctx* c, const MacMulti& m, int n_out, int n_
     double rows = (double)n_terms * batch * 2 * nl + (double)n_out * n_terms * nl +
                   (1.0 + accumulate) * n_out * batch * 2 * nl;
     LaunchTimer tm(KF_MAC, 8.0 * c->n * rows, s);
-    if (batch >= 2) {
-        dim3 g3((c->n + EW_THREADS - 1) / EW_THREADS, nl, (batch + 1) / 2);
-        k_mac_multi<2><<<g3, EW_THREADS, 0, s>>>(m, n_out, n_terms, c->dev, nl, batch, accumulate);
-    } else {
-        dim3 g3((c->n + EW_THREADS - 1) / EW_THREADS, nl, batch);
-        k_mac_multi<1><<<g3, EW_THREADS, 0, s>>>(m, n_out, n_terms, c->dev, nl, batch, accumulate);
+    int opt, bch;
+    mac_multi_shape(n_out, nl, batch, c->n, &opt, &bch);
+    const int G = (n_out + opt - 1) / opt, Z = (batch + bch - 1) / bch, C = (c->n + EW_THREADS - 1) / EW_THREADS;
+#define MM(O, B) launch_mm<O, B>(m, n_out, n_terms, c->dev, nl, batch, accumulate, G, Z, C, s)
+    switch (bch * 100 + opt) {
+    case 101: MM(1, 1); break;
+    case 102: MM(2, 1); break;
+    case 104: MM(4, 1); break;
+    case 108: MM(8, 1); break;
+    case 116: MM(16, 1); break;
+    case 201: MM(1, 2); break;
+    case 202: MM(2, 2); break;
+    case 204: MM(4, 2); break;
+    case 208: MM(8, 2); break;
+    case 401: MM(1, 4); break;
+    case 402: MM(2, 4); break;
+    default: MM(4, 4); break;
     }
+#undef MM
 }
 
 // ------------------------------------------------------------------ grouped elementwise steps

@@ -1090,11 +1090,9 @@ struct Exec {
 
     int run(size_t begin, size_t end)
     {
-        const size_t rn = (size_t)c->n;
         for (size_t si = begin; si < end; ++si) {
             const Step& st = net->steps[si];
             const int nl = net->regs[st.dst].nl;
-            KsWs w = ks_ws_carve(net->ws, nl, B, c->n);
             switch (st.kind) {
             case ST_DROP:
                 launch_gather_rows(c, reg(st.dst), ext_in, B * 2 * nl, nl, ext_in_limbs, 0, s);

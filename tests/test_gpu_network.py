@@ -69,12 +69,14 @@ def test_lenet1_small_ring_bit_exact():
     _run_parity(cfg)
 
 
-def test_lenet1_packed_batch_bit_exact():
-    """Two images per ciphertext at stride 784 and two ciphertexts per launch."""
+@pytest.mark.parametrize("n_cts", [2, 5])
+def test_lenet1_packed_batch_bit_exact(n_cts):
+    """Two images per ciphertext at stride 784 and several ciphertexts per
+    launch (5: a full batch chunk of 4 plus a ragged one)."""
     cfg = W.config("lenet1_batched")
     cfg["log_n"] = 12
     cfg["samples_per_ct"] = 2
-    _run_parity(cfg, n_cts=2)
+    _run_parity(cfg, n_cts=n_cts)
 
 
 def test_cnn1d_small_ring_bit_exact():
@@ -237,3 +239,42 @@ def test_graph_cache_several_shapes():
         for k in range(len(got)):
             for i, src in enumerate(perm):
                 assert np.array_equal(got[k][i], eager[k][src]), (rep, b, k, i)
+
+
+def _digest(arrays) -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for a in arrays:
+        h.update(np.ascontiguousarray(a, dtype=np.uint64).tobytes())
+    return h.hexdigest()
+
+
+def test_lenet1_full_size_golden():
+    """Full-size LeNet-1 (N = 2^14, 8 limbs, 81 rotation keys + relin) on
+    oracle keys and an oracle ciphertext: the GPU outputs hash to the digest
+    the oracle wrote (tests/golden/make_lenet1_golden.py), in plain graph
+    replay and hoisted modes."""
+    import json
+    import os
+    import paper_2402_03060_amd as P
+    with open(os.path.join(os.path.dirname(__file__), "golden", "lenet1_full.json")) as f:
+        rec = json.load(f)
+    cfg = W.config("lenet1")
+    sess = OracleSession(cfg, key_seed=rec["key_seed"])
+    onet = build_net(cfg, sess.ck.slots)
+    assert onet.rotation_set() == rec["rotations"]
+    sess.ensure_keys(onet.rotation_set())
+    assert _digest([sess.key_coeff[r] for r in sorted(sess.key_coeff)] + [sess.rlk_coeff]) == rec["keys_sha256"]
+    xs = W.gen_inputs(cfg["input"], 1)
+    ct = sess.ck.encrypt(onet.input_vector(xs), rec["encrypt_seed"])
+    assert _digest([ct.data]) == rec["input_sha256"]
+    ctx = _ctx(P, cfg)
+    gnet = _gpu_net(P, ctx, cfg, sess, onet)
+    gin = ctx.import_ct(ct.data, ct.scale)
+    for mode in (P.EVAL_PLAIN | P.EVAL_GRAPH, P.EVAL_HOISTED):
+        gnet.set_mode(mode)
+        outs = gnet.eval(gin)
+        assert [o.scale for o in outs] == rec["output_scales"]
+        got = [ctx.export_ct(o)[0] for o in outs]
+        assert [g.shape[1] for g in got] == rec["output_limbs"]
+        assert _digest(got) == rec["outputs_sha256"], mode

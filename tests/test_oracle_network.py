@@ -155,3 +155,21 @@ def test_encrypted_lenet1_small_ring():
     assert ev.count.rescale == 57
     got = decrypt_outputs(sess, net, outs)
     assert np.abs(got - reference_outputs(net, xs)).max() < 1e-3
+
+
+@pytest.mark.slow
+def test_lenet1_full_size_golden_is_current():
+    """The oracle still produces the committed full-size LeNet-1 digests
+    (keys, input, outputs), so the GPU golden test compares against the
+    oracle as it stands."""
+    import importlib.util
+    import json
+    import os
+    here = os.path.join(os.path.dirname(__file__), "golden")
+    with open(os.path.join(here, "lenet1_full.json")) as f:
+        rec = json.load(f)
+    spec = importlib.util.spec_from_file_location("make_lenet1_golden", os.path.join(here, "make_lenet1_golden.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    assert json.loads(json.dumps(mod.compute())) == rec
+    assert rec["max_abs_err_vs_fp64"] < 1e-3
