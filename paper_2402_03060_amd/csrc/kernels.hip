@@ -97,6 +97,7 @@ __global__ void __launch_bounds__(EW_THREADS) k_ks_inner(u64* __restrict__ U, u6
     const int tm = t == nl ? ctx.p_index : t;
     const int klimb = t == nl ? nd : t;
     const Modulus M = ctx.mod[tm];
+    const int period = wide_period(M.ratio);
     const u32 src = g == 1 ? (u32)k : auto_perm((u32)k, g, ctx.log_n);
     u64 k0[MAXL], k1[MAXL];
 #pragma unroll
@@ -107,7 +108,10 @@ __global__ void __launch_bounds__(EW_THREADS) k_ks_inner(u64* __restrict__ U, u6
         }
     }
     for (int b = b_lo; b < b_hi; ++b) {
-        u64 a0 = 0, a1 = 0;
+        WideAcc a0, a1;
+        wide_init(a0, 0);
+        wide_init(a1, 0);
+        int since = 0;
 #pragma unroll
         for (int j = 0; j < MAXL; ++j) {
             if (j < nl) {
@@ -118,16 +122,22 @@ __global__ void __launch_bounds__(EW_THREADS) k_ks_inner(u64* __restrict__ U, u6
                     const int s = t < j ? t : t - 1;
                     d = modup[(((size_t)b * nl + j) * nl + s) * n + src];
                 }
-                a0 = add_mod(a0, mont_mul(d, k0[j], M.q, M.qinv_neg), M.q);
-                a1 = add_mod(a1, mont_mul(d, k1[j], M.q, M.qinv_neg), M.q);
+                wide_mac(a0, d, k0[j]);
+                wide_mac(a1, d, k1[j]);
+                if (++since == period) {
+                    wide_fold(a0, M.q, M.qinv_neg);
+                    wide_fold(a1, M.q, M.qinv_neg);
+                    since = 0;
+                }
             }
         }
+        const u64 r0 = wide_redc(a0, M.q, M.qinv_neg), r1 = wide_redc(a1, M.q, M.qinv_neg);
         if (t < nl) {
-            U[(((size_t)b * 2 + 0) * nl + t) * n + k] = a0;
-            U[(((size_t)b * 2 + 1) * nl + t) * n + k] = a1;
+            U[(((size_t)b * 2 + 0) * nl + t) * n + k] = r0;
+            U[(((size_t)b * 2 + 1) * nl + t) * n + k] = r1;
         } else {
-            Up[((size_t)b * 2 + 0) * n + k] = a0;
-            Up[((size_t)b * 2 + 1) * n + k] = a1;
+            Up[((size_t)b * 2 + 0) * n + k] = r0;
+            Up[((size_t)b * 2 + 1) * n + k] = r1;
         }
     }
 }
@@ -188,32 +198,33 @@ __global__ void __launch_bounds__(EW_THREADS) k_mac(u64* __restrict__ acc, MacTe
     const int i = blockIdx.y;
     const int b0 = blockIdx.z * BCH;
     const Modulus M = ctx.mod[i];
-    u64 a[2 * BCH];
+    const int period = wide_period(M.ratio);
+    WideAcc a[2 * BCH];
 #pragma unroll
-    for (int u = 0; u < 2 * BCH; ++u) a[u] = 0;
-    if (accumulate) {
-#pragma unroll
-        for (int u = 0; u < 2 * BCH; ++u) {
-            const int b = b0 + u / 2, c = u & 1;
-            if (b < batch) a[u] = acc[(((size_t)b * 2 + c) * nl + i) * n + k];
-        }
+    for (int u = 0; u < 2 * BCH; ++u) {
+        const int b = b0 + u / 2, c = u & 1;
+        wide_init(a[u], (accumulate && b < batch) ? acc[(((size_t)b * 2 + c) * nl + i) * n + k] : 0);
     }
+    int since = 0;
     for (int t = 0; t < n_terms; ++t) {
         const u64 p = terms.pt[t][(size_t)i * n + k];
         const u64* ct = terms.ct[t];
 #pragma unroll
         for (int u = 0; u < 2 * BCH; ++u) {
             const int b = b0 + u / 2, c = u & 1;
-            if (b < batch) {
-                const u64 v = ct[(((size_t)b * 2 + c) * nl + i) * n + k];
-                a[u] = add_mod(a[u], mont_mul(p, v, M.q, M.qinv_neg), M.q);
-            }
+            const u64 v = b < batch ? ct[(((size_t)b * 2 + c) * nl + i) * n + k] : 0;
+            wide_mac(a[u], p, v);
+        }
+        if (++since == period) {
+#pragma unroll
+            for (int u = 0; u < 2 * BCH; ++u) wide_fold(a[u], M.q, M.qinv_neg);
+            since = 0;
         }
     }
 #pragma unroll
     for (int u = 0; u < 2 * BCH; ++u) {
         const int b = b0 + u / 2, c = u & 1;
-        if (b < batch) acc[(((size_t)b * 2 + c) * nl + i) * n + k] = a[u];
+        if (b < batch) acc[(((size_t)b * 2 + c) * nl + i) * n + k] = wide_redc(a[u], M.q, M.qinv_neg);
     }
 }
 
@@ -430,6 +441,7 @@ __global__ void __launch_bounds__(EW_THREADS) k_group_inner(u64* __restrict__ U,
     const int tm = t == nl ? ctx.p_index : t;
     const int klimb = t == nl ? nd : t;
     const Modulus M = ctx.mod[tm];
+    const int period = wide_period(M.ratio);
     const u32 g = ga.gin[e];
     const u32 src = g == 1 ? (u32)k : auto_perm((u32)k, g, ctx.log_n);
     const u64* __restrict__ key = ga.key[e];
@@ -444,7 +456,10 @@ __global__ void __launch_bounds__(EW_THREADS) k_group_inner(u64* __restrict__ U,
         }
     }
     for (int b = b_lo; b < b_hi; ++b) {
-        u64 a0 = 0, a1 = 0;
+        WideAcc a0, a1;
+        wide_init(a0, 0);
+        wide_init(a1, 0);
+        int since = 0;
 #pragma unroll
         for (int j = 0; j < MAXL; ++j) {
             if (j < nl) {
@@ -455,17 +470,23 @@ __global__ void __launch_bounds__(EW_THREADS) k_group_inner(u64* __restrict__ U,
                     const int s = t < j ? t : t - 1;
                     d = modup[((((size_t)blk * batch + b) * nl + j) * nl + s) * n + src];
                 }
-                a0 = add_mod(a0, mont_mul(d, k0[j], M.q, M.qinv_neg), M.q);
-                a1 = add_mod(a1, mont_mul(d, k1[j], M.q, M.qinv_neg), M.q);
+                wide_mac(a0, d, k0[j]);
+                wide_mac(a1, d, k1[j]);
+                if (++since == period) {
+                    wide_fold(a0, M.q, M.qinv_neg);
+                    wide_fold(a1, M.q, M.qinv_neg);
+                    since = 0;
+                }
             }
         }
+        const u64 r0 = wide_redc(a0, M.q, M.qinv_neg), r1 = wide_redc(a1, M.q, M.qinv_neg);
         const size_t eb = (size_t)e * batch + b;
         if (t < nl) {
-            U[((eb * 2 + 0) * nl + t) * n + k] = a0;
-            U[((eb * 2 + 1) * nl + t) * n + k] = a1;
+            U[((eb * 2 + 0) * nl + t) * n + k] = r0;
+            U[((eb * 2 + 1) * nl + t) * n + k] = r1;
         } else {
-            Up[(eb * 2 + 0) * n + k] = a0;
-            Up[(eb * 2 + 1) * n + k] = a1;
+            Up[(eb * 2 + 0) * n + k] = r0;
+            Up[(eb * 2 + 1) * n + k] = r1;
         }
     }
 }
@@ -578,16 +599,18 @@ __global__ void __launch_bounds__(EW_THREADS) k_mac_multi(MacMulti m, int n_out,
     if (k >= n) return;
     const int o0 = g * OPT, b0 = z * BCH;
     const Modulus M = ctx.mod[i];
-    u64 a[OPT][2 * BCH];
+    const int period = wide_period(M.ratio);
+    WideAcc a[OPT][2 * BCH];
 #pragma unroll
     for (int o = 0; o < OPT; ++o)
 #pragma unroll
         for (int u = 0; u < 2 * BCH; ++u) {
             const int b = b0 + u / 2, c = u & 1;
-            a[o][u] = (accumulate && o0 + o < n_out && b < batch)
-                          ? m.acc[o0 + o][(((size_t)b * 2 + c) * nl + i) * n + k] : 0;
+            wide_init(a[o][u], (accumulate && o0 + o < n_out && b < batch)
+                                   ? m.acc[o0 + o][(((size_t)b * 2 + c) * nl + i) * n + k] : 0);
         }
     const size_t row = (size_t)nl * n;
+    int since = 0;
     for (int t = 0; t < n_terms; ++t) {
         u64 v[2 * BCH];
 #pragma unroll
@@ -601,8 +624,15 @@ __global__ void __launch_bounds__(EW_THREADS) k_mac_multi(MacMulti m, int n_out,
             if (o0 + o < n_out) {
                 const u64 p = p0[(size_t)(o0 + o) * m.o_stride * row];
 #pragma unroll
-                for (int u = 0; u < 2 * BCH; ++u) a[o][u] = add_mod(a[o][u], mont_mul(p, v[u], M.q, M.qinv_neg), M.q);
+                for (int u = 0; u < 2 * BCH; ++u) wide_mac(a[o][u], p, v[u]);
             }
+        }
+        if (++since == period) {
+#pragma unroll
+            for (int o = 0; o < OPT; ++o)
+#pragma unroll
+                for (int u = 0; u < 2 * BCH; ++u) wide_fold(a[o][u], M.q, M.qinv_neg);
+            since = 0;
         }
     }
 #pragma unroll
@@ -610,7 +640,8 @@ __global__ void __launch_bounds__(EW_THREADS) k_mac_multi(MacMulti m, int n_out,
 #pragma unroll
         for (int u = 0; u < 2 * BCH; ++u) {
             const int b = b0 + u / 2, c = u & 1;
-            if (o0 + o < n_out && b < batch) m.acc[o0 + o][(((size_t)b * 2 + c) * nl + i) * n + k] = a[o][u];
+            if (o0 + o < n_out && b < batch)
+                m.acc[o0 + o][(((size_t)b * 2 + c) * nl + i) * n + k] = wide_redc(a[o][u], M.q, M.qinv_neg);
         }
 }
 
@@ -761,22 +792,29 @@ __global__ void __launch_bounds__(EW_THREADS) k_mac_group(MacGroup m, DevCtx ctx
     const int e = blockIdx.z % m.E;
     const int b0 = (blockIdx.z / m.E) * BCH;
     const Modulus M = ctx.mod[i];
-    u64 a[2 * BCH];
+    const int period = wide_period(M.ratio);
+    WideAcc a[2 * BCH];
 #pragma unroll
-    for (int u = 0; u < 2 * BCH; ++u) a[u] = 0;
+    for (int u = 0; u < 2 * BCH; ++u) wide_init(a[u], 0);
+    int since = 0;
     for (int t = 0; t < m.T; ++t) {
         const u64 p = m.pt[e * m.T + t][(size_t)i * n + k];
         const u64* ct = m.ct[e * m.T + t];
 #pragma unroll
         for (int u = 0; u < 2 * BCH; ++u) {
             const int b = b0 + u / 2, c = u & 1;
-            if (b < batch) a[u] = add_mod(a[u], mont_mul(p, ct[(((size_t)b * 2 + c) * nl + i) * n + k], M.q, M.qinv_neg), M.q);
+            wide_mac(a[u], p, b < batch ? ct[(((size_t)b * 2 + c) * nl + i) * n + k] : 0);
+        }
+        if (++since == period) {
+#pragma unroll
+            for (int u = 0; u < 2 * BCH; ++u) wide_fold(a[u], M.q, M.qinv_neg);
+            since = 0;
         }
     }
 #pragma unroll
     for (int u = 0; u < 2 * BCH; ++u) {
         const int b = b0 + u / 2, c = u & 1;
-        if (b < batch) m.acc[e][(((size_t)b * 2 + c) * nl + i) * n + k] = a[u];
+        if (b < batch) m.acc[e][(((size_t)b * 2 + c) * nl + i) * n + k] = wide_redc(a[u], M.q, M.qinv_neg);
     }
 }
 }  // namespace

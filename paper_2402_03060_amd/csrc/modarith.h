@@ -7,6 +7,8 @@
 //   mont_mul    a * b * 2^-64 mod q (Montgomery, R = 2^64): used where one
 //               operand is stored pre-multiplied by R (keys, plaintexts).
 //   reduce64    x mod q for any 64-bit x, with r = floor(2^64 / q).
+//   WideAcc     a lazily reduced sum of Montgomery products (one reduction
+//               per output instead of one per term).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -91,3 +93,51 @@ __host__ __device__ __forceinline__ u64 centered_lift(u64 x, u64 p_half, u64 p_m
     u64 r = reduce64(x, q, ratio);
     return x > p_half ? sub_mod(r, p_mod_q, q) : r;
 }
+
+// Sum of Montgomery products with one reduction at the end.  The 128-bit
+// value T = hi 2^64 + lo stands for T 2^-64 mod q.  wide_init(v) sets T = v
+// 2^64 (standing for v); wide_mac adds a full product x y (x, y < 2^61), which
+// contributes x y 2^-64 mod q like mont_mul.  T < 2 q 2^64 holds while at most
+// floor(2^64 / q) products (each below q^2) are added after an init or fold,
+// and wide_redc of such a T is (T + m q) / 2^64 < 3q, brought into [0, q).
+struct WideAcc {
+    u64 lo, hi;
+};
+
+__host__ __device__ __forceinline__ void wide_init(WideAcc& a, u64 v)
+{
+    a.lo = 0;
+    a.hi = v;
+}
+
+__host__ __device__ __forceinline__ void wide_mac(WideAcc& a, u64 x, u64 y)
+{
+#ifdef __HIP_DEVICE_COMPILE__
+    const u32 x0 = (u32)x, x1 = (u32)(x >> 32), y0 = (u32)y, y1 = (u32)(y >> 32);
+    const u64 p00 = (u64)x0 * y0;
+    const u64 mid = (u64)x0 * y1 + (u64)x1 * y0 + (p00 >> 32);   // < 2^62 + 2^32 for x, y < 2^61
+    const u64 plo = (mid << 32) | (u32)p00;
+    const u64 phi = (u64)x1 * y1 + (mid >> 32);
+#else
+    const unsigned __int128 p = (unsigned __int128)x * y;
+    const u64 plo = (u64)p, phi = (u64)(p >> 64);
+#endif
+    a.lo += plo;
+    a.hi += phi + (a.lo < plo);
+}
+
+__host__ __device__ __forceinline__ u64 wide_redc(const WideAcc& a, u64 q, u64 qinv_neg)
+{
+    const u64 m = a.lo * qinv_neg;
+    const u64 u = a.hi + umulhi64(m, q) + (a.lo != 0);
+    return csub(csub(u, q), q);
+}
+
+__host__ __device__ __forceinline__ void wide_fold(WideAcc& a, u64 q, u64 qinv_neg)
+{
+    a.hi = wide_redc(a, q, qinv_neg);
+    a.lo = 0;
+}
+
+// products that may be added between folds: floor(2^64 / q), capped
+__host__ __device__ __forceinline__ int wide_period(u64 ratio) { return ratio < 4096 ? (int)ratio : 4096; }
