@@ -39,7 +39,10 @@ def _pack(net_input: dict, xs: np.ndarray, n_slots: int, stride: int) -> np.ndar
     return v
 
 
-def setup(P, W, name: str, batch: int, seed: int = 5):
+TUNING_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2402_03060_amd", "tuning_cache.json")
+
+
+def setup(P, W, name: str, batch: int, seed: int = 5, tune: bool = True, mode: int = 0):
     import torch
     cfg = W.config(name)
     ctx = P.Context(cfg["log_n"], cfg["prime_bits"], cfg["special_bits"], 2.0 ** cfg["log_scale"])
@@ -55,8 +58,10 @@ def setup(P, W, name: str, batch: int, seed: int = 5):
                       ctx.scale, net.in_limbs, mont=False) for b in range(batch)]
     ct = P.encrypt_sk(ctx, sk, torch.stack(pts), seed + 3, ctx.scale)
     torch.cuda.synchronize()
+    net.set_mode(mode)
+    tuning = net.autotune(batch, cache_path=TUNING_CACHE) if tune else net.tuning()
     return {"cfg": cfg, "ctx": ctx, "net": net, "sk": sk, "keys": keys, "rlk": rlk, "ct": ct, "xs": xs,
-            "params": params, "outs": net.alloc_outputs(batch)}
+            "params": params, "outs": net.alloc_outputs(batch), "tuning": tuning}
 
 
 def max_error(P, W, st) -> float:
@@ -280,50 +285,6 @@ def cpu_baseline(W) -> dict:
             "sample": f"one whole LeNet-1 encrypted inference (N=2^14, 8 limbs, 288 rotations), {dt:.1f} s"}
 
 
-SERVE_MODELS = {"conv1": 16, "cnn1d": 8, "cifar_cnn": 4}     # model -> largest batch (ciphertexts)
-SERVE_MIX = {"conv1": 0.5, "cnn1d": 0.3, "cifar_cnn": 0.2}
-SERVE_HBM_BUDGET = 8 << 30                                    # bytes of admitted request ciphertexts
-
-
-def serving_bench(P, W, n_requests: int) -> dict:
-    """Three models of different ring sizes behind the continuous-batching
-    server: saturation throughput (all requests queued at t = 0), then
-    Poisson arrivals (seed 4, mix 50/30/20) at 0.5, 0.8 and 1.0 times it."""
-    import torch
-    from paper_2402_03060_amd.serve import GpuExecutor, Scheduler, poisson_requests, prepare_model, serve
-    print("[bench] setup serving models " + ", ".join(SERVE_MODELS), file=sys.stderr, flush=True)
-    models = {m: prepare_model(P, W, m, b, pool_size=16) for m, b in SERVE_MODELS.items()}
-    ex = GpuExecutor(models)
-    ex.warmup()
-    specs = {m: d["spec"] for m, d in models.items()}
-    payloads = {m: list(range(16)) for m in models}
-    out = {"models": {m: {"log_n": d["cfg"]["log_n"], "max_batch": SERVE_MODELS[m],
-                          "ciphertexts_per_request": 1, "samples_per_ct": d["cfg"]["samples_per_ct"]}
-                      for m, d in models.items()},
-           "mix": SERVE_MIX, "arrival_seed": W.SEED_ARRIVALS, "hbm_budget_bytes": SERVE_HBM_BUDGET,
-           "requests_per_level": n_requests}
-    burst = poisson_requests(SERVE_MIX, 1e9, n_requests, W.SEED_ARRIVALS, payloads)
-    s = serve(Scheduler(specs, SERVE_HBM_BUDGET), ex, burst)
-    torch.cuda.synchronize()
-    sat = s.completed / s.duration
-    out["saturation_requests_per_s"] = round(sat, 2)
-    print(f"[bench] serving saturation {sat:.1f} req/s", file=sys.stderr, flush=True)
-    levels = {}
-    for frac in (0.5, 0.8, 1.0):
-        reqs = poisson_requests(SERVE_MIX, frac * sat, n_requests, W.SEED_ARRIVALS, payloads)
-        s = serve(Scheduler(specs, SERVE_HBM_BUDGET), ex, reqs)
-        torch.cuda.synchronize()
-        summ = s.summary()
-        summ["offered_requests_per_s"] = round(frac * sat, 2)
-        levels[str(frac)] = summ
-        print(f"[bench] serving at {frac:.1f}x: {summ['throughput_per_s']} req/s, p50 {summ['p50_ms']} ms, "
-              f"p99 {summ['p99_ms']} ms", file=sys.stderr, flush=True)
-    out["load_levels"] = levels
-    del ex, models
-    torch.cuda.empty_cache()
-    return out
-
-
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -335,6 +296,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--only-plain", action="store_true", help="skip every extra measurement (for profiling)")
     ap.add_argument("--no-rotation-sweep", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="default launch parameters instead of the tuned ones")
     ap.add_argument("--serve-requests", type=int, default=300,
                     help="requests per load level of the serving measurement (0 skips it)")
     ap.add_argument("--ntt-probe", type=int, default=0, metavar="ROWS",
@@ -384,9 +346,8 @@ def main():
     import workloads as W
 
     print("[bench] setup plain LeNet-1 (N=2^14)", file=sys.stderr, flush=True)
-    st = setup(P, W, "lenet1", batch=1)
+    st = setup(P, W, "lenet1", batch=1, tune=not args.no_tune, mode=P.EVAL_PLAIN | P.EVAL_GRAPH)
     net, ct, outs = st["net"], st["ct"], st["outs"]
-    net.set_mode(P.EVAL_PLAIN | P.EVAL_GRAPH)
     step = lambda: net.eval(ct, outs)
     dt = timed(step, args.steps, args.warmup)
     value = args.steps / dt
@@ -402,6 +363,7 @@ def main():
                                "flatten, FC 192->10", "log_n": 14, "primes": "60 + 7x40 (+60 special)",
                    "scale": "2^40", "images_per_ct": 1, "mode": "plain, replayed as one HIP graph"},
         "max_abs_err_vs_fp64": err,
+        "tuning": st["tuning"],
     }
     if args.only_plain:
         print(json.dumps(res))
@@ -444,7 +406,7 @@ def main():
         print(f"[bench] setup batched LeNet-1 ({B} ciphertexts x 10 images)", file=sys.stderr, flush=True)
         del st, step
         torch.cuda.empty_cache()
-        sb = setup(P, W, "lenet1_batched", batch=B)
+        sb = setup(P, W, "lenet1_batched", batch=B, tune=not args.no_tune, mode=P.EVAL_HOISTED | P.EVAL_GRAPH)
         nb, ctb, outb = sb["net"], sb["ct"], sb["outs"]
         nb.set_mode(P.EVAL_HOISTED | P.EVAL_GRAPH)
         stepb = lambda: nb.eval(ctb, outb)
@@ -453,7 +415,7 @@ def main():
         errb = max_error(P, W, sb)
         res["batched"] = {"images_per_s": round(imgs, 2), "ms_per_launch": round(1e3 * dtb / args.batched_steps, 2),
                           "images_per_launch": B * 10, "multiple_of_plain": round(imgs / value, 2),
-                          "max_abs_err_vs_fp64": errb}
+                          "max_abs_err_vs_fp64": errb, "tuning": sb["tuning"]}
         sbs = family_stats(P, stepb, 1)
         res["batched"]["kernel_families"] = family_table(sbs, 1)
         res["batched"]["roofline"] = roofline_entry(sbs)
@@ -464,7 +426,7 @@ def main():
         del sb, stepb
         torch.cuda.empty_cache()
         print("[bench] setup batched 1D CNN (64 ciphertexts x 8 sequences)", file=sys.stderr, flush=True)
-        sc = setup(P, W, "cnn1d", batch=64)
+        sc = setup(P, W, "cnn1d", batch=64, tune=not args.no_tune, mode=P.EVAL_HOISTED | P.EVAL_GRAPH)
         nc, ctc, outc = sc["net"], sc["ct"], sc["outs"]
         nc.set_mode(P.EVAL_HOISTED | P.EVAL_GRAPH)
         stepc = lambda: nc.eval(ctc, outc)
@@ -473,13 +435,16 @@ def main():
         errc = max_error(P, W, sc)
         res["batched_cnn1d"] = {"sequences_per_s": round(seqs, 2),
                                 "ms_per_launch": round(1e3 * dtc / args.batched_steps, 2),
-                                "sequences_per_launch": 64 * 8, "max_abs_err_vs_fp64": errc}
+                                "sequences_per_launch": 64 * 8, "max_abs_err_vs_fp64": errc,
+                                "tuning": sc["tuning"]}
         print(f"[bench] batched cnn1d: {seqs:.1f} seq/s, max |err| {errc:.2e}", file=sys.stderr, flush=True)
         del sc, stepc
         torch.cuda.empty_cache()
 
     if args.serve_requests:
-        res["serving"] = serving_bench(P, W, args.serve_requests)
+        from paper_2402_03060_amd.serve import serving_benchmark
+        res["serving"] = serving_benchmark(P, W, args.serve_requests, tuning_cache=TUNING_CACHE,
+                                           log=lambda m: print("[bench] " + m, file=sys.stderr, flush=True))
 
     if not args.no_cpu_baseline:
         print("[bench] CPU oracle baseline (one inference)", file=sys.stderr, flush=True)

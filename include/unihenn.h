@@ -253,6 +253,48 @@ int unihenn_eval_network(const unihenn_ctx* ctx, unihenn_net* net, const unihenn
  * n_values (host) receives the number of values per sample. */
 int unihenn_net_output_slots(const unihenn_net* net, uint64_t* positions, uint32_t* n_values);
 
+/* ------------------------------------------------------------ autotuning */
+/* Launch parameters of the batched evaluator.  Every setting computes the
+ * same results bit for bit; only speed changes.
+ *   ntt_split     stages in the NTT column pass (the row pass does the rest)
+ *   ntt_tile_log  LDS tile of the radix-8 NTT passes: 11 or 12 (2^t words)
+ *   mac_min_wg    workgroups a multi-output MAC launch aims for (it trades
+ *                 outputs per thread against parallelism)
+ *   ks_min_wg     workgroups a key-switch inner product aims for (it splits
+ *                 the batch to reach it)
+ *   ks_group      rotations per grouped key-switch launch set (net only)
+ *   ntt_ms, net_ms  timings of the chosen setting (filled by autotune) */
+typedef struct {
+    int32_t ntt_split;
+    int32_t ntt_tile_log;
+    int32_t mac_min_wg;
+    int32_t ks_min_wg;
+    int32_t ks_group;
+    double ntt_ms;
+    double net_ms;
+} unihenn_tuning;
+/* Time candidate settings on the device and keep the fastest: first the NTT
+ * split and tile on a forward + inverse transform of a batch of rows sized
+ * from `batch`; then, when net is non-NULL and its keys are bound, one
+ * coordinate at a time (NTT split and tile, group size, the two workgroup
+ * targets) on whole evaluations of `batch` ciphertexts in the net's mode
+ * (graph replay included when set).  With a non-NULL cache_path the result
+ * is looked up in, and then written to, a JSON file keyed by device, ring,
+ * batch, a fingerprint of the net's plan and its mode (set the mode first);
+ * a hit applies the stored setting without timing.  The chosen setting is
+ * applied to ctx (and net) and returned in *out (may be NULL).  Allocates
+ * scratch buffers, may grow the net's workspace and drops its captured
+ * graphs; must not run concurrently with other calls on ctx or net.
+ * Synchronous. */
+int unihenn_autotune(unihenn_ctx* ctx, unihenn_net* net, uint32_t batch, const char* cache_path,
+                     unihenn_tuning* out, void* stream);
+/* Current setting of ctx (and net, when non-NULL; ks_group is 0 without). */
+int unihenn_tuning_get(const unihenn_ctx* ctx, const unihenn_net* net, unihenn_tuning* out);
+/* Apply a setting; fields <= 0 keep their current value.  Drops the net's
+ * captured graphs.  Errors: EINVAL (split outside 1..log_n-1, tile not 11 or
+ * 12, group above the library limit), ENOMEM. */
+int unihenn_tuning_set(unihenn_ctx* ctx, unihenn_net* net, const unihenn_tuning* t);
+
 /* ---------------------------------------------------------------- client */
 /* A client for benchmarks and examples (the paper's client encrypts and
  * decrypts, Section III; Fig. 1).  Randomness: a counter-based hash of

@@ -42,6 +42,14 @@ class LAYER(C.Structure):
                 ("bias", C.POINTER(C.c_double))]
 
 
+class TUNING(C.Structure):
+    _fields_ = [("ntt_split", C.c_int32), ("ntt_tile_log", C.c_int32), ("mac_min_wg", C.c_int32),
+                ("ks_min_wg", C.c_int32), ("ks_group", C.c_int32), ("ntt_ms", C.c_double), ("net_ms", C.c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class INPUT(C.Structure):
     _fields_ = [("c", C.c_uint32), ("h", C.c_uint32), ("w", C.c_uint32), ("samples", C.c_uint32),
                 ("stride", C.c_uint32)]
@@ -79,6 +87,9 @@ SIGNATURES = {
     "unihenn_conv": (C.c_int, [_vp, _vp, _u32, _P(CT), _u32, _P(CT), _P(_u32), _vp]),
     "unihenn_eval_network": (C.c_int, [_vp, _vp, _P(CT), _P(CT), _vp]),
     "unihenn_net_output_slots": (C.c_int, [_vp, _P(_u64), _P(_u32)]),
+    "unihenn_autotune": (C.c_int, [_vp, _vp, _u32, C.c_char_p, _P(TUNING), _vp]),
+    "unihenn_tuning_get": (C.c_int, [_vp, _vp, _P(TUNING)]),
+    "unihenn_tuning_set": (C.c_int, [_vp, _vp, _P(TUNING)]),
     "unihenn_keygen_secret": (C.c_int, [_vp, _u64, _vp, _vp]),
     "unihenn_gen_switch_key": (C.c_int, [_vp, _vp, _u64, _i32, C.c_int, _vp, _vp]),
     "unihenn_encrypt_sk": (C.c_int, [_vp, _vp, _vp, _u64, _P(CT), _vp]),
@@ -180,6 +191,23 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    # ---- launch parameters ----
+    def tuning(self) -> dict:
+        t = TUNING()
+        _check(lib().unihenn_tuning_get(self.h, None, C.byref(t)))
+        return t.as_dict()
+
+    def set_tuning(self, **kw):
+        t = TUNING(**{k: int(v) for k, v in kw.items()})
+        _check(lib().unihenn_tuning_set(self.h, None, C.byref(t)))
+
+    def autotune(self, batch: int = 1, cache_path: str | None = None) -> dict:
+        """Tune the NTT split and tile for transforms of about `batch` ciphertexts."""
+        t = TUNING()
+        _check(lib().unihenn_autotune(self.h, None, batch, cache_path.encode() if cache_path else None,
+                                      C.byref(t), _stream()))
+        return t.as_dict()
 
     # ---- allocation helpers (torch) ----
     def empty_ct(self, batch: int, n_limbs: int, scale: float = 0.0) -> Ciphertext:
@@ -425,6 +453,25 @@ class Net:
 
     def set_mode(self, mode: int):
         _check(lib().unihenn_net_set_mode(self.h, mode))
+
+    def tuning(self) -> dict:
+        t = TUNING()
+        _check(lib().unihenn_tuning_get(self.ctx.h, self.h, C.byref(t)))
+        return t.as_dict()
+
+    def set_tuning(self, **kw):
+        t = TUNING(**{k: int(v) for k, v in kw.items()})
+        _check(lib().unihenn_tuning_set(self.ctx.h, self.h, C.byref(t)))
+
+    def autotune(self, batch: int | None = None, cache_path: str | None = None) -> dict:
+        """Tune the context's NTT launches and this net's key-switch group size
+        and workgroup targets on whole evaluations of `batch` ciphertexts
+        (default max_batch); with cache_path, reuse or record the result."""
+        t = TUNING()
+        b = self.max_batch if batch is None else batch
+        _check(lib().unihenn_autotune(self.ctx.h, self.h, b, cache_path.encode() if cache_path else None,
+                                      C.byref(t), _stream()))
+        return t.as_dict()
 
     def output_slots(self) -> np.ndarray:
         nv = C.c_uint32()

@@ -45,6 +45,12 @@ struct unihenn_ctx {
     double* d_cos = nullptr;          // cos(pi t / N) as double-double, t < 2N: [2N][2]
     int device = 0;
     DevCtx dev;
+    // launch parameters (defaults, or chosen by unihenn_autotune); every
+    // choice gives the same results bit for bit
+    int ntt_split = 0;                // stages in the column pass (0: log_n / 2)
+    int ntt_tile_log = 11;            // LDS tile of the radix-8 passes: 2^11 or 2^12 words
+    int mac_min_wg = 2048;            // workgroups a multi-output MAC launch aims for
+    int ks_min_wg = 2048;             // workgroups a key-switch inner product aims for
 };
 
 // error reporting (thread-local message)
@@ -109,3 +115,16 @@ struct LaunchTimer {
 };
 void stats_collect();
 bool stats_enabled();
+
+// network hooks for the tuner (network.hip)
+struct unihenn_net;
+int net_ks_group(const unihenn_net* net);
+int net_ks_group_cap(const unihenn_ctx* c, const unihenn_net* net);
+int net_set_ks_group(const unihenn_ctx* c, unihenn_net* net, int e);
+void net_drop_graphs(unihenn_net* net);
+int net_max_batch(const unihenn_net* net);
+int net_in_limbs(const unihenn_net* net);
+int net_n_out(const unihenn_net* net);
+int net_mode(const unihenn_net* net);
+void net_set_mode_raw(unihenn_net* net, int mode);
+uint64_t net_fingerprint(const unihenn_net* net);

@@ -38,12 +38,12 @@ __device__ __forceinline__ int xcd_logical(int W)
 inline unsigned xcd_grid(long W) { return (unsigned)((W + UH_XCDS - 1) / UH_XCDS * UH_XCDS); }
 
 // Key-switch inner products: split the batch into Zb chunks so that a
-// launch has about 8 workgroups per CU; the chunks of one (coefficient
-// chunk, target limb, rotation) share its key rows.
-inline void inner_split(long C, int T, int E, int batch, int* bb, int* zb)
+// launch has about min_wg workgroups (8 per CU by default); the chunks of one
+// (coefficient chunk, target limb, rotation) share its key rows.
+inline void inner_split(long C, int T, int E, int batch, int min_wg, int* bb, int* zb)
 {
     int z = 1;
-    while (C * T * E * z < 2048 && z < batch) z *= 2;
+    while (C * T * E * z < min_wg && z < batch) z *= 2;
     *bb = (batch + z - 1) / z;
     *zb = (batch + *bb - 1) / *bb;
 }
@@ -315,7 +315,7 @@ void launch_ks_inner(const unihenn_ctx* c, u64* U, u64* Up, const u64* dntt, int
     LaunchTimer tm(KF_KS_INNER, 8.0 * c->n * rows, s);
     const int C = (c->n + EW_THREADS - 1) / EW_THREADS;
     int bb, zb;
-    inner_split(C, nl + 1, 1, batch, &bb, &zb);
+    inner_split(C, nl + 1, 1, batch, c->ks_min_wg, &bb, &zb);
     const int W = zb * C * (nl + 1);
     const unsigned gx = xcd_grid(W);
 #define KSI(M) k_ks_inner<M><<<gx, EW_THREADS, 0, s>>>(U, Up, dntt, d_stride, modup, key, c->dev, nl, nd, batch, g, \
@@ -538,7 +538,7 @@ void group_switch(const unihenn_ctx* c, const GroupArgs& ga, int B, int nl, bool
         double rows = (double)E * 2.0 * nl * (nl + 1) + (double)E * B * (nl * (nl + 1) + 2 * (nl + 1));
         LaunchTimer tm(KF_KS_INNER, 8.0 * c->n * rows, s);
         int bb, zb;
-        inner_split((long)gx, nl + 1, E, B, &bb, &zb);
+        inner_split((long)gx, nl + 1, E, B, c->ks_min_wg, &bb, &zb);
         const int W = zb * (int)gx * (nl + 1) * E;
         const unsigned gw = xcd_grid(W);
 #define GI(M) k_group_inner<M><<<gw, EW_THREADS, 0, s>>>(U, Up, modup, ga, c->dev, nl, c->n_data, B, bb, zb, (int)gx, W)
@@ -655,14 +655,15 @@ void launch_mm(const MacMulti& m, int n_out, int n_terms, DevCtx dev, int nl, in
 }  // namespace
 
 // Outputs per thread and batch entries per thread: at most 32 accumulators,
-// and enough workgroups (about 8 per CU) to keep the memory system busy.
-void mac_multi_shape(int n_out, int nl, int batch, int n, int* opt, int* bch)
+// and enough workgroups (min_wg, about 8 per CU by default) to keep the
+// memory system busy.
+void mac_multi_shape(int n_out, int nl, int batch, int n, int min_wg, int* opt, int* bch)
 {
     const int b = batch >= 4 ? 4 : (batch >= 2 ? 2 : 1);
     int o = 16 / b;
     const long C = (n + EW_THREADS - 1) / EW_THREADS;
     const long Z = (batch + b - 1) / b;
-    while (o > 1 && (long)((n_out + o - 1) / o) * Z * C * nl < 2048) o /= 2;
+    while (o > 1 && (long)((n_out + o - 1) / o) * Z * C * nl < min_wg) o /= 2;
     while (o > 1 && o / 2 >= n_out) o /= 2;
     *opt = o;
     *bch = b;
@@ -676,7 +677,7 @@ void launch_mac_multi(const unihenn_ctx* c, const MacMulti& m, int n_out, int n_
                   (1.0 + accumulate) * n_out * batch * 2 * nl;
     LaunchTimer tm(KF_MAC, 8.0 * c->n * rows, s);
     int opt, bch;
-    mac_multi_shape(n_out, nl, batch, c->n, &opt, &bch);
+    mac_multi_shape(n_out, nl, batch, c->n, c->mac_min_wg, &opt, &bch);
     const int G = (n_out + opt - 1) / opt, Z = (batch + bch - 1) / bch, C = (c->n + EW_THREADS - 1) / EW_THREADS;
 #define MM(O, B) launch_mm<O, B>(m, n_out, n_terms, c->dev, nl, batch, accumulate, G, Z, C, s)
     switch (bch * 100 + opt) {

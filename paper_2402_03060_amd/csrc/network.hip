@@ -109,7 +109,9 @@ struct unihenn_net {
     std::vector<size_t> phys_off;
     u64* ws = nullptr;
     int ws_nl = 0;
-    int group_max = 1;       // rotations per grouped key-switch launch set
+    int group_max = 1;       // rotations per grouped key-switch launch set (in use)
+    int group_alloc = 1;     // group size the workspace layout holds
+    size_t ws_words = 0;
     std::map<int, const u64*> keys;
     const u64* rlk = nullptr;
     int mode = UNIHENN_EVAL_PLAIN;
@@ -741,14 +743,35 @@ void schedule_layers(unihenn_net* net)
 
 }  // namespace
 
+// Workspace words for grouped key switching with groups of E rotations (at
+// the widest level and largest batch), single key switches, grouped squares
+// and grouped rescales.
+static size_t net_ws_words(const unihenn_ctx* c, const unihenn_net* net, int E_)
+{
+    const size_t L0 = (size_t)net->ws_nl, Bm = (size_t)net->max_batch, E = (size_t)E_;
+    const size_t group_rows = Bm * (L0 + L0 * L0) + E * Bm * (L0 * L0 + 7 * L0 + 2);
+    const int mb = net->max_batch;
+    const int e_sq = std::max(1, 32 / mb), e_rs = std::max(1, std::min(UH_EW_GROUP_MAX, 64 / mb));
+    size_t ws_rows = std::max(ks_ws_rows(net->ws_nl, mb), group_rows);
+    ws_rows = std::max(ws_rows, group_square_ws_rows(std::min(e_sq, UH_EW_GROUP_MAX), net->ws_nl, mb));
+    ws_rows = std::max(ws_rows, (size_t)e_rs * Bm * 2 * L0);
+    return ws_rows * (size_t)c->n;
+}
+
+static void drop_graphs(unihenn_net* net)
+{
+    if (net->gstream) (void)hipStreamSynchronize(net->gstream);
+    for (auto& g : net->graphs)
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    net->graphs.clear();
+}
+
 // ---------------------------------------------------------------- C ABI
 extern "C" int unihenn_net_destroy(unihenn_net* net)
 {
     if (!net) return UNIHENN_OK;
     // a replay still in flight reads the arenas: let it finish first
-    if (net->gstream) (void)hipStreamSynchronize(net->gstream);
-    for (auto& g : net->graphs)
-        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    drop_graphs(net);
     if (net->ev_in) (void)hipEventDestroy(net->ev_in);
     if (net->ev_out) (void)hipEventDestroy(net->ev_out);
     if (net->gstream) (void)hipStreamDestroy(net->gstream);
@@ -876,17 +899,11 @@ extern "C" int unihenn_net_create(const unihenn_ctx* c, const unihenn_input* in,
         reg_words += (size_t)max_batch * 2 * nl * c->n;
     }
     net->ws_nl = net->in_limbs;
-    net->group_max = std::max(1, std::min(UH_GROUP_MAX, 32 / (int)max_batch));
-    const size_t L0 = (size_t)net->ws_nl, Bm = max_batch, E = (size_t)net->group_max;
-    const size_t group_rows = Bm * (L0 + L0 * L0) + E * Bm * (L0 * L0 + 7 * L0 + 2);
-    const int e_sq = std::max(1, 32 / (int)max_batch), e_rs = std::max(1, std::min(UH_EW_GROUP_MAX, 64 / (int)max_batch));
-    size_t ws_rows = std::max(ks_ws_rows(net->ws_nl, (int)max_batch), group_rows);
-    ws_rows = std::max(ws_rows, group_square_ws_rows(std::min(e_sq, UH_EW_GROUP_MAX), net->ws_nl, (int)max_batch));
-    ws_rows = std::max(ws_rows, (size_t)e_rs * max_batch * 2 * net->ws_nl);
-    size_t ws_words = ws_rows * c->n;
+    net->group_max = net->group_alloc = std::max(1, std::min(UH_GROUP_MAX, 32 / (int)max_batch));
+    net->ws_words = net_ws_words(c, net, net->group_alloc);
     if (hipMalloc(&net->pt_arena, sizeof(u64) * std::max<size_t>(net->pt_words, 1)) != hipSuccess ||
         hipMalloc(&net->reg_arena, sizeof(u64) * std::max<size_t>(reg_words, 1)) != hipSuccess ||
-        hipMalloc(&net->ws, sizeof(u64) * ws_words) != hipSuccess) {
+        hipMalloc(&net->ws, sizeof(u64) * net->ws_words) != hipSuccess) {
         unihenn_net_destroy(net);
         return uh_fail(UNIHENN_ENOMEM, "network buffers");
     }
@@ -988,7 +1005,7 @@ struct Exec {
     GroupWs carve() const
     {
         const size_t rn = (size_t)c->n, L0 = (size_t)net->ws_nl, Bm = (size_t)net->max_batch,
-                     E = (size_t)net->group_max;
+                     E = (size_t)net->group_alloc;
         GroupWs w;
         u64* p = net->ws;
         w.pdcoef = p; p += Bm * L0 * rn;
@@ -1352,4 +1369,68 @@ extern "C" int unihenn_conv(const unihenn_ctx* c, unihenn_net* net, uint32_t lay
     }
     if (interval_out) *interval_out = (uint32_t)L.interval_out;
     return UNIHENN_OK;
+}
+
+// ---------------------------------------------------------------- tuner hooks
+int net_ks_group(const unihenn_net* net) { return net->group_max; }
+
+// Largest group size worth trying: the library cap, limited so that the
+// grouped workspace stays within 16 GiB.
+int net_ks_group_cap(const unihenn_ctx* c, const unihenn_net* net)
+{
+    int e = 1;
+    while (e * 2 <= UH_GROUP_MAX && sizeof(u64) * net_ws_words(c, net, e * 2) <= (16ull << 30)) e *= 2;
+    return e;
+}
+
+// Use groups of e rotations; grows the workspace when its layout holds fewer.
+// Captured graphs are dropped (they hold launch shapes and buffer addresses).
+int net_set_ks_group(const unihenn_ctx* c, unihenn_net* net, int e)
+{
+    if (e < 1 || e > UH_GROUP_MAX) return uh_fail(UNIHENN_EINVAL, "group size out of range");
+    drop_graphs(net);
+    if (e > net->group_alloc) {
+        const size_t words = net_ws_words(c, net, e);
+        u64* ws = nullptr;
+        UH_CHECK_HIP(hipDeviceSynchronize());
+        if (hipMalloc(&ws, sizeof(u64) * words) != hipSuccess) return uh_fail(UNIHENN_ENOMEM, "grouped workspace");
+        (void)hipFree(net->ws);
+        net->ws = ws;
+        net->ws_words = words;
+        net->group_alloc = e;
+    }
+    net->group_max = e;
+    return UNIHENN_OK;
+}
+
+void net_drop_graphs(unihenn_net* net) { drop_graphs(net); }
+
+int net_max_batch(const unihenn_net* net) { return net->max_batch; }
+int net_in_limbs(const unihenn_net* net) { return net->in_limbs; }
+int net_n_out(const unihenn_net* net) { return (int)net->out_regs.size(); }
+int net_mode(const unihenn_net* net) { return net->mode; }
+void net_set_mode_raw(unihenn_net* net, int mode) { net->mode = mode; }
+
+// FNV-1a over the plan: step kinds, levels, term / output / source counts
+uint64_t net_fingerprint(const unihenn_net* net)
+{
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](uint64_t v) {
+        for (int i = 0; i < 8; ++i) {
+            h ^= (v >> (8 * i)) & 0xff;
+            h *= 1099511628211ull;
+        }
+    };
+    mix(net->steps.size());
+    mix((uint64_t)net->in_limbs);
+    mix((uint64_t)net->max_batch);
+    for (const Step& st : net->steps) {
+        mix((uint64_t)st.kind);
+        mix((uint64_t)net->regs[st.dst].nl);
+        mix(st.terms.size());
+        mix(st.outs.size());
+        mix(st.srcs.size());
+        mix((uint64_t)(int64_t)st.rot);
+    }
+    return h;
 }

@@ -12,8 +12,9 @@
 //                N / 2^L1; a tile holds COLS consecutive columns so every
 //                global row access is COLS contiguous words;
 //   row pass     stages [L1, log N): contiguous 2^(log N - L1)-point blocks.
-// Each tile is TILE words (16 KiB) of LDS; 256 threads, one butterfly per
-// thread per four-butterfly slice of a stage.
+// The generic kernels (sub-transforms below 8 points) use tiles of TILE
+// words (16 KiB) of LDS and 256 threads; the radix-8 kernels take the tile
+// size (2^11 or 2^12 words, with 2^8 or 2^9 threads) as a launch parameter.
 #include "internal.h"
 
 namespace {
@@ -164,15 +165,16 @@ __global__ void __launch_bounds__(NTT_THREADS) k_ntt_inv(u64* __restrict__ data,
 // so each distinct twiddle is loaded once per round.  The contiguous pass
 // pads its LDS tile by one word per eight (u + u/8) so that the sixteen
 // lanes serving one sub-transform hit distinct banks in every round.
-template <int LOG_R, bool STRIDED, bool INV, bool LAST>
-__global__ void __launch_bounds__(NTT_THREADS) k_ntt_r8(u64* __restrict__ data, DevCtx ctx, RowMap map, int log_cols,
-                                                        int sigma0)
+template <int LOG_R, int TILE_LOG, bool STRIDED, bool INV, bool LAST>
+__global__ void __launch_bounds__((1 << TILE_LOG) / 8) k_ntt_r8(u64* __restrict__ data, DevCtx ctx, RowMap map,
+                                                                int log_cols, int sigma0)
 {
     constexpr int LOG_G = LOG_R - 3;  // threads per sub-transform: 2^LOG_G
     constexpr int ROUNDS = (LOG_R + 2) / 3;
     constexpr int R = 1 << LOG_R;
     constexpr int RP = R + R / 8;     // padded sub-transform stride (contiguous pass)
-    __shared__ u64 s[TILE + TILE / 8];
+    constexpr int T = 1 << TILE_LOG;
+    __shared__ u64 s[T + T / 8];
     const int n = ctx.n, log_n = ctx.log_n;
     const int row = blockIdx.y;
     const int mi = rowmap_mod(map, row);
@@ -282,16 +284,16 @@ __global__ void __launch_bounds__(NTT_THREADS) k_ntt_r8(u64* __restrict__ data, 
 #undef LIDX
 }
 
-template <int LOG_R>
+template <int LOG_R, int TILE_LOG>
 void launch_r8(u64* data, const DevCtx& dev, const RowMap& map, int n_rows, int log_n, int sigma0, bool strided,
                bool inv, bool last, hipStream_t st)
 {
     const int avail_log = log_n - LOG_R;                 // log2 of sub-transforms per row
-    int log_cols = 11 - LOG_R;                            // TILE = 2^11 words
+    int log_cols = TILE_LOG - LOG_R;                      // tile of 2^TILE_LOG words
     if (log_cols > avail_log) log_cols = avail_log;
     const int threads = 1 << (LOG_R - 3 + log_cols);
     dim3 grid(1 << (avail_log - log_cols), n_rows);
-#define L8(S, I, Z) k_ntt_r8<LOG_R, S, I, Z><<<grid, threads, 0, st>>>(data, dev, map, log_cols, sigma0)
+#define L8(S, I, Z) k_ntt_r8<LOG_R, TILE_LOG, S, I, Z><<<grid, threads, 0, st>>>(data, dev, map, log_cols, sigma0)
     if (strided) {
         if (!inv) { if (last) L8(true, false, true); else L8(true, false, false); }
         else { if (last) L8(true, true, true); else L8(true, true, false); }
@@ -302,25 +304,27 @@ void launch_r8(u64* data, const DevCtx& dev, const RowMap& map, int n_rows, int 
 #undef L8
 }
 
-// dispatch on the sub-transform size; sizes below 8 points use the generic kernel
+// dispatch on the sub-transform size and tile; sizes below 8 points use the
+// generic kernel
 bool launch_pass_r8(u64* data, const DevCtx& dev, const RowMap& map, int n_rows, int log_n, int log_r, int sigma0,
-                    bool strided, bool inv, bool last, hipStream_t st)
+                    bool strided, bool inv, bool last, int tile_log, hipStream_t st)
 {
+#define LR(K)                                                                                      \
+    case K:                                                                                        \
+        if (tile_log == 12) launch_r8<K, 12>(data, dev, map, n_rows, log_n, sigma0, strided, inv, last, st); \
+        else launch_r8<K, 11>(data, dev, map, n_rows, log_n, sigma0, strided, inv, last, st);      \
+        return true;
     switch (log_r) {
-    case 3: launch_r8<3>(data, dev, map, n_rows, log_n, sigma0, strided, inv, last, st); return true;
-    case 4: launch_r8<4>(data, dev, map, n_rows, log_n, sigma0, strided, inv, last, st); return true;
-    case 5: launch_r8<5>(data, dev, map, n_rows, log_n, sigma0, strided, inv, last, st); return true;
-    case 6: launch_r8<6>(data, dev, map, n_rows, log_n, sigma0, strided, inv, last, st); return true;
-    case 7: launch_r8<7>(data, dev, map, n_rows, log_n, sigma0, strided, inv, last, st); return true;
-    case 8: launch_r8<8>(data, dev, map, n_rows, log_n, sigma0, strided, inv, last, st); return true;
+    LR(3) LR(4) LR(5) LR(6) LR(7) LR(8)
     default: return false;
     }
+#undef LR
 }
 
-void split(int log_n, int* l1, int* l2)
+void split(const unihenn_ctx* c, int* l1, int* l2)
 {
-    *l1 = log_n / 2;
-    *l2 = log_n - *l1;
+    *l1 = c->ntt_split > 0 && c->ntt_split < c->log_n ? c->ntt_split : c->log_n / 2;
+    *l2 = c->log_n - *l1;
 }
 
 int tile_cols(int log_r, int log_n)
@@ -337,11 +341,11 @@ void launch_ntt_fwd(const unihenn_ctx* c, u64* data, int n_rows, const RowMap& m
 {
     if (n_rows <= 0) return;
     int l1, l2;
-    split(c->log_n, &l1, &l2);
+    split(c, &l1, &l2);
     const double bytes = 16.0 * c->n * n_rows, half = 0.5 * c->n * n_rows;
     {
         LaunchTimer tm(KF_NTT_FWD_COL, bytes, st, half * l1);
-        if (!launch_pass_r8(data, c->dev, map, n_rows, c->log_n, l1, 0, true, false, false, st)) {
+        if (!launch_pass_r8(data, c->dev, map, n_rows, c->log_n, l1, 0, true, false, false, c->ntt_tile_log, st)) {
             int cols1 = tile_cols(l1, c->log_n);
             dim3 g1((1 << (c->log_n - l1)) / cols1, n_rows);
             k_ntt_fwd<true, false><<<g1, NTT_THREADS, 0, st>>>(data, c->dev, map, l1, cols1, 0);
@@ -349,7 +353,7 @@ void launch_ntt_fwd(const unihenn_ctx* c, u64* data, int n_rows, const RowMap& m
     }
     {
         LaunchTimer tm(KF_NTT_FWD_ROW, bytes, st, half * l2);
-        if (!launch_pass_r8(data, c->dev, map, n_rows, c->log_n, l2, l1, false, false, true, st)) {
+        if (!launch_pass_r8(data, c->dev, map, n_rows, c->log_n, l2, l1, false, false, true, c->ntt_tile_log, st)) {
             int cols2 = tile_cols(l2, c->log_n);
             dim3 g2((1 << (c->log_n - l2)) / cols2, n_rows);
             k_ntt_fwd<false, true><<<g2, NTT_THREADS, 0, st>>>(data, c->dev, map, l2, cols2, l1);
@@ -361,11 +365,11 @@ void launch_ntt_inv(const unihenn_ctx* c, u64* data, int n_rows, const RowMap& m
 {
     if (n_rows <= 0) return;
     int l1, l2;
-    split(c->log_n, &l1, &l2);
+    split(c, &l1, &l2);
     const double bytes = 16.0 * c->n * n_rows, half = 0.5 * c->n * n_rows;
     {
         LaunchTimer tm(KF_NTT_INV_ROW, bytes, st, half * l2);
-        if (!launch_pass_r8(data, c->dev, map, n_rows, c->log_n, l2, l1, false, true, false, st)) {
+        if (!launch_pass_r8(data, c->dev, map, n_rows, c->log_n, l2, l1, false, true, false, c->ntt_tile_log, st)) {
             int cols2 = tile_cols(l2, c->log_n);
             dim3 g2((1 << (c->log_n - l2)) / cols2, n_rows);
             k_ntt_inv<false, false><<<g2, NTT_THREADS, 0, st>>>(data, c->dev, map, l2, cols2, l1);
@@ -373,7 +377,7 @@ void launch_ntt_inv(const unihenn_ctx* c, u64* data, int n_rows, const RowMap& m
     }
     {
         LaunchTimer tm(KF_NTT_INV_COL, bytes, st, half * l1);
-        if (!launch_pass_r8(data, c->dev, map, n_rows, c->log_n, l1, 0, true, true, true, st)) {
+        if (!launch_pass_r8(data, c->dev, map, n_rows, c->log_n, l1, 0, true, true, true, c->ntt_tile_log, st)) {
             int cols1 = tile_cols(l1, c->log_n);
             dim3 g1((1 << (c->log_n - l1)) / cols1, n_rows);
             k_ntt_inv<true, true><<<g1, NTT_THREADS, 0, st>>>(data, c->dev, map, l1, cols1, 0);

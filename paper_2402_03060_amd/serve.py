@@ -224,9 +224,11 @@ class GpuExecutor:
             r.result = [o.data[i].clone() for o in outs]
 
 
-def prepare_model(P, W, name: str, max_batch: int, pool_size: int, seed: int = 5) -> dict:
+def prepare_model(P, W, name: str, max_batch: int, pool_size: int, seed: int = 5,
+                  tuning_cache: str | None = None) -> dict:
     """Context, net (hoisted, graph replay), product-client keys and a pool of
-    encrypted synthetic inputs for one workload."""
+    encrypted synthetic inputs for one workload; with tuning_cache, launch
+    parameters tuned for full batches (looked up in or recorded to that file)."""
     import torch
     cfg = W.config(name)
     ctx = P.Context(cfg["log_n"], cfg["prime_bits"], cfg["special_bits"], 2.0 ** cfg["log_scale"])
@@ -238,6 +240,8 @@ def prepare_model(P, W, name: str, max_batch: int, pool_size: int, seed: int = 5
     rlk = P.gen_switch_key(ctx, sk, seed + 2, relin=True)
     net.bind_keys(keys, rlk)
     net.set_mode(P.EVAL_HOISTED | P.EVAL_GRAPH)
+    if tuning_cache:
+        net.autotune(max_batch, cache_path=tuning_cache)
     xs = W.gen_inputs(cfg["input"], S * pool_size)
     st = stride if S > 1 else ctx.slots
     pts = []
@@ -253,3 +257,75 @@ def prepare_model(P, W, name: str, max_batch: int, pool_size: int, seed: int = 5
     out_bytes = net.n_out * 2 * ctx.n * 8
     return {"ctx": ctx, "net": net, "sk": sk, "keys": keys, "rlk": rlk, "pool": pool, "xs": xs, "cfg": cfg,
             "params": params, "spec": ModelSpec(name, max_batch, ct_bytes + out_bytes)}
+
+
+# ---------------------------------------------------------------- measurement
+SERVE_MODELS = {"conv1": 16, "cnn1d": 8, "cifar_cnn": 4}     # model -> largest batch (ciphertexts)
+SERVE_MIX = {"conv1": 0.5, "cnn1d": 0.3, "cifar_cnn": 0.2}
+
+
+def serving_benchmark(P, W, n_requests: int, tuning_cache: str | None = None, hbm_budget: int | None = None,
+                      levels=(0.5, 0.8, 1.0), log=print) -> dict:
+    """Three models of different ring sizes behind the server: saturation
+    throughput (all requests queued at t = 0), then Poisson arrivals (seed 4,
+    mix 50/30/20) at the given fractions of it.  The admission budget
+    defaults to 90% of the HBM left free once the models are resident."""
+    import torch
+    log("setup serving models " + ", ".join(SERVE_MODELS))
+    models = {m: prepare_model(P, W, m, b, pool_size=16, tuning_cache=tuning_cache) for m, b in SERVE_MODELS.items()}
+    ex = GpuExecutor(models)
+    ex.warmup()
+    if hbm_budget is None:
+        free, _ = torch.cuda.mem_get_info()
+        hbm_budget = int(0.9 * free)
+    specs = {m: d["spec"] for m, d in models.items()}
+    payloads = {m: list(range(16)) for m in models}
+    out = {"models": {m: {"log_n": d["cfg"]["log_n"], "max_batch": SERVE_MODELS[m], "ciphertexts_per_request": 1,
+                          "samples_per_ct": d["cfg"]["samples_per_ct"], "request_bytes": d["spec"].footprint_bytes}
+                      for m, d in models.items()},
+           "mix": SERVE_MIX, "arrival_seed": W.SEED_ARRIVALS, "hbm_budget_bytes": hbm_budget,
+           "requests_per_level": n_requests}
+    burst = poisson_requests(SERVE_MIX, 1e9, n_requests, W.SEED_ARRIVALS, payloads)
+    st = serve(Scheduler(specs, hbm_budget), ex, burst)
+    torch.cuda.synchronize()
+    sat = st.completed / st.duration
+    out["saturation_requests_per_s"] = round(sat, 2)
+    log(f"serving saturation {sat:.1f} req/s")
+    res = {}
+    for frac in levels:
+        reqs = poisson_requests(SERVE_MIX, frac * sat, n_requests, W.SEED_ARRIVALS, payloads)
+        st = serve(Scheduler(specs, hbm_budget), ex, reqs)
+        torch.cuda.synchronize()
+        summ = st.summary()
+        summ["offered_requests_per_s"] = round(frac * sat, 2)
+        res[str(frac)] = summ
+        log(f"serving at {frac:.1f}x: {summ['throughput_per_s']} req/s, p50 {summ['p50_ms']} ms, "
+            f"p99 {summ['p99_ms']} ms")
+    out["load_levels"] = res
+    del ex, models
+    torch.cuda.empty_cache()
+    return out
+
+
+def main():
+    import argparse
+    import json
+    import os
+    import sys
+    ap = argparse.ArgumentParser(description="serving measurement: saturation, then Poisson load levels")
+    ap.add_argument("--requests", type=int, default=10000, help="requests per load level")
+    ap.add_argument("--levels", default="0.5,0.8,1.0")
+    ap.add_argument("--tuning-cache", default=os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                                                           "tuning_cache.json"))
+    a = ap.parse_args()
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import paper_2402_03060_amd as P
+    import workloads as W
+    out = serving_benchmark(P, W, a.requests, tuning_cache=a.tuning_cache,
+                            levels=tuple(float(x) for x in a.levels.split(",")),
+                            log=lambda m: print("[serve] " + m, file=sys.stderr, flush=True))
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

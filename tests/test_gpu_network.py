@@ -278,3 +278,54 @@ def test_lenet1_full_size_golden():
         got = [ctx.export_ct(o)[0] for o in outs]
         assert [g.shape[1] for g in got] == rec["output_limbs"]
         assert _digest(got) == rec["outputs_sha256"], mode
+
+
+def test_autotune_keeps_results_and_caches(tmp_path):
+    """The tuner's settings (group sizes, workgroup targets, NTT split and
+    tile) leave the network outputs bit-identical to the oracle's; a second
+    call with the same cache file applies the stored setting."""
+    import json
+    import paper_2402_03060_amd as P
+    cfg = W.config("lenet1_batched")
+    cfg["log_n"] = 12
+    cfg["samples_per_ct"] = 2
+    n_cts = 3
+    sess = OracleSession(cfg)
+    onet = build_net(cfg, sess.ck.slots)
+    xs_all = W.gen_inputs(cfg["input"], cfg["samples_per_ct"] * n_cts)
+    expected, cts = [], []
+    for b in range(n_cts):
+        ct, outs, _ = run_encrypted(sess, onet, xs_all[2 * b:2 * b + 2], enc_seed=400 + b)
+        expected.append([o.data for o in outs])
+        cts.append(ct)
+    ctx = _ctx(P, cfg)
+    net = _gpu_net(P, ctx, cfg, sess, onet, batch=n_cts)
+    gin = ctx.import_ct(np.stack([c.data for c in cts]), cts[0].scale)
+
+    def check(tag):
+        for mode in (P.EVAL_PLAIN, P.EVAL_HOISTED | P.EVAL_GRAPH):
+            net.set_mode(mode)
+            got = [ctx.export_ct(o) for o in net.eval(gin)]
+            for b in range(n_cts):
+                for k in range(len(got)):
+                    assert np.array_equal(got[k][b], expected[b][k]), (tag, mode, b, k)
+
+    for setting in ({"ks_group": 1}, {"ks_group": 2, "mac_min_wg": 512}, {"ks_min_wg": 8192, "mac_min_wg": 8192},
+                    {"ntt_split": 5, "ntt_tile_log": 12}, {"ntt_split": 7, "ntt_tile_log": 11, "ks_group": 4}):
+        net.set_tuning(**setting)
+        check(setting)
+    cache = str(tmp_path / "tuning.json")
+    net.set_mode(P.EVAL_HOISTED)
+    first = net.autotune(cache_path=cache)
+    check("tuned")
+    entries = json.load(open(cache))
+    assert len(entries) == 1
+    net.set_tuning(ks_group=1, mac_min_wg=512, ks_min_wg=512, ntt_split=4, ntt_tile_log=12)
+    net.set_mode(P.EVAL_HOISTED)          # the cache key includes the mode
+    second = net.autotune(cache_path=cache)
+    for k in ("ntt_split", "ntt_tile_log", "mac_min_wg", "ks_min_wg", "ks_group"):
+        assert second[k] == first[k], k
+    now = net.tuning()
+    for k in ("ntt_split", "ntt_tile_log", "mac_min_wg", "ks_min_wg", "ks_group"):
+        assert now[k] == first[k], k
+    check("cached")

@@ -43,6 +43,41 @@ def test_ntt_roundtrip_all_sizes(log_n):
         assert int(ntt[:, i].max()) < q  # canonical residues
 
 
+@pytest.mark.parametrize("log_n", [11, 13, 14, 15])
+def test_ntt_every_tuning_setting_identical(log_n):
+    """Every NTT split / tile the tuner can choose gives the same forward
+    transform as the default one, and inverts exactly."""
+    import torch
+    from paper_2402_03060_amd import Context, device_u64, host_u64
+    ctx = Context(log_n, [60, 40, 40], 60, 2.0 ** 40)
+    rng = np.random.default_rng(1000 + log_n)
+    a = np.stack([np.stack([rng.integers(0, q, ctx.n, dtype=np.uint64) for q in ctx.primes]) for _ in range(5)])
+    t = device_u64(a)
+    ctx.to_ntt(t, 3, 5)
+    ref = host_u64(t)
+    default = ctx.tuning()
+    tried = 0
+    for l1 in range(3, log_n - 2):
+        if l1 > 8 or log_n - l1 > 8:
+            continue
+        for tile in (11, 12):
+            ctx.set_tuning(ntt_split=l1, ntt_tile_log=tile)
+            t = device_u64(a)
+            ctx.to_ntt(t, 3, 5)
+            assert np.array_equal(host_u64(t), ref), (l1, tile)
+            ctx.from_ntt(t, 3, 5)
+            torch.cuda.synchronize()
+            assert np.array_equal(host_u64(t), a), (l1, tile)
+            tried += 1
+    assert tried >= 4
+    ctx.set_tuning(ntt_split=default["ntt_split"], ntt_tile_log=default["ntt_tile_log"])
+    info = ctx.autotune(batch=2)
+    assert 3 <= info["ntt_split"] <= 8 and info["ntt_tile_log"] in (11, 12) and info["ntt_ms"] > 0
+    t = device_u64(a)
+    ctx.to_ntt(t, 3, 5)
+    assert np.array_equal(host_u64(t), ref)
+
+
 def test_mac_parity(pair):
     ck, ctx, _ = pair
     nl = len(ck.primes)
