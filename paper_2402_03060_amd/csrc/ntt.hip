@@ -156,6 +156,33 @@ __global__ void __launch_bounds__(NTT_THREADS) k_ntt_inv(u64* __restrict__ data,
 }
 
 
+// Shoup product for primes below 2^40, with x of any size below 2^64: the
+// quotient estimate is the usual floor(x w' / 2^64), and since the remainder
+// r = x w - qh q lies in [0, 2q) below 2^41, only r mod 2^42 is formed.  Its
+// upper ten bits need the cross products only mod 2^10, which full-rate
+// 24-bit multiplies give (they use the low 24 bits of each operand).
+// v_mul_u32_u24: low 32 bits of the product of the operands' low 24 bits (a
+// full-rate VALU instruction; the compiler folds the masked C form into
+// 64-bit multiply-adds instead).  Register operands only, no memory access.
+__device__ __forceinline__ u32 mul_u24(u32 a, u32 b)
+{
+    u32 r;
+    asm("v_mul_u32_u24 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
+__device__ __forceinline__ u64 mul_shoup_lazy_small(u64 x, u64 w, u64 w_sh, u64 nq)
+{
+    const u64 qh = umulhi64(x, w_sh);
+    const u32 x0 = (u32)x, x1 = (u32)(x >> 32), w0 = (u32)w, w1 = (u32)(w >> 32);
+    const u32 h0 = (u32)qh, h1 = (u32)(qh >> 32), n0 = (u32)nq, n1 = (u32)(nq >> 32);
+    u64 acc = (u64)h0 * n0;          // - qh q = qh (2^64 - q) mod 2^64
+    acc += (u64)x0 * w0;
+    const u32 c = mul_u24(x0, w1) + mul_u24(x1, w0) + mul_u24(h0, n1) + mul_u24(h1, n0);
+    const u32 hi = ((u32)(acc >> 32) + c) & 0x3ffu;
+    return ((u64)hi << 32) | (u32)acc;
+}
+
 // Radix-8 register rounds: each thread holds the 8 elements of its
 // sub-transform that differ in three consecutive index bits, applies up to
 // three butterfly stages in registers, and exchanges through LDS once per
@@ -165,24 +192,23 @@ __global__ void __launch_bounds__(NTT_THREADS) k_ntt_inv(u64* __restrict__ data,
 // so each distinct twiddle is loaded once per round.  The contiguous pass
 // pads its LDS tile by one word per eight (u + u/8) so that the sixteen
 // lanes serving one sub-transform hit distinct banks in every round.
-template <int LOG_R, int TILE_LOG, bool STRIDED, bool INV, bool LAST>
-__global__ void __launch_bounds__((1 << TILE_LOG) / 8) k_ntt_r8(u64* __restrict__ data, DevCtx ctx, RowMap map,
-                                                                int log_cols, int sigma0)
+//
+// Rows of primes below 2^40 (SMALL, when both passes of the transform use
+// these kernels) skip the per-stage reductions: forward values grow by 2q
+// per stage from [0, q) (below 33q for N <= 2^16) and are reduced once at the
+// end; inverse values double per stage (the difference term adds 2q 2^e at
+// executed stage e so it stays non-negative) and the final product by N^-1
+// reduces them.  Other rows keep the [0, 4q) / [0, 2q) invariants.
+template <int LOG_R, int TILE_LOG, bool STRIDED, bool INV, bool LAST, bool SMALL>
+__device__ __forceinline__ void ntt_r8_body(u64* __restrict__ s, u64* __restrict__ a, const Modulus& M,
+                                            const u64* __restrict__ tw, const u64* __restrict__ tw_sh, int log_n,
+                                            int log_cols, int sigma0)
 {
     constexpr int LOG_G = LOG_R - 3;  // threads per sub-transform: 2^LOG_G
     constexpr int ROUNDS = (LOG_R + 2) / 3;
     constexpr int R = 1 << LOG_R;
     constexpr int RP = R + R / 8;     // padded sub-transform stride (contiguous pass)
-    constexpr int T = 1 << TILE_LOG;
-    __shared__ u64 s[T + T / 8];
-    const int n = ctx.n, log_n = ctx.log_n;
-    const int row = blockIdx.y;
-    const int mi = rowmap_mod(map, row);
-    const Modulus M = ctx.mod[mi];
-    const u64 q = M.q, q2 = 2 * q;
-    const u64* __restrict__ tw = (INV ? ctx.itw : ctx.tw) + (size_t)mi * n;
-    const u64* __restrict__ tw_sh = (INV ? ctx.itw_sh : ctx.tw_sh) + (size_t)mi * n;
-    u64* __restrict__ a = data + (size_t)row * n;
+    const u64 q = M.q, q2 = 2 * q, nq = 0 - q;
     const int tid = threadIdx.x;
     const int cmask = (1 << log_cols) - 1;
     int c, g;
@@ -227,6 +253,9 @@ __global__ void __launch_bounds__((1 << TILE_LOG) / 8) k_ntt_r8(u64* __restrict_
             const int mb = b - lo;
             const int sigma = sigma0 + tau;
             const int shift = log_n - sigma;
+            // inverse, SMALL: values entering this stage are below 2q 2^e,
+            // e = stages already executed = log_n - 1 - sigma
+            const u64 kdiff = (INV && SMALL) ? (q2 << (log_n - 1 - sigma)) : q2;
             // groups of held bits above mb share one twiddle
 #pragma unroll
             for (int hi = 0; hi < (4 >> mb); ++hi) {
@@ -238,15 +267,17 @@ __global__ void __launch_bounds__((1 << TILE_LOG) / 8) k_ntt_r8(u64* __restrict_
                     const int m0 = mbase | low, m1 = m0 | (1 << mb);
                     if (!INV) {
                         u64 U = x[m0];
-                        U = U >= q2 ? U - q2 : U;
-                        const u64 V = mul_shoup_lazy(x[m1], w, wsh, q);
+                        if (!SMALL) U = U >= q2 ? U - q2 : U;
+                        const u64 V = SMALL ? mul_shoup_lazy_small(x[m1], w, wsh, nq)
+                                            : mul_shoup_lazy(x[m1], w, wsh, q);
                         x[m0] = U + V;
                         x[m1] = U - V + q2;
                     } else {
                         const u64 U = x[m0], V = x[m1];
                         const u64 sum = U + V;
-                        x[m0] = sum >= q2 ? sum - q2 : sum;
-                        x[m1] = mul_shoup_lazy(U - V + q2, w, wsh, q);
+                        x[m0] = SMALL ? sum : (sum >= q2 ? sum - q2 : sum);
+                        x[m1] = SMALL ? mul_shoup_lazy_small(U - V + kdiff, w, wsh, nq)
+                                      : mul_shoup_lazy(U - V + q2, w, wsh, q);
                     }
                 }
             }
@@ -263,6 +294,8 @@ __global__ void __launch_bounds__((1 << TILE_LOG) / 8) k_ntt_r8(u64* __restrict_
                 if (LAST) {
                     if (INV) {
                         v = mul_shoup(v, M.n_inv, M.n_inv_sh, q);
+                    } else if (SMALL) {
+                        v = reduce64(v, q, M.ratio);
                     } else {
                         v = v >= q2 ? v - q2 : v;
                         v = v >= q ? v - q : v;
@@ -284,16 +317,35 @@ __global__ void __launch_bounds__((1 << TILE_LOG) / 8) k_ntt_r8(u64* __restrict_
 #undef LIDX
 }
 
+template <int LOG_R, int TILE_LOG, bool STRIDED, bool INV, bool LAST>
+__global__ void __launch_bounds__((1 << TILE_LOG) / 8) k_ntt_r8(u64* __restrict__ data, DevCtx ctx, RowMap map,
+                                                                int log_cols, int sigma0, int lazy_small)
+{
+    constexpr int T = 1 << TILE_LOG;
+    __shared__ u64 s[T + T / 8];
+    const int row = blockIdx.y;
+    const int mi = rowmap_mod(map, row);
+    const Modulus M = ctx.mod[mi];
+    const u64* __restrict__ tw = (INV ? ctx.itw : ctx.tw) + (size_t)mi * ctx.n;
+    const u64* __restrict__ tw_sh = (INV ? ctx.itw_sh : ctx.tw_sh) + (size_t)mi * ctx.n;
+    u64* __restrict__ a = data + (size_t)row * ctx.n;
+    if (lazy_small && M.q < (1ull << 40))
+        ntt_r8_body<LOG_R, TILE_LOG, STRIDED, INV, LAST, true>(s, a, M, tw, tw_sh, ctx.log_n, log_cols, sigma0);
+    else
+        ntt_r8_body<LOG_R, TILE_LOG, STRIDED, INV, LAST, false>(s, a, M, tw, tw_sh, ctx.log_n, log_cols, sigma0);
+}
+
 template <int LOG_R, int TILE_LOG>
 void launch_r8(u64* data, const DevCtx& dev, const RowMap& map, int n_rows, int log_n, int sigma0, bool strided,
-               bool inv, bool last, hipStream_t st)
+               bool inv, bool last, int lazy_small, hipStream_t st)
 {
     const int avail_log = log_n - LOG_R;                 // log2 of sub-transforms per row
     int log_cols = TILE_LOG - LOG_R;                      // tile of 2^TILE_LOG words
     if (log_cols > avail_log) log_cols = avail_log;
     const int threads = 1 << (LOG_R - 3 + log_cols);
     dim3 grid(1 << (avail_log - log_cols), n_rows);
-#define L8(S, I, Z) k_ntt_r8<LOG_R, TILE_LOG, S, I, Z><<<grid, threads, 0, st>>>(data, dev, map, log_cols, sigma0)
+#define L8(S, I, Z) \
+    k_ntt_r8<LOG_R, TILE_LOG, S, I, Z><<<grid, threads, 0, st>>>(data, dev, map, log_cols, sigma0, lazy_small)
     if (strided) {
         if (!inv) { if (last) L8(true, false, true); else L8(true, false, false); }
         else { if (last) L8(true, true, true); else L8(true, true, false); }
@@ -307,12 +359,12 @@ void launch_r8(u64* data, const DevCtx& dev, const RowMap& map, int n_rows, int 
 // dispatch on the sub-transform size and tile; sizes below 8 points use the
 // generic kernel
 bool launch_pass_r8(u64* data, const DevCtx& dev, const RowMap& map, int n_rows, int log_n, int log_r, int sigma0,
-                    bool strided, bool inv, bool last, int tile_log, hipStream_t st)
+                    bool strided, bool inv, bool last, int tile_log, int lazy_small, hipStream_t st)
 {
 #define LR(K)                                                                                      \
     case K:                                                                                        \
-        if (tile_log == 12) launch_r8<K, 12>(data, dev, map, n_rows, log_n, sigma0, strided, inv, last, st); \
-        else launch_r8<K, 11>(data, dev, map, n_rows, log_n, sigma0, strided, inv, last, st);      \
+        if (tile_log == 12) launch_r8<K, 12>(data, dev, map, n_rows, log_n, sigma0, strided, inv, last, lazy_small, st); \
+        else launch_r8<K, 11>(data, dev, map, n_rows, log_n, sigma0, strided, inv, last, lazy_small, st);      \
         return true;
     switch (log_r) {
     LR(3) LR(4) LR(5) LR(6) LR(7) LR(8)
@@ -342,10 +394,12 @@ void launch_ntt_fwd(const unihenn_ctx* c, u64* data, int n_rows, const RowMap& m
     if (n_rows <= 0) return;
     int l1, l2;
     split(c, &l1, &l2);
+    // the unreduced small-prime path needs both passes in the radix-8 kernels
+    const int lazy = (l1 >= 3 && l1 <= 8 && l2 >= 3 && l2 <= 8) ? 1 : 0;
     const double bytes = 16.0 * c->n * n_rows, half = 0.5 * c->n * n_rows;
     {
         LaunchTimer tm(KF_NTT_FWD_COL, bytes, st, half * l1);
-        if (!launch_pass_r8(data, c->dev, map, n_rows, c->log_n, l1, 0, true, false, false, c->ntt_tile_log, st)) {
+        if (!launch_pass_r8(data, c->dev, map, n_rows, c->log_n, l1, 0, true, false, false, c->ntt_tile_log, lazy, st)) {
             int cols1 = tile_cols(l1, c->log_n);
             dim3 g1((1 << (c->log_n - l1)) / cols1, n_rows);
             k_ntt_fwd<true, false><<<g1, NTT_THREADS, 0, st>>>(data, c->dev, map, l1, cols1, 0);
@@ -353,7 +407,7 @@ void launch_ntt_fwd(const unihenn_ctx* c, u64* data, int n_rows, const RowMap& m
     }
     {
         LaunchTimer tm(KF_NTT_FWD_ROW, bytes, st, half * l2);
-        if (!launch_pass_r8(data, c->dev, map, n_rows, c->log_n, l2, l1, false, false, true, c->ntt_tile_log, st)) {
+        if (!launch_pass_r8(data, c->dev, map, n_rows, c->log_n, l2, l1, false, false, true, c->ntt_tile_log, lazy, st)) {
             int cols2 = tile_cols(l2, c->log_n);
             dim3 g2((1 << (c->log_n - l2)) / cols2, n_rows);
             k_ntt_fwd<false, true><<<g2, NTT_THREADS, 0, st>>>(data, c->dev, map, l2, cols2, l1);
@@ -366,10 +420,12 @@ void launch_ntt_inv(const unihenn_ctx* c, u64* data, int n_rows, const RowMap& m
     if (n_rows <= 0) return;
     int l1, l2;
     split(c, &l1, &l2);
+    // the unreduced small-prime path needs both passes in the radix-8 kernels
+    const int lazy = (l1 >= 3 && l1 <= 8 && l2 >= 3 && l2 <= 8) ? 1 : 0;
     const double bytes = 16.0 * c->n * n_rows, half = 0.5 * c->n * n_rows;
     {
         LaunchTimer tm(KF_NTT_INV_ROW, bytes, st, half * l2);
-        if (!launch_pass_r8(data, c->dev, map, n_rows, c->log_n, l2, l1, false, true, false, c->ntt_tile_log, st)) {
+        if (!launch_pass_r8(data, c->dev, map, n_rows, c->log_n, l2, l1, false, true, false, c->ntt_tile_log, lazy, st)) {
             int cols2 = tile_cols(l2, c->log_n);
             dim3 g2((1 << (c->log_n - l2)) / cols2, n_rows);
             k_ntt_inv<false, false><<<g2, NTT_THREADS, 0, st>>>(data, c->dev, map, l2, cols2, l1);
@@ -377,7 +433,7 @@ void launch_ntt_inv(const unihenn_ctx* c, u64* data, int n_rows, const RowMap& m
     }
     {
         LaunchTimer tm(KF_NTT_INV_COL, bytes, st, half * l1);
-        if (!launch_pass_r8(data, c->dev, map, n_rows, c->log_n, l1, 0, true, true, true, c->ntt_tile_log, st)) {
+        if (!launch_pass_r8(data, c->dev, map, n_rows, c->log_n, l1, 0, true, true, true, c->ntt_tile_log, lazy, st)) {
             int cols1 = tile_cols(l1, c->log_n);
             dim3 g1((1 << (c->log_n - l1)) / cols1, n_rows);
             k_ntt_inv<true, true><<<g1, NTT_THREADS, 0, st>>>(data, c->dev, map, l1, cols1, 0);
