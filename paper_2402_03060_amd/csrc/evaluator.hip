@@ -4,6 +4,8 @@
 // the import / export conversions of the C ABI.
 #include <algorithm>
 
+#include <cstring>
+
 #include "kernels.h"
 
 // ---------------------------------------------------------------- helpers
@@ -45,6 +47,21 @@ void ks_finish(const unihenn_ctx* c, const u64* d, int d_stride, const u64* key,
 {
     launch_ks_inner(c, ws.U, ws.Up, d, d_stride, ws.modup, key, nd, batch, nl, g, s);
     launch_ntt_inv(c, ws.Up, batch * 2, rowmap_list({c->n_data}), s);
+    FuseArgs fa;
+    memset(&fa, 0, sizeof(fa));
+    fa.src = ws.Up;
+    fa.src_mod = c->n_data;
+    fa.nl = nl;
+    fa.polys = batch * 2;
+    fa.x[0] = ws.U;
+    fa.x_limbs = nl;
+    fa.add[0][0] = add0;
+    fa.add[0][1] = add1;
+    fa.add_stride = add_stride;
+    fa.add_perm[0] = 1;
+    fa.out[0] = out;
+    fa.inv = c->d_p_inv;
+    if (launch_ntt_fwd_fused(c, ws.R, fa, batch * 2 * nl, KF_MODDOWN, s)) return;
     launch_lift_last(c, ws.R, ws.Up, batch * 2, nl, c->n_data, KF_MODDOWN, s);
     launch_ntt_fwd(c, ws.R, batch * 2 * nl, rowmap_ct(nl), s);
     launch_sub_scale(c, out, ws.U, nl, ws.R, c->d_p_inv, batch * 2, nl, add0, add1, add_stride, KF_MODDOWN, s);
@@ -55,9 +72,21 @@ void rescale_core(const unihenn_ctx* c, const u64* in, int batch, int nl, u64* o
     const int l = nl - 1;
     launch_gather_rows(c, ws.Up, in, batch * 2, 1, nl, l, s);
     launch_ntt_inv(c, ws.Up, batch * 2, rowmap_list({l}), s);
+    const u64* inv = c->d_inv_last + (size_t)l * c->primes.size() * 2;
+    FuseArgs fa;
+    memset(&fa, 0, sizeof(fa));
+    fa.src = ws.Up;
+    fa.src_mod = l;
+    fa.nl = l;
+    fa.polys = batch * 2;
+    fa.x[0] = in;
+    fa.x_limbs = nl;
+    fa.add_perm[0] = 1;
+    fa.out[0] = out;
+    fa.inv = inv;
+    if (launch_ntt_fwd_fused(c, ws.R, fa, batch * 2 * l, KF_RESCALE, s)) return;
     launch_lift_last(c, ws.R, ws.Up, batch * 2, l, l, KF_RESCALE, s);
     launch_ntt_fwd(c, ws.R, batch * 2 * l, rowmap_ct(l), s);
-    const u64* inv = c->d_inv_last + (size_t)l * c->primes.size() * 2;
     launch_sub_scale(c, out, in, nl, ws.R, inv, batch * 2, l, nullptr, nullptr, 0, KF_RESCALE, s);
 }
 

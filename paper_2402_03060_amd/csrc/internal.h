@@ -95,8 +95,32 @@ RowMap rowmap_modup(int n_limbs, int p_index);
 void launch_ntt_fwd(const unihenn_ctx* c, u64* data, int n_rows, const RowMap& map, hipStream_t s);
 void launch_ntt_inv(const unihenn_ctx* c, u64* data, int n_rows, const RowMap& map, hipStream_t s);
 
+// Lift + forward NTT + combine (ModDown, relinearisation, rescale) over the
+// rows r = (e * polys + p) * nl + i of R:
+//   R[r] = NTT(centered lift of src[e * polys + p] (modulus src_mod) to q_i)
+//   out[e][p][i] = (x[e][(p * x_limbs + i)] - R[r]) * inv_i
+//                  + add[e][p & 1][((p >> 1) * add_stride + i)] (read through
+//                  the automorphism of Galois element add_perm[e] when != 1)
+#define UH_FUSE_MAX 32
+struct FuseArgs {
+    const u64* src;
+    int src_mod;
+    int nl;                          // limbs of R and of the outputs
+    int polys;                       // polynomials per element
+    const u64* x[UH_FUSE_MAX];
+    int x_limbs;
+    const u64* add[UH_FUSE_MAX][2];
+    int add_stride;
+    u32 add_perm[UH_FUSE_MAX];
+    u64* out[UH_FUSE_MAX];
+    const u64* inv;                  // [i][2] value, Shoup companion
+};
+enum KernelFamily : int;
+bool launch_ntt_fwd_fused(const unihenn_ctx* c, u64* R, const FuseArgs& fa, int n_rows, KernelFamily fam,
+                          hipStream_t st);
+
 // kernel timing hooks (per kernel family), see unihenn_stats_*
-enum KernelFamily {
+enum KernelFamily : int {
     KF_NTT_FWD_COL = 0, KF_NTT_FWD_ROW, KF_NTT_INV_ROW, KF_NTT_INV_COL, KF_MODUP, KF_KS_INNER, KF_MODDOWN,
     KF_RESCALE, KF_MAC, KF_AUTO, KF_TENSOR, KF_ADD, KF_ENCODE, KF_OTHER, KF_COUNT
 };

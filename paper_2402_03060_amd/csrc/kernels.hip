@@ -548,12 +548,39 @@ void group_switch(const unihenn_ctx* c, const GroupArgs& ga, int B, int nl, bool
         else GI(UH_MAX_MODULI);
 #undef GI
     }
+    launch_ntt_inv(c, Up, E * B * 2, rowmap_list({c->n_data}), s);
+    {
+        // the c0 addend: tau(c0) read straight from the source (c0_only), or
+        // the automorphism already in aux
+        FuseArgs fa;
+        memset(&fa, 0, sizeof(fa));
+        fa.src = Up;
+        fa.src_mod = c->n_data;
+        fa.nl = nl;
+        fa.polys = B * 2;
+        fa.x_limbs = nl;
+        fa.add_stride = 2 * nl;
+        fa.inv = c->d_p_inv;
+        const size_t per = (size_t)B * 2 * nl * c->n;
+        // reading c0 from the sources while other workgroups write the
+        // destinations needs the two sets of buffers to be disjoint
+        bool disjoint = true;
+        for (int e = 0; e < E && c0_only; ++e)
+            for (int f = 0; f < E; ++f)
+                if (ga.dst[e] < ga.src[f] + per && ga.src[f] < ga.dst[e] + per) disjoint = false;
+        for (int e = 0; e < E; ++e) {
+            fa.x[e] = U + e * per;
+            fa.out[e] = ga.dst[e];
+            fa.add[e][0] = c0_only ? ga.src[e] : aux + e * per;
+            fa.add_perm[e] = c0_only ? ga.g[e] : 1u;
+        }
+        if (disjoint && launch_ntt_fwd_fused(c, R, fa, E * B * 2 * nl, KF_MODDOWN, s)) return;
+    }
     if (c0_only) {
         LaunchTimer tm(KF_AUTO, 16.0 * c->n * E * B * nl, s);
         dim3 g3(gx, B * nl, E);
         k_group_auto<<<g3, EW_THREADS, 0, s>>>(aux, ga, nl, B, c->log_n, 1);
     }
-    launch_ntt_inv(c, Up, E * B * 2, rowmap_list({c->n_data}), s);
     launch_lift_last(c, R, Up, E * B * 2, nl, c->n_data, KF_MODDOWN, s);
     launch_ntt_fwd(c, R, E * B * 2 * nl, rowmap_ct(nl), s);
     {
@@ -847,9 +874,25 @@ void group_rescale(const unihenn_ctx* c, int E, const u64* const* in, u64* const
         k_group_last<<<dim3(gx, B * 2, E), EW_THREADS, 0, s>>>(last, g, nl, c->n);
     }
     launch_ntt_inv(c, last, E * B * 2, rowmap_list({l}), s);
+    const u64* inv = c->d_inv_last + (size_t)l * c->primes.size() * 2;
+    {
+        FuseArgs fa;
+        memset(&fa, 0, sizeof(fa));
+        fa.src = last;
+        fa.src_mod = l;
+        fa.nl = l;
+        fa.polys = B * 2;
+        fa.x_limbs = nl;
+        fa.inv = inv;
+        for (int e = 0; e < E; ++e) {
+            fa.x[e] = in[e];
+            fa.out[e] = out[e];
+            fa.add_perm[e] = 1;
+        }
+        if (launch_ntt_fwd_fused(c, R, fa, E * B * 2 * l, KF_RESCALE, s)) return;
+    }
     launch_lift_last(c, R, last, E * B * 2, l, l, KF_RESCALE, s);
     launch_ntt_fwd(c, R, E * B * 2 * l, rowmap_ct(l), s);
-    const u64* inv = c->d_inv_last + (size_t)l * c->primes.size() * 2;
     {
         LaunchTimer tm(KF_RESCALE, 8.0 * c->n * E * B * 2 * l * 3, s);
         k_group_sub_scale2<<<dim3(gx, B * 2 * l, E), EW_THREADS, 0, s>>>(g, R, nl, inv, c->dev, l, B * 2);
@@ -893,9 +936,23 @@ void group_square(const unihenn_ctx* c, int E, const u64* const* in, u64* const*
     launch_ntt_fwd(c, modup, (int)EB * nl * nl, rowmap_modup(nl, c->n_data), s);
     launch_ks_inner(c, U, Up, d2, nl, modup, rlk, c->n_data, (int)EB, nl, 1, s);
     launch_ntt_inv(c, Up, (int)EB * 2, rowmap_list({c->n_data}), s);
-    launch_lift_last(c, R, Up, (int)EB * 2, nl, c->n_data, KF_MODDOWN, s);
-    launch_ntt_fwd(c, R, (int)EB * 2 * nl, rowmap_ct(nl), s);
-    {
+    FuseArgs fa;
+    memset(&fa, 0, sizeof(fa));
+    fa.src = Up;
+    fa.src_mod = c->n_data;
+    fa.nl = nl;
+    fa.polys = (int)EB * 2;
+    fa.x[0] = U;
+    fa.x_limbs = nl;
+    fa.add[0][0] = d0;
+    fa.add[0][1] = d1;
+    fa.add_stride = nl;
+    fa.add_perm[0] = 1;
+    fa.out[0] = rel;
+    fa.inv = c->d_p_inv;
+    if (!launch_ntt_fwd_fused(c, R, fa, (int)EB * 2 * nl, KF_MODDOWN, s)) {
+        launch_lift_last(c, R, Up, (int)EB * 2, nl, c->n_data, KF_MODDOWN, s);
+        launch_ntt_fwd(c, R, (int)EB * 2 * nl, rowmap_ct(nl), s);
         LaunchTimer tm(KF_MODDOWN, 8.0 * c->n * EB * 2 * nl * 3.5, s);
         k_relin_combine<<<dim3(gx, (unsigned)(EB * 2 * nl)), EW_THREADS, 0, s>>>(rel, U, R, d0, d1, c->d_p_inv, c->dev,
                                                                                  nl);

@@ -199,8 +199,26 @@ __device__ __forceinline__ u64 mul_shoup_lazy_small(u64 x, u64 w, u64 w_sh, u64 
 // end; inverse values double per stage (the difference term adds 2q 2^e at
 // executed stage e so it stays non-negative) and the final product by N^-1
 // reduces them.  Other rows keep the [0, 4q) / [0, 2q) invariants.
-template <int LOG_R, int TILE_LOG, bool STRIDED, bool INV, bool LAST, bool SMALL>
-__device__ __forceinline__ void ntt_r8_body(u64* __restrict__ s, u64* __restrict__ a, const Modulus& M,
+// Row access of a pass: load/store one word at global index g of the row, or
+// two adjacent words (g even) on the contiguous 16-byte path.
+struct RowIO {
+    u64* __restrict__ a;
+    __device__ __forceinline__ u64 load(int g) const { return a[g]; }
+    __device__ __forceinline__ void store(int g, u64 v) const { a[g] = v; }
+    __device__ __forceinline__ void load2(int g, u64& v0, u64& v1) const
+    {
+        const ulonglong2 v = *reinterpret_cast<const ulonglong2*>(a + g);
+        v0 = v.x;
+        v1 = v.y;
+    }
+    __device__ __forceinline__ void store2(int g, u64 v0, u64 v1) const
+    {
+        *reinterpret_cast<ulonglong2*>(a + g) = make_ulonglong2(v0, v1);
+    }
+};
+
+template <int LOG_R, int TILE_LOG, bool STRIDED, bool INV, bool LAST, bool SMALL, class IO>
+__device__ __forceinline__ void ntt_r8_body(u64* __restrict__ s, const IO& io, const Modulus& M,
                                             const u64* __restrict__ tw, const u64* __restrict__ tw_sh, int log_n,
                                             int log_cols, int sigma0)
 {
@@ -229,16 +247,11 @@ __device__ __forceinline__ void ntt_r8_body(u64* __restrict__ s, u64* __restrict
         const int ub = ((g >> lo) << (lo + 3)) | (g & umask);
         if (rho == 0) {
             if (!STRIDED && lo == 0) {
-                const ulonglong2* src = reinterpret_cast<const ulonglong2*>(a + GIDX(ub));
 #pragma unroll
-                for (int h = 0; h < 4; ++h) {
-                    const ulonglong2 v = src[h];
-                    x[2 * h] = v.x;
-                    x[2 * h + 1] = v.y;
-                }
+                for (int h = 0; h < 4; ++h) io.load2(GIDX(ub) + 2 * h, x[2 * h], x[2 * h + 1]);
             } else {
 #pragma unroll
-                for (int m = 0; m < 8; ++m) x[m] = a[GIDX(ub | (m << lo))];
+                for (int m = 0; m < 8; ++m) x[m] = io.load(GIDX(ub | (m << lo)));
             }
         } else {
 #pragma unroll
@@ -304,12 +317,11 @@ __device__ __forceinline__ void ntt_r8_body(u64* __restrict__ s, u64* __restrict
                 x[m] = v;
             }
             if (!STRIDED && lo == 0) {
-                ulonglong2* dst = reinterpret_cast<ulonglong2*>(a + GIDX(ub));
 #pragma unroll
-                for (int h = 0; h < 4; ++h) dst[h] = make_ulonglong2(x[2 * h], x[2 * h + 1]);
+                for (int h = 0; h < 4; ++h) io.store2(GIDX(ub) + 2 * h, x[2 * h], x[2 * h + 1]);
             } else {
 #pragma unroll
-                for (int m = 0; m < 8; ++m) a[GIDX(ub | (m << lo))] = x[m];
+                for (int m = 0; m < 8; ++m) io.store(GIDX(ub | (m << lo)), x[m]);
             }
         }
     }
@@ -328,11 +340,129 @@ __global__ void __launch_bounds__((1 << TILE_LOG) / 8) k_ntt_r8(u64* __restrict_
     const Modulus M = ctx.mod[mi];
     const u64* __restrict__ tw = (INV ? ctx.itw : ctx.tw) + (size_t)mi * ctx.n;
     const u64* __restrict__ tw_sh = (INV ? ctx.itw_sh : ctx.tw_sh) + (size_t)mi * ctx.n;
-    u64* __restrict__ a = data + (size_t)row * ctx.n;
+    const RowIO io{data + (size_t)row * ctx.n};
     if (lazy_small && M.q < (1ull << 40))
-        ntt_r8_body<LOG_R, TILE_LOG, STRIDED, INV, LAST, true>(s, a, M, tw, tw_sh, ctx.log_n, log_cols, sigma0);
+        ntt_r8_body<LOG_R, TILE_LOG, STRIDED, INV, LAST, true>(s, io, M, tw, tw_sh, ctx.log_n, log_cols, sigma0);
     else
-        ntt_r8_body<LOG_R, TILE_LOG, STRIDED, INV, LAST, false>(s, a, M, tw, tw_sh, ctx.log_n, log_cols, sigma0);
+        ntt_r8_body<LOG_R, TILE_LOG, STRIDED, INV, LAST, false>(s, io, M, tw, tw_sh, ctx.log_n, log_cols, sigma0);
+}
+
+// ---- forward NTT fused with the lift before it and the combine after it
+// (ModDown, relinearisation, rescale).  Row r of the transform is limb
+// i = r % nl of polynomial pg = r / nl; polynomial pg = e * polys + p belongs
+// to element e of the group.
+//   column pass: reads source row pg (coefficient form, modulus src_mod) and
+//                lifts it to q_i (centered) on load, writes row r of R;
+//   row pass:    reads R in place and, instead of storing the transform t,
+//                stores out_e[p][i] = (x_e[p][i] - t) * inv_i (+ addend).
+struct LiftIO {
+    const u64* __restrict__ src;
+    u64* __restrict__ a;
+    u64 p_half, p_mod_q, q, ratio;
+    __device__ __forceinline__ u64 load(int g) const { return centered_lift(src[g], p_half, p_mod_q, q, ratio); }
+    __device__ __forceinline__ void store(int g, u64 v) const { a[g] = v; }
+    __device__ __forceinline__ void load2(int g, u64& v0, u64& v1) const
+    {
+        v0 = load(g);
+        v1 = load(g + 1);
+    }
+    __device__ __forceinline__ void store2(int g, u64 v0, u64 v1) const
+    {
+        *reinterpret_cast<ulonglong2*>(a + g) = make_ulonglong2(v0, v1);
+    }
+};
+
+struct FinishIO {
+    u64* __restrict__ a;                 // R row (read)
+    const u64* __restrict__ x;           // minuend row
+    const u64* __restrict__ add;         // addend row or null
+    u64* __restrict__ out;               // destination row
+    u64 q, inv, inv_sh;
+    u32 perm;                            // Galois element for reading the addend (1: none)
+    int log_n;
+    __device__ __forceinline__ u64 load(int g) const { return a[g]; }
+    __device__ __forceinline__ void load2(int g, u64& v0, u64& v1) const
+    {
+        const ulonglong2 v = *reinterpret_cast<const ulonglong2*>(a + g);
+        v0 = v.x;
+        v1 = v.y;
+    }
+    __device__ __forceinline__ u64 addend(int g) const
+    {
+        if (!add) return 0;
+        if (perm == 1) return add[g];
+        // NTT-form automorphism: entry g of tau(a) is entry pi(g) of a,
+        // 2 brev(pi(g)) + 1 = perm (2 brev(g) + 1) mod 2N
+        const u32 bits = (u32)log_n;
+        const u32 bg = __brev((u32)g) >> (32 - bits);
+        const u32 e = (u32)(((u64)perm * (2u * bg + 1u)) & ((2u << bits) - 1u));
+        return add[__brev((e - 1u) >> 1) >> (32 - bits)];
+    }
+    __device__ __forceinline__ u64 finish(u64 t, u64 xv, u64 av) const
+    {
+        const u64 v = mul_shoup(sub_mod(xv, t, q), inv, inv_sh, q);
+        return add_mod(v, av, q);
+    }
+    __device__ __forceinline__ void store(int g, u64 t) const { out[g] = finish(t, x[g], addend(g)); }
+    __device__ __forceinline__ void store2(int g, u64 t0, u64 t1) const
+    {
+        const ulonglong2 xv = *reinterpret_cast<const ulonglong2*>(x + g);
+        u64 a0 = 0, a1 = 0;
+        if (add && perm == 1) {
+            const ulonglong2 av = *reinterpret_cast<const ulonglong2*>(add + g);
+            a0 = av.x;
+            a1 = av.y;
+        } else if (add) {
+            a0 = addend(g);
+            a1 = addend(g + 1);
+        }
+        *reinterpret_cast<ulonglong2*>(out + g) = make_ulonglong2(finish(t0, xv.x, a0), finish(t1, xv.y, a1));
+    }
+};
+
+template <int LOG_R, int TILE_LOG>
+__global__ void __launch_bounds__((1 << TILE_LOG) / 8) k_ntt_r8_lift(u64* __restrict__ R, DevCtx ctx, FuseArgs fa,
+                                                                     const u64* __restrict__ qmod, int n_mod,
+                                                                     int log_cols, int lazy_small)
+{
+    constexpr int T = 1 << TILE_LOG;
+    __shared__ u64 s[T + T / 8];
+    const int row = blockIdx.y;
+    const int i = row % fa.nl, pg = row / fa.nl;
+    const Modulus M = ctx.mod[i];
+    const u64* __restrict__ tw = ctx.tw + (size_t)i * ctx.n;
+    const u64* __restrict__ tw_sh = ctx.tw_sh + (size_t)i * ctx.n;
+    const LiftIO io{fa.src + (size_t)pg * ctx.n, R + (size_t)row * ctx.n, ctx.mod[fa.src_mod].half,
+                    qmod[(size_t)fa.src_mod * n_mod + i], M.q, M.ratio};
+    if (lazy_small && M.q < (1ull << 40))
+        ntt_r8_body<LOG_R, TILE_LOG, true, false, false, true>(s, io, M, tw, tw_sh, ctx.log_n, log_cols, 0);
+    else
+        ntt_r8_body<LOG_R, TILE_LOG, true, false, false, false>(s, io, M, tw, tw_sh, ctx.log_n, log_cols, 0);
+}
+
+template <int LOG_R, int TILE_LOG>
+__global__ void __launch_bounds__((1 << TILE_LOG) / 8) k_ntt_r8_finish(u64* __restrict__ R, DevCtx ctx, FuseArgs fa,
+                                                                       int log_cols, int sigma0, int lazy_small)
+{
+    constexpr int T = 1 << TILE_LOG;
+    __shared__ u64 s[T + T / 8];
+    const int row = blockIdx.y;
+    const int i = row % fa.nl, pg = row / fa.nl;
+    const int e = pg / fa.polys, p = pg % fa.polys, c = p & 1, b = p >> 1;
+    const Modulus M = ctx.mod[i];
+    const u64* __restrict__ tw = ctx.tw + (size_t)i * ctx.n;
+    const u64* __restrict__ tw_sh = ctx.tw_sh + (size_t)i * ctx.n;
+    const size_t n = (size_t)ctx.n;
+    const u64* add = fa.add[e][c];
+    const FinishIO io{R + (size_t)row * n,
+                      fa.x[e] + ((size_t)p * fa.x_limbs + i) * n,
+                      add ? add + ((size_t)b * fa.add_stride + i) * n : nullptr,
+                      fa.out[e] + ((size_t)p * fa.nl + i) * n,
+                      M.q, fa.inv[2 * i], fa.inv[2 * i + 1], fa.add_perm[e], ctx.log_n};
+    if (lazy_small && M.q < (1ull << 40))
+        ntt_r8_body<LOG_R, TILE_LOG, false, false, true, true>(s, io, M, tw, tw_sh, ctx.log_n, log_cols, sigma0);
+    else
+        ntt_r8_body<LOG_R, TILE_LOG, false, false, true, false>(s, io, M, tw, tw_sh, ctx.log_n, log_cols, sigma0);
 }
 
 template <int LOG_R, int TILE_LOG>
@@ -439,4 +569,48 @@ void launch_ntt_inv(const unihenn_ctx* c, u64* data, int n_rows, const RowMap& m
             k_ntt_inv<true, true><<<g1, NTT_THREADS, 0, st>>>(data, c->dev, map, l1, cols1, 0);
         }
     }
+}
+
+// Lift + forward NTT + combine in two passes (both radix-8); false when the
+// ring's split puts a pass outside the radix-8 kernels (the caller then runs
+// the separate kernels).
+bool launch_ntt_fwd_fused(const unihenn_ctx* c, u64* R, const FuseArgs& fa, int n_rows, KernelFamily fam,
+                          hipStream_t st)
+{
+    int l1, l2;
+    split(c, &l1, &l2);
+    if (n_rows <= 0 || l1 < 3 || l1 > 8 || l2 < 3 || l2 > 8) return false;
+    const int tile = c->ntt_tile_log == 12 ? 12 : 11;
+    const double half = 0.5 * c->n * n_rows, rows = n_rows, polys = (double)n_rows / fa.nl;
+    auto geom = [&](int log_r, int* log_cols, dim3* grid, int* threads) {
+        const int avail_log = c->log_n - log_r;
+        int lc = tile - log_r;
+        if (lc > avail_log) lc = avail_log;
+        *log_cols = lc;
+        *threads = 1 << (log_r - 3 + lc);
+        *grid = dim3(1 << (avail_log - lc), n_rows);
+    };
+    int lc, thr;
+    dim3 grid;
+    {
+        // source rows once, R rows written
+        LaunchTimer tm(KF_NTT_FWD_COL, 8.0 * c->n * (polys + rows), st, half * l1);
+        geom(l1, &lc, &grid, &thr);
+#define LC(K, TL) k_ntt_r8_lift<K, TL><<<grid, thr, 0, st>>>(R, c->dev, fa, c->d_qmod, (int)c->primes.size(), lc, 1)
+#define LCT(K) case K: if (tile == 12) LC(K, 12); else LC(K, 11); break;
+        switch (l1) { LCT(3) LCT(4) LCT(5) LCT(6) LCT(7) LCT(8) }
+#undef LCT
+#undef LC
+    }
+    {
+        // R rows read, minuend rows read, addend rows (c = 0 or both), outputs written
+        LaunchTimer tm(fam, 8.0 * c->n * rows * 3.5, st, half * l2);
+        geom(l2, &lc, &grid, &thr);
+#define LF(K, TL) k_ntt_r8_finish<K, TL><<<grid, thr, 0, st>>>(R, c->dev, fa, lc, l1, 1)
+#define LFT(K) case K: if (tile == 12) LF(K, 12); else LF(K, 11); break;
+        switch (l2) { LFT(3) LFT(4) LFT(5) LFT(6) LFT(7) LFT(8) }
+#undef LFT
+#undef LF
+    }
+    return true;
 }
