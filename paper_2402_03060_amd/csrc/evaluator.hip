@@ -38,6 +38,7 @@ void ks_modup(const unihenn_ctx* c, const u64* d, int d_stride, int batch, int n
 {
     launch_gather_rows(c, ws.dcoef, d, batch * nl, nl, d_stride, 0, s);
     launch_ntt_inv(c, ws.dcoef, batch * nl, rowmap_ct(nl), s);
+    if (launch_ntt_fwd_modup(c, ws.modup, ws.dcoef, batch * nl, nl, s)) return;
     launch_modup(c, ws.modup, ws.dcoef, batch, nl, s);
     launch_ntt_fwd(c, ws.modup, batch * nl * nl, rowmap_modup(nl, c->n_data), s);
 }

@@ -118,6 +118,9 @@ struct FuseArgs {
 enum KernelFamily : int;
 bool launch_ntt_fwd_fused(const unihenn_ctx* c, u64* R, const FuseArgs& fa, int n_rows, KernelFamily fam,
                           hipStream_t st);
+// ModUp (centered lift of each digit to every other target) fused with the
+// forward NTT of the lifted rows; false when not applicable
+bool launch_ntt_fwd_modup(const unihenn_ctx* c, u64* modup, const u64* dcoef, int n_src, int nl, hipStream_t st);
 
 // kernel timing hooks (per kernel family), see unihenn_stats_*
 enum KernelFamily : int {

@@ -525,6 +525,7 @@ void group_modup(const unihenn_ctx* c, int D, const u64* const* dsrc, int dstrid
         k_group_gather<<<g3, EW_THREADS, 0, s>>>(dcoef, ga, nl, B, c->n);
     }
     launch_ntt_inv(c, dcoef, D * B * nl, rowmap_ct(nl), s);
+    if (launch_ntt_fwd_modup(c, modup, dcoef, D * B * nl, nl, s)) return;
     launch_modup(c, modup, dcoef, D * B, nl, s);
     launch_ntt_fwd(c, modup, D * B * nl * nl, rowmap_modup(nl, c->n_data), s);
 }
@@ -932,8 +933,10 @@ void group_square(const unihenn_ctx* c, int E, const u64* const* in, u64* const*
     // ModUp of every d2 (E * B ciphertext-polys as one batch), inner product with the relinearisation key
     launch_gather_rows(c, dcoef, d2, (int)EB * nl, nl, nl, 0, s);
     launch_ntt_inv(c, dcoef, (int)EB * nl, rowmap_ct(nl), s);
-    launch_modup(c, modup, dcoef, (int)EB, nl, s);
-    launch_ntt_fwd(c, modup, (int)EB * nl * nl, rowmap_modup(nl, c->n_data), s);
+    if (!launch_ntt_fwd_modup(c, modup, dcoef, (int)EB * nl, nl, s)) {
+        launch_modup(c, modup, dcoef, (int)EB, nl, s);
+        launch_ntt_fwd(c, modup, (int)EB * nl * nl, rowmap_modup(nl, c->n_data), s);
+    }
     launch_ks_inner(c, U, Up, d2, nl, modup, rlk, c->n_data, (int)EB, nl, 1, s);
     launch_ntt_inv(c, Up, (int)EB * 2, rowmap_list({c->n_data}), s);
     FuseArgs fa;

@@ -15,6 +15,8 @@
 // The generic kernels (sub-transforms below 8 points) use tiles of TILE
 // words (16 KiB) of LDS and 256 threads; the radix-8 kernels take the tile
 // size (2^11 or 2^12 words, with 2^8 or 2^9 threads) as a launch parameter.
+#include <cstring>
+
 #include "internal.h"
 
 namespace {
@@ -420,7 +422,11 @@ struct FinishIO {
     }
 };
 
-template <int LOG_R, int TILE_LOG>
+// MODUP: rows r = (pg * nl) + s hold digit j = pg % nl of source row pg,
+// lifted to target t = s < j ? s : s + 1 (t = nl: the special prime); the
+// source modulus is q_j.  Otherwise the source modulus is fa.src_mod and
+// the target is q_s.
+template <int LOG_R, int TILE_LOG, bool MODUP>
 __global__ void __launch_bounds__((1 << TILE_LOG) / 8) k_ntt_r8_lift(u64* __restrict__ R, DevCtx ctx, FuseArgs fa,
                                                                      const u64* __restrict__ qmod, int n_mod,
                                                                      int log_cols, int lazy_small)
@@ -429,11 +435,17 @@ __global__ void __launch_bounds__((1 << TILE_LOG) / 8) k_ntt_r8_lift(u64* __rest
     __shared__ u64 s[T + T / 8];
     const int row = blockIdx.y;
     const int i = row % fa.nl, pg = row / fa.nl;
-    const Modulus M = ctx.mod[i];
-    const u64* __restrict__ tw = ctx.tw + (size_t)i * ctx.n;
-    const u64* __restrict__ tw_sh = ctx.tw_sh + (size_t)i * ctx.n;
-    const LiftIO io{fa.src + (size_t)pg * ctx.n, R + (size_t)row * ctx.n, ctx.mod[fa.src_mod].half,
-                    qmod[(size_t)fa.src_mod * n_mod + i], M.q, M.ratio};
+    int sm = fa.src_mod, mi = i;
+    if (MODUP) {
+        sm = pg % fa.nl;
+        const int t = i < sm ? i : i + 1;
+        mi = t == fa.nl ? ctx.p_index : t;
+    }
+    const Modulus M = ctx.mod[mi];
+    const u64* __restrict__ tw = ctx.tw + (size_t)mi * ctx.n;
+    const u64* __restrict__ tw_sh = ctx.tw_sh + (size_t)mi * ctx.n;
+    const LiftIO io{fa.src + (size_t)pg * ctx.n, R + (size_t)row * ctx.n, ctx.mod[sm].half,
+                    qmod[(size_t)sm * n_mod + mi], M.q, M.ratio};
     if (lazy_small && M.q < (1ull << 40))
         ntt_r8_body<LOG_R, TILE_LOG, true, false, false, true>(s, io, M, tw, tw_sh, ctx.log_n, log_cols, 0);
     else
@@ -596,7 +608,8 @@ bool launch_ntt_fwd_fused(const unihenn_ctx* c, u64* R, const FuseArgs& fa, int 
         // source rows once, R rows written
         LaunchTimer tm(KF_NTT_FWD_COL, 8.0 * c->n * (polys + rows), st, half * l1);
         geom(l1, &lc, &grid, &thr);
-#define LC(K, TL) k_ntt_r8_lift<K, TL><<<grid, thr, 0, st>>>(R, c->dev, fa, c->d_qmod, (int)c->primes.size(), lc, 1)
+#define LC(K, TL) \
+    k_ntt_r8_lift<K, TL, false><<<grid, thr, 0, st>>>(R, c->dev, fa, c->d_qmod, (int)c->primes.size(), lc, 1)
 #define LCT(K) case K: if (tile == 12) LC(K, 12); else LC(K, 11); break;
         switch (l1) { LCT(3) LCT(4) LCT(5) LCT(6) LCT(7) LCT(8) }
 #undef LCT
@@ -611,6 +624,44 @@ bool launch_ntt_fwd_fused(const unihenn_ctx* c, u64* R, const FuseArgs& fa, int 
         switch (l2) { LFT(3) LFT(4) LFT(5) LFT(6) LFT(7) LFT(8) }
 #undef LFT
 #undef LF
+    }
+    return true;
+}
+
+// ModUp fused with its forward NTT: dcoef holds n_src coefficient-form rows
+// (polynomial b, digit j) = row b * nl + j; modup receives rows
+// ((b * nl + j) * nl + s), the digit lifted to target s < j ? s : s + 1 and
+// transformed.  False when a pass is outside the radix-8 kernels.
+bool launch_ntt_fwd_modup(const unihenn_ctx* c, u64* modup, const u64* dcoef, int n_src, int nl, hipStream_t st)
+{
+    int l1, l2;
+    split(c, &l1, &l2);
+    const int n_rows = n_src * nl;
+    if (n_rows <= 0 || l1 < 3 || l1 > 8 || l2 < 3 || l2 > 8) return false;
+    const int tile = c->ntt_tile_log == 12 ? 12 : 11;
+    FuseArgs fa;
+    memset(&fa, 0, sizeof(fa));
+    fa.src = dcoef;
+    fa.nl = nl;
+    const double half = 0.5 * c->n * n_rows;
+    {
+        LaunchTimer tm(KF_NTT_FWD_COL, 8.0 * c->n * (n_src + n_rows), st, half * l1);
+        const int avail_log = c->log_n - l1;
+        int lc = tile - l1;
+        if (lc > avail_log) lc = avail_log;
+        const int thr = 1 << (l1 - 3 + lc);
+        dim3 grid(1 << (avail_log - lc), n_rows);
+#define LC(K, TL) \
+    k_ntt_r8_lift<K, TL, true><<<grid, thr, 0, st>>>(modup, c->dev, fa, c->d_qmod, (int)c->primes.size(), lc, 1)
+#define LCT(K) case K: if (tile == 12) LC(K, 12); else LC(K, 11); break;
+        switch (l1) { LCT(3) LCT(4) LCT(5) LCT(6) LCT(7) LCT(8) }
+#undef LCT
+#undef LC
+    }
+    {
+        LaunchTimer tm(KF_NTT_FWD_ROW, 16.0 * c->n * n_rows, st, half * l2);
+        launch_pass_r8(modup, c->dev, rowmap_modup(nl, c->n_data), n_rows, c->log_n, l2, l1, false, false, true, tile,
+                       1, st);
     }
     return true;
 }
