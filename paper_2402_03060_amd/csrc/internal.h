@@ -118,6 +118,15 @@ struct FuseArgs {
 enum KernelFamily : int;
 bool launch_ntt_fwd_fused(const unihenn_ctx* c, u64* R, const FuseArgs& fa, int n_rows, KernelFamily fam,
                           hipStream_t st);
+// sources of a gathering inverse NTT (up to UH_FUSE_MAX blocks)
+struct GatherArgs {
+    const u64* src[UH_FUSE_MAX];
+    u32 perm[UH_FUSE_MAX];
+    int stride;                      // rows per polynomial in the sources
+};
+bool launch_ntt_inv_gather(const unihenn_ctx* c, u64* dcoef, const GatherArgs& ga, int D, int B, int nl,
+                           hipStream_t st);
+bool ntt_fusable(const unihenn_ctx* c);
 // ModUp (centered lift of each digit to every other target) fused with the
 // forward NTT of the lifted rows; false when not applicable
 bool launch_ntt_fwd_modup(const unihenn_ctx* c, u64* modup, const u64* dcoef, int n_src, int nl, hipStream_t st);

@@ -60,15 +60,18 @@ struct GroupArgs {
     u64* dst[UH_GROUP_MAX];         // destinations [B][2][nl]
     const u64* key[UH_GROUP_MAX];   // switching keys (device form)
     u32 g[UH_GROUP_MAX];            // Galois element of the rotation
-    u32 gin[UH_GROUP_MAX];          // permutation applied when reading digits (hoisted: g, plain: 1)
+    u32 gin[UH_GROUP_MAX];          // permutation applied when reading ModUp digits (hoisted: g, plain: 1)
+    u32 gdig[UH_GROUP_MAX];         // permutation applied when reading the same-limb digit from dsrc
     int blk[UH_GROUP_MAX];          // ModUp block holding the element's digits
     const u64* dsrc[UH_GROUP_MAX];  // per ModUp block: NTT rows (b, j) at dsrc + (b * dstride + j) * N
     int dstride;
 };
 // ModUp of D polynomials (rows (b, j) at dsrc[d] + (b * dstride + j) * N, NTT
 // form): dcoef [D][B][nl] and modup [D][B][nl][nl]
+// perm (may be null): Galois element per block to read its rows through
+// (honoured only where the fused transforms apply: ntt_fusable)
 void group_modup(const unihenn_ctx* c, int D, const u64* const* dsrc, int dstride, int B, int nl, u64* dcoef,
-                 u64* modup, hipStream_t s);
+                 u64* modup, hipStream_t s, const u32* perm = nullptr);
 // inner product with each element's key, ModDown, and the c0 addend: aux holds
 // tau_g(src) per element ([E][B][2][nl]); with c0_only the c0 rows of aux
 // are computed here (hoisted), otherwise the caller filled aux.

@@ -442,8 +442,9 @@ __global__ void __launch_bounds__(EW_THREADS) k_group_inner(u64* __restrict__ U,
     const int klimb = t == nl ? nd : t;
     const Modulus M = ctx.mod[tm];
     const int period = wide_period(M.ratio);
-    const u32 g = ga.gin[e];
+    const u32 g = ga.gin[e], gd = ga.gdig[e];
     const u32 src = g == 1 ? (u32)k : auto_perm((u32)k, g, ctx.log_n);
+    const u32 srcd = gd == 1 ? (u32)k : (gd == g ? src : auto_perm((u32)k, gd, ctx.log_n));
     const u64* __restrict__ key = ga.key[e];
     const u64* __restrict__ dsrc = ga.dsrc[ga.blk[e]];
     const int blk = ga.blk[e];
@@ -465,7 +466,7 @@ __global__ void __launch_bounds__(EW_THREADS) k_group_inner(u64* __restrict__ U,
             if (j < nl) {
                 u64 d;
                 if (t == j) {
-                    d = dsrc[((size_t)b * ga.dstride + j) * n + src];
+                    d = dsrc[((size_t)b * ga.dstride + j) * n + srcd];
                 } else {
                     const int s = t < j ? t : t - 1;
                     d = modup[((((size_t)blk * batch + b) * nl + j) * nl + s) * n + src];
@@ -513,8 +514,20 @@ __global__ void k_group_sub_scale(GroupArgs ga, const u64* __restrict__ U, const
 }  // namespace
 
 void group_modup(const unihenn_ctx* c, int D, const u64* const* dsrc, int dstride, int B, int nl, u64* dcoef,
-                 u64* modup, hipStream_t s)
+                 u64* modup, hipStream_t s, const u32* perm)
 {
+    if (ntt_fusable(c)) {
+        // the inverse NTT gathers (and permutes) its rows, the forward NTT lifts them
+        GatherArgs gta;
+        memset(&gta, 0, sizeof(gta));
+        for (int d = 0; d < D; ++d) {
+            gta.src[d] = dsrc[d];
+            gta.perm[d] = perm ? perm[d] : 1u;
+        }
+        gta.stride = dstride;
+        if (launch_ntt_inv_gather(c, dcoef, gta, D, B, nl, s) && launch_ntt_fwd_modup(c, modup, dcoef, D * B * nl, nl, s))
+            return;
+    }
     GroupArgs ga;
     memset(&ga, 0, sizeof(ga));
     for (int d = 0; d < D; ++d) ga.dsrc[d] = dsrc[d];

@@ -1079,12 +1079,35 @@ struct Exec {
                     ga.dstride = 2 * nl;
                     for (int e = 0; e < ga.E; ++e) {
                         ga.blk[e] = 0;
-                        ga.gin[e] = ga.g[e];
+                        ga.gin[e] = ga.gdig[e] = ga.g[e];
                     }
                     group_switch(c, ga, B, nl, true, w.pmodup, w.aux, w.U, w.Up, w.R, s);
                 }
                 i = j;
             }
+        } else if (ntt_fusable(c)) {
+            // each rotation decomposes its own tau(c1): the inverse NTT reads
+            // c1 through the automorphism, the inner product reads the
+            // digit of the same limb through it, and the ModDown takes tau(c0)
+            // straight from the source
+            for (size_t k = 0; k < run.size(); k += Emax) {
+                GroupArgs ga;
+                fill(ga, run, k, (int)std::min<size_t>(Emax, run.size() - k));
+                ga.dstride = 2 * nl;
+                std::vector<const u64*> d(ga.E);
+                std::vector<u32> perm(ga.E);
+                for (int e = 0; e < ga.E; ++e) {
+                    ga.blk[e] = e;
+                    ga.gin[e] = 1;                              // digits of tau(c1) itself
+                    ga.gdig[e] = ga.g[e];                       // limb j of tau(c1), read from c1
+                    ga.dsrc[e] = ga.src[e] + (size_t)nl * rn;  // c1 of src_e
+                    d[e] = ga.dsrc[e];
+                    perm[e] = ga.g[e];
+                }
+                group_modup(c, ga.E, d.data(), 2 * nl, B, nl, w.dcoef, w.modup, s, perm.data());
+                group_switch(c, ga, B, nl, true, w.modup, w.aux, w.U, w.Up, w.R, s);
+            }
+            modup_owner = -1;
         } else {
             for (size_t k = 0; k < run.size(); k += Emax) {
                 GroupArgs ga;
@@ -1093,7 +1116,7 @@ struct Exec {
                 std::vector<const u64*> d(ga.E);
                 for (int e = 0; e < ga.E; ++e) {
                     ga.blk[e] = e;
-                    ga.gin[e] = 1;
+                    ga.gin[e] = ga.gdig[e] = 1;
                     ga.dsrc[e] = w.aux + ((size_t)e * B * 2 * nl + nl) * rn;  // c1 of tau(src_e)
                     d[e] = ga.dsrc[e];
                 }

@@ -452,6 +452,61 @@ __global__ void __launch_bounds__((1 << TILE_LOG) / 8) k_ntt_r8_lift(u64* __rest
         ntt_r8_body<LOG_R, TILE_LOG, true, false, false, false>(s, io, M, tw, tw_sh, ctx.log_n, log_cols, 0);
 }
 
+// First (row) pass of an inverse NTT that gathers its input: row
+// r = (blk * B + b) * nl + j reads limb j of polynomial b of source block blk,
+// through the automorphism of Galois element perm[blk] when it is not 1.
+struct GatherIO {
+    const u64* __restrict__ src;
+    u64* __restrict__ a;
+    u32 perm;
+    int log_n;
+    __device__ __forceinline__ u64 load(int g) const
+    {
+        if (perm == 1) return src[g];
+        const u32 bits = (u32)log_n;
+        const u32 bg = __brev((u32)g) >> (32 - bits);
+        const u32 e = (u32)(((u64)perm * (2u * bg + 1u)) & ((2u << bits) - 1u));
+        return src[__brev((e - 1u) >> 1) >> (32 - bits)];
+    }
+    __device__ __forceinline__ void load2(int g, u64& v0, u64& v1) const
+    {
+        if (perm == 1) {
+            const ulonglong2 v = *reinterpret_cast<const ulonglong2*>(src + g);
+            v0 = v.x;
+            v1 = v.y;
+        } else {
+            v0 = load(g);
+            v1 = load(g + 1);
+        }
+    }
+    __device__ __forceinline__ void store(int g, u64 v) const { a[g] = v; }
+    __device__ __forceinline__ void store2(int g, u64 v0, u64 v1) const
+    {
+        *reinterpret_cast<ulonglong2*>(a + g) = make_ulonglong2(v0, v1);
+    }
+};
+
+template <int LOG_R, int TILE_LOG>
+__global__ void __launch_bounds__((1 << TILE_LOG) / 8) k_intt_r8_gather(u64* __restrict__ dcoef, DevCtx ctx,
+                                                                        GatherArgs ga, int nl, int B, int log_cols,
+                                                                        int sigma0, int lazy_small)
+{
+    constexpr int T = 1 << TILE_LOG;
+    __shared__ u64 s[T + T / 8];
+    const int row = blockIdx.y;
+    const int j = row % nl, pb = row / nl;
+    const int blk = pb / B, b = pb % B;
+    const Modulus M = ctx.mod[j];
+    const u64* __restrict__ tw = ctx.itw + (size_t)j * ctx.n;
+    const u64* __restrict__ tw_sh = ctx.itw_sh + (size_t)j * ctx.n;
+    const GatherIO io{ga.src[blk] + ((size_t)b * ga.stride + j) * ctx.n, dcoef + (size_t)row * ctx.n, ga.perm[blk],
+                      ctx.log_n};
+    if (lazy_small && M.q < (1ull << 40))
+        ntt_r8_body<LOG_R, TILE_LOG, false, true, false, true>(s, io, M, tw, tw_sh, ctx.log_n, log_cols, sigma0);
+    else
+        ntt_r8_body<LOG_R, TILE_LOG, false, true, false, false>(s, io, M, tw, tw_sh, ctx.log_n, log_cols, sigma0);
+}
+
 template <int LOG_R, int TILE_LOG>
 __global__ void __launch_bounds__((1 << TILE_LOG) / 8) k_ntt_r8_finish(u64* __restrict__ R, DevCtx ctx, FuseArgs fa,
                                                                        int log_cols, int sigma0, int lazy_small)
@@ -664,4 +719,45 @@ bool launch_ntt_fwd_modup(const unihenn_ctx* c, u64* modup, const u64* dcoef, in
                        1, st);
     }
     return true;
+}
+
+// Inverse NTT of gathered rows: dcoef row (blk * B + b) * nl + j is limb j
+// of polynomial b of block blk (rows at ga.src[blk] + (b * ga.stride + j) * N),
+// read through the automorphism ga.perm[blk]; the first pass loads them
+// directly.  False when a pass is outside the radix-8 kernels.
+bool launch_ntt_inv_gather(const unihenn_ctx* c, u64* dcoef, const GatherArgs& ga, int D, int B, int nl,
+                           hipStream_t st)
+{
+    int l1, l2;
+    split(c, &l1, &l2);
+    const int n_rows = D * B * nl;
+    if (n_rows <= 0 || l1 < 3 || l1 > 8 || l2 < 3 || l2 > 8) return false;
+    const int tile = c->ntt_tile_log == 12 ? 12 : 11;
+    const double half = 0.5 * c->n * n_rows;
+    {
+        LaunchTimer tm(KF_NTT_INV_ROW, 16.0 * c->n * n_rows, st, half * l2);
+        const int avail_log = c->log_n - l2;
+        int lc = tile - l2;
+        if (lc > avail_log) lc = avail_log;
+        const int thr = 1 << (l2 - 3 + lc);
+        dim3 grid(1 << (avail_log - lc), n_rows);
+#define LG(K, TL) k_intt_r8_gather<K, TL><<<grid, thr, 0, st>>>(dcoef, c->dev, ga, nl, B, lc, l1, 1)
+#define LGT(K) case K: if (tile == 12) LG(K, 12); else LG(K, 11); break;
+        switch (l2) { LGT(3) LGT(4) LGT(5) LGT(6) LGT(7) LGT(8) }
+#undef LGT
+#undef LG
+    }
+    {
+        LaunchTimer tm(KF_NTT_INV_COL, 16.0 * c->n * n_rows, st, half * l1);
+        launch_pass_r8(dcoef, c->dev, rowmap_ct(nl), n_rows, c->log_n, l1, 0, true, true, true, tile, 1, st);
+    }
+    return true;
+}
+
+// whether the fused transforms apply (both passes in the radix-8 kernels)
+bool ntt_fusable(const unihenn_ctx* c)
+{
+    int l1, l2;
+    split(c, &l1, &l2);
+    return l1 >= 3 && l1 <= 8 && l2 >= 3 && l2 <= 8;
 }
