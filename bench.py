@@ -156,10 +156,10 @@ PROFILES = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles")
 
 
 def measured_traffic(family: str, workload: str = "lenet1_plain"):
-    """Measured over algorithmic HBM bytes (read, write) of the family's
-    kernel from the committed rocprofv3 PMC summary, or None when there is
-    none or the kernel source has changed since the counters were taken."""
-    import hashlib
+    """HBM bytes per launch of a kernel family from the committed rocprofv3
+    PMC summary, or None when there is none or any kernel source has changed
+    since the counters were taken."""
+    from paper_2402_03060_amd.profiling import source_digest
     path = os.path.join(PROFILES, f"{family}_{workload}_traffic.txt")
     if not os.path.exists(path):
         return None
@@ -168,11 +168,13 @@ def measured_traffic(family: str, workload: str = "lenet1_plain"):
         if "=" in line and not line.startswith("#"):
             k, v = line.split("=", 1)
             kv[k.strip()] = v.strip()
-    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2402_03060_amd", "csrc", kv["source"])
-    if hashlib.sha256(open(src, "rb").read()).hexdigest() != kv.get("source_sha256"):
+    csrc = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2402_03060_amd", "csrc")
+    if source_digest(csrc) != kv.get("source_sha256"):
         return None
-    return {"read_over_algorithmic": float(kv["read_over_algorithmic"]),
-            "write_over_algorithmic": float(kv["write_over_algorithmic"]),
+    return {"bytes_per_launch": float(kv["measured_bytes_per_launch"]),
+            "read_bytes_per_launch": float(kv["measured_read_bytes_per_launch"]),
+            "write_bytes_per_launch": float(kv["measured_write_bytes_per_launch"]),
+            "measured_over_algorithmic": float(kv["measured_over_algorithmic"]),
             "fetch_scale": float(kv["fetch_scale"]), "write_scale": float(kv["write_scale"]),
             "source": os.path.basename(path)}
 
@@ -373,9 +375,7 @@ def main():
     rf = roofline_entry(stats)
     tr = measured_traffic(rf["kernel"])
     if tr is not None:
-        # algorithmic bytes per launch are half reads, half writes for every NTT pass
-        half = rf["bytes_per_launch"] / 2
-        rf["traffic"] = round(half * tr["read_over_algorithmic"] + half * tr["write_over_algorithmic"])
+        rf["traffic"] = round(tr["bytes_per_launch"])
         rf["traffic_detail"] = tr
     res["roofline"] = rf
     res["kernel_families"] = family_table(stats, args.steps)

@@ -422,11 +422,12 @@ struct FinishIO {
     }
 };
 
-// MODUP: rows r = (pg * nl) + s hold digit j = pg % nl of source row pg,
-// lifted to target t = s < j ? s : s + 1 (t = nl: the special prime); the
-// source modulus is q_j.  Otherwise the source modulus is fa.src_mod and
-// the target is q_s.
-template <int LOG_R, int TILE_LOG, bool MODUP>
+// TAG names the step the kernel serves (0 ModDown, 1 rescale, 2 ModUp), so
+// that profiles can tell them apart.  ModUp: rows r = (pg * nl) + s hold
+// digit j = pg % nl of source row pg, lifted to target t = s < j ? s : s + 1
+// (t = nl: the special prime); the source modulus is q_j.  Otherwise the
+// source modulus is fa.src_mod and the target is q_s.
+template <int LOG_R, int TILE_LOG, int TAG>
 __global__ void __launch_bounds__((1 << TILE_LOG) / 8) k_ntt_r8_lift(u64* __restrict__ R, DevCtx ctx, FuseArgs fa,
                                                                      const u64* __restrict__ qmod, int n_mod,
                                                                      int log_cols, int lazy_small)
@@ -435,6 +436,7 @@ __global__ void __launch_bounds__((1 << TILE_LOG) / 8) k_ntt_r8_lift(u64* __rest
     __shared__ u64 s[T + T / 8];
     const int row = blockIdx.y;
     const int i = row % fa.nl, pg = row / fa.nl;
+    constexpr bool MODUP = TAG == 2;
     int sm = fa.src_mod, mi = i;
     if (MODUP) {
         sm = pg % fa.nl;
@@ -507,7 +509,7 @@ __global__ void __launch_bounds__((1 << TILE_LOG) / 8) k_intt_r8_gather(u64* __r
         ntt_r8_body<LOG_R, TILE_LOG, false, true, false, false>(s, io, M, tw, tw_sh, ctx.log_n, log_cols, sigma0);
 }
 
-template <int LOG_R, int TILE_LOG>
+template <int LOG_R, int TILE_LOG, int TAG>
 __global__ void __launch_bounds__((1 << TILE_LOG) / 8) k_ntt_r8_finish(u64* __restrict__ R, DevCtx ctx, FuseArgs fa,
                                                                        int log_cols, int sigma0, int lazy_small)
 {
@@ -661,11 +663,14 @@ bool launch_ntt_fwd_fused(const unihenn_ctx* c, u64* R, const FuseArgs& fa, int 
     dim3 grid;
     {
         // source rows once, R rows written
-        LaunchTimer tm(KF_NTT_FWD_COL, 8.0 * c->n * (polys + rows), st, half * l1);
+        LaunchTimer tm(fam, 8.0 * c->n * (polys + rows), st, half * l1);
         geom(l1, &lc, &grid, &thr);
-#define LC(K, TL) \
-    k_ntt_r8_lift<K, TL, false><<<grid, thr, 0, st>>>(R, c->dev, fa, c->d_qmod, (int)c->primes.size(), lc, 1)
-#define LCT(K) case K: if (tile == 12) LC(K, 12); else LC(K, 11); break;
+#define LC(K, TL)                                                                                          \
+    if (fam == KF_RESCALE)                                                                                 \
+        k_ntt_r8_lift<K, TL, 1><<<grid, thr, 0, st>>>(R, c->dev, fa, c->d_qmod, (int)c->primes.size(), lc, 1); \
+    else                                                                                                   \
+        k_ntt_r8_lift<K, TL, 0><<<grid, thr, 0, st>>>(R, c->dev, fa, c->d_qmod, (int)c->primes.size(), lc, 1)
+#define LCT(K) case K: if (tile == 12) { LC(K, 12); } else { LC(K, 11); } break;
         switch (l1) { LCT(3) LCT(4) LCT(5) LCT(6) LCT(7) LCT(8) }
 #undef LCT
 #undef LC
@@ -674,8 +679,10 @@ bool launch_ntt_fwd_fused(const unihenn_ctx* c, u64* R, const FuseArgs& fa, int 
         // R rows read, minuend rows read, addend rows (c = 0 or both), outputs written
         LaunchTimer tm(fam, 8.0 * c->n * rows * 3.5, st, half * l2);
         geom(l2, &lc, &grid, &thr);
-#define LF(K, TL) k_ntt_r8_finish<K, TL><<<grid, thr, 0, st>>>(R, c->dev, fa, lc, l1, 1)
-#define LFT(K) case K: if (tile == 12) LF(K, 12); else LF(K, 11); break;
+#define LF(K, TL)                                                                   \
+    if (fam == KF_RESCALE) k_ntt_r8_finish<K, TL, 1><<<grid, thr, 0, st>>>(R, c->dev, fa, lc, l1, 1); \
+    else k_ntt_r8_finish<K, TL, 0><<<grid, thr, 0, st>>>(R, c->dev, fa, lc, l1, 1)
+#define LFT(K) case K: if (tile == 12) { LF(K, 12); } else { LF(K, 11); } break;
         switch (l2) { LFT(3) LFT(4) LFT(5) LFT(6) LFT(7) LFT(8) }
 #undef LFT
 #undef LF
@@ -700,14 +707,14 @@ bool launch_ntt_fwd_modup(const unihenn_ctx* c, u64* modup, const u64* dcoef, in
     fa.nl = nl;
     const double half = 0.5 * c->n * n_rows;
     {
-        LaunchTimer tm(KF_NTT_FWD_COL, 8.0 * c->n * (n_src + n_rows), st, half * l1);
+        LaunchTimer tm(KF_MODUP, 8.0 * c->n * (n_src + n_rows), st, half * l1);
         const int avail_log = c->log_n - l1;
         int lc = tile - l1;
         if (lc > avail_log) lc = avail_log;
         const int thr = 1 << (l1 - 3 + lc);
         dim3 grid(1 << (avail_log - lc), n_rows);
 #define LC(K, TL) \
-    k_ntt_r8_lift<K, TL, true><<<grid, thr, 0, st>>>(modup, c->dev, fa, c->d_qmod, (int)c->primes.size(), lc, 1)
+    k_ntt_r8_lift<K, TL, 2><<<grid, thr, 0, st>>>(modup, c->dev, fa, c->d_qmod, (int)c->primes.size(), lc, 1)
 #define LCT(K) case K: if (tile == 12) LC(K, 12); else LC(K, 11); break;
         switch (l1) { LCT(3) LCT(4) LCT(5) LCT(6) LCT(7) LCT(8) }
 #undef LCT

@@ -2,20 +2,36 @@
 
     python -m paper_2402_03060_amd.profiling stats <kernel_stats.csv> --title T --command C -o out.txt
     python -m paper_2402_03060_amd.profiling traffic --fetch F.csv --write W.csv \
-        --copy-fetch CF.csv --copy-write CW.csv --copy-bytes B --kernel SUBSTR \
-        --bytes-per-item 64 --family ntt_fwd_row --source csrc/ntt.hip --title T --command C -o out.txt
+        --copy-fetch CF.csv --copy-write CW.csv --copy-bytes B --family ks_inner \
+        --bench-json bench.json --evals 3 --title T --command C -o out.txt
 
-`traffic` turns FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of one kernel into
-bytes, calibrated by what the same counters read for plain device copies of
-known size, and compares them with the kernel's algorithmic bytes: Grid_Size
-work-items times the bytes each work-item reads (and writes) once.
+`traffic` turns FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of one kernel
+family into bytes per launch, calibrated by what the same counters read for
+plain device copies of known size, and compares them with the family's
+algorithmic bytes per launch from the library's own launch statistics.
 """
 from __future__ import annotations
 
 import argparse
 import csv
 import hashlib
+import json
 import os
+import re
+
+# kernel-name patterns of each family of the library's launch statistics
+FAMILY_KERNELS = {
+    "ntt_fwd_col": r"k_ntt_r8<\d+, \d+, true, false, false>|k_ntt_fwd<true",
+    "ntt_fwd_row": r"k_ntt_r8<\d+, \d+, false, false, true>|k_ntt_fwd<false",
+    "ntt_inv_row": r"k_ntt_r8<\d+, \d+, false, true, false>|k_intt_r8_gather<|k_ntt_inv<false",
+    "ntt_inv_col": r"k_ntt_r8<\d+, \d+, true, true, true>|k_ntt_inv<true",
+    "modup": r"k_ntt_r8_lift<\d+, \d+, 2>|k_modup",
+    "ks_inner": r"k_group_inner<|k_ks_inner<",
+    "moddown": r"k_ntt_r8_lift<\d+, \d+, 0>|k_ntt_r8_finish<\d+, \d+, 0>|k_relin_combine|k_group_sub_scale\(",
+    "rescale": r"k_ntt_r8_lift<\d+, \d+, 1>|k_ntt_r8_finish<\d+, \d+, 1>|k_group_sub_scale2",
+    "mac": r"k_mac_multi<|k_mac<|k_mac_group<",
+    "add": r"k_group_add|k_add\(|k_add_plain",
+}
 
 
 def _rows(path):
@@ -29,67 +45,91 @@ def kernel_stats_summary(path: str, title: str, command: str, top: int = 40) -> 
     out = [f"# {title}", f"# command: {command}", "# durations in ns",
            "name | calls | total_ns | avg_ns | percent"]
     for r in rows[:top]:
-        name = r["Name"].replace("(anonymous namespace)::", "")
-        name = name.split("(unsigned long")[0].split("(DevCtx")[0]
-        out.append(f"{name} | {r['Calls']} | {r['TotalDurationNs']} | {float(r['AverageNs']):.1f} | "
+        name = r["Name"].replace("(anonymous namespace)::", "").replace("void ", "")
+        depth, cut = 0, len(name)
+        for i, ch in enumerate(name):        # drop the parameter list
+            if ch == "<":
+                depth += 1
+            elif ch == ">":
+                depth -= 1
+            elif ch == "(" and depth == 0:
+                cut = i
+                break
+        out.append(f"{name[:cut]} | {r['Calls']} | {r['TotalDurationNs']} | {float(r['AverageNs']):.1f} | "
                    f"{float(r['Percentage']):.2f}")
     return "\n".join(out) + "\n"
 
 
-def _counter_sum(path: str, counter: str, substr: str):
-    n, kib, items = 0, 0.0, 0
+def _counter_sum(path: str, counter: str, pattern: str):
+    rx = re.compile(pattern)
+    n, kib = 0, 0.0
     for r in _rows(path):
-        if r["Counter_Name"] != counter or substr not in r["Kernel_Name"]:
+        if r["Counter_Name"] != counter or not rx.search(r["Kernel_Name"]):
             continue
         n += 1
         kib += float(r["Counter_Value"])
-        items += int(r["Grid_Size"])
-    return n, kib, items
+    return n, kib
 
 
-def traffic_summary(fetch: str, write: str, copy_fetch: str, copy_write: str, copy_bytes: int, kernel: str,
-                    bytes_per_item: int, family: str, source: str, title: str, command: str) -> str:
-    cn_f, cf_kib, _ = _counter_sum(copy_fetch, "FETCH_SIZE", "copyBuffer")
-    cn_w, cw_kib, _ = _counter_sum(copy_write, "WRITE_SIZE", "copyBuffer")
-    # the largest copies dominate; scale = true KiB per copy / counted KiB per copy
+def source_digest(csrc: str) -> str:
+    """SHA-256 over every kernel source file (sorted names and contents)."""
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".h", ".cpp")):
+            h.update(name.encode())
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()
+
+
+def _copy_scale(path: str, counter: str, true_kib: float) -> tuple:
+    vals = sorted(float(r["Counter_Value"]) for r in _rows(path)
+                  if r["Counter_Name"] == counter and "copyBuffer" in r["Kernel_Name"])[-3:]
+    mean = sum(vals) / len(vals)
+    return true_kib / mean, mean
+
+
+def traffic_summary(fetch: str, write: str, copy_fetch: str, copy_write: str, copy_bytes: int, family: str,
+                    bench_json: str, evals: int, csrc: str, title: str, command: str) -> str:
+    """HBM bytes per launch of one kernel family: FETCH_SIZE and WRITE_SIZE
+    summed over the family's dispatches, each counter scaled by what it reads
+    for device copies of known size, divided by the launches of `evals`
+    evaluations (launches per evaluation from the bench JSON's family table
+    of the same code), against the family's algorithmic bytes per launch
+    from the same table."""
     true_kib = copy_bytes / 1024.0
-    big_f = [float(r["Counter_Value"]) for r in _rows(copy_fetch)
-             if r["Counter_Name"] == "FETCH_SIZE" and "copyBuffer" in r["Kernel_Name"]]
-    big_w = [float(r["Counter_Value"]) for r in _rows(copy_write)
-             if r["Counter_Name"] == "WRITE_SIZE" and "copyBuffer" in r["Kernel_Name"]]
-    big_f = sorted(big_f)[-3:]
-    big_w = sorted(big_w)[-3:]
-    fetch_scale = true_kib / (sum(big_f) / len(big_f))
-    write_scale = true_kib / (sum(big_w) / len(big_w))
-    nf, f_kib, items_f = _counter_sum(fetch, "FETCH_SIZE", kernel)
-    nw, w_kib, items_w = _counter_sum(write, "WRITE_SIZE", kernel)
+    fscale, fmean = _copy_scale(copy_fetch, "FETCH_SIZE", true_kib)
+    wscale, wmean = _copy_scale(copy_write, "WRITE_SIZE", true_kib)
+    pat = FAMILY_KERNELS[family]
+    nf, f_kib = _counter_sum(fetch, "FETCH_SIZE", pat)
+    nw, w_kib = _counter_sum(write, "WRITE_SIZE", pat)
     if not nf or not nw:
-        raise SystemExit(f"no dispatches of {kernel!r} in the counter files")
-    read_b = f_kib * 1024 * fetch_scale
-    write_b = w_kib * 1024 * write_scale
-    alg_r = items_f * bytes_per_item
-    alg_w = items_w * bytes_per_item
-    sha = hashlib.sha256(open(source, "rb").read()).hexdigest()
+        raise SystemExit(f"no dispatches of family {family!r} in the counter files")
+    with open(bench_json) as f:
+        fam = json.load(f)["kernel_families"][family]
+    launches = fam["launches_per_step"] * evals
+    alg = fam["gbs"] * 1e9 * fam["avg_us"] * 1e-6       # algorithmic bytes per launch
+    read_b = f_kib * 1024 * fscale / launches
+    write_b = w_kib * 1024 * wscale / launches
     lines = [
         f"# {title}",
         f"# command: {command}",
         f"# calibration: FETCH_SIZE / WRITE_SIZE of device copies of {copy_bytes} bytes",
-        f"kernel = {kernel}",
         f"family = {family}",
+        f"kernels = {pat}",
         f"copy_true_kib = {true_kib:.0f}",
-        f"copy_fetch_kib_mean = {sum(big_f) / len(big_f):.2f}",
-        f"copy_write_kib_mean = {sum(big_w) / len(big_w):.2f}",
-        f"fetch_scale = {fetch_scale:.4f}",
-        f"write_scale = {write_scale:.4f}",
+        f"copy_fetch_kib_mean = {fmean:.2f}",
+        f"copy_write_kib_mean = {wmean:.2f}",
+        f"fetch_scale = {fscale:.4f}",
+        f"write_scale = {wscale:.4f}",
         f"dispatches = {nf}",
-        f"measured_read_bytes_per_dispatch = {read_b / nf:.1f}",
-        f"measured_write_bytes_per_dispatch = {write_b / nw:.1f}",
-        f"algorithmic_read_bytes_per_dispatch = {alg_r / nf:.1f}",
-        f"algorithmic_write_bytes_per_dispatch = {alg_w / nw:.1f}",
-        f"read_over_algorithmic = {read_b / alg_r:.4f}",
-        f"write_over_algorithmic = {write_b / alg_w:.4f}",
-        f"source = {os.path.basename(source)}",
-        f"source_sha256 = {sha}",
+        f"launches = {launches:.0f}",
+        f"measured_read_bytes_per_launch = {read_b:.1f}",
+        f"measured_write_bytes_per_launch = {write_b:.1f}",
+        f"measured_bytes_per_launch = {read_b + write_b:.1f}",
+        f"algorithmic_bytes_per_launch = {alg:.1f}",
+        f"measured_over_algorithmic = {(read_b + write_b) / alg:.4f}",
+        f"source_sha256 = {source_digest(csrc)}",
     ]
     return "\n".join(lines) + "\n"
 
@@ -103,17 +143,18 @@ def main():
     s.add_argument("--command", required=True)
     s.add_argument("-o", required=True)
     t = sub.add_parser("traffic")
-    for k in ("fetch", "write", "copy-fetch", "copy-write", "kernel", "family", "source", "title", "command"):
+    for k in ("fetch", "write", "copy-fetch", "copy-write", "family", "bench-json", "title", "command"):
         t.add_argument("--" + k, required=True)
     t.add_argument("--copy-bytes", type=int, required=True)
-    t.add_argument("--bytes-per-item", type=int, required=True)
+    t.add_argument("--evals", type=int, required=True, help="evaluations the counted run made")
+    t.add_argument("--csrc", default=os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc"))
     t.add_argument("-o", required=True)
     a = ap.parse_args()
     if a.cmd == "stats":
         text = kernel_stats_summary(a.csv, a.title, a.command)
     else:
-        text = traffic_summary(a.fetch, a.write, a.copy_fetch, a.copy_write, a.copy_bytes, a.kernel,
-                               a.bytes_per_item, a.family, a.source, a.title, a.command)
+        text = traffic_summary(a.fetch, a.write, a.copy_fetch, a.copy_write, a.copy_bytes, a.family, a.bench_json,
+                               a.evals, a.csrc, a.title, a.command)
     with open(a.o, "w") as f:
         f.write(text)
     print(text)
