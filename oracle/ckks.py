@@ -78,6 +78,7 @@ def lib():
                                     C.POINTER(_u64p)]
         L.or_add.argtypes = [_vp, _u64p, _u64p, C.c_int, C.c_int, _u64p]
         L.or_square_relin.argtypes = [_vp, _u64p, C.c_int, _vp, _u64p]
+        L.or_mul_relin.argtypes = [_vp, _u64p, _u64p, C.c_int, _vp, _u64p]
         L.or_rescale.argtypes = [_vp, _u64p, C.c_int, C.c_int, _u64p]
         _lib = L
     return _lib
@@ -328,6 +329,16 @@ class OracleCKKS:
         if lib().or_square_relin(self.ctx, _p64(np.ascontiguousarray(ct.data)), ct.nl, rlk, _p64(out)) != 0:
             raise ValueError("key level")
         return Ciphertext(out, ct.scale * ct.scale)
+
+    def mul_relin(self, a: Ciphertext, b: Ciphertext, rlk) -> Ciphertext:
+        """Mul(C) + relinearisation of two ciphertexts at the same level."""
+        if a.nl != b.nl:
+            raise ValueError("operands at different levels")
+        out = np.zeros_like(a.data)
+        if lib().or_mul_relin(self.ctx, _p64(np.ascontiguousarray(a.data)), _p64(np.ascontiguousarray(b.data)),
+                              a.nl, rlk, _p64(out)) != 0:
+            raise ValueError("key level")
+        return Ciphertext(out, a.scale * b.scale)
 
     def rescale(self, ct: Ciphertext) -> Ciphertext:
         nl = ct.nl

@@ -837,6 +837,42 @@ int or_square_relin(void *vc, const u64 *ct, int nl, void *vk, u64 *out)
     return rc;
 }
 
+/* Mul(C) of Section II-B with relinearisation: the tensor product
+ * (a0 b0, a0 b1 + a1 b0, a1 b1) of two ciphertexts at nl limbs, then the
+ * key switch of the last part with the key of s^2 added in.  out: [2][nl][N]. */
+int or_mul_relin(void *vc, const u64 *a, const u64 *b, int nl, void *vk, u64 *out)
+{
+    ctx_t *c = (ctx_t *)vc;
+    int n = c->n;
+    size_t lsz = (size_t)nl * n;
+    u64 *d0 = (u64 *)malloc(sizeof(u64) * lsz), *d1 = (u64 *)malloc(sizeof(u64) * lsz),
+        *d2 = (u64 *)malloc(sizeof(u64) * lsz), *t = (u64 *)malloc(sizeof(u64) * n),
+        *ks = (u64 *)malloc(sizeof(u64) * 2 * lsz);
+    for (int i = 0; i < nl; i++) {
+        u64 q = c->mod[i].q;
+        const u64 *a0 = a + (size_t)i * n, *a1 = a + lsz + (size_t)i * n;
+        const u64 *b0 = b + (size_t)i * n, *b1 = b + lsz + (size_t)i * n;
+        or_poly_mul(vc, i, a0, b0, d0 + (size_t)i * n);
+        or_poly_mul(vc, i, a0, b1, d1 + (size_t)i * n);
+        or_poly_mul(vc, i, a1, b0, t);
+        for (int j = 0; j < n; j++) d1[(size_t)i * n + j] = add_mod(d1[(size_t)i * n + j], t[j], q);
+        or_poly_mul(vc, i, a1, b1, d2 + (size_t)i * n);
+    }
+    int rc = or_keyswitch(vc, d2, nl, vk, ks);
+    if (rc == 0) {
+        for (int i = 0; i < nl; i++) {
+            u64 q = c->mod[i].q;
+            for (int j = 0; j < n; j++) {
+                size_t o = (size_t)i * n + j;
+                out[o] = add_mod(d0[o], ks[o], q);
+                out[lsz + o] = add_mod(d1[o], ks[lsz + o], q);
+            }
+        }
+    }
+    free(d0); free(d1); free(d2); free(t); free(ks);
+    return rc;
+}
+
 /* Rescale by the last prime q_l (l = nl-1): exact rounding division,
  * c'[i] = (c[i] - centered([c]_{q_l})) q_l^-1 mod q_i.  n_polys polynomials;
  * in: [n_polys][nl][N], out: [n_polys][nl-1][N]. */

@@ -49,6 +49,14 @@ class PlanError(ValueError):
     pass
 
 
+# degree-2 approximation of ReLU (Section V-A): f(x) = a + b x + c x^2
+RELU_APPROX = (0.375373, 0.5, 0.117071)
+
+
+def relu_coeffs(lay) -> tuple:
+    return tuple(lay.get("coeffs", RELU_APPROX))
+
+
 def kernel_hw(lay) -> tuple[int, int, int, int]:
     """(K_h, K_w, S_h, S_w): a 1D convolution has a 1 x K kernel."""
     if lay.get("dims") == 1:
@@ -132,23 +140,26 @@ def shapes(inp: dict, layers):
 def network_depth(inp: dict, layers) -> int:
     d = 0
     prev, I, pending = "input", 1, 1.0
-    H = inp["h"]
+    H, W = inp["h"], inp["w"]
     for lay in layers:
         k = lay["kind"]
         if k == "conv":
             d += 1
             Kh, K, Sh, S = kernel_hw(lay)
             prev, I, pending = "conv", I * S, 1.0
-            H = (H - Kh) // Sh + 1
+            H, W = (H - Kh) // Sh + 1, (W - K) // S + 1
         elif k == "square":
             d += 1
             pending *= pending
+        elif k == "relu_approx":
+            d += 2
+            prev, pending = "relu", 1.0
         elif k == "avgpool":
             prev, I = "avgpool", I * lay["c"]
             pending /= lay["c"] ** 2
-            H = H // lay["c"]
+            H, W = H // lay["c"], W // lay["c"]
         elif k == "flatten":
-            d += int(prev == "avgpool" or I > 1 or pending != 1.0)
+            d += int(prev == "avgpool" or (I > 1 and W > 1) or pending != 1.0)
             d += int(H > 1)
         elif k == "fc":
             d += 1
@@ -176,6 +187,9 @@ def cnn_fp64(x: np.ndarray, layers, params) -> np.ndarray:
             a = out
         elif k == "square":
             a = a * a
+        elif k == "relu_approx":
+            ca, cb, cc = relu_coeffs(lay)
+            a = ca + cb * a + cc * a * a
         elif k == "avgpool":
             c = lay["c"]
             C, H, W = a.shape
@@ -238,6 +252,14 @@ class SlotEval:
         self.count.relin += 1
         self.count.rescale += 1
         return x * x
+
+    def mul(self, a, b):
+        self.count.relin += 1
+        self.count.rescale += 1
+        return a * b
+
+    def drop_to(self, x, like):
+        return x
 
 
 class CkksEval:
@@ -304,6 +326,15 @@ class CkksEval:
         self.count.rescale += 1
         return self.ck.rescale(self.ck.square_relin(x, self.rlk))
 
+    def mul(self, a, b):
+        self.count.relin += 1
+        self.count.rescale += 1
+        return self.ck.rescale(self.ck.mul_relin(a, b, self.rlk))
+
+    def drop_to(self, x, like):
+        """x with its top limbs discarded down to like's level (scale kept)."""
+        return self.ck.limb_drop(x, like.nl)
+
 
 # --------------------------------------------------------------------------
 # the layers
@@ -361,6 +392,8 @@ class Net:
             elif k == "square":
                 xs = [ev.square(x) for x in xs]
                 L.pending = L.pending * L.pending
+            elif k == "relu_approx":
+                xs, L = self._relu(ev, xs, L, lay)
             elif k == "avgpool":
                 xs, L = self._avgpool(ev, xs, L, lay)
             elif k == "flatten":
@@ -409,6 +442,35 @@ class Net:
         L2 = Layout("map", co, Ho, Wo, I_out, L.W_img, list(range(co)), [0] * co, "conv", 1.0)
         return outs, L2
 
+    def _valid_positions(self, L, ct: int) -> list:
+        """In-sample slots of the valid values that ciphertext `ct` holds."""
+        if L.kind == "vec":
+            return list(range(L.length))
+        pos = []
+        for c in range(L.C):
+            if L.ch_ct[c] == ct:
+                pos.extend(L.ch_off[c] + L.I * (x + L.W_img * y) for y in range(L.H) for x in range(L.W))
+        return pos
+
+    # Section V-A: f(x) = a + b x + c x^2, as x (c x + b) + a ----------------
+    def _relu(self, ev, xs, L, lay):
+        """Two levels: Y = Rescale(X * Encode(c' M)) + b' M, then
+        Z = Rescale(Relin(Y * X)) + a M, X dropped to Y's level, with M the
+        valid slots.  A pending pooling factor p folds into the coefficients
+        (c' = c p^2, b' = b p: f applied to the average, Section IV-C).  Zero
+        outside M."""
+        ca, cb, cc = relu_coeffs(lay)
+        p = L.pending
+        outs = []
+        for i, X in enumerate(xs):
+            M = self._mask(self._valid_positions(L, i))
+            Y = ev.mac_rescale([X], [[(0, cc * p * p, M)]])[0]
+            Y = ev.add_plain(Y, (cb * p) * M)
+            Z = ev.mul(Y, ev.drop_to(X, Y))
+            outs.append(ev.add_plain(Z, ca * M))
+        L2 = Layout(L.kind, L.C, L.H, L.W, L.I, L.W_img, L.ch_ct, L.ch_off, "relu", 1.0, L.length)
+        return outs, L2
+
     # Section IV-C -----------------------------------------------------------
     def _avgpool(self, ev, xs, L, lay):
         c = lay["c"]
@@ -438,7 +500,7 @@ class Net:
             ys = []
             for R in rots_all:
                 ys.extend(ev.mac_rescale(R, [[(x, L.pending, masks[x]) for x in range(Wi)]]))
-        elif S > 1:
+        elif S > 1 and Wi > 1:
             G = math.ceil(Wi / S)
             masks = [self._mask([S * Wimg * y + g * S + m for y in range(Hi) for m in range(S) if g * S + m < Wi])
                      for g in range(G)]

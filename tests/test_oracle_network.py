@@ -173,3 +173,36 @@ def test_lenet1_full_size_golden_is_current():
     spec.loader.exec_module(mod)
     assert json.loads(json.dumps(mod.compute())) == rec
     assert rec["max_abs_err_vs_fp64"] < 1e-3
+
+
+def test_relu_after_pooling_folds_the_factor():
+    """Approximate ReLU right after average pooling applies f to the
+    average: the deferred 1/c^2 enters as b/c^2 and c/c^4 (Section IV-C)."""
+    inp = {"c": 1, "h": 12, "w": 12, "dist": "uniform01"}
+    layers = [{"kind": "conv", "ch_in": 1, "ch_out": 2, "k": 3, "s": 1}, {"kind": "avgpool", "c": 2},
+              W.RELU, W.FLATTEN, {"kind": "fc", "din": 50, "dout": 4}]
+    params = W.gen_params(layers)
+    xs = W.gen_inputs(inp, 1)
+    net = Net(inp, layers, params, 1024)
+    ev = SlotEval(1024)
+    got = read_outputs(net, net.run(ev, [net.input_vector(xs)]))
+    ref = cnn_fp64(xs[0], layers, params).reshape(-1)
+    assert np.abs(got[0] - ref).max() < 1e-12
+    assert network_depth(inp, layers) == 1 + 2 + 2 + 1
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name,log_n", [("m3", 12), ("m7", 11), ("m6", 11)])
+def test_encrypted_models_small_ring(name, log_n):
+    """Approximate ReLU (M3), 1D convolutions of stride 2 with FC -> square ->
+    FC (M7), and a stride-2 2D model (M6) end to end on the CPU CKKS oracle:
+    every level consumed, outputs within 1e-3 of the FP64 CNN."""
+    cfg = W.config(name)
+    cfg["log_n"] = log_n
+    sess = OracleSession(cfg)
+    net = build_net(cfg, sess.ck.slots)
+    xs = W.gen_inputs(cfg["input"], 1)
+    _, outs, ev = run_encrypted(sess, net, xs)
+    assert all(o.nl == 1 for o in outs)
+    got = decrypt_outputs(sess, net, outs)
+    assert np.abs(got - reference_outputs(net, xs)).max() < 1e-3

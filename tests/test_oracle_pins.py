@@ -236,6 +236,41 @@ def test_square_relin_rescale(mid):
     assert np.abs(mid.decrypt(sq) - z * z).max() < 1e-6
 
 
+def test_mul_relin(mid):
+    """Mul(C): equals the square when both operands are the same ciphertext
+    (bit for bit), is symmetric (bit for bit), and decrypts to the slotwise
+    product."""
+    z1 = W.gen_slots(mid.slots, 1, seed=23)[0]
+    z2 = W.gen_slots(mid.slots, 1, seed=24)[0]
+    a, b = mid.encrypt(z1, 25), mid.encrypt(z2, 26)
+    rlk = mid.load_key(mid.relin_key())
+    assert np.array_equal(mid.mul_relin(a, a, rlk).data, mid.square_relin(a, rlk).data)
+    ab, ba = mid.mul_relin(a, b, rlk), mid.mul_relin(b, a, rlk)
+    assert np.array_equal(ab.data, ba.data)
+    r = mid.rescale(ab)
+    assert np.abs(mid.decrypt(r) - z1 * z2).max() < 1e-6
+
+
+def test_mul_relin_tensor_bruteforce(tiny):
+    """The tensor part, checked with schoolbook negacyclic products: with a
+    zero relinearisation contribution (c1 parts zero) the product is
+    (a0 b0, a0 b1 + a1 b0) exactly."""
+    rng = np.random.default_rng(27)
+    nl = len(tiny.primes)
+    a = np.stack([np.stack([rng.integers(0, q, tiny.n, dtype=np.uint64) for q in tiny.primes]),
+                  np.zeros((nl, tiny.n), dtype=np.uint64)])
+    b = np.stack([np.stack([rng.integers(0, q, tiny.n, dtype=np.uint64) for q in tiny.primes]) for _ in range(2)])
+    from oracle.ckks import Ciphertext
+    rlk = tiny.load_key(tiny.relin_key())
+    out = tiny.mul_relin(Ciphertext(a, 1.0), Ciphertext(b, 1.0), rlk)
+    for i, q in enumerate(tiny.primes):
+        a0 = [int(x) for x in a[0, i]]
+        e0 = R.negacyclic(a0, [int(x) for x in b[0, i]], tiny.n, q)
+        e1 = R.negacyclic(a0, [int(x) for x in b[1, i]], tiny.n, q)
+        assert [int(x) for x in out.data[0, i]] == e0
+        assert [int(x) for x in out.data[1, i]] == e1
+
+
 def test_mac_schoolbook(tiny):
     rng = np.random.default_rng(22)
     nl = 2
@@ -272,6 +307,18 @@ def test_paper_facts():
         assert d - acc == per[i]["mult"], (i, lay)
         acc = d
     assert acc == facts["lenet1_total_mults"]
+    # Tables of M1 and M3 to M7: per-layer #Mult and totals
+    for name, rows in facts["model_mults"].items():
+        cfg = W.config(name)
+        layers = cfg["layers"]
+        assert len(layers) == len(rows), name
+        acc = 0
+        for i in range(len(layers)):
+            d = network_depth(cfg["input"], layers[: i + 1])
+            assert d - acc == rows[i]["mult"], (name, i, rows[i]["layer"])
+            acc = d
+        assert acc == facts["model_total_mults"][name]
+    assert tuple(facts["approx_relu"][k] for k in ("c0", "c1", "c2")) == __import__("oracle.network").network.RELU_APPROX
     # FC 64 -> 10: the first loop of Algorithm 2 runs DAT_out = 10 times, not 64
     fc = facts["fc_64_10"]
     ev = SlotEval(4096)

@@ -28,6 +28,7 @@ SEED_ENCRYPT = 12
 # Layer records use the paper's notation (Table 1, Algorithms 1 and 2):
 #   conv:    ch_in, ch_out, k (kernel K), s (stride S)
 #   square:  the x^2 activation
+#   relu_approx: the degree-2 polynomial approximation of ReLU
 #   avgpool: c (kernel size and stride)
 #   flatten: the flatten-layer converter
 #   fc:      din (DAT_in), dout (DAT_out)
@@ -42,6 +43,7 @@ def _conv1d(ci, co, k, s):
 
 SQUARE = {"kind": "square"}
 FLATTEN = {"kind": "flatten"}
+RELU = {"kind": "relu_approx"}   # the degree-2 approximation of ReLU (Section V-A)
 
 
 def _pool(c):
@@ -96,6 +98,60 @@ CONFIGS = {
         "samples_per_ct": 1, "sample_stride": 0, "cts_per_batch": 1,
     },
 }
+
+# The paper's other model shapes (Section V, Tables of detailed parameters
+# for M1 and M3 to M7), with synthetic weights.  M4 is LeNet-5, whose third
+# convolution needs a 32 x 32 input (28 x 28 would leave no output); rings
+# of 2^15 hold the depth-8 and depth-9 models at a 2^40 scale.
+MODEL_CONFIGS = {
+    "m1": {
+        "desc": "M1: conv 1->8 K4 S3, sq, flatten, FC 648->64, sq, FC 64->10 (28x28)",
+        "log_n": 14, "prime_bits": [60] + [40] * 7, "special_bits": 60, "log_scale": 40,
+        "input": {"c": 1, "h": 28, "w": 28, "dist": "uniform01"},
+        "layers": [_conv(1, 8, 4, 3), SQUARE, FLATTEN, _fc(648, 64), SQUARE, _fc(64, 10)],
+        "samples_per_ct": 1, "sample_stride": 0, "cts_per_batch": 1,
+    },
+    "m3": {
+        "desc": "M3: conv 1->6 K3, approx ReLU, pool2, flatten, FC 1014->120, approx ReLU, FC 120->10 (28x28)",
+        "log_n": 15, "prime_bits": [60] + [40] * 10, "special_bits": 60, "log_scale": 40,
+        "input": {"c": 1, "h": 28, "w": 28, "dist": "uniform01"},
+        "layers": [_conv(1, 6, 3, 1), RELU, _pool(2), FLATTEN, _fc(1014, 120), RELU, _fc(120, 10)],
+        "samples_per_ct": 1, "sample_stride": 0, "cts_per_batch": 1,
+    },
+    "m4": {
+        "desc": "M4 (LeNet-5 with squares): conv 1->6 K5, sq, pool2, conv 6->16 K5, sq, pool2, conv 16->120 K5, "
+                "sq, flatten, FC 120->84, sq, FC 84->10 (32x32)",
+        "log_n": 15, "prime_bits": [60] + [40] * 10, "special_bits": 60, "log_scale": 40,
+        "input": {"c": 1, "h": 32, "w": 32, "dist": "uniform01"},
+        "layers": [_conv(1, 6, 5, 1), SQUARE, _pool(2), _conv(6, 16, 5, 1), SQUARE, _pool(2), _conv(16, 120, 5, 1),
+                   SQUARE, FLATTEN, _fc(120, 84), SQUARE, _fc(84, 10)],
+        "samples_per_ct": 1, "sample_stride": 0, "cts_per_batch": 1,
+    },
+    "m5": {
+        "desc": "M5: conv 3->16 K3, sq, pool2, conv 16->64 K4, sq, pool2, conv 64->128 K3, sq, pool4, flatten, "
+                "FC 128->10 (3x32x32)",
+        "log_n": 15, "prime_bits": [60] + [40] * 10, "special_bits": 60, "log_scale": 40,
+        "input": {"c": 3, "h": 32, "w": 32, "dist": "uniform01"},
+        "layers": [_conv(3, 16, 3, 1), SQUARE, _pool(2), _conv(16, 64, 4, 1), SQUARE, _pool(2), _conv(64, 128, 3, 1),
+                   SQUARE, _pool(4), FLATTEN, _fc(128, 10)],
+        "samples_per_ct": 1, "sample_stride": 0, "cts_per_batch": 1,
+    },
+    "m6": {
+        "desc": "M6: conv 1->6 K4 S2, sq, flatten, FC 294->64, sq, FC 64->10 (16x16)",
+        "log_n": 14, "prime_bits": [60] + [40] * 7, "special_bits": 60, "log_scale": 40,
+        "input": {"c": 1, "h": 16, "w": 16, "dist": "uniform01"},
+        "layers": [_conv(1, 6, 4, 2), SQUARE, FLATTEN, _fc(294, 64), SQUARE, _fc(64, 10)],
+        "samples_per_ct": 1, "sample_stride": 0, "cts_per_batch": 1,
+    },
+    "m7": {
+        "desc": "M7: conv1d 1->2 k2 s2, sq, conv1d 2->4 k2 s2, flatten, FC 128->32, sq, FC 32->5 (length 128)",
+        "log_n": 14, "prime_bits": [60] + [40] * 7, "special_bits": 60, "log_scale": 40,
+        "input": {"c": 1, "h": 1, "w": 128, "dist": "normal"},
+        "layers": [_conv1d(1, 2, 2, 2), SQUARE, _conv1d(2, 4, 2, 2), FLATTEN, _fc(128, 32), SQUARE, _fc(32, 5)],
+        "samples_per_ct": 1, "sample_stride": 0, "cts_per_batch": 1,
+    },
+}
+CONFIGS.update(MODEL_CONFIGS)
 
 # Small rings used by unit and parity tests (same shapes of work, tiny N).
 TINY_RINGS = {
