@@ -105,6 +105,9 @@ def _fp64_cnn(x, layers, params):
             a = out
         elif k == "square":
             a = a * a
+        elif k == "relu_approx":
+            ca, cb, cc = L.get("coeffs", (0.375373, 0.5, 0.117071))
+            a = ca + cb * a + cc * a * a
         elif k == "avgpool":
             c = L["c"]
             C, H, Wd = a.shape
@@ -287,6 +290,35 @@ def cpu_baseline(W) -> dict:
             "sample": f"one whole LeNet-1 encrypted inference (N=2^14, 8 limbs, 288 rotations), {dt:.1f} s"}
 
 
+# The paper's own single-inference times (seconds; SEAL on one Xeon Gold 5220
+# core, scale 2^32, trained models): context only, different parameters.
+PAPER_MODEL_SECONDS = {"m1": 16.247, "m3": 29.105, "m4": 740.128, "m6": 12.309, "m7": 5.119}
+MODEL_NAMES = ["m1", "m3", "m4", "m5", "m6", "m7"]
+
+
+def models_bench(P, W, steps: int = 3) -> dict:
+    """Each of the paper's other model shapes at its full ring: plain
+    evaluation of one ciphertext (graph replay, tuned), inferences/s and the
+    largest deviation of the decrypted outputs from the FP64 CNN."""
+    import torch
+    out = {}
+    for name in MODEL_NAMES:
+        print(f"[bench] model {name}", file=sys.stderr, flush=True)
+        st = setup(P, W, name, batch=1, mode=P.EVAL_PLAIN | P.EVAL_GRAPH)
+        net, ct, outs = st["net"], st["ct"], st["outs"]
+        dt = timed(lambda: net.eval(ct, outs), steps, 1)
+        err = max_error(P, W, st)
+        cfg = st["cfg"]
+        out[name] = {"inferences_per_s": round(steps / dt, 3), "ms_per_inference": round(1e3 * dt / steps, 2),
+                     "max_abs_err_vs_fp64": err, "log_n": cfg["log_n"], "depth": net.depth,
+                     "rotation_keys": len(net.rotations()), "desc": cfg["desc"]}
+        if name in PAPER_MODEL_SECONDS:
+            out[name]["paper_cpu_seconds"] = PAPER_MODEL_SECONDS[name]
+        del st, net, ct, outs
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -299,6 +331,7 @@ def main():
     ap.add_argument("--only-plain", action="store_true", help="skip every extra measurement (for profiling)")
     ap.add_argument("--no-rotation-sweep", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="default launch parameters instead of the tuned ones")
+    ap.add_argument("--no-models", action="store_true", help="skip the paper's other model shapes")
     ap.add_argument("--serve-requests", type=int, default=300,
                     help="requests per load level of the serving measurement (0 skips it)")
     ap.add_argument("--ntt-probe", type=int, default=0, metavar="ROWS",
@@ -440,6 +473,9 @@ def main():
         print(f"[bench] batched cnn1d: {seqs:.1f} seq/s, max |err| {errc:.2e}", file=sys.stderr, flush=True)
         del sc, stepc
         torch.cuda.empty_cache()
+
+    if not args.no_models:
+        res["models"] = models_bench(P, W)
 
     if args.serve_requests:
         from paper_2402_03060_amd.serve import serving_benchmark

@@ -157,6 +157,14 @@ int unihenn_mul_plain_acc(const unihenn_ctx* ctx, const unihenn_ct* cts, const u
  * in.scale / q_l.  Errors: ELEVEL (n_limbs < 2). */
 int unihenn_rescale(const unihenn_ctx* ctx, const unihenn_ct* in, unihenn_ct* out, void* ws, size_t ws_bytes,
                     void* stream);
+/* Mul(C) of Section II-B followed by relinearisation with the key of s^2:
+ * the tensor (a0 b0, a0 b1 + a1 b0, a1 b1) with the last part key-switched
+ * into the first two.  b may hold more limbs than a (its first a->n_limbs
+ * are used: b dropped to a's level); out has a's limbs and scale
+ * a.scale * b.scale, no rescale.  out may alias neither operand.  Errors:
+ * ELEVEL (b has fewer limbs), EINVAL (batch sizes differ), ENOKEY. */
+int unihenn_mul_relin(const unihenn_ctx* ctx, const unihenn_ct* a, const unihenn_ct* b, const unihenn_evk* rlk,
+                      unihenn_ct* out, void* ws, size_t ws_bytes, void* stream);
 /* Mul(C) of a ciphertext with itself followed by relinearisation with the
  * key of s^2 (the square activation, Section IV-F): out = (c0^2 + KS_0(c1^2),
  * 2 c0 c1 + KS_1(c1^2)), scale in.scale^2, no rescale. */
@@ -178,7 +186,9 @@ enum {
     UNIHENN_LAYER_SQUARE = 2,   /* x^2 activation                                         */
     UNIHENN_LAYER_AVGPOOL = 3,  /* Section IV-C: k = c (kernel and stride)                 */
     UNIHENN_LAYER_FLATTEN = 4,  /* Section IV-E                                            */
-    UNIHENN_LAYER_FC = 5        /* Algorithm 2: ch_in = DAT_in, ch_out = DAT_out            */
+    UNIHENN_LAYER_FC = 5,       /* Algorithm 2: ch_in = DAT_in, ch_out = DAT_out            */
+    UNIHENN_LAYER_RELU_APPROX = 6 /* Section V-A: f(x) = a + b x + c x^2; weights (or NULL for
+                                   * the paper's 0.375373, 0.5, 0.117071) holds (a, b, c)   */
 };
 
 typedef struct {

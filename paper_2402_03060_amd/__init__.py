@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libunihenn.so")
 
 OK, EINVAL, ELEVEL, ESCALE, ENOKEY, ESLOTS, ENOMEM, EDEVICE = 0, -1, -2, -3, -4, -5, -6, -7
-LAYER_CONV, LAYER_SQUARE, LAYER_AVGPOOL, LAYER_FLATTEN, LAYER_FC = 1, 2, 3, 4, 5
+LAYER_CONV, LAYER_SQUARE, LAYER_AVGPOOL, LAYER_FLATTEN, LAYER_FC, LAYER_RELU_APPROX = 1, 2, 3, 4, 5, 6
 EVAL_PLAIN, EVAL_HOISTED, EVAL_GRAPH = 0, 1, 2
 KERNEL_FAMILIES = ["ntt_fwd_col", "ntt_fwd_row", "ntt_inv_row", "ntt_inv_col", "modup", "ks_inner", "moddown",
                    "rescale", "mac", "automorphism", "tensor", "add", "encode", "other"]
@@ -75,6 +75,7 @@ SIGNATURES = {
     "unihenn_mul_plain_acc": (C.c_int, [_vp, _P(CT), _P(_vp), _u32, C.c_int, _P(CT), _vp]),
     "unihenn_rescale": (C.c_int, [_vp, _P(CT), _P(CT), _vp, _sz, _vp]),
     "unihenn_square_relin": (C.c_int, [_vp, _P(CT), _P(EVK), _P(CT), _vp, _sz, _vp]),
+    "unihenn_mul_relin": (C.c_int, [_vp, _P(CT), _P(CT), _P(EVK), _P(CT), _vp, _sz, _vp]),
     "unihenn_add": (C.c_int, [_vp, _P(CT), _P(CT), _P(CT), _vp]),
     "unihenn_add_plain": (C.c_int, [_vp, _P(CT), _vp, _P(CT), _vp]),
     "unihenn_mod_drop": (C.c_int, [_vp, _P(CT), _u32, _P(CT), _vp]),
@@ -313,6 +314,15 @@ class Context:
         out.scale = o.scale
         return out
 
+    def mul_relin(self, a: Ciphertext, b: Ciphertext, rlk: torch.Tensor, ws: torch.Tensor) -> Ciphertext:
+        out = self.empty_ct(a.batch, a.n_limbs)
+        d = out.desc()
+        k = self.evk(rlk)
+        _check(lib().unihenn_mul_relin(self.h, C.byref(a.desc()), C.byref(b.desc()), C.byref(k), C.byref(d),
+                                       ws.data_ptr(), ws.numel() * 8, _stream()))
+        out.scale = d.scale
+        return out
+
     def add(self, a: Ciphertext, b: Ciphertext) -> Ciphertext:
         out = self.empty_ct(a.batch, a.n_limbs)
         o = out.desc()
@@ -390,7 +400,7 @@ def decrypt_slots(ctx: Context, sk: torch.Tensor, ct: Ciphertext, slots) -> np.n
 
 # ---------------------------------------------------------------- network
 _KIND = {"conv": LAYER_CONV, "square": LAYER_SQUARE, "avgpool": LAYER_AVGPOOL, "flatten": LAYER_FLATTEN,
-         "fc": LAYER_FC}
+         "fc": LAYER_FC, "relu_approx": LAYER_RELU_APPROX}
 
 
 class Net:
@@ -410,6 +420,10 @@ class Net:
                 d.k = L["c"]
             elif L["kind"] == "fc":
                 d.ch_in, d.ch_out = L["din"], L["dout"]
+            elif L["kind"] == "relu_approx" and "coeffs" in L:
+                cf = np.ascontiguousarray(L["coeffs"], dtype=np.float64)
+                self._keep.append(cf)
+                d.weights = cf.ctypes.data_as(C.POINTER(C.c_double))
             if p is not None:
                 w = np.ascontiguousarray(p[0], dtype=np.float64)
                 b = np.ascontiguousarray(p[1], dtype=np.float64)

@@ -300,6 +300,33 @@ extern "C" int unihenn_rescale(const unihenn_ctx* c, const unihenn_ct* in, unihe
     return UNIHENN_OK;
 }
 
+extern "C" int unihenn_mul_relin(const unihenn_ctx* c, const unihenn_ct* a, const unihenn_ct* b,
+                                 const unihenn_evk* rlk, unihenn_ct* out, void* ws, size_t ws_bytes, void* stream)
+{
+    int rc = rotate_checks(c, a, out);
+    if (rc) return rc;
+    if ((rc = check_ct(c, b, "second operand"))) return rc;
+    if (out->data == b->data) return uh_fail(UNIHENN_EINVAL, "output aliases input");
+    if (b->batch != a->batch) return uh_fail(UNIHENN_EINVAL, "operands of different batch sizes");
+    if (b->n_limbs < a->n_limbs) return uh_fail(UNIHENN_ELEVEL, "second operand has fewer limbs than the first");
+    const int nl = (int)a->n_limbs, B = (int)a->batch;
+    if ((rc = check_key(c, rlk, nl))) return rc;
+    if ((rc = check_ws(c, nl, B, ws_bytes, ws))) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    KsWs w = ks_ws_carve((u64*)ws, nl, B, c->n);
+    u64* d0 = w.aux;
+    u64* d1 = w.aux + (size_t)B * nl * c->n;
+    u64* d2 = w.aux + (size_t)2 * B * nl * c->n;
+    launch_tensor_mul(c, d0, d1, d2, a->data, b->data, (int)b->n_limbs, B, nl, s);
+    ks_modup(c, d2, nl, B, nl, w, s);
+    ks_finish(c, d2, nl, rlk->data, c->n_data, B, nl, 1, out->data, d0, d1, nl, w, s);
+    out->n_limbs = a->n_limbs;
+    out->batch = a->batch;
+    out->scale = a->scale * b->scale;
+    UH_LAUNCH_CHECK();
+    return UNIHENN_OK;
+}
+
 extern "C" int unihenn_square_relin(const unihenn_ctx* c, const unihenn_ct* in, const unihenn_evk* rlk,
                                     unihenn_ct* out, void* ws, size_t ws_bytes, void* stream)
 {

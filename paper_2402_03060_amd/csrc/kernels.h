@@ -23,6 +23,8 @@ void launch_gather_rows(const unihenn_ctx* c, u64* dst, const u64* src, int rows
                         hipStream_t s);
 void launch_mac(const unihenn_ctx* c, u64* acc, const MacTerms& terms, int n_terms, int nl, int batch, int accumulate,
                 hipStream_t s);
+void launch_tensor_mul(const unihenn_ctx* c, u64* d0, u64* d1, u64* d2, const u64* a, const u64* b, int b_limbs,
+                       int batch, int nl, hipStream_t s);
 void launch_tensor_square(const unihenn_ctx* c, u64* d0, u64* d1, u64* d2, const u64* ct, int batch, int nl,
                           hipStream_t s);
 void launch_add(const unihenn_ctx* c, u64* out, const u64* a, const u64* b, int rows, int nl, hipStream_t s);
@@ -108,8 +110,10 @@ void group_rescale(const unihenn_ctx* c, int E, const u64* const* in, u64* const
 // square + relinearise + rescale of E ciphertext batches at nl limbs
 // ([B][2][nl] -> [B][2][nl-1]); ws holds group_square_ws_rows rows
 size_t group_square_ws_rows(int E, int nl, int batch);
+// with in2: the product in[e] x in2[e] instead of the square (in2 rows have
+// in2_limbs limbs per polynomial, the first nl used)
 void group_square(const unihenn_ctx* c, int E, const u64* const* in, u64* const* out, const u64* rlk, int batch, int nl,
-                  u64* ws, hipStream_t s);
+                  u64* ws, hipStream_t s, const u64* const* in2 = nullptr, int in2_limbs = 0);
 // E single-output multiply-accumulates with T terms each (E * T <= 64)
 #define UH_MACG_MAX 64
 struct MacGroup {

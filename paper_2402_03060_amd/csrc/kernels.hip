@@ -368,6 +368,37 @@ void launch_mac(const unihenn_ctx* c, u64* acc, const MacTerms& terms, int n_ter
     }
 }
 
+// (a0, a1) x (b0, b1) -> d0 = a0 b0, d1 = a0 b1 + a1 b0, d2 = a1 b1, each
+// [B][nl][N]; b rows have b_limbs limbs per polynomial (its first nl used)
+__global__ void k_tensor_mul(u64* __restrict__ d0, u64* __restrict__ d1, u64* __restrict__ d2,
+                             const u64* __restrict__ a, const u64* __restrict__ bct, int b_limbs, DevCtx ctx, int nl)
+{
+    const int n = ctx.n;
+    const int k = blockIdx.x * EW_THREADS + threadIdx.x;
+    if (k >= n) return;
+    const int r = blockIdx.y;  // b * nl + i
+    const int i = r % nl, b = r / nl;
+    const Modulus M = ctx.mod[i];
+    const u64 a0 = a[(((size_t)b * 2 + 0) * nl + i) * n + k];
+    const u64 a1 = a[(((size_t)b * 2 + 1) * nl + i) * n + k];
+    const u64 b0 = bct[(((size_t)b * 2 + 0) * b_limbs + i) * n + k];
+    const u64 b1 = bct[(((size_t)b * 2 + 1) * b_limbs + i) * n + k];
+    const u64 s00 = mont_mul(mont_mul(a0, b0, M.q, M.qinv_neg), M.r2, M.q, M.qinv_neg);
+    const u64 s01 = mont_mul(mont_mul(a0, b1, M.q, M.qinv_neg), M.r2, M.q, M.qinv_neg);
+    const u64 s10 = mont_mul(mont_mul(a1, b0, M.q, M.qinv_neg), M.r2, M.q, M.qinv_neg);
+    const u64 s11 = mont_mul(mont_mul(a1, b1, M.q, M.qinv_neg), M.r2, M.q, M.qinv_neg);
+    d0[(size_t)r * n + k] = s00;
+    d1[(size_t)r * n + k] = add_mod(s01, s10, M.q);
+    d2[(size_t)r * n + k] = s11;
+}
+
+void launch_tensor_mul(const unihenn_ctx* c, u64* d0, u64* d1, u64* d2, const u64* a, const u64* b, int b_limbs,
+                       int batch, int nl, hipStream_t s)
+{
+    LaunchTimer tm(KF_TENSOR, 8.0 * c->n * batch * nl * 7, s);
+    k_tensor_mul<<<grid_rows(c->n, batch * nl), EW_THREADS, 0, s>>>(d0, d1, d2, a, b, b_limbs, c->dev, nl);
+}
+
 void launch_tensor_square(const unihenn_ctx* c, u64* d0, u64* d1, u64* d2, const u64* ct, int batch, int nl,
                           hipStream_t s)
 {
@@ -803,8 +834,10 @@ __global__ void k_relin_combine(u64* __restrict__ out, const u64* __restrict__ U
 }
 
 // tensor of E ciphertext batches: d0/d1/d2 [E][B][nl]
+// tensor of E ciphertext batches: a[e] x b[e] (b[e] null: a[e] squared; b rows
+// with b_limbs limbs per polynomial, its first nl used); d0/d1/d2 [E][B][nl]
 __global__ void k_group_tensor(u64* __restrict__ d0, u64* __restrict__ d1, u64* __restrict__ d2, EwGroup g, DevCtx ctx,
-                               int nl, int batch)
+                               int nl, int batch, int b_limbs)
 {
     const int n = ctx.n;
     const int k = blockIdx.x * EW_THREADS + threadIdx.x;
@@ -815,13 +848,25 @@ __global__ void k_group_tensor(u64* __restrict__ d0, u64* __restrict__ d1, u64* 
     const Modulus M = ctx.mod[i];
     const u64 c0 = g.a[e][(((size_t)b * 2 + 0) * nl + i) * n + k];
     const u64 c1 = g.a[e][(((size_t)b * 2 + 1) * nl + i) * n + k];
-    const u64 s00 = mont_mul(mont_mul(c0, c0, M.q, M.qinv_neg), M.r2, M.q, M.qinv_neg);
-    const u64 s01 = mont_mul(mont_mul(c0, c1, M.q, M.qinv_neg), M.r2, M.q, M.qinv_neg);
-    const u64 s11 = mont_mul(mont_mul(c1, c1, M.q, M.qinv_neg), M.r2, M.q, M.qinv_neg);
     const size_t o = ((size_t)e * batch * nl + r) * n + k;
-    d0[o] = s00;
-    d1[o] = add_mod(s01, s01, M.q);
-    d2[o] = s11;
+    if (!g.b[e]) {
+        const u64 s00 = mont_mul(mont_mul(c0, c0, M.q, M.qinv_neg), M.r2, M.q, M.qinv_neg);
+        const u64 s01 = mont_mul(mont_mul(c0, c1, M.q, M.qinv_neg), M.r2, M.q, M.qinv_neg);
+        const u64 s11 = mont_mul(mont_mul(c1, c1, M.q, M.qinv_neg), M.r2, M.q, M.qinv_neg);
+        d0[o] = s00;
+        d1[o] = add_mod(s01, s01, M.q);
+        d2[o] = s11;
+    } else {
+        const u64 e0 = g.b[e][(((size_t)b * 2 + 0) * b_limbs + i) * n + k];
+        const u64 e1 = g.b[e][(((size_t)b * 2 + 1) * b_limbs + i) * n + k];
+        const u64 s00 = mont_mul(mont_mul(c0, e0, M.q, M.qinv_neg), M.r2, M.q, M.qinv_neg);
+        const u64 s01 = mont_mul(mont_mul(c0, e1, M.q, M.qinv_neg), M.r2, M.q, M.qinv_neg);
+        const u64 s10 = mont_mul(mont_mul(c1, e0, M.q, M.qinv_neg), M.r2, M.q, M.qinv_neg);
+        const u64 s11 = mont_mul(mont_mul(c1, e1, M.q, M.qinv_neg), M.r2, M.q, M.qinv_neg);
+        d0[o] = s00;
+        d1[o] = add_mod(s01, s10, M.q);
+        d2[o] = s11;
+    }
 }
 
 template <int BCH>
@@ -921,7 +966,7 @@ size_t group_square_ws_rows(int E, int nl, int batch)
 }
 
 void group_square(const unihenn_ctx* c, int E, const u64* const* in, u64* const* out, const u64* rlk, int B, int nl,
-                  u64* ws, hipStream_t s)
+                  u64* ws, hipStream_t s, const u64* const* in2, int in2_limbs)
 {
     const size_t rn = (size_t)c->n, EB = (size_t)E * B;
     u64* d0 = ws;
@@ -938,10 +983,13 @@ void group_square(const unihenn_ctx* c, int E, const u64* const* in, u64* const*
     EwGroup g;
     memset(&g, 0, sizeof(g));
     g.E = E;
-    for (int e = 0; e < E; ++e) g.a[e] = in[e];
+    for (int e = 0; e < E; ++e) {
+        g.a[e] = in[e];
+        g.b[e] = in2 ? in2[e] : nullptr;
+    }
     {
-        LaunchTimer tm(KF_TENSOR, 8.0 * c->n * EB * nl * 5, s);
-        k_group_tensor<<<dim3(gx, B * nl, E), EW_THREADS, 0, s>>>(d0, d1, d2, g, c->dev, nl, B);
+        LaunchTimer tm(KF_TENSOR, 8.0 * c->n * EB * nl * (in2 ? 7 : 5), s);
+        k_group_tensor<<<dim3(gx, B * nl, E), EW_THREADS, 0, s>>>(d0, d1, d2, g, c->dev, nl, B, in2 ? in2_limbs : nl);
     }
     // ModUp of every d2 (E * B ciphertext-polys as one batch), inner product with the relinearisation key
     launch_gather_rows(c, dcoef, d2, (int)EB * nl, nl, nl, 0, s);

@@ -28,7 +28,7 @@ int encode_scaled_batch(const unihenn_ctx* c, const double* z, int n_slots, cons
 
 namespace {
 
-enum StepKind { ST_DROP, ST_ROT, ST_MAC, ST_MACM, ST_RESCALE, ST_ADD, ST_ADD_PLAIN, ST_SQUARE };
+enum StepKind { ST_DROP, ST_ROT, ST_MAC, ST_MACM, ST_RESCALE, ST_ADD, ST_ADD_PLAIN, ST_SQUARE, ST_MUL };
 
 struct VReg {
     int nl;
@@ -73,7 +73,7 @@ struct Layout {
     bool vec = false;
     int C = 1, H = 1, W = 1, I = 1, W_img = 1;
     std::vector<int> ch_reg, ch_off;  // register and slot offset of channel c
-    int prev = 0;                      // 0 input, 1 conv, 2 avgpool (last non-square layer)
+    int prev = 0;                      // 0 input, 1 conv, 2 avgpool, 3 approximate ReLU (last non-square layer)
     double pending = 1.0;              // deferred pooling factor (Section IV-C)
     int length = 0;
 };
@@ -278,6 +278,67 @@ struct Planner {
         return d;
     }
 
+    // Mul(C) + relinearisation + rescale of a by b (b dropped to a's level)
+    int mul(int a, int b)
+    {
+        const VReg ra = net->regs[a], rb = net->regs[b];
+        if (ra.nl < 2) return fail(UNIHENN_ELEVEL, "level exhausted");
+        if (rb.nl < ra.nl) return fail(UNIHENN_ELEVEL, "product operand below the other's level");
+        int d = newreg(ra.nl - 1, ra.scale * rb.scale / (double)c->primes[ra.nl - 1]);
+        Step s;
+        s.kind = ST_MUL;
+        s.dst = d;
+        s.a = a;
+        s.b = b;
+        net->steps.push_back(s);
+        return d;
+    }
+
+    // in-sample slots of the valid values register `reg` holds
+    std::vector<long> valid_positions(const Layout& L, int reg) const
+    {
+        std::vector<long> pos;
+        if (L.vec) {
+            for (int v = 0; v < L.length; ++v) pos.push_back(v);
+            return pos;
+        }
+        for (int ch = 0; ch < L.C; ++ch)
+            if (L.ch_reg[ch] == reg)
+                for (int y = 0; y < L.H; ++y)
+                    for (int x = 0; x < L.W; ++x) pos.push_back((long)L.ch_off[ch] + (long)L.I * (x + (long)L.W_img * y));
+        return pos;
+    }
+
+    // Section V-A: f(x) = a + b x + c x^2 evaluated as x (c' x + b') + a in
+    // two levels, with a pending pooling factor p folded into the
+    // coefficients (c' = c p^2, b' = b p; Section IV-C); zero outside the
+    // valid slots
+    int relu_layer(Layout& L, const unihenn_layer& ly)
+    {
+        const double ca = ly.weights ? ly.weights[0] : 0.375373;
+        const double cb = ly.weights ? ly.weights[1] : 0.5;
+        const double cc = ly.weights ? ly.weights[2] : 0.117071;
+        const double p = L.pending;
+        std::map<int, int> mapped;
+        for (int& reg : L.ch_reg) {
+            if (!mapped.count(reg)) {
+                const std::vector<long> pos = valid_positions(L, reg);
+                const VReg r = net->regs[reg];
+                size_t off = request(mask(pos), std::vector<double>(1, cc * p * p), delta, r.nl, 1);
+                int y = mac_rescale({Term{reg, off}});
+                if (y < 0) return -1;
+                y = add_plain_vec(y, mask(pos, cb * p));
+                int z = mul(y, reg);
+                if (z < 0) return -1;
+                mapped[reg] = add_plain_vec(z, mask(pos, ca));
+            }
+            reg = mapped[reg];
+        }
+        L.prev = 3;
+        L.pending = 1.0;
+        return 0;
+    }
+
     // Algorithm 1 -----------------------------------------------------------
     int conv(Layout& L, const unihenn_layer& ly)
     {
@@ -456,7 +517,7 @@ struct Planner {
                 X = mac_rescale(terms);
                 if (X < 0) return -1;
             }
-        } else if (S > 1) {
+        } else if (S > 1 && Wi > 1) {
             // zeros between the values: S shifted copies summed, then one mask per group of S columns
             const int G = (Wi + S - 1) / S;
             std::vector<size_t> pts;
@@ -609,7 +670,7 @@ int footprint(const unihenn_input& in, const unihenn_layer* ls, int n, long* out
 // [after pooling, or interval > 1, or a pending factor] + [H > 1]
 int count_depth(const unihenn_input& in, const unihenn_layer* ls, int n)
 {
-    int d = 0, prev = 0, I = 1, H = (int)in.h;
+    int d = 0, prev = 0, I = 1, H = (int)in.h, W = (int)in.w;
     double pending = 1.0;
     for (int l = 0; l < n; ++l) {
         const unihenn_layer& L = ls[l];
@@ -621,11 +682,19 @@ int count_depth(const unihenn_input& in, const unihenn_layer* ls, int n)
             I *= g.sw;
             pending = 1.0;
             H = (H - g.kh) / g.sh + 1;
+            W = (W - g.kw) / g.sw + 1;
             break;
         }
         case UNIHENN_LAYER_SQUARE: d += 1; pending *= pending; break;
-        case UNIHENN_LAYER_AVGPOOL: prev = 2; I *= (int)L.k; pending /= (double)(L.k * L.k); H /= (int)L.k; break;
-        case UNIHENN_LAYER_FLATTEN: d += (prev == 2 || I > 1 || pending != 1.0) + (H > 1); break;
+        case UNIHENN_LAYER_RELU_APPROX: d += 2; prev = 3; pending = 1.0; break;
+        case UNIHENN_LAYER_AVGPOOL:
+            prev = 2;
+            I *= (int)L.k;
+            pending /= (double)(L.k * L.k);
+            H /= (int)L.k;
+            W /= (int)L.k;
+            break;
+        case UNIHENN_LAYER_FLATTEN: d += (prev == 2 || (I > 1 && W > 1) || pending != 1.0) + (H > 1); break;
         case UNIHENN_LAYER_FC: d += 1; break;
         default: return -1;
         }
@@ -696,6 +765,7 @@ void schedule_layers(unihenn_net* net)
         case ST_MAC: return 2;
         case ST_RESCALE: return 3;
         case ST_SQUARE: return 4;
+        case ST_MUL: return 4;
         case ST_ADD_PLAIN: return 5;
         case ST_ADD: return 6;
         default: return 7;
@@ -789,7 +859,7 @@ extern "C" int unihenn_net_create(const unihenn_ctx* c, const unihenn_input* in,
     if (in->c < 1 || in->h < 1 || in->w < 1 || in->samples < 1 || max_batch < 1)
         return uh_fail(UNIHENN_EINVAL, "empty input shape, sample count or batch");
     for (uint32_t l = 0; l < n_layers; ++l)
-        if (layers[l].kind < UNIHENN_LAYER_CONV || layers[l].kind > UNIHENN_LAYER_FC)
+        if (layers[l].kind < UNIHENN_LAYER_CONV || layers[l].kind > UNIHENN_LAYER_RELU_APPROX)
             return uh_fail(UNIHENN_EINVAL, "unknown layer kind");
     unihenn_net* net = new unihenn_net();
     net->ctx = c;
@@ -850,6 +920,7 @@ extern "C" int unihenn_net_create(const unihenn_ctx* c, const unihenn_input* in,
         switch (layers[l].kind) {
         case UNIHENN_LAYER_CONV: rc = P.conv(L, layers[l]); break;
         case UNIHENN_LAYER_SQUARE: rc = P.square_layer(L); break;
+        case UNIHENN_LAYER_RELU_APPROX: rc = P.relu_layer(L, layers[l]); break;
         case UNIHENN_LAYER_AVGPOOL: rc = P.avgpool(L, layers[l]); break;
         case UNIHENN_LAYER_FLATTEN: rc = P.flatten(L); break;
         case UNIHENN_LAYER_FC: rc = P.fc(L, layers[l]); break;
@@ -961,7 +1032,7 @@ extern "C" int unihenn_net_bind_keys(unihenn_net* net, const int32_t* steps, con
     for (int r : net->rotations)
         if (!k.count(r)) return uh_fail(UNIHENN_ENOKEY, "no key for rotation " + std::to_string(r));
     bool needs_rlk = false;
-    for (const Step& s : net->steps) needs_rlk |= s.kind == ST_SQUARE;
+    for (const Step& s : net->steps) needs_rlk |= s.kind == ST_SQUARE || s.kind == ST_MUL;
     if (needs_rlk && (!rlk || !rlk->data || (int)rlk->n_data != c->n_data))
         return uh_fail(UNIHENN_ENOKEY, "no relinearisation key");
     net->keys = k;
@@ -1252,6 +1323,24 @@ struct Exec {
                 si = run.back();
                 break;
             }
+            case ST_MUL: {
+                const int nla = net->regs[st.a].nl, nlb = net->regs[st.b].nl;
+                std::vector<size_t> run = collect(si, end, nl, [&](const Step& x) {
+                    return x.kind == ST_MUL && net->regs[x.a].nl == nla && net->regs[x.b].nl == nlb;
+                }, UH_EW_GROUP_MAX, std::max(1, 32 / B));
+                std::vector<const u64*> ins, in2;
+                std::vector<u64*> outs;
+                for (size_t x : run) {
+                    ins.push_back(reg(net->steps[x].a));
+                    in2.push_back(reg(net->steps[x].b));
+                    outs.push_back(reg(net->steps[x].dst));
+                }
+                group_square(c, (int)run.size(), ins.data(), outs.data(), net->rlk, B, nla, net->ws, s, in2.data(),
+                             nlb);
+                modup_owner = -1;
+                si = run.back();
+                break;
+            }
             }
         }
         hipError_t e = hipGetLastError();
@@ -1264,7 +1353,8 @@ int check_keys(const unihenn_net* net)
 {
     if (net->keys.size() < net->rotations.size()) return uh_fail(UNIHENN_ENOKEY, "keys not bound");
     for (const Step& s : net->steps)
-        if (s.kind == ST_SQUARE && !net->rlk) return uh_fail(UNIHENN_ENOKEY, "relinearisation key not bound");
+        if ((s.kind == ST_SQUARE || s.kind == ST_MUL) && !net->rlk)
+            return uh_fail(UNIHENN_ENOKEY, "relinearisation key not bound");
     return UNIHENN_OK;
 }
 

@@ -88,6 +88,17 @@ def test_cnn1d_small_ring_bit_exact():
     _run_parity(cfg)
 
 
+@pytest.mark.parametrize("name,log_n", [("m3", 12), ("m1", 11), ("m6", 11), ("m7", 11), ("m4", 11)])
+def test_paper_model_shapes_bit_exact(name, log_n):
+    """The paper's other model shapes on small rings: approximate ReLU with
+    Mul(C) (M3), stride-3 and stride-2 convolutions with FC -> square -> FC
+    (M1, M6), 1D convolutions of stride 2 (M7), LeNet-5 with its 16 -> 120
+    convolution and a flatten of 1 x 1 maps (M4)."""
+    cfg = W.config(name)
+    cfg["log_n"] = log_n
+    _run_parity(cfg)
+
+
 def test_conv_layer_entry_point():
     """unihenn_conv (Algorithm 1 alone) on the LeNet-1 second conv at N = 2^11."""
     import paper_2402_03060_amd as P

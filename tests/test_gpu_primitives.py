@@ -141,6 +141,28 @@ def test_square_relin_parity(pair):
     assert got.scale == exp.scale
 
 
+def test_mul_relin_parity(pair):
+    """Mul(C) + relinearisation of two ciphertexts, with the second operand
+    also one level above the first (its top limb ignored)."""
+    ck, ctx, _ = pair
+    nl = len(ck.primes)
+    za, zb = W.gen_slots(ck.slots, 2, seed=37)
+    a, b = ck.encrypt(za, 38), ck.encrypt(zb, 39)
+    rk = ck.relin_key()
+    rlk = ck.load_key(rk)
+    g_rlk = ctx.import_evk(rk)
+    ws = ctx.workspace(nl, 1)
+    exp = ck.mul_relin(a, b, rlk)
+    got = ctx.mul_relin(ctx.import_ct(a.data, a.scale), ctx.import_ct(b.data, b.scale), g_rlk, ws)
+    assert np.array_equal(ctx.export_ct(got)[0], exp.data)
+    assert got.scale == exp.scale
+    if nl > 1:
+        a2 = ck.limb_drop(a, nl - 1)
+        exp2 = ck.mul_relin(a2, ck.limb_drop(b, nl - 1), rlk)
+        got2 = ctx.mul_relin(ctx.import_ct(a2.data, a2.scale), ctx.import_ct(b.data, b.scale), g_rlk, ws)
+        assert np.array_equal(ctx.export_ct(got2)[0], exp2.data)
+
+
 def test_add_and_add_plain_parity(pair):
     ck, ctx, _ = pair
     nl = len(ck.primes)
