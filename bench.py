@@ -42,9 +42,11 @@ def _pack(net_input: dict, xs: np.ndarray, n_slots: int, stride: int) -> np.ndar
 TUNING_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2402_03060_amd", "tuning_cache.json")
 
 
-def setup(P, W, name: str, batch: int, seed: int = 5, tune: bool = True, mode: int = 0):
+def setup(P, W, name: str, batch: int, seed: int = 5, tune: bool = True, mode: int = 0, log_n: int | None = None):
     import torch
     cfg = W.config(name)
+    if log_n is not None:
+        cfg["log_n"] = log_n
     ctx = P.Context(cfg["log_n"], cfg["prime_bits"], cfg["special_bits"], 2.0 ** cfg["log_scale"])
     params = W.gen_params(cfg["layers"])
     S, stride = cfg["samples_per_ct"], cfg["sample_stride"]
@@ -294,6 +296,10 @@ def cpu_baseline(W) -> dict:
 # core, scale 2^32, trained models): context only, different parameters.
 PAPER_MODEL_SECONDS = {"m1": 16.247, "m3": 29.105, "m4": 740.128, "m6": 12.309, "m7": 5.119}
 MODEL_NAMES = ["m1", "m3", "m4", "m5", "m6", "m7"]
+# M5 at N = 2^15 would hold ~150 GB of plaintexts (90,691 weights of its
+# 64 -> 128 convolution, most on a few valid slots); it runs at N = 2^13, the
+# smallest ring whose slots hold a 3 x 32 x 32 input
+MODEL_LOG_N = {"m5": 13}
 
 
 def models_bench(P, W, steps: int = 3) -> dict:
@@ -304,7 +310,7 @@ def models_bench(P, W, steps: int = 3) -> dict:
     out = {}
     for name in MODEL_NAMES:
         print(f"[bench] model {name}", file=sys.stderr, flush=True)
-        st = setup(P, W, name, batch=1, mode=P.EVAL_PLAIN | P.EVAL_GRAPH)
+        st = setup(P, W, name, batch=1, mode=P.EVAL_PLAIN | P.EVAL_GRAPH, log_n=MODEL_LOG_N.get(name))
         net, ct, outs = st["net"], st["ct"], st["outs"]
         dt = timed(lambda: net.eval(ct, outs), steps, 1)
         err = max_error(P, W, st)
