@@ -80,6 +80,14 @@ def lib():
         L.or_square_relin.argtypes = [_vp, _u64p, C.c_int, _vp, _u64p]
         L.or_mul_relin.argtypes = [_vp, _u64p, _u64p, C.c_int, _vp, _u64p]
         L.or_rescale.argtypes = [_vp, _u64p, C.c_int, C.c_int, _u64p]
+        L.or_encode_scaled_ext.argtypes = [_vp, C.POINTER(C.c_double), C.c_int, C.POINTER(C.c_double), C.c_int,
+                                           C.c_double, C.c_int, _u64p]
+        L.or_rotate_ext.argtypes = [_vp, _u64p, C.c_int, C.c_int64, _vp, _u64p]
+        L.or_to_ext.argtypes = [_vp, _u64p, C.c_int, C.c_int, _u64p]
+        L.or_moddown.argtypes = [_vp, _u64p, C.c_int, C.c_int, _u64p]
+        L.or_add_ext.argtypes = [_vp, _u64p, _u64p, C.c_int, C.c_int, _u64p]
+        L.or_mac_matrix_ext.argtypes = [_vp, C.c_int, C.c_int, C.POINTER(_u64p), C.c_int, C.POINTER(_u64p),
+                                        C.POINTER(_u64p)]
         _lib = L
     return _lib
 
@@ -113,6 +121,18 @@ class Ciphertext:
     @property
     def nl(self) -> int:
         return self.data.shape[1]
+
+
+@dataclass
+class ExtCiphertext:
+    """Ciphertext over the extended basis {q_0..q_{nl-1}, P}: it stands for
+    ModDown of itself (see the deferred-ModDown section of ckks_oracle.c)."""
+    data: np.ndarray  # uint64 [2][nl+1][N], coefficient form
+    scale: float
+
+    @property
+    def nl(self) -> int:
+        return self.data.shape[1] - 1
 
 
 class Secret:
@@ -163,6 +183,16 @@ class OracleCKKS:
         ws = np.ascontiguousarray(np.asarray(ws, dtype=np.float64).ravel())
         out = np.zeros((len(ws), nl, self.n), dtype=np.uint64)
         rc = lib().or_encode_scaled(self.ctx, _pd(z), len(z), _pd(ws), len(ws), float(scale), nl, _p64(out))
+        if rc != 0:
+            raise ValueError("encode overflow")
+        return out
+
+    def encode_scaled_ext(self, z, ws, scale: float, nl: int) -> np.ndarray:
+        """encode_scaled with the residue mod P as limb nl: [len(ws)][nl+1][N]."""
+        z = np.ascontiguousarray(np.asarray(z, dtype=np.float64))
+        ws = np.ascontiguousarray(np.asarray(ws, dtype=np.float64).ravel())
+        out = np.zeros((len(ws), nl + 1, self.n), dtype=np.uint64)
+        rc = lib().or_encode_scaled_ext(self.ctx, _pd(z), len(z), _pd(ws), len(ws), float(scale), nl, _p64(out))
         if rc != 0:
             raise ValueError("encode overflow")
         return out
@@ -307,6 +337,50 @@ class OracleCKKS:
         outs = [np.zeros((2, nl, self.n), dtype=np.uint64) for _ in range(n_out)]
         oa = (_u64p * n_out)(*[_p64(o) for o in outs])
         lib().or_mac_matrix(self.ctx, nl, n_ct, ca, n_out, pa, oa)
+        return outs
+
+    # -- deferred ModDown ----------------------------------------------------
+    def rotate_ext(self, ct: Ciphertext, r: int, key) -> ExtCiphertext:
+        """Rot(ct, r) before its ModDown: (P tau(c0) + U_0, U_1)."""
+        out = np.zeros((2, ct.nl + 1, self.n), dtype=np.uint64)
+        if lib().or_rotate_ext(self.ctx, _p64(np.ascontiguousarray(ct.data)), ct.nl, int(r), key, _p64(out)) != 0:
+            raise ValueError("key level")
+        return ExtCiphertext(out, ct.scale)
+
+    def to_ext(self, ct: Ciphertext) -> ExtCiphertext:
+        out = np.zeros((2, ct.nl + 1, self.n), dtype=np.uint64)
+        lib().or_to_ext(self.ctx, _p64(np.ascontiguousarray(ct.data)), ct.nl, 2, _p64(out))
+        return ExtCiphertext(out, ct.scale)
+
+    def moddown(self, e: ExtCiphertext) -> Ciphertext:
+        out = np.zeros((2, e.nl, self.n), dtype=np.uint64)
+        lib().or_moddown(self.ctx, _p64(np.ascontiguousarray(e.data)), e.nl, 2, _p64(out))
+        return Ciphertext(out, e.scale)
+
+    def add_ext(self, a: ExtCiphertext, b: ExtCiphertext) -> ExtCiphertext:
+        if a.nl != b.nl:
+            raise ValueError("operands at different levels")
+        out = np.zeros_like(a.data)
+        lib().or_add_ext(self.ctx, _p64(np.ascontiguousarray(a.data)), _p64(np.ascontiguousarray(b.data)),
+                         a.nl, 2, _p64(out))
+        return ExtCiphertext(out, a.scale)
+
+    def mac_matrix_ext(self, cts: list[ExtCiphertext], pts) -> list[np.ndarray]:
+        """acc[o] = sum_t pts[o][t] * cts[t] over the extended basis
+        (pts[o][t]: [nl+1][N] or None); acc[o]: [2][nl+1][N]."""
+        nl = cts[0].nl
+        n_ct, n_out = len(cts), len(pts)
+        keep = [np.ascontiguousarray(c.data) for c in cts]
+        ca = (_u64p * n_ct)(*[_p64(c) for c in keep])
+        flat = []
+        for o in range(n_out):
+            for t in range(n_ct):
+                p = pts[o][t]
+                flat.append(None if p is None else np.ascontiguousarray(p))
+        pa = (_u64p * len(flat))(*[(_p64(p) if p is not None else _u64p()) for p in flat])
+        outs = [np.zeros((2, nl + 1, self.n), dtype=np.uint64) for _ in range(n_out)]
+        oa = (_u64p * n_out)(*[_p64(o) for o in outs])
+        lib().or_mac_matrix_ext(self.ctx, nl, n_ct, ca, n_out, pa, oa)
         return outs
 
     def add(self, a: Ciphertext, b: Ciphertext) -> Ciphertext:

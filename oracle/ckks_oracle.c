@@ -357,11 +357,16 @@ static void real_transform(ctx_t *c, const double *z, int n_slots, __float128 *m
     for (int j = 0; j < n; j++) m[j] *= f;
 }
 
-static void round_reduce(const ctx_t *c, __float128 v, int n_limbs, u64 *out, int j)
+/* limb i < n_limbs of coefficient j: the rounded value mod q_i; with ext
+ * (n_limbs = nl + 1) the last limb is taken mod P */
+static void round_reduce(const ctx_t *c, __float128 v, int n_limbs, u64 *out, int j, int ext)
 {
     __float128 r = roundq(v); /* half away from zero */
     i128 iv = (i128)r;
-    for (int i = 0; i < n_limbs; i++) out[(size_t)i * c->n + j] = reduce_i128(iv, c->mod[i].q);
+    for (int i = 0; i < n_limbs; i++) {
+        int mi = (ext && i == n_limbs - 1) ? c->n_mod - 1 : i;
+        out[(size_t)i * c->n + j] = reduce_i128(iv, c->mod[mi].q);
+    }
 }
 
 /* pt[i][j] for i < n_limbs.  Returns -1 if a coefficient does not fit. */
@@ -376,7 +381,7 @@ int or_encode(void *vc, const double *z, int n_slots, double scale, int n_limbs,
     for (int j = 0; j < n; j++) {
         __float128 v = (__float128)scale * m[j];
         if (fabsq(v) > 0x1p100Q) { rc = -1; break; }
-        round_reduce(c, v, n_limbs, pt, j);
+        round_reduce(c, v, n_limbs, pt, j, 0);
     }
     free(m);
     return rc;
@@ -386,10 +391,9 @@ int or_encode(void *vc, const double *z, int n_slots, double scale, int n_limbs,
  * exact transform, m(w z) = w m(z); the product scale * w is exact in
  * binary128, so only the final product with m_j is rounded before the
  * rounding to an integer.  out: [n_w][n_limbs][N]. */
-int or_encode_scaled(void *vc, const double *z, int n_slots, const double *w, int n_w, double scale,
-                     int n_limbs, u64 *out)
+static int encode_scaled(ctx_t *c, const double *z, int n_slots, const double *w, int n_w, double scale,
+                         int n_limbs, int ext, u64 *out)
 {
-    ctx_t *c = (ctx_t *)vc;
     int n = c->n;
     if (n_slots > n / 2) return -1;
     __float128 *m = (__float128 *)malloc(sizeof(__float128) * n);
@@ -401,11 +405,25 @@ int or_encode_scaled(void *vc, const double *z, int n_slots, const double *w, in
         for (int j = 0; j < n; j++) {
             __float128 v = sw * m[j];
             if (fabsq(v) > 0x1p100Q) { rc = -1; break; }
-            round_reduce(c, v, n_limbs, pt, j);
+            round_reduce(c, v, n_limbs, pt, j, ext);
         }
     }
     free(m);
     return rc;
+}
+
+int or_encode_scaled(void *vc, const double *z, int n_slots, const double *w, int n_w, double scale,
+                     int n_limbs, u64 *out)
+{
+    return encode_scaled((ctx_t *)vc, z, n_slots, w, n_w, scale, n_limbs, 0, out);
+}
+
+/* the same with the residue mod P as limb nl: out [n_w][nl+1][N], the
+ * plaintexts of products with extended ciphertexts */
+int or_encode_scaled_ext(void *vc, const double *z, int n_slots, const double *w, int n_w, double scale, int nl,
+                         u64 *out)
+{
+    return encode_scaled((ctx_t *)vc, z, n_slots, w, n_w, scale, nl + 1, 1, out);
 }
 
 /* exact real transform, exported as hi/lo doubles for tests */
@@ -627,12 +645,12 @@ void or_key_free(void *vk) { swkey_t *k = (swkey_t *)vk; free(k->ev); free(k); }
 /* target basis index b (0..nl-1 data limbs, nl -> P) to moduli index */
 static int basis_mod(const swkey_t *k, int nl, int b) { return b < nl ? b : k->n_data; }
 
-/* Given the centered digits dig[j][coef] (j < nl), compute
- * out_c[i] = round((sum_j d_j evk_{j,c}) / P) mod q_i, i < nl. */
-static void ks_from_digits(ctx_t *c, const swkey_t *k, const i64 *dig, int nl, u64 *out)
+/* U_c = sum_j d_j evk_{j,c} for the centered digits dig[j][coef] (j < nl),
+ * over the basis {q_0..q_{nl-1}, P}: acc [2][nl+1][N], coefficient form. */
+static void ks_accumulate(ctx_t *c, const swkey_t *k, const i64 *dig, int nl, u64 *acc)
 {
     int n = c->n, nbk = k->n_data + 1, nb = nl + 1;
-    u64 *acc = (u64 *)calloc((size_t)2 * nb * n, sizeof(u64));
+    memset(acc, 0, sizeof(u64) * (size_t)2 * nb * n);
     u64 *ev = (u64 *)malloc(sizeof(u64) * n), *dm = (u64 *)malloc(sizeof(u64) * n);
     for (int b = 0; b < nb; b++) {
         int mi = basis_mod(k, nl, b);
@@ -649,21 +667,38 @@ static void ks_from_digits(ctx_t *c, const swkey_t *k, const i64 *dig, int nl, u
         }
         for (int cc = 0; cc < 2; cc++) from_eval(c, mi, acc + ((size_t)cc * nb + b) * n);
     }
-    /* ModDown: out_c[i] = (U_c[i] - centered(U_c[P])) * P^-1 mod q_i */
-    u64 P = c->mod[k->n_data].q;
-    for (int cc = 0; cc < 2; cc++) {
-        const u64 *up = acc + ((size_t)cc * nb + nl) * n;
+    free(ev); free(dm);
+}
+
+/* ModDown: out_p[i] = (E_p[i] - centered(E_p[P])) * P^-1 mod q_i, the exact
+ * rounding division by P of each of n_polys polynomials over
+ * {q_0..q_{nl-1}, P} (in: [n_polys][nl+1][N], out: [n_polys][nl][N]) */
+static void moddown(const ctx_t *c, const u64 *in, int nl, int n_polys, u64 *out)
+{
+    int n = c->n;
+    u64 P = c->mod[c->n_mod - 1].q;
+    for (int p = 0; p < n_polys; p++) {
+        const u64 *up = in + ((size_t)p * (nl + 1) + nl) * n;
         for (int i = 0; i < nl; i++) {
             u64 q = c->mod[i].q, pinv = inv_mod(P % q, q);
-            const u64 *ui = acc + ((size_t)cc * nb + i) * n;
-            u64 *o = out + ((size_t)cc * nl + i) * n;
+            const u64 *ui = in + ((size_t)p * (nl + 1) + i) * n;
+            u64 *o = out + ((size_t)p * nl + i) * n;
             for (int t = 0; t < n; t++) {
                 u64 r = reduce_i128(centered(up[t], P), q);
                 o[t] = mul_mod(sub_mod(ui[t], r, q), pinv, q);
             }
         }
     }
-    free(acc); free(ev); free(dm);
+}
+
+/* Given the centered digits dig[j][coef] (j < nl), compute
+ * out_c[i] = round((sum_j d_j evk_{j,c}) / P) mod q_i, i < nl. */
+static void ks_from_digits(ctx_t *c, const swkey_t *k, const i64 *dig, int nl, u64 *out)
+{
+    u64 *acc = (u64 *)malloc(sizeof(u64) * (size_t)2 * (nl + 1) * c->n);
+    ks_accumulate(c, k, dig, nl, acc);
+    moddown(c, acc, nl, 2, out);
+    free(acc);
 }
 
 /* digits of d (coefficient form, nl limbs): centered residues, as integers */
@@ -753,22 +788,102 @@ int or_rotate_hoisted(void *vc, const u64 *ct, int nl, const i64 *rs, int nr, vo
 }
 
 /* ------------------------------------------------------------------------ */
+/* deferred ModDown: ciphertexts over the extended basis {q_0..q_{nl-1}, P}  */
+/* ------------------------------------------------------------------------ */
+/* An extended ciphertext E = (E_0, E_1) over Q_l P stands for the ciphertext
+ * ModDown(E) over Q_l (the exact rounding division by P above).  A rotation
+ * kept in this form skips the ModDown of its key switch:
+ *     E = (P tau_g(c0) + U_0, U_1),   U = sum_j d_j evk_j  (d: digits of tau_g(c1)),
+ * and ModDown(E) is exactly Rot(ct, r): P tau_g(c0) has residue 0 mod P and
+ * divides exactly.  A ciphertext enters the form as P ct (residue 0 mod P).
+ * Sums and plaintext products (with the plaintext's residue mod P as the
+ * last limb) act limb by limb, so one ModDown of a sum of such terms
+ * replaces one per rotation; it rounds once, where the sum of rotated
+ * ciphertexts rounds once per term, so the two differ in the last bits. */
+
+/* out [2][nl+1][N]: (P tau_g(c0) + U_0, U_1) for the left rotation by r */
+int or_rotate_ext(void *vc, const u64 *ct, int nl, i64 r, void *vk, u64 *out)
+{
+    ctx_t *c = (ctx_t *)vc;
+    swkey_t *k = (swkey_t *)vk;
+    int n = c->n;
+    if (nl > k->n_data) return -1;
+    size_t lsz = (size_t)nl * n;
+    u64 g = or_galois_elt(vc, r);
+    u64 P = c->mod[c->n_mod - 1].q;
+    u64 *t0 = (u64 *)malloc(sizeof(u64) * lsz), *t1 = (u64 *)malloc(sizeof(u64) * lsz);
+    i64 *dig = (i64 *)malloc(sizeof(i64) * lsz);
+    or_automorphism(vc, ct, nl, g, t0);
+    or_automorphism(vc, ct + lsz, nl, g, t1);
+    centered_digits(c, t1, nl, dig);
+    ks_accumulate(c, k, dig, nl, out);
+    for (int i = 0; i < nl; i++) {
+        u64 q = c->mod[i].q, pm = P % q;
+        for (int t = 0; t < n; t++) {
+            size_t o = (size_t)i * n + t;
+            out[o] = add_mod(out[o], mul_mod(pm, t0[o], q), q);
+        }
+    }
+    free(t0); free(t1); free(dig);
+    return 0;
+}
+
+/* out [n_polys][nl+1][N] = P in [n_polys][nl][N]: limbs i < nl scaled by
+ * P mod q_i, limb nl zero */
+void or_to_ext(void *vc, const u64 *in, int nl, int n_polys, u64 *out)
+{
+    ctx_t *c = (ctx_t *)vc;
+    int n = c->n;
+    u64 P = c->mod[c->n_mod - 1].q;
+    for (int p = 0; p < n_polys; p++) {
+        for (int i = 0; i < nl; i++) {
+            u64 q = c->mod[i].q, pm = P % q;
+            const u64 *x = in + ((size_t)p * nl + i) * n;
+            u64 *y = out + ((size_t)p * (nl + 1) + i) * n;
+            for (int t = 0; t < n; t++) y[t] = mul_mod(pm, x[t], q);
+        }
+        memset(out + ((size_t)p * (nl + 1) + nl) * n, 0, sizeof(u64) * n);
+    }
+}
+
+/* ModDown of n_polys extended polynomials: [n_polys][nl+1][N] -> [n_polys][nl][N] */
+void or_moddown(void *vc, const u64 *in, int nl, int n_polys, u64 *out)
+{
+    moddown((const ctx_t *)vc, in, nl, n_polys, out);
+}
+
+/* out = a + b over extended operands (n_polys polynomials of nl+1 limbs) */
+void or_add_ext(void *vc, const u64 *a, const u64 *b, int nl, int n_polys, u64 *out)
+{
+    ctx_t *c = (ctx_t *)vc;
+    int n = c->n;
+    for (int p = 0; p < n_polys; p++)
+        for (int i = 0; i <= nl; i++) {
+            u64 q = c->mod[i < nl ? i : c->n_mod - 1].q;
+            size_t off = ((size_t)p * (nl + 1) + i) * n;
+            for (int j = 0; j < n; j++) out[off + j] = add_mod(a[off + j], b[off + j], q);
+        }
+}
+
+/* ------------------------------------------------------------------------ */
 /* plaintext multiply-accumulate, add, square + relinearise, rescale        */
 /* ------------------------------------------------------------------------ */
 /* acc[o] = sum_t pts[o*n_ct + t] * cts[t], for o < n_out.  Each ciphertext is
  * evaluated once and shared by every output (Algorithm 1 reuses each rotated
  * ciphertext for all output channels).  A NULL plaintext is a zero term.
- * cts[t]: [2][nl][N]; pts: [nl][N]; acc[o]: [2][nl][N]. */
-void or_mac_matrix(void *vc, int nl, int n_ct, const u64 **cts, int n_out, const u64 **pts, u64 **acc)
+ * Limb i of every operand is taken modulo c->mod[mods[i]].
+ * cts[t]: [2][nb][N]; pts: [nb][N]; acc[o]: [2][nb][N]. */
+static void mac_matrix(ctx_t *c, const int *mods, int nb, int n_ct, const u64 **cts, int n_out, const u64 **pts,
+                       u64 **acc)
 {
-    ctx_t *c = (ctx_t *)vc;
     int n = c->n;
-    size_t lsz = (size_t)nl * n;
+    size_t lsz = (size_t)nb * n;
     u64 *ev = (u64 *)malloc(sizeof(u64) * (size_t)n_ct * 2 * lsz);
     for (int t = 0; t < n_ct; t++)
         for (int cc = 0; cc < 2; cc++)
-            for (int i = 0; i < nl; i++)
-                to_eval(c, i, cts[t] + (size_t)cc * lsz + (size_t)i * n, ev + ((size_t)t * 2 + cc) * lsz + (size_t)i * n);
+            for (int i = 0; i < nb; i++)
+                to_eval(c, mods[i], cts[t] + (size_t)cc * lsz + (size_t)i * n,
+                        ev + ((size_t)t * 2 + cc) * lsz + (size_t)i * n);
     u64 *pev = (u64 *)malloc(sizeof(u64) * n);
     u64 *a = (u64 *)malloc(sizeof(u64) * 2 * lsz);
     for (int o = 0; o < n_out; o++) {
@@ -776,9 +891,9 @@ void or_mac_matrix(void *vc, int nl, int n_ct, const u64 **cts, int n_out, const
         for (int t = 0; t < n_ct; t++) {
             const u64 *pt = pts[(size_t)o * n_ct + t];
             if (!pt) continue;
-            for (int i = 0; i < nl; i++) {
-                u64 q = c->mod[i].q;
-                to_eval(c, i, pt + (size_t)i * n, pev);
+            for (int i = 0; i < nb; i++) {
+                u64 q = c->mod[mods[i]].q;
+                to_eval(c, mods[i], pt + (size_t)i * n, pev);
                 for (int cc = 0; cc < 2; cc++) {
                     const u64 *x = ev + ((size_t)t * 2 + cc) * lsz + (size_t)i * n;
                     u64 *y = a + (size_t)cc * lsz + (size_t)i * n;
@@ -787,10 +902,37 @@ void or_mac_matrix(void *vc, int nl, int n_ct, const u64 **cts, int n_out, const
             }
         }
         for (int cc = 0; cc < 2; cc++)
-            for (int i = 0; i < nl; i++) from_eval(c, i, a + (size_t)cc * lsz + (size_t)i * n);
+            for (int i = 0; i < nb; i++) from_eval(c, mods[i], a + (size_t)cc * lsz + (size_t)i * n);
         memcpy(acc[o], a, sizeof(u64) * 2 * lsz);
     }
     free(ev); free(pev); free(a);
+}
+
+/* moduli of the limbs of an extended operand: q_0..q_{nl-1}, then P */
+static int *limb_mods(const ctx_t *c, int nl)
+{
+    int *m = (int *)malloc(sizeof(int) * (nl + 1));
+    for (int i = 0; i < nl; i++) m[i] = i;
+    m[nl] = c->n_mod - 1;
+    return m;
+}
+
+void or_mac_matrix(void *vc, int nl, int n_ct, const u64 **cts, int n_out, const u64 **pts, u64 **acc)
+{
+    ctx_t *c = (ctx_t *)vc;
+    int *m = limb_mods(c, nl);
+    mac_matrix(c, m, nl, n_ct, cts, n_out, pts, acc);
+    free(m);
+}
+
+/* the same over extended operands (nl data limbs and P): cts[t], acc[o]
+ * [2][nl+1][N], pts [nl+1][N] */
+void or_mac_matrix_ext(void *vc, int nl, int n_ct, const u64 **cts, int n_out, const u64 **pts, u64 **acc)
+{
+    ctx_t *c = (ctx_t *)vc;
+    int *m = limb_mods(c, nl);
+    mac_matrix(c, m, nl + 1, n_ct, cts, n_out, pts, acc);
+    free(m);
 }
 
 /* out = a + b (n_polys polynomials of nl limbs each) */

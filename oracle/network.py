@@ -261,6 +261,9 @@ class SlotEval:
     def drop_to(self, x, like):
         return x
 
+    def finish(self, x):
+        return x
+
 
 class CkksEval:
     """The CPU CKKS oracle.  keys: {r mod N/2: loaded key}, rlk: loaded key."""
@@ -282,12 +285,20 @@ class CkksEval:
         return self.ck.rotate(x, r, self.keys[r])
 
     def mac_rescale(self, srcs, terms_per_out):
+        return self._mac_rescale(srcs, terms_per_out, ext=False)
+
+    def _mac_rescale(self, srcs, terms_per_out, ext: bool):
+        """Rescale(sum_t Encode(w_t m_t) * srcs[t]) per output; with ext the
+        sources are extended ciphertexts, the plaintexts carry their residue
+        mod P, and each sum is brought down by one ModDown before the rescale."""
+        from oracle.ckks import Ciphertext, ExtCiphertext
         ck = self.ck
         nl = srcs[0].nl
         scale = srcs[0].scale
         for s in srcs:
             if s.nl != nl or s.scale != scale:
                 raise ValueError("MAC terms must share level and scale")
+        encode = ck.encode_scaled_ext if ext else ck.encode_scaled
         outs = []
         chunk = 4
         for o0 in range(0, len(terms_per_out), chunk):
@@ -300,16 +311,18 @@ class CkksEval:
                 for t, w, m in terms:
                     bymask.setdefault(id(m), (m, []))[1].append((t, w))
                 for _, (m, tw) in bymask.items():
-                    enc = ck.encode_scaled(m, [w for _, w in tw], ck.delta, nl)
+                    enc = encode(m, [w for _, w in tw], ck.delta, nl)
                     for (t, _), p in zip(tw, enc):
                         if row[t] is not None:
                             raise ValueError("duplicate term")
                         row[t] = p
                 self.count.mac += len(terms)
                 pts.append(row)
-            accs = ck.mac_matrix(srcs, pts)
+            if ext:
+                accs = [ck.moddown(ExtCiphertext(a, scale * ck.delta)).data for a in ck.mac_matrix_ext(srcs, pts)]
+            else:
+                accs = ck.mac_matrix(srcs, pts)
             for a in accs:
-                from oracle.ckks import Ciphertext
                 self.count.rescale += 1
                 outs.append(ck.rescale(Ciphertext(a, scale * ck.delta)))
         return outs
@@ -334,6 +347,77 @@ class CkksEval:
     def drop_to(self, x, like):
         """x with its top limbs discarded down to like's level (scale kept)."""
         return self.ck.limb_drop(x, like.nl)
+
+    def finish(self, x):
+        return x
+
+
+class LazyCkksEval(CkksEval):
+    """CkksEval with the ModDown of rotations deferred (an evaluator variant
+    of this implementation; the paper's evaluator is the one above).
+
+    A rotation by r != 0 yields its extended form (P tau(c0) + U_0, U_1) over
+    {q_0..q_{nl-1}, P} (oracle.ckks.ExtCiphertext); a rotation by 0 returns
+    its input unchanged.  Additions and plaintext sums with an extended
+    operand stay extended (a plain ciphertext x enters as P x), and a sum of
+    products is brought down by a single ModDown before its rescale.  Any
+    other use of an extended value (a rotation source, a plaintext addition,
+    a product, the network output) first takes its ModDown, once per value.
+    Every sum is exact modulo each prime, so the result depends only on which
+    sums are brought down, not on the order of their terms."""
+
+    def _norm(self, x):
+        from oracle.ckks import ExtCiphertext
+        if not isinstance(x, ExtCiphertext):
+            return x
+        md = getattr(x, "_md", None)
+        if md is None:
+            md = self.ck.moddown(x)
+            x._md = md
+        return md
+
+    def _ext(self, x):
+        from oracle.ckks import ExtCiphertext
+        return x if isinstance(x, ExtCiphertext) else self.ck.to_ext(x)
+
+    @staticmethod
+    def _is_ext(x) -> bool:
+        from oracle.ckks import ExtCiphertext
+        return isinstance(x, ExtCiphertext)
+
+    def rot(self, x, r):
+        r = r % self.n_slots
+        if r == 0:
+            return x
+        if r not in self.keys:
+            raise KeyError(f"no rotation key for {r}")
+        self.count.rot += 1
+        return self.ck.rotate_ext(self._norm(x), r, self.keys[r])
+
+    def add(self, a, b):
+        if self._is_ext(a) or self._is_ext(b):
+            return self.ck.add_ext(self._ext(a), self._ext(b))
+        return self.ck.add(a, b)
+
+    def mac_rescale(self, srcs, terms_per_out):
+        if any(self._is_ext(s) for s in srcs):
+            return self._mac_rescale([self._ext(s) for s in srcs], terms_per_out, ext=True)
+        return self._mac_rescale(srcs, terms_per_out, ext=False)
+
+    def add_plain(self, x, vec):
+        return super().add_plain(self._norm(x), vec)
+
+    def square(self, x):
+        return super().square(self._norm(x))
+
+    def mul(self, a, b):
+        return super().mul(self._norm(a), self._norm(b))
+
+    def drop_to(self, x, like):
+        return super().drop_to(self._norm(x), like)
+
+    def finish(self, x):
+        return self._norm(x)
 
 
 # --------------------------------------------------------------------------
@@ -403,7 +487,7 @@ class Net:
             else:
                 raise PlanError(k)
         self.out_layout = L
-        return xs
+        return [ev.finish(x) for x in xs]
 
     # Algorithm 1 ----------------------------------------------------------
     def _conv(self, ev, xs, L, lay, p):

@@ -8,7 +8,7 @@ import numpy as np
 
 import workloads as W
 from oracle.ckks import OracleCKKS
-from oracle.network import CkksEval, Net, cnn_fp64, read_outputs
+from oracle.network import CkksEval, LazyCkksEval, Net, cnn_fp64, read_outputs
 
 
 class OracleSession:
@@ -39,14 +39,16 @@ def build_net(cfg: dict, n_slots: int, params=None) -> Net:
     return Net(cfg["input"], cfg["layers"], params, n_slots, cfg["samples_per_ct"], cfg["sample_stride"])
 
 
-def run_encrypted(sess: OracleSession, net: Net, xs: np.ndarray, enc_seed: int = W.SEED_ENCRYPT):
-    """Encrypt the packed inputs, drop to the network depth, evaluate.
+def run_encrypted(sess: OracleSession, net: Net, xs: np.ndarray, enc_seed: int = W.SEED_ENCRYPT,
+                  lazy: bool = False):
+    """Encrypt the packed inputs, drop to the network depth, evaluate (with
+    lazy: deferred ModDown, LazyCkksEval).
     Returns (input ciphertext, output ciphertexts, evaluator)."""
     ck = sess.ck
     sess.ensure_keys(net.rotation_set())
     ct = ck.encrypt(net.input_vector(xs), enc_seed)
     x = ck.limb_drop(ct, net.depth + 1)
-    ev = CkksEval(ck, sess.key_handle, sess.rlk)
+    ev = (LazyCkksEval if lazy else CkksEval)(ck, sess.key_handle, sess.rlk)
     outs = net.run(ev, [x])
     return ct, outs, ev
 
