@@ -217,6 +217,26 @@ typedef struct {
  * n_data), ENOMEM. */
 int unihenn_net_create(const unihenn_ctx* ctx, const unihenn_input* input, const unihenn_layer* layers,
                        uint32_t n_layers, uint32_t max_batch, unihenn_net** out);
+
+/* Plan options of unihenn_net_create_ex (or-ed).
+ *   UNIHENN_PLAN_LAZY_MODDOWN  deferred ModDown, an evaluator variant of this
+ *     library (the paper's evaluator rounds after every key switch): a
+ *     rotation keeps its key-switch output over {q_0..q_l, P} as
+ *     (P tau(c0) + U_0, U_1) (hybrid key switching with one special prime
+ *     P, Section II-B's Rot); the multiply-accumulate sums of Algorithms 1
+ *     and 2, the pooling sums of Section IV-C and the flatten sums of
+ *     Section IV-E run over that basis (plaintexts carry their residue mod
+ *     P), and one ModDown per sum replaces one per rotation.  A rotation by
+ *     0 passes its input through; a rotation source, a plaintext addition,
+ *     a product and the network outputs take the ModDown first.  Results
+ *     differ from the default plan in their last bits (each sum is rounded
+ *     once instead of once per term); the decrypted outputs meet the same
+ *     bounds. */
+enum { UNIHENN_PLAN_LAZY_MODDOWN = 1 };
+/* unihenn_net_create with plan options (plan_flags, 0 = the default plan).
+ * Errors: as unihenn_net_create, and EINVAL for an unknown flag. */
+int unihenn_net_create_ex(const unihenn_ctx* ctx, const unihenn_input* input, const unihenn_layer* layers,
+                          uint32_t n_layers, uint32_t max_batch, uint32_t plan_flags, unihenn_net** out);
 int unihenn_net_destroy(unihenn_net* net);
 /* depth, number of distinct rotation keys, number of output ciphertexts,
  * and the number of limbs the input is reduced to. */

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libunihenn.so")
 OK, EINVAL, ELEVEL, ESCALE, ENOKEY, ESLOTS, ENOMEM, EDEVICE = 0, -1, -2, -3, -4, -5, -6, -7
 LAYER_CONV, LAYER_SQUARE, LAYER_AVGPOOL, LAYER_FLATTEN, LAYER_FC, LAYER_RELU_APPROX = 1, 2, 3, 4, 5, 6
 EVAL_PLAIN, EVAL_HOISTED, EVAL_GRAPH = 0, 1, 2
+PLAN_LAZY_MODDOWN = 1
 KERNEL_FAMILIES = ["ntt_fwd_col", "ntt_fwd_row", "ntt_inv_row", "ntt_inv_col", "modup", "ks_inner", "moddown",
                    "rescale", "mac", "automorphism", "tensor", "add", "encode", "other"]
 
@@ -80,6 +81,7 @@ SIGNATURES = {
     "unihenn_add_plain": (C.c_int, [_vp, _P(CT), _vp, _P(CT), _vp]),
     "unihenn_mod_drop": (C.c_int, [_vp, _P(CT), _u32, _P(CT), _vp]),
     "unihenn_net_create": (C.c_int, [_vp, _P(INPUT), _P(LAYER), _u32, _u32, _P(_vp)]),
+    "unihenn_net_create_ex": (C.c_int, [_vp, _P(INPUT), _P(LAYER), _u32, _u32, _u32, _P(_vp)]),
     "unihenn_net_destroy": (C.c_int, [_vp]),
     "unihenn_net_info": (C.c_int, [_vp, _P(_u32), _P(_u32), _P(_u32), _P(_u32)]),
     "unihenn_net_rotations": (C.c_int, [_vp, _P(_i32)]),
@@ -407,8 +409,10 @@ class Net:
     """A planned network with its plaintexts encoded on the device."""
 
     def __init__(self, ctx: Context, inp: dict, layers, params, samples: int = 1, stride: int = 0,
-                 max_batch: int = 1):
+                 max_batch: int = 1, lazy: bool = False):
+        """lazy: plan with deferred ModDown (PLAN_LAZY_MODDOWN)."""
         self.ctx = ctx
+        self.lazy = lazy
         self._keep = []
         arr = (LAYER * len(layers))()
         for i, (L, p) in enumerate(zip(layers, params)):
@@ -432,7 +436,8 @@ class Net:
                 d.bias = b.ctypes.data_as(C.POINTER(C.c_double))
         ind = INPUT(inp["c"], inp["h"], inp["w"], samples, stride)
         h = C.c_void_p()
-        _check(lib().unihenn_net_create(ctx.h, C.byref(ind), arr, len(layers), max_batch, C.byref(h)))
+        _check(lib().unihenn_net_create_ex(ctx.h, C.byref(ind), arr, len(layers), max_batch,
+                                           PLAN_LAZY_MODDOWN if lazy else 0, C.byref(h)))
         self.h = h
         self.samples = samples
         self.max_batch = max_batch

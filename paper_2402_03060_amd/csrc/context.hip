@@ -251,10 +251,13 @@ extern "C" int unihenn_ctx_create(uint32_t log_n, const uint32_t* prime_bits, ui
         }
     u64 P = primes[n_data];
     c->p_inv.assign((size_t)nm * 2, 0);
+    c->p_mod.assign((size_t)nm * 2, 0);
     for (int i = 0; i < (int)n_data; ++i) {
         u64 v = h_inv(P % primes[i], primes[i]);
         c->p_inv[2 * i] = v;
         c->p_inv[2 * i + 1] = shoup(v, primes[i]);
+        c->p_mod[2 * i] = P % primes[i];
+        c->p_mod[2 * i + 1] = shoup(P % primes[i], primes[i]);
     }
     std::vector<uint32_t> ge(n / 2);
     u64 e = 1;
@@ -271,6 +274,7 @@ extern "C" int unihenn_ctx_create(uint32_t log_n, const uint32_t* prime_bits, ui
     if (hipMalloc(&c->d_qmod, sizeof(u64) * c->q_mod.size()) != hipSuccess) return fail("hipMalloc qmod");
     if (hipMalloc(&c->d_inv_last, sizeof(u64) * c->inv_last.size()) != hipSuccess) return fail("hipMalloc inv");
     if (hipMalloc(&c->d_p_inv, sizeof(u64) * c->p_inv.size()) != hipSuccess) return fail("hipMalloc pinv");
+    if (hipMalloc(&c->d_p_mod, sizeof(u64) * c->p_mod.size()) != hipSuccess) return fail("hipMalloc pmod");
     if (hipMalloc(&c->d_galois_e, sizeof(uint32_t) * ge.size()) != hipSuccess) return fail("hipMalloc galois");
     if (hipMalloc(&c->d_cos, sizeof(double) * cs.size()) != hipSuccess) return fail("hipMalloc cos");
     hipError_t up = hipMemcpy(c->d_mod, c->host_mod.data(), sizeof(Modulus) * nm, hipMemcpyHostToDevice);
@@ -279,6 +283,7 @@ extern "C" int unihenn_ctx_create(uint32_t log_n, const uint32_t* prime_bits, ui
     if (up == hipSuccess)
         up = hipMemcpy(c->d_inv_last, c->inv_last.data(), sizeof(u64) * c->inv_last.size(), hipMemcpyHostToDevice);
     if (up == hipSuccess) up = hipMemcpy(c->d_p_inv, c->p_inv.data(), sizeof(u64) * c->p_inv.size(), hipMemcpyHostToDevice);
+    if (up == hipSuccess) up = hipMemcpy(c->d_p_mod, c->p_mod.data(), sizeof(u64) * c->p_mod.size(), hipMemcpyHostToDevice);
     if (up == hipSuccess) up = hipMemcpy(c->d_galois_e, ge.data(), sizeof(uint32_t) * ge.size(), hipMemcpyHostToDevice);
     if (up == hipSuccess) up = hipMemcpy(c->d_cos, cs.data(), sizeof(double) * cs.size(), hipMemcpyHostToDevice);
     if (up != hipSuccess) {
@@ -295,6 +300,7 @@ extern "C" int unihenn_ctx_create(uint32_t log_n, const uint32_t* prime_bits, ui
     c->dev.tw_sh = c->d_tw + (size_t)nm * n;
     c->dev.itw = c->d_tw + (size_t)2 * nm * n;
     c->dev.itw_sh = c->d_tw + (size_t)3 * nm * n;
+    c->dev.p_mod = c->d_p_mod;
     *out = c;
     return UNIHENN_OK;
 }
@@ -307,6 +313,7 @@ extern "C" int unihenn_ctx_destroy(unihenn_ctx* c)
     (void)hipFree(c->d_qmod);
     (void)hipFree(c->d_inv_last);
     (void)hipFree(c->d_p_inv);
+    (void)hipFree(c->d_p_mod);
     (void)hipFree(c->d_galois_e);
     (void)hipFree(c->d_cos);
     delete c;

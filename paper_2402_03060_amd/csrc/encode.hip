@@ -46,9 +46,10 @@ __device__ __forceinline__ bool dd_round(dd v, i64* out)
     return true;
 }
 
-// pt[w][i][j] = round(s_w * m_j) mod q_i with s_w = scale * w (exact double-double)
+// pt[w][i][j] = round(s_w * m_j) mod q_i with s_w = scale * w (exact double-double);
+// with ext the last of the nl rows is taken mod P
 __global__ void k_encode_round(u64* __restrict__ pt, const double* __restrict__ m, const double* __restrict__ ws,
-                               int n_w, double scale, DevCtx ctx, int nl, int* __restrict__ overflow)
+                               int n_w, double scale, DevCtx ctx, int nl, int ext, int* __restrict__ overflow)
 {
     const int n = ctx.n;
     const int j = blockIdx.x * ENC_THREADS + threadIdx.x;
@@ -63,7 +64,7 @@ __global__ void k_encode_round(u64* __restrict__ pt, const double* __restrict__ 
     }
     const u64 mag = (u64)(iv < 0 ? -iv : iv);
     for (int i = 0; i < nl; ++i) {
-        const Modulus M = ctx.mod[i];
+        const Modulus M = ctx.mod[(ext && i == nl - 1) ? ctx.p_index : i];
         u64 r = reduce64(mag, M.q, M.ratio);
         if (iv < 0 && r) r = M.q - r;
         pt[(((size_t)w * nl) + i) * n + j] = r;
@@ -89,10 +90,12 @@ struct EncodeJob {
     }
 };
 
-// Encode(w_t * z) for every weight (n_w plaintexts, [n_w][nl][N]); internal
-// entry used by the network builder and unihenn_encode.
+// Encode(w_t * z) for every weight (n_w plaintexts, [n_w][nl][N], or with
+// ext [n_w][nl+1][N] whose limb nl is the residue mod P, for products with
+// extended ciphertexts); internal entry used by the network builder and
+// unihenn_encode.
 int encode_scaled_batch(const unihenn_ctx* c, const double* z, int n_slots, const double* w, int n_w, double scale,
-                        int nl, int mont, u64* out, hipStream_t s)
+                        int nl, int mont, u64* out, hipStream_t s, int ext)
 {
     if (n_slots > c->n / 2) return uh_fail(UNIHENN_EINVAL, "more values than slots");
     if (nl < 1 || nl > c->n_data) return uh_fail(UNIHENN_EINVAL, "bad limb count");
@@ -123,14 +126,18 @@ int encode_scaled_batch(const unihenn_ctx* c, const double* z, int n_slots, cons
     const int zero = 0;
     UH_CHECK_HIP(hipMemcpyAsync(job.ovf, &zero, sizeof(int), hipMemcpyHostToDevice, s));
     {
-        LaunchTimer tm(KF_ENCODE, 8.0 * (2.0 * c->n + (double)n_w * nl * c->n), s);
+        LaunchTimer tm(KF_ENCODE, 8.0 * (2.0 * c->n + (double)n_w * (nl + ext) * c->n), s);
         dim3 g1((c->n + ENC_THREADS - 1) / ENC_THREADS);
         k_encode_sum<<<g1, ENC_THREADS, 0, s>>>(job.m, job.ek, job.zv, nnz, c->d_cos, c->log_n);
         dim3 g2((c->n + ENC_THREADS - 1) / ENC_THREADS, n_w);
-        k_encode_round<<<g2, ENC_THREADS, 0, s>>>(out, job.m, job.ws, n_w, scale, c->dev, nl, job.ovf);
+        k_encode_round<<<g2, ENC_THREADS, 0, s>>>(out, job.m, job.ws, n_w, scale, c->dev, nl + ext, ext, job.ovf);
     }
-    launch_ntt_fwd(c, out, n_w * nl, rowmap_ct(nl), s);
-    if (mont) launch_mont_convert(c, out, n_w * nl, rowmap_ct(nl), 1, s);
+    std::vector<int> mods;
+    for (int i = 0; i < nl; ++i) mods.push_back(i);
+    if (ext) mods.push_back(c->n_data);
+    const RowMap map = rowmap_list(mods);
+    launch_ntt_fwd(c, out, n_w * (nl + ext), map, s);
+    if (mont) launch_mont_convert(c, out, n_w * (nl + ext), map, 1, s);
     int ovf = 0;
     UH_CHECK_HIP(hipMemcpyAsync(&ovf, job.ovf, sizeof(int), hipMemcpyDeviceToHost, s));
     UH_CHECK_HIP(hipStreamSynchronize(s));
@@ -143,7 +150,7 @@ extern "C" int unihenn_encode(const unihenn_ctx* c, const double* slots, uint32_
 {
     if (!c || !pt || (n_slots && !slots)) return uh_fail(UNIHENN_EINVAL, "null argument");
     const double one = 1.0;
-    return encode_scaled_batch(c, slots, (int)n_slots, &one, 1, scale, (int)n_limbs, mont, pt, (hipStream_t)stream);
+    return encode_scaled_batch(c, slots, (int)n_slots, &one, 1, scale, (int)n_limbs, mont, pt, (hipStream_t)stream, 0);
 }
 
 extern "C" int unihenn_import_pt(const unihenn_ctx* c, const uint64_t* coeff, uint32_t n_limbs, int mont,

@@ -22,6 +22,7 @@ struct DevCtx {
     const u64* tw_sh;      // Shoup companions
     const u64* itw;        // inverse twiddles  [n_mod][N]: psi^-brev(k)
     const u64* itw_sh;
+    const u64* p_mod;      // [i][2]: P mod q_i and its Shoup companion, i < n_data
 };
 
 struct unihenn_ctx {
@@ -35,12 +36,14 @@ struct unihenn_ctx {
     std::vector<u64> q_mod;           // [a][b] = q_a mod q_b   (n_mod x n_mod)
     std::vector<u64> inv_last;        // [l][i] = q_l^-1 mod q_i (Shoup pair interleaved)
     std::vector<u64> p_inv;           // [i] = P^-1 mod q_i (value, shoup)
+    std::vector<u64> p_mod;           // [i] = P mod q_i (value, shoup)
     // device memory
     Modulus* d_mod = nullptr;
     u64* d_tw = nullptr;              // 4 tables of n_mod * N
     u64* d_qmod = nullptr;            // q_mod on device
     u64* d_inv_last = nullptr;
     u64* d_p_inv = nullptr;
+    u64* d_p_mod = nullptr;
     uint32_t* d_galois_e = nullptr;   // 5^k mod 2N, k < N/2
     double* d_cos = nullptr;          // cos(pi t / N) as double-double, t < 2N: [2N][2]
     int device = 0;

@@ -21,8 +21,10 @@ void launch_sub_scale(const unihenn_ctx* c, u64* out, const u64* x, int x_limbs,
                       hipStream_t s);
 void launch_gather_rows(const unihenn_ctx* c, u64* dst, const u64* src, int rows, int per, int src_stride, int off,
                         hipStream_t s);
+// pl (here and below): limb index taken modulo the special prime P (extended
+// operands over {q_0..q_{nl-2}, P}, pl = nl - 1), or -1
 void launch_mac(const unihenn_ctx* c, u64* acc, const MacTerms& terms, int n_terms, int nl, int batch, int accumulate,
-                hipStream_t s);
+                hipStream_t s, int pl = -1);
 void launch_tensor_mul(const unihenn_ctx* c, u64* d0, u64* d1, u64* d2, const u64* a, const u64* b, int b_limbs,
                        int batch, int nl, hipStream_t s);
 void launch_tensor_square(const unihenn_ctx* c, u64* d0, u64* d1, u64* d2, const u64* ct, int batch, int nl,
@@ -79,6 +81,10 @@ void group_modup(const unihenn_ctx* c, int D, const u64* const* dsrc, int dstrid
 // are computed here (hoisted), otherwise the caller filled aux.
 void group_switch(const unihenn_ctx* c, const GroupArgs& ga, int B, int nl, bool c0_only, const u64* modup, u64* aux,
                   u64* U, u64* Up, u64* R, hipStream_t s);
+// extended rotations (deferred ModDown): dst_e [B][2][nl+1] = (P tau(c0) +
+// U_0, U_1) over {q_0..q_{nl-1}, P}, U the inner product of the digits in
+// modup with element e's key; dst must not overlap any src
+void group_switch_ext(const unihenn_ctx* c, const GroupArgs& ga, int B, int nl, const u64* modup, hipStream_t s);
 // aux[e] = tau_{g_e}(src_e), both polynomials
 void group_auto_both(const unihenn_ctx* c, const GroupArgs& ga, int B, int nl, u64* aux, hipStream_t s);
 
@@ -92,7 +98,7 @@ struct MacMulti {
 };
 // acc[o] (+)= sum_t pt(o, t) (*) ct[t] for o < n_out, t < n_terms
 void launch_mac_multi(const unihenn_ctx* c, const MacMulti& m, int n_out, int n_terms, int nl, int batch,
-                      int accumulate, hipStream_t s);
+                      int accumulate, hipStream_t s, int pl = -1);
 
 // ---- grouped elementwise steps (independent steps of one kind, one launch) ----
 #define UH_EW_GROUP_MAX 32
@@ -102,7 +108,14 @@ struct EwGroup {
     const u64* a[UH_EW_GROUP_MAX];
     const u64* b[UH_EW_GROUP_MAX];   // second operand (add) or plaintext (add_plain)
 };
-void launch_group_add(const unihenn_ctx* c, const EwGroup& g, int batch, int nl, bool plain, hipStream_t s);
+void launch_group_add(const unihenn_ctx* c, const EwGroup& g, int batch, int nl, bool plain, hipStream_t s,
+                      int pl = -1);
+// out_e [B][2][nl+1] = P a_e ([B][2][nl]): limbs i < nl times P mod q_i, limb nl zero
+void launch_group_to_ext(const unihenn_ctx* c, const EwGroup& g, int batch, int nl, hipStream_t s);
+// ModDown of E extended ciphertext batches [B][2][nl+1] -> [B][2][nl]; ws
+// holds E * B * 2 * (nl + 1) rows
+void group_moddown(const unihenn_ctx* c, int E, const u64* const* in, u64* const* out, int batch, int nl, u64* ws,
+                   hipStream_t s);
 // rescale of E ciphertext batches [B][2][nl] -> [B][2][nl-1]; ws holds
 // E * B * 2 * nl rows
 void group_rescale(const unihenn_ctx* c, int E, const u64* const* in, u64* const* out, int batch, int nl, u64* ws,
@@ -122,4 +135,4 @@ struct MacGroup {
     const u64* ct[UH_MACG_MAX];
     const u64* pt[UH_MACG_MAX];
 };
-void launch_mac_group(const unihenn_ctx* c, const MacGroup& m, int nl, int batch, hipStream_t s);
+void launch_mac_group(const unihenn_ctx* c, const MacGroup& m, int nl, int batch, hipStream_t s, int pl = -1);

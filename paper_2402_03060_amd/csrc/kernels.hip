@@ -190,14 +190,14 @@ __global__ void k_gather_rows(u64* __restrict__ dst, const u64* __restrict__ src
 
 template <int BCH>
 __global__ void __launch_bounds__(EW_THREADS) k_mac(u64* __restrict__ acc, MacTerms terms, int n_terms, DevCtx ctx,
-                                                    int nl, int batch, int accumulate)
+                                                    int nl, int batch, int accumulate, int pl)
 {
     const int n = ctx.n;
     const int k = blockIdx.x * EW_THREADS + threadIdx.x;
     if (k >= n) return;
     const int i = blockIdx.y;
     const int b0 = blockIdx.z * BCH;
-    const Modulus M = ctx.mod[i];
+    const Modulus M = ctx.mod[i == pl ? ctx.p_index : i];
     const int period = wide_period(M.ratio);
     WideAcc a[2 * BCH];
 #pragma unroll
@@ -354,17 +354,17 @@ void launch_gather_rows(const unihenn_ctx* c, u64* dst, const u64* src, int rows
 }
 
 void launch_mac(const unihenn_ctx* c, u64* acc, const MacTerms& terms, int n_terms, int nl, int batch, int accumulate,
-                hipStream_t s)
+                hipStream_t s, int pl)
 {
     // algorithmic bytes: plaintexts once, ciphertexts once, acc written (and read when accumulating)
     double rows = (double)n_terms * nl + (double)n_terms * batch * 2 * nl + (1 + accumulate) * batch * 2.0 * nl;
     LaunchTimer tm(KF_MAC, 8.0 * c->n * rows, s);
     if (batch >= 4) {
         k_mac<4><<<grid_rows(c->n, nl, (batch + 3) / 4), EW_THREADS, 0, s>>>(acc, terms, n_terms, c->dev, nl, batch,
-                                                                             accumulate);
+                                                                             accumulate, pl);
     } else {
         k_mac<1><<<grid_rows(c->n, nl, batch), EW_THREADS, 0, s>>>(acc, terms, n_terms, c->dev, nl, batch,
-                                                                   accumulate);
+                                                                   accumulate, pl);
     }
 }
 
@@ -454,7 +454,12 @@ __global__ void k_group_gather(u64* __restrict__ dcoef, GroupArgs ga, int nl, in
     dcoef[(((size_t)blk * batch + b) * nl + j) * n + k] = ga.dsrc[blk][((size_t)b * ga.dstride + j) * n + k];
 }
 
-template <int MAXL>
+// Inner product of the ModUp digits with each element's key, limb t of
+// {q_0..q_{nl-1}, P} per thread.  EXT = false: U [E][B][2][nl] and Up
+// [E][B][2] for the ModDown that follows.  EXT = true: the extended rotation
+// (P tau(c0) + U_0, U_1) straight into dst_e [B][2][nl+1] (limb nl = P),
+// with tau(c0) read from src_e through the automorphism.
+template <int MAXL, bool EXT>
 __global__ void __launch_bounds__(EW_THREADS) k_group_inner(u64* __restrict__ U, u64* __restrict__ Up,
                                                             const u64* __restrict__ modup, GroupArgs ga, DevCtx ctx,
                                                             int nl, int nd, int batch, int BB, int Zb, int C, int W)
@@ -479,6 +484,13 @@ __global__ void __launch_bounds__(EW_THREADS) k_group_inner(u64* __restrict__ U,
     const u64* __restrict__ key = ga.key[e];
     const u64* __restrict__ dsrc = ga.dsrc[ga.blk[e]];
     const int blk = ga.blk[e];
+    u32 c0i = 0;
+    u64 pm = 0, pm_sh = 0;
+    if (EXT && t < nl) {
+        c0i = auto_perm((u32)k, ga.g[e], ctx.log_n);
+        pm = ctx.p_mod[2 * t];
+        pm_sh = ctx.p_mod[2 * t + 1];
+    }
     u64 k0[MAXL], k1[MAXL];
 #pragma unroll
     for (int j = 0; j < MAXL; ++j) {
@@ -511,7 +523,19 @@ __global__ void __launch_bounds__(EW_THREADS) k_group_inner(u64* __restrict__ U,
                 }
             }
         }
-        const u64 r0 = wide_redc(a0, M.q, M.qinv_neg), r1 = wide_redc(a1, M.q, M.qinv_neg);
+        u64 r0 = wide_redc(a0, M.q, M.qinv_neg);
+        const u64 r1 = wide_redc(a1, M.q, M.qinv_neg);
+        if (EXT) {
+            u64* __restrict__ dst = ga.dst[e];
+            const size_t base = (size_t)b * 2 * (nl + 1);
+            if (t < nl) {
+                const u64 x = ga.src[e][((size_t)b * 2 * nl + t) * n + c0i];
+                r0 = add_mod(r0, mul_shoup(x, pm, pm_sh, M.q), M.q);
+            }
+            dst[(base + t) * n + k] = r0;
+            dst[(base + nl + 1 + t) * n + k] = r1;
+            continue;
+        }
         const size_t eb = (size_t)e * batch + b;
         if (t < nl) {
             U[((eb * 2 + 0) * nl + t) * n + k] = r0;
@@ -574,25 +598,40 @@ void group_modup(const unihenn_ctx* c, int D, const u64* const* dsrc, int dstrid
     launch_ntt_fwd(c, modup, D * B * nl * nl, rowmap_modup(nl, c->n_data), s);
 }
 
+namespace {
+template <bool EXT>
+void launch_group_inner(const unihenn_ctx* c, const GroupArgs& ga, int B, int nl, const u64* modup, u64* U, u64* Up,
+                        hipStream_t s)
+{
+    const int E = ga.E;
+    const unsigned gx = (c->n + EW_THREADS - 1) / EW_THREADS;
+    // keys, digits, the outputs (and the c0 rows of the sources when extended)
+    double rows = (double)E * 2.0 * nl * (nl + 1) + (double)E * B * (nl * (nl + 1) + 2 * (nl + 1) + (EXT ? nl : 0));
+    LaunchTimer tm(KF_KS_INNER, 8.0 * c->n * rows, s);
+    int bb, zb;
+    inner_split((long)gx, nl + 1, E, B, c->ks_min_wg, &bb, &zb);
+    const int W = zb * (int)gx * (nl + 1) * E;
+    const unsigned gw = xcd_grid(W);
+#define GI(M) k_group_inner<M, EXT><<<gw, EW_THREADS, 0, s>>>(U, Up, modup, ga, c->dev, nl, c->n_data, B, bb, zb, (int)gx, W)
+    if (nl <= 4) GI(4);
+    else if (nl <= 8) GI(8);
+    else if (nl <= 12) GI(12);
+    else GI(UH_MAX_MODULI);
+#undef GI
+}
+}  // namespace
+
+void group_switch_ext(const unihenn_ctx* c, const GroupArgs& ga, int B, int nl, const u64* modup, hipStream_t s)
+{
+    launch_group_inner<true>(c, ga, B, nl, modup, nullptr, nullptr, s);
+}
+
 void group_switch(const unihenn_ctx* c, const GroupArgs& ga, int B, int nl, bool c0_only, const u64* modup, u64* aux,
                   u64* U, u64* Up, u64* R, hipStream_t s)
 {
     const int E = ga.E;
     const unsigned gx = (c->n + EW_THREADS - 1) / EW_THREADS;
-    {
-        double rows = (double)E * 2.0 * nl * (nl + 1) + (double)E * B * (nl * (nl + 1) + 2 * (nl + 1));
-        LaunchTimer tm(KF_KS_INNER, 8.0 * c->n * rows, s);
-        int bb, zb;
-        inner_split((long)gx, nl + 1, E, B, c->ks_min_wg, &bb, &zb);
-        const int W = zb * (int)gx * (nl + 1) * E;
-        const unsigned gw = xcd_grid(W);
-#define GI(M) k_group_inner<M><<<gw, EW_THREADS, 0, s>>>(U, Up, modup, ga, c->dev, nl, c->n_data, B, bb, zb, (int)gx, W)
-        if (nl <= 4) GI(4);
-        else if (nl <= 8) GI(8);
-        else if (nl <= 12) GI(12);
-        else GI(UH_MAX_MODULI);
-#undef GI
-    }
+    launch_group_inner<false>(c, ga, B, nl, modup, U, Up, s);
     launch_ntt_inv(c, Up, E * B * 2, rowmap_list({c->n_data}), s);
     {
         // the c0 addend: tau(c0) read straight from the source (c0_only), or
@@ -658,7 +697,8 @@ void group_auto_both(const unihenn_ctx* c, const GroupArgs& ga, int B, int nl, u
 namespace {
 template <int OPT, int BCH>
 __global__ void __launch_bounds__(EW_THREADS) k_mac_multi(MacMulti m, int n_out, int n_terms, DevCtx ctx, int nl,
-                                                          int batch, int accumulate, int G, int Z, int C, int W)
+                                                          int batch, int accumulate, int G, int Z, int C, int W,
+                                                          int pl)
 {
     const int L = xcd_logical(W);
     if (L < 0) return;
@@ -670,7 +710,7 @@ __global__ void __launch_bounds__(EW_THREADS) k_mac_multi(MacMulti m, int n_out,
     const int k = x * EW_THREADS + threadIdx.x;
     if (k >= n) return;
     const int o0 = g * OPT, b0 = z * BCH;
-    const Modulus M = ctx.mod[i];
+    const Modulus M = ctx.mod[i == pl ? ctx.p_index : i];
     const int period = wide_period(M.ratio);
     WideAcc a[OPT][2 * BCH];
 #pragma unroll
@@ -719,10 +759,11 @@ __global__ void __launch_bounds__(EW_THREADS) k_mac_multi(MacMulti m, int n_out,
 
 template <int OPT, int BCH>
 void launch_mm(const MacMulti& m, int n_out, int n_terms, DevCtx dev, int nl, int batch, int accumulate, int G,
-               int Z, int C, hipStream_t s)
+               int Z, int C, int pl, hipStream_t s)
 {
     const int W = G * Z * C * nl;
-    k_mac_multi<OPT, BCH><<<xcd_grid(W), EW_THREADS, 0, s>>>(m, n_out, n_terms, dev, nl, batch, accumulate, G, Z, C, W);
+    k_mac_multi<OPT, BCH><<<xcd_grid(W), EW_THREADS, 0, s>>>(m, n_out, n_terms, dev, nl, batch, accumulate, G, Z, C, W,
+                                                              pl);
 }
 }  // namespace
 
@@ -742,7 +783,7 @@ void mac_multi_shape(int n_out, int nl, int batch, int n, int min_wg, int* opt, 
 }
 
 void launch_mac_multi(const unihenn_ctx* c, const MacMulti& m, int n_out, int n_terms, int nl, int batch,
-                      int accumulate, hipStream_t s)
+                      int accumulate, hipStream_t s, int pl)
 {
     // algorithmic bytes: each term ciphertext once, each plaintext once, outputs written (read when accumulating)
     double rows = (double)n_terms * batch * 2 * nl + (double)n_out * n_terms * nl +
@@ -751,7 +792,7 @@ void launch_mac_multi(const unihenn_ctx* c, const MacMulti& m, int n_out, int n_
     int opt, bch;
     mac_multi_shape(n_out, nl, batch, c->n, c->mac_min_wg, &opt, &bch);
     const int G = (n_out + opt - 1) / opt, Z = (batch + bch - 1) / bch, C = (c->n + EW_THREADS - 1) / EW_THREADS;
-#define MM(O, B) launch_mm<O, B>(m, n_out, n_terms, c->dev, nl, batch, accumulate, G, Z, C, s)
+#define MM(O, B) launch_mm<O, B>(m, n_out, n_terms, c->dev, nl, batch, accumulate, G, Z, C, pl, s)
     switch (bch * 100 + opt) {
     case 101: MM(1, 1); break;
     case 102: MM(2, 1); break;
@@ -771,7 +812,7 @@ void launch_mac_multi(const unihenn_ctx* c, const MacMulti& m, int n_out, int n_
 
 // ------------------------------------------------------------------ grouped elementwise steps
 namespace {
-__global__ void k_group_add(EwGroup g, DevCtx ctx, int nl, int plain)
+__global__ void k_group_add(EwGroup g, DevCtx ctx, int nl, int plain, int pl)
 {
     const int n = ctx.n;
     const int k = blockIdx.x * EW_THREADS + threadIdx.x;
@@ -779,7 +820,7 @@ __global__ void k_group_add(EwGroup g, DevCtx ctx, int nl, int plain)
     const int r = blockIdx.y;  // (b * 2 + c) * nl + i
     const int e = blockIdx.z;
     const int i = r % nl, c = (r / nl) & 1;
-    const u64 q = ctx.mod[i].q;
+    const u64 q = ctx.mod[i == pl ? ctx.p_index : i].q;
     const u64 x = g.a[e][(size_t)r * n + k];
     u64 v;
     if (plain) v = c == 0 ? add_mod(x, g.b[e][(size_t)i * n + k], q) : x;
@@ -795,6 +836,21 @@ __global__ void k_group_last(u64* __restrict__ last, EwGroup g, int nl, int n)
     const int p = blockIdx.y;  // b * 2 + c
     const int e = blockIdx.z;
     last[((size_t)e * gridDim.y + p) * n + k] = g.a[e][((size_t)p * nl + nl - 1) * n + k];
+}
+
+// out_e[(b * 2 + c) * (nl + 1) + i] = P in_e[(b * 2 + c) * nl + i] (i < nl), 0 (i = nl)
+__global__ void k_group_to_ext(EwGroup g, DevCtx ctx, int nl)
+{
+    const int n = ctx.n;
+    const int k = blockIdx.x * EW_THREADS + threadIdx.x;
+    if (k >= n) return;
+    const int r = blockIdx.y;  // p * (nl + 1) + i
+    const int e = blockIdx.z;
+    const int i = r % (nl + 1), p = r / (nl + 1);
+    u64 v = 0;
+    if (i < nl)
+        v = mul_shoup(g.a[e][((size_t)p * nl + i) * n + k], ctx.p_mod[2 * i], ctx.p_mod[2 * i + 1], ctx.mod[i].q);
+    g.out[e][(size_t)r * n + k] = v;
 }
 
 // out_e[p][i] = (in_e[p][i] - r[e][p][i]) * inv_i (+ d0 / d1 addends: relinearisation)
@@ -870,7 +926,7 @@ __global__ void k_group_tensor(u64* __restrict__ d0, u64* __restrict__ d1, u64* 
 }
 
 template <int BCH>
-__global__ void __launch_bounds__(EW_THREADS) k_mac_group(MacGroup m, DevCtx ctx, int nl, int batch)
+__global__ void __launch_bounds__(EW_THREADS) k_mac_group(MacGroup m, DevCtx ctx, int nl, int batch, int pl)
 {
     const int n = ctx.n;
     const int k = blockIdx.x * EW_THREADS + threadIdx.x;
@@ -878,7 +934,7 @@ __global__ void __launch_bounds__(EW_THREADS) k_mac_group(MacGroup m, DevCtx ctx
     const int i = blockIdx.y;
     const int e = blockIdx.z % m.E;
     const int b0 = (blockIdx.z / m.E) * BCH;
-    const Modulus M = ctx.mod[i];
+    const Modulus M = ctx.mod[i == pl ? ctx.p_index : i];
     const int period = wide_period(M.ratio);
     WideAcc a[2 * BCH];
 #pragma unroll
@@ -906,11 +962,63 @@ __global__ void __launch_bounds__(EW_THREADS) k_mac_group(MacGroup m, DevCtx ctx
 }
 }  // namespace
 
-void launch_group_add(const unihenn_ctx* c, const EwGroup& g, int batch, int nl, bool plain, hipStream_t s)
+void launch_group_add(const unihenn_ctx* c, const EwGroup& g, int batch, int nl, bool plain, hipStream_t s, int pl)
 {
     LaunchTimer tm(KF_ADD, 8.0 * c->n * g.E * (batch * 2.0 * nl * (plain ? 2.0 : 3.0) + (plain ? nl : 0)), s);
     dim3 g3((c->n + EW_THREADS - 1) / EW_THREADS, batch * 2 * nl, g.E);
-    k_group_add<<<g3, EW_THREADS, 0, s>>>(g, c->dev, nl, plain ? 1 : 0);
+    k_group_add<<<g3, EW_THREADS, 0, s>>>(g, c->dev, nl, plain ? 1 : 0, pl);
+}
+
+void launch_group_to_ext(const unihenn_ctx* c, const EwGroup& g, int batch, int nl, hipStream_t s)
+{
+    LaunchTimer tm(KF_OTHER, 8.0 * c->n * g.E * batch * 2.0 * (2 * nl + 1), s);
+    dim3 g3((c->n + EW_THREADS - 1) / EW_THREADS, batch * 2 * (nl + 1), g.E);
+    k_group_to_ext<<<g3, EW_THREADS, 0, s>>>(g, c->dev, nl);
+}
+
+// ModDown of extended sums: the P rows gathered and inverse transformed, then
+// lifted, forward transformed and combined, (x - R) P^-1, in one fused pass
+void group_moddown(const unihenn_ctx* c, int E, const u64* const* in, u64* const* out, int B, int nl, u64* ws,
+                   hipStream_t s)
+{
+    const size_t rn = (size_t)c->n;
+    EwGroup g;
+    memset(&g, 0, sizeof(g));
+    g.E = E;
+    for (int e = 0; e < E; ++e) {
+        g.a[e] = in[e];
+        g.out[e] = out[e];
+    }
+    u64* last = ws;                               // [E][B][2]
+    u64* R = ws + (size_t)E * B * 2 * rn;         // [E][B][2][nl]
+    const unsigned gx = (c->n + EW_THREADS - 1) / EW_THREADS;
+    {
+        LaunchTimer tm(KF_OTHER, 16.0 * c->n * E * B * 2, s);
+        k_group_last<<<dim3(gx, B * 2, E), EW_THREADS, 0, s>>>(last, g, nl + 1, c->n);
+    }
+    launch_ntt_inv(c, last, E * B * 2, rowmap_list({c->n_data}), s);
+    {
+        FuseArgs fa;
+        memset(&fa, 0, sizeof(fa));
+        fa.src = last;
+        fa.src_mod = c->n_data;
+        fa.nl = nl;
+        fa.polys = B * 2;
+        fa.x_limbs = nl + 1;
+        fa.inv = c->d_p_inv;
+        for (int e = 0; e < E; ++e) {
+            fa.x[e] = in[e];
+            fa.out[e] = out[e];
+            fa.add_perm[e] = 1;
+        }
+        if (launch_ntt_fwd_fused(c, R, fa, E * B * 2 * nl, KF_MODDOWN, s)) return;
+    }
+    launch_lift_last(c, R, last, E * B * 2, nl, c->n_data, KF_MODDOWN, s);
+    launch_ntt_fwd(c, R, E * B * 2 * nl, rowmap_ct(nl), s);
+    {
+        LaunchTimer tm(KF_MODDOWN, 8.0 * c->n * E * B * 2 * nl * 3, s);
+        k_group_sub_scale2<<<dim3(gx, B * 2 * nl, E), EW_THREADS, 0, s>>>(g, R, nl + 1, c->d_p_inv, c->dev, nl, B * 2);
+    }
 }
 
 void group_rescale(const unihenn_ctx* c, int E, const u64* const* in, u64* const* out, int B, int nl, u64* ws,
@@ -1026,13 +1134,13 @@ void group_square(const unihenn_ctx* c, int E, const u64* const* in, u64* const*
     group_rescale(c, E, ins.data(), out, B, nl, scratch, s);
 }
 
-void launch_mac_group(const unihenn_ctx* c, const MacGroup& m, int nl, int batch, hipStream_t s)
+void launch_mac_group(const unihenn_ctx* c, const MacGroup& m, int nl, int batch, hipStream_t s, int pl)
 {
     double rows = (double)m.E * m.T * (nl + batch * 2.0 * nl) + m.E * batch * 2.0 * nl;
     LaunchTimer tm(KF_MAC, 8.0 * c->n * rows, s);
     const unsigned gx = (c->n + EW_THREADS - 1) / EW_THREADS;
     if (batch >= 4)
-        k_mac_group<4><<<dim3(gx, nl, m.E * ((batch + 3) / 4)), EW_THREADS, 0, s>>>(m, c->dev, nl, batch);
+        k_mac_group<4><<<dim3(gx, nl, m.E * ((batch + 3) / 4)), EW_THREADS, 0, s>>>(m, c->dev, nl, batch, pl);
     else
-        k_mac_group<1><<<dim3(gx, nl, m.E * batch), EW_THREADS, 0, s>>>(m, c->dev, nl, batch);
+        k_mac_group<1><<<dim3(gx, nl, m.E * batch), EW_THREADS, 0, s>>>(m, c->dev, nl, batch, pl);
 }

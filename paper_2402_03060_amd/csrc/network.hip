@@ -24,16 +24,21 @@
 #include "kernels.h"
 
 int encode_scaled_batch(const unihenn_ctx* c, const double* z, int n_slots, const double* w, int n_w, double scale,
-                        int nl, int mont, u64* out, hipStream_t s);
+                        int nl, int mont, u64* out, hipStream_t s, int ext);
 
 namespace {
 
-enum StepKind { ST_DROP, ST_ROT, ST_MAC, ST_MACM, ST_RESCALE, ST_ADD, ST_ADD_PLAIN, ST_SQUARE, ST_MUL };
+enum StepKind { ST_DROP, ST_ROT, ST_MAC, ST_MACM, ST_RESCALE, ST_ADD, ST_ADD_PLAIN, ST_SQUARE, ST_MUL, ST_EXT, ST_MODDOWN };
 
+// A register holds a batch of ciphertexts at level nl; an extended register
+// (deferred ModDown) holds them over {q_0..q_{nl-1}, P}, one limb more, and
+// stands for their ModDown.
 struct VReg {
     int nl;
     double scale;
     int phys = -1;
+    bool ext = false;
+    int limbs() const { return nl + (ext ? 1 : 0); }
 };
 
 struct Term {
@@ -60,6 +65,7 @@ struct PtRequest {
     int nl;
     int mont;
     size_t offset;
+    int ext;  // residue mod P as limb nl (plaintexts of extended products)
 };
 
 struct LayerRecord {
@@ -115,6 +121,7 @@ struct unihenn_net {
     std::map<int, const u64*> keys;
     const u64* rlk = nullptr;
     int mode = UNIHENN_EVAL_PLAIN;
+    bool lazy = false;  // planned with deferred ModDown (UNIHENN_PLAN_LAZY_MODDOWN)
     // captured evaluations (UNIHENN_EVAL_GRAPH), one per batch size and buffer set
     hipStream_t gstream = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
@@ -141,6 +148,13 @@ struct Planner {
     std::map<int, int> rotset;
     std::string err;
     int err_code = 0;
+    // deferred ModDown: rotations by r != 0 give extended registers; sums
+    // and plaintext products of extended registers stay extended and are
+    // brought down once, before their rescale; every other use of an
+    // extended register takes its ModDown first (once per register)
+    bool lazy = false;
+    std::map<int, int> md_of, ext_of;
+    std::map<size_t, int> pt_ext;  // plaintext offset -> has the P limb
 
     int fail(int code, const std::string& m)
     {
@@ -148,10 +162,50 @@ struct Planner {
         return -1;
     }
 
-    int newreg(int nl, double scale)
+    int newreg(int nl, double scale, bool ext = false)
     {
-        net->regs.push_back({nl, scale, -1});
+        VReg r;
+        r.nl = nl;
+        r.scale = scale;
+        r.ext = ext;
+        net->regs.push_back(r);
         return (int)net->regs.size() - 1;
+    }
+
+    bool is_ext(int r) const { return r >= 0 && net->regs[r].ext; }
+
+    // the register in normal form: an extended one is brought down (once)
+    int norm(int r)
+    {
+        if (!is_ext(r)) return r;
+        auto it = md_of.find(r);
+        if (it != md_of.end()) return it->second;
+        const VReg v = net->regs[r];
+        int d = newreg(v.nl, v.scale);
+        Step s;
+        s.kind = ST_MODDOWN;
+        s.dst = d;
+        s.a = r;
+        net->steps.push_back(s);
+        md_of[r] = d;
+        return d;
+    }
+
+    // the register in extended form: a normal one enters as P x (once)
+    int to_ext(int r)
+    {
+        if (is_ext(r)) return r;
+        auto it = ext_of.find(r);
+        if (it != ext_of.end()) return it->second;
+        const VReg v = net->regs[r];
+        int d = newreg(v.nl, v.scale, true);
+        Step s;
+        s.kind = ST_EXT;
+        s.dst = d;
+        s.a = r;
+        net->steps.push_back(s);
+        ext_of[r] = d;
+        return d;
     }
 
     int norm_rot(long r) const
@@ -164,7 +218,8 @@ struct Planner {
     {
         int rr = norm_rot(r);
         if (rr == 0) return src;
-        int d = newreg(net->regs[src].nl, net->regs[src].scale);
+        src = norm(src);
+        int d = newreg(net->regs[src].nl, net->regs[src].scale, lazy);
         Step s;
         s.kind = ST_ROT;
         s.dst = d;
@@ -177,9 +232,13 @@ struct Planner {
 
     int add(int a, int b)
     {
+        if (is_ext(a) || is_ext(b)) {
+            a = to_ext(a);
+            b = to_ext(b);
+        }
         if (net->regs[a].nl != net->regs[b].nl || net->regs[a].scale != net->regs[b].scale)
             return fail(UNIHENN_ESCALE, "addition of ciphertexts at different levels or scales");
-        int d = newreg(net->regs[a].nl, net->regs[a].scale);
+        int d = newreg(net->regs[a].nl, net->regs[a].scale, is_ext(a));
         Step s;
         s.kind = ST_ADD;
         s.dst = d;
@@ -200,14 +259,25 @@ struct Planner {
         return acc;
     }
 
-    // request plaintexts Encode(w_t * z) at `scale` and nl limbs; returns the
-    // offset of the first (the others follow, nl * N words apart)
-    size_t request(const std::vector<double>& z, const std::vector<double>& w, double scale, int nl, int mont)
+    // request plaintexts Encode(w_t * z) at `scale` and nl limbs (nl + 1
+    // with ext: the residue mod P follows); returns the offset of the first
+    // (the others follow, (nl + ext) * N words apart)
+    size_t request(const std::vector<double>& z, const std::vector<double>& w, double scale, int nl, int mont,
+                   bool ext = false)
     {
-        PtRequest r{z, w, scale, nl, mont, net->pt_words};
-        net->pt_words += w.size() * (size_t)nl * c->n;
+        PtRequest r{z, w, scale, nl, mont, net->pt_words, ext ? 1 : 0};
+        for (size_t t = 0; t < w.size(); ++t) pt_ext[net->pt_words + t * (size_t)(nl + r.ext) * c->n] = r.ext;
+        net->pt_words += w.size() * (size_t)(nl + r.ext) * c->n;
         net->requests.push_back(std::move(r));
         return net->requests.back().offset;
+    }
+
+    // whether a sum over these sources runs in extended form
+    bool any_ext(const std::vector<int>& srcs) const
+    {
+        for (int r : srcs)
+            if (is_ext(r)) return true;
+        return false;
     }
 
     std::vector<double> mask(const std::vector<long>& pos, double value = 1.0) const
@@ -219,25 +289,34 @@ struct Planner {
     }
 
     // out = Rescale(sum_t pts[t] (*) srcs[t]); one MAC step then one rescale
-    int mac_rescale(const std::vector<Term>& terms)
+    // (extended sources: the sum is extended and brought down before the
+    // rescale; its plaintexts must carry the P limb)
+    int mac_rescale(std::vector<Term> terms)
     {
         if (terms.empty()) return fail(UNIHENN_EINVAL, "empty sum");
+        bool ext = false;
+        for (const Term& t : terms) ext |= is_ext(t.src);
+        for (Term& t : terms) {
+            if (ext) t.src = to_ext(t.src);
+            if (pt_ext.at(t.pt) != (int)ext) return fail(UNIHENN_EINVAL, "plaintext form does not match its sum");
+        }
         const VReg r0 = net->regs[terms[0].src];
         for (const Term& t : terms)
             if (net->regs[t.src].nl != r0.nl || net->regs[t.src].scale != r0.scale)
                 return fail(UNIHENN_ESCALE, "multiply-accumulate terms at different levels or scales");
         if (r0.nl < 2) return fail(UNIHENN_ELEVEL, "level exhausted");
-        int acc = newreg(r0.nl, r0.scale * delta);
+        int acc = newreg(r0.nl, r0.scale * delta, ext);
         Step s;
         s.kind = ST_MAC;
         s.dst = acc;
         s.terms = terms;
         net->steps.push_back(s);
-        return rescale(acc);
+        return rescale(norm(acc));
     }
 
     int rescale(int a)
     {
+        a = norm(a);
         const VReg r = net->regs[a];
         if (r.nl < 2) return fail(UNIHENN_ELEVEL, "level exhausted");
         int d = newreg(r.nl - 1, r.scale / (double)c->primes[r.nl - 1]);
@@ -251,6 +330,7 @@ struct Planner {
 
     int add_plain_vec(int a, const std::vector<double>& z)
     {
+        a = norm(a);
         const VReg r = net->regs[a];
         double one = 1.0;
         size_t off = request(z, std::vector<double>(1, one), r.scale, r.nl, 0);
@@ -266,6 +346,7 @@ struct Planner {
 
     int square(int a)
     {
+        a = norm(a);
         const VReg r = net->regs[a];
         if (r.nl < 2) return fail(UNIHENN_ELEVEL, "level exhausted");
         const double s2 = r.scale * r.scale;
@@ -281,6 +362,8 @@ struct Planner {
     // Mul(C) + relinearisation + rescale of a by b (b dropped to a's level)
     int mul(int a, int b)
     {
+        a = norm(a);
+        b = norm(b);
         const VReg ra = net->regs[a], rb = net->regs[b];
         if (ra.nl < 2) return fail(UNIHENN_ELEVEL, "level exhausted");
         if (rb.nl < ra.nl) return fail(UNIHENN_ELEVEL, "product operand below the other's level");
@@ -324,7 +407,7 @@ struct Planner {
             if (!mapped.count(reg)) {
                 const std::vector<long> pos = valid_positions(L, reg);
                 const VReg r = net->regs[reg];
-                size_t off = request(mask(pos), std::vector<double>(1, cc * p * p), delta, r.nl, 1);
+                size_t off = request(mask(pos), std::vector<double>(1, cc * p * p), delta, r.nl, 1, is_ext(reg));
                 int y = mac_rescale({Term{reg, off}});
                 if (y < 0) return -1;
                 y = add_plain_vec(y, mask(pos, cb * p));
@@ -364,6 +447,13 @@ struct Planner {
         bool one_ct = true;
         for (int i = 1; i < ci; ++i) one_ct &= L.ch_reg[i] == L.ch_reg[0];
         one_ct &= ci > 1;
+        // deferred ModDown: the sums are extended when any term is (a
+        // rotation by r != 0, or an extended input)
+        bool ext = false;
+        if (lazy)
+            for (int i = 0; i < ci; ++i)
+                for (int j = 0; j < g.kh; ++j)
+                    for (int k = 0; k < g.kw; ++k) ext |= norm_rot(amount(i, j, k)) != 0 || is_ext(L.ch_reg[i]);
 
         std::vector<int> acc(co, -1);
         // plaintexts: per output, every (i, j, k) weight on the valid output slots
@@ -373,12 +463,12 @@ struct Planner {
             for (int i = 0; i < ci; ++i)
                 for (int j = 0; j < g.kh; ++j)
                     for (int k = 0; k < g.kw; ++k) w.push_back(weight(o, i, j, k));
-            size_t off = request(m_out, w, delta, nl, 1);
-            for (size_t t = 0; t < w.size(); ++t) pt[o].push_back(off + t * (size_t)nl * c->n);
+            size_t off = request(m_out, w, delta, nl, 1, ext);
+            for (size_t t = 0; t < w.size(); ++t) pt[o].push_back(off + t * (size_t)(nl + ext) * c->n);
         }
         const int kk = g.kh * g.kw;
         // one step per input channel: every output accumulates that channel's K^2 products
-        for (int o = 0; o < co; ++o) acc[o] = newreg(nl, s_in * delta);
+        for (int o = 0; o < co; ++o) acc[o] = newreg(nl, s_in * delta, ext);
         auto emit_macs = [&](int i_begin, int i_end, const std::vector<int>& rot_regs, bool accumulate) {
             Step s;
             s.kind = ST_MACM;
@@ -406,6 +496,7 @@ struct Planner {
                         long r = norm_rot(amount(i, j, k));
                         auto it = seen.find(r);
                         int reg = it != seen.end() ? it->second : rot(L.ch_reg[0], r);
+                        if (ext) reg = to_ext(reg);
                         seen[r] = reg;
                         rr.push_back(reg);
                     }
@@ -420,6 +511,7 @@ struct Planner {
                         long r = norm_rot(amount(i, j, k));
                         auto it = seen.find(r);
                         int reg = it != seen.end() ? it->second : rot(L.ch_reg[i], r);
+                        if (ext) reg = to_ext(reg);
                         seen[r] = reg;
                         rr.push_back(reg);
                     }
@@ -503,38 +595,47 @@ struct Planner {
         const int S = L.I, Wi = L.W, Hi = L.H, Wimg = L.W_img;
         std::vector<int> ys = L.ch_reg;
         const int nl = net->regs[ys[0]].nl;
+        // a sum is extended when any of its terms is; its plaintexts follow (pts[ext])
         if (L.prev == 2) {
             // invalid values between the pooled ones: one mask per column x
-            std::vector<size_t> pts;
-            for (int x = 0; x < Wi; ++x) {
-                std::vector<long> pos;
-                for (int y = 0; y < Hi; ++y) pos.push_back((long)S * Wimg * y + x);
-                pts.push_back(request(mask(pos), std::vector<double>(1, L.pending), delta, nl, 1));
-            }
+            std::vector<size_t> pts[2];
             for (int& X : ys) {
+                std::vector<int> srcs;
+                for (int x = 0; x < Wi; ++x) srcs.push_back(rot(X, (long)x * (S - 1)));
+                const bool ext = any_ext(srcs);
+                if (pts[ext].empty())
+                    for (int x = 0; x < Wi; ++x) {
+                        std::vector<long> pos;
+                        for (int y = 0; y < Hi; ++y) pos.push_back((long)S * Wimg * y + x);
+                        pts[ext].push_back(request(mask(pos), std::vector<double>(1, L.pending), delta, nl, 1, ext));
+                    }
                 std::vector<Term> terms;
-                for (int x = 0; x < Wi; ++x) terms.push_back({rot(X, (long)x * (S - 1)), pts[x]});
+                for (int x = 0; x < Wi; ++x) terms.push_back({srcs[x], pts[ext][x]});
                 X = mac_rescale(terms);
                 if (X < 0) return -1;
             }
         } else if (S > 1 && Wi > 1) {
             // zeros between the values: S shifted copies summed, then one mask per group of S columns
             const int G = (Wi + S - 1) / S;
-            std::vector<size_t> pts;
-            for (int gq = 0; gq < G; ++gq) {
-                std::vector<long> pos;
-                for (int y = 0; y < Hi; ++y)
-                    for (int m = 0; m < S; ++m)
-                        if (gq * S + m < Wi) pos.push_back((long)S * Wimg * y + (long)gq * S + m);
-                pts.push_back(request(mask(pos), std::vector<double>(1, L.pending), delta, nl, 1));
-            }
+            std::vector<size_t> pts[2];
             for (int& X : ys) {
                 std::vector<int> shifted;
                 for (int m = 0; m < S; ++m) shifted.push_back(rot(X, (long)m * (S - 1)));
                 int T = sum(shifted);
                 if (T < 0) return -1;
+                std::vector<int> srcs;
+                for (int gq = 0; gq < G; ++gq) srcs.push_back(rot(T, (long)gq * S * (S - 1)));
+                const bool ext = any_ext(srcs);
+                if (pts[ext].empty())
+                    for (int gq = 0; gq < G; ++gq) {
+                        std::vector<long> pos;
+                        for (int y = 0; y < Hi; ++y)
+                            for (int m = 0; m < S; ++m)
+                                if (gq * S + m < Wi) pos.push_back((long)S * Wimg * y + (long)gq * S + m);
+                        pts[ext].push_back(request(mask(pos), std::vector<double>(1, L.pending), delta, nl, 1, ext));
+                    }
                 std::vector<Term> terms;
-                for (int gq = 0; gq < G; ++gq) terms.push_back({rot(T, (long)gq * S * (S - 1)), pts[gq]});
+                for (int gq = 0; gq < G; ++gq) terms.push_back({srcs[gq], pts[ext][gq]});
                 X = mac_rescale(terms);
                 if (X < 0) return -1;
             }
@@ -542,24 +643,34 @@ struct Planner {
             std::vector<long> pos;
             for (int y = 0; y < Hi; ++y)
                 for (int x = 0; x < Wi; ++x) pos.push_back((long)Wimg * y + x);
-            size_t pt = request(mask(pos), std::vector<double>(1, L.pending), delta, nl, 1);
+            size_t pts[2] = {0, 0};
+            bool have[2] = {false, false};
             for (int& X : ys) {
-                X = mac_rescale({{X, pt}});
+                const bool ext = is_ext(X);
+                if (!have[ext]) {
+                    pts[ext] = request(mask(pos), std::vector<double>(1, L.pending), delta, nl, 1, ext);
+                    have[ext] = true;
+                }
+                X = mac_rescale({{X, pts[ext]}});
                 if (X < 0) return -1;
             }
         }
         // (y, x) now sits at S W_img y + x; remove the column interval
         if (Hi > 1) {
             const int nl2 = net->regs[ys[0]].nl;
-            std::vector<size_t> pts;
-            for (int y = 0; y < Hi; ++y) {
-                std::vector<long> pos;
-                for (int x = 0; x < Wi; ++x) pos.push_back((long)y * Wi + x);
-                pts.push_back(request(mask(pos), std::vector<double>(1, 1.0), delta, nl2, 1));
-            }
+            std::vector<size_t> pts[2];
             for (int& X : ys) {
+                std::vector<int> srcs;
+                for (int y = 0; y < Hi; ++y) srcs.push_back(rot(X, (long)y * ((long)Wimg * S - Wi)));
+                const bool ext = any_ext(srcs);
+                if (pts[ext].empty())
+                    for (int y = 0; y < Hi; ++y) {
+                        std::vector<long> pos;
+                        for (int x = 0; x < Wi; ++x) pos.push_back((long)y * Wi + x);
+                        pts[ext].push_back(request(mask(pos), std::vector<double>(1, 1.0), delta, nl2, 1, ext));
+                    }
                 std::vector<Term> terms;
-                for (int y = 0; y < Hi; ++y) terms.push_back({rot(X, (long)y * ((long)Wimg * S - Wi)), pts[y]});
+                for (int y = 0; y < Hi; ++y) terms.push_back({srcs[y], pts[ext][y]});
                 X = mac_rescale(terms);
                 if (X < 0) return -1;
             }
@@ -588,7 +699,8 @@ struct Planner {
         const int Wvec = D * reps;
         const int X = L.ch_reg[0];
         const int nl = net->regs[X].nl;
-        std::vector<Term> terms;
+        std::vector<int> srcs;
+        std::vector<std::vector<double>> vs;
         for (int o = 0; o < D; ++o) {
             std::vector<double> mrot(Wvec);
             for (int p = 0; p < Wvec; ++p) {
@@ -598,9 +710,17 @@ struct Planner {
             std::vector<double> v1(net->n_slots, 0.0), v2(net->n_slots, 0.0);
             for (int b = 0; b < net->samples; ++b)
                 for (int p = 0; p < Wvec; ++p) (p < Wvec - o ? v1 : v2)[(size_t)b * net->stride + p] = mrot[p];
-            terms.push_back({rot(X, o), request(v1, std::vector<double>(1, 1.0), delta, nl, 1)});
-            if (o >= 1) terms.push_back({rot(X, (long)o - Wvec), request(v2, std::vector<double>(1, 1.0), delta, nl, 1)});
+            srcs.push_back(rot(X, o));
+            vs.push_back(std::move(v1));
+            if (o >= 1) {
+                srcs.push_back(rot(X, (long)o - Wvec));
+                vs.push_back(std::move(v2));
+            }
         }
+        const bool ext = any_ext(srcs);
+        std::vector<Term> terms;
+        for (size_t t = 0; t < srcs.size(); ++t)
+            terms.push_back({srcs[t], request(vs[t], std::vector<double>(1, 1.0), delta, nl, 1, ext)});
         int csum = mac_rescale(terms);
         if (csum < 0) return -1;
         std::vector<int> parts;
@@ -702,7 +822,8 @@ int count_depth(const unihenn_input& in, const unihenn_layer* ls, int n)
     return d;
 }
 
-// register allocation: buffers by limb count, reused after a value's last use
+// register allocation: buffers by limb count (extended registers hold one
+// more), reused after a value's last use
 void allocate(unihenn_net* net, std::vector<int>& phys_nl)
 {
     const int nr = (int)net->regs.size();
@@ -739,17 +860,17 @@ void allocate(unihenn_net* net, std::vector<int>& phys_nl)
         if (net->steps[s].dst >= 0) defs.push_back(net->steps[s].dst);
         for (int d : defs) {
             if (def[d] != s || net->regs[d].phys >= 0) continue;
-            auto& fl = free_by_nl[net->regs[d].nl];
+            auto& fl = free_by_nl[net->regs[d].limbs()];
             if (!fl.empty()) {
                 net->regs[d].phys = fl.back();
                 fl.pop_back();
             } else {
                 net->regs[d].phys = (int)phys_nl.size();
-                phys_nl.push_back(net->regs[d].nl);
+                phys_nl.push_back(net->regs[d].limbs());
             }
         }
         for (int r : dying[s])
-            if (net->regs[r].phys >= 0) free_by_nl[net->regs[r].nl].push_back(net->regs[r].phys);
+            if (net->regs[r].phys >= 0) free_by_nl[net->regs[r].limbs()].push_back(net->regs[r].phys);
     }
 }
 
@@ -761,8 +882,10 @@ void schedule_layers(unihenn_net* net)
     auto kind_order = [](StepKind k) {
         switch (k) {
         case ST_ROT: return 0;
+        case ST_EXT: return 0;
         case ST_MACM: return 1;
         case ST_MAC: return 2;
+        case ST_MODDOWN: return 3;
         case ST_RESCALE: return 3;
         case ST_SQUARE: return 4;
         case ST_MUL: return 4;
@@ -816,15 +939,25 @@ void schedule_layers(unihenn_net* net)
 // Workspace words for grouped key switching with groups of E rotations (at
 // the widest level and largest batch), single key switches, grouped squares
 // and grouped rescales.
+// Largest E * B of a grouped elementwise run over batches B <= max_batch when
+// the executor groups E = min(UH_EW_GROUP_MAX, max(1, per / B)) steps.
+static size_t max_group_batch(int max_batch, int per)
+{
+    size_t m = 0;
+    for (int b = 1; b <= max_batch; ++b)
+        m = std::max(m, (size_t)std::min(UH_EW_GROUP_MAX, std::max(1, per / b)) * (size_t)b);
+    return m;
+}
+
 static size_t net_ws_words(const unihenn_ctx* c, const unihenn_net* net, int E_)
 {
     const size_t L0 = (size_t)net->ws_nl, Bm = (size_t)net->max_batch, E = (size_t)E_;
     const size_t group_rows = Bm * (L0 + L0 * L0) + E * Bm * (L0 * L0 + 7 * L0 + 2);
     const int mb = net->max_batch;
-    const int e_sq = std::max(1, 32 / mb), e_rs = std::max(1, std::min(UH_EW_GROUP_MAX, 64 / mb));
     size_t ws_rows = std::max(ks_ws_rows(net->ws_nl, mb), group_rows);
-    ws_rows = std::max(ws_rows, group_square_ws_rows(std::min(e_sq, UH_EW_GROUP_MAX), net->ws_nl, mb));
-    ws_rows = std::max(ws_rows, (size_t)e_rs * Bm * 2 * L0);
+    // grouped squares and products (E * B batches at once), grouped rescales and ModDowns
+    ws_rows = std::max(ws_rows, group_square_ws_rows((int)max_group_batch(mb, 32), net->ws_nl, 1));
+    ws_rows = std::max(ws_rows, max_group_batch(mb, 64) * 2 * (L0 + 1));
     return ws_rows * (size_t)c->n;
 }
 
@@ -855,7 +988,14 @@ extern "C" int unihenn_net_destroy(unihenn_net* net)
 extern "C" int unihenn_net_create(const unihenn_ctx* c, const unihenn_input* in, const unihenn_layer* layers,
                                   uint32_t n_layers, uint32_t max_batch, unihenn_net** out)
 {
+    return unihenn_net_create_ex(c, in, layers, n_layers, max_batch, 0u, out);
+}
+
+extern "C" int unihenn_net_create_ex(const unihenn_ctx* c, const unihenn_input* in, const unihenn_layer* layers,
+                                     uint32_t n_layers, uint32_t max_batch, uint32_t plan_flags, unihenn_net** out)
+{
     if (!c || !in || !out || (n_layers && !layers)) return uh_fail(UNIHENN_EINVAL, "null argument");
+    if (plan_flags & ~(uint32_t)UNIHENN_PLAN_LAZY_MODDOWN) return uh_fail(UNIHENN_EINVAL, "unknown plan flag");
     if (in->c < 1 || in->h < 1 || in->w < 1 || in->samples < 1 || max_batch < 1)
         return uh_fail(UNIHENN_EINVAL, "empty input shape, sample count or batch");
     for (uint32_t l = 0; l < n_layers; ++l)
@@ -863,6 +1003,7 @@ extern "C" int unihenn_net_create(const unihenn_ctx* c, const unihenn_input* in,
             return uh_fail(UNIHENN_EINVAL, "unknown layer kind");
     unihenn_net* net = new unihenn_net();
     net->ctx = c;
+    net->lazy = (plan_flags & UNIHENN_PLAN_LAZY_MODDOWN) != 0;
     net->n_slots = c->n / 2;
     net->samples = (int)in->samples;
     net->max_batch = (int)max_batch;
@@ -894,6 +1035,7 @@ extern "C" int unihenn_net_create(const unihenn_ctx* c, const unihenn_input* in,
     }
 
     Planner P{net, c, c->scale, {}, "", 0};
+    P.lazy = net->lazy;
     net->input_reg = P.newreg(net->in_limbs, c->scale);
     {
         Step s;
@@ -925,6 +1067,9 @@ extern "C" int unihenn_net_create(const unihenn_ctx* c, const unihenn_input* in,
         case UNIHENN_LAYER_FLATTEN: rc = P.flatten(L); break;
         case UNIHENN_LAYER_FC: rc = P.fc(L, layers[l]); break;
         }
+        // the network's outputs in normal form
+        if (rc >= 0 && l + 1 == n_layers)
+            for (int& r : L.ch_reg) r = P.norm(r);
         if (rc < 0 || P.err_code) {
             int code = P.err_code ? P.err_code : UNIHENN_EINVAL;
             std::string m = P.err;
@@ -980,7 +1125,7 @@ extern "C" int unihenn_net_create(const unihenn_ctx* c, const unihenn_input* in,
     }
     for (const PtRequest& r : net->requests) {
         int rc = encode_scaled_batch(c, r.z.data(), (int)r.z.size(), r.w.data(), (int)r.w.size(), r.scale, r.nl,
-                                     r.mont, net->pt_arena + r.offset, nullptr);
+                                     r.mont, net->pt_arena + r.offset, nullptr, r.ext);
         if (rc) {
             unihenn_net_destroy(net);
             return rc;
@@ -1113,9 +1258,10 @@ struct Exec {
         int cap = std::max(1, std::min(max_e, max_e2));
         static const char* nog = getenv("UNIHENN_NO_GROUP");  // kinds (step enum digits) never grouped
         if (nog && strchr(nog, '0' + (int)net->steps[si].kind)) cap = 1;
+        const bool ext = net->regs[net->steps[si].dst].ext;
         for (size_t sj = si; sj < end && (int)run.size() < cap; ++sj) {
             const Step& x = net->steps[sj];
-            if (!ok(x) || net->regs[x.dst].nl != nl) break;
+            if (!ok(x) || net->regs[x.dst].nl != nl || net->regs[x.dst].ext != ext) break;
             bool dep = false;
             auto reads = [&](int r) { return r >= 0 && std::find(made.begin(), made.end(), r) != made.end(); };
             dep |= reads(x.a) || reads(x.b);
@@ -1127,7 +1273,8 @@ struct Exec {
         return run;
     }
 
-    void rotations(const std::vector<size_t>& run, int nl)
+    // ext: the rotations stay extended (inner product only, no ModDown)
+    void rotations(const std::vector<size_t>& run, int nl, bool ext)
     {
         const size_t rn = (size_t)c->n;
         GroupWs w = carve();
@@ -1152,7 +1299,8 @@ struct Exec {
                         ga.blk[e] = 0;
                         ga.gin[e] = ga.gdig[e] = ga.g[e];
                     }
-                    group_switch(c, ga, B, nl, true, w.pmodup, w.aux, w.U, w.Up, w.R, s);
+                    if (ext) group_switch_ext(c, ga, B, nl, w.pmodup, s);
+                    else group_switch(c, ga, B, nl, true, w.pmodup, w.aux, w.U, w.Up, w.R, s);
                 }
                 i = j;
             }
@@ -1176,7 +1324,8 @@ struct Exec {
                     perm[e] = ga.g[e];
                 }
                 group_modup(c, ga.E, d.data(), 2 * nl, B, nl, w.dcoef, w.modup, s, perm.data());
-                group_switch(c, ga, B, nl, true, w.modup, w.aux, w.U, w.Up, w.R, s);
+                if (ext) group_switch_ext(c, ga, B, nl, w.modup, s);
+                else group_switch(c, ga, B, nl, true, w.modup, w.aux, w.U, w.Up, w.R, s);
             }
             modup_owner = -1;
         } else {
@@ -1193,7 +1342,8 @@ struct Exec {
                 }
                 group_auto_both(c, ga, B, nl, w.aux, s);
                 group_modup(c, ga.E, d.data(), 2 * nl, B, nl, w.dcoef, w.modup, s);
-                group_switch(c, ga, B, nl, false, w.modup, w.aux, w.U, w.Up, w.R, s);
+                if (ext) group_switch_ext(c, ga, B, nl, w.modup, s);
+                else group_switch(c, ga, B, nl, false, w.modup, w.aux, w.U, w.Up, w.R, s);
             }
             modup_owner = -1;
         }
@@ -1204,6 +1354,10 @@ struct Exec {
         for (size_t si = begin; si < end; ++si) {
             const Step& st = net->steps[si];
             const int nl = net->regs[st.dst].nl;
+            // rows per polynomial of the destination, and its P limb (extended) or -1
+            const bool ext = net->regs[st.dst].ext;
+            const int lim = net->regs[st.dst].limbs();
+            const int pl = ext ? nl : -1;
             switch (st.kind) {
             case ST_DROP:
                 launch_gather_rows(c, reg(st.dst), ext_in, B * 2 * nl, nl, ext_in_limbs, 0, s);
@@ -1212,13 +1366,14 @@ struct Exec {
                 // a run of consecutive rotations at this level, none reading another's result
                 std::vector<size_t> run;
                 size_t sj = si;
-                while (sj < end && net->steps[sj].kind == ST_ROT && net->regs[net->steps[sj].dst].nl == nl) {
+                while (sj < end && net->steps[sj].kind == ST_ROT && net->regs[net->steps[sj].dst].nl == nl &&
+                       net->regs[net->steps[sj].dst].ext == ext) {
                     bool dep = false;
                     for (size_t x : run) dep |= net->steps[x].dst == net->steps[sj].a;
                     if (dep) break;
                     run.push_back(sj++);
                 }
-                rotations(run, nl);
+                rotations(run, nl, ext);
                 si = sj - 1;
                 break;
             }
@@ -1241,7 +1396,7 @@ struct Exec {
                             m.pt[e * m.T + t] = net->pt_arena + x.terms[t].pt;
                         }
                     }
-                    launch_mac_group(c, m, nl, B, s);
+                    launch_mac_group(c, m, lim, B, s, pl);
                     si = run.back();
                     break;
                 }
@@ -1253,7 +1408,7 @@ struct Exec {
                         mt.ct[t] = reg(st.terms[t0 + t].src);
                         mt.pt[t] = net->pt_arena + st.terms[t0 + t].pt;
                     }
-                    launch_mac(c, reg(st.dst), mt, k, nl, B, (st.acc || t0 > 0) ? 1 : 0, s);
+                    launch_mac(c, reg(st.dst), mt, k, lim, B, (st.acc || t0 > 0) ? 1 : 0, s, pl);
                 }
                 break;
             }
@@ -1267,10 +1422,10 @@ struct Exec {
                         memset(&m, 0, sizeof(m));
                         for (int o = 0; o < no; ++o) m.acc[o] = reg(st.outs[o0 + o]);
                         for (int t = 0; t < nt; ++t) m.ct[t] = reg(st.srcs[t0 + t]);
-                        m.pt_base = net->pt_arena + st.pt + (size_t)o0 * st.pt_ostride * nl * c->n;
+                        m.pt_base = net->pt_arena + st.pt + (size_t)o0 * st.pt_ostride * lim * c->n;
                         m.o_stride = st.pt_ostride;
                         m.t_off = st.pt_toff + t0;
-                        launch_mac_multi(c, m, no, nt, nl, B, (st.acc || t0 > 0) ? 1 : 0, s);
+                        launch_mac_multi(c, m, no, nt, lim, B, (st.acc || t0 > 0) ? 1 : 0, s, pl);
                     }
                 }
                 break;
@@ -1304,7 +1459,35 @@ struct Exec {
                     g.a[e] = reg(x.a);
                     g.b[e] = kind == ST_ADD ? reg(x.b) : net->pt_arena + x.pt;
                 }
-                launch_group_add(c, g, B, nl, kind == ST_ADD_PLAIN, s);
+                launch_group_add(c, g, B, lim, kind == ST_ADD_PLAIN, s, pl);
+                si = run.back();
+                break;
+            }
+            case ST_EXT: {
+                std::vector<size_t> run = collect(si, end, nl, [&](const Step& x) { return x.kind == ST_EXT; },
+                                                  UH_EW_GROUP_MAX, UH_EW_GROUP_MAX);
+                EwGroup g;
+                memset(&g, 0, sizeof(g));
+                g.E = (int)run.size();
+                for (int e = 0; e < g.E; ++e) {
+                    g.a[e] = reg(net->steps[run[e]].a);
+                    g.out[e] = reg(net->steps[run[e]].dst);
+                }
+                launch_group_to_ext(c, g, B, nl, s);
+                si = run.back();
+                break;
+            }
+            case ST_MODDOWN: {
+                std::vector<size_t> run = collect(si, end, nl, [&](const Step& x) { return x.kind == ST_MODDOWN; },
+                                                  UH_EW_GROUP_MAX, std::max(1, 64 / B));
+                std::vector<const u64*> ins;
+                std::vector<u64*> outs;
+                for (size_t x : run) {
+                    ins.push_back(reg(net->steps[x].a));
+                    outs.push_back(reg(net->steps[x].dst));
+                }
+                group_moddown(c, (int)run.size(), ins.data(), outs.data(), B, nl, net->ws, s);
+                modup_owner = -1;
                 si = run.back();
                 break;
             }
@@ -1460,6 +1643,7 @@ extern "C" int unihenn_conv(const unihenn_ctx* c, unihenn_net* net, uint32_t lay
     if (B < 1 || B > net->max_batch) return uh_fail(UNIHENN_EINVAL, "batch exceeds max_batch");
     for (uint32_t i = 0; i < n_in; ++i) {
         const VReg& r = net->regs[uniq[i]];
+        if (r.ext) return uh_fail(UNIHENN_EINVAL, "the layer's input is an extended sum in this plan");
         if (!in[i].data || (int)in[i].n_limbs != r.nl || (int)in[i].batch != B)
             return uh_fail(UNIHENN_ELEVEL, "input " + std::to_string(i) + " not at the layer's level");
         if (in[i].scale != r.scale) return uh_fail(UNIHENN_ESCALE, "input scale differs from the plan");
@@ -1540,6 +1724,7 @@ uint64_t net_fingerprint(const unihenn_net* net)
     for (const Step& st : net->steps) {
         mix((uint64_t)st.kind);
         mix((uint64_t)net->regs[st.dst].nl);
+        mix((uint64_t)net->regs[st.dst].ext);
         mix(st.terms.size());
         mix(st.outs.size());
         mix(st.srcs.size());

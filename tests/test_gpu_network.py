@@ -14,9 +14,9 @@ from oracle.run import OracleSession, build_net, reference_outputs, run_encrypte
 pytestmark = pytest.mark.gpu
 
 
-def _gpu_net(P, ctx, cfg, sess, net_oracle, batch=1):
+def _gpu_net(P, ctx, cfg, sess, net_oracle, batch=1, lazy=False):
     net = P.Net(ctx, cfg["input"], cfg["layers"], net_oracle.params, samples=cfg["samples_per_ct"],
-                stride=cfg["sample_stride"], max_batch=batch)
+                stride=cfg["sample_stride"], max_batch=batch, lazy=lazy)
     assert net.depth == net_oracle.depth
     assert sorted(net.rotations()) == net_oracle.rotation_set()
     keys = {r: ctx.import_evk(sess.key_coeff[r]) for r in net.rotations()}
@@ -29,7 +29,9 @@ def _ctx(P, cfg):
     return P.Context(cfg["log_n"], cfg["prime_bits"], cfg["special_bits"], 2.0 ** cfg["log_scale"])
 
 
-def _run_parity(cfg, n_cts=1, seeds=(W.SEED_ENCRYPT,)):
+def _run_parity(cfg, n_cts=1, seeds=(W.SEED_ENCRYPT,), lazy=False, modes=None):
+    """GPU outputs equal to the oracle's, residue by residue, in every mode
+    (default: plain and hoisted); lazy: both sides plan deferred ModDown."""
     import paper_2402_03060_amd as P
     sess = OracleSession(cfg)
     onet = build_net(cfg, sess.ck.slots)
@@ -37,15 +39,15 @@ def _run_parity(cfg, n_cts=1, seeds=(W.SEED_ENCRYPT,)):
     expected, cts = [], []
     for b in range(n_cts):
         xs = xs_all[b * cfg["samples_per_ct"]:(b + 1) * cfg["samples_per_ct"]]
-        ct, outs, _ = run_encrypted(sess, onet, xs, enc_seed=seeds[b % len(seeds)] + b)
+        ct, outs, _ = run_encrypted(sess, onet, xs, enc_seed=seeds[b % len(seeds)] + b, lazy=lazy)
         expected.append([o.data for o in outs])
         cts.append(ct)
     ctx = _ctx(P, cfg)
     assert ctx.primes == sess.ck.primes
-    gnet = _gpu_net(P, ctx, cfg, sess, onet, batch=n_cts)
+    gnet = _gpu_net(P, ctx, cfg, sess, onet, batch=n_cts, lazy=lazy)
     gin = ctx.import_ct(np.stack([c.data for c in cts]), cts[0].scale)
     results = {}
-    for mode in (P.EVAL_PLAIN, P.EVAL_HOISTED):
+    for mode in (modes or (P.EVAL_PLAIN, P.EVAL_HOISTED)):
         gnet.set_mode(mode)
         outs = gnet.eval(gin)
         got = [ctx.export_ct(o) for o in outs]
