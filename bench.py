@@ -42,7 +42,8 @@ def _pack(net_input: dict, xs: np.ndarray, n_slots: int, stride: int) -> np.ndar
 TUNING_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2402_03060_amd", "tuning_cache.json")
 
 
-def setup(P, W, name: str, batch: int, seed: int = 5, tune: bool = True, mode: int = 0, log_n: int | None = None):
+def setup(P, W, name: str, batch: int, seed: int = 5, tune: bool = True, mode: int = 0, log_n: int | None = None,
+          lazy: bool = False):
     import torch
     cfg = W.config(name)
     if log_n is not None:
@@ -50,7 +51,7 @@ def setup(P, W, name: str, batch: int, seed: int = 5, tune: bool = True, mode: i
     ctx = P.Context(cfg["log_n"], cfg["prime_bits"], cfg["special_bits"], 2.0 ** cfg["log_scale"])
     params = W.gen_params(cfg["layers"])
     S, stride = cfg["samples_per_ct"], cfg["sample_stride"]
-    net = P.Net(ctx, cfg["input"], cfg["layers"], params, samples=S, stride=stride, max_batch=batch)
+    net = P.Net(ctx, cfg["input"], cfg["layers"], params, samples=S, stride=stride, max_batch=batch, lazy=lazy)
     sk = P.keygen_secret(ctx, seed)
     keys = {r: P.gen_switch_key(ctx, sk, seed + 1, steps=r) for r in net.rotations()}
     rlk = P.gen_switch_key(ctx, sk, seed + 2, relin=True)
@@ -276,6 +277,30 @@ def rotation_microbench(P, batch: int = 128, hoisted: int = 24) -> dict:
     return out
 
 
+def batched_leg(P, W, name: str, B: int, per_ct: int, steps: int, tune: bool, lazy: bool, unit: str) -> dict:
+    """One batched configuration (B ciphertexts of per_ct samples, hoisted,
+    graph replay, tuned) in the default or the deferred-ModDown plan:
+    samples/s, per-family kernel table and the dominant family's roofline."""
+    import torch
+    plan = "deferred ModDown" if lazy else "default"
+    print(f"[bench] setup batched {name} ({B} ciphertexts x {per_ct}, {plan} plan)", file=sys.stderr, flush=True)
+    sb = setup(P, W, name, batch=B, tune=tune, mode=P.EVAL_HOISTED | P.EVAL_GRAPH, lazy=lazy)
+    nb, ctb, outb = sb["net"], sb["ct"], sb["outs"]
+    stepb = lambda: nb.eval(ctb, outb)
+    dtb = timed(stepb, steps, 1)
+    rate = steps * B * per_ct / dtb
+    errb = max_error(P, W, sb)
+    out = {unit: round(rate, 2), "ms_per_launch": round(1e3 * dtb / steps, 2), "per_launch": B * per_ct,
+           "plan": plan, "max_abs_err_vs_fp64": errb, "tuning": sb["tuning"]}
+    sbs = family_stats(P, stepb, 1)
+    out["kernel_families"] = family_table(sbs, 1)
+    out["roofline"] = roofline_entry(sbs)
+    print(f"[bench] batched {name} ({plan}): {rate:.1f} {unit}, max |err| {errb:.2e}", file=sys.stderr, flush=True)
+    del sb, nb, ctb, outb, stepb
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(W) -> dict:
     """The oracle (scalar C, one thread) on one whole encrypted LeNet-1
     inference at the same parameters; keys are made before the timer."""
@@ -338,6 +363,7 @@ def main():
     ap.add_argument("--no-rotation-sweep", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="default launch parameters instead of the tuned ones")
     ap.add_argument("--no-models", action="store_true", help="skip the paper's other model shapes")
+    ap.add_argument("--no-lazy", action="store_true", help="skip the deferred-ModDown plan measurements")
     ap.add_argument("--serve-requests", type=int, default=300,
                     help="requests per load level of the serving measurement (0 skips it)")
     ap.add_argument("--ntt-probe", type=int, default=0, metavar="ROWS",
@@ -426,6 +452,26 @@ def main():
     res["plain_hoisted_inferences_per_s"] = round(args.steps / dth, 3)
     net.set_mode(P.EVAL_PLAIN | P.EVAL_GRAPH)
 
+    if not args.no_lazy:
+        # the same single-image workload in the deferred-ModDown plan
+        print("[bench] setup plain LeNet-1, deferred-ModDown plan", file=sys.stderr, flush=True)
+        sl = setup(P, W, "lenet1", batch=1, tune=not args.no_tune, mode=P.EVAL_PLAIN | P.EVAL_GRAPH, lazy=True)
+        nlz, ctl, outl = sl["net"], sl["ct"], sl["outs"]
+        stepl = lambda: nlz.eval(ctl, outl)
+        dtl = timed(stepl, args.steps, args.warmup)
+        nlz.set_mode(P.EVAL_HOISTED | P.EVAL_GRAPH)
+        dtlh = timed(stepl, args.steps, 1)
+        nlz.set_mode(P.EVAL_PLAIN | P.EVAL_GRAPH)
+        lazy_families = family_table(family_stats(P, stepl, args.steps), args.steps)
+        res["plain_lazy"] = {"inferences_per_s": round(args.steps / dtl, 3),
+                             "ms_per_step": round(1e3 * dtl / args.steps, 3),
+                             "hoisted_inferences_per_s": round(args.steps / dtlh, 3),
+                             "multiple_of_default_plan": round(dt / dtl, 3),
+                             "max_abs_err_vs_fp64": max_error(P, W, sl), "tuning": sl["tuning"],
+                             "kernel_families": lazy_families}
+        print(f"[bench] plain, deferred ModDown: {args.steps / dtl:.2f} inf/s", file=sys.stderr, flush=True)
+        del sl, nlz, ctl, outl, stepl
+
     # rotations/s at the same size (one ciphertext, 8 limbs)
     ctx = st["ctx"]
     ws = ctx.workspace(8, 1)
@@ -442,43 +488,16 @@ def main():
 
     if not args.no_batched:
         B = args.batched_cts
-        print(f"[bench] setup batched LeNet-1 ({B} ciphertexts x 10 images)", file=sys.stderr, flush=True)
         del st, step
         torch.cuda.empty_cache()
-        sb = setup(P, W, "lenet1_batched", batch=B, tune=not args.no_tune, mode=P.EVAL_HOISTED | P.EVAL_GRAPH)
-        nb, ctb, outb = sb["net"], sb["ct"], sb["outs"]
-        nb.set_mode(P.EVAL_HOISTED | P.EVAL_GRAPH)
-        stepb = lambda: nb.eval(ctb, outb)
-        dtb = timed(stepb, args.batched_steps, 1)
-        imgs = args.batched_steps * B * 10 / dtb
-        errb = max_error(P, W, sb)
-        res["batched"] = {"images_per_s": round(imgs, 2), "ms_per_launch": round(1e3 * dtb / args.batched_steps, 2),
-                          "images_per_launch": B * 10, "multiple_of_plain": round(imgs / value, 2),
-                          "max_abs_err_vs_fp64": errb, "tuning": sb["tuning"]}
-        sbs = family_stats(P, stepb, 1)
-        res["batched"]["kernel_families"] = family_table(sbs, 1)
-        res["batched"]["roofline"] = roofline_entry(sbs)
-        print(f"[bench] batched: {imgs:.1f} img/s ({imgs / value:.1f}x plain), max |err| {errb:.2e}",
-              file=sys.stderr, flush=True)
-
-    if not args.no_batched:
-        del sb, stepb
-        torch.cuda.empty_cache()
-        print("[bench] setup batched 1D CNN (64 ciphertexts x 8 sequences)", file=sys.stderr, flush=True)
-        sc = setup(P, W, "cnn1d", batch=64, tune=not args.no_tune, mode=P.EVAL_HOISTED | P.EVAL_GRAPH)
-        nc, ctc, outc = sc["net"], sc["ct"], sc["outs"]
-        nc.set_mode(P.EVAL_HOISTED | P.EVAL_GRAPH)
-        stepc = lambda: nc.eval(ctc, outc)
-        dtc = timed(stepc, args.batched_steps, 1)
-        seqs = args.batched_steps * 64 * 8 / dtc
-        errc = max_error(P, W, sc)
-        res["batched_cnn1d"] = {"sequences_per_s": round(seqs, 2),
-                                "ms_per_launch": round(1e3 * dtc / args.batched_steps, 2),
-                                "sequences_per_launch": 64 * 8, "max_abs_err_vs_fp64": errc,
-                                "tuning": sc["tuning"]}
-        print(f"[bench] batched cnn1d: {seqs:.1f} seq/s, max |err| {errc:.2e}", file=sys.stderr, flush=True)
-        del sc, stepc
-        torch.cuda.empty_cache()
+        plans = [False] + ([] if args.no_lazy else [True])
+        for lazy in plans:
+            r = batched_leg(P, W, "lenet1_batched", B, 10, args.batched_steps, not args.no_tune, lazy, "images_per_s")
+            r["multiple_of_plain"] = round(r["images_per_s"] / value, 2)
+            res["batched_lazy" if lazy else "batched"] = r
+        for lazy in plans:
+            r = batched_leg(P, W, "cnn1d", 64, 8, args.batched_steps, not args.no_tune, lazy, "sequences_per_s")
+            res["batched_cnn1d_lazy" if lazy else "batched_cnn1d"] = r
 
     if not args.no_models:
         res["models"] = models_bench(P, W)

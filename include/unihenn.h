@@ -293,6 +293,9 @@ int unihenn_net_output_slots(const unihenn_net* net, uint64_t* positions, uint32
  *   ks_min_wg     workgroups a key-switch inner product aims for (it splits
  *                 the batch to reach it)
  *   ks_group      rotations per grouped key-switch launch set (net only)
+ *   ks_order      workgroup order of the grouped inner product: 0 batch
+ *                 chunks fastest (keys re-read from cache), 1 rotations
+ *                 fastest (digits re-read from cache)
  *   ntt_ms, net_ms  timings of the chosen setting (filled by autotune) */
 typedef struct {
     int32_t ntt_split;
@@ -300,14 +303,15 @@ typedef struct {
     int32_t mac_min_wg;
     int32_t ks_min_wg;
     int32_t ks_group;
+    int32_t ks_order;
     double ntt_ms;
     double net_ms;
 } unihenn_tuning;
 /* Time candidate settings on the device and keep the fastest: first the NTT
  * split and tile on a forward + inverse transform of a batch of rows sized
  * from `batch`; then, when net is non-NULL and its keys are bound, one
- * coordinate at a time (NTT split and tile, group size, the two workgroup
- * targets) on whole evaluations of `batch` ciphertexts in the net's mode
+ * coordinate at a time (NTT split and tile, group size with each workgroup
+ * order, the two workgroup targets) on whole evaluations of `batch` ciphertexts in the net's mode
  * (graph replay included when set).  With a non-NULL cache_path the result
  * is looked up in, and then written to, a JSON file keyed by device, ring,
  * batch, a fingerprint of the net's plan and its mode (set the mode first);

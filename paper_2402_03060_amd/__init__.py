@@ -45,7 +45,8 @@ class LAYER(C.Structure):
 
 class TUNING(C.Structure):
     _fields_ = [("ntt_split", C.c_int32), ("ntt_tile_log", C.c_int32), ("mac_min_wg", C.c_int32),
-                ("ks_min_wg", C.c_int32), ("ks_group", C.c_int32), ("ntt_ms", C.c_double), ("net_ms", C.c_double)]
+                ("ks_min_wg", C.c_int32), ("ks_group", C.c_int32), ("ks_order", C.c_int32), ("ntt_ms", C.c_double),
+                ("net_ms", C.c_double)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}

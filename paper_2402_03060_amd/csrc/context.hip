@@ -3,6 +3,7 @@
 // per-kernel-family launch timers.
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>

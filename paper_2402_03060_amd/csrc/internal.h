@@ -54,6 +54,7 @@ struct unihenn_ctx {
     int ntt_tile_log = 11;            // LDS tile of the radix-8 passes: 2^11 or 2^12 words
     int mac_min_wg = 2048;            // workgroups a multi-output MAC launch aims for
     int ks_min_wg = 2048;             // workgroups a key-switch inner product aims for
+    int ks_order = 0;                 // workgroup order of the grouped inner product (0 or 1)
 };
 
 // error reporting (thread-local message)

@@ -2,7 +2,7 @@
 #pragma once
 #include "internal.h"
 
-#define UH_MAC_MAX_TERMS 32
+#define UH_MAC_MAX_TERMS 128
 
 // up to UH_MAC_MAX_TERMS (ciphertext batch, plaintext) pairs, passed by value
 struct MacTerms {

@@ -459,17 +459,33 @@ __global__ void k_group_gather(u64* __restrict__ dcoef, GroupArgs ga, int nl, in
 // [E][B][2] for the ModDown that follows.  EXT = true: the extended rotation
 // (P tau(c0) + U_0, U_1) straight into dst_e [B][2][nl+1] (limb nl = P),
 // with tau(c0) read from src_e through the automorphism.
+//
+// Logical workgroup order (each XCD runs a contiguous range): order 0 varies
+// the batch chunk fastest, then the coefficient chunk, the limb and the
+// element (keys re-read from L2 across batch chunks); order 1 varies the
+// element fastest, then the coefficient chunk, the batch chunk and the limb,
+// so that the elements of a group gather the same digit rows back to back
+// (digits re-read from L2 across rotations).
 template <int MAXL, bool EXT>
 __global__ void __launch_bounds__(EW_THREADS) k_group_inner(u64* __restrict__ U, u64* __restrict__ Up,
                                                             const u64* __restrict__ modup, GroupArgs ga, DevCtx ctx,
-                                                            int nl, int nd, int batch, int BB, int Zb, int C, int W)
+                                                            int nl, int nd, int batch, int BB, int Zb, int C, int W,
+                                                            int order)
 {
     const int L = xcd_logical(W);
     if (L < 0) return;
-    const int zb = L % Zb;
-    const int x = (L / Zb) % C;
-    const int t = (L / (Zb * C)) % (nl + 1);  // 0..nl
-    const int e = L / (Zb * C * (nl + 1));
+    int zb, x, t, e;
+    if (order == 0) {
+        zb = L % Zb;
+        x = (L / Zb) % C;
+        t = (L / (Zb * C)) % (nl + 1);  // 0..nl
+        e = L / (Zb * C * (nl + 1));
+    } else {
+        e = L % ga.E;
+        x = (L / ga.E) % C;
+        zb = (L / (ga.E * C)) % Zb;
+        t = L / (ga.E * C * Zb);
+    }
     const int n = ctx.n;
     const int k = x * EW_THREADS + threadIdx.x;
     if (k >= n) return;
@@ -612,7 +628,9 @@ void launch_group_inner(const unihenn_ctx* c, const GroupArgs& ga, int B, int nl
     inner_split((long)gx, nl + 1, E, B, c->ks_min_wg, &bb, &zb);
     const int W = zb * (int)gx * (nl + 1) * E;
     const unsigned gw = xcd_grid(W);
-#define GI(M) k_group_inner<M, EXT><<<gw, EW_THREADS, 0, s>>>(U, Up, modup, ga, c->dev, nl, c->n_data, B, bb, zb, (int)gx, W)
+#define GI(M)                                                                                                  \
+    k_group_inner<M, EXT><<<gw, EW_THREADS, 0, s>>>(U, Up, modup, ga, c->dev, nl, c->n_data, B, bb, zb, (int)gx, W, \
+                                                    c->ks_order)
     if (nl <= 4) GI(4);
     else if (nl <= 8) GI(8);
     else if (nl <= 12) GI(12);

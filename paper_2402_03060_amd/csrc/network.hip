@@ -88,6 +88,10 @@ struct KernelGeom {
     int kh, kw, sh, sw;
 };
 
+// Largest total size of the rotated batches of one convolution kept live at
+// once so that every output is one sum over all its terms.
+constexpr size_t kOneSumBytes = (size_t)24 << 30;
+
 KernelGeom geom(const unihenn_layer& L)
 {
     if (L.dims == 1) return {1, (int)L.k, 1, (int)L.s};
@@ -502,7 +506,13 @@ struct Planner {
                     }
             emit_macs(0, ci, rr, false);
         } else {
-            // one input channel at a time: its K^2 rotations, then every output accumulates
+            // every channel's K^2 rotations, then one sum per output over all
+            // CH_in K^2 terms (each output written once); when the rotated
+            // batches would not fit kOneSumBytes, one channel at a time, every
+            // output accumulating that channel's K^2 products
+            const size_t reg_bytes = (size_t)net->max_batch * 2 * (size_t)(nl + ext) * c->n * sizeof(u64);
+            const bool one_sum = (size_t)ci * kk * reg_bytes <= kOneSumBytes;
+            std::vector<int> all;
             for (int i = 0; i < ci; ++i) {
                 std::map<long, int> seen;
                 std::vector<int> rr;
@@ -515,8 +525,10 @@ struct Planner {
                         seen[r] = reg;
                         rr.push_back(reg);
                     }
-                emit_macs(i, i + 1, rr, i > 0);
+                if (one_sum) all.insert(all.end(), rr.begin(), rr.end());
+                else emit_macs(i, i + 1, rr, i > 0);
             }
+            if (one_sum) emit_macs(0, ci, all, false);
         }
         Layout out;
         out.C = co;
@@ -882,16 +894,16 @@ void schedule_layers(unihenn_net* net)
     auto kind_order = [](StepKind k) {
         switch (k) {
         case ST_ROT: return 0;
-        case ST_EXT: return 0;
-        case ST_MACM: return 1;
-        case ST_MAC: return 2;
-        case ST_MODDOWN: return 3;
-        case ST_RESCALE: return 3;
-        case ST_SQUARE: return 4;
-        case ST_MUL: return 4;
-        case ST_ADD_PLAIN: return 5;
-        case ST_ADD: return 6;
-        default: return 7;
+        case ST_EXT: return 1;       // after the rotations: their runs stay unbroken
+        case ST_MACM: return 2;
+        case ST_MAC: return 3;
+        case ST_MODDOWN: return 4;
+        case ST_RESCALE: return 4;
+        case ST_SQUARE: return 5;
+        case ST_MUL: return 5;
+        case ST_ADD_PLAIN: return 6;
+        case ST_ADD: return 7;
+        default: return 8;
         }
     };
     for (LayerRecord& L : net->layers) {

@@ -101,7 +101,7 @@ int time_net(unihenn_ctx* c, unihenn_net* net, int batch, u64* in, u64* outs, hi
 
 // ---- cache file: one JSON object, one entry per line
 const char* kFmt = "{\"ntt_split\": %d, \"ntt_tile_log\": %d, \"mac_min_wg\": %d, \"ks_min_wg\": %d, "
-                   "\"ks_group\": %d, \"ntt_ms\": %lf, \"net_ms\": %lf}";
+                   "\"ks_group\": %d, \"ks_order\": %d, \"ntt_ms\": %lf, \"net_ms\": %lf}";
 
 std::map<std::string, unihenn_tuning> read_cache(const char* path)
 {
@@ -116,7 +116,7 @@ std::map<std::string, unihenn_tuning> read_cache(const char* path)
         if (b == std::string::npos || brace == std::string::npos) continue;
         unihenn_tuning t{};
         if (sscanf(line.c_str() + brace, kFmt, &t.ntt_split, &t.ntt_tile_log, &t.mac_min_wg, &t.ks_min_wg,
-                   &t.ks_group, &t.ntt_ms, &t.net_ms) == 7)
+                   &t.ks_group, &t.ks_order, &t.ntt_ms, &t.net_ms) == 8)
             out[line.substr(a + 1, b - a - 1)] = t;
     }
     return out;
@@ -132,7 +132,8 @@ int write_cache(const char* path, const std::map<std::string, unihenn_tuning>& m
     for (const auto& kv : m) {
         const unihenn_tuning& t = kv.second;
         fprintf(f, "\"%s\": ", kv.first.c_str());
-        fprintf(f, kFmt, t.ntt_split, t.ntt_tile_log, t.mac_min_wg, t.ks_min_wg, t.ks_group, t.ntt_ms, t.net_ms);
+        fprintf(f, kFmt, t.ntt_split, t.ntt_tile_log, t.mac_min_wg, t.ks_min_wg, t.ks_group, t.ks_order, t.ntt_ms,
+                t.net_ms);
         fprintf(f, "%s\n", ++i < m.size() ? "," : "");
     }
     fprintf(f, "}\n");
@@ -167,6 +168,7 @@ void current(const unihenn_ctx* c, const unihenn_net* net, unihenn_tuning* t)
     t->mac_min_wg = c->mac_min_wg;
     t->ks_min_wg = c->ks_min_wg;
     t->ks_group = net ? net_ks_group(net) : 0;
+    t->ks_order = c->ks_order;
 }
 
 int apply(unihenn_ctx* c, unihenn_net* net, const unihenn_tuning* t)
@@ -174,6 +176,7 @@ int apply(unihenn_ctx* c, unihenn_net* net, const unihenn_tuning* t)
     if (t->ntt_split > 0 && t->ntt_split >= c->log_n) return uh_fail(UNIHENN_EINVAL, "NTT split out of range");
     if (t->ntt_tile_log > 0 && t->ntt_tile_log != 11 && t->ntt_tile_log != 12)
         return uh_fail(UNIHENN_EINVAL, "NTT tile must be 2^11 or 2^12 words");
+    if (t->ks_order != 0 && t->ks_order != 1) return uh_fail(UNIHENN_EINVAL, "workgroup order must be 0 or 1");
     if (net && t->ks_group > 0) {
         int rc = net_set_ks_group(c, net, t->ks_group);
         if (rc) return rc;
@@ -183,6 +186,7 @@ int apply(unihenn_ctx* c, unihenn_net* net, const unihenn_tuning* t)
     if (t->ntt_tile_log > 0) c->ntt_tile_log = t->ntt_tile_log;
     if (t->mac_min_wg > 0) c->mac_min_wg = t->mac_min_wg;
     if (t->ks_min_wg > 0) c->ks_min_wg = t->ks_min_wg;
+    c->ks_order = t->ks_order;
     return UNIHENN_OK;
 }
 
@@ -292,21 +296,27 @@ extern "C" int unihenn_autotune(unihenn_ctx* c, unihenn_net* net, uint32_t batch
                 c->ntt_split = best.ntt_split;
                 c->ntt_tile_log = best.ntt_tile_log;
             }
-            // group size
+            // group size, under each workgroup order of the inner product
             const int cap = net_ks_group_cap(c, net);
-            int g_best = net_ks_group(net);
-            for (int e = 1; e <= cap && !rc; e *= 2) {
-                if (e == g_best) continue;
-                rc = net_set_ks_group(c, net, e);
-                double ms = 0;
-                if (!rc) rc = time_net(c, net, batch, in.p, outs.p, s, &ms);
-                if (!rc && ms < cur) {
-                    cur = ms;
-                    g_best = e;
+            int g_best = net_ks_group(net), o_best = c->ks_order;
+            for (int order = 0; order < 2 && !rc; ++order) {
+                c->ks_order = order;
+                for (int e = 1; e <= cap && !rc; e *= 2) {
+                    if (e == g_best && order == o_best) continue;
+                    rc = net_set_ks_group(c, net, e);
+                    double ms = 0;
+                    if (!rc) rc = time_net(c, net, batch, in.p, outs.p, s, &ms);
+                    if (!rc && ms < cur) {
+                        cur = ms;
+                        g_best = e;
+                        o_best = order;
+                    }
                 }
             }
+            c->ks_order = o_best;
             if (!rc) rc = net_set_ks_group(c, net, g_best);
             best.ks_group = g_best;
+            best.ks_order = o_best;
             // workgroup targets
             for (int which = 0; which < 2 && !rc; ++which) {
                 int* field = which == 0 ? &c->mac_min_wg : &c->ks_min_wg;

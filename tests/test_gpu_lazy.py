@@ -106,3 +106,28 @@ def test_lazy_plan_differs_and_rejects_extended_conv_input():
            for i in range(4)]
     with pytest.raises(P.UnihennError):
         gnet.conv(3, ins, 12, nl - 1)
+
+
+def test_lazy_workgroup_orders_and_groups_identical():
+    """Both workgroup orders of the extended inner product, at several group
+    sizes, give the oracle's residues (LeNet-1 at N = 2^11, hoisted and plain)."""
+    import paper_2402_03060_amd as P
+    from oracle.run import build_net
+    from tests.test_gpu_network import _gpu_net
+    cfg = W.config("lenet1")
+    cfg["log_n"] = 11
+    sess = OracleSession(cfg)
+    onet = build_net(cfg, sess.ck.slots)
+    xs = W.gen_inputs(cfg["input"], 1)
+    ct, outs, _ = run_encrypted(sess, onet, xs, lazy=True)
+    ctx = _ctx(P, cfg)
+    gnet = _gpu_net(P, ctx, cfg, sess, onet, lazy=True)
+    gin = ctx.import_ct(ct.data[None], ct.scale)
+    for setting in ({"ks_group": 8, "ks_order": 1}, {"ks_group": 32, "ks_order": 1, "ks_min_wg": 512},
+                    {"ks_group": 3, "ks_order": 0}):
+        gnet.set_tuning(**setting)
+        for mode in (P.EVAL_PLAIN, P.EVAL_HOISTED):
+            gnet.set_mode(mode)
+            got = [ctx.export_ct(o)[0] for o in gnet.eval(gin)]
+            for g, e in zip(got, outs):
+                assert np.array_equal(g, e.data), (setting, mode)

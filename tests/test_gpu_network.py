@@ -324,7 +324,8 @@ def test_autotune_keeps_results_and_caches(tmp_path):
                     assert np.array_equal(got[k][b], expected[b][k]), (tag, mode, b, k)
 
     for setting in ({"ks_group": 1}, {"ks_group": 2, "mac_min_wg": 512}, {"ks_min_wg": 8192, "mac_min_wg": 8192},
-                    {"ntt_split": 5, "ntt_tile_log": 12}, {"ntt_split": 7, "ntt_tile_log": 11, "ks_group": 4}):
+                    {"ntt_split": 5, "ntt_tile_log": 12}, {"ntt_split": 7, "ntt_tile_log": 11, "ks_group": 4},
+                    {"ks_group": 4, "ks_order": 1}, {"ks_group": 1, "ks_order": 1, "ks_min_wg": 512}):
         net.set_tuning(**setting)
         check(setting)
     cache = str(tmp_path / "tuning.json")
@@ -336,9 +337,9 @@ def test_autotune_keeps_results_and_caches(tmp_path):
     net.set_tuning(ks_group=1, mac_min_wg=512, ks_min_wg=512, ntt_split=4, ntt_tile_log=12)
     net.set_mode(P.EVAL_HOISTED)          # the cache key includes the mode
     second = net.autotune(cache_path=cache)
-    for k in ("ntt_split", "ntt_tile_log", "mac_min_wg", "ks_min_wg", "ks_group"):
+    for k in ("ntt_split", "ntt_tile_log", "mac_min_wg", "ks_min_wg", "ks_group", "ks_order"):
         assert second[k] == first[k], k
     now = net.tuning()
-    for k in ("ntt_split", "ntt_tile_log", "mac_min_wg", "ks_min_wg", "ks_group"):
+    for k in ("ntt_split", "ntt_tile_log", "mac_min_wg", "ks_min_wg", "ks_group", "ks_order"):
         assert now[k] == first[k], k
     check("cached")
