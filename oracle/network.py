@@ -427,10 +427,15 @@ class Net:
     """Plan + evaluation of a UniHENN network on one ciphertext of packed
     samples (or one FP64 slot vector)."""
 
-    def __init__(self, inp: dict, layers, params, n_slots: int, samples: int = 1, stride: int = 0):
+    def __init__(self, inp: dict, layers, params, n_slots: int, samples: int = 1, stride: int = 0,
+                 fc_doubling: bool = False):
+        """fc_doubling: Algorithm 2's closing sum of ceil(DAT_in / DAT_out)
+        rotated copies by doubling (a variant of this implementation, see
+        _rotate_sum) instead of one rotation per copy."""
         self.inp = inp
         self.layers = layers
         self.params = params
+        self.fc_doubling = fc_doubling
         self.n_slots = n_slots
         self.samples = samples
         self.stride = check_packing(inp, layers, n_slots, samples, stride if samples > 1 else n_slots)
@@ -639,12 +644,38 @@ class Net:
                 srcs.append(ev.rot(X, o - Wvec))
                 terms.append((len(srcs) - 1, 1.0, v2))
         csum = ev.mac_rescale(srcs, [terms])[0]
-        acc = None
-        for i in range(math.ceil(din / D)):
-            t = ev.rot(csum, i * D)
-            acc = t if acc is None else ev.add(acc, t)
+        reps = math.ceil(din / D)
+        if self.fc_doubling:
+            acc = self._rotate_sum(ev, csum, reps, D)
+        else:
+            acc = None
+            for i in range(reps):
+                t = ev.rot(csum, i * D)
+                acc = t if acc is None else ev.add(acc, t)
         acc = ev.add_plain(acc, self._vec({q: float(b[q]) for q in range(D)}))
         return [acc], Layout("vec", length=D)
+
+    @staticmethod
+    def _rotate_sum(ev, x, reps: int, step: int):
+        """sum_{i < reps} Rot(x, i step) by doubling: S_1 = x and
+        S_2m = S_m + Rot(S_m, m step) give S_m = sum_{i < m} Rot(x, i step)
+        for powers of two m <= reps; the result adds, for each set bit 2^b
+        of reps from the highest down, Rot(S_(2^b), o step), o the sum of the
+        bits above it.  floor(log2 reps) + popcount(reps) - 1 rotations
+        instead of reps - 1; equal slot by slot (rotations are linear), not
+        bit for bit, since each rotation rounds its own key switch."""
+        S = {1: x}
+        m = 1
+        while 2 * m <= reps:
+            S[2 * m] = ev.add(S[m], ev.rot(S[m], m * step))
+            m *= 2
+        acc, off = None, 0
+        for bit in reversed(range(reps.bit_length())):
+            if reps >> bit & 1:
+                t = ev.rot(S[1 << bit], off * step)
+                acc = t if acc is None else ev.add(acc, t)
+                off += 1 << bit
+        return acc
 
     # read-out -----------------------------------------------------------------
     def output_positions(self) -> list[list[int]]:

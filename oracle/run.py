@@ -34,9 +34,10 @@ class OracleSession:
             self.rlk = self.ck.load_key(self.rlk_coeff)
 
 
-def build_net(cfg: dict, n_slots: int, params=None) -> Net:
+def build_net(cfg: dict, n_slots: int, params=None, fc_doubling: bool = False) -> Net:
     params = W.gen_params(cfg["layers"]) if params is None else params
-    return Net(cfg["input"], cfg["layers"], params, n_slots, cfg["samples_per_ct"], cfg["sample_stride"])
+    return Net(cfg["input"], cfg["layers"], params, n_slots, cfg["samples_per_ct"], cfg["sample_stride"],
+               fc_doubling=fc_doubling)
 
 
 def run_encrypted(sess: OracleSession, net: Net, xs: np.ndarray, enc_seed: int = W.SEED_ENCRYPT,

@@ -206,3 +206,58 @@ def test_encrypted_models_small_ring(name, log_n):
     assert all(o.nl == 1 for o in outs)
     got = decrypt_outputs(sess, net, outs)
     assert np.abs(got - reference_outputs(net, xs)).max() < 1e-3
+
+
+# ------------------------------------------------------------ doubling FC sum
+def _doubling_rotations(reps: int) -> int:
+    return (reps.bit_length() - 1) + bin(reps).count("1") - 1
+
+
+@pytest.mark.parametrize("name", list(W.CONFIGS))
+def test_fc_doubling_slot_simulation(name):
+    """The doubling form of Algorithm 2's closing sum gives the FP64 CNN slot
+    for slot on every workload, and saves exactly
+    (reps - 1) - (floor(log2 reps) + popcount(reps) - 1) rotations per FC."""
+    cfg = W.config(name)
+    n_slots = 2 ** (cfg["log_n"] - 1)
+    params = W.gen_params(cfg["layers"])
+    S, st = cfg["samples_per_ct"], cfg["sample_stride"]
+    xs = W.gen_inputs(cfg["input"], S)
+    ref = np.array([cnn_fp64(x, cfg["layers"], params).reshape(-1) for x in xs])
+    counts = []
+    for dbl in (False, True):
+        net = Net(cfg["input"], cfg["layers"], params, n_slots, S, st, fc_doubling=dbl)
+        ev = SlotEval(n_slots)
+        got = read_outputs(net, net.run(ev, [net.input_vector(xs)]))
+        assert np.abs(got - ref).max() < 1e-12
+        counts.append(ev.count.rot)
+    saved = 0
+    for lay in cfg["layers"]:
+        if lay["kind"] == "fc":
+            reps = math.ceil(lay["din"] / lay["dout"])
+            saved += (reps - 1) - _doubling_rotations(reps)
+    assert counts[0] - counts[1] == saved
+
+
+def test_fc_doubling_counts_lenet1_cnn1d():
+    """LeNet-1's 192 -> 10 FC sums 20 copies with 4 + 2 - 1 = 5 rotations
+    (19 before); the 1D CNN's 944 -> 5 FC sums 189 copies with 7 + 6 - 1 = 12
+    (188 before)."""
+    assert _doubling_rotations(20) == 5 and _doubling_rotations(189) == 12
+    assert _doubling_rotations(1) == 0 and _doubling_rotations(2) == 1 and _doubling_rotations(3) == 2
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("lazy", [False, True])
+def test_encrypted_lenet1_fc_doubling(lazy):
+    """LeNet-1 at N = 2^11 with the doubling FC sum (and with deferred
+    ModDown): within 1e-3 of the FP64 CNN."""
+    cfg = W.config("lenet1")
+    cfg["log_n"] = 11
+    sess = OracleSession(cfg)
+    net = build_net(cfg, sess.ck.slots, fc_doubling=True)
+    xs = W.gen_inputs(cfg["input"], 1)
+    _, outs, ev = run_encrypted(sess, net, xs, lazy=lazy)
+    assert ev.count.rot == 274
+    got = decrypt_outputs(sess, net, outs)
+    assert np.abs(got - reference_outputs(net, xs)).max() < 1e-3
