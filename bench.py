@@ -43,7 +43,7 @@ TUNING_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2
 
 
 def setup(P, W, name: str, batch: int, seed: int = 5, tune: bool = True, mode: int = 0, log_n: int | None = None,
-          lazy: bool = False):
+          lazy: bool = False, fc_doubling: bool = False):
     import torch
     cfg = W.config(name)
     if log_n is not None:
@@ -51,7 +51,8 @@ def setup(P, W, name: str, batch: int, seed: int = 5, tune: bool = True, mode: i
     ctx = P.Context(cfg["log_n"], cfg["prime_bits"], cfg["special_bits"], 2.0 ** cfg["log_scale"])
     params = W.gen_params(cfg["layers"])
     S, stride = cfg["samples_per_ct"], cfg["sample_stride"]
-    net = P.Net(ctx, cfg["input"], cfg["layers"], params, samples=S, stride=stride, max_batch=batch, lazy=lazy)
+    net = P.Net(ctx, cfg["input"], cfg["layers"], params, samples=S, stride=stride, max_batch=batch, lazy=lazy,
+                fc_doubling=fc_doubling)
     sk = P.keygen_secret(ctx, seed)
     keys = {r: P.gen_switch_key(ctx, sk, seed + 1, steps=r) for r in net.rotations()}
     rlk = P.gen_switch_key(ctx, sk, seed + 2, relin=True)
@@ -277,14 +278,22 @@ def rotation_microbench(P, batch: int = 128, hoisted: int = 24) -> dict:
     return out
 
 
-def batched_leg(P, W, name: str, B: int, per_ct: int, steps: int, tune: bool, lazy: bool, unit: str) -> dict:
+# plan variants measured beside the default plan: (name, deferred ModDown, doubling FC sum)
+PLAN_VARIANTS = [("deferred ModDown", True, False), ("doubling FC sum", False, True),
+                 ("deferred ModDown + doubling FC sum", True, True)]
+
+
+def batched_leg(P, W, name: str, B: int, per_ct: int, steps: int, tune: bool, lazy: bool, unit: str,
+                fc_doubling: bool = False) -> dict:
     """One batched configuration (B ciphertexts of per_ct samples, hoisted,
-    graph replay, tuned) in the default or the deferred-ModDown plan:
-    samples/s, per-family kernel table and the dominant family's roofline."""
+    graph replay, tuned) in the default plan or a variant: samples/s,
+    per-family kernel table and the dominant family's roofline."""
     import torch
-    plan = "deferred ModDown" if lazy else "default"
+    plan = " + ".join([n for n, on in (("deferred ModDown", lazy), ("doubling FC sum", fc_doubling)) if on]) \
+        or "default"
     print(f"[bench] setup batched {name} ({B} ciphertexts x {per_ct}, {plan} plan)", file=sys.stderr, flush=True)
-    sb = setup(P, W, name, batch=B, tune=tune, mode=P.EVAL_HOISTED | P.EVAL_GRAPH, lazy=lazy)
+    sb = setup(P, W, name, batch=B, tune=tune, mode=P.EVAL_HOISTED | P.EVAL_GRAPH, lazy=lazy,
+               fc_doubling=fc_doubling)
     nb, ctb, outb = sb["net"], sb["ct"], sb["outs"]
     stepb = lambda: nb.eval(ctb, outb)
     dtb = timed(stepb, steps, 1)
@@ -363,7 +372,8 @@ def main():
     ap.add_argument("--no-rotation-sweep", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="default launch parameters instead of the tuned ones")
     ap.add_argument("--no-models", action="store_true", help="skip the paper's other model shapes")
-    ap.add_argument("--no-lazy", action="store_true", help="skip the deferred-ModDown plan measurements")
+    ap.add_argument("--no-lazy", action="store_true",
+                    help="skip the plan variants (deferred ModDown, doubling FC sum)")
     ap.add_argument("--serve-requests", type=int, default=300,
                     help="requests per load level of the serving measurement (0 skips it)")
     ap.add_argument("--ntt-probe", type=int, default=0, metavar="ROWS",
@@ -453,24 +463,27 @@ def main():
     net.set_mode(P.EVAL_PLAIN | P.EVAL_GRAPH)
 
     if not args.no_lazy:
-        # the same single-image workload in the deferred-ModDown plan
-        print("[bench] setup plain LeNet-1, deferred-ModDown plan", file=sys.stderr, flush=True)
-        sl = setup(P, W, "lenet1", batch=1, tune=not args.no_tune, mode=P.EVAL_PLAIN | P.EVAL_GRAPH, lazy=True)
-        nlz, ctl, outl = sl["net"], sl["ct"], sl["outs"]
-        stepl = lambda: nlz.eval(ctl, outl)
-        dtl = timed(stepl, args.steps, args.warmup)
-        nlz.set_mode(P.EVAL_HOISTED | P.EVAL_GRAPH)
-        dtlh = timed(stepl, args.steps, 1)
-        nlz.set_mode(P.EVAL_PLAIN | P.EVAL_GRAPH)
-        lazy_families = family_table(family_stats(P, stepl, args.steps), args.steps)
-        res["plain_lazy"] = {"inferences_per_s": round(args.steps / dtl, 3),
-                             "ms_per_step": round(1e3 * dtl / args.steps, 3),
-                             "hoisted_inferences_per_s": round(args.steps / dtlh, 3),
-                             "multiple_of_default_plan": round(dt / dtl, 3),
-                             "max_abs_err_vs_fp64": max_error(P, W, sl), "tuning": sl["tuning"],
-                             "kernel_families": lazy_families}
-        print(f"[bench] plain, deferred ModDown: {args.steps / dtl:.2f} inf/s", file=sys.stderr, flush=True)
-        del sl, nlz, ctl, outl, stepl
+        # the same single-image workload in the plan variants
+        res["plain_variants"] = {}
+        for vname, lazy, dbl in PLAN_VARIANTS:
+            print(f"[bench] setup plain LeNet-1, {vname}", file=sys.stderr, flush=True)
+            sl = setup(P, W, "lenet1", batch=1, tune=not args.no_tune, mode=P.EVAL_PLAIN | P.EVAL_GRAPH, lazy=lazy,
+                       fc_doubling=dbl)
+            nlz, ctl, outl = sl["net"], sl["ct"], sl["outs"]
+            stepl = lambda: nlz.eval(ctl, outl)
+            dtl = timed(stepl, args.steps, args.warmup)
+            nlz.set_mode(P.EVAL_HOISTED | P.EVAL_GRAPH)
+            dtlh = timed(stepl, args.steps, 1)
+            nlz.set_mode(P.EVAL_PLAIN | P.EVAL_GRAPH)
+            fams = family_table(family_stats(P, stepl, args.steps), args.steps)
+            res["plain_variants"][vname] = {
+                "inferences_per_s": round(args.steps / dtl, 3), "ms_per_step": round(1e3 * dtl / args.steps, 3),
+                "hoisted_inferences_per_s": round(args.steps / dtlh, 3),
+                "multiple_of_default_plan": round(dt / dtl, 3), "rotation_keys": len(nlz.rotations()),
+                "max_abs_err_vs_fp64": max_error(P, W, sl), "tuning": sl["tuning"], "kernel_families": fams}
+            print(f"[bench] plain, {vname}: {args.steps / dtl:.2f} inf/s", file=sys.stderr, flush=True)
+            del sl, nlz, ctl, outl, stepl
+        torch.cuda.empty_cache()
 
     # rotations/s at the same size (one ciphertext, 8 limbs)
     ctx = st["ctx"]
@@ -490,14 +503,17 @@ def main():
         B = args.batched_cts
         del st, step
         torch.cuda.empty_cache()
-        plans = [False] + ([] if args.no_lazy else [True])
-        for lazy in plans:
-            r = batched_leg(P, W, "lenet1_batched", B, 10, args.batched_steps, not args.no_tune, lazy, "images_per_s")
+        # default plan, then deferred ModDown with the doubling FC sum
+        plans = [(False, False)] + ([] if args.no_lazy else [(True, True)])
+        for lazy, dbl in plans:
+            r = batched_leg(P, W, "lenet1_batched", B, 10, args.batched_steps, not args.no_tune, lazy, "images_per_s",
+                            fc_doubling=dbl)
             r["multiple_of_plain"] = round(r["images_per_s"] / value, 2)
-            res["batched_lazy" if lazy else "batched"] = r
-        for lazy in plans:
-            r = batched_leg(P, W, "cnn1d", 64, 8, args.batched_steps, not args.no_tune, lazy, "sequences_per_s")
-            res["batched_cnn1d_lazy" if lazy else "batched_cnn1d"] = r
+            res["batched_variant" if lazy else "batched"] = r
+        for lazy, dbl in plans:
+            r = batched_leg(P, W, "cnn1d", 64, 8, args.batched_steps, not args.no_tune, lazy, "sequences_per_s",
+                            fc_doubling=dbl)
+            res["batched_cnn1d_variant" if lazy else "batched_cnn1d"] = r
 
     if not args.no_models:
         res["models"] = models_bench(P, W)

@@ -231,8 +231,15 @@ int unihenn_net_create(const unihenn_ctx* ctx, const unihenn_input* input, const
  *     a product and the network outputs take the ModDown first.  Results
  *     differ from the default plan in their last bits (each sum is rounded
  *     once instead of once per term); the decrypted outputs meet the same
- *     bounds. */
-enum { UNIHENN_PLAN_LAZY_MODDOWN = 1 };
+ *     bounds.
+ *   UNIHENN_PLAN_FC_DOUBLING  Algorithm 2's closing sum of
+ *     ceil(DAT_in / DAT_out) rotated copies by doubling, another variant of
+ *     this library: S_1 = x, S_2m = S_m + Rot(S_m, m DAT_out), then one
+ *     rotation per further set bit of the copy count, floor(log2 reps) +
+ *     popcount(reps) - 1 rotations instead of reps - 1 (fewer rotation keys
+ *     too).  The same sum slot by slot; results differ in their last bits.
+ */
+enum { UNIHENN_PLAN_LAZY_MODDOWN = 1, UNIHENN_PLAN_FC_DOUBLING = 2 };
 /* unihenn_net_create with plan options (plan_flags, 0 = the default plan).
  * Errors: as unihenn_net_create, and EINVAL for an unknown flag. */
 int unihenn_net_create_ex(const unihenn_ctx* ctx, const unihenn_input* input, const unihenn_layer* layers,

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libunihenn.so")
 OK, EINVAL, ELEVEL, ESCALE, ENOKEY, ESLOTS, ENOMEM, EDEVICE = 0, -1, -2, -3, -4, -5, -6, -7
 LAYER_CONV, LAYER_SQUARE, LAYER_AVGPOOL, LAYER_FLATTEN, LAYER_FC, LAYER_RELU_APPROX = 1, 2, 3, 4, 5, 6
 EVAL_PLAIN, EVAL_HOISTED, EVAL_GRAPH = 0, 1, 2
-PLAN_LAZY_MODDOWN = 1
+PLAN_LAZY_MODDOWN, PLAN_FC_DOUBLING = 1, 2
 KERNEL_FAMILIES = ["ntt_fwd_col", "ntt_fwd_row", "ntt_inv_row", "ntt_inv_col", "modup", "ks_inner", "moddown",
                    "rescale", "mac", "automorphism", "tensor", "add", "encode", "other"]
 
@@ -410,10 +410,12 @@ class Net:
     """A planned network with its plaintexts encoded on the device."""
 
     def __init__(self, ctx: Context, inp: dict, layers, params, samples: int = 1, stride: int = 0,
-                 max_batch: int = 1, lazy: bool = False):
-        """lazy: plan with deferred ModDown (PLAN_LAZY_MODDOWN)."""
+                 max_batch: int = 1, lazy: bool = False, fc_doubling: bool = False):
+        """lazy: plan with deferred ModDown (PLAN_LAZY_MODDOWN); fc_doubling:
+        the FC's closing sum by doubling (PLAN_FC_DOUBLING)."""
         self.ctx = ctx
         self.lazy = lazy
+        self.fc_doubling = fc_doubling
         self._keep = []
         arr = (LAYER * len(layers))()
         for i, (L, p) in enumerate(zip(layers, params)):
@@ -438,7 +440,8 @@ class Net:
         ind = INPUT(inp["c"], inp["h"], inp["w"], samples, stride)
         h = C.c_void_p()
         _check(lib().unihenn_net_create_ex(ctx.h, C.byref(ind), arr, len(layers), max_batch,
-                                           PLAN_LAZY_MODDOWN if lazy else 0, C.byref(h)))
+                                           (PLAN_LAZY_MODDOWN if lazy else 0) |
+                                           (PLAN_FC_DOUBLING if fc_doubling else 0), C.byref(h)))
         self.h = h
         self.samples = samples
         self.max_batch = max_batch

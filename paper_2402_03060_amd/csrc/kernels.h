@@ -110,6 +110,16 @@ struct EwGroup {
 };
 void launch_group_add(const unihenn_ctx* c, const EwGroup& g, int batch, int nl, bool plain, hipStream_t s,
                       int pl = -1);
+// E independent sums of T ciphertext batches each (E * T <= UH_SUM_MAX_TERMS):
+// out[e] (+)= sum_t in[e * T + t]
+#define UH_SUM_MAX_TERMS 128
+struct SumGroup {
+    int E, T;
+    u64* out[UH_EW_GROUP_MAX];
+    const u64* in[UH_SUM_MAX_TERMS];
+};
+void launch_group_sum(const unihenn_ctx* c, const SumGroup& g, int batch, int nl, bool accumulate, hipStream_t s,
+                      int pl = -1);
 // out_e [B][2][nl+1] = P a_e ([B][2][nl]): limbs i < nl times P mod q_i, limb nl zero
 void launch_group_to_ext(const unihenn_ctx* c, const EwGroup& g, int batch, int nl, hipStream_t s);
 // ModDown of E extended ciphertext batches [B][2][nl+1] -> [B][2][nl]; ws

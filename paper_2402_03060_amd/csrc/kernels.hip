@@ -856,6 +856,21 @@ __global__ void k_group_last(u64* __restrict__ last, EwGroup g, int nl, int n)
     last[((size_t)e * gridDim.y + p) * n + k] = g.a[e][((size_t)p * nl + nl - 1) * n + k];
 }
 
+__global__ void k_group_sum(SumGroup g, DevCtx ctx, int nl, int accumulate, int pl)
+{
+    const int n = ctx.n;
+    const int k = blockIdx.x * EW_THREADS + threadIdx.x;
+    if (k >= n) return;
+    const size_t r = blockIdx.y;  // (b * 2 + c) * nl + i
+    const int e = blockIdx.z;
+    const int i = (int)(r % nl);
+    const u64 q = ctx.mod[i == pl ? ctx.p_index : i].q;
+    const size_t o = r * n + k;
+    u64 v = accumulate ? g.out[e][o] : 0;
+    for (int t = 0; t < g.T; ++t) v = add_mod(v, g.in[e * g.T + t][o], q);
+    g.out[e][o] = v;
+}
+
 // out_e[(b * 2 + c) * (nl + 1) + i] = P in_e[(b * 2 + c) * nl + i] (i < nl), 0 (i = nl)
 __global__ void k_group_to_ext(EwGroup g, DevCtx ctx, int nl)
 {
@@ -985,6 +1000,14 @@ void launch_group_add(const unihenn_ctx* c, const EwGroup& g, int batch, int nl,
     LaunchTimer tm(KF_ADD, 8.0 * c->n * g.E * (batch * 2.0 * nl * (plain ? 2.0 : 3.0) + (plain ? nl : 0)), s);
     dim3 g3((c->n + EW_THREADS - 1) / EW_THREADS, batch * 2 * nl, g.E);
     k_group_add<<<g3, EW_THREADS, 0, s>>>(g, c->dev, nl, plain ? 1 : 0, pl);
+}
+
+void launch_group_sum(const unihenn_ctx* c, const SumGroup& g, int batch, int nl, bool accumulate, hipStream_t s,
+                      int pl)
+{
+    LaunchTimer tm(KF_ADD, 8.0 * c->n * g.E * batch * 2.0 * nl * (g.T + 1 + (accumulate ? 1 : 0)), s);
+    dim3 g3((c->n + EW_THREADS - 1) / EW_THREADS, batch * 2 * nl, g.E);
+    k_group_sum<<<g3, EW_THREADS, 0, s>>>(g, c->dev, nl, accumulate ? 1 : 0, pl);
 }
 
 void launch_group_to_ext(const unihenn_ctx* c, const EwGroup& g, int batch, int nl, hipStream_t s)

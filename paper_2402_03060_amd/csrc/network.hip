@@ -28,7 +28,9 @@ int encode_scaled_batch(const unihenn_ctx* c, const double* z, int n_slots, cons
 
 namespace {
 
-enum StepKind { ST_DROP, ST_ROT, ST_MAC, ST_MACM, ST_RESCALE, ST_ADD, ST_ADD_PLAIN, ST_SQUARE, ST_MUL, ST_EXT, ST_MODDOWN };
+enum StepKind {
+    ST_DROP, ST_ROT, ST_MAC, ST_MACM, ST_RESCALE, ST_ADD, ST_ADD_PLAIN, ST_SQUARE, ST_MUL, ST_EXT, ST_MODDOWN, ST_SUM
+};
 
 // A register holds a batch of ciphertexts at level nl; an extended register
 // (deferred ModDown) holds them over {q_0..q_{nl-1}, P}, one limb more, and
@@ -157,6 +159,7 @@ struct Planner {
     // brought down once, before their rescale; every other use of an
     // extended register takes its ModDown first (once per register)
     bool lazy = false;
+    bool fc_doubling = false;  // Algorithm 2's closing sum by doubling (UNIHENN_PLAN_FC_DOUBLING)
     std::map<int, int> md_of, ext_of;
     std::map<size_t, int> pt_ext;  // plaintext offset -> has the P limb
 
@@ -252,15 +255,26 @@ struct Planner {
         return d;
     }
 
-    // sum of ciphertexts (a chain of additions)
-    int sum(const std::vector<int>& xs)
+    // sum of ciphertexts: one n-ary step (an addition for two terms); the
+    // same residues as a chain of additions, since the sum is exact mod q
+    int sum(std::vector<int> xs)
     {
-        int acc = -1;
-        for (int x : xs) {
-            acc = acc < 0 ? x : add(acc, x);
-            if (acc < 0) return -1;
-        }
-        return acc;
+        if (xs.empty()) return fail(UNIHENN_EINVAL, "empty sum");
+        if (xs.size() == 1) return xs[0];
+        if (xs.size() == 2) return add(xs[0], xs[1]);
+        if (any_ext(xs))
+            for (int& x : xs) x = to_ext(x);
+        const VReg r0 = net->regs[xs[0]];
+        for (int x : xs)
+            if (net->regs[x].nl != r0.nl || net->regs[x].scale != r0.scale)
+                return fail(UNIHENN_ESCALE, "addition of ciphertexts at different levels or scales");
+        int d = newreg(r0.nl, r0.scale, r0.ext);
+        Step s;
+        s.kind = ST_SUM;
+        s.dst = d;
+        s.srcs = xs;
+        net->steps.push_back(s);
+        return d;
     }
 
     // request plaintexts Encode(w_t * z) at `scale` and nl limbs (nl + 1
@@ -701,6 +715,34 @@ struct Planner {
         return 0;
     }
 
+    // sum_{i < reps} Rot(x, i step) by doubling: S_1 = x, S_2m = S_m +
+    // Rot(S_m, m step); then, for each set bit 2^b of reps from the highest
+    // down, Rot(S_(2^b), o step) with o the sum of the bits above it.
+    // floor(log2 reps) + popcount(reps) - 1 rotations instead of reps - 1;
+    // the same slots, different rounding (each rotation rounds its own key
+    // switch)
+    int rotate_sum(int x, int reps, int step)
+    {
+        std::map<int, int> S;
+        S[1] = x;
+        int m = 1;
+        while (2 * m <= reps) {
+            S[2 * m] = add(S[m], rot(S[m], (long)m * step));
+            if (S[2 * m] < 0) return -1;
+            m *= 2;
+        }
+        int acc = -1;
+        long off = 0;
+        for (int bit = 30; bit >= 0; --bit) {
+            if (!((reps >> bit) & 1)) continue;
+            int t = rot(S[1 << bit], off * step);
+            acc = acc < 0 ? t : add(acc, t);
+            if (acc < 0) return -1;
+            off += 1L << bit;
+        }
+        return acc;
+    }
+
     // Algorithm 2 -----------------------------------------------------------
     int fc(Layout& L, const unihenn_layer& ly)
     {
@@ -735,9 +777,14 @@ struct Planner {
             terms.push_back({srcs[t], request(vs[t], std::vector<double>(1, 1.0), delta, nl, 1, ext)});
         int csum = mac_rescale(terms);
         if (csum < 0) return -1;
-        std::vector<int> parts;
-        for (int i = 0; i < reps; ++i) parts.push_back(rot(csum, (long)i * D));
-        int acc = sum(parts);
+        int acc;
+        if (fc_doubling) {
+            acc = rotate_sum(csum, reps, D);
+        } else {
+            std::vector<int> parts;
+            for (int i = 0; i < reps; ++i) parts.push_back(rot(csum, (long)i * D));
+            acc = sum(parts);
+        }
         if (acc < 0) return -1;
         std::vector<long> pos;
         for (int p = 0; p < D; ++p) pos.push_back(p);
@@ -903,6 +950,7 @@ void schedule_layers(unihenn_net* net)
         case ST_MUL: return 5;
         case ST_ADD_PLAIN: return 6;
         case ST_ADD: return 7;
+        case ST_SUM: return 7;
         default: return 8;
         }
     };
@@ -1007,7 +1055,8 @@ extern "C" int unihenn_net_create_ex(const unihenn_ctx* c, const unihenn_input* 
                                      uint32_t n_layers, uint32_t max_batch, uint32_t plan_flags, unihenn_net** out)
 {
     if (!c || !in || !out || (n_layers && !layers)) return uh_fail(UNIHENN_EINVAL, "null argument");
-    if (plan_flags & ~(uint32_t)UNIHENN_PLAN_LAZY_MODDOWN) return uh_fail(UNIHENN_EINVAL, "unknown plan flag");
+    if (plan_flags & ~(uint32_t)(UNIHENN_PLAN_LAZY_MODDOWN | UNIHENN_PLAN_FC_DOUBLING))
+        return uh_fail(UNIHENN_EINVAL, "unknown plan flag");
     if (in->c < 1 || in->h < 1 || in->w < 1 || in->samples < 1 || max_batch < 1)
         return uh_fail(UNIHENN_EINVAL, "empty input shape, sample count or batch");
     for (uint32_t l = 0; l < n_layers; ++l)
@@ -1048,6 +1097,7 @@ extern "C" int unihenn_net_create_ex(const unihenn_ctx* c, const unihenn_input* 
 
     Planner P{net, c, c->scale, {}, "", 0};
     P.lazy = net->lazy;
+    P.fc_doubling = (plan_flags & UNIHENN_PLAN_FC_DOUBLING) != 0;
     net->input_reg = P.newreg(net->in_limbs, c->scale);
     {
         Step s;
@@ -1472,6 +1522,28 @@ struct Exec {
                     g.b[e] = kind == ST_ADD ? reg(x.b) : net->pt_arena + x.pt;
                 }
                 launch_group_add(c, g, B, lim, kind == ST_ADD_PLAIN, s, pl);
+                si = run.back();
+                break;
+            }
+            case ST_SUM: {
+                // independent sums with the same term count, one launch per
+                // UH_SUM_MAX_TERMS terms of the group
+                const int T = (int)st.srcs.size();
+                std::vector<size_t> run = collect(si, end, nl, [&](const Step& x) {
+                    return x.kind == ST_SUM && (int)x.srcs.size() == T;
+                }, UH_EW_GROUP_MAX, std::max(1, UH_SUM_MAX_TERMS / T));
+                SumGroup g;
+                memset(&g, 0, sizeof(g));
+                g.E = (int)run.size();
+                for (int t0 = 0; t0 < T; t0 += UH_SUM_MAX_TERMS) {
+                    g.T = std::min(UH_SUM_MAX_TERMS, T - t0);
+                    for (int e = 0; e < g.E; ++e) {
+                        const Step& x = net->steps[run[e]];
+                        g.out[e] = reg(x.dst);
+                        for (int t = 0; t < g.T; ++t) g.in[e * g.T + t] = reg(x.srcs[t0 + t]);
+                    }
+                    launch_group_sum(c, g, B, lim, t0 > 0, s, pl);
+                }
                 si = run.back();
                 break;
             }

@@ -225,16 +225,18 @@ class GpuExecutor:
 
 
 def prepare_model(P, W, name: str, max_batch: int, pool_size: int, seed: int = 5,
-                  tuning_cache: str | None = None) -> dict:
-    """Context, net (hoisted, graph replay), product-client keys and a pool of
-    encrypted synthetic inputs for one workload; with tuning_cache, launch
-    parameters tuned for full batches (looked up in or recorded to that file)."""
+                  tuning_cache: str | None = None, lazy: bool = False, fc_doubling: bool = False) -> dict:
+    """Context, net (hoisted, graph replay; lazy / fc_doubling select the plan
+    variants), product-client keys and a pool of encrypted synthetic inputs
+    for one workload; with tuning_cache, launch parameters tuned for full
+    batches (looked up in or recorded to that file)."""
     import torch
     cfg = W.config(name)
     ctx = P.Context(cfg["log_n"], cfg["prime_bits"], cfg["special_bits"], 2.0 ** cfg["log_scale"])
     params = W.gen_params(cfg["layers"])
     S, stride = cfg["samples_per_ct"], cfg["sample_stride"]
-    net = P.Net(ctx, cfg["input"], cfg["layers"], params, samples=S, stride=stride, max_batch=max_batch)
+    net = P.Net(ctx, cfg["input"], cfg["layers"], params, samples=S, stride=stride, max_batch=max_batch,
+                lazy=lazy, fc_doubling=fc_doubling)
     sk = P.keygen_secret(ctx, seed)
     keys = {r: P.gen_switch_key(ctx, sk, seed + 1, steps=r) for r in net.rotations()}
     rlk = P.gen_switch_key(ctx, sk, seed + 2, relin=True)
@@ -265,14 +267,19 @@ SERVE_MIX = {"conv1": 0.5, "cnn1d": 0.3, "cifar_cnn": 0.2}
 
 
 def serving_benchmark(P, W, n_requests: int, tuning_cache: str | None = None, hbm_budget: int | None = None,
-                      levels=(0.5, 0.8, 1.0), log=print) -> dict:
+                      levels=(0.5, 0.8, 1.0), log=print, lazy: bool = True, fc_doubling: bool = True) -> dict:
     """Three models of different ring sizes behind the server: saturation
     throughput (all requests queued at t = 0), then Poisson arrivals (seed 4,
     mix 50/30/20) at the given fractions of it.  The admission budget
-    defaults to 90% of the HBM left free once the models are resident."""
+    defaults to 90% of the HBM left free once the models are resident.  The
+    models run the deferred-ModDown plan with the doubling FC sum unless
+    lazy / fc_doubling say otherwise."""
     import torch
-    log("setup serving models " + ", ".join(SERVE_MODELS))
-    models = {m: prepare_model(P, W, m, b, pool_size=16, tuning_cache=tuning_cache) for m, b in SERVE_MODELS.items()}
+    plan = " + ".join([n for n, on in (("deferred ModDown", lazy), ("doubling FC sum", fc_doubling)) if on]) \
+        or "default"
+    log("setup serving models " + ", ".join(SERVE_MODELS) + f" ({plan} plan)")
+    models = {m: prepare_model(P, W, m, b, pool_size=16, tuning_cache=tuning_cache, lazy=lazy, fc_doubling=fc_doubling)
+              for m, b in SERVE_MODELS.items()}
     ex = GpuExecutor(models)
     ex.warmup()
     if hbm_budget is None:
@@ -283,7 +290,7 @@ def serving_benchmark(P, W, n_requests: int, tuning_cache: str | None = None, hb
     out = {"models": {m: {"log_n": d["cfg"]["log_n"], "max_batch": SERVE_MODELS[m], "ciphertexts_per_request": 1,
                           "samples_per_ct": d["cfg"]["samples_per_ct"], "request_bytes": d["spec"].footprint_bytes}
                       for m, d in models.items()},
-           "mix": SERVE_MIX, "arrival_seed": W.SEED_ARRIVALS, "hbm_budget_bytes": hbm_budget,
+           "plan": plan, "mix": SERVE_MIX, "arrival_seed": W.SEED_ARRIVALS, "hbm_budget_bytes": hbm_budget,
            "requests_per_level": n_requests}
     burst = poisson_requests(SERVE_MIX, 1e9, n_requests, W.SEED_ARRIVALS, payloads)
     st = serve(Scheduler(specs, hbm_budget), ex, burst)
@@ -315,6 +322,8 @@ def main():
     ap = argparse.ArgumentParser(description="serving measurement: saturation, then Poisson load levels")
     ap.add_argument("--requests", type=int, default=10000, help="requests per load level")
     ap.add_argument("--levels", default="0.5,0.8,1.0")
+    ap.add_argument("--default-plan", action="store_true",
+                    help="the default plan instead of deferred ModDown + doubling FC sum")
     ap.add_argument("--tuning-cache", default=os.path.join(os.path.dirname(os.path.abspath(__file__)),
                                                            "tuning_cache.json"))
     a = ap.parse_args()
@@ -323,6 +332,7 @@ def main():
     import workloads as W
     out = serving_benchmark(P, W, a.requests, tuning_cache=a.tuning_cache,
                             levels=tuple(float(x) for x in a.levels.split(",")),
+                            lazy=not a.default_plan, fc_doubling=not a.default_plan,
                             log=lambda m: print("[serve] " + m, file=sys.stderr, flush=True))
     print(json.dumps(out))
 

@@ -131,3 +131,18 @@ def test_lazy_workgroup_orders_and_groups_identical():
             got = [ctx.export_ct(o)[0] for o in gnet.eval(gin)]
             for g, e in zip(got, outs):
                 assert np.array_equal(g, e.data), (setting, mode)
+
+
+@pytest.mark.parametrize("name,log_n,lazy", [("lenet1", 11, False), ("lenet1", 11, True), ("cnn1d", 12, False),
+                                             ("cnn1d", 12, True)])
+def test_fc_doubling_bit_exact(name, log_n, lazy):
+    """Algorithm 2's closing sum by doubling (PLAN_FC_DOUBLING), alone and with
+    deferred ModDown, against the oracle's fc_doubling mode: LeNet-1 (20
+    copies, 5 rotations) and the 1D CNN (189 copies, 12 rotations; two
+    sequences per ciphertext)."""
+    import paper_2402_03060_amd as P
+    cfg = W.config(name)
+    cfg["log_n"] = log_n
+    if name == "cnn1d":
+        cfg["samples_per_ct"] = 2
+    _run_parity(cfg, lazy=lazy, fc_doubling=True, modes=_all_modes(P))

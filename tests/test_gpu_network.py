@@ -16,7 +16,7 @@ pytestmark = pytest.mark.gpu
 
 def _gpu_net(P, ctx, cfg, sess, net_oracle, batch=1, lazy=False):
     net = P.Net(ctx, cfg["input"], cfg["layers"], net_oracle.params, samples=cfg["samples_per_ct"],
-                stride=cfg["sample_stride"], max_batch=batch, lazy=lazy)
+                stride=cfg["sample_stride"], max_batch=batch, lazy=lazy, fc_doubling=net_oracle.fc_doubling)
     assert net.depth == net_oracle.depth
     assert sorted(net.rotations()) == net_oracle.rotation_set()
     keys = {r: ctx.import_evk(sess.key_coeff[r]) for r in net.rotations()}
@@ -29,12 +29,13 @@ def _ctx(P, cfg):
     return P.Context(cfg["log_n"], cfg["prime_bits"], cfg["special_bits"], 2.0 ** cfg["log_scale"])
 
 
-def _run_parity(cfg, n_cts=1, seeds=(W.SEED_ENCRYPT,), lazy=False, modes=None):
+def _run_parity(cfg, n_cts=1, seeds=(W.SEED_ENCRYPT,), lazy=False, modes=None, fc_doubling=False):
     """GPU outputs equal to the oracle's, residue by residue, in every mode
-    (default: plain and hoisted); lazy: both sides plan deferred ModDown."""
+    (default: plain and hoisted); lazy: both sides plan deferred ModDown;
+    fc_doubling: both sides sum the FC's rotated copies by doubling."""
     import paper_2402_03060_amd as P
     sess = OracleSession(cfg)
-    onet = build_net(cfg, sess.ck.slots)
+    onet = build_net(cfg, sess.ck.slots, fc_doubling=fc_doubling)
     xs_all = W.gen_inputs(cfg["input"], cfg["samples_per_ct"] * n_cts)
     expected, cts = [], []
     for b in range(n_cts):

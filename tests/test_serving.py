@@ -147,10 +147,12 @@ def test_poisson_mix_is_seeded():
 
 
 @pytest.mark.gpu
-def test_served_outputs_equal_alone():
+@pytest.mark.parametrize("variant", [False, True])
+def test_served_outputs_equal_alone(variant):
     """Three models (ring sizes 2^11, 2^12, 2^12 here) served together from a
     Poisson stream with varying batch sizes: each request's output
-    ciphertexts equal those of evaluating its ciphertext alone."""
+    ciphertexts equal those of evaluating its ciphertext alone (default plan,
+    and deferred ModDown with the doubling FC sum, which the server runs)."""
     import torch
     import workloads as W
     import paper_2402_03060_amd as P
@@ -169,7 +171,8 @@ def test_served_outputs_equal_alone():
             return c
         W.config = small
         for name in shrink:
-            models[name] = prepare_model(P, W, name, batches[name], pool_size=5, seed=40)
+            models[name] = prepare_model(P, W, name, batches[name], pool_size=5, seed=40, lazy=variant,
+                                         fc_doubling=variant)
     finally:
         W.config = orig
     ex = GpuExecutor(models, keep_results=True)
