@@ -64,19 +64,23 @@ def kernel_hw(lay) -> tuple[int, int, int, int]:
     return lay["k"], lay["k"], lay["s"], lay["s"]
 
 
-def input_layout(inp: dict) -> Layout:
+def input_layout(inp: dict, channel_cts: bool = False) -> Layout:
     C, H, W = inp["c"], inp["h"], inp["w"]
+    if channel_cts:
+        # one ciphertext per input channel, the channel at offset 0 of each
+        return Layout("map", C, H, W, 1, W, list(range(C)), [0] * C, "input", 1.0)
     # one ciphertext per sample, channels row-major at offset c*H*W (Sec. III-A)
     return Layout("map", C, H, W, 1, W, [0] * C, [c * H * W for c in range(C)], "input", 1.0)
 
 
-def footprint(inp: dict, layers) -> int:
+def footprint(inp: dict, layers, channel_cts: bool = False) -> int:
     """Slots each packed sample needs (Section VI): the largest extent, over
     all layers, of the slots that hold the sample's valid values or that a
     valid output reads; the flatten output C*H*W; the FC width
-    DAT_out * ceil(DAT_in / DAT_out)."""
-    L = input_layout(inp)
-    need = inp["c"] * inp["h"] * inp["w"]
+    DAT_out * ceil(DAT_in / DAT_out).  With channel_cts each input channel
+    sits in its own ciphertext (H*W slots)."""
+    L = input_layout(inp, channel_cts)
+    need = (1 if channel_cts else inp["c"]) * inp["h"] * inp["w"]
     for lay in layers:
         k = lay["kind"]
         if k == "conv":
@@ -106,8 +110,8 @@ def footprint(inp: dict, layers) -> int:
     return need
 
 
-def check_packing(inp: dict, layers, n_slots: int, samples: int, stride: int) -> int:
-    fp = footprint(inp, layers)
+def check_packing(inp: dict, layers, n_slots: int, samples: int, stride: int, channel_cts: bool = False) -> int:
+    fp = footprint(inp, layers, channel_cts)
     if samples == 1:
         if fp > n_slots:
             raise PlanError("model does not fit the slots")
@@ -428,17 +432,20 @@ class Net:
     samples (or one FP64 slot vector)."""
 
     def __init__(self, inp: dict, layers, params, n_slots: int, samples: int = 1, stride: int = 0,
-                 fc_doubling: bool = False):
+                 fc_doubling: bool = False, channel_cts: bool = False):
         """fc_doubling: Algorithm 2's closing sum of ceil(DAT_in / DAT_out)
         rotated copies by doubling (a variant of this implementation, see
-        _rotate_sum) instead of one rotation per copy."""
+        _rotate_sum) instead of one rotation per copy.  channel_cts: the input
+        arrives as one ciphertext per channel (for inputs whose C*H*W
+        exceeds a sample's slots); run() then takes C input ciphertexts."""
         self.inp = inp
         self.layers = layers
         self.params = params
         self.fc_doubling = fc_doubling
+        self.channel_cts = channel_cts
         self.n_slots = n_slots
         self.samples = samples
-        self.stride = check_packing(inp, layers, n_slots, samples, stride if samples > 1 else n_slots)
+        self.stride = check_packing(inp, layers, n_slots, samples, stride if samples > 1 else n_slots, channel_cts)
         self.depth = network_depth(inp, layers)
 
     # slot vector helper: ones at the given in-sample positions of every sample
@@ -465,14 +472,29 @@ class Net:
             v[b * self.stride: b * self.stride + flat.size] = flat
         return v
 
+    def input_vectors(self, xs: np.ndarray) -> list:
+        """The network's input slot vectors: [input_vector(xs)], or with
+        channel_cts one vector per channel c holding sample b's (H,W) plane
+        of channel c at slot b*stride."""
+        if not self.channel_cts:
+            return [self.input_vector(xs)]
+        vs = []
+        for c in range(self.inp["c"]):
+            v = np.zeros(self.n_slots)
+            for b, x in enumerate(xs):
+                flat = np.asarray(x, dtype=np.float64)[c].reshape(-1)
+                v[b * self.stride: b * self.stride + flat.size] = flat
+            vs.append(v)
+        return vs
+
     def rotation_set(self) -> list[int]:
         """Distinct non-zero rotation amounts (mod N/2) the evaluation uses."""
         rec = _RotRecorder(self.n_slots)
-        self.run(rec, [np.zeros(self.n_slots)])
+        self.run(rec, [np.zeros(self.n_slots)] * (self.inp["c"] if self.channel_cts else 1))
         return sorted(rec.seen)
 
     def run(self, ev, cts):
-        L = input_layout(self.inp)
+        L = input_layout(self.inp, self.channel_cts)
         xs = list(cts)
         for lay, p in zip(self.layers, self.params):
             k = lay["kind"]

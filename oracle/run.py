@@ -34,24 +34,26 @@ class OracleSession:
             self.rlk = self.ck.load_key(self.rlk_coeff)
 
 
-def build_net(cfg: dict, n_slots: int, params=None, fc_doubling: bool = False) -> Net:
+def build_net(cfg: dict, n_slots: int, params=None, fc_doubling: bool = False, channel_cts: bool = False) -> Net:
     params = W.gen_params(cfg["layers"]) if params is None else params
     return Net(cfg["input"], cfg["layers"], params, n_slots, cfg["samples_per_ct"], cfg["sample_stride"],
-               fc_doubling=fc_doubling)
+               fc_doubling=fc_doubling, channel_cts=channel_cts)
 
 
 def run_encrypted(sess: OracleSession, net: Net, xs: np.ndarray, enc_seed: int = W.SEED_ENCRYPT,
                   lazy: bool = False):
     """Encrypt the packed inputs, drop to the network depth, evaluate (with
     lazy: deferred ModDown, LazyCkksEval).
-    Returns (input ciphertext, output ciphertexts, evaluator)."""
+    Returns (input ciphertext, output ciphertexts, evaluator); with the net's
+    channel_cts the input is a list of one ciphertext per channel, encrypted
+    with seeds enc_seed, enc_seed + 1000, ..."""
     ck = sess.ck
     sess.ensure_keys(net.rotation_set())
-    ct = ck.encrypt(net.input_vector(xs), enc_seed)
-    x = ck.limb_drop(ct, net.depth + 1)
+    cts = [ck.encrypt(v, enc_seed + 1000 * i) for i, v in enumerate(net.input_vectors(xs))]
+    xs_in = [ck.limb_drop(ct, net.depth + 1) for ct in cts]
     ev = (LazyCkksEval if lazy else CkksEval)(ck, sess.key_handle, sess.rlk)
-    outs = net.run(ev, [x])
-    return ct, outs, ev
+    outs = net.run(ev, xs_in)
+    return (cts if net.channel_cts else cts[0]), outs, ev
 
 
 def decrypt_outputs(sess: OracleSession, net: Net, outs) -> np.ndarray:

@@ -261,3 +261,49 @@ def test_encrypted_lenet1_fc_doubling(lazy):
     assert ev.count.rot == 274
     got = decrypt_outputs(sess, net, outs)
     assert np.abs(got - reference_outputs(net, xs)).max() < 1e-3
+
+
+# ------------------------------------------------- one ciphertext per channel
+@pytest.mark.parametrize("name", ["cifar_cnn", "m5"])
+def test_channel_cts_slot_simulation(name):
+    """Multi-channel inputs given as one ciphertext per channel (each plane
+    at offset 0) reproduce the FP64 CNN like the single-ciphertext layout."""
+    cfg = W.config(name)
+    n_slots = 2 ** (cfg["log_n"] - 1)
+    params = W.gen_params(cfg["layers"])
+    xs = W.gen_inputs(cfg["input"], 1)
+    net = Net(cfg["input"], cfg["layers"], params, n_slots, channel_cts=True)
+    ev = SlotEval(n_slots)
+    got = read_outputs(net, net.run(ev, net.input_vectors(xs)))
+    ref = np.array([cnn_fp64(x, cfg["layers"], params).reshape(-1) for x in xs])
+    assert np.abs(got - ref).max() < 1e-12
+
+
+def test_channel_cts_fit_where_one_ciphertext_cannot():
+    """3 x 32 x 32 inputs need 3072 slots in one ciphertext; at N = 2^12
+    (2048 slots) only the per-channel layout (1024 slots each) fits."""
+    cfg = W.config("cifar_cnn")
+    with pytest.raises(PlanError):
+        check_packing(cfg["input"], cfg["layers"], 2048, 1, 2048)
+    assert footprint(cfg["input"], cfg["layers"], channel_cts=True) <= 2048
+
+
+SMALL3 = ({"c": 3, "h": 12, "w": 12, "dist": "uniform01"},
+          [{"kind": "conv", "ch_in": 3, "ch_out": 2, "k": 3, "s": 1}, W.SQUARE, {"kind": "avgpool", "c": 2},
+           W.FLATTEN, {"kind": "fc", "din": 50, "dout": 4}])
+
+
+@pytest.mark.parametrize("lazy", [False, True])
+def test_encrypted_channel_cts_small(lazy):
+    """A three-channel input as three ciphertexts (N = 2^11), eager and with
+    deferred ModDown: within 1e-3 of the FP64 CNN."""
+    inp, layers = SMALL3
+    ring = dict(W.config("lenet1"), log_n=11)
+    sess = OracleSession(ring)
+    params = W.gen_params(layers)
+    xs = W.gen_inputs(inp, 1)
+    net = Net(inp, layers, params, sess.ck.slots, channel_cts=True)
+    cts, outs, _ = run_encrypted(sess, net, xs, lazy=lazy)
+    assert len(cts) == 3
+    got = read_outputs(net, [sess.ck.decrypt(o) for o in outs])
+    assert np.abs(got[0] - cnn_fp64(xs[0], layers, params).reshape(-1)).max() < 1e-3
