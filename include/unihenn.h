@@ -238,8 +238,14 @@ int unihenn_net_create(const unihenn_ctx* ctx, const unihenn_input* input, const
  *     rotation per further set bit of the copy count, floor(log2 reps) +
  *     popcount(reps) - 1 rotations instead of reps - 1 (fewer rotation keys
  *     too).  The same sum slot by slot; results differ in their last bits.
+ *   UNIHENN_PLAN_CHANNEL_CTS  a multi-channel input arrives as c ciphertexts,
+ *     channel i's (h, w) plane at offset 0 of ciphertext i (sample b at
+ *     b * stride; Section III-A lays out one channel per plane), so inputs
+ *     whose c h w exceeds a sample's slots fit; the sample footprint counts
+ *     h w for the input.  unihenn_eval_network then reads c input
+ *     descriptors.
  */
-enum { UNIHENN_PLAN_LAZY_MODDOWN = 1, UNIHENN_PLAN_FC_DOUBLING = 2 };
+enum { UNIHENN_PLAN_LAZY_MODDOWN = 1, UNIHENN_PLAN_FC_DOUBLING = 2, UNIHENN_PLAN_CHANNEL_CTS = 4 };
 /* unihenn_net_create with plan options (plan_flags, 0 = the default plan).
  * Errors: as unihenn_net_create, and EINVAL for an unknown flag. */
 int unihenn_net_create_ex(const unihenn_ctx* ctx, const unihenn_input* input, const unihenn_layer* layers,
@@ -252,6 +258,8 @@ int unihenn_net_info(const unihenn_net* net, uint32_t* depth, uint32_t* n_rotati
 /* The rotation amounts (in [1, N/2)) whose keys the evaluation needs;
  * steps (host) must hold unihenn_net_info's n_rotations entries. */
 int unihenn_net_rotations(const unihenn_net* net, int32_t* steps);
+/* Input ciphertexts per evaluation: 1, or c with UNIHENN_PLAN_CHANNEL_CTS. */
+int unihenn_net_inputs(const unihenn_net* net, uint32_t* n_inputs);
 /* Bind keys: gks[i] is the rotation key of steps[i]; rlk the key of s^2.
  * The descriptors are copied; the key memory must outlive the net's use.
  * Errors: ENOKEY if a needed rotation is missing. */
@@ -278,10 +286,11 @@ int unihenn_conv(const unihenn_ctx* ctx, unihenn_net* net, uint32_t layer, const
                  unihenn_ct* out, uint32_t* interval_out, void* stream);
 
 /* Whole network: in is a batch of input ciphertexts (at >= depth+1 limbs,
- * scale Delta); out (host array of n_outputs descriptors) receives the
- * output ciphertexts at 1 limb (buffers [batch][2][1][N]).  Uses the net's
- * workspace.  Errors: ENOKEY (keys not bound), ELEVEL, EINVAL (batch >
- * max_batch). */
+ * scale Delta), or unihenn_net_inputs' count of such descriptors (one per
+ * input channel, equal batch, limbs and scale); out (host array of
+ * n_outputs descriptors) receives the output ciphertexts at 1 limb (buffers
+ * [batch][2][1][N]).  Uses the net's workspace.  Errors: ENOKEY (keys not
+ * bound), ELEVEL, EINVAL (batch > max_batch, inputs that differ). */
 int unihenn_eval_network(const unihenn_ctx* ctx, unihenn_net* net, const unihenn_ct* in, unihenn_ct* out,
                          void* stream);
 

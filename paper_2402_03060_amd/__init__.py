@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libunihenn.so")
 OK, EINVAL, ELEVEL, ESCALE, ENOKEY, ESLOTS, ENOMEM, EDEVICE = 0, -1, -2, -3, -4, -5, -6, -7
 LAYER_CONV, LAYER_SQUARE, LAYER_AVGPOOL, LAYER_FLATTEN, LAYER_FC, LAYER_RELU_APPROX = 1, 2, 3, 4, 5, 6
 EVAL_PLAIN, EVAL_HOISTED, EVAL_GRAPH = 0, 1, 2
-PLAN_LAZY_MODDOWN, PLAN_FC_DOUBLING = 1, 2
+PLAN_LAZY_MODDOWN, PLAN_FC_DOUBLING, PLAN_CHANNEL_CTS = 1, 2, 4
 KERNEL_FAMILIES = ["ntt_fwd_col", "ntt_fwd_row", "ntt_inv_row", "ntt_inv_col", "modup", "ks_inner", "moddown",
                    "rescale", "mac", "automorphism", "tensor", "add", "encode", "other"]
 
@@ -83,6 +83,7 @@ SIGNATURES = {
     "unihenn_mod_drop": (C.c_int, [_vp, _P(CT), _u32, _P(CT), _vp]),
     "unihenn_net_create": (C.c_int, [_vp, _P(INPUT), _P(LAYER), _u32, _u32, _P(_vp)]),
     "unihenn_net_create_ex": (C.c_int, [_vp, _P(INPUT), _P(LAYER), _u32, _u32, _u32, _P(_vp)]),
+    "unihenn_net_inputs": (C.c_int, [_vp, _P(_u32)]),
     "unihenn_net_destroy": (C.c_int, [_vp]),
     "unihenn_net_info": (C.c_int, [_vp, _P(_u32), _P(_u32), _P(_u32), _P(_u32)]),
     "unihenn_net_rotations": (C.c_int, [_vp, _P(_i32)]),
@@ -410,12 +411,14 @@ class Net:
     """A planned network with its plaintexts encoded on the device."""
 
     def __init__(self, ctx: Context, inp: dict, layers, params, samples: int = 1, stride: int = 0,
-                 max_batch: int = 1, lazy: bool = False, fc_doubling: bool = False):
+                 max_batch: int = 1, lazy: bool = False, fc_doubling: bool = False, channel_cts: bool = False):
         """lazy: plan with deferred ModDown (PLAN_LAZY_MODDOWN); fc_doubling:
-        the FC's closing sum by doubling (PLAN_FC_DOUBLING)."""
+        the FC's closing sum by doubling (PLAN_FC_DOUBLING); channel_cts: one
+        input ciphertext per channel (PLAN_CHANNEL_CTS; eval takes a list)."""
         self.ctx = ctx
         self.lazy = lazy
         self.fc_doubling = fc_doubling
+        self.channel_cts = channel_cts
         self._keep = []
         arr = (LAYER * len(layers))()
         for i, (L, p) in enumerate(zip(layers, params)):
@@ -441,13 +444,17 @@ class Net:
         h = C.c_void_p()
         _check(lib().unihenn_net_create_ex(ctx.h, C.byref(ind), arr, len(layers), max_batch,
                                            (PLAN_LAZY_MODDOWN if lazy else 0) |
-                                           (PLAN_FC_DOUBLING if fc_doubling else 0), C.byref(h)))
+                                           (PLAN_FC_DOUBLING if fc_doubling else 0) |
+                                           (PLAN_CHANNEL_CTS if channel_cts else 0), C.byref(h)))
         self.h = h
         self.samples = samples
         self.max_batch = max_batch
         dep, nrot, nout, inl = C.c_uint32(), C.c_uint32(), C.c_uint32(), C.c_uint32()
         _check(lib().unihenn_net_info(h, C.byref(dep), C.byref(nrot), C.byref(nout), C.byref(inl)))
         self.depth, self.n_rot, self.n_out, self.in_limbs = dep.value, nrot.value, nout.value, inl.value
+        nin = C.c_uint32()
+        _check(lib().unihenn_net_inputs(h, C.byref(nin)))
+        self.n_inputs = nin.value
         self._bound = None
 
     def close(self):
@@ -506,10 +513,16 @@ class Net:
     def alloc_outputs(self, batch: int) -> list[Ciphertext]:
         return [self.ctx.empty_ct(batch, 1) for _ in range(self.n_out)]
 
-    def eval(self, ct: Ciphertext, outs: list[Ciphertext] | None = None, stream=None) -> list[Ciphertext]:
-        outs = self.alloc_outputs(ct.batch) if outs is None else outs
+    def eval(self, ct, outs: list[Ciphertext] | None = None, stream=None) -> list[Ciphertext]:
+        """ct: the input Ciphertext, or a list of n_inputs of them (one per
+        channel with channel_cts)."""
+        cts = list(ct) if isinstance(ct, (list, tuple)) else [ct]
+        if len(cts) != self.n_inputs:
+            raise ValueError(f"the net takes {self.n_inputs} input ciphertexts, got {len(cts)}")
+        outs = self.alloc_outputs(cts[0].batch) if outs is None else outs
         od = (CT * self.n_out)(*[o.desc() for o in outs])
-        _check(lib().unihenn_eval_network(self.ctx.h, self.h, C.byref(ct.desc()), od, _stream(stream)))
+        ia = (CT * len(cts))(*[c.desc() for c in cts])
+        _check(lib().unihenn_eval_network(self.ctx.h, self.h, ia, od, _stream(stream)))
         for o, d in zip(outs, od):
             o.scale = d.scale
         return outs

@@ -165,6 +165,7 @@ void net_drop_graphs(unihenn_net* net);
 int net_max_batch(const unihenn_net* net);
 int net_in_limbs(const unihenn_net* net);
 int net_n_out(const unihenn_net* net);
+int net_n_inputs(const unihenn_net* net);
 int net_mode(const unihenn_net* net);
 void net_set_mode_raw(unihenn_net* net, int mode);
 uint64_t net_fingerprint(const unihenn_net* net);

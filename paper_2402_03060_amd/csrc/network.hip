@@ -58,6 +58,7 @@ struct Step {
     // ST_MACM: outs[o] (+)= sum_t pt(o, t) (*) srcs[t], pt(o, t) at pt + (o * pt_ostride + pt_toff + t) * nl * N
     std::vector<int> outs, srcs;
     int pt_ostride = 0, pt_toff = 0;
+    int in_idx = 0;  // ST_DROP: which network input
 };
 
 struct PtRequest {
@@ -113,6 +114,7 @@ struct unihenn_net {
     std::vector<uint64_t> out_slots;
     int n_values = 0;
     int input_reg = -1;
+    int n_inputs = 1;  // input ciphertexts per evaluation (C with UNIHENN_PLAN_CHANNEL_CTS)
     std::vector<PtRequest> requests;
     size_t pt_words = 0;
     // device
@@ -133,7 +135,7 @@ struct unihenn_net {
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
     struct GraphEntry {
         int batch = 0, in_limbs = 0, mode = -1;
-        const u64* in = nullptr;
+        std::vector<const u64*> in;
         std::vector<u64*> outs;
         size_t key_version = 0;
         hipGraphExec_t exec = nullptr;
@@ -804,12 +806,14 @@ struct Planner {
 
 // Slots one packed sample needs (Section VI): the largest extent of the
 // slots holding its valid values or read by a valid output, the flatten
-// output C H W, and the FC width DAT_out ceil(DAT_in / DAT_out).
-int footprint(const unihenn_input& in, const unihenn_layer* ls, int n, long* out)
+// output C H W, and the FC width DAT_out ceil(DAT_in / DAT_out); with
+// channel_cts the input holds one H x W plane per ciphertext.
+int footprint(const unihenn_input& in, const unihenn_layer* ls, int n, long* out, bool channel_cts)
 {
-    long need = (long)in.c * in.h * in.w;
+    // one ciphertext per channel: each holds one H x W plane at offset 0
+    long need = (long)(channel_cts ? 1 : in.c) * in.h * in.w;
     int C = (int)in.c, H = (int)in.h, W = (int)in.w, I = 1, Wimg = (int)in.w;
-    long max_off = (long)(in.c - 1) * in.h * in.w;
+    long max_off = channel_cts ? 0 : (long)(in.c - 1) * in.h * in.w;
     bool vec = false;
     for (int l = 0; l < n; ++l) {
         const unihenn_layer& L = ls[l];
@@ -1055,8 +1059,9 @@ extern "C" int unihenn_net_create_ex(const unihenn_ctx* c, const unihenn_input* 
                                      uint32_t n_layers, uint32_t max_batch, uint32_t plan_flags, unihenn_net** out)
 {
     if (!c || !in || !out || (n_layers && !layers)) return uh_fail(UNIHENN_EINVAL, "null argument");
-    if (plan_flags & ~(uint32_t)(UNIHENN_PLAN_LAZY_MODDOWN | UNIHENN_PLAN_FC_DOUBLING))
+    if (plan_flags & ~(uint32_t)(UNIHENN_PLAN_LAZY_MODDOWN | UNIHENN_PLAN_FC_DOUBLING | UNIHENN_PLAN_CHANNEL_CTS))
         return uh_fail(UNIHENN_EINVAL, "unknown plan flag");
+    const bool channel_cts = (plan_flags & UNIHENN_PLAN_CHANNEL_CTS) != 0;
     if (in->c < 1 || in->h < 1 || in->w < 1 || in->samples < 1 || max_batch < 1)
         return uh_fail(UNIHENN_EINVAL, "empty input shape, sample count or batch");
     for (uint32_t l = 0; l < n_layers; ++l)
@@ -1069,7 +1074,7 @@ extern "C" int unihenn_net_create_ex(const unihenn_ctx* c, const unihenn_input* 
     net->samples = (int)in->samples;
     net->max_batch = (int)max_batch;
     long fp = 0;
-    if (footprint(*in, layers, (int)n_layers, &fp)) {
+    if (footprint(*in, layers, (int)n_layers, &fp, channel_cts)) {
         delete net;
         return uh_fail(UNIHENN_EINVAL, "layer shapes do not chain");
     }
@@ -1098,13 +1103,18 @@ extern "C" int unihenn_net_create_ex(const unihenn_ctx* c, const unihenn_input* 
     Planner P{net, c, c->scale, {}, "", 0};
     P.lazy = net->lazy;
     P.fc_doubling = (plan_flags & UNIHENN_PLAN_FC_DOUBLING) != 0;
-    net->input_reg = P.newreg(net->in_limbs, c->scale);
-    {
+    // the inputs, reduced to depth + 1 limbs: one ciphertext, or one per channel
+    net->n_inputs = channel_cts ? (int)in->c : 1;
+    std::vector<int> input_regs;
+    for (int i = 0; i < net->n_inputs; ++i) {
+        input_regs.push_back(P.newreg(net->in_limbs, c->scale));
         Step s;
         s.kind = ST_DROP;
-        s.dst = net->input_reg;
+        s.dst = input_regs.back();
+        s.in_idx = i;
         net->steps.push_back(s);
     }
+    net->input_reg = input_regs[0];
     Layout L;
     L.C = (int)in->c;
     L.H = (int)in->h;
@@ -1112,8 +1122,8 @@ extern "C" int unihenn_net_create_ex(const unihenn_ctx* c, const unihenn_input* 
     L.I = 1;
     L.W_img = (int)in->w;
     for (uint32_t ch = 0; ch < in->c; ++ch) {
-        L.ch_reg.push_back(net->input_reg);
-        L.ch_off.push_back((int)(ch * in->h * in->w));
+        L.ch_reg.push_back(channel_cts ? input_regs[ch] : net->input_reg);
+        L.ch_off.push_back(channel_cts ? 0 : (int)(ch * in->h * in->w));
     }
     for (uint32_t l = 0; l < n_layers; ++l) {
         LayerRecord rec;
@@ -1210,6 +1220,13 @@ extern "C" int unihenn_net_info(const unihenn_net* net, uint32_t* depth, uint32_
     return UNIHENN_OK;
 }
 
+extern "C" int unihenn_net_inputs(const unihenn_net* net, uint32_t* n_inputs)
+{
+    if (!net || !n_inputs) return uh_fail(UNIHENN_EINVAL, "null argument");
+    *n_inputs = (uint32_t)net->n_inputs;
+    return UNIHENN_OK;
+}
+
 extern "C" int unihenn_net_rotations(const unihenn_net* net, int32_t* steps)
 {
     if (!net || !steps) return uh_fail(UNIHENN_EINVAL, "null argument");
@@ -1266,7 +1283,7 @@ struct Exec {
     hipStream_t s;
     std::map<int, u64*> bound;  // registers bound to caller buffers
     int modup_owner = -1;       // register whose digits the workspace holds
-    const u64* ext_in = nullptr;
+    std::vector<const u64*> ext_in;  // network inputs (ST_DROP sources), all at ext_in_limbs
     int ext_in_limbs = 0;
 
     u64* reg(int r)
@@ -1422,7 +1439,7 @@ struct Exec {
             const int pl = ext ? nl : -1;
             switch (st.kind) {
             case ST_DROP:
-                launch_gather_rows(c, reg(st.dst), ext_in, B * 2 * nl, nl, ext_in_limbs, 0, s);
+                launch_gather_rows(c, reg(st.dst), ext_in.at(st.in_idx), B * 2 * nl, nl, ext_in_limbs, 0, s);
                 break;
             case ST_ROT: {
                 // a run of consecutive rotations at this level, none reading another's result
@@ -1636,6 +1653,13 @@ extern "C" int unihenn_eval_network(const unihenn_ctx* c, unihenn_net* net, cons
     if ((int)in->n_limbs < net->in_limbs) return uh_fail(UNIHENN_ELEVEL, "input has fewer limbs than the depth needs");
     if ((int)in->n_limbs > c->n_data) return uh_fail(UNIHENN_ELEVEL, "bad input limb count");
     if (in->scale != c->scale) return uh_fail(UNIHENN_ESCALE, "input scale differs from the encoding scale");
+    std::vector<const u64*> ins;
+    for (int i = 0; i < net->n_inputs; ++i) {
+        if (!in[i].data) return uh_fail(UNIHENN_EINVAL, "null input " + std::to_string(i));
+        if (in[i].batch != in->batch || in[i].n_limbs != in->n_limbs || in[i].scale != in->scale)
+            return uh_fail(UNIHENN_EINVAL, "input " + std::to_string(i) + " differs in batch, limbs or scale");
+        ins.push_back(in[i].data);
+    }
     int rc = check_keys(net);
     if (rc) return rc;
     for (size_t i = 0; i < net->out_regs.size(); ++i)
@@ -1643,7 +1667,7 @@ extern "C" int unihenn_eval_network(const unihenn_ctx* c, unihenn_net* net, cons
     const bool graph = (net->mode & UNIHENN_EVAL_GRAPH) && !stats_enabled();
     hipStream_t cs = (hipStream_t)stream;
     if (!graph) {
-        Exec ex{net, c, (int)in->batch, cs, {}, -1, in->data, (int)in->n_limbs};
+        Exec ex{net, c, (int)in->batch, cs, {}, -1, ins, (int)in->n_limbs};
         for (size_t i = 0; i < net->out_regs.size(); ++i) ex.bound[net->out_regs[i]] = out[i].data;
         rc = ex.run(0, net->steps.size());
         if (rc) return rc;
@@ -1657,7 +1681,7 @@ extern "C" int unihenn_eval_network(const unihenn_ctx* c, unihenn_net* net, cons
         for (size_t i = 0; i < net->out_regs.size(); ++i) outs.push_back(out[i].data);
         unihenn_net::GraphEntry* hit = nullptr;
         for (auto& g : net->graphs)
-            if (g.exec && g.batch == (int)in->batch && g.in == in->data && g.in_limbs == (int)in->n_limbs &&
+            if (g.exec && g.batch == (int)in->batch && g.in == ins && g.in_limbs == (int)in->n_limbs &&
                 g.outs == outs && g.mode == net->mode && g.key_version == net->key_version)
                 hit = &g;
         if (!hit) {
@@ -1672,7 +1696,7 @@ extern "C" int unihenn_eval_network(const unihenn_ctx* c, unihenn_net* net, cons
                 if (hit->exec) (void)hipGraphExecDestroy(hit->exec);
                 hit->exec = nullptr;
             }
-            Exec ex{net, c, (int)in->batch, net->gstream, {}, -1, in->data, (int)in->n_limbs};
+            Exec ex{net, c, (int)in->batch, net->gstream, {}, -1, ins, (int)in->n_limbs};
             for (size_t i = 0; i < net->out_regs.size(); ++i) ex.bound[net->out_regs[i]] = out[i].data;
             UH_CHECK_HIP(hipStreamBeginCapture(net->gstream, hipStreamCaptureModeThreadLocal));
             int rc2 = ex.run(0, net->steps.size());
@@ -1690,7 +1714,7 @@ extern "C" int unihenn_eval_network(const unihenn_ctx* c, unihenn_net* net, cons
                 return uh_fail(UNIHENN_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
             }
             hit->batch = (int)in->batch;
-            hit->in = in->data;
+            hit->in = ins;
             hit->in_limbs = (int)in->n_limbs;
             hit->outs = outs;
             hit->mode = net->mode;
@@ -1734,7 +1758,7 @@ extern "C" int unihenn_conv(const unihenn_ctx* c, unihenn_net* net, uint32_t lay
     }
     int rc = check_keys(net);
     if (rc) return rc;
-    Exec ex{net, c, B, (hipStream_t)stream, {}, -1, nullptr, 0};
+    Exec ex{net, c, B, (hipStream_t)stream, {}, -1, {}, 0};
     for (uint32_t i = 0; i < n_in; ++i) ex.bound[uniq[i]] = in[i].data;
     for (size_t o = 0; o < L.out_regs.size(); ++o) {
         if (!out[o].data) return uh_fail(UNIHENN_EINVAL, "null output buffer");
@@ -1789,6 +1813,7 @@ void net_drop_graphs(unihenn_net* net) { drop_graphs(net); }
 int net_max_batch(const unihenn_net* net) { return net->max_batch; }
 int net_in_limbs(const unihenn_net* net) { return net->in_limbs; }
 int net_n_out(const unihenn_net* net) { return (int)net->out_regs.size(); }
+int net_n_inputs(const unihenn_net* net) { return net->n_inputs; }
 int net_mode(const unihenn_net* net) { return net->mode; }
 void net_set_mode_raw(unihenn_net* net, int mode) { net->mode = mode; }
 

@@ -92,11 +92,12 @@ int time_ntt(unihenn_ctx* c, u64* data, int rows, hipStream_t s, double* ms)
 int time_net(unihenn_ctx* c, unihenn_net* net, int batch, u64* in, u64* outs, hipStream_t s, double* ms)
 {
     const int nl = net_in_limbs(net), no = net_n_out(net);
-    unihenn_ct cin{in, (uint32_t)nl, (uint32_t)batch, c->scale};
+    // every network input reads the same (zero) buffer
+    std::vector<unihenn_ct> cin((size_t)net_n_inputs(net), unihenn_ct{in, (uint32_t)nl, (uint32_t)batch, c->scale});
     std::vector<unihenn_ct> co(no);
     for (int o = 0; o < no; ++o) co[o] = unihenn_ct{outs + (size_t)o * batch * 2 * c->n, 1, (uint32_t)batch, 0.0};
     net_drop_graphs(net);
-    return time_ms(s, 0, [&]() { return unihenn_eval_network(c, net, &cin, co.data(), s); }, ms);
+    return time_ms(s, 0, [&]() { return unihenn_eval_network(c, net, cin.data(), co.data(), s); }, ms);
 }
 
 // ---- cache file: one JSON object, one entry per line

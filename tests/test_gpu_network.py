@@ -344,3 +344,49 @@ def test_autotune_keeps_results_and_caches(tmp_path):
     for k in ("ntt_split", "ntt_tile_log", "mac_min_wg", "ks_min_wg", "ks_group", "ks_order"):
         assert now[k] == first[k], k
     check("cached")
+
+
+def _channel_parity(cfg, inp, layers, params, lazy):
+    import paper_2402_03060_amd as P
+    from oracle.network import Net as ONet
+    sess = OracleSession(cfg)
+    onet = ONet(inp, layers, params, sess.ck.slots, channel_cts=True)
+    xs = W.gen_inputs(inp, 1)
+    cts, outs, _ = run_encrypted(sess, onet, xs, lazy=lazy)
+    ctx = _ctx(P, cfg)
+    gnet = P.Net(ctx, inp, layers, params, max_batch=1, lazy=lazy, channel_cts=True)
+    assert gnet.n_inputs == inp["c"] and gnet.depth == onet.depth
+    assert sorted(gnet.rotations()) == onet.rotation_set()
+    keys = {r: ctx.import_evk(sess.key_coeff[r]) for r in gnet.rotations()}
+    gnet.bind_keys(keys, ctx.import_evk(sess.rlk_coeff))
+    gins = [ctx.import_ct(c.data[None], c.scale) for c in cts]
+    for mode in (P.EVAL_PLAIN, P.EVAL_HOISTED, P.EVAL_HOISTED | P.EVAL_GRAPH):
+        gnet.set_mode(mode)
+        got = [ctx.export_ct(o)[0] for o in gnet.eval(gins)]
+        for g, e in zip(got, outs):
+            assert np.array_equal(g, e.data), mode
+    with pytest.raises(ValueError):
+        gnet.eval(gins[0])
+
+
+@pytest.mark.parametrize("lazy", [False, True])
+def test_channel_cts_small_bit_exact(lazy):
+    """A three-channel input as three ciphertexts (PLAN_CHANNEL_CTS) at
+    N = 2^11, default and deferred-ModDown plans."""
+    inp = {"c": 3, "h": 12, "w": 12, "dist": "uniform01"}
+    layers = [{"kind": "conv", "ch_in": 3, "ch_out": 2, "k": 3, "s": 1}, W.SQUARE, {"kind": "avgpool", "c": 2},
+              W.FLATTEN, {"kind": "fc", "din": 50, "dout": 4}]
+    _channel_parity(dict(W.config("lenet1"), log_n=11), inp, layers, W.gen_params(layers), lazy)
+
+
+def test_channel_cts_cifar_shape_where_one_ciphertext_cannot():
+    """The CIFAR-shaped CNN at N = 2^12: 3 x 32 x 32 does not fit 2048 slots
+    in one ciphertext, it does as three (one plane each)."""
+    import paper_2402_03060_amd as P
+    cfg = W.config("cifar_cnn")
+    cfg["log_n"] = 12
+    params = W.gen_params(cfg["layers"])
+    ctx = _ctx(P, cfg)
+    with pytest.raises(P.UnihennError):
+        P.Net(ctx, cfg["input"], cfg["layers"], params, max_batch=1)
+    _channel_parity(cfg, cfg["input"], cfg["layers"], params, False)
