@@ -43,7 +43,7 @@ TUNING_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_2
 
 
 def setup(P, W, name: str, batch: int, seed: int = 5, tune: bool = True, mode: int = 0, log_n: int | None = None,
-          lazy: bool = False, fc_doubling: bool = False):
+          lazy: bool = False, fc_doubling: bool = False, channel_cts: bool = False):
     import torch
     cfg = W.config(name)
     if log_n is not None:
@@ -52,15 +52,24 @@ def setup(P, W, name: str, batch: int, seed: int = 5, tune: bool = True, mode: i
     params = W.gen_params(cfg["layers"])
     S, stride = cfg["samples_per_ct"], cfg["sample_stride"]
     net = P.Net(ctx, cfg["input"], cfg["layers"], params, samples=S, stride=stride, max_batch=batch, lazy=lazy,
-                fc_doubling=fc_doubling)
+                fc_doubling=fc_doubling, channel_cts=channel_cts)
     sk = P.keygen_secret(ctx, seed)
     keys = {r: P.gen_switch_key(ctx, sk, seed + 1, steps=r) for r in net.rotations()}
     rlk = P.gen_switch_key(ctx, sk, seed + 2, relin=True)
     net.bind_keys(keys, rlk)
     xs = W.gen_inputs(cfg["input"], S * batch)
-    pts = [ctx.encode(_pack(cfg["input"], xs[b * S:(b + 1) * S], ctx.slots, stride if S > 1 else ctx.slots),
-                      ctx.scale, net.in_limbs, mont=False) for b in range(batch)]
-    ct = P.encrypt_sk(ctx, sk, torch.stack(pts), seed + 3, ctx.scale)
+    st = stride if S > 1 else ctx.slots
+    if channel_cts:
+        # one ciphertext batch per channel: channel c's planes of the samples
+        ct = []
+        for c in range(cfg["input"]["c"]):
+            pts = [ctx.encode(_pack(cfg["input"], xs[b * S:(b + 1) * S, c], ctx.slots, st), ctx.scale,
+                              net.in_limbs, mont=False) for b in range(batch)]
+            ct.append(P.encrypt_sk(ctx, sk, torch.stack(pts), seed + 3 + c, ctx.scale))
+    else:
+        pts = [ctx.encode(_pack(cfg["input"], xs[b * S:(b + 1) * S], ctx.slots, st), ctx.scale, net.in_limbs,
+                          mont=False) for b in range(batch)]
+        ct = P.encrypt_sk(ctx, sk, torch.stack(pts), seed + 3, ctx.scale)
     torch.cuda.synchronize()
     net.set_mode(mode)
     tuning = net.autotune(batch, cache_path=TUNING_CACHE) if tune else net.tuning()
@@ -71,7 +80,8 @@ def setup(P, W, name: str, batch: int, seed: int = 5, tune: bool = True, mode: i
 def max_error(P, W, st) -> float:
     """Decrypt every sample's outputs and compare with a direct FP64 CNN."""
     cfg, ctx, net = st["cfg"], st["ctx"], st["net"]
-    S, B = cfg["samples_per_ct"], st["ct"].batch
+    S = cfg["samples_per_ct"]
+    B = (st["ct"][0] if isinstance(st["ct"], list) else st["ct"]).batch
     pos = net.output_slots()                     # [S][values]: (ciphertext << 32) | slot
     ids = pos >> np.uint64(32)
     slots = (pos & np.uint64(0xFFFFFFFF)).astype(np.uint32)
@@ -329,11 +339,13 @@ def cpu_baseline(W) -> dict:
 # The paper's own single-inference times (seconds; SEAL on one Xeon Gold 5220
 # core, scale 2^32, trained models): context only, different parameters.
 PAPER_MODEL_SECONDS = {"m1": 16.247, "m3": 29.105, "m4": 740.128, "m6": 12.309, "m7": 5.119}
-MODEL_NAMES = ["m1", "m3", "m4", "m5", "m6", "m7"]
+MODEL_NAMES = ["m1", "m3", "m4", "m5", "m6", "m7", "cifar_cnn"]
 # M5 at N = 2^15 would hold ~150 GB of plaintexts (90,691 weights of its
 # 64 -> 128 convolution, most on a few valid slots); it runs at N = 2^13, the
 # smallest ring whose slots hold a 3 x 32 x 32 input
 MODEL_LOG_N = {"m5": 13}
+# multi-channel workloads also measured with one input ciphertext per channel
+CHANNEL_CT_MODELS = ["cifar_cnn", "m5"]
 
 
 def models_bench(P, W, steps: int = 3) -> dict:
@@ -354,6 +366,18 @@ def models_bench(P, W, steps: int = 3) -> dict:
                      "rotation_keys": len(net.rotations()), "desc": cfg["desc"]}
         if name in PAPER_MODEL_SECONDS:
             out[name]["paper_cpu_seconds"] = PAPER_MODEL_SECONDS[name]
+        del st, net, ct, outs
+        torch.cuda.empty_cache()
+    for name in CHANNEL_CT_MODELS:
+        print(f"[bench] model {name}, one input ciphertext per channel", file=sys.stderr, flush=True)
+        st = setup(P, W, name, batch=1, mode=P.EVAL_PLAIN | P.EVAL_GRAPH, log_n=MODEL_LOG_N.get(name),
+                   channel_cts=True)
+        net, ct, outs = st["net"], st["ct"], st["outs"]
+        dt = timed(lambda: net.eval(ct, outs), steps, 1)
+        out[name + "_channel_cts"] = {"inferences_per_s": round(steps / dt, 3),
+                                      "ms_per_inference": round(1e3 * dt / steps, 2),
+                                      "max_abs_err_vs_fp64": max_error(P, W, st), "log_n": st["cfg"]["log_n"],
+                                      "input_ciphertexts": net.n_inputs, "rotation_keys": len(net.rotations())}
         del st, net, ct, outs
         torch.cuda.empty_cache()
     return out
