@@ -175,8 +175,23 @@ int unihenn_square_relin(const unihenn_ctx* ctx, const unihenn_ct* in, const uni
 int unihenn_add(const unihenn_ctx* ctx, const unihenn_ct* a, const unihenn_ct* b, unihenn_ct* out, void* stream);
 int unihenn_add_plain(const unihenn_ctx* ctx, const unihenn_ct* a, const uint64_t* pt, unihenn_ct* out,
                       void* stream);
+/* Drop-Level as Section IV-A states it: the input (n_limbs = l + 1) is
+ * multiplied by n_ones encryptions of all-ones vectors, each product
+ * relinearised (unihenn_mul_relin) and rescaled (unihenn_rescale), so out
+ * has n_limbs - n_ones limbs.  ones[k] (host array of descriptors) must
+ * share the input's batch and hold at least n_limbs - k limbs (it is used
+ * dropped to its product's level).  out->scale = in.scale * prod_k
+ * ones[k].scale / q_(n_limbs-1-k); all-ones vectors encrypted at scale
+ * q_(n_limbs-1-k) keep the input scale exactly.  ws: at least
+ * unihenn_drop_level_workspace_size(n_limbs, batch) bytes.  out may alias
+ * no operand.  Errors: ELEVEL (n_ones outside 1 .. n_limbs - 1, short
+ * operands), EINVAL, ENOKEY. */
+size_t unihenn_drop_level_workspace_size(const unihenn_ctx* ctx, uint32_t n_limbs, uint32_t batch);
+int unihenn_drop_level(const unihenn_ctx* ctx, const unihenn_ct* in, const unihenn_ct* ones, uint32_t n_ones,
+                       const unihenn_evk* rlk, unihenn_ct* out, void* ws, size_t ws_bytes, void* stream);
 /* Drop-Level (Section IV-A) read as discarding the top limbs: copy the first
- * n_limbs_out limbs of each polynomial into out. */
+ * n_limbs_out limbs of each polynomial into out; exact and free (the
+ * network's input reduction). */
 int unihenn_mod_drop(const unihenn_ctx* ctx, const unihenn_ct* in, uint32_t n_limbs_out, unihenn_ct* out,
                      void* stream);
 

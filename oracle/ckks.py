@@ -414,6 +414,15 @@ class OracleCKKS:
             raise ValueError("key level")
         return Ciphertext(out, a.scale * b.scale)
 
+    def drop_level(self, ct: Ciphertext, ones: list, rlk) -> Ciphertext:
+        """Drop-Level of Section IV-A as written: multiply by encryptions of
+        all-ones vectors, one per level to drop, each product relinearised
+        and rescaled (the all-ones ciphertext dropped to its product's level)."""
+        x = ct
+        for o in ones:
+            x = self.rescale(self.mul_relin(x, self.limb_drop(o, x.nl), rlk))
+        return x
+
     def rescale(self, ct: Ciphertext) -> Ciphertext:
         nl = ct.nl
         if nl < 2:

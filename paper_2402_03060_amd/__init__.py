@@ -77,6 +77,8 @@ SIGNATURES = {
     "unihenn_mul_plain_acc": (C.c_int, [_vp, _P(CT), _P(_vp), _u32, C.c_int, _P(CT), _vp]),
     "unihenn_rescale": (C.c_int, [_vp, _P(CT), _P(CT), _vp, _sz, _vp]),
     "unihenn_square_relin": (C.c_int, [_vp, _P(CT), _P(EVK), _P(CT), _vp, _sz, _vp]),
+    "unihenn_drop_level_workspace_size": (C.c_size_t, [_vp, _u32, _u32]),
+    "unihenn_drop_level": (C.c_int, [_vp, _P(CT), _P(CT), _u32, _P(EVK), _P(CT), _vp, C.c_size_t, _vp]),
     "unihenn_mul_relin": (C.c_int, [_vp, _P(CT), _P(CT), _P(EVK), _P(CT), _vp, _sz, _vp]),
     "unihenn_add": (C.c_int, [_vp, _P(CT), _P(CT), _P(CT), _vp]),
     "unihenn_add_plain": (C.c_int, [_vp, _P(CT), _vp, _P(CT), _vp]),
@@ -339,6 +341,20 @@ class Context:
         o = out.desc()
         _check(lib().unihenn_add_plain(self.h, C.byref(a.desc()), pt.data_ptr(), C.byref(o), _stream()))
         out.scale = o.scale
+        return out
+
+    def drop_level(self, a: Ciphertext, ones: list[Ciphertext], rlk: torch.Tensor) -> Ciphertext:
+        """Drop-Level of Section IV-A as written: len(ones) products with
+        encryptions of all-ones vectors, each relinearised and rescaled."""
+        out = self.empty_ct(a.batch, a.n_limbs - len(ones))
+        o = out.desc()
+        oa = (CT * len(ones))(*[x.desc() for x in ones])
+        nbytes = lib().unihenn_drop_level_workspace_size(self.h, a.n_limbs, a.batch)
+        ws = torch.empty(max(nbytes // 8, 1), dtype=torch.int64, device="cuda")
+        _check(lib().unihenn_drop_level(self.h, C.byref(a.desc()), oa, len(ones), C.byref(self.evk(rlk)),
+                                        C.byref(o), ws.data_ptr(), nbytes, _stream()))
+        out.scale = o.scale
+        self._last_drop_ws = ws  # kept until the next call: the launches are asynchronous
         return out
 
     def mod_drop(self, a: Ciphertext, n_limbs: int) -> Ciphertext:

@@ -327,6 +327,63 @@ extern "C" int unihenn_mul_relin(const unihenn_ctx* c, const unihenn_ct* a, cons
     return UNIHENN_OK;
 }
 
+extern "C" size_t unihenn_drop_level_workspace_size(const unihenn_ctx* c, uint32_t n_limbs, uint32_t batch)
+{
+    if (!c) return 0;
+    return (ks_ws_rows((int)n_limbs, (int)batch) + (size_t)4 * batch * n_limbs) * c->n * sizeof(u64);
+}
+
+// Drop-Level as Section IV-A states it: n_ones products with encryptions of
+// all-ones vectors, each relinearised and rescaled (one level each).  The
+// workspace holds the key-switch scratch, the product t and the running
+// value x, which alternate so that no launch reads what it writes.
+extern "C" int unihenn_drop_level(const unihenn_ctx* c, const unihenn_ct* in, const unihenn_ct* ones,
+                                  uint32_t n_ones, const unihenn_evk* rlk, unihenn_ct* out, void* ws, size_t ws_bytes,
+                                  void* stream)
+{
+    int rc = rotate_checks(c, in, out);
+    if (rc) return rc;
+    if (n_ones < 1 || n_ones >= in->n_limbs) return uh_fail(UNIHENN_ELEVEL, "drop count must be in 1 .. limbs - 1");
+    if (!ones) return uh_fail(UNIHENN_EINVAL, "null all-ones ciphertexts");
+    const int nl0 = (int)in->n_limbs, B = (int)in->batch;
+    for (uint32_t k = 0; k < n_ones; ++k) {
+        if ((rc = check_ct(c, &ones[k], "all-ones ciphertext"))) return rc;
+        if ((int)ones[k].batch != B) return uh_fail(UNIHENN_EINVAL, "all-ones ciphertext of another batch size");
+        if ((int)ones[k].n_limbs < nl0 - (int)k)
+            return uh_fail(UNIHENN_ELEVEL, "all-ones ciphertext " + std::to_string(k) + " below its product's level");
+        if (ones[k].data == out->data) return uh_fail(UNIHENN_EINVAL, "output aliases an all-ones ciphertext");
+    }
+    if ((rc = check_key(c, rlk, nl0))) return rc;
+    const size_t need = unihenn_drop_level_workspace_size(c, (uint32_t)nl0, (uint32_t)B);
+    if (!ws || ws_bytes < need) return uh_fail(UNIHENN_EINVAL, "workspace too small: need " + std::to_string(need) + " bytes");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t rn = (size_t)c->n;
+    u64* base = (u64*)ws;
+    u64* t = base + ks_ws_rows(nl0, B) * rn;       // [B][2][nl] product
+    u64* x = t + (size_t)2 * B * nl0 * rn;         // [B][2][nl - 1] running value
+    const u64* cur = in->data;
+    double scale = in->scale;
+    for (uint32_t k = 0; k < n_ones; ++k) {
+        const int nl = nl0 - (int)k;
+        KsWs w = ks_ws_carve(base, nl, B, c->n);
+        u64* d0 = w.aux;
+        u64* d1 = w.aux + (size_t)B * nl * rn;
+        u64* d2 = w.aux + (size_t)2 * B * nl * rn;
+        launch_tensor_mul(c, d0, d1, d2, cur, ones[k].data, (int)ones[k].n_limbs, B, nl, s);
+        ks_modup(c, d2, nl, B, nl, w, s);
+        ks_finish(c, d2, nl, rlk->data, c->n_data, B, nl, 1, t, d0, d1, nl, w, s);
+        u64* dst = k + 1 == n_ones ? out->data : x;
+        rescale_core(c, t, B, nl, dst, w, s);
+        cur = dst;
+        scale = scale * ones[k].scale / (double)c->primes[nl - 1];
+    }
+    out->n_limbs = in->n_limbs - n_ones;
+    out->batch = in->batch;
+    out->scale = scale;
+    UH_LAUNCH_CHECK();
+    return UNIHENN_OK;
+}
+
 extern "C" int unihenn_square_relin(const unihenn_ctx* c, const unihenn_ct* in, const unihenn_evk* rlk,
                                     unihenn_ct* out, void* ws, size_t ws_bytes, void* stream)
 {

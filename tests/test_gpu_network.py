@@ -9,7 +9,7 @@ import pytest
 
 import workloads as W
 from oracle.network import input_layout, read_outputs
-from oracle.run import OracleSession, build_net, reference_outputs, run_encrypted
+from oracle.run import OracleSession, build_net, decrypt_outputs, reference_outputs, run_encrypted
 
 pytestmark = pytest.mark.gpu
 
@@ -390,3 +390,39 @@ def test_channel_cts_cifar_shape_where_one_ciphertext_cannot():
     with pytest.raises(P.UnihennError):
         P.Net(ctx, cfg["input"], cfg["layers"], params, max_batch=1)
     _channel_parity(cfg, cfg["input"], cfg["layers"], params, False)
+
+
+def test_literal_drop_level_feeds_the_network():
+    """A LeNet-1 input encrypted on a longer chain (10 data primes, N = 2^11)
+    is brought to the network's 8 limbs by Drop-Level as written (two
+    products with encrypted all-ones vectors); the network's outputs equal
+    the oracle's on its own dropped input, bit for bit."""
+    import paper_2402_03060_amd as P
+    from oracle.network import CkksEval
+    cfg = W.config("lenet1")
+    cfg["log_n"] = 11
+    cfg["prime_bits"] = [60] + [40] * 9
+    sess = OracleSession(cfg)
+    ck = sess.ck
+    onet = build_net(cfg, ck.slots)
+    sess.ensure_keys(onet.rotation_set())
+    xs = W.gen_inputs(cfg["input"], 1)
+    ct = ck.encrypt(onet.input_vector(xs), 81)
+    nl = ck.n_data
+    ones = [ck.encrypt_pt(ck.encode(np.ones(ck.slots), float(ck.primes[nl - 1 - k]), nl), 82 + k,
+                          float(ck.primes[nl - 1 - k])) for k in range(2)]
+    dropped = ck.drop_level(ct, ones, sess.rlk)
+    assert dropped.nl == onet.depth + 1 and dropped.scale == ct.scale
+    exp = onet.run(CkksEval(ck, sess.key_handle, sess.rlk), [dropped])
+    ctx = _ctx(P, cfg)
+    g_rlk = ctx.import_evk(sess.rlk_coeff)
+    g_drop = ctx.drop_level(ctx.import_ct(ct.data, ct.scale), [ctx.import_ct(o.data, o.scale) for o in ones], g_rlk)
+    assert np.array_equal(ctx.export_ct(g_drop)[0], dropped.data)
+    gnet = _gpu_net(P, ctx, cfg, sess, onet)
+    for mode in (P.EVAL_PLAIN, P.EVAL_HOISTED):
+        gnet.set_mode(mode)
+        got = [ctx.export_ct(o)[0] for o in gnet.eval(g_drop)]
+        for g, e in zip(got, exp):
+            assert np.array_equal(g, e.data), mode
+    got = decrypt_outputs(sess, onet, exp)
+    assert np.abs(got - reference_outputs(onet, xs)).max() < 1e-3

@@ -201,3 +201,26 @@ def test_mod_drop(pair):
     a = random_ct(ck, nl, 71, batch=2)
     got = ctx.export_ct(ctx.mod_drop(ctx.import_ct(a, 1.0), 1))
     assert np.array_equal(got, a[:, :, :1, :])
+
+
+def test_drop_level_parity(pair):
+    """Drop-Level by encrypted all-ones vectors (Section IV-A as written):
+    every limb count it can drop, bit for bit against the oracle's products
+    and rescales; ones at scale q_l keep the scale exactly."""
+    ck, ctx, _ = pair
+    nl = len(ck.primes)
+    z = W.gen_slots(ck.slots, 1, seed=71)[0]
+    ct = ck.encrypt(z, 72)
+    rk = ck.relin_key()
+    rlk, g_rlk = ck.load_key(rk), ctx.import_evk(rk)
+    ones = []
+    for k in range(nl - 1):
+        q = float(ck.primes[nl - 1 - k])
+        ones.append(ck.encrypt_pt(ck.encode(np.ones(ck.slots), q, nl), 73 + k, q))
+    g_in = ctx.import_ct(ct.data, ct.scale)
+    g_ones = [ctx.import_ct(o.data, o.scale) for o in ones]
+    for n in range(1, nl):
+        exp = ck.drop_level(ct, ones[:n], rlk)
+        got = ctx.drop_level(g_in, g_ones[:n], g_rlk)
+        assert np.array_equal(ctx.export_ct(got)[0], exp.data), n
+        assert got.n_limbs == nl - n and got.scale == exp.scale == ct.scale

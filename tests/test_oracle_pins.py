@@ -336,3 +336,21 @@ def test_paper_facts():
     v = net.input_vector(np.ones((3, 1, 1, 784)))
     for i in range(1, 4):
         assert v[(i - 1) * ex["stride"]] == 1.0 and v[(i - 1) * ex["stride"] + 784] == 0.0
+
+
+def test_drop_level_by_encrypted_ones(mid):
+    """Drop-Level as Section IV-A writes it: two products with encryptions of
+    all-ones vectors take a 4-limb ciphertext to 2 limbs; with the ones at
+    scale q_l (the prime each rescale divides by) the scale is unchanged
+    exactly, and the slots decrypt to the input's."""
+    z = W.gen_slots(mid.slots, 1, seed=61)[0]
+    ct = mid.encrypt(z, 62)
+    rlk = mid.load_key(mid.relin_key())
+    ones = []
+    for k in range(2):
+        q = float(mid.primes[ct.nl - 1 - k])
+        ones.append(mid.encrypt_pt(mid.encode(np.ones(mid.slots), q, mid.n_data), 63 + k, q))
+    out = mid.drop_level(ct, ones, rlk)
+    assert out.nl == ct.nl - 2
+    assert out.scale == ct.scale
+    assert np.abs(mid.decrypt(out) - z).max() < 1e-6
