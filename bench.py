@@ -320,6 +320,33 @@ def batched_leg(P, W, name: str, B: int, per_ct: int, steps: int, tune: bool, la
     return out
 
 
+def drop_level_bench(P, W, reps: int = 20) -> dict:
+    """Drop-Level as Section IV-A writes it on the CIFAR-shaped ring (N =
+    2^15, 11 limbs): one ciphertext brought to the network's 8 limbs by three
+    products with encrypted all-ones vectors (ones at scale q_l, input scale
+    kept), against the limb discard the network uses."""
+    import torch
+    cfg = W.config("cifar_cnn")
+    ctx = P.Context(cfg["log_n"], cfg["prime_bits"], cfg["special_bits"], 2.0 ** cfg["log_scale"])
+    sk = P.keygen_secret(ctx, 31)
+    rlk = P.gen_switch_key(ctx, sk, 32, relin=True)
+    nl = len(ctx.primes)
+    z = np.random.default_rng(33).uniform(0, 1, ctx.slots)
+    ct = P.encrypt_sk(ctx, sk, ctx.encode(z, ctx.scale, nl, mont=False)[None], 34, ctx.scale)
+    ones = []
+    for k in range(3):
+        q = float(ctx.primes[nl - 1 - k])
+        ones.append(P.encrypt_sk(ctx, sk, ctx.encode(np.ones(ctx.slots), q, nl, mont=False)[None], 35 + k, q))
+    out = ctx.drop_level(ct, ones, rlk)
+    torch.cuda.synchronize()
+    err = float(np.abs(P.decrypt_slots(ctx, sk, out, np.arange(64, dtype=np.uint32))[0] - z[:64]).max())
+    dt = timed(lambda: ctx.drop_level(ct, ones, rlk), reps, 2)
+    dtm = timed(lambda: ctx.mod_drop(ct, nl - 3), reps, 2)
+    return {"ms_per_drop": round(1e3 * dt / reps, 4), "limbs": f"{nl} -> {nl - 3}", "products": 3,
+            "scale_kept": out.scale == ct.scale, "max_abs_err": err,
+            "limb_discard_ms": round(1e3 * dtm / reps, 4), "paper_cpu_seconds_m5": 0.155}
+
+
 def cpu_baseline(W) -> dict:
     """The oracle (scalar C, one thread) on one whole encrypted LeNet-1
     inference at the same parameters; keys are made before the timer."""
@@ -541,6 +568,7 @@ def main():
 
     if not args.no_models:
         res["models"] = models_bench(P, W)
+        res["drop_level"] = drop_level_bench(P, W)
 
     if args.serve_requests:
         from paper_2402_03060_amd.serve import serving_benchmark
