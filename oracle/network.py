@@ -43,6 +43,8 @@ class Layout:
     prev: str = "input"       # last non-square layer: input / conv / avgpool
     pending: float = 1.0      # deferred average-pooling factor (Section IV-C)
     length: int = 0           # vector length for kind == "vec"
+    clean: bool = True        # zero on every grid slot outside the valid map (padded reads need it)
+    lead: int = 0             # leading zero slots of each sample (the reserved padding space)
 
 
 class PlanError(ValueError):
@@ -64,13 +66,50 @@ def kernel_hw(lay) -> tuple[int, int, int, int]:
     return lay["k"], lay["k"], lay["s"], lay["s"]
 
 
+def pad_hw(lay) -> tuple[int, int]:
+    """(P_h, P_w) zero padding of a convolution (a 1D one pads its width)."""
+    p = lay.get("pad", 0)
+    return (0, p) if lay.get("dims") == 1 else (p, p)
+
+
+def conv_out(H: int, W: int, lay) -> tuple[int, int]:
+    Kh, K, Sh, S = kernel_hw(lay)
+    Ph, Pw = pad_hw(lay)
+    return (H + 2 * Ph - Kh) // Sh + 1, (W + 2 * Pw - K) // S + 1
+
+
 def input_layout(inp: dict, channel_cts: bool = False) -> Layout:
+    """Sample layout: `lead` zero slots (the space Section VI reserves for
+    padding), then the rows at pitch W_img = inp["pitch"] (default W; the
+    extra columns are zero); channels row-major at offset c*H*W_img
+    (Section III-A), or one ciphertext per channel at offset lead."""
     C, H, W = inp["c"], inp["h"], inp["w"]
+    Wp, lead = inp.get("pitch", W), inp.get("lead", 0)
+    if Wp < W or lead < 0:
+        raise PlanError("row pitch below the width or negative lead")
     if channel_cts:
-        # one ciphertext per input channel, the channel at offset 0 of each
-        return Layout("map", C, H, W, 1, W, list(range(C)), [0] * C, "input", 1.0)
-    # one ciphertext per sample, channels row-major at offset c*H*W (Sec. III-A)
-    return Layout("map", C, H, W, 1, W, [0] * C, [c * H * W for c in range(C)], "input", 1.0)
+        return Layout("map", C, H, W, 1, Wp, list(range(C)), [lead] * C, "input", 1.0, lead=lead)
+    return Layout("map", C, H, W, 1, Wp, [0] * C, [lead + c * H * Wp for c in range(C)], "input", 1.0, lead=lead)
+
+
+def check_padded_read(L: Layout, lay) -> None:
+    """A padded convolution reads up to P_h rows above, P_w columns beside and
+    P_h rows below the map.  Those slots must hold zeros: the map is clean,
+    every channel has its own ciphertext (or there is one channel), the row
+    pitch leaves P_w zero columns (a read left of column 0 lands in the
+    previous row's right margin), and the sample's lead holds the rows above
+    (I (P_h W_img + P_w) slots)."""
+    Ph, Pw = pad_hw(lay)
+    if not Ph and not Pw:
+        return
+    if not L.clean:
+        raise PlanError("padded convolution of a pooled map (partial sums lie where the padding reads)")
+    if L.C > 1 and len(set(L.ch_ct)) != L.C:
+        raise PlanError("padded convolution needs one ciphertext per input channel")
+    if L.W_img - L.W < Pw:
+        raise PlanError("row pitch leaves fewer zero columns than the padding")
+    if L.lead < L.I * (Ph * L.W_img + Pw):
+        raise PlanError("leading space below the padding's rows")
 
 
 def footprint(inp: dict, layers, channel_cts: bool = False) -> int:
@@ -80,26 +119,28 @@ def footprint(inp: dict, layers, channel_cts: bool = False) -> int:
     DAT_out * ceil(DAT_in / DAT_out).  With channel_cts each input channel
     sits in its own ciphertext (H*W slots)."""
     L = input_layout(inp, channel_cts)
-    need = (1 if channel_cts else inp["c"]) * inp["h"] * inp["w"]
+    need = L.lead + (1 if channel_cts else inp["c"]) * inp["h"] * L.W_img
     for lay in layers:
         k = lay["kind"]
         if k == "conv":
             Kh, K, Sh, S = kernel_hw(lay)
+            Ph, Pw = pad_hw(lay)
             if not K >= S >= 1:
                 raise PlanError("Theorem 1 needs K >= S >= 1")
-            Ho, Wo = (L.H - Kh) // Sh + 1, (L.W - K) // S + 1
+            Ho, Wo = conv_out(L.H, L.W, lay)
             # last slot read by a valid output
-            read = max(L.ch_off) + L.I * ((S * (Wo - 1) + K - 1) + L.W_img * (Sh * (Ho - 1) + Kh - 1)) + 1
+            read = max(L.ch_off) + L.I * ((S * (Wo - 1) + K - 1 - Pw) + L.W_img * (Sh * (Ho - 1) + Kh - 1 - Ph)) + 1
             need = max(need, read)
             I = L.I * S
             L = Layout("map", lay["ch_out"], Ho, Wo, I, L.W_img, list(range(lay["ch_out"])),
-                       [0] * lay["ch_out"], "conv", 1.0)
-            need = max(need, I * ((Wo - 1) + L.W_img * (Ho - 1)) + 1)
+                       [L.lead] * lay["ch_out"], "conv", 1.0, lead=L.lead)
+            need = max(need, L.lead + I * ((Wo - 1) + L.W_img * (Ho - 1)) + 1)
         elif k == "avgpool":
             c = lay["c"]
             read = max(L.ch_off) + L.I * ((c * (L.W // c) - 1) + L.W_img * (c * (L.H // c) - 1)) + 1
             need = max(need, read)
-            L = Layout("map", L.C, L.H // c, L.W // c, L.I * c, L.W_img, L.ch_ct, L.ch_off, "avgpool", 1.0)
+            L = Layout("map", L.C, L.H // c, L.W // c, L.I * c, L.W_img, L.ch_ct, L.ch_off, "avgpool", 1.0,
+                       lead=L.lead)
         elif k == "flatten":
             need = max(need, L.C * L.H * L.W)
             L = Layout("vec", length=L.C * L.H * L.W)
@@ -129,8 +170,8 @@ def shapes(inp: dict, layers):
     for lay in layers:
         k = lay["kind"]
         if k == "conv":
-            Kh, K, Sh, S = kernel_hw(lay)
-            C, H, W = lay["ch_out"], (H - Kh) // Sh + 1, (W - K) // S + 1
+            C = lay["ch_out"]
+            H, W = conv_out(H, W, lay)
         elif k == "avgpool":
             H, W = H // lay["c"], W // lay["c"]
         elif k == "flatten":
@@ -151,7 +192,7 @@ def network_depth(inp: dict, layers) -> int:
             d += 1
             Kh, K, Sh, S = kernel_hw(lay)
             prev, I, pending = "conv", I * S, 1.0
-            H, W = (H - Kh) // Sh + 1, (W - K) // S + 1
+            H, W = conv_out(H, W, lay)
         elif k == "square":
             d += 1
             pending *= pending
@@ -181,6 +222,8 @@ def cnn_fp64(x: np.ndarray, layers, params) -> np.ndarray:
         if k == "conv":
             w, b = p
             Kh, K, Sh, S = kernel_hw(lay)
+            Ph, Pw = pad_hw(lay)
+            a = np.pad(a, ((0, 0), (Ph, Ph), (Pw, Pw)))
             C, H, W = a.shape
             Ho, Wo = (H - Kh) // Sh + 1, (W - K) // S + 1
             out = np.zeros((w.shape[0], Ho, Wo))
@@ -464,12 +507,17 @@ class Net:
         return v
 
     def input_vector(self, xs: np.ndarray) -> np.ndarray:
-        """Client-side packing (Section III-B): sample b's row-major (C,H,W)
-        data starts at slot b*stride."""
+        """Client-side packing (Section III-B): sample b's (C,H,W) data at
+        slot b*stride + lead, channel c's rows at pitch W_img from
+        lead + c*H*W_img (row-major when there is no lead or extra pitch)."""
+        L = input_layout(self.inp)
         v = np.zeros(self.n_slots)
         for b, x in enumerate(xs):
-            flat = np.asarray(x, dtype=np.float64).reshape(-1)
-            v[b * self.stride: b * self.stride + flat.size] = flat
+            a = np.asarray(x, dtype=np.float64)
+            for c in range(a.shape[0]):
+                for y in range(a.shape[1]):
+                    base = b * self.stride + L.ch_off[c] + y * L.W_img
+                    v[base: base + a.shape[2]] = a[c, y]
         return v
 
     def input_vectors(self, xs: np.ndarray) -> list:
@@ -478,12 +526,15 @@ class Net:
         of channel c at slot b*stride."""
         if not self.channel_cts:
             return [self.input_vector(xs)]
+        L = input_layout(self.inp, True)
         vs = []
         for c in range(self.inp["c"]):
             v = np.zeros(self.n_slots)
             for b, x in enumerate(xs):
-                flat = np.asarray(x, dtype=np.float64)[c].reshape(-1)
-                v[b * self.stride: b * self.stride + flat.size] = flat
+                a = np.asarray(x, dtype=np.float64)[c]
+                for y in range(a.shape[0]):
+                    base = b * self.stride + L.lead + y * L.W_img
+                    v[base: base + a.shape[1]] = a[y]
             vs.append(v)
         return vs
 
@@ -518,26 +569,35 @@ class Net:
 
     # Algorithm 1 ----------------------------------------------------------
     def _conv(self, ev, xs, L, lay, p):
+        """Output (y, x) sits at lead + I_out (x + W_img y); its term (i, j, k)
+        reads input (S_h y + j - P_h, S x + k - P_w) of channel i, whose slot
+        is ch_off[i] + I (...), so the rotation amount is
+        ch_off[i] - lead + I ((k - P_w) + W_img (j - P_h)).  Unpadded and
+        with lead 0 this is Algorithm 1's I (k + W_img j) plus the channel
+        offset."""
         w, b = p
         Kh, K, Sh, S = kernel_hw(lay)
+        Ph, Pw = pad_hw(lay)
         ci, co = lay["ch_in"], lay["ch_out"]
         if ci != L.C:
             raise PlanError("channel mismatch")
         if not K >= S >= 1:
             raise PlanError("Theorem 1 needs K >= S >= 1")
-        Ho, Wo = (L.H - Kh) // Sh + 1, (L.W - K) // S + 1
+        check_padded_read(L, lay)
+        Ho, Wo = conv_out(L.H, L.W, lay)
         I_out = L.I * S
         # first loop: C_rot(i,j,k) = Rot(C_in(i), I_in (k + W_img j)) (+ channel offset)
         rots, src_index = [], {}
+        amount = lambda i, j, kk: L.ch_off[i] - L.lead + L.I * ((kk - Pw) + L.W_img * (j - Ph))
         for i in range(ci):
             for j in range(Kh):
                 for kk in range(K):
-                    key = (L.ch_ct[i], L.ch_off[i] + L.I * (kk + L.W_img * j))
+                    key = (L.ch_ct[i], amount(i, j, kk))
                     if key not in src_index:
                         src_index[key] = len(rots)
                         rots.append(ev.rot(xs[key[0]], key[1]))
         # structured kernel vector: the weight on the valid output slots
-        m_out = self._mask([I_out * (x + L.W_img * y) for y in range(Ho) for x in range(Wo)])
+        m_out = self._mask([L.lead + I_out * (x + L.W_img * y) for y in range(Ho) for x in range(Wo)])
         wp = w * L.pending
         terms = []
         for o in range(co):
@@ -545,12 +605,12 @@ class Net:
             for i in range(ci):
                 for j in range(Kh):
                     for kk in range(K):
-                        key = (L.ch_ct[i], L.ch_off[i] + L.I * (kk + L.W_img * j))
+                        key = (L.ch_ct[i], amount(i, j, kk))
                         t.append((src_index[key], float(wp[o, i, j, kk]), m_out))
             terms.append(t)
         outs = ev.mac_rescale(rots, terms)
         outs = [ev.add_plain(outs[o], float(b[o]) * m_out) for o in range(co)]
-        L2 = Layout("map", co, Ho, Wo, I_out, L.W_img, list(range(co)), [0] * co, "conv", 1.0)
+        L2 = Layout("map", co, Ho, Wo, I_out, L.W_img, list(range(co)), [L.lead] * co, "conv", 1.0, lead=L.lead)
         return outs, L2
 
     def _valid_positions(self, L, ct: int) -> list:
@@ -579,7 +639,7 @@ class Net:
             Y = ev.add_plain(Y, (cb * p) * M)
             Z = ev.mul(Y, ev.drop_to(X, Y))
             outs.append(ev.add_plain(Z, ca * M))
-        L2 = Layout(L.kind, L.C, L.H, L.W, L.I, L.W_img, L.ch_ct, L.ch_off, "relu", 1.0, L.length)
+        L2 = Layout(L.kind, L.C, L.H, L.W, L.I, L.W_img, L.ch_ct, L.ch_off, "relu", 1.0, L.length, lead=L.lead)
         return outs, L2
 
     # Section IV-C -----------------------------------------------------------
@@ -593,20 +653,27 @@ class Net:
                 t = ev.rot(x, r)
                 acc = t if acc is None else ev.add(acc, t)
             outs.append(acc)
+        # the sums leave partial sums on slots around the pooled grid (and on
+        # grid slots past its width, which alias other rows): not clean
         L2 = Layout("map", L.C, L.H // c, L.W // c, L.I * c, L.W_img, L.ch_ct, L.ch_off, "avgpool",
-                    L.pending / (c * c))
+                    L.pending / (c * c), clean=False, lead=L.lead)
         return outs, L2
 
     # Section IV-E -----------------------------------------------------------
     def _flatten(self, ev, xs, L):
-        if len(set(L.ch_ct)) != L.C or any(L.ch_off):
+        """The channels sit at the sample's lead; the first stage that rotates
+        (A, B or the packing) also moves them down by lead, so every mask is
+        the one of a map at offset 0."""
+        if len(set(L.ch_ct)) != L.C or any(off != L.lead for off in L.ch_off):
             raise PlanError("flatten expects one ciphertext per channel")
         S, Wi, Hi, Wimg = L.I, L.W, L.H, L.W_img
         ys = list(xs)
+        sh = L.lead
         # step A: remove the row interval / invalid data
         if L.prev == "avgpool":
             # term x: Rot(X, x(S-1)) * (pending at slot S W_img y + x)
-            rots_all = [[ev.rot(X, x * (S - 1)) for x in range(Wi)] for X in ys]
+            rots_all = [[ev.rot(X, sh + x * (S - 1)) for x in range(Wi)] for X in ys]
+            sh = 0
             masks = [self._mask([S * Wimg * y + x for y in range(Hi)]) for x in range(Wi)]
             ys = []
             for R in rots_all:
@@ -619,27 +686,30 @@ class Net:
             for X in ys:
                 T = None
                 for m in range(S):
-                    t = ev.rot(X, m * (S - 1))
+                    t = ev.rot(X, sh + m * (S - 1))
                     T = t if T is None else ev.add(T, t)
                 R = [ev.rot(T, g * S * (S - 1)) for g in range(G)]
                 out.extend(ev.mac_rescale(R, [[(g, L.pending, masks[g]) for g in range(G)]]))
             ys = out
+            sh = 0
         elif L.pending != 1.0:
             m = self._mask([Wimg * y + x for y in range(Hi) for x in range(Wi)])
-            ys = [ev.mac_rescale([X], [[(0, L.pending, m)]])[0] for X in ys]
+            ys = [ev.mac_rescale([ev.rot(X, sh)], [[(0, L.pending, m)]])[0] for X in ys]
+            sh = 0
         # now (y, x) sits at S W_img y + x
         # step B: remove the column interval
         if Hi > 1:
             masks = [self._mask([y * Wi + x for x in range(Wi)]) for y in range(Hi)]
             out = []
             for X in ys:
-                R = [ev.rot(X, y * (Wimg * S - Wi)) for y in range(Hi)]
+                R = [ev.rot(X, sh + y * (Wimg * S - Wi)) for y in range(Hi)]
                 out.extend(ev.mac_rescale(R, [[(y, 1.0, masks[y]) for y in range(Hi)]]))
             ys = out
+            sh = 0
         # step C: pack channel o at o * H * W (right rotation)
         acc = None
         for o, X in enumerate(ys):
-            t = ev.rot(X, -o * Wi * Hi)
+            t = ev.rot(X, sh - o * Wi * Hi)
             acc = t if acc is None else ev.add(acc, t)
         return [acc], Layout("vec", length=L.C * Hi * Wi)
 

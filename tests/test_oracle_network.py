@@ -307,3 +307,95 @@ def test_encrypted_channel_cts_small(lazy):
     assert len(cts) == 3
     got = read_outputs(net, [sess.ck.decrypt(o) for o in outs])
     assert np.abs(got[0] - cnn_fp64(xs[0], layers, params).reshape(-1)).max() < 1e-3
+
+
+# ------------------------------------------------------------ padding
+PAD_INPUT = {"c": 1, "h": 12, "w": 12, "dist": "uniform01", "pitch": 13, "lead": 14}
+PAD_NETS = {
+    # "same" padding, then pooling and the flatten after pooling
+    "same_pool": (PAD_INPUT, [{"kind": "conv", "ch_in": 1, "ch_out": 2, "k": 3, "s": 1, "pad": 1}, W.SQUARE,
+                              {"kind": "avgpool", "c": 2}, W.FLATTEN, {"kind": "fc", "din": 72, "dout": 5}]),
+    # two padded convolutions, the second of stride 2 on a convolution output
+    "two_padded": (PAD_INPUT, [{"kind": "conv", "ch_in": 1, "ch_out": 2, "k": 3, "s": 1, "pad": 1}, W.SQUARE,
+                               {"kind": "conv", "ch_in": 2, "ch_out": 3, "k": 3, "s": 2, "pad": 1}, W.SQUARE,
+                               W.FLATTEN, {"kind": "fc", "din": 108, "dout": 5}]),
+    # a padded stride-2 convolution first: the next one reads at interval 2
+    "strided_first": ({"c": 1, "h": 12, "w": 12, "dist": "uniform01", "pitch": 14, "lead": 30},
+                      [{"kind": "conv", "ch_in": 1, "ch_out": 2, "k": 3, "s": 2, "pad": 1}, W.SQUARE,
+                       {"kind": "conv", "ch_in": 2, "ch_out": 2, "k": 3, "s": 1, "pad": 1}, W.FLATTEN,
+                       {"kind": "fc", "din": 72, "dout": 4}]),
+    # 1D convolutions padded along the width
+    "1d": ({"c": 1, "h": 1, "w": 32, "dist": "normal", "pitch": 34, "lead": 2},
+           [{"kind": "conv", "ch_in": 1, "ch_out": 2, "k": 3, "s": 1, "dims": 1, "pad": 1}, W.SQUARE,
+            {"kind": "conv", "ch_in": 2, "ch_out": 2, "k": 3, "s": 2, "dims": 1, "pad": 1}, W.FLATTEN,
+            {"kind": "fc", "din": 32, "dout": 4}]),
+}
+
+
+@pytest.mark.parametrize("name", list(PAD_NETS))
+@pytest.mark.parametrize("samples", [1, 3])
+def test_padding_slot_simulation(name, samples):
+    """Zero-padded convolutions (Section VI's reserved space: a lead of zero
+    slots per sample and a wider row pitch) give the FP64 CNN on zero-padded
+    inputs, slot for slot, alone and with three packed samples."""
+    inp, layers = PAD_NETS[name]
+    params = W.gen_params(layers)
+    xs = W.gen_inputs(inp, samples)
+    n_slots, stride = (2048, 0) if samples == 1 else (4096, 1024)
+    net = Net(inp, layers, params, n_slots, samples, stride)
+    ev = SlotEval(n_slots)
+    got = read_outputs(net, net.run(ev, net.input_vectors(xs)))
+    ref = np.array([cnn_fp64(x, layers, params).reshape(-1) for x in xs])
+    assert np.abs(got - ref).max() < 1e-12
+
+
+def test_padding_fp64_reference_is_zero_padding():
+    """The FP64 reference pads with zeros: a 1 x 1 kernel of weight 1 and
+    padding 1 returns the input inside a zero border."""
+    x = np.arange(12.0).reshape(1, 3, 4)
+    lay = {"kind": "conv", "ch_in": 1, "ch_out": 1, "k": 1, "s": 1, "pad": 1}
+    out = cnn_fp64(x, [lay], [(np.ones((1, 1, 1, 1)), np.zeros(1))])
+    assert out.shape == (1, 5, 6) and np.array_equal(out[0, 1:4, 1:5], x[0]) and out.sum() == x.sum()
+
+
+@pytest.mark.parametrize("inp,layers,channel_cts,msg", [
+    ({"c": 3, "h": 8, "w": 8, "dist": "uniform01", "pitch": 9, "lead": 10},
+     [{"kind": "conv", "ch_in": 3, "ch_out": 2, "k": 3, "s": 1, "pad": 1}], False, "one ciphertext per input channel"),
+    (dict(PAD_INPUT, pitch=12), PAD_NETS["same_pool"][1], False, "zero columns"),
+    (dict(PAD_INPUT, lead=13), PAD_NETS["same_pool"][1], False, "leading space"),
+    (PAD_INPUT, [{"kind": "conv", "ch_in": 1, "ch_out": 2, "k": 3, "s": 1}, {"kind": "avgpool", "c": 2},
+                 {"kind": "conv", "ch_in": 2, "ch_out": 2, "k": 3, "s": 1, "pad": 1}], False, "pooled map"),
+])
+def test_padding_rejected_where_the_reads_are_not_zero(inp, layers, channel_cts, msg):
+    params = W.gen_params(layers)
+    net = Net(inp, layers, params, 2048, channel_cts=channel_cts)
+    with pytest.raises(PlanError, match=msg):
+        net.run(SlotEval(2048), net.input_vectors(W.gen_inputs(inp, 1)))
+
+
+def test_padding_channel_cts():
+    """A padded convolution of a three-channel input given as one ciphertext
+    per channel."""
+    inp = {"c": 3, "h": 8, "w": 8, "dist": "uniform01", "pitch": 9, "lead": 10}
+    layers = [{"kind": "conv", "ch_in": 3, "ch_out": 2, "k": 3, "s": 1, "pad": 1}, W.SQUARE, W.FLATTEN,
+              {"kind": "fc", "din": 128, "dout": 4}]
+    params = W.gen_params(layers)
+    xs = W.gen_inputs(inp, 1)
+    net = Net(inp, layers, params, 2048, channel_cts=True)
+    got = read_outputs(net, net.run(SlotEval(2048), net.input_vectors(xs)))
+    assert np.abs(got[0] - cnn_fp64(xs[0], layers, params).reshape(-1)).max() < 1e-12
+
+
+@pytest.mark.parametrize("lazy", [False, True])
+def test_encrypted_padding(lazy):
+    """The two-padded-convolution net encrypted at N = 2^11 (eager and with
+    deferred ModDown): within 1e-3 of the FP64 CNN."""
+    inp, layers = PAD_NETS["two_padded"]
+    ring = dict(W.config("lenet1"), log_n=11)
+    sess = OracleSession(ring)
+    params = W.gen_params(layers)
+    xs = W.gen_inputs(inp, 1)
+    net = Net(inp, layers, params, sess.ck.slots)
+    _, outs, _ = run_encrypted(sess, net, xs, lazy=lazy)
+    got = read_outputs(net, [sess.ck.decrypt(o) for o in outs])
+    assert np.abs(got[0] - cnn_fp64(xs[0], layers, params).reshape(-1)).max() < 1e-3
