@@ -211,15 +211,26 @@ typedef struct {
     uint32_t ch_in, ch_out, k, s, dims;
     const double* weights;  /* host; conv [ch_out][ch_in][kh][k], fc [ch_out][ch_in] */
     const double* bias;     /* host; [ch_out] */
+    uint32_t pad;           /* conv: zero padding on each side (1D: of the width), Section VI;
+                             * reads land in the input's lead and row-pitch margin */
 } unihenn_layer;
 
 /* Input tensor (C, H, W) flattened row-major into the slots (Section III-A);
  * `samples` inputs per ciphertext at slot stride `stride` (Section III-B);
- * stride is ignored for one sample. */
+ * stride is ignored for one sample.  Padding space (Section VI): each sample
+ * starts with `lead` zero slots and its rows sit at pitch `pitch` (0: w;
+ * the columns past w are zero), so channel c's row y starts at
+ * b * stride + lead + (c h + y) pitch.  A convolution of padding P reading
+ * at interval I needs pitch - (map width) >= P and lead >= I (P pitch + P);
+ * its input map must be zero off its valid slots (the input, a convolution
+ * or activation output; not a pooled map) with one ciphertext per channel
+ * (or one channel); net_create fails with EINVAL otherwise. */
 typedef struct {
     uint32_t c, h, w;
     uint32_t samples;
     uint32_t stride;
+    uint32_t pitch;
+    uint32_t lead;
 } unihenn_input;
 
 /* Plan a network and encode its plaintexts on the device: the rotation

@@ -40,7 +40,7 @@ class EVK(C.Structure):
 class LAYER(C.Structure):
     _fields_ = [("kind", C.c_int32), ("ch_in", C.c_uint32), ("ch_out", C.c_uint32), ("k", C.c_uint32),
                 ("s", C.c_uint32), ("dims", C.c_uint32), ("weights", C.POINTER(C.c_double)),
-                ("bias", C.POINTER(C.c_double))]
+                ("bias", C.POINTER(C.c_double)), ("pad", C.c_uint32)]
 
 
 class TUNING(C.Structure):
@@ -54,7 +54,7 @@ class TUNING(C.Structure):
 
 class INPUT(C.Structure):
     _fields_ = [("c", C.c_uint32), ("h", C.c_uint32), ("w", C.c_uint32), ("samples", C.c_uint32),
-                ("stride", C.c_uint32)]
+                ("stride", C.c_uint32), ("pitch", C.c_uint32), ("lead", C.c_uint32)]
 
 
 # name -> (restype, argtypes); every symbol declared in include/unihenn.h
@@ -442,6 +442,7 @@ class Net:
             d.kind = _KIND[L["kind"]]
             if L["kind"] == "conv":
                 d.ch_in, d.ch_out, d.k, d.s, d.dims = L["ch_in"], L["ch_out"], L["k"], L["s"], L.get("dims", 2)
+                d.pad = L.get("pad", 0)
             elif L["kind"] == "avgpool":
                 d.k = L["c"]
             elif L["kind"] == "fc":
@@ -456,7 +457,7 @@ class Net:
                 self._keep += [w, b]
                 d.weights = w.ctypes.data_as(C.POINTER(C.c_double))
                 d.bias = b.ctypes.data_as(C.POINTER(C.c_double))
-        ind = INPUT(inp["c"], inp["h"], inp["w"], samples, stride)
+        ind = INPUT(inp["c"], inp["h"], inp["w"], samples, stride, inp.get("pitch", 0), inp.get("lead", 0))
         h = C.c_void_p()
         _check(lib().unihenn_net_create_ex(ctx.h, C.byref(ind), arr, len(layers), max_batch,
                                            (PLAN_LAZY_MODDOWN if lazy else 0) |

@@ -85,10 +85,12 @@ struct Layout {
     int prev = 0;                      // 0 input, 1 conv, 2 avgpool, 3 approximate ReLU (last non-square layer)
     double pending = 1.0;              // deferred pooling factor (Section IV-C)
     int length = 0;
+    bool clean = true;                 // zero on every slot off the valid map (padded reads need it)
+    int lead = 0;                      // leading zero slots of each sample (the reserved padding space)
 };
 
 struct KernelGeom {
-    int kh, kw, sh, sw;
+    int kh, kw, sh, sw, ph, pw;  // kernel, stride and zero padding (height, width)
 };
 
 // Largest total size of the rotated batches of one convolution kept live at
@@ -97,8 +99,8 @@ constexpr size_t kOneSumBytes = (size_t)24 << 30;
 
 KernelGeom geom(const unihenn_layer& L)
 {
-    if (L.dims == 1) return {1, (int)L.k, 1, (int)L.s};
-    return {(int)L.k, (int)L.k, (int)L.s, (int)L.s};
+    if (L.dims == 1) return {1, (int)L.k, 1, (int)L.s, 0, (int)L.pad};
+    return {(int)L.k, (int)L.k, (int)L.s, (int)L.s, (int)L.pad, (int)L.pad};
 }
 
 }  // namespace
@@ -439,6 +441,7 @@ struct Planner {
         }
         L.prev = 3;
         L.pending = 1.0;
+        L.clean = true;  // masked to the valid slots
         return 0;
     }
 
@@ -450,20 +453,39 @@ struct Planner {
         if (L.vec || ci != L.C) return fail(UNIHENN_EINVAL, "conv input channels do not match");
         if (!(g.kw >= g.sw && g.sw >= 1 && g.kh >= g.sh && g.sh >= 1))
             return fail(UNIHENN_EINVAL, "conv needs kernel >= stride >= 1 (Theorem 1)");
-        if (L.H < g.kh || L.W < g.kw) return fail(UNIHENN_EINVAL, "conv kernel larger than its input");
+        if (L.H + 2 * g.ph < g.kh || L.W + 2 * g.pw < g.kw) return fail(UNIHENN_EINVAL, "conv kernel larger than its input");
         if (!ly.weights || !ly.bias) return fail(UNIHENN_EINVAL, "conv without weights or bias");
-        const int Ho = (L.H - g.kh) / g.sh + 1, Wo = (L.W - g.kw) / g.sw + 1;
+        // Section VI's padding space: a padded read above the map lands in the
+        // sample's lead, one left of column 0 in the previous row's zero
+        // margin, one below the map past its last row; all of them must be
+        // zero slots
+        if (g.ph || g.pw) {
+            if (!L.clean)
+                return fail(UNIHENN_EINVAL, "padded convolution of a pooled map (partial sums lie where the padding reads)");
+            bool own = true;
+            for (int i = 0; i < ci; ++i)
+                for (int i2 = i + 1; i2 < ci; ++i2) own &= L.ch_reg[i] != L.ch_reg[i2];
+            if (!own) return fail(UNIHENN_EINVAL, "padded convolution needs one ciphertext per input channel");
+            if (L.W_img - L.W < g.pw) return fail(UNIHENN_EINVAL, "row pitch leaves fewer zero columns than the padding");
+            if ((long)L.lead < (long)L.I * ((long)g.ph * L.W_img + g.pw))
+                return fail(UNIHENN_EINVAL, "leading space below the padding's rows");
+        }
+        const int Ho = (L.H + 2 * g.ph - g.kh) / g.sh + 1, Wo = (L.W + 2 * g.pw - g.kw) / g.sw + 1;
         const int I_out = L.I * g.sw;
         std::vector<long> pos;
         for (int y = 0; y < Ho; ++y)
-            for (int x = 0; x < Wo; ++x) pos.push_back((long)I_out * (x + (long)L.W_img * y));
+            for (int x = 0; x < Wo; ++x) pos.push_back((long)L.lead + (long)I_out * (x + (long)L.W_img * y));
         const std::vector<double> m_out = mask(pos);
         const int nl = net->regs[L.ch_reg[0]].nl;
         const double s_in = net->regs[L.ch_reg[0]].scale;
         auto weight = [&](int o, int i, int j, int k) {
             return ly.weights[(((size_t)o * ci + i) * g.kh + j) * g.kw + k] * L.pending;
         };
-        auto amount = [&](int i, int j, int k) { return (long)L.ch_off[i] + (long)L.I * (k + (long)L.W_img * j); };
+        // output (y, x) sits at lead + I_out (x + W_img y) and its term (i, j, k)
+        // reads input (S_h y + j - P_h, S x + k - P_w) of channel i
+        auto amount = [&](int i, int j, int k) {
+            return (long)L.ch_off[i] - L.lead + (long)L.I * ((k - g.pw) + (long)L.W_img * (j - g.ph));
+        };
         bool one_ct = true;
         for (int i = 1; i < ci; ++i) one_ct &= L.ch_reg[i] == L.ch_reg[0];
         one_ct &= ci > 1;
@@ -554,13 +576,14 @@ struct Planner {
         out.W_img = L.W_img;
         out.prev = 1;
         out.pending = 1.0;
+        out.lead = L.lead;
         for (int o = 0; o < co; ++o) {
             int r = rescale(acc[o]);
             if (r < 0) return -1;
             std::vector<double> bz = mask(pos, ly.bias[o]);
             int d = add_plain_vec(r, bz);
             out.ch_reg.push_back(d);
-            out.ch_off.push_back(0);
+            out.ch_off.push_back(L.lead);
         }
         L = out;
         return 0;
@@ -587,6 +610,7 @@ struct Planner {
         L.I *= cc;
         L.prev = 2;
         L.pending /= (double)(cc * cc);
+        L.clean = false;  // partial sums around the pooled grid (and past its width)
         return 0;
     }
 
@@ -619,8 +643,10 @@ struct Planner {
             for (int c1 = c0 + 1; c1 < L.C; ++c1)
                 if (L.ch_reg[c0] == L.ch_reg[c1]) return fail(UNIHENN_EINVAL, "flatten needs one ciphertext per channel");
         for (int off : L.ch_off)
-            if (off) return fail(UNIHENN_EINVAL, "flatten needs channels at offset 0");
+            if (off != L.lead) return fail(UNIHENN_EINVAL, "flatten needs every channel at the sample's lead");
         const int S = L.I, Wi = L.W, Hi = L.H, Wimg = L.W_img;
+        // the first stage that rotates also moves the maps from the lead to 0
+        long sh = L.lead;
         std::vector<int> ys = L.ch_reg;
         const int nl = net->regs[ys[0]].nl;
         // a sum is extended when any of its terms is; its plaintexts follow (pts[ext])
@@ -629,7 +655,7 @@ struct Planner {
             std::vector<size_t> pts[2];
             for (int& X : ys) {
                 std::vector<int> srcs;
-                for (int x = 0; x < Wi; ++x) srcs.push_back(rot(X, (long)x * (S - 1)));
+                for (int x = 0; x < Wi; ++x) srcs.push_back(rot(X, sh + (long)x * (S - 1)));
                 const bool ext = any_ext(srcs);
                 if (pts[ext].empty())
                     for (int x = 0; x < Wi; ++x) {
@@ -642,13 +668,14 @@ struct Planner {
                 X = mac_rescale(terms);
                 if (X < 0) return -1;
             }
+            sh = 0;
         } else if (S > 1 && Wi > 1) {
             // zeros between the values: S shifted copies summed, then one mask per group of S columns
             const int G = (Wi + S - 1) / S;
             std::vector<size_t> pts[2];
             for (int& X : ys) {
                 std::vector<int> shifted;
-                for (int m = 0; m < S; ++m) shifted.push_back(rot(X, (long)m * (S - 1)));
+                for (int m = 0; m < S; ++m) shifted.push_back(rot(X, sh + (long)m * (S - 1)));
                 int T = sum(shifted);
                 if (T < 0) return -1;
                 std::vector<int> srcs;
@@ -667,6 +694,7 @@ struct Planner {
                 X = mac_rescale(terms);
                 if (X < 0) return -1;
             }
+            sh = 0;
         } else if (L.pending != 1.0) {
             std::vector<long> pos;
             for (int y = 0; y < Hi; ++y)
@@ -674,14 +702,16 @@ struct Planner {
             size_t pts[2] = {0, 0};
             bool have[2] = {false, false};
             for (int& X : ys) {
-                const bool ext = is_ext(X);
+                const int src = rot(X, sh);
+                const bool ext = is_ext(src);
                 if (!have[ext]) {
                     pts[ext] = request(mask(pos), std::vector<double>(1, L.pending), delta, nl, 1, ext);
                     have[ext] = true;
                 }
-                X = mac_rescale({{X, pts[ext]}});
+                X = mac_rescale({{src, pts[ext]}});
                 if (X < 0) return -1;
             }
+            sh = 0;
         }
         // (y, x) now sits at S W_img y + x; remove the column interval
         if (Hi > 1) {
@@ -689,7 +719,7 @@ struct Planner {
             std::vector<size_t> pts[2];
             for (int& X : ys) {
                 std::vector<int> srcs;
-                for (int y = 0; y < Hi; ++y) srcs.push_back(rot(X, (long)y * ((long)Wimg * S - Wi)));
+                for (int y = 0; y < Hi; ++y) srcs.push_back(rot(X, sh + (long)y * ((long)Wimg * S - Wi)));
                 const bool ext = any_ext(srcs);
                 if (pts[ext].empty())
                     for (int y = 0; y < Hi; ++y) {
@@ -702,10 +732,11 @@ struct Planner {
                 X = mac_rescale(terms);
                 if (X < 0) return -1;
             }
+            sh = 0;
         }
         // pack: channel o shifted right by o H W
         std::vector<int> placed;
-        for (int o = 0; o < (int)ys.size(); ++o) placed.push_back(rot(ys[o], -(long)o * Wi * Hi));
+        for (int o = 0; o < (int)ys.size(); ++o) placed.push_back(rot(ys[o], sh - (long)o * Wi * Hi));
         int acc = sum(placed);
         if (acc < 0) return -1;
         Layout out;
@@ -810,25 +841,28 @@ struct Planner {
 // channel_cts the input holds one H x W plane per ciphertext.
 int footprint(const unihenn_input& in, const unihenn_layer* ls, int n, long* out, bool channel_cts)
 {
-    // one ciphertext per channel: each holds one H x W plane at offset 0
-    long need = (long)(channel_cts ? 1 : in.c) * in.h * in.w;
-    int C = (int)in.c, H = (int)in.h, W = (int)in.w, I = 1, Wimg = (int)in.w;
-    long max_off = channel_cts ? 0 : (long)(in.c - 1) * in.h * in.w;
+    // the sample's lead, then the rows at pitch W_img; one ciphertext per
+    // channel: each holds one H x W_img plane after the lead
+    const int Wimg = in.pitch ? (int)in.pitch : (int)in.w;
+    const long lead = (long)in.lead;
+    long need = lead + (long)(channel_cts ? 1 : in.c) * in.h * Wimg;
+    int C = (int)in.c, H = (int)in.h, W = (int)in.w, I = 1;
+    long max_off = lead + (channel_cts ? 0 : (long)(in.c - 1) * in.h * Wimg);
     bool vec = false;
     for (int l = 0; l < n; ++l) {
         const unihenn_layer& L = ls[l];
         if (L.kind == UNIHENN_LAYER_CONV) {
             KernelGeom g = geom(L);
-            if (vec || H < g.kh || W < g.kw || g.sw < 1 || g.sh < 1) return UNIHENN_EINVAL;
-            int Ho = (H - g.kh) / g.sh + 1, Wo = (W - g.kw) / g.sw + 1;
-            need = std::max(need, max_off + (long)I * ((g.sw * (Wo - 1) + g.kw - 1) +
-                                                       (long)Wimg * (g.sh * (Ho - 1) + g.kh - 1)) + 1);
+            if (vec || H + 2 * g.ph < g.kh || W + 2 * g.pw < g.kw || g.sw < 1 || g.sh < 1) return UNIHENN_EINVAL;
+            int Ho = (H + 2 * g.ph - g.kh) / g.sh + 1, Wo = (W + 2 * g.pw - g.kw) / g.sw + 1;
+            need = std::max(need, max_off + (long)I * ((g.sw * (Wo - 1) + g.kw - 1 - g.pw) +
+                                                       (long)Wimg * (g.sh * (Ho - 1) + g.kh - 1 - g.ph)) + 1);
             I *= g.sw;
             C = (int)L.ch_out;
             H = Ho;
             W = Wo;
-            max_off = 0;
-            need = std::max(need, (long)I * ((Wo - 1) + (long)Wimg * (Ho - 1)) + 1);
+            max_off = lead;
+            need = std::max(need, lead + (long)I * ((Wo - 1) + (long)Wimg * (Ho - 1)) + 1);
         } else if (L.kind == UNIHENN_LAYER_AVGPOOL) {
             int cc = (int)L.k;
             if (vec || cc < 1 || H < cc || W < cc) return UNIHENN_EINVAL;
@@ -864,8 +898,8 @@ int count_depth(const unihenn_input& in, const unihenn_layer* ls, int n)
             prev = 1;
             I *= g.sw;
             pending = 1.0;
-            H = (H - g.kh) / g.sh + 1;
-            W = (W - g.kw) / g.sw + 1;
+            H = (H + 2 * g.ph - g.kh) / g.sh + 1;
+            W = (W + 2 * g.pw - g.kw) / g.sw + 1;
             break;
         }
         case UNIHENN_LAYER_SQUARE: d += 1; pending *= pending; break;
@@ -1064,6 +1098,7 @@ extern "C" int unihenn_net_create_ex(const unihenn_ctx* c, const unihenn_input* 
     const bool channel_cts = (plan_flags & UNIHENN_PLAN_CHANNEL_CTS) != 0;
     if (in->c < 1 || in->h < 1 || in->w < 1 || in->samples < 1 || max_batch < 1)
         return uh_fail(UNIHENN_EINVAL, "empty input shape, sample count or batch");
+    if (in->pitch && in->pitch < in->w) return uh_fail(UNIHENN_EINVAL, "row pitch below the input width");
     for (uint32_t l = 0; l < n_layers; ++l)
         if (layers[l].kind < UNIHENN_LAYER_CONV || layers[l].kind > UNIHENN_LAYER_RELU_APPROX)
             return uh_fail(UNIHENN_EINVAL, "unknown layer kind");
@@ -1115,15 +1150,18 @@ extern "C" int unihenn_net_create_ex(const unihenn_ctx* c, const unihenn_input* 
         net->steps.push_back(s);
     }
     net->input_reg = input_regs[0];
+    // input layout: the sample's lead of zero slots (Section VI's padding
+    // space), then the rows at pitch W_img (zero beyond the width)
     Layout L;
     L.C = (int)in->c;
     L.H = (int)in->h;
     L.W = (int)in->w;
     L.I = 1;
-    L.W_img = (int)in->w;
+    L.W_img = in->pitch ? (int)in->pitch : (int)in->w;
+    L.lead = (int)in->lead;
     for (uint32_t ch = 0; ch < in->c; ++ch) {
         L.ch_reg.push_back(channel_cts ? input_regs[ch] : net->input_reg);
-        L.ch_off.push_back(channel_cts ? 0 : (int)(ch * in->h * in->w));
+        L.ch_off.push_back(L.lead + (channel_cts ? 0 : (int)(ch * in->h * (uint32_t)L.W_img)));
     }
     for (uint32_t l = 0; l < n_layers; ++l) {
         LayerRecord rec;

@@ -426,3 +426,64 @@ def test_literal_drop_level_feeds_the_network():
             assert np.array_equal(g, e.data), mode
     got = decrypt_outputs(sess, onet, exp)
     assert np.abs(got - reference_outputs(onet, xs)).max() < 1e-3
+
+
+def _custom_parity(log_n, inp, layers, samples=1, stride=0, lazy=False):
+    """GPU outputs equal to the oracle's for a network given by its layers
+    (plain and hoisted modes)."""
+    import paper_2402_03060_amd as P
+    from oracle.network import Net as ONet
+    ring = dict(W.config("lenet1"), log_n=log_n)
+    sess = OracleSession(ring)
+    params = W.gen_params(layers)
+    onet = ONet(inp, layers, params, sess.ck.slots, samples, stride)
+    xs = W.gen_inputs(inp, samples)
+    ct, outs, _ = run_encrypted(sess, onet, xs, lazy=lazy)
+    ctx = _ctx(P, ring)
+    gnet = P.Net(ctx, inp, layers, params, samples=samples, stride=stride, max_batch=1, lazy=lazy)
+    assert gnet.depth == onet.depth and sorted(gnet.rotations()) == onet.rotation_set()
+    keys = {r: ctx.import_evk(sess.key_coeff[r]) for r in gnet.rotations()}
+    gnet.bind_keys(keys, ctx.import_evk(sess.rlk_coeff))
+    gin = ctx.import_ct(ct.data[None], ct.scale)
+    for mode in (P.EVAL_PLAIN, P.EVAL_HOISTED):
+        gnet.set_mode(mode)
+        got = [ctx.export_ct(o)[0] for o in gnet.eval(gin)]
+        for g, e in zip(got, outs):
+            assert np.array_equal(g, e.data), mode
+    return gnet
+
+
+@pytest.mark.parametrize("name", ["same_pool", "two_padded", "strided_first", "1d"])
+@pytest.mark.parametrize("lazy", [False, True])
+def test_padding_bit_exact(name, lazy):
+    """Zero-padded convolutions over Section VI's reserved space (a lead of
+    zero slots, a wider row pitch) at N = 2^11, default and deferred-ModDown
+    plans, against the oracle."""
+    from tests.test_oracle_network import PAD_NETS
+    inp, layers = PAD_NETS[name]
+    _custom_parity(11, inp, layers, lazy=lazy)
+
+
+def test_padding_packed_samples_bit_exact():
+    """Three padded samples per ciphertext at stride 512 (N = 2^12)."""
+    from tests.test_oracle_network import PAD_NETS
+    inp, layers = PAD_NETS["two_padded"]
+    _custom_parity(12, inp, layers, samples=3, stride=512)
+
+
+def test_padding_rejected_by_the_planner():
+    """The planner refuses padded reads that would not be zero: no margin
+    columns, too short a lead, a pooled input."""
+    import paper_2402_03060_amd as P
+    from tests.test_oracle_network import PAD_INPUT, PAD_NETS
+    ctx = _ctx(P, dict(W.config("lenet1"), log_n=11))
+    layers = PAD_NETS["same_pool"][1]
+    params = W.gen_params(layers)
+    for inp in (dict(PAD_INPUT, pitch=12), dict(PAD_INPUT, lead=13)):
+        with pytest.raises(P.UnihennError):
+            P.Net(ctx, inp, layers, params)
+    pooled = [{"kind": "conv", "ch_in": 1, "ch_out": 2, "k": 3, "s": 1}, {"kind": "avgpool", "c": 2},
+              {"kind": "conv", "ch_in": 2, "ch_out": 2, "k": 3, "s": 1, "pad": 1}, W.FLATTEN,
+              {"kind": "fc", "din": 50, "dout": 2}]
+    with pytest.raises(P.UnihennError):
+        P.Net(ctx, PAD_INPUT, pooled, W.gen_params(pooled))
