@@ -31,11 +31,18 @@ HBM_PEAK_GBS = 8000.0
 
 
 def _pack(net_input: dict, xs: np.ndarray, n_slots: int, stride: int) -> np.ndarray:
-    """Client-side packing: sample b's row-major (C, H, W) values at slot b * stride."""
+    """Client-side packing: sample b's channel c, row y at slot
+    b * stride + lead + (c H + y) pitch (row-major (C, H, W) without padding
+    space)."""
+    H, Wd = net_input["h"], net_input["w"]
+    pitch, lead = net_input.get("pitch", Wd), net_input.get("lead", 0)
     v = np.zeros(n_slots)
     for b, x in enumerate(xs):
-        flat = np.asarray(x, dtype=np.float64).reshape(-1)
-        v[b * stride: b * stride + flat.size] = flat
+        a = np.asarray(x, dtype=np.float64).reshape(-1, H, Wd)
+        for c in range(a.shape[0]):
+            for y in range(H):
+                base = b * stride + lead + (c * H + y) * pitch
+                v[base: base + Wd] = a[c, y]
     return v
 
 
@@ -109,6 +116,8 @@ def _fp64_cnn(x, layers, params):
             kh, kw = w.shape[2], w.shape[3]
             sh = 1 if L.get("dims") == 1 else L["s"]
             sw = L["s"]
+            pw = L.get("pad", 0)
+            a = np.pad(a, ((0, 0), (0 if L.get("dims") == 1 else pw,) * 2, (pw, pw)))
             C, H, Wd = a.shape
             Ho, Wo = (H - kh) // sh + 1, (Wd - kw) // sw + 1
             out = np.zeros((w.shape[0], Ho, Wo))
@@ -366,7 +375,7 @@ def cpu_baseline(W) -> dict:
 # The paper's own single-inference times (seconds; SEAL on one Xeon Gold 5220
 # core, scale 2^32, trained models): context only, different parameters.
 PAPER_MODEL_SECONDS = {"m1": 16.247, "m3": 29.105, "m4": 740.128, "m6": 12.309, "m7": 5.119}
-MODEL_NAMES = ["m1", "m3", "m4", "m5", "m6", "m7", "cifar_cnn"]
+MODEL_NAMES = ["m1", "m3", "m4", "m5", "m6", "m7", "cifar_cnn", "lenet1_padded"]
 # M5 at N = 2^15 would hold ~150 GB of plaintexts (90,691 weights of its
 # 64 -> 128 convolution, most on a few valid slots); it runs at N = 2^13, the
 # smallest ring whose slots hold a 3 x 32 x 32 input

@@ -153,6 +153,22 @@ MODEL_CONFIGS = {
 }
 CONFIGS.update(MODEL_CONFIGS)
 
+# LeNet-1 with a "same"-padded first convolution (not one of the paper's
+# models: the padded-convolution workload).  The sample keeps the padding
+# space of Section VI: 2 zero columns per row (pitch 30) and a lead of
+# 2 * 30 + 2 zero slots for the rows above the image.
+PADDED_CONFIGS = {
+    "lenet1_padded": {
+        "desc": "LeNet-1 with conv1 padded: conv 1->4 K5 P2, sq, pool2, conv 4->12 K5, sq, pool2, flatten, FC 300->10",
+        "log_n": 14, "prime_bits": [60] + [40] * 7, "special_bits": 60, "log_scale": 40,
+        "input": {"c": 1, "h": 28, "w": 28, "dist": "uniform01", "pitch": 30, "lead": 62},
+        "layers": [dict(_conv(1, 4, 5, 1), pad=2), SQUARE, _pool(2), _conv(4, 12, 5, 1), SQUARE, _pool(2), FLATTEN,
+                   _fc(300, 10)],
+        "samples_per_ct": 1, "sample_stride": 0, "cts_per_batch": 1,
+    },
+}
+CONFIGS.update(PADDED_CONFIGS)
+
 # Small rings used by unit and parity tests (same shapes of work, tiny N).
 TINY_RINGS = {
     "n16": {"log_n": 4, "prime_bits": [50, 40, 40], "special_bits": 50, "log_scale": 30},
