@@ -91,7 +91,8 @@ def test_cnn1d_small_ring_bit_exact():
     _run_parity(cfg)
 
 
-@pytest.mark.parametrize("name,log_n", [("m3", 12), ("m1", 11), ("m6", 11), ("m7", 11), ("m4", 11)])
+@pytest.mark.parametrize("name,log_n", [("m3", 12), ("m1", 11), ("m6", 11), ("m7", 11), ("m4", 11),
+                                        ("lenet1_padded", 11)])
 def test_paper_model_shapes_bit_exact(name, log_n):
     """The paper's other model shapes on small rings: approximate ReLU with
     Mul(C) (M3), stride-3 and stride-2 convolutions with FC -> square -> FC
