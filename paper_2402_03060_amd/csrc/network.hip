@@ -1397,29 +1397,61 @@ struct Exec {
         GroupWs w = carve();
         const int Emax = net->group_max;
         if (net->mode & UNIHENN_EVAL_HOISTED) {
+            // Launch sets of up to Emax rotations: whole runs of one source
+            // while they fit, a source with more rotations alone in pieces of
+            // Emax.  The distinct sources of a set are its ModUp blocks (each
+            // decomposed once); every rotation reads its source's digits
+            // through its automorphism.  A one-source set whose digits the
+            // workspace still holds (the previous set's) skips the ModUp.
             size_t i = 0;
             while (i < run.size()) {
-                const int src = net->steps[run[i]].a;
+                std::vector<size_t> set;
                 size_t j = i;
-                while (j < run.size() && net->steps[run[j]].a == src) ++j;
-                if (modup_owner != src) {
-                    const u64* d = reg(src) + (size_t)nl * rn;
-                    group_modup(c, 1, &d, 2 * nl, B, nl, w.pdcoef, w.pmodup, s);
-                    modup_owner = src;
-                }
-                for (size_t k = i; k < j; k += Emax) {
-                    GroupArgs ga;
-                    fill(ga, run, k, (int)std::min<size_t>(Emax, j - k));
-                    ga.dsrc[0] = reg(src) + (size_t)nl * rn;
-                    ga.dstride = 2 * nl;
-                    for (int e = 0; e < ga.E; ++e) {
-                        ga.blk[e] = 0;
-                        ga.gin[e] = ga.gdig[e] = ga.g[e];
+                while (j < run.size()) {
+                    const int src = net->steps[run[j]].a;
+                    size_t e = j;
+                    while (e < run.size() && net->steps[run[e]].a == src) ++e;
+                    if (set.empty()) {
+                        const size_t take = std::min<size_t>(e - j, (size_t)Emax);
+                        set.insert(set.end(), run.begin() + j, run.begin() + j + take);
+                        j += take;
+                        if (j < e) break;  // the source continues in the next set
+                    } else if (set.size() + (e - j) <= (size_t)Emax) {
+                        set.insert(set.end(), run.begin() + j, run.begin() + e);
+                        j = e;
+                    } else {
+                        break;
                     }
-                    if (ext) group_switch_ext(c, ga, B, nl, w.pmodup, s);
-                    else group_switch(c, ga, B, nl, true, w.pmodup, w.aux, w.U, w.Up, w.R, s);
                 }
                 i = j;
+                GroupArgs ga;
+                fill(ga, set, 0, (int)set.size());
+                ga.dstride = 2 * nl;
+                std::vector<int> srcs;
+                for (int e = 0; e < ga.E; ++e) {
+                    const int src = net->steps[set[e]].a;
+                    int d = (int)(std::find(srcs.begin(), srcs.end(), src) - srcs.begin());
+                    if (d == (int)srcs.size()) srcs.push_back(src);
+                    ga.blk[e] = d;
+                    ga.gin[e] = ga.gdig[e] = ga.g[e];
+                }
+                const u64* digits;
+                if (srcs.size() == 1) {
+                    const u64* d = reg(srcs[0]) + (size_t)nl * rn;
+                    if (modup_owner != srcs[0]) {
+                        group_modup(c, 1, &d, 2 * nl, B, nl, w.pdcoef, w.pmodup, s);
+                        modup_owner = srcs[0];
+                    }
+                    ga.dsrc[0] = d;
+                    digits = w.pmodup;
+                } else {
+                    std::vector<const u64*> d(srcs.size());
+                    for (size_t q = 0; q < srcs.size(); ++q) d[q] = ga.dsrc[q] = reg(srcs[q]) + (size_t)nl * rn;
+                    group_modup(c, (int)srcs.size(), d.data(), 2 * nl, B, nl, w.dcoef, w.modup, s);
+                    digits = w.modup;
+                }
+                if (ext) group_switch_ext(c, ga, B, nl, digits, s);
+                else group_switch(c, ga, B, nl, true, digits, w.aux, w.U, w.Up, w.R, s);
             }
         } else if (ntt_fusable(c)) {
             // each rotation decomposes its own tau(c1): the inverse NTT reads
