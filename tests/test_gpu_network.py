@@ -488,3 +488,12 @@ def test_padding_rejected_by_the_planner():
               {"kind": "fc", "din": 50, "dout": 2}]
     with pytest.raises(P.UnihennError):
         P.Net(ctx, PAD_INPUT, pooled, W.gen_params(pooled))
+
+
+@pytest.mark.parametrize("name", ["k1", "k2s2", "fc_wide"])
+def test_degenerate_shapes_bit_exact(name):
+    """1 x 1 kernels, stride equal to the kernel, an FC wider than its input
+    and an FC to a single output (N = 2^11)."""
+    from tests.test_oracle_network import DEGENERATE_INPUT, DEGENERATE_NETS
+    _custom_parity(11, DEGENERATE_INPUT, DEGENERATE_NETS[name])
+    _custom_parity(11, DEGENERATE_INPUT, DEGENERATE_NETS[name], lazy=True)

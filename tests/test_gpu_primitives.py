@@ -25,7 +25,7 @@ def pair(request):
     return ck, ctx, ring
 
 
-@pytest.mark.parametrize("log_n", [4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15])
+@pytest.mark.parametrize("log_n", [4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16])
 def test_ntt_roundtrip_all_sizes(log_n):
     import torch
     from paper_2402_03060_amd import Context, device_u64, host_u64
@@ -224,3 +224,21 @@ def test_drop_level_parity(pair):
         got = ctx.drop_level(g_in, g_ones[:n], g_rlk)
         assert np.array_equal(ctx.export_ct(got)[0], exp.data), n
         assert got.n_limbs == nl - n and got.scale == exp.scale == ct.scale
+
+
+def test_largest_ring_rotation():
+    """The largest ring the library takes (N = 2^16, three primes), where the
+    oracle is too slow for a test: the product client's keys and ciphertext,
+    and rotations by 1 and by N/4 - 1 slots decrypting to the rolled slots
+    (a property that holds at any size)."""
+    import paper_2402_03060_amd as P
+    ctx = P.Context(16, [60, 40, 40], 60, 2.0 ** 40)
+    sk = P.keygen_secret(ctx, 93)
+    z = np.random.default_rng(94).uniform(-1, 1, ctx.slots)
+    ct = P.encrypt_sk(ctx, sk, ctx.encode(z, ctx.scale, 3, mont=False)[None], 95, ctx.scale)
+    ws = ctx.workspace(3, 1)
+    probe = np.arange(0, ctx.slots, 997, dtype=np.uint32)
+    for r in (1, ctx.slots // 2 - 1):
+        key = P.gen_switch_key(ctx, sk, 96, steps=r)
+        got = P.decrypt_slots(ctx, sk, ctx.rotate(ct, r, key, ws), probe)[0]
+        assert np.abs(got - np.roll(z, -r)[probe]).max() < 1e-6, r

@@ -399,3 +399,28 @@ def test_encrypted_padding(lazy):
     _, outs, _ = run_encrypted(sess, net, xs, lazy=lazy)
     got = read_outputs(net, [sess.ck.decrypt(o) for o in outs])
     assert np.abs(got[0] - cnn_fp64(xs[0], layers, params).reshape(-1)).max() < 1e-3
+
+
+# ------------------------------------------------------- degenerate shapes
+DEGENERATE_INPUT = {"c": 1, "h": 8, "w": 8, "dist": "uniform01"}
+DEGENERATE_NETS = {
+    # 1 x 1 kernels: Algorithm 1 with a single term per output (no rotation)
+    "k1": [{"kind": "conv", "ch_in": 1, "ch_out": 3, "k": 1, "s": 1}, W.SQUARE, W.FLATTEN,
+           {"kind": "fc", "din": 192, "dout": 4}],
+    # stride equal to the kernel (Theorem 1's boundary K = S)
+    "k2s2": [{"kind": "conv", "ch_in": 1, "ch_out": 2, "k": 2, "s": 2}, W.SQUARE, W.FLATTEN,
+             {"kind": "fc", "din": 32, "dout": 3}],
+    # FC wider than its input (one copy, no closing rotations) and an FC to one output
+    "fc_wide": [{"kind": "conv", "ch_in": 1, "ch_out": 1, "k": 3, "s": 1}, W.SQUARE, W.FLATTEN,
+                {"kind": "fc", "din": 36, "dout": 50}, W.SQUARE, {"kind": "fc", "din": 50, "dout": 1}],
+}
+
+
+@pytest.mark.parametrize("name", list(DEGENERATE_NETS))
+def test_degenerate_shapes_slot_simulation(name):
+    layers = DEGENERATE_NETS[name]
+    params = W.gen_params(layers)
+    xs = W.gen_inputs(DEGENERATE_INPUT, 1)
+    net = Net(DEGENERATE_INPUT, layers, params, 1024)
+    got = read_outputs(net, net.run(SlotEval(1024), net.input_vectors(xs)))
+    assert np.abs(got[0] - cnn_fp64(xs[0], layers, params).reshape(-1)).max() < 1e-12
