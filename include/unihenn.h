@@ -337,7 +337,10 @@ int unihenn_net_output_slots(const unihenn_net* net, uint64_t* positions, uint32
  *   ks_group      rotations per grouped key-switch launch set (net only)
  *   ks_order      workgroup order of the grouped inner product: 0 batch
  *                 chunks fastest (keys re-read from cache), 1 rotations
- *                 fastest (digits re-read from cache)
+ *                 fastest (digits re-read from cache), 2 (plain rotations;
+ *                 others take 0) one workgroup per output row that runs the
+ *                 row pass of the digits' forward NTT in LDS and accumulates
+ *                 its outputs, so the transformed digits never reach memory
  *   ntt_ms, net_ms  timings of the chosen setting (filled by autotune) */
 typedef struct {
     int32_t ntt_split;

@@ -54,7 +54,7 @@ struct unihenn_ctx {
     int ntt_tile_log = 11;            // LDS tile of the radix-8 passes: 2^11 or 2^12 words
     int mac_min_wg = 2048;            // workgroups a multi-output MAC launch aims for
     int ks_min_wg = 2048;             // workgroups a key-switch inner product aims for
-    int ks_order = 0;                 // workgroup order of the grouped inner product (0 or 1)
+    int ks_order = 0;                 // workgroup order of the grouped inner product (0, 1), 2: row-fused
 };
 
 // error reporting (thread-local message)
@@ -133,7 +133,16 @@ bool launch_ntt_inv_gather(const unihenn_ctx* c, u64* dcoef, const GatherArgs& g
 bool ntt_fusable(const unihenn_ctx* c);
 // ModUp (centered lift of each digit to every other target) fused with the
 // forward NTT of the lifted rows; false when not applicable
-bool launch_ntt_fwd_modup(const unihenn_ctx* c, u64* modup, const u64* dcoef, int n_src, int nl, hipStream_t st);
+bool launch_ntt_fwd_modup(const unihenn_ctx* c, u64* modup, const u64* dcoef, int n_src, int nl, hipStream_t st,
+                          bool row_pass = true);
+// ModUp row pass fused with the inner product of plain rotations
+// (k_ntt_r8_ksrow) over n_blocks = E B (element, batch entry) pairs; false
+// when the ring's transform split or the grid does not allow it
+bool ks_rowfusable(const unihenn_ctx* c, int nl, int n_blocks);
+struct GroupArgs;
+// requires ks_rowfusable(c, nl, ga.E * B)
+void launch_ks_rowfused(const unihenn_ctx* c, const GroupArgs& ga, int B, int nl, const u64* modup, u64* U, u64* Up,
+                        bool ext, hipStream_t st);
 
 // kernel timing hooks (per kernel family), see unihenn_stats_*
 enum KernelFamily : int {

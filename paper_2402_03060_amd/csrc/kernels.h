@@ -2,6 +2,15 @@
 #pragma once
 #include "internal.h"
 
+// NTT-form automorphism: entry k of tau_g(a) is entry perm(k) of a, where
+// 2 brev(perm(k)) + 1 = g (2 brev(k) + 1) mod 2N.
+__device__ __forceinline__ u32 auto_perm(u32 k, u32 g, int log_n)
+{
+    const u32 bk = __brev(k) >> (32 - log_n);
+    const u32 e = (u32)(((u64)g * (2u * bk + 1u)) & ((2u << log_n) - 1u));
+    return __brev((e - 1u) >> 1) >> (32 - log_n);
+}
+
 #define UH_MAC_MAX_TERMS 128
 
 // up to UH_MAC_MAX_TERMS (ciphertext batch, plaintext) pairs, passed by value
@@ -74,17 +83,25 @@ struct GroupArgs {
 // form): dcoef [D][B][nl] and modup [D][B][nl][nl]
 // perm (may be null): Galois element per block to read its rows through
 // (honoured only where the fused transforms apply: ntt_fusable)
-void group_modup(const unihenn_ctx* c, int D, const u64* const* dsrc, int dstride, int B, int nl, u64* dcoef,
-                 u64* modup, hipStream_t s, const u32* perm = nullptr);
+// row_pass = false asks to leave the digits after the column pass of their
+// forward NTT; returns true when it did so (the fused transforms apply and
+// ks_rowfusable holds), and then the inner product must run the row pass
+// (group_switch / group_switch_ext with row_fused).
+bool group_modup(const unihenn_ctx* c, int D, const u64* const* dsrc, int dstride, int B, int nl, u64* dcoef,
+                 u64* modup, hipStream_t s, const u32* perm = nullptr, bool row_pass = true);
 // inner product with each element's key, ModDown, and the c0 addend: aux holds
 // tau_g(src) per element ([E][B][2][nl]); with c0_only the c0 rows of aux
 // are computed here (hoisted), otherwise the caller filled aux.
+// row_fused: modup holds the ModUp digits after the column pass of their
+// forward NTT only (group_modup returned true); the row pass runs inside the
+// inner product (launch_ks_rowfused).  Plain rotations only (gin = 1).
 void group_switch(const unihenn_ctx* c, const GroupArgs& ga, int B, int nl, bool c0_only, const u64* modup, u64* aux,
-                  u64* U, u64* Up, u64* R, hipStream_t s);
+                  u64* U, u64* Up, u64* R, hipStream_t s, bool row_fused = false);
 // extended rotations (deferred ModDown): dst_e [B][2][nl+1] = (P tau(c0) +
 // U_0, U_1) over {q_0..q_{nl-1}, P}, U the inner product of the digits in
 // modup with element e's key; dst must not overlap any src
-void group_switch_ext(const unihenn_ctx* c, const GroupArgs& ga, int B, int nl, const u64* modup, hipStream_t s);
+void group_switch_ext(const unihenn_ctx* c, const GroupArgs& ga, int B, int nl, const u64* modup, hipStream_t s,
+                      bool row_fused = false);
 // aux[e] = tau_{g_e}(src_e), both polynomials
 void group_auto_both(const unihenn_ctx* c, const GroupArgs& ga, int B, int nl, u64* aux, hipStream_t s);
 

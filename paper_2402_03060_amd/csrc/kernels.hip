@@ -11,16 +11,6 @@ namespace {
 
 constexpr int EW_THREADS = 256;
 
-__device__ __forceinline__ u32 brev_bits(u32 x, int bits) { return __brev(x) >> (32 - bits); }
-
-// NTT-form automorphism: entry k of tau_g(a) is entry perm(k) of a, where
-// 2 brev(perm(k)) + 1 = g (2 brev(k) + 1) mod 2N.
-__device__ __forceinline__ u32 auto_perm(u32 k, u32 g, int log_n)
-{
-    u32 e = (u32)(((u64)g * (2u * brev_bits(k, log_n) + 1u)) & ((2u << log_n) - 1u));
-    return brev_bits((e - 1u) >> 1, log_n);
-}
-
 // Consecutive hardware workgroup ids are dealt to the 8 XCDs in turn (each
 // with its own L2).  For a 1D grid padded to a multiple of 8, hardware id w
 // runs logical workgroup (w mod 8) * (grid / 8) + w / 8, so every XCD holds a
@@ -584,10 +574,11 @@ __global__ void k_group_sub_scale(GroupArgs ga, const u64* __restrict__ U, const
 
 }  // namespace
 
-void group_modup(const unihenn_ctx* c, int D, const u64* const* dsrc, int dstride, int B, int nl, u64* dcoef,
-                 u64* modup, hipStream_t s, const u32* perm)
+bool group_modup(const unihenn_ctx* c, int D, const u64* const* dsrc, int dstride, int B, int nl, u64* dcoef,
+                 u64* modup, hipStream_t s, const u32* perm, bool row_pass)
 {
     if (ntt_fusable(c)) {
+        const bool skip = !row_pass && ks_rowfusable(c, nl, D * B);
         // the inverse NTT gathers (and permutes) its rows, the forward NTT lifts them
         GatherArgs gta;
         memset(&gta, 0, sizeof(gta));
@@ -596,8 +587,9 @@ void group_modup(const unihenn_ctx* c, int D, const u64* const* dsrc, int dstrid
             gta.perm[d] = perm ? perm[d] : 1u;
         }
         gta.stride = dstride;
-        if (launch_ntt_inv_gather(c, dcoef, gta, D, B, nl, s) && launch_ntt_fwd_modup(c, modup, dcoef, D * B * nl, nl, s))
-            return;
+        if (launch_ntt_inv_gather(c, dcoef, gta, D, B, nl, s) &&
+            launch_ntt_fwd_modup(c, modup, dcoef, D * B * nl, nl, s, !skip))
+            return skip;
     }
     GroupArgs ga;
     memset(&ga, 0, sizeof(ga));
@@ -609,9 +601,10 @@ void group_modup(const unihenn_ctx* c, int D, const u64* const* dsrc, int dstrid
         k_group_gather<<<g3, EW_THREADS, 0, s>>>(dcoef, ga, nl, B, c->n);
     }
     launch_ntt_inv(c, dcoef, D * B * nl, rowmap_ct(nl), s);
-    if (launch_ntt_fwd_modup(c, modup, dcoef, D * B * nl, nl, s)) return;
+    if (launch_ntt_fwd_modup(c, modup, dcoef, D * B * nl, nl, s)) return false;
     launch_modup(c, modup, dcoef, D * B, nl, s);
     launch_ntt_fwd(c, modup, D * B * nl * nl, rowmap_modup(nl, c->n_data), s);
+    return false;
 }
 
 namespace {
@@ -630,7 +623,7 @@ void launch_group_inner(const unihenn_ctx* c, const GroupArgs& ga, int B, int nl
     const unsigned gw = xcd_grid(W);
 #define GI(M)                                                                                                  \
     k_group_inner<M, EXT><<<gw, EW_THREADS, 0, s>>>(U, Up, modup, ga, c->dev, nl, c->n_data, B, bb, zb, (int)gx, W, \
-                                                    c->ks_order)
+                                                    c->ks_order == 1 ? 1 : 0)
     if (nl <= 4) GI(4);
     else if (nl <= 8) GI(8);
     else if (nl <= 12) GI(12);
@@ -639,17 +632,20 @@ void launch_group_inner(const unihenn_ctx* c, const GroupArgs& ga, int B, int nl
 }
 }  // namespace
 
-void group_switch_ext(const unihenn_ctx* c, const GroupArgs& ga, int B, int nl, const u64* modup, hipStream_t s)
+void group_switch_ext(const unihenn_ctx* c, const GroupArgs& ga, int B, int nl, const u64* modup, hipStream_t s,
+                      bool row_fused)
 {
-    launch_group_inner<true>(c, ga, B, nl, modup, nullptr, nullptr, s);
+    if (row_fused) launch_ks_rowfused(c, ga, B, nl, modup, nullptr, nullptr, true, s);
+    else launch_group_inner<true>(c, ga, B, nl, modup, nullptr, nullptr, s);
 }
 
 void group_switch(const unihenn_ctx* c, const GroupArgs& ga, int B, int nl, bool c0_only, const u64* modup, u64* aux,
-                  u64* U, u64* Up, u64* R, hipStream_t s)
+                  u64* U, u64* Up, u64* R, hipStream_t s, bool row_fused)
 {
     const int E = ga.E;
     const unsigned gx = (c->n + EW_THREADS - 1) / EW_THREADS;
-    launch_group_inner<false>(c, ga, B, nl, modup, U, Up, s);
+    if (row_fused) launch_ks_rowfused(c, ga, B, nl, modup, U, Up, false, s);
+    else launch_group_inner<false>(c, ga, B, nl, modup, U, Up, s);
     launch_ntt_inv(c, Up, E * B * 2, rowmap_list({c->n_data}), s);
     {
         // the c0 addend: tau(c0) read straight from the source (c0_only), or

@@ -1472,9 +1472,12 @@ struct Exec {
                     d[e] = ga.dsrc[e];
                     perm[e] = ga.g[e];
                 }
-                group_modup(c, ga.E, d.data(), 2 * nl, B, nl, w.dcoef, w.modup, s, perm.data());
-                if (ext) group_switch_ext(c, ga, B, nl, w.modup, s);
-                else group_switch(c, ga, B, nl, true, w.modup, w.aux, w.U, w.Up, w.R, s);
+                // workgroup order 2: the row pass of the digits' forward NTT
+                // runs inside the inner product
+                const bool rf = group_modup(c, ga.E, d.data(), 2 * nl, B, nl, w.dcoef, w.modup, s, perm.data(),
+                                            c->ks_order != 2);
+                if (ext) group_switch_ext(c, ga, B, nl, w.modup, s, rf);
+                else group_switch(c, ga, B, nl, true, w.modup, w.aux, w.U, w.Up, w.R, s, rf);
             }
             modup_owner = -1;
         } else {

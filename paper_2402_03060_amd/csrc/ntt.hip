@@ -17,7 +17,7 @@
 // size (2^11 or 2^12 words, with 2^8 or 2^9 threads) as a launch parameter.
 #include <cstring>
 
-#include "internal.h"
+#include "kernels.h"
 
 namespace {
 
@@ -204,6 +204,7 @@ __device__ __forceinline__ u64 mul_shoup_lazy_small(u64 x, u64 w, u64 w_sh, u64 
 // Row access of a pass: load/store one word at global index g of the row, or
 // two adjacent words (g even) on the contiguous 16-byte path.
 struct RowIO {
+    static constexpr bool kAccumulate = false;
     u64* __restrict__ a;
     __device__ __forceinline__ u64 load(int g) const { return a[g]; }
     __device__ __forceinline__ void store(int g, u64 v) const { a[g] = v; }
@@ -318,7 +319,9 @@ __device__ __forceinline__ void ntt_r8_body(u64* __restrict__ s, const IO& io, c
                 }
                 x[m] = v;
             }
-            if (!STRIDED && lo == 0) {
+            if constexpr (IO::kAccumulate) {
+                // handed to the policy after the loop
+            } else if (!STRIDED && lo == 0) {
 #pragma unroll
                 for (int h = 0; h < 4; ++h) io.store2(GIDX(ub) + 2 * h, x[2 * h], x[2 * h + 1]);
             } else {
@@ -327,6 +330,9 @@ __device__ __forceinline__ void ntt_r8_body(u64* __restrict__ s, const IO& io, c
             }
         }
     }
+    // accumulating policies (contiguous forward passes only) take the
+    // thread's eight outputs, which are the consecutive slots of its last round
+    if constexpr (IO::kAccumulate) io.acc8(x);
 #undef GIDX
 #undef LIDX
 }
@@ -358,6 +364,7 @@ __global__ void __launch_bounds__((1 << TILE_LOG) / 8) k_ntt_r8(u64* __restrict_
 //   row pass:    reads R in place and, instead of storing the transform t,
 //                stores out_e[p][i] = (x_e[p][i] - t) * inv_i (+ addend).
 struct LiftIO {
+    static constexpr bool kAccumulate = false;
     const u64* __restrict__ src;
     u64* __restrict__ a;
     u64 p_half, p_mod_q, q, ratio;
@@ -375,6 +382,7 @@ struct LiftIO {
 };
 
 struct FinishIO {
+    static constexpr bool kAccumulate = false;
     u64* __restrict__ a;                 // R row (read)
     const u64* __restrict__ x;           // minuend row
     const u64* __restrict__ add;         // addend row or null
@@ -458,6 +466,7 @@ __global__ void __launch_bounds__((1 << TILE_LOG) / 8) k_ntt_r8_lift(u64* __rest
 // r = (blk * B + b) * nl + j reads limb j of polynomial b of source block blk,
 // through the automorphism of Galois element perm[blk] when it is not 1.
 struct GatherIO {
+    static constexpr bool kAccumulate = false;
     const u64* __restrict__ src;
     u64* __restrict__ a;
     u32 perm;
@@ -487,6 +496,133 @@ struct GatherIO {
         *reinterpret_cast<ulonglong2*>(a + g) = make_ulonglong2(v0, v1);
     }
 };
+
+// Row-pass outputs of one digit row go into the key-switch sums.  In the
+// last round of a contiguous forward pass a thread holds the eight
+// consecutive slots base + m (the held bits are the lowest three).  Each
+// product is a reduced Montgomery product (one word per sum keeps the
+// thread's sixteen sums small in registers).
+struct KsIO {
+    static constexpr bool kAccumulate = true;
+    const u64* __restrict__ a;       // digit row (column-pass output)
+    const u64* __restrict__ k0;      // key rows of this digit, this limb, from the thread's first slot
+    const u64* __restrict__ k1;
+    u64 q, qinv_neg;
+    u64* acc0;
+    u64* acc1;
+    __device__ __forceinline__ u64 load(int g) const { return a[g]; }
+    __device__ __forceinline__ void load2(int g, u64& v0, u64& v1) const
+    {
+        const ulonglong2 v = *reinterpret_cast<const ulonglong2*>(a + g);
+        v0 = v.x;
+        v1 = v.y;
+    }
+    __device__ __forceinline__ void acc8(const u64 (&x)[8]) const
+    {
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            acc0[m] = add_mod(acc0[m], mont_mul(x[m], k0[m], q, qinv_neg), q);
+            acc1[m] = add_mod(acc1[m], mont_mul(x[m], k1[m], q, qinv_neg), q);
+        }
+    }
+};
+
+// The row pass of ModUp's forward NTT fused with the key-switch inner
+// product of a group of rotations whose digits are those of tau(c1) itself
+// (plain rotations).  Workgroup (tile, r = (e B + b)(nl + 1) + t) owns the
+// tile's slots of target limb t (t = nl: P) of element e, batch entry b.  It
+// starts its sums with the digit of limb t itself (limb t of tau(c1), read
+// from dsrc through gdig), then for each digit j != t runs the row pass of
+// modup row ((blk_e B + b) nl + j) nl + s (s: the target's place among digit
+// j's targets; the column pass is done) in LDS and adds its outputs times
+// element e's key rows (j, c, t).  The sums go to U (t < nl) / Up (t = nl),
+// or with EXT to dst_e as (P tau(c0) + U_0, U_1).  The transformed digits
+// never reach memory.  Needs nl >= 2 (at least one digit row per target).
+template <int LOG_R, int TILE_LOG, bool EXT>
+__global__ void __launch_bounds__((1 << TILE_LOG) / 8) k_ntt_r8_ksrow(u64* __restrict__ U, u64* __restrict__ Up,
+                                                                      const u64* __restrict__ modup, GroupArgs ga,
+                                                                      DevCtx ctx, int nl, int nd, int B, int log_cols,
+                                                                      int sigma0)
+{
+    constexpr int T = 1 << TILE_LOG;
+    __shared__ u64 s[T + T / 8];
+    const int n = ctx.n;
+    const int r = blockIdx.y;
+    const int t = r % (nl + 1), eb = r / (nl + 1);
+    const int e = eb / B, b = eb % B;
+    const int tm = t == nl ? ctx.p_index : t;
+    const int klimb = t == nl ? nd : t;
+    const Modulus M = ctx.mod[tm];
+    const u64* __restrict__ tw = ctx.tw + (size_t)tm * n;
+    const u64* __restrict__ tw_sh = ctx.tw_sh + (size_t)tm * n;
+    const int blk = ga.blk[e];
+    const u64* __restrict__ key = ga.key[e];
+    const bool small = M.q < (1ull << 40);
+    // the thread's slots in the last round (thread layout of the contiguous pass)
+    const int gth = threadIdx.x & ((1 << (LOG_R - 3)) - 1), cth = threadIdx.x >> (LOG_R - 3);
+    const int base = (((blockIdx.x << log_cols) + cth) << LOG_R) + (gth << 3);
+    u64 a0[8], a1[8];
+    if (t < nl) {
+        const u64* __restrict__ dl = ga.dsrc[blk] + ((size_t)b * ga.dstride + t) * n;
+        const u64* __restrict__ k0 = key + (((size_t)t * 2 + 0) * (nd + 1) + klimb) * n;
+        const u64* __restrict__ k1 = key + (((size_t)t * 2 + 1) * (nd + 1) + klimb) * n;
+        const u32 gd = ga.gdig[e];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            const u64 d = dl[auto_perm((u32)(base + m), gd, ctx.log_n)];
+            a0[m] = mont_mul(d, k0[base + m], M.q, M.qinv_neg);
+            a1[m] = mont_mul(d, k1[base + m], M.q, M.qinv_neg);
+        }
+    } else {
+#pragma unroll
+        for (int m = 0; m < 8; ++m) a0[m] = a1[m] = 0;
+    }
+#pragma unroll 1
+    for (int j = 0; j < nl; ++j) {
+        if (j == t) continue;
+        const int sidx = t < j ? t : t - 1;
+        const KsIO io{modup + ((((size_t)blk * B + b) * nl + j) * nl + sidx) * n,
+                      key + (((size_t)j * 2 + 0) * (nd + 1) + klimb) * n + base,
+                      key + (((size_t)j * 2 + 1) * (nd + 1) + klimb) * n + base, M.q, M.qinv_neg, a0, a1};
+        // the twiddle tables are the same for every row: an opaque copy of
+        // their (uniform) addresses keeps the compiler from holding every
+        // twiddle address of the pass in vector registers across rows
+        const u64* twr = tw;
+        const u64* twr_sh = tw_sh;
+        asm volatile("" : "+v"(twr), "+v"(twr_sh));
+        if (small)
+            ntt_r8_body<LOG_R, TILE_LOG, false, false, true, true>(s, io, M, twr, twr_sh, ctx.log_n, log_cols, sigma0);
+        else
+            ntt_r8_body<LOG_R, TILE_LOG, false, false, true, false>(s, io, M, twr, twr_sh, ctx.log_n, log_cols, sigma0);
+        __syncthreads();  // the next row's first LDS writes must follow this row's last reads
+    }
+    u64 *o0, *o1;
+    if (EXT) {
+        const size_t row = (size_t)b * 2 * (nl + 1) + t;
+        o0 = ga.dst[e] + row * n;
+        o1 = ga.dst[e] + (row + nl + 1) * n;
+        if (t < nl) {
+            const u64 pm = ctx.p_mod[2 * t], pm_sh = ctx.p_mod[2 * t + 1];
+            const u64* __restrict__ c0 = ga.src[e] + ((size_t)b * 2 * nl + t) * n;
+#pragma unroll
+            for (int m = 0; m < 8; ++m) {
+                const u64 x = c0[auto_perm((u32)(base + m), ga.g[e], ctx.log_n)];
+                a0[m] = add_mod(a0[m], mul_shoup(x, pm, pm_sh, M.q), M.q);
+            }
+        }
+    } else if (t < nl) {
+        o0 = U + (((size_t)eb * 2 + 0) * nl + t) * n;
+        o1 = U + (((size_t)eb * 2 + 1) * nl + t) * n;
+    } else {
+        o0 = Up + ((size_t)eb * 2 + 0) * n;
+        o1 = Up + ((size_t)eb * 2 + 1) * n;
+    }
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+        *reinterpret_cast<ulonglong2*>(o0 + base + 2 * h) = make_ulonglong2(a0[2 * h], a0[2 * h + 1]);
+        *reinterpret_cast<ulonglong2*>(o1 + base + 2 * h) = make_ulonglong2(a1[2 * h], a1[2 * h + 1]);
+    }
+}
 
 template <int LOG_R, int TILE_LOG>
 __global__ void __launch_bounds__((1 << TILE_LOG) / 8) k_intt_r8_gather(u64* __restrict__ dcoef, DevCtx ctx,
@@ -694,7 +830,8 @@ bool launch_ntt_fwd_fused(const unihenn_ctx* c, u64* R, const FuseArgs& fa, int 
 // (polynomial b, digit j) = row b * nl + j; modup receives rows
 // ((b * nl + j) * nl + s), the digit lifted to target s < j ? s : s + 1 and
 // transformed.  False when a pass is outside the radix-8 kernels.
-bool launch_ntt_fwd_modup(const unihenn_ctx* c, u64* modup, const u64* dcoef, int n_src, int nl, hipStream_t st)
+bool launch_ntt_fwd_modup(const unihenn_ctx* c, u64* modup, const u64* dcoef, int n_src, int nl, hipStream_t st,
+                          bool row_pass)
 {
     int l1, l2;
     split(c, &l1, &l2);
@@ -720,12 +857,50 @@ bool launch_ntt_fwd_modup(const unihenn_ctx* c, u64* modup, const u64* dcoef, in
 #undef LCT
 #undef LC
     }
-    {
+    if (row_pass) {
         LaunchTimer tm(KF_NTT_FWD_ROW, 16.0 * c->n * n_rows, st, half * l2);
         launch_pass_r8(modup, c->dev, rowmap_modup(nl, c->n_data), n_rows, c->log_n, l2, l1, false, false, true, tile,
                        1, st);
     }
     return true;
+}
+
+bool ks_rowfusable(const unihenn_ctx* c, int nl, int n_blocks)
+{
+    int l1, l2;
+    split(c, &l1, &l2);
+    // one grid row per (block, target limb)
+    return nl >= 2 && l1 >= 3 && l1 <= 8 && l2 >= 3 && l2 <= 8 && (long)n_blocks * (nl + 1) <= 65535;
+}
+
+void launch_ks_rowfused(const unihenn_ctx* c, const GroupArgs& ga, int B, int nl, const u64* modup, u64* U, u64* Up,
+                        bool ext, hipStream_t st)
+{
+    int l1, l2;
+    split(c, &l1, &l2);
+    const int tile = c->ntt_tile_log == 12 ? 12 : 11;
+    const int E = ga.E;
+    // digit rows (column-pass output) once, keys, the same-limb digits, the outputs (and c0 when extended)
+    const double rows = (double)E * B * ((double)(nl + 1) * nl - nl) + (double)E * 2 * nl * (nl + 1) +
+                        (double)E * B * nl + (double)E * B * 2 * (nl + 1) + (ext ? (double)E * B * nl : 0.0);
+    // work in butterfly equivalents: the row passes' butterflies plus the
+    // products with the keys (two per digit row and slot), each a reduced
+    // Montgomery product of about 52 VALU lane slots against 38 per butterfly
+    const double bfly = (double)E * B * nl * nl * 0.5 * c->n * l2;
+    const double macs = (double)E * B * nl * (nl + 1) * 2.0 * c->n;
+    LaunchTimer tm(KF_KS_INNER, 8.0 * c->n * rows, st, bfly + macs * 52.0 / 38.0);
+    const int avail_log = c->log_n - l2;
+    int lc = tile - l2;
+    if (lc > avail_log) lc = avail_log;
+    const int thr = 1 << (l2 - 3 + lc);
+    dim3 grid(1 << (avail_log - lc), E * B * (nl + 1));
+#define KR(K, TL)                                                                                             \
+    if (ext) k_ntt_r8_ksrow<K, TL, true><<<grid, thr, 0, st>>>(U, Up, modup, ga, c->dev, nl, c->n_data, B, lc, l1); \
+    else k_ntt_r8_ksrow<K, TL, false><<<grid, thr, 0, st>>>(U, Up, modup, ga, c->dev, nl, c->n_data, B, lc, l1)
+#define KRT(K) case K: if (tile == 12) { KR(K, 12); } else { KR(K, 11); } break;
+    switch (l2) { KRT(3) KRT(4) KRT(5) KRT(6) KRT(7) KRT(8) }
+#undef KRT
+#undef KR
 }
 
 // Inverse NTT of gathered rows: dcoef row (blk * B + b) * nl + j is limb j

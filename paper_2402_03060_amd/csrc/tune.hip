@@ -177,7 +177,7 @@ int apply(unihenn_ctx* c, unihenn_net* net, const unihenn_tuning* t)
     if (t->ntt_split > 0 && t->ntt_split >= c->log_n) return uh_fail(UNIHENN_EINVAL, "NTT split out of range");
     if (t->ntt_tile_log > 0 && t->ntt_tile_log != 11 && t->ntt_tile_log != 12)
         return uh_fail(UNIHENN_EINVAL, "NTT tile must be 2^11 or 2^12 words");
-    if (t->ks_order != 0 && t->ks_order != 1) return uh_fail(UNIHENN_EINVAL, "workgroup order must be 0 or 1");
+    if (t->ks_order < 0 || t->ks_order > 2) return uh_fail(UNIHENN_EINVAL, "workgroup order must be 0, 1 or 2");
     if (net && t->ks_group > 0) {
         int rc = net_set_ks_group(c, net, t->ks_group);
         if (rc) return rc;
@@ -300,7 +300,9 @@ extern "C" int unihenn_autotune(unihenn_ctx* c, unihenn_net* net, uint32_t batch
             // group size, under each workgroup order of the inner product
             const int cap = net_ks_group_cap(c, net);
             int g_best = net_ks_group(net), o_best = c->ks_order;
-            for (int order = 0; order < 2 && !rc; ++order) {
+            // order 2 (row-fused inner product) applies to plain rotations only
+            const int n_orders = (net_mode(net) & UNIHENN_EVAL_HOISTED) ? 2 : 3;
+            for (int order = 0; order < n_orders && !rc; ++order) {
                 c->ks_order = order;
                 for (int e = 1; e <= cap && !rc; e *= 2) {
                     if (e == g_best && order == o_best) continue;

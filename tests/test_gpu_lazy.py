@@ -109,8 +109,9 @@ def test_lazy_plan_differs_and_rejects_extended_conv_input():
 
 
 def test_lazy_workgroup_orders_and_groups_identical():
-    """Both workgroup orders of the extended inner product, at several group
-    sizes, give the oracle's residues (LeNet-1 at N = 2^11, hoisted and plain)."""
+    """Every workgroup order of the extended inner product (the row-fused one
+    on the plain path), at several group sizes, gives the oracle's residues
+    (LeNet-1 at N = 2^11, hoisted and plain)."""
     import paper_2402_03060_amd as P
     from oracle.run import build_net
     from tests.test_gpu_network import _gpu_net
@@ -124,7 +125,8 @@ def test_lazy_workgroup_orders_and_groups_identical():
     gnet = _gpu_net(P, ctx, cfg, sess, onet, lazy=True)
     gin = ctx.import_ct(ct.data[None], ct.scale)
     for setting in ({"ks_group": 8, "ks_order": 1}, {"ks_group": 32, "ks_order": 1, "ks_min_wg": 512},
-                    {"ks_group": 3, "ks_order": 0}):
+                    {"ks_group": 3, "ks_order": 0}, {"ks_group": 8, "ks_order": 2},
+                    {"ks_group": 3, "ks_order": 2, "ntt_tile_log": 12}):
         gnet.set_tuning(**setting)
         for mode in (P.EVAL_PLAIN, P.EVAL_HOISTED):
             gnet.set_mode(mode)

@@ -297,8 +297,9 @@ def test_lenet1_full_size_golden():
 
 def test_autotune_keeps_results_and_caches(tmp_path):
     """The tuner's settings (group sizes, workgroup targets, NTT split and
-    tile) leave the network outputs bit-identical to the oracle's; a second
-    call with the same cache file applies the stored setting."""
+    tile, the inner product's workgroup order including the row-fused one)
+    leave the network outputs bit-identical to the oracle's; a second call
+    with the same cache file applies the stored setting."""
     import json
     import paper_2402_03060_amd as P
     cfg = W.config("lenet1_batched")
@@ -327,9 +328,13 @@ def test_autotune_keeps_results_and_caches(tmp_path):
 
     for setting in ({"ks_group": 1}, {"ks_group": 2, "mac_min_wg": 512}, {"ks_min_wg": 8192, "mac_min_wg": 8192},
                     {"ntt_split": 5, "ntt_tile_log": 12}, {"ntt_split": 7, "ntt_tile_log": 11, "ks_group": 4},
-                    {"ks_group": 4, "ks_order": 1}, {"ks_group": 1, "ks_order": 1, "ks_min_wg": 512}):
+                    {"ks_group": 4, "ks_order": 1}, {"ks_group": 1, "ks_order": 1, "ks_min_wg": 512},
+                    {"ks_group": 4, "ks_order": 2}, {"ks_group": 1, "ks_order": 2, "ntt_split": 5, "ntt_tile_log": 12},
+                    {"ks_group": 8, "ks_order": 2, "ntt_split": 4, "ntt_tile_log": 11}):
         net.set_tuning(**setting)
         check(setting)
+    with pytest.raises(P.UnihennError):
+        net.set_tuning(ks_order=3)
     cache = str(tmp_path / "tuning.json")
     net.set_mode(P.EVAL_HOISTED)
     first = net.autotune(cache_path=cache)
