@@ -736,30 +736,49 @@ __global__ void __launch_bounds__(EW_THREADS) k_mac_multi(MacMulti m, int n_out,
                                    ? m.acc[o0 + o][(((size_t)b * 2 + c) * nl + i) * n + k] : 0);
         }
     const size_t row = (size_t)nl * n;
+    // Terms go in chunks of UNR whose loads are all issued before their
+    // products, so that a thread with few accumulators still keeps several
+    // rows in flight (the one-image MAC is bound by plaintext reads; each
+    // plaintext word is read once, so those loads are non-temporal).  A fold
+    // comes before any chunk that would take the products since the last one
+    // past the period.
+    constexpr int UNR = OPT * BCH <= 2 ? 4 : (OPT * BCH <= 4 ? 2 : 1);
     int since = 0;
-    for (int t = 0; t < n_terms; ++t) {
-        u64 v[2 * BCH];
-#pragma unroll
-        for (int u = 0; u < 2 * BCH; ++u) {
-            const int b = b0 + u / 2, c = u & 1;
-            v[u] = b < batch ? m.ct[t][(((size_t)b * 2 + c) * nl + i) * n + k] : 0;
-        }
-        const u64* p0 = m.pt_base + (size_t)(m.t_off + t) * row + (size_t)i * n + k;
-#pragma unroll
-        for (int o = 0; o < OPT; ++o) {
-            if (o0 + o < n_out) {
-                const u64 p = p0[(size_t)(o0 + o) * m.o_stride * row];
-#pragma unroll
-                for (int u = 0; u < 2 * BCH; ++u) wide_mac(a[o][u], p, v[u]);
-            }
-        }
-        if (++since == period) {
+    for (int t0 = 0; t0 < n_terms; t0 += UNR) {
+        const int nt = n_terms - t0 < UNR ? n_terms - t0 : UNR;
+        if (since + nt > period) {
 #pragma unroll
             for (int o = 0; o < OPT; ++o)
 #pragma unroll
                 for (int u = 0; u < 2 * BCH; ++u) wide_fold(a[o][u], M.q, M.qinv_neg);
             since = 0;
         }
+        u64 v[UNR][2 * BCH], p[UNR][OPT];
+#pragma unroll
+        for (int h = 0; h < UNR; ++h) {
+            const int t = t0 + h;
+            const bool live = h < nt;
+#pragma unroll
+            for (int u = 0; u < 2 * BCH; ++u) {
+                const int b = b0 + u / 2, c = u & 1;
+                v[h][u] = live && b < batch ? m.ct[t][(((size_t)b * 2 + c) * nl + i) * n + k] : 0;
+            }
+            const u64* p0 = m.pt_base + (size_t)(m.t_off + t) * row + (size_t)i * n + k;
+#pragma unroll
+            for (int o = 0; o < OPT; ++o)
+                p[h][o] = live && o0 + o < n_out
+                              ? __builtin_nontemporal_load(p0 + (size_t)(o0 + o) * m.o_stride * row) : 0;
+        }
+#pragma unroll
+        for (int h = 0; h < UNR; ++h) {
+            if (h < nt) {
+#pragma unroll
+                for (int o = 0; o < OPT; ++o)
+#pragma unroll
+                    for (int u = 0; u < 2 * BCH; ++u) wide_mac(a[o][u], p[h][o], v[h][u]);
+            }
+        }
+        since += nt;
     }
 #pragma unroll
     for (int o = 0; o < OPT; ++o)
