@@ -212,6 +212,7 @@ extern "C" int unihenn_ctx_create(uint32_t log_n, const uint32_t* prime_bits, ui
     }
     unihenn_ctx* c = new unihenn_ctx();
     c->log_n = (int)log_n;
+    if (const char* v = getenv("UNIHENN_KS_FUSE_MIN_WG")) c->ks_fuse_min_wg = atoi(v);
     c->n = 1 << log_n;
     c->n_data = (int)n_data;
     c->scale = scale;

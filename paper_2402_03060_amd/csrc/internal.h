@@ -55,6 +55,8 @@ struct unihenn_ctx {
     int mac_min_wg = 2048;            // workgroups a multi-output MAC launch aims for
     int ks_min_wg = 2048;             // workgroups a key-switch inner product aims for
     int ks_order = 0;                 // workgroup order of the grouped inner product (0, 1), 2: row-fused
+    int ks_fuse_min_wg = 384;         // order 2 fuses only launches of at least this many workgroups
+                                      // (environment UNIHENN_KS_FUSE_MIN_WG at context creation)
 };
 
 // error reporting (thread-local message)

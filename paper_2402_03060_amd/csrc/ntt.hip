@@ -870,7 +870,17 @@ bool ks_rowfusable(const unihenn_ctx* c, int nl, int n_blocks)
     int l1, l2;
     split(c, &l1, &l2);
     // one grid row per (block, target limb)
-    return nl >= 2 && l1 >= 3 && l1 <= 8 && l2 >= 3 && l2 <= 8 && (long)n_blocks * (nl + 1) <= 65535;
+    if (nl < 2 || l1 < 3 || l1 > 8 || l2 < 3 || l2 > 8 || (long)n_blocks * (nl + 1) > 65535) return false;
+    // Each workgroup runs its n - 1 or n row passes one after another, so a
+    // small group (few rotations at few limbs) is faster unfused, where the
+    // row pass and the inner product each spread over many more workgroups:
+    // fuse only with at least ks_fuse_min_wg workgroups (default 384, 1.5
+    // per CU of a 256-CU device; measured on plain LeNet-1: 160 workgroups
+    // 30 us fused against 19 us unfused, 432 workgroups 24 us against 28 us).
+    const int tile = c->ntt_tile_log == 12 ? 12 : 11;
+    const int avail_log = c->log_n - l2;
+    const int lc = tile - l2 < avail_log ? tile - l2 : avail_log;
+    return ((long)n_blocks * (nl + 1) << (avail_log - lc)) >= c->ks_fuse_min_wg;
 }
 
 void launch_ks_rowfused(const unihenn_ctx* c, const GroupArgs& ga, int B, int nl, const u64* modup, u64* U, u64* Up,

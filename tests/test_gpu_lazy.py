@@ -108,10 +108,14 @@ def test_lazy_plan_differs_and_rejects_extended_conv_input():
         gnet.conv(3, ins, 12, nl - 1)
 
 
-def test_lazy_workgroup_orders_and_groups_identical():
+@pytest.mark.parametrize("fuse_min_wg", [None, "0"])
+def test_lazy_workgroup_orders_and_groups_identical(monkeypatch, fuse_min_wg):
     """Every workgroup order of the extended inner product (the row-fused one
-    on the plain path), at several group sizes, gives the oracle's residues
-    (LeNet-1 at N = 2^11, hoisted and plain)."""
+    on the plain path, also forced onto every group), at several group
+    sizes, gives the oracle's residues (LeNet-1 at N = 2^11, hoisted and
+    plain)."""
+    if fuse_min_wg is not None:
+        monkeypatch.setenv("UNIHENN_KS_FUSE_MIN_WG", fuse_min_wg)
     import paper_2402_03060_amd as P
     from oracle.run import build_net
     from tests.test_gpu_network import _gpu_net

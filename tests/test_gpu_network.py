@@ -295,7 +295,7 @@ def test_lenet1_full_size_golden():
         assert _digest(got) == rec["outputs_sha256"], mode
 
 
-def test_autotune_keeps_results_and_caches(tmp_path):
+def test_autotune_keeps_results_and_caches(tmp_path, monkeypatch):
     """The tuner's settings (group sizes, workgroup targets, NTT split and
     tile, the inner product's workgroup order including the row-fused one)
     leave the network outputs bit-identical to the oracle's; a second call
@@ -335,6 +335,16 @@ def test_autotune_keeps_results_and_caches(tmp_path):
         check(setting)
     with pytest.raises(P.UnihennError):
         net.set_tuning(ks_order=3)
+    # the row-fused kernel on every group, however small (by default small
+    # groups stay unfused)
+    monkeypatch.setenv("UNIHENN_KS_FUSE_MIN_WG", "0")
+    ctx = _ctx(P, cfg)
+    net = _gpu_net(P, ctx, cfg, sess, onet, batch=n_cts)
+    gin = ctx.import_ct(np.stack([c.data for c in cts]), cts[0].scale)
+    for setting in ({"ks_group": 4, "ks_order": 2}, {"ks_group": 1, "ks_order": 2, "ntt_split": 5, "ntt_tile_log": 12},
+                    {"ks_group": 8, "ks_order": 2, "ntt_split": 4, "ntt_tile_log": 11}):
+        net.set_tuning(**setting)
+        check(("fused everywhere", setting))
     cache = str(tmp_path / "tuning.json")
     net.set_mode(P.EVAL_HOISTED)
     first = net.autotune(cache_path=cache)
