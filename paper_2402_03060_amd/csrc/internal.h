@@ -107,7 +107,7 @@ void launch_ntt_inv(const unihenn_ctx* c, u64* data, int n_rows, const RowMap& m
 //   out[e][p][i] = (x[e][(p * x_limbs + i)] - R[r]) * inv_i
 //                  + add[e][p & 1][((p >> 1) * add_stride + i)] (read through
 //                  the automorphism of Galois element add_perm[e] when != 1)
-#define UH_FUSE_MAX 32
+#define UH_FUSE_MAX 64
 struct FuseArgs {
     const u64* src;
     int src_mod;

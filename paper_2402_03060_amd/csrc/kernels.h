@@ -66,7 +66,7 @@ void ks_finish(const unihenn_ctx* c, const u64* d, int d_stride, const u64* key,
 void rescale_core(const unihenn_ctx* c, const u64* in, int batch, int nl, u64* out, KsWs& ws, hipStream_t s);
 
 // ---- grouped rotations (several rotations per launch set) ----
-#define UH_GROUP_MAX 32
+#define UH_GROUP_MAX 64
 struct GroupArgs {
     int E;                          // rotations in the group
     const u64* src[UH_GROUP_MAX];   // source ciphertexts [B][2][nl]

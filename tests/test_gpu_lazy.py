@@ -129,7 +129,7 @@ def test_lazy_workgroup_orders_and_groups_identical(monkeypatch, fuse_min_wg):
     gnet = _gpu_net(P, ctx, cfg, sess, onet, lazy=True)
     gin = ctx.import_ct(ct.data[None], ct.scale)
     for setting in ({"ks_group": 8, "ks_order": 1}, {"ks_group": 32, "ks_order": 1, "ks_min_wg": 512},
-                    {"ks_group": 3, "ks_order": 0}, {"ks_group": 8, "ks_order": 2},
+                    {"ks_group": 3, "ks_order": 0}, {"ks_group": 8, "ks_order": 2}, {"ks_group": 64, "ks_order": 2},
                     {"ks_group": 3, "ks_order": 2, "ntt_tile_log": 12}):
         gnet.set_tuning(**setting)
         for mode in (P.EVAL_PLAIN, P.EVAL_HOISTED):

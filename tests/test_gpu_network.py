@@ -337,7 +337,8 @@ def test_autotune_keeps_results_and_caches(tmp_path, monkeypatch):
                     {"ntt_split": 5, "ntt_tile_log": 12}, {"ntt_split": 7, "ntt_tile_log": 11, "ks_group": 4},
                     {"ks_group": 4, "ks_order": 1}, {"ks_group": 1, "ks_order": 1, "ks_min_wg": 512},
                     {"ks_group": 4, "ks_order": 2}, {"ks_group": 1, "ks_order": 2, "ntt_split": 5, "ntt_tile_log": 12},
-                    {"ks_group": 8, "ks_order": 2, "ntt_split": 4, "ntt_tile_log": 11}):
+                    {"ks_group": 8, "ks_order": 2, "ntt_split": 4, "ntt_tile_log": 11},
+                    {"ks_group": 64, "ks_order": 2}, {"ks_group": 64, "ks_order": 1}):
         net.set_tuning(**setting)
         check(setting)
     with pytest.raises(P.UnihennError):
