@@ -269,8 +269,8 @@ def test_lenet1_full_size_golden():
     oracle keys and an oracle ciphertext: the GPU outputs hash to the digest
     the oracle wrote (tests/golden/make_lenet1_golden.py), in plain graph
     replay and hoisted modes, and in plain mode under the row-fused inner
-    product at the benchmark's launch shape (groups of 32, NTT splits 6 and
-    7: large groups fused, small ones not)."""
+    product at the benchmark's launch shapes (groups of 32 and 64, NTT
+    splits 6 and 7: large groups fused, small ones not)."""
     import json
     import os
     import paper_2402_03060_amd as P
@@ -295,11 +295,11 @@ def test_lenet1_full_size_golden():
         got = [ctx.export_ct(o)[0] for o in outs]
         assert [g.shape[1] for g in got] == rec["output_limbs"]
         assert _digest(got) == rec["outputs_sha256"], mode
-    for split in (6, 7):
-        gnet.set_tuning(ks_group=32, ks_order=2, ntt_split=split, ntt_tile_log=11)
+    for group, split in ((32, 6), (32, 7), (64, 6)):
+        gnet.set_tuning(ks_group=group, ks_order=2, ntt_split=split, ntt_tile_log=11)
         gnet.set_mode(P.EVAL_PLAIN | P.EVAL_GRAPH)
         got = [ctx.export_ct(o)[0] for o in gnet.eval(gin)]
-        assert _digest(got) == rec["outputs_sha256"], ("row-fused", split)
+        assert _digest(got) == rec["outputs_sha256"], ("row-fused", group, split)
 
 
 def test_autotune_keeps_results_and_caches(tmp_path, monkeypatch):
