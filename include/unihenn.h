@@ -334,13 +334,17 @@ int unihenn_net_output_slots(const unihenn_net* net, uint64_t* positions, uint32
  *                 outputs per thread against parallelism)
  *   ks_min_wg     workgroups a key-switch inner product aims for (it splits
  *                 the batch to reach it)
- *   ks_group      rotations per grouped key-switch launch set (net only)
+ *   ks_group      rotations per grouped key-switch launch set, 1..64 (net
+ *                 only)
  *   ks_order      workgroup order of the grouped inner product: 0 batch
  *                 chunks fastest (keys re-read from cache), 1 rotations
  *                 fastest (digits re-read from cache), 2 (plain rotations;
  *                 others take 0) one workgroup per output row that runs the
  *                 row pass of the digits' forward NTT in LDS and accumulates
  *                 its outputs, so the transformed digits never reach memory
+ *                 (launches below 384 workgroups, or the value of the
+ *                 environment variable UNIHENN_KS_FUSE_MIN_WG when the
+ *                 context was created, stay unfused)
  *   ntt_ms, net_ms  timings of the chosen setting (filled by autotune) */
 typedef struct {
     int32_t ntt_split;
