@@ -7,15 +7,20 @@ evaluated layer by layer (the paper's method as written).  A step is one
 whole encrypted inference; its input ciphertext and the evaluation keys are
 resident in HBM before the timer starts.
 
-Also reported on the same JSON line:
+The last stdout line is one compact JSON object (see `headline`):
   batched   - the batched evaluator (ten 28 x 28 images per ciphertext at
-              stride 784, many ciphertexts per launch, hoisted rotations):
-              images/s and its multiple of the plain rate;
-  rotations - rotations/s of a single rotation at the same size;
-  roofline  - the dominant kernel family, timed with HIP events on its launch
-              stream over a replay of the timed steps;
-  cpu_baseline - the CPU oracle (scalar C, one thread) timed on one whole
-              inference of the same workload.
+              stride 784, 128 ciphertexts per launch, hoisted rotations, one
+              HIP graph): images/s, launch-time distribution and its multiple
+              of the plain rate; the same for the 1D CNN (8 sequences x 64);
+  rotations - rotations/s of one rotation at the same size, and a sweep over
+              ring sizes (single, 24 hoisted, 128 ciphertexts per launch);
+  serving   - the three-model server under Poisson load: p50/p99 latency;
+  roofline  - the dominant kernel, timed with HIP events on its launch stream
+              over a replay of the timed steps, on its algorithmic bytes;
+  cpu_baseline - the CPU oracle (scalar C, one thread per process) on the
+              host's cores.
+The full result (kernel-family tables, tuning, plan variants) goes to the
+file named by --detail, whose path is printed on stderr.
 """
 from __future__ import annotations
 
@@ -23,6 +28,7 @@ import argparse
 import json
 import os
 import sys
+import tempfile
 import time
 
 import numpy as np
@@ -205,23 +211,22 @@ def measured_traffic(family: str, workload: str = "lenet1_plain"):
             "source": os.path.basename(path)}
 
 
-def roofline_entry(stats: dict, traffic=None) -> dict:
-    fam = max(stats, key=lambda k: stats[k][1])
+def roofline_entry(stats: dict, family: str | None = None) -> dict:
+    """The roofline of one kernel family (default: the one with the most
+    time): achieved = its algorithmic bytes per launch / its average launch
+    duration (HIP events on the launch stream), against the 8 TB/s HBM peak;
+    for families with an operation count also the butterfly-equivalent rate
+    against the derived integer-ALU peak."""
+    fam = family if family is not None else max(stats, key=lambda k: stats[k][1])
     n, ms, by, ops = stats[fam]
     n = max(n, 1)
     avg_s = ms / 1e3 / n
-    out = {"kernel": fam, "launches": n, "avg_us": round(avg_s * 1e6, 3), "traffic": traffic}
+    achieved = by / n / avg_s / 1e9
+    out = {"bound": "hbm", "kernel": fam, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "launches": n,
+           "avg_us": round(avg_s * 1e6, 3), "bytes_per_launch": round(by / n)}
     if ops > 0:
-        achieved = ops / n / avg_s / 1e9
-        peak = BUTTERFLY_PEAK / 1e9
-        out.update({"bound": "alu", "achieved": round(achieved, 2), "peak": round(peak, 1),
-                    "unit": "G butterflies/s", "frac": round(achieved / peak, 4),
-                    "ops_per_launch": ops / n, "bytes_per_launch": by / n,
-                    "hbm_gbs_equivalent": round(by / n / avg_s / 1e9, 1)})
-    else:
-        achieved = by / n / avg_s / 1e9
-        out.update({"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4), "bytes_per_launch": by / n})
+        out["alu_frac"] = round(ops / n / avg_s / BUTTERFLY_PEAK, 4)
     return out
 
 
@@ -315,10 +320,12 @@ def batched_leg(P, W, name: str, B: int, per_ct: int, steps: int, tune: bool, la
                fc_doubling=fc_doubling)
     nb, ctb, outb = sb["net"], sb["ct"], sb["outs"]
     stepb = lambda: nb.eval(ctb, outb)
-    dtb = timed(stepb, steps, 1)
+    dtb = timed(stepb, steps, 2)
     rate = steps * B * per_ct / dtb
+    dist = step_distribution(stepb, reps=steps, warmup=0)
     errb = max_error(P, W, sb)
-    out = {unit: round(rate, 2), "ms_per_launch": round(1e3 * dtb / steps, 2), "per_launch": B * per_ct,
+    out = {unit: round(rate, 2), "ms_per_launch": round(1e3 * dtb / steps, 2), "launches_timed": steps,
+           "launch_distribution": dist, "per_launch": B * per_ct,
            "plan": plan, "max_abs_err_vs_fp64": errb, "tuning": sb["tuning"]}
     sbs = family_stats(P, stepb, 1)
     out["kernel_families"] = family_table(sbs, 1)
@@ -356,32 +363,76 @@ def drop_level_bench(P, W, reps: int = 20) -> dict:
             "limb_discard_ms": round(1e3 * dtm / reps, 4), "paper_cpu_seconds_m5": 0.155}
 
 
-def cpu_baseline(W) -> dict:
-    """The oracle (scalar C, one thread) on one whole encrypted LeNet-1
-    inference at the same parameters; keys are made before the timer."""
-    from oracle.run import OracleSession, build_net, run_encrypted
-    cfg = W.config("lenet1")
-    sess = OracleSession(cfg)
-    net = build_net(cfg, sess.ck.slots)
-    sess.ensure_keys(net.rotation_set())
-    xs = W.gen_inputs(cfg["input"], 1)
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_children(jobs: list, timeout: float) -> list:
+    """Run oracle timing children (python -m oracle.timing ...) side by side,
+    one thread each; returns their JSON results in order."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    root = os.path.dirname(os.path.abspath(__file__))
+    procs = [subprocess.Popen([sys.executable, "-m", "oracle.timing", *args], cwd=root, env=env,
+                              stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True) for args in jobs]
+    out = []
+    for p in procs:
+        so, se = p.communicate(timeout=timeout)
+        if p.returncode != 0:
+            raise RuntimeError(f"oracle timing child failed ({p.returncode}): {se[-2000:]}")
+        out.append(json.loads(so.strip().splitlines()[-1]))
+    return out
+
+
+def cpu_baseline(W, max_procs: int = 16) -> dict:
+    """The oracle (scalar C, `%` on 128-bit products, untuned), timed on the
+    host's cores, each run in a process of its own on one thread, keys made
+    before the timer:
+      conv1 (one conv layer, N = 2^13): median of 5 runs, one after another;
+      LeNet-1 (N = 2^14): median of 5 runs, five processes side by side;
+      batched LeNet-1: one ten-image ciphertext per process, min(cores, 16)
+        processes side by side; images/s over what ran (ten images per
+        process over the slowest process's time), no extrapolation."""
+    nproc = os.cpu_count() or 1
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = nproc
+    procs = max(1, min(avail, max_procs))
     t0 = time.perf_counter()
-    run_encrypted(sess, net, xs)
-    dt = time.perf_counter() - t0
-    return {"value": round(1.0 / dt, 5), "unit": "inferences/s", "cores": 1, "kind": "oracle",
-            "sample": f"one whole LeNet-1 encrypted inference (N=2^14, 8 limbs, 288 rotations), {dt:.1f} s"}
+    c1 = _oracle_children([["--workload", "conv1", "--reps", "5"]], 600)[0]
+    c2 = _oracle_children([["--workload", "lenet1"] for _ in range(5)], 900)
+    c3 = _oracle_children([["--workload", "lenet1_batched", "--ct-index", str(i)] for i in range(procs)], 900)
+    wall = time.perf_counter() - t0
+    s1 = float(np.median(c1["seconds"]))
+    s2_all = [c["seconds"][0] for c in c2]
+    s2 = float(np.median(s2_all))
+    s3 = [c["seconds"][0] for c in c3]
+    imgs = sum(c["samples"] for c in c3)
+    return {"value": round(1.0 / s2, 5), "unit": "inferences/s", "cores": 1, "kind": "oracle",
+            "sample": ("LeNet-1 shape, N=2^14, 8 limbs, 288 rotations: median of 5 whole encrypted inferences, "
+                       "each one thread in its own process, the 5 side by side"),
+            "nproc": nproc, "cores_available": avail, "cpu_model": _cpu_model(),
+            "conv1_median_s": round(s1, 3), "conv1_runs_s": [round(x, 3) for x in c1["seconds"]],
+            "lenet1_median_s": round(s2, 3), "lenet1_runs_s": [round(x, 3) for x in s2_all],
+            "batched": {"images_per_s": round(imgs / max(s3), 4), "processes": procs, "ciphertexts": procs,
+                        "images": imgs, "slowest_s": round(max(s3), 3), "fastest_s": round(min(s3), 3)},
+            "leg_wall_s": round(wall, 1)}
 
 
 # The paper's own single-inference times (seconds; SEAL on one Xeon Gold 5220
 # core, scale 2^32, trained models): context only, different parameters.
 PAPER_MODEL_SECONDS = {"m1": 16.247, "m3": 29.105, "m4": 740.128, "m6": 12.309, "m7": 5.119}
-MODEL_NAMES = ["m1", "m3", "m4", "m5", "m6", "m7", "cifar_cnn", "lenet1_padded"]
-# M5 at N = 2^15 would hold ~150 GB of plaintexts (90,691 weights of its
-# 64 -> 128 convolution, most on a few valid slots); it runs at N = 2^13, the
-# smallest ring whose slots hold a 3 x 32 x 32 input
-MODEL_LOG_N = {"m5": 13}
+MODEL_NAMES = ["m1", "m3", "m4", "m6", "m7", "cifar_cnn", "lenet1_padded"]
+MODEL_LOG_N: dict = {}
 # multi-channel workloads also measured with one input ciphertext per channel
-CHANNEL_CT_MODELS = ["cifar_cnn", "m5"]
+CHANNEL_CT_MODELS = ["cifar_cnn"]
 
 
 def models_bench(P, W, steps: int = 3) -> dict:
@@ -419,23 +470,82 @@ def models_bench(P, W, steps: int = 3) -> dict:
     return out
 
 
+def headline(res: dict) -> dict:
+    """The compact result line (about 2 KB): the headline rate, the batched
+    multiple, rotations/s, serving latency, the dominant kernel's roofline
+    and the CPU baseline; everything else stays in the detail file."""
+    keep = ["metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better", "scaling",
+            "vs_baseline", "dtype", "data", "config", "max_abs_err_vs_fp64"]
+    h = {k: res[k] for k in keep if k in res}
+    d = res.get("plain_step_distribution")
+    if d:
+        h["plain_p50_ms"], h["plain_p99_ms"] = d["p50_ms"], d["p99_ms"]
+    if "plain_hoisted_inferences_per_s" in res:
+        h["plain_hoisted_inferences_per_s"] = res["plain_hoisted_inferences_per_s"]
+    b = res.get("batched")
+    if b:
+        h["batched"] = {"images_per_s": b["images_per_s"], "multiple_of_plain": b.get("multiple_of_plain"),
+                        "images_per_launch": b["per_launch"], "launches_timed": b["launches_timed"],
+                        "launch_ms_mean": b["launch_distribution"]["mean_ms"],
+                        "launch_ms_p50": b["launch_distribution"]["p50_ms"],
+                        "launch_ms_p99": b["launch_distribution"]["p99_ms"],
+                        "max_abs_err_vs_fp64": b["max_abs_err_vs_fp64"]}
+        if b.get("roofline"):
+            h["batched"]["top_kernel"] = {k: b["roofline"][k] for k in ("kernel", "frac")}
+    for key, unit in (("batched_variant", "images_per_s"), ("batched_cnn1d", "sequences_per_s"),
+                      ("batched_cnn1d_variant", "sequences_per_s")):
+        v = res.get(key)
+        if v:
+            h[key] = {unit: v[unit], "plan": v["plan"], "launch_ms_p99": v["launch_distribution"]["p99_ms"]}
+            if "multiple_of_plain" in v:
+                h[key]["multiple_of_plain"] = v["multiple_of_plain"]
+    if "rotations_per_s" in res:
+        h["rotations_per_s"] = res["rotations_per_s"]
+    sw = res.get("rotation_sweep")
+    if sw:
+        h["rotations_per_s_single_hoisted24_batched128"] = {
+            k.replace("N=2^", "").replace(",limbs=", "/"): [v["single_per_s"], v["hoisted24_per_s"],
+                                                           v["batched128_per_s"]] for k, v in sw.items()}
+    sv = res.get("serving")
+    if sv:
+        h["serving"] = {"saturation_requests_per_s": sv["saturation_requests_per_s"],
+                        "requests_per_level": sv["requests_per_level"],
+                        "p50_p99_ms": {k: [v["p50_ms"], v["p99_ms"]] for k, v in sv["load_levels"].items()}}
+    if "roofline" in res:
+        h["roofline"] = {k: res["roofline"][k] for k in ("bound", "kernel", "achieved", "peak", "unit", "frac",
+                                                         "traffic", "avg_us", "alu_frac") if k in res["roofline"]}
+    cb = res.get("cpu_baseline")
+    if cb:
+        h["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample", "nproc",
+                                                "cores_available", "cpu_model", "conv1_median_s",
+                                                "lenet1_median_s") if k in cb}
+        if "batched" in cb:
+            h["cpu_baseline"]["batched_images_per_s"] = cb["batched"]["images_per_s"]
+            h["cpu_baseline"]["batched_processes"] = cb["batched"]["processes"]
+    if "detail_path" in res:
+        h["detail"] = res["detail_path"]
+    return h
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--batched-cts", type=int, default=128, help="ciphertexts per batched launch (10 images each)")
-    ap.add_argument("--batched-steps", type=int, default=2)
+    ap.add_argument("--batched-steps", type=int, default=5, help="timed batched launches (after 2 warm-ups)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--only-plain", action="store_true", help="skip every extra measurement (for profiling)")
     ap.add_argument("--no-rotation-sweep", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="default launch parameters instead of the tuned ones")
-    ap.add_argument("--no-models", action="store_true", help="skip the paper's other model shapes")
+    ap.add_argument("--models", action="store_true", help="also time the paper's other model shapes")
     ap.add_argument("--no-lazy", action="store_true",
                     help="skip the plan variants (deferred ModDown, doubling FC sum)")
-    ap.add_argument("--serve-requests", type=int, default=300,
+    ap.add_argument("--serve-requests", type=int, default=10000,
                     help="requests per load level of the serving measurement (0 skips it)")
+    ap.add_argument("--detail", default=os.path.join(tempfile.gettempdir(), "unihenn_bench_detail.json"),
+                    help="file for the full result (kernel tables, tuning, per-model figures)")
     ap.add_argument("--ntt-probe", type=int, default=0, metavar="ROWS",
                     help="only time forward+inverse NTTs of ROWS limb rows at N=2^14 (kernel throughput)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -482,36 +592,38 @@ def main():
     import paper_2402_03060_amd as P
     import workloads as W
 
-    print("[bench] setup plain LeNet-1 (N=2^14)", file=sys.stderr, flush=True)
+    log = lambda m: print("[bench] " + m, file=sys.stderr, flush=True)
+    log("setup plain LeNet-1 (N=2^14)")
     st = setup(P, W, "lenet1", batch=1, tune=not args.no_tune, mode=P.EVAL_PLAIN | P.EVAL_GRAPH)
     net, ct, outs = st["net"], st["ct"], st["outs"]
     step = lambda: net.eval(ct, outs)
     dt = timed(step, args.steps, args.warmup)
     value = args.steps / dt
     err = max_error(P, W, st)
-    print(f"[bench] plain: {value:.2f} inf/s, max |err| {err:.2e}", file=sys.stderr, flush=True)
+    log(f"plain: {value:.2f} inf/s, max |err| {err:.2e}")
     res = {
-        "metric": "encrypted LeNet-1-shape inferences/s (plain: one image per ciphertext, one key switch per rotation)",
+        "metric": "encrypted LeNet-1-shape inferences/s, batched vs plain; rotations/s; p99 latency",
         "value": round(value, 3), "unit": "inferences/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(1e3 * dt / args.steps, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "u64",
-        "data": "synthetic (seeded: uniform [0,1] 28x28 images, weights N(0,0.1^2), biases N(0,0.01^2))",
-        "config": {"workload": "LeNet-1 shape (Table M2): conv 1->4 K5, sq, pool2, conv 4->12 K5, sq, pool2, "
-                               "flatten, FC 192->10", "log_n": 14, "primes": "60 + 7x40 (+60 special)",
-                   "scale": "2^40", "images_per_ct": 1, "mode": "plain, replayed as one HIP graph"},
+        "data": "synthetic, seeded: U[0,1] 28x28 images, weights N(0,0.1^2), biases N(0,0.01^2)",
+        "config": {"workload": "plain LeNet-1 shape (conv 1->4 K5, sq, pool2, conv 4->12 K5, sq, pool2, flatten, "
+                               "FC 192->10), CKKS N=2^14, primes 60+7x40 (+60 special), scale 2^40, one image per "
+                               "ciphertext, one key switch per rotation, one HIP graph per inference"},
         "max_abs_err_vs_fp64": err,
         "tuning": st["tuning"],
     }
     if args.only_plain:
-        print(json.dumps(res))
+        print(json.dumps(headline(res)))
         return
 
     stats = family_stats(P, step, args.steps)
-    rf = roofline_entry(stats)
+    fams = {k: v for k, v in stats.items() if v[0] and v[1] > 0}
+    rf = roofline_entry(fams)
     tr = measured_traffic(rf["kernel"])
     if tr is not None:
         rf["traffic"] = round(tr["bytes_per_launch"])
-        rf["traffic_detail"] = tr
+        rf["traffic_over_algorithmic"] = tr["measured_over_algorithmic"]
     res["roofline"] = rf
     res["kernel_families"] = family_table(stats, args.steps)
     res["plain_step_distribution"] = step_distribution(step)
@@ -526,7 +638,7 @@ def main():
         # the same single-image workload in the plan variants
         res["plain_variants"] = {}
         for vname, lazy, dbl in PLAN_VARIANTS:
-            print(f"[bench] setup plain LeNet-1, {vname}", file=sys.stderr, flush=True)
+            log(f"setup plain LeNet-1, {vname}")
             sl = setup(P, W, "lenet1", batch=1, tune=not args.no_tune, mode=P.EVAL_PLAIN | P.EVAL_GRAPH, lazy=lazy,
                        fc_doubling=dbl)
             nlz, ctl, outl = sl["net"], sl["ct"], sl["outs"]
@@ -535,13 +647,13 @@ def main():
             nlz.set_mode(P.EVAL_HOISTED | P.EVAL_GRAPH)
             dtlh = timed(stepl, args.steps, 1)
             nlz.set_mode(P.EVAL_PLAIN | P.EVAL_GRAPH)
-            fams = family_table(family_stats(P, stepl, args.steps), args.steps)
+            fv = family_table(family_stats(P, stepl, args.steps), args.steps)
             res["plain_variants"][vname] = {
                 "inferences_per_s": round(args.steps / dtl, 3), "ms_per_step": round(1e3 * dtl / args.steps, 3),
                 "hoisted_inferences_per_s": round(args.steps / dtlh, 3),
                 "multiple_of_default_plan": round(dt / dtl, 3), "rotation_keys": len(nlz.rotations()),
-                "max_abs_err_vs_fp64": max_error(P, W, sl), "tuning": sl["tuning"], "kernel_families": fams}
-            print(f"[bench] plain, {vname}: {args.steps / dtl:.2f} inf/s", file=sys.stderr, flush=True)
+                "max_abs_err_vs_fp64": max_error(P, W, sl), "tuning": sl["tuning"], "kernel_families": fv}
+            log(f"plain, {vname}: {args.steps / dtl:.2f} inf/s")
             del sl, nlz, ctl, outl, stepl
         torch.cuda.empty_cache()
 
@@ -555,7 +667,7 @@ def main():
     dtr = timed(rot, 50, 5)
     res["rotations_per_s"] = round(50 / dtr, 1)
     if not args.no_rotation_sweep:
-        print("[bench] rotation microbenchmark", file=sys.stderr, flush=True)
+        log("rotation microbenchmark")
         del ws, full
         res["rotation_sweep"] = rotation_microbench(P)
 
@@ -575,21 +687,27 @@ def main():
                             fc_doubling=dbl)
             res["batched_cnn1d_variant" if lazy else "batched_cnn1d"] = r
 
-    if not args.no_models:
+    if args.models:
         res["models"] = models_bench(P, W)
         res["drop_level"] = drop_level_bench(P, W)
 
     if args.serve_requests:
         from paper_2402_03060_amd.serve import serving_benchmark
-        res["serving"] = serving_benchmark(P, W, args.serve_requests, tuning_cache=TUNING_CACHE,
-                                           log=lambda m: print("[bench] " + m, file=sys.stderr, flush=True))
+        res["serving"] = serving_benchmark(P, W, args.serve_requests, tuning_cache=TUNING_CACHE, log=log)
 
     if not args.no_cpu_baseline:
-        print("[bench] CPU oracle baseline (one inference)", file=sys.stderr, flush=True)
+        log("CPU oracle baseline (conv1 x5, LeNet-1 x5, batched LeNet-1 on up to 16 processes)")
         res["cpu_baseline"] = cpu_baseline(W)
     res["paper_context"] = {"lenet1_seconds": 30.089, "ten_samples_m1_seconds": 16.247,
                             "hardware": "Intel Xeon Gold 5220 @ 2.2 GHz, SEAL single-threaded, N=2^14, scale 2^32"}
-    print(json.dumps(res))
+    res["detail_path"] = args.detail
+    try:
+        with open(args.detail, "w") as f:
+            json.dump(res, f, indent=1)
+        log(f"full result: {args.detail}")
+    except OSError as e:
+        log(f"could not write {args.detail}: {e}")
+    print(json.dumps(headline(res)))
 
 
 if __name__ == "__main__":

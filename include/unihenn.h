@@ -400,11 +400,15 @@ int unihenn_decrypt_slots(const unihenn_ctx* ctx, const uint64_t* sk, const unih
 
 /* ------------------------------------------------------------ measurement */
 /* Per-kernel-family launch timing with HIP events recorded on the launch
- * stream around each launch (adds a little overhead while on). */
+ * stream around each launch (adds a little overhead while on).  KS_INNER
+ * counts the separate key-switch inner products (and relinearisation);
+ * KS_ROWFUSED counts the inner products fused with ModUp's row pass (one
+ * kernel, k_ntt_r8_ksrow). */
 enum {
     UNIHENN_KF_NTT_FWD_COL = 0, UNIHENN_KF_NTT_FWD_ROW, UNIHENN_KF_NTT_INV_ROW, UNIHENN_KF_NTT_INV_COL,
     UNIHENN_KF_MODUP, UNIHENN_KF_KS_INNER, UNIHENN_KF_MODDOWN, UNIHENN_KF_RESCALE, UNIHENN_KF_MAC, UNIHENN_KF_AUTO,
-    UNIHENN_KF_TENSOR, UNIHENN_KF_ADD, UNIHENN_KF_ENCODE, UNIHENN_KF_OTHER, UNIHENN_KF_COUNT
+    UNIHENN_KF_TENSOR, UNIHENN_KF_ADD, UNIHENN_KF_ENCODE, UNIHENN_KF_OTHER, UNIHENN_KF_KS_ROWFUSED,
+    UNIHENN_KF_COUNT
 };
 int unihenn_stats_enable(int on);
 int unihenn_stats_reset(void);

@@ -20,7 +20,7 @@ LAYER_CONV, LAYER_SQUARE, LAYER_AVGPOOL, LAYER_FLATTEN, LAYER_FC, LAYER_RELU_APP
 EVAL_PLAIN, EVAL_HOISTED, EVAL_GRAPH = 0, 1, 2
 PLAN_LAZY_MODDOWN, PLAN_FC_DOUBLING, PLAN_CHANNEL_CTS = 1, 2, 4
 KERNEL_FAMILIES = ["ntt_fwd_col", "ntt_fwd_row", "ntt_inv_row", "ntt_inv_col", "modup", "ks_inner", "moddown",
-                   "rescale", "mac", "automorphism", "tensor", "add", "encode", "other"]
+                   "rescale", "mac", "automorphism", "tensor", "add", "encode", "other", "ks_rowfused"]
 
 
 class UnihennError(RuntimeError):

@@ -344,7 +344,8 @@ double g_ms[KF_COUNT];
 double g_bytes[KF_COUNT];
 double g_ops[KF_COUNT];
 const char* g_names[KF_COUNT] = {"ntt_fwd_col", "ntt_fwd_row", "ntt_inv_row", "ntt_inv_col", "modup", "ks_inner",
-                                 "moddown", "rescale", "mac", "automorphism", "tensor", "add", "encode", "other"};
+                                 "moddown", "rescale", "mac", "automorphism", "tensor", "add", "encode", "other",
+                                 "ks_rowfused"};
 }  // namespace
 
 // fold finished timer pairs into the per-family totals (g_stats_mu held)

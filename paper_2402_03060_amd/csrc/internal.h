@@ -149,7 +149,7 @@ void launch_ks_rowfused(const unihenn_ctx* c, const GroupArgs& ga, int B, int nl
 // kernel timing hooks (per kernel family), see unihenn_stats_*
 enum KernelFamily : int {
     KF_NTT_FWD_COL = 0, KF_NTT_FWD_ROW, KF_NTT_INV_ROW, KF_NTT_INV_COL, KF_MODUP, KF_KS_INNER, KF_MODDOWN,
-    KF_RESCALE, KF_MAC, KF_AUTO, KF_TENSOR, KF_ADD, KF_ENCODE, KF_OTHER, KF_COUNT
+    KF_RESCALE, KF_MAC, KF_AUTO, KF_TENSOR, KF_ADD, KF_ENCODE, KF_OTHER, KF_KS_ROWFUSED, KF_COUNT
 };
 // Times one launch (or a group of launches) on its stream with HIP events when
 // timing is on; `bytes` is the algorithmic traffic, `ops` the algorithmic

@@ -898,7 +898,7 @@ void launch_ks_rowfused(const unihenn_ctx* c, const GroupArgs& ga, int B, int nl
     // Montgomery product of about 52 VALU lane slots against 38 per butterfly
     const double bfly = (double)E * B * nl * nl * 0.5 * c->n * l2;
     const double macs = (double)E * B * nl * (nl + 1) * 2.0 * c->n;
-    LaunchTimer tm(KF_KS_INNER, 8.0 * c->n * rows, st, bfly + macs * 52.0 / 38.0);
+    LaunchTimer tm(KF_KS_ROWFUSED, 8.0 * c->n * rows, st, bfly + macs * 52.0 / 38.0);
     const int avail_log = c->log_n - l2;
     int lc = tile - l2;
     if (lc > avail_log) lc = avail_log;

@@ -26,7 +26,8 @@ FAMILY_KERNELS = {
     "ntt_inv_row": r"k_ntt_r8<\d+, \d+, false, true, false>|k_intt_r8_gather<|k_ntt_inv<false",
     "ntt_inv_col": r"k_ntt_r8<\d+, \d+, true, true, true>|k_ntt_inv<true",
     "modup": r"k_ntt_r8_lift<\d+, \d+, 2>|k_modup",
-    "ks_inner": r"k_group_inner<|k_ks_inner<|k_ntt_r8_ksrow<",
+    "ks_inner": r"k_group_inner<|k_ks_inner<",
+    "ks_rowfused": r"k_ntt_r8_ksrow<",
     "moddown": r"k_ntt_r8_lift<\d+, \d+, 0>|k_ntt_r8_finish<\d+, \d+, 0>|k_relin_combine|k_group_sub_scale\(",
     "rescale": r"k_ntt_r8_lift<\d+, \d+, 1>|k_ntt_r8_finish<\d+, \d+, 1>|k_group_sub_scale2",
     "mac": r"k_mac_multi<|k_mac<|k_mac_group<",

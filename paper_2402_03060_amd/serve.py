@@ -292,7 +292,7 @@ def serving_benchmark(P, W, n_requests: int, tuning_cache: str | None = None, hb
                       for m, d in models.items()},
            "plan": plan, "mix": SERVE_MIX, "arrival_seed": W.SEED_ARRIVALS, "hbm_budget_bytes": hbm_budget,
            "requests_per_level": n_requests}
-    burst = poisson_requests(SERVE_MIX, 1e9, n_requests, W.SEED_ARRIVALS, payloads)
+    burst = poisson_requests(SERVE_MIX, 1e9, min(n_requests, 3000), W.SEED_ARRIVALS, payloads)
     st = serve(Scheduler(specs, hbm_budget), ex, burst)
     torch.cuda.synchronize()
     sat = st.completed / st.duration
