@@ -48,6 +48,8 @@ def lib():
         L.or_prng_new.argtypes = [C.c_uint64]
         L.or_prng_new.restype = _vp
         L.or_prng_free.argtypes = [_vp]
+        L.or_sample.argtypes = [_vp, C.c_int, C.c_uint64, C.c_int, _i64p]
+        L.or_gauss_candidate.argtypes = [C.c_double, C.c_double, C.POINTER(C.c_int)]
         L.or_ctx_new.argtypes = [C.c_int, _u64p, C.c_int]
         L.or_ctx_new.restype = _vp
         L.or_ctx_free.argtypes = [_vp]
@@ -66,6 +68,8 @@ def lib():
         L.or_gen_pk.argtypes = [_vp, _vp, C.POINTER(C.c_int8), C.c_int, _u64p]
         L.or_gen_rotation_key.argtypes = [_vp, _vp, C.POINTER(C.c_int8), C.c_int, C.c_int64, _u64p]
         L.or_gen_relin_key.argtypes = [_vp, _vp, C.POINTER(C.c_int8), C.c_int, _u64p]
+        L.or_gen_rotation_key_rows.argtypes = [_vp, _vp, C.POINTER(C.c_int8), C.c_int, C.c_int64, C.c_int, _u64p]
+        L.or_gen_relin_key_rows.argtypes = [_vp, _vp, C.POINTER(C.c_int8), C.c_int, C.c_int, _u64p]
         L.or_encrypt_pk.argtypes = [_vp, _vp, _u64p, _u64p, C.c_int, _u64p]
         L.or_decrypt.argtypes = [_vp, C.POINTER(C.c_int8), _u64p, C.c_int, _u64p]
         L.or_key_load.argtypes = [_vp, _u64p, C.c_int]
@@ -259,6 +263,25 @@ class OracleCKKS:
         k = np.zeros((self.n_data, 2, self.n_data + 1, self.n), dtype=np.uint64)
         lib().or_gen_relin_key(self.ctx, self._prng, self.sk.s.ctypes.data_as(C.POINTER(C.c_int8)),
                                self.n_data, _p64(k))
+        return k
+
+    def seeded_key(self, seed: int, r: int | None = None, levels: int | None = None) -> np.ndarray:
+        """A switching key from a generator of its own (seeded by `seed`, not
+        the session's stream), so that keys can be made in any order or in
+        parallel: Rot(., r), or relinearisation when r is None.  With
+        `levels`, only the rows a ciphertext of that many limbs reads are
+        formed (digits and limbs below `levels`, and P); the others are zero
+        and the formed rows equal the whole key's."""
+        lv = self.n_data if levels is None else int(levels)
+        assert 1 <= lv <= self.n_data
+        k = np.zeros((self.n_data, 2, self.n_data + 1, self.n), dtype=np.uint64)
+        p = lib().or_prng_new(seed)
+        s = self.sk.s.ctypes.data_as(C.POINTER(C.c_int8))
+        if r is None:
+            lib().or_gen_relin_key_rows(self.ctx, p, s, self.n_data, lv, _p64(k))
+        else:
+            lib().or_gen_rotation_key_rows(self.ctx, p, s, self.n_data, int(r), lv, _p64(k))
+        lib().or_prng_free(p)
         return k
 
     def load_key(self, key: np.ndarray):

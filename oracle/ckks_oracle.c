@@ -159,15 +159,24 @@ static int sample_ternary(prng_t *p)
         if (r < 3) return (int)r - 1;
     }
 }
-/* rounded Gaussian, sigma = 3.2, redrawn when |e| > 19 (Box-Muller) */
+/* one rounded-Gaussian candidate (Box-Muller, sigma = 3.2) from u1 in (0,1]
+   and u2 in [0,1): returns 1 and stores it in *e when |e| <= 19 (accepted),
+   0 when it must be redrawn */
+int or_gauss_candidate(double u1, double u2, int *e)
+{
+    double z = sqrt(-2.0 * log(u1)) * cos(2.0 * M_PI * u2);
+    double r = nearbyint(3.2 * z);
+    if (fabs(r) > 19.0) return 0;
+    *e = (int)r;
+    return 1;
+}
 static int sample_gauss(prng_t *p)
 {
     for (;;) {
         double u1 = ((prng_next(p) >> 11) + 1) * 0x1p-53; /* (0,1] */
         double u2 = (prng_next(p) >> 11) * 0x1p-53;       /* [0,1) */
-        double z = sqrt(-2.0 * log(u1)) * cos(2.0 * M_PI * u2);
-        double e = nearbyint(3.2 * z);
-        if (fabs(e) <= 19.0) return (int)e;
+        int e;
+        if (or_gauss_candidate(u1, u2, &e)) return e;
     }
 }
 /* uniform in [0,q) by rejection on the top bits */
@@ -178,6 +187,15 @@ static u64 sample_uniform(prng_t *p, u64 q)
         u64 r = prng_next(p) >> (64 - bits);
         if (r < q) return r;
     }
+}
+
+/* n draws of one sampler (test hook): kind 0 ternary, 1 rounded Gaussian,
+   2 uniform in [0, q) */
+void or_sample(void *pv, int kind, u64 q, int n, int64_t *out)
+{
+    prng_t *p = (prng_t *)pv;
+    for (int i = 0; i < n; i++)
+        out[i] = kind == 0 ? sample_ternary(p) : kind == 1 ? sample_gauss(p) : (int64_t)sample_uniform(p, q);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -508,7 +526,13 @@ void or_gen_pk(void *vc, void *vp, const int8_t *s, int n_data, u64 *pk)
  * the basis {q_0..q_L, P} (n_data = L+1 data primes, P = moduli[n_data]):
  *   evk_j = (-a_j s + e_j + [i == j] (P mod q_i) t, a_j)   for j <= L.
  * key: [L+1][2][L+2][N]. */
-static void gen_switch_key(ctx_t *c, prng_t *p, const int8_t *s, const i64 *t, int n_data, u64 *key)
+/* Switching key for target t (C3): digit d, basis limb i (q_0..q_{n_data-1},
+ * then P) holds (-a s + e + [i = d] (P mod q_i) t, a).  With levels < n_data
+ * only the rows a ciphertext of `levels` limbs reads are formed (digits below
+ * `levels`, limbs below `levels` and P); the others stay zero.  Every random
+ * draw is still made, so the formed rows equal those of the whole key. */
+static void gen_switch_key_rows(ctx_t *c, prng_t *p, const int8_t *s, const i64 *t, int n_data, int levels,
+                                u64 *key)
 {
     int n = c->n, nb = n_data + 1;
     i64 *e = (i64 *)malloc(sizeof(i64) * n), *si = (i64 *)malloc(sizeof(i64) * n);
@@ -522,6 +546,11 @@ static void gen_switch_key(ctx_t *c, prng_t *p, const int8_t *s, const i64 *t, i
             u64 *k0 = key + (((size_t)d * 2 + 0) * nb + i) * n;
             u64 *k1 = key + (((size_t)d * 2 + 1) * nb + i) * n;
             for (int k = 0; k < n; k++) k1[k] = sample_uniform(p, q);
+            if (d >= levels || (i >= levels && i != n_data)) {
+                memset(k0, 0, sizeof(u64) * n);
+                memset(k1, 0, sizeof(u64) * n);
+                continue;
+            }
             small_to_mod(c, si, i, sm);
             or_poly_mul(c, i, k1, sm, as);
             u64 pmod = P % q;
@@ -535,8 +564,14 @@ static void gen_switch_key(ctx_t *c, prng_t *p, const int8_t *s, const i64 *t, i
     free(e); free(si); free(sm); free(as);
 }
 
-/* rotation key for a left rotation by r: target tau_g(s), g = 5^r mod 2N */
+/* rotation key for a left rotation by r: target tau_g(s), g = 5^r mod 2N;
+ * or_gen_rotation_key_rows forms only the rows of `levels` limbs */
+void or_gen_rotation_key_rows(void *vc, void *vp, const int8_t *s, int n_data, i64 r, int levels, u64 *key);
 void or_gen_rotation_key(void *vc, void *vp, const int8_t *s, int n_data, i64 r, u64 *key)
+{
+    or_gen_rotation_key_rows(vc, vp, s, n_data, r, n_data, key);
+}
+void or_gen_rotation_key_rows(void *vc, void *vp, const int8_t *s, int n_data, i64 r, int levels, u64 *key)
 {
     ctx_t *c = (ctx_t *)vc;
     int n = c->n;
@@ -548,12 +583,17 @@ void or_gen_rotation_key(void *vc, void *vp, const int8_t *s, int n_data, i64 r,
         if (e < (u64)n) t[e] = s[j];
         else t[e - n] = -(i64)s[j];
     }
-    gen_switch_key(c, (prng_t *)vp, s, t, n_data, key);
+    gen_switch_key_rows(c, (prng_t *)vp, s, t, n_data, levels, key);
     free(t);
 }
 
 /* relinearisation key: target s^2 (product over the integers, |coef| <= N) */
+void or_gen_relin_key_rows(void *vc, void *vp, const int8_t *s, int n_data, int levels, u64 *key);
 void or_gen_relin_key(void *vc, void *vp, const int8_t *s, int n_data, u64 *key)
+{
+    or_gen_relin_key_rows(vc, vp, s, n_data, n_data, key);
+}
+void or_gen_relin_key_rows(void *vc, void *vp, const int8_t *s, int n_data, int levels, u64 *key)
 {
     ctx_t *c = (ctx_t *)vc;
     int n = c->n;
@@ -568,7 +608,7 @@ void or_gen_relin_key(void *vc, void *vp, const int8_t *s, int n_data, u64 *key)
             else t[k - n] -= v; /* X^N = -1 */
         }
     }
-    gen_switch_key(c, (prng_t *)vp, s, t, n_data, key);
+    gen_switch_key_rows(c, (prng_t *)vp, s, t, n_data, levels, key);
     free(t);
 }
 

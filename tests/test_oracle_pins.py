@@ -354,3 +354,101 @@ def test_drop_level_by_encrypted_ones(mid):
     assert out.nl == ct.nl - 2
     assert out.scale == ct.scale
     assert np.abs(mid.decrypt(out) - z).max() < 1e-6
+
+
+# ---------------------------------------------------------------- samplers
+# The client's samplers (ternary secret, rounded Gaussian errors of sigma 3.2
+# redrawn past |e| = 19, uniform residues) pinned by their distributions.
+def _draws(kind: int, n: int, seed: int, q: int = 0) -> np.ndarray:
+    import ctypes
+    from oracle.ckks import lib
+    L = lib()
+    p = L.or_prng_new(seed)
+    out = np.zeros(n, dtype=np.int64)
+    L.or_sample(p, kind, q, n, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+    L.or_prng_free(p)
+    return out
+
+
+def test_sampler_ternary_is_uniform_on_three_values():
+    n = 300_000
+    x = _draws(0, n, 7)
+    vals, counts = np.unique(x, return_counts=True)
+    assert vals.tolist() == [-1, 0, 1]
+    # each frequency within 6 standard errors (sqrt(2/9 / n) = 0.00086) of 1/3
+    assert np.all(np.abs(counts / n - 1 / 3) < 0.0052), counts
+
+
+def test_sampler_gauss_sigma_shape_and_bound():
+    from scipy.stats import chi2, norm
+    n = 1_000_000
+    x = _draws(1, n, 8)
+    assert np.abs(x).max() <= 19
+    # rounding a N(0, 3.2^2) variable adds 1/12 to its variance
+    sd = np.sqrt(3.2 ** 2 + 1 / 12)
+    assert abs(x.mean()) < 6 * sd / np.sqrt(n)
+    assert abs(x.std() - sd) < 6 * sd / np.sqrt(2 * n)
+    # probability of each value against the rounded normal law (tails merged)
+    ks = np.arange(-10, 11)
+    exp = norm.cdf((ks + 0.5) / 3.2) - norm.cdf((ks - 0.5) / 3.2)
+    obs = np.array([(x == k).sum() for k in ks], dtype=np.float64)
+    tail_exp = 1.0 - exp.sum()
+    tail_obs = n - obs.sum()
+    stat = ((obs - n * exp) ** 2 / (n * exp)).sum() + (tail_obs - n * tail_exp) ** 2 / (n * tail_exp)
+    assert chi2.sf(stat, len(ks)) > 1e-6, stat
+
+
+def test_sampler_gauss_redraw_boundary():
+    """With u2 = 0 (cos = 1) or u2 = 1/2 (cos = -1) the candidate is
+    +-3.2 sqrt(-2 ln u1): 19.4 rounds to 19 and is kept, 19.6 rounds to 20
+    and is redrawn, on both sides."""
+    import ctypes
+    from oracle.ckks import lib
+    L = lib()
+    e = ctypes.c_int(0)
+    for u2, sign in ((0.0, 1), (0.5, -1)):
+        for target, keep in ((19.4, True), (19.6, False), (3.0, True)):
+            u1 = float(np.exp(-((target / 3.2) ** 2) / 2))
+            ok = L.or_gauss_candidate(u1, u2, ctypes.byref(e))
+            assert bool(ok) == keep, (u2, target)
+            if keep:
+                assert e.value == sign * int(round(target))
+
+
+def test_sampler_uniform_range_and_spread():
+    q = 1099510054913                       # a 40-bit prime of the chain
+    n = 200_000
+    x = _draws(2, n, 9, q).astype(np.uint64)
+    assert int(x.min()) >= 0 and int(x.max()) < q
+    u = x.astype(np.float64) / q
+    assert abs(u.mean() - 0.5) < 6 * np.sqrt(1 / 12 / n)
+    counts = np.histogram(u, bins=16, range=(0, 1))[0]
+    assert np.all(np.abs(counts / n - 1 / 16) < 6 * np.sqrt(15 / 256 / n)), counts
+
+
+def test_seeded_keys_partial_rows_equal_whole_key(mid):
+    """Keys from their own seeded generator: the rows formed for `levels`
+    limbs equal the whole key's rows, the others are zero, and a rotation
+    (and a relinearised square) at that many limbs gives the same
+    ciphertext with either key, which decrypts to the rolled slots."""
+    nd = mid.n_data
+    lv = 2
+    for r in (3, None):
+        whole = mid.seeded_key(1234, r=r)
+        part = mid.seeded_key(1234, r=r, levels=lv)
+        assert not np.array_equal(whole, mid.seeded_key(1235, r=r))
+        for d in range(nd):
+            for i in range(nd + 1):
+                used = d < lv and (i < lv or i == nd)
+                if used:
+                    assert np.array_equal(part[d, :, i], whole[d, :, i]), (d, i)
+                else:
+                    assert not part[d, :, i].any(), (d, i)
+    z = W.gen_slots(mid.slots, 1, seed=21)[0]
+    ct = mid.limb_drop(mid.encrypt(z, 22), lv)
+    kw, kp = mid.load_key(mid.seeded_key(77, r=3)), mid.load_key(mid.seeded_key(77, r=3, levels=lv))
+    a, b = mid.rotate(ct, 3, kw), mid.rotate(ct, 3, kp)
+    assert np.array_equal(a.data, b.data)
+    assert np.abs(mid.decrypt(a) - np.roll(z, -3)).max() < 1e-6
+    rw, rp = mid.load_key(mid.seeded_key(78)), mid.load_key(mid.seeded_key(78, levels=lv))
+    assert np.array_equal(mid.square_relin(ct, rw).data, mid.square_relin(ct, rp).data)
