@@ -286,8 +286,8 @@ extern "C" int unihenn_rescale(const unihenn_ctx* c, const unihenn_ct* in, unihe
 {
     int rc = check_ct(c, in, "input");
     if (rc) return rc;
-    if (!out || !out->data) return uh_fail(UNIHENN_EINVAL, "null output");
     if (in->n_limbs < 2) return uh_fail(UNIHENN_ELEVEL, "level exhausted: one limb left");
+    if (!out || !out->data) return uh_fail(UNIHENN_EINVAL, "null output");
     if (out->data == in->data) return uh_fail(UNIHENN_EINVAL, "output aliases input");
     const int nl = (int)in->n_limbs, B = (int)in->batch;
     if ((rc = check_ws(c, nl, B, ws_bytes, ws))) return rc;
