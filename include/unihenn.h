@@ -139,6 +139,21 @@ size_t unihenn_ks_workspace_size(const unihenn_ctx* ctx, uint32_t n_limbs, uint3
  * steps != 0). */
 int unihenn_rotate(const unihenn_ctx* ctx, const unihenn_ct* in, int32_t steps, const unihenn_evk* gk,
                    unihenn_ct* out, void* ws, size_t ws_bytes, void* stream);
+/* unihenn_rotate for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same rotation, bit for bit, with its key-switching workspace in a
+ * fixed 64 MiB device array of the library instead of a caller buffer.  The
+ * caller still passes the input, key and output.  It allocates nothing and
+ * calls no allocating routine.  Each GPU holds its own copy of the array from
+ * the library's load until the process ends; the first call on a device
+ * looks up its address (the context's device must be current).  Every call
+ * on one GPU shares that array, so calls that overlap on one GPU (on
+ * different streams or threads) race; calls on one stream are ordered.
+ * Errors: as unihenn_rotate, and EINVAL when the workspace the rotation needs
+ * (unihenn_ks_workspace_size(ctx, n_limbs, batch)) exceeds 64 MiB, or when
+ * another device than the context's is current. */
+int unihenn_rotate_noalloc(const unihenn_ctx* ctx, const unihenn_ct* in, int32_t steps, const unihenn_evk* gk,
+                           unihenn_ct* out, void* stream);
 /* n_steps rotations of the same ciphertexts sharing one digit decomposition
  * (hoisting).  Bit-identical to n_steps calls of unihenn_rotate.  gks[i] and
  * outs[i] belong to steps[i] (host arrays of descriptors). */

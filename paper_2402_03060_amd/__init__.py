@@ -74,6 +74,7 @@ SIGNATURES = {
     "unihenn_ks_workspace_size": (_sz, [_vp, _u32, _u32]),
     "unihenn_rotate": (C.c_int, [_vp, _P(CT), _i32, _P(EVK), _P(CT), _vp, _sz, _vp]),
     "unihenn_rotate_hoisted": (C.c_int, [_vp, _P(CT), _P(_i32), _u32, _P(EVK), _P(CT), _vp, _sz, _vp]),
+    "unihenn_rotate_noalloc": (C.c_int, [_vp, _P(CT), _i32, _P(EVK), _P(CT), _vp]),
     "unihenn_mul_plain_acc": (C.c_int, [_vp, _P(CT), _P(_vp), _u32, C.c_int, _P(CT), _vp]),
     "unihenn_rescale": (C.c_int, [_vp, _P(CT), _P(CT), _vp, _sz, _vp]),
     "unihenn_square_relin": (C.c_int, [_vp, _P(CT), _P(EVK), _P(CT), _vp, _sz, _vp]),
@@ -278,6 +279,17 @@ class Context:
         k = self.evk(key) if key is not None else None
         _check(lib().unihenn_rotate(self.h, C.byref(ct.desc()), int(steps), C.byref(k) if k else None, C.byref(o),
                                     ws.data_ptr(), ws.numel() * 8, _stream()))
+        out.scale = o.scale
+        return out
+
+    def rotate_noalloc(self, ct: Ciphertext, steps: int, key: torch.Tensor | None, out: Ciphertext,
+                       stream=None) -> Ciphertext:
+        """unihenn_rotate_noalloc into a caller-made output (the library's
+        fixed scratch array replaces the workspace)."""
+        o = out.desc()
+        k = self.evk(key) if key is not None else None
+        _check(lib().unihenn_rotate_noalloc(self.h, C.byref(ct.desc()), int(steps), C.byref(k) if k else None,
+                                            C.byref(o), _stream(stream)))
         out.scale = o.scale
         return out
 

@@ -5,6 +5,9 @@
 #include <algorithm>
 
 #include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
 
 #include "kernels.h"
 
@@ -204,6 +207,54 @@ extern "C" int unihenn_rotate(const unihenn_ctx* c, const unihenn_ct* in, int32_
               w, s);
     UH_LAUNCH_CHECK();
     return UNIHENN_OK;
+}
+
+// ---- rotation without allocation: a fixed device scratch array per GPU
+// holds the key-switching workspace instead of a caller buffer.
+#define UH_SCRATCH_BYTES (64ull << 20)
+static __device__ __align__(256) u64 scratch[UH_SCRATCH_BYTES / sizeof(u64)];
+namespace {
+std::mutex g_scratch_mu;
+std::vector<u64*> g_scratch_dev;  // device address of `scratch`, by device ordinal (null until looked up)
+}  // namespace
+
+// The device address of this GPU's copy of `scratch`, looked up once per
+// device with that device current.  The host-side name of the array is only a
+// stand-in: kernels and copies take the address found here.
+static int scratch_address(const unihenn_ctx* c, u64** out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return uh_fail(UNIHENN_EDEVICE, "hipGetDevice failed");
+    if (dev != c->device)
+        return uh_fail(UNIHENN_EINVAL, "the context's device must be current (context on device " +
+                                           std::to_string(c->device) + ", current " + std::to_string(dev) + ")");
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if ((int)g_scratch_dev.size() <= dev) g_scratch_dev.resize(dev + 1, nullptr);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return uh_fail(UNIHENN_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_dev[dev] = (u64*)p;
+    }
+    *out = g_scratch_dev[dev];
+    return UNIHENN_OK;
+}
+
+extern "C" int unihenn_rotate_noalloc(const unihenn_ctx* c, const unihenn_ct* in, int32_t steps,
+                                      const unihenn_evk* gk, unihenn_ct* out, void* stream)
+{
+    int rc = rotate_checks(c, in, out);
+    if (rc) return rc;
+    const size_t need = ks_ws_rows((int)in->n_limbs, (int)in->batch) * c->n * sizeof(u64);
+    if (need > UH_SCRATCH_BYTES)
+        return uh_fail(UNIHENN_EINVAL, "rotation needs " + std::to_string(need) +
+                                           " bytes of workspace, above the fixed scratch of " +
+                                           std::to_string(UH_SCRATCH_BYTES) + " bytes (use unihenn_rotate)");
+    if (galois_elt(c, steps) != 1 && (rc = check_key(c, gk, (int)in->n_limbs))) return rc;
+    u64* ws = nullptr;
+    if ((rc = scratch_address(c, &ws))) return rc;
+    return unihenn_rotate(c, in, steps, gk, out, ws, UH_SCRATCH_BYTES, stream);
 }
 
 extern "C" int unihenn_rotate_hoisted(const unihenn_ctx* c, const unihenn_ct* in, const int32_t* steps,
