@@ -213,6 +213,8 @@ extern "C" int unihenn_ctx_create(uint32_t log_n, const uint32_t* prime_bits, ui
     unihenn_ctx* c = new unihenn_ctx();
     c->log_n = (int)log_n;
     if (const char* v = getenv("UNIHENN_KS_FUSE_MIN_WG")) c->ks_fuse_min_wg = atoi(v);
+    if (const char* v = getenv("UNIHENN_KSROW_TILE")) c->ks_tile_log = atoi(v);
+    if (const char* v = getenv("UNIHENN_KSROW_SPLIT")) c->ks_split = atoi(v) != 0;
     c->n = 1 << log_n;
     c->n_data = (int)n_data;
     c->scale = scale;
@@ -239,6 +241,30 @@ extern "C" int unihenn_ctx_create(uint32_t log_n, const uint32_t* prime_bits, ui
             tw[(size_t)2 * nm * n + o] = ipw[r];
             tw[(size_t)3 * nm * n + o] = shoup(ipw[r], q);
         }
+    }
+    // binary64 tables for primes below 2^41: twiddles and twiddle / q
+    std::vector<double> twf((size_t)4 * nm * n, 0.0);
+    std::vector<FpModulus> fm(nm);
+    memset(fm.data(), 0, sizeof(FpModulus) * nm);
+    for (int mi = 0; mi < nm; ++mi) {
+        const u64 q = primes[mi];
+        if (q >= (1ull << 41)) continue;
+        const double qd = (double)q;
+        for (int k = 0; k < n; ++k) {
+            const size_t o = (size_t)mi * n + k;
+            twf[o] = (double)tw[o];
+            twf[(size_t)nm * n + o] = (double)tw[o] / qd;
+            twf[(size_t)2 * nm * n + o] = (double)tw[(size_t)2 * nm * n + o];
+            twf[(size_t)3 * nm * n + o] = (double)tw[(size_t)2 * nm * n + o] / qd;
+        }
+        const u64 r64 = (u64)(((unsigned __int128)1 << 64) % q);
+        const u64 rinv = h_inv(r64, q);
+        fm[mi].q = qd;
+        fm[mi].qinv = 1.0 / qd;
+        fm[mi].ninv = (double)c->host_mod[mi].n_inv;
+        fm[mi].ninvq = fm[mi].ninv / qd;
+        fm[mi].rinv = (double)rinv;
+        fm[mi].rinvq = (double)rinv / qd;
     }
     c->q_mod.resize((size_t)nm * nm);
     for (int a = 0; a < nm; ++a)
@@ -279,6 +305,8 @@ extern "C" int unihenn_ctx_create(uint32_t log_n, const uint32_t* prime_bits, ui
     if (hipMalloc(&c->d_p_mod, sizeof(u64) * c->p_mod.size()) != hipSuccess) return fail("hipMalloc pmod");
     if (hipMalloc(&c->d_galois_e, sizeof(uint32_t) * ge.size()) != hipSuccess) return fail("hipMalloc galois");
     if (hipMalloc(&c->d_cos, sizeof(double) * cs.size()) != hipSuccess) return fail("hipMalloc cos");
+    if (hipMalloc(&c->d_fmod, sizeof(FpModulus) * nm) != hipSuccess) return fail("hipMalloc fp moduli");
+    if (hipMalloc(&c->d_twf, sizeof(double) * twf.size()) != hipSuccess) return fail("hipMalloc fp twiddles");
     hipError_t up = hipMemcpy(c->d_mod, c->host_mod.data(), sizeof(Modulus) * nm, hipMemcpyHostToDevice);
     if (up == hipSuccess) up = hipMemcpy(c->d_tw, tw.data(), sizeof(u64) * tw.size(), hipMemcpyHostToDevice);
     if (up == hipSuccess) up = hipMemcpy(c->d_qmod, c->q_mod.data(), sizeof(u64) * c->q_mod.size(), hipMemcpyHostToDevice);
@@ -288,6 +316,8 @@ extern "C" int unihenn_ctx_create(uint32_t log_n, const uint32_t* prime_bits, ui
     if (up == hipSuccess) up = hipMemcpy(c->d_p_mod, c->p_mod.data(), sizeof(u64) * c->p_mod.size(), hipMemcpyHostToDevice);
     if (up == hipSuccess) up = hipMemcpy(c->d_galois_e, ge.data(), sizeof(uint32_t) * ge.size(), hipMemcpyHostToDevice);
     if (up == hipSuccess) up = hipMemcpy(c->d_cos, cs.data(), sizeof(double) * cs.size(), hipMemcpyHostToDevice);
+    if (up == hipSuccess) up = hipMemcpy(c->d_fmod, fm.data(), sizeof(FpModulus) * nm, hipMemcpyHostToDevice);
+    if (up == hipSuccess) up = hipMemcpy(c->d_twf, twf.data(), sizeof(double) * twf.size(), hipMemcpyHostToDevice);
     if (up != hipSuccess) {
         unihenn_ctx_destroy(c);
         return uh_fail(UNIHENN_EDEVICE, std::string("constant upload: ") + hipGetErrorString(up));
@@ -303,6 +333,13 @@ extern "C" int unihenn_ctx_create(uint32_t log_n, const uint32_t* prime_bits, ui
     c->dev.itw = c->d_tw + (size_t)2 * nm * n;
     c->dev.itw_sh = c->d_tw + (size_t)3 * nm * n;
     c->dev.p_mod = c->d_p_mod;
+    c->dev.fmod = c->d_fmod;
+    c->dev.twf = c->d_twf;
+    c->dev.twfq = c->d_twf + (size_t)nm * n;
+    c->dev.itwf = c->d_twf + (size_t)2 * nm * n;
+    c->dev.itwfq = c->d_twf + (size_t)3 * nm * n;
+    c->dev.fp = 1;
+    if (const char* v = getenv("UNIHENN_NTT_FP")) c->dev.fp = atoi(v) != 0;
     *out = c;
     return UNIHENN_OK;
 }
@@ -318,6 +355,8 @@ extern "C" int unihenn_ctx_destroy(unihenn_ctx* c)
     (void)hipFree(c->d_p_mod);
     (void)hipFree(c->d_galois_e);
     (void)hipFree(c->d_cos);
+    (void)hipFree(c->d_fmod);
+    (void)hipFree(c->d_twf);
     delete c;
     return UNIHENN_OK;
 }

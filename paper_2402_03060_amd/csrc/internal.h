@@ -23,6 +23,13 @@ struct DevCtx {
     const u64* itw;        // inverse twiddles  [n_mod][N]: psi^-brev(k)
     const u64* itw_sh;
     const u64* p_mod;      // [i][2]: P mod q_i and its Shoup companion, i < n_data
+    // binary64 arithmetic for primes below 2^41 (FpModulus; other moduli hold zeros)
+    const FpModulus* fmod; // [n_mod]
+    const double* twf;     // [n_mod][N]: forward twiddles as doubles
+    const double* twfq;    // fl(twiddle / q)
+    const double* itwf;    // inverse twiddles
+    const double* itwfq;
+    int fp;                // 1: transforms of primes below 2^41 use the binary64 path
 };
 
 struct unihenn_ctx {
@@ -46,6 +53,8 @@ struct unihenn_ctx {
     u64* d_p_mod = nullptr;
     uint32_t* d_galois_e = nullptr;   // 5^k mod 2N, k < N/2
     double* d_cos = nullptr;          // cos(pi t / N) as double-double, t < 2N: [2N][2]
+    FpModulus* d_fmod = nullptr;      // binary64 constants per modulus
+    double* d_twf = nullptr;          // 4 tables of n_mod * N doubles (twf, twfq, itwf, itwfq)
     int device = 0;
     DevCtx dev;
     // launch parameters (defaults, or chosen by unihenn_autotune); every
@@ -55,6 +64,8 @@ struct unihenn_ctx {
     int mac_min_wg = 2048;            // workgroups a multi-output MAC launch aims for
     int ks_min_wg = 2048;             // workgroups a key-switch inner product aims for
     int ks_order = 0;                 // workgroup order of the grouped inner product (0, 1), 2: row-fused
+    int ks_tile_log = 9;              // LDS tile of the row-fused inner product, 9..12 (2^9 words: one wave per workgroup)
+    int ks_split = 0;                 // row-fused inner product: binary64 and integer targets in two launches
     int ks_fuse_min_wg = 384;         // order 2 fuses only launches of at least this many workgroups
                                       // (environment UNIHENN_KS_FUSE_MIN_WG at context creation)
 };

