@@ -330,6 +330,10 @@ def batched_leg(P, W, name: str, B: int, per_ct: int, steps: int, tune: bool, la
     sbs = family_stats(P, stepb, 1)
     out["kernel_families"] = family_table(sbs, 1)
     out["roofline"] = roofline_entry(sbs)
+    tr = measured_traffic(out["roofline"]["kernel"], name + ("_variant" if lazy else ""))
+    if tr is not None:
+        out["roofline"]["traffic"] = round(tr["bytes_per_launch"])
+        out["roofline"]["traffic_over_algorithmic"] = tr["measured_over_algorithmic"]
     print(f"[bench] batched {name} ({plan}): {rate:.1f} {unit}, max |err| {errb:.2e}", file=sys.stderr, flush=True)
     del sb, nb, ctb, outb, stepb
     torch.cuda.empty_cache()
@@ -491,7 +495,7 @@ def headline(res: dict) -> dict:
                         "launch_ms_p99": b["launch_distribution"]["p99_ms"],
                         "max_abs_err_vs_fp64": b["max_abs_err_vs_fp64"]}
         if b.get("roofline"):
-            h["batched"]["top_kernel"] = {k: b["roofline"][k] for k in ("kernel", "frac")}
+            h["batched"]["top_kernel"] = {k: b["roofline"][k] for k in ("kernel", "frac", "traffic")}
     for key, unit in (("batched_variant", "images_per_s"), ("batched_cnn1d", "sequences_per_s"),
                       ("batched_cnn1d_variant", "sequences_per_s")):
         v = res.get(key)
@@ -546,6 +550,8 @@ def main():
                     help="requests per load level of the serving measurement (0 skips it)")
     ap.add_argument("--detail", default=os.path.join(tempfile.gettempdir(), "unihenn_bench_detail.json"),
                     help="file for the full result (kernel tables, tuning, per-model figures)")
+    ap.add_argument("--only-batched", action="store_true",
+                    help="only the batched LeNet-1 leg in the default plan (for profiling)")
     ap.add_argument("--ntt-probe", type=int, default=0, metavar="ROWS",
                     help="only time forward+inverse NTTs of ROWS limb rows at N=2^14 (kernel throughput)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -593,6 +599,17 @@ def main():
     import workloads as W
 
     log = lambda m: print("[bench] " + m, file=sys.stderr, flush=True)
+    if args.only_batched:
+        # evaluations made: batched_steps + 2 timed, batched_steps for the
+        # distribution, 1 for the kernel families
+        r = batched_leg(P, W, "lenet1_batched", args.batched_cts, 10, args.batched_steps, not args.no_tune, False,
+                        "images_per_s")
+        out = {"images_per_s": r["images_per_s"], "ms_per_launch": r["ms_per_launch"],
+               "evaluations": 2 * args.batched_steps + 3, "roofline": r["roofline"]}
+        with open(args.detail, "w") as f:
+            json.dump(dict(r, evaluations=out["evaluations"]), f, indent=1)
+        print(json.dumps(out))
+        return
     log("setup plain LeNet-1 (N=2^14)")
     st = setup(P, W, "lenet1", batch=1, tune=not args.no_tune, mode=P.EVAL_PLAIN | P.EVAL_GRAPH)
     net, ct, outs = st["net"], st["ct"], st["outs"]

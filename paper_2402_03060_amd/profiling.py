@@ -1,6 +1,7 @@
 """Summaries of rocprofv3 CSV output (kernel statistics and HBM counters).
 
     python -m paper_2402_03060_amd.profiling stats <kernel_stats.csv> --title T --command C -o out.txt
+    python -m paper_2402_03060_amd.profiling busy <counter_collection.csv> --title T --command C -o out.txt
     python -m paper_2402_03060_amd.profiling traffic --fetch F.csv --write W.csv \
         --copy-fetch CF.csv --copy-write CW.csv --copy-bytes B --family ks_inner \
         --bench-json bench.json --evals 3 --title T --command C -o out.txt
@@ -26,8 +27,8 @@ FAMILY_KERNELS = {
     "ntt_inv_row": r"k_ntt_r8<\d+, \d+, false, true, false>|k_intt_r8_gather<|k_ntt_inv<false",
     "ntt_inv_col": r"k_ntt_r8<\d+, \d+, true, true, true>|k_ntt_inv<true",
     "modup": r"k_ntt_r8_lift<\d+, \d+, 2>|k_modup",
-    "ks_inner": r"k_group_inner<|k_ks_inner<",
-    "ks_rowfused": r"k_ntt_r8_ksrow<",
+    "ks_inner": r"k_group_inner<|k_ks_inner<|k_ntt_r8_ksrow<",
+    "ks_rowfused": r"k_ks_rowmix<|k_ks_rowfp<",
     "moddown": r"k_ntt_r8_lift<\d+, \d+, 0>|k_ntt_r8_finish<\d+, \d+, 0>|k_relin_combine|k_group_sub_scale\(",
     "rescale": r"k_ntt_r8_lift<\d+, \d+, 1>|k_ntt_r8_finish<\d+, \d+, 1>|k_group_sub_scale2",
     "mac": r"k_mac_multi<|k_mac<|k_mac_group<",
@@ -135,6 +136,31 @@ def traffic_summary(fetch: str, write: str, copy_fetch: str, copy_write: str, co
     return "\n".join(lines) + "\n"
 
 
+def busy_summary(path: str, title: str, command: str) -> str:
+    """Per kernel (and per family): dispatches and the mean of each derived
+    counter (VALUBusy, OccupancyPercent) over its dispatches."""
+    per = {}
+    for r in _rows(path):
+        name = r["Kernel_Name"].replace("(anonymous namespace)::", "").replace("void ", "")
+        cut = name.find("(")
+        name = name[:cut] if cut > 0 else name
+        d = per.setdefault(name, {})
+        d.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    counters = sorted({c for d in per.values() for c in d})
+    out = [f"# {title}", f"# command: {command}",
+           "# mean over dispatches; VALUBusy: percent of GPU time the vector ALUs issue; OccupancyPercent: resident "
+           "waves against the maximum", "kernel | dispatches | " + " | ".join(counters)]
+    for name, d in sorted(per.items(), key=lambda kv: -len(kv[1].get(counters[0], []))):
+        n = len(d[counters[0]])
+        if name.startswith("__amd"):
+            continue
+        out.append(f"{name} | {n} | " + " | ".join(f"{sum(d[c]) / len(d[c]):.1f}" for c in counters))
+    fam = [f"family {f}: " + ", ".join(
+        f"{c} {sum(sum(d[c]) for k, d in per.items() if re.search(p, k)) / max(1, sum(len(d[c]) for k, d in per.items() if re.search(p, k))):.1f}"
+        for c in counters) for f, p in FAMILY_KERNELS.items() if any(re.search(p, k) for k in per)]
+    return "\n".join(out + ["# per family (mean over its dispatches)"] + fam) + "\n"
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -143,6 +169,11 @@ def main():
     s.add_argument("--title", required=True)
     s.add_argument("--command", required=True)
     s.add_argument("-o", required=True)
+    b = sub.add_parser("busy")
+    b.add_argument("csv")
+    b.add_argument("--title", required=True)
+    b.add_argument("--command", required=True)
+    b.add_argument("-o", required=True)
     t = sub.add_parser("traffic")
     for k in ("fetch", "write", "copy-fetch", "copy-write", "family", "bench-json", "title", "command"):
         t.add_argument("--" + k, required=True)
@@ -153,6 +184,8 @@ def main():
     a = ap.parse_args()
     if a.cmd == "stats":
         text = kernel_stats_summary(a.csv, a.title, a.command)
+    elif a.cmd == "busy":
+        text = busy_summary(a.csv, a.title, a.command)
     else:
         text = traffic_summary(a.fetch, a.write, a.copy_fetch, a.copy_write, a.copy_bytes, a.family, a.bench_json,
                                a.evals, a.csrc, a.title, a.command)
