@@ -312,9 +312,10 @@ enum { UNIHENN_EVAL_PLAIN = 0, UNIHENN_EVAL_HOISTED = 1, UNIHENN_EVAL_GRAPH = 2 
  * rotations of one ciphertext share the digit decomposition; results are
  * bit-identical.  GRAPH may be or-ed into either: unihenn_eval_network then
  * records its launches once into a HIP graph (per batch size and buffer
- * set) on a stream of the net's own, and replays it; the caller's stream
- * is ordered before and after the replay with events.  While kernel timing
- * (unihenn_stats_enable) is on, launches are issued directly. */
+ * set, up to 16 per net) on an idle stream of the net's own, and replays it
+ * on the caller's stream.  Replacing or dropping a graph synchronizes the
+ * device.  While kernel timing (unihenn_stats_enable) is on, launches are
+ * issued directly. */
 int unihenn_net_set_mode(unihenn_net* net, int mode);
 
 /* One convolution layer (Algorithm 1) of the net, layer index `layer`:
@@ -334,6 +335,33 @@ int unihenn_conv(const unihenn_ctx* ctx, unihenn_net* net, uint32_t layer, const
  * bound), ELEVEL, EINVAL (batch > max_batch, inputs that differ). */
 int unihenn_eval_network(const unihenn_ctx* ctx, unihenn_net* net, const unihenn_ct* in, unihenn_ct* out,
                          void* stream);
+
+/* Layer stages, for continuous batching of a stream of requests (the
+ * multi-request service of Fig. 1): stage k is layer k of the plan (stage 0
+ * also reduces the inputs to the network's level).  unihenn_eval_stage runs
+ * one stage on the ciphertexts in batch slots [slot, slot + batch) of the
+ * net's own registers (slot + batch <= max_batch): stage 0 reads `in`
+ * (unihenn_net_inputs' count of descriptors of `batch` ciphertexts, as for
+ * unihenn_eval_network), the last stage writes `out` (n_outputs descriptors
+ * of `batch` ciphertexts at 1 limb); other stages ignore both (may be NULL).
+ * A group of slots must run stages 0, 1, ..., n_stages - 1 in order; groups
+ * on disjoint slots may interleave their stages in any order, because each
+ * launch touches only its own slots, so requests that arrive while others
+ * are in flight join at the next layer boundary.  Results equal those of
+ * unihenn_eval_network bit for bit.  The stages of a net share its
+ * workspace: issue all of them on one stream.  With UNIHENN_EVAL_GRAPH in the
+ * net's mode each (stage, slot range, buffer set) is captured into a HIP
+ * graph once (up to 256 per net) and replayed on the caller's stream.
+ * Errors: EINVAL
+ * (stage or slots out of range, missing inputs or outputs), ELEVEL, ESCALE,
+ * ENOKEY, EDEVICE. */
+int unihenn_net_stages(const unihenn_net* net, uint32_t* n_stages);
+int unihenn_eval_stage(const unihenn_ctx* ctx, unihenn_net* net, uint32_t stage, uint32_t slot, uint32_t batch,
+                       const unihenn_ct* in, unihenn_ct* out, void* stream);
+/* Device memory of a net: fixed_bytes of encoded plaintexts, and
+ * per_slot_bytes for each of its max_batch batch slots (registers and the
+ * slot's share of the workspace), for admission by HBM footprint. */
+int unihenn_net_memory(const unihenn_net* net, size_t* fixed_bytes, size_t* per_slot_bytes);
 
 /* Slots of the network output: for sample b and output value v,
  * positions[b * n_values + v] is (output ciphertext index << 32) | slot.

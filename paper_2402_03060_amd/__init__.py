@@ -95,6 +95,9 @@ SIGNATURES = {
     "unihenn_conv": (C.c_int, [_vp, _vp, _u32, _P(CT), _u32, _P(CT), _P(_u32), _vp]),
     "unihenn_eval_network": (C.c_int, [_vp, _vp, _P(CT), _P(CT), _vp]),
     "unihenn_net_output_slots": (C.c_int, [_vp, _P(_u64), _P(_u32)]),
+    "unihenn_net_stages": (C.c_int, [_vp, _P(_u32)]),
+    "unihenn_eval_stage": (C.c_int, [_vp, _vp, _u32, _u32, _u32, _P(CT), _P(CT), _vp]),
+    "unihenn_net_memory": (C.c_int, [_vp, _P(_sz), _P(_sz)]),
     "unihenn_autotune": (C.c_int, [_vp, _vp, _u32, C.c_char_p, _P(TUNING), _vp]),
     "unihenn_tuning_get": (C.c_int, [_vp, _vp, _P(TUNING)]),
     "unihenn_tuning_set": (C.c_int, [_vp, _vp, _P(TUNING)]),
@@ -554,6 +557,33 @@ class Net:
         _check(lib().unihenn_eval_network(self.ctx.h, self.h, ia, od, _stream(stream)))
         for o, d in zip(outs, od):
             o.scale = d.scale
+        return outs
+
+    def stages(self) -> int:
+        n = C.c_uint32()
+        _check(lib().unihenn_net_stages(self.h, C.byref(n)))
+        return n.value
+
+    def memory(self) -> tuple[int, int]:
+        """(fixed bytes, bytes per batch slot) of the net's device memory."""
+        f, p = C.c_size_t(), C.c_size_t()
+        _check(lib().unihenn_net_memory(self.h, C.byref(f), C.byref(p)))
+        return f.value, p.value
+
+    def eval_stage(self, stage: int, slot: int, batch: int, ct=None, outs: list[Ciphertext] | None = None,
+                   stream=None):
+        """unihenn_eval_stage: stage `stage` on batch slots [slot, slot + batch);
+        ct (stage 0): the input Ciphertext or a list of n_inputs of them; outs
+        (last stage): n_out Ciphertexts of `batch` entries."""
+        ia = None
+        if ct is not None:
+            cts = list(ct) if isinstance(ct, (list, tuple)) else [ct]
+            ia = (CT * len(cts))(*[c.desc() for c in cts])
+        od = (CT * self.n_out)(*[o.desc() for o in outs]) if outs is not None else None
+        _check(lib().unihenn_eval_stage(self.ctx.h, self.h, stage, slot, batch, ia, od, _stream(stream)))
+        if outs is not None:
+            for o, d in zip(outs, od):
+                o.scale = d.scale
         return outs
 
     def conv(self, layer: int, ins: list[Ciphertext], n_out: int, out_limbs: int):

@@ -133,10 +133,10 @@ struct unihenn_net {
     int mode = UNIHENN_EVAL_PLAIN;
     bool lazy = false;  // planned with deferred ModDown (UNIHENN_PLAN_LAZY_MODDOWN)
     // captured evaluations (UNIHENN_EVAL_GRAPH), one per batch size and buffer set
-    hipStream_t gstream = nullptr;
-    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    hipStream_t gstream = nullptr;  // capture only
     struct GraphEntry {
         int batch = 0, in_limbs = 0, mode = -1;
+        int stage = -1, slot = 0;  // layer stages (unihenn_eval_stage); -1: whole evaluation
         std::vector<const u64*> in;
         std::vector<u64*> outs;
         size_t key_version = 0;
@@ -144,6 +144,7 @@ struct unihenn_net {
         unsigned long long last_use = 0;
     };
     std::vector<GraphEntry> graphs;
+    std::vector<GraphEntry> stage_graphs;
     unsigned long long graph_clock = 0;
     size_t key_version = 0;
 };
@@ -1059,12 +1060,24 @@ static size_t net_ws_words(const unihenn_ctx* c, const unihenn_net* net, int E_)
     return ws_rows * (size_t)c->n;
 }
 
+// Graphs are captured on the net's own stream, which then stays idle, and
+// replayed on the caller's stream in order with the caller's other work.
+static hipError_t begin_capture(unihenn_net* net)
+{
+    hipError_t e = hipStreamSynchronize(net->gstream);
+    return e != hipSuccess ? e : hipStreamBeginCapture(net->gstream, hipStreamCaptureModeThreadLocal);
+}
+
 static void drop_graphs(unihenn_net* net)
 {
-    if (net->gstream) (void)hipStreamSynchronize(net->gstream);
+    // a replay may still run on a caller's stream
+    if (!net->graphs.empty() || !net->stage_graphs.empty()) (void)hipDeviceSynchronize();
     for (auto& g : net->graphs)
         if (g.exec) (void)hipGraphExecDestroy(g.exec);
     net->graphs.clear();
+    for (auto& g : net->stage_graphs)
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    net->stage_graphs.clear();
 }
 
 // ---------------------------------------------------------------- C ABI
@@ -1073,8 +1086,6 @@ extern "C" int unihenn_net_destroy(unihenn_net* net)
     if (!net) return UNIHENN_OK;
     // a replay still in flight reads the arenas: let it finish first
     drop_graphs(net);
-    if (net->ev_in) (void)hipEventDestroy(net->ev_in);
-    if (net->ev_out) (void)hipEventDestroy(net->ev_out);
     if (net->gstream) (void)hipStreamDestroy(net->gstream);
     (void)hipFree(net->pt_arena);
     (void)hipFree(net->reg_arena);
@@ -1323,12 +1334,13 @@ struct Exec {
     int modup_owner = -1;       // register whose digits the workspace holds
     std::vector<const u64*> ext_in;  // network inputs (ST_DROP sources), all at ext_in_limbs
     int ext_in_limbs = 0;
+    size_t slot = 0;                 // first batch slot of the net's registers this evaluation uses
 
     u64* reg(int r)
     {
         auto it = bound.find(r);
         if (it != bound.end()) return it->second;
-        return net->reg_arena + net->phys_off[net->regs[r].phys];
+        return net->reg_arena + net->phys_off[net->regs[r].phys] + slot * 2 * net->regs[r].limbs() * c->n;
     }
 
     // workspace carve for grouped rotations (fixed offsets at the net's widest level)
@@ -1745,11 +1757,7 @@ extern "C" int unihenn_eval_network(const unihenn_ctx* c, unihenn_net* net, cons
         rc = ex.run(0, net->steps.size());
         if (rc) return rc;
     } else {
-        if (!net->gstream) {
-            UH_CHECK_HIP(hipStreamCreateWithFlags(&net->gstream, hipStreamNonBlocking));
-            UH_CHECK_HIP(hipEventCreateWithFlags(&net->ev_in, hipEventDisableTiming));
-            UH_CHECK_HIP(hipEventCreateWithFlags(&net->ev_out, hipEventDisableTiming));
-        }
+        if (!net->gstream) UH_CHECK_HIP(hipStreamCreateWithFlags(&net->gstream, hipStreamNonBlocking));
         std::vector<u64*> outs;
         for (size_t i = 0; i < net->out_regs.size(); ++i) outs.push_back(out[i].data);
         unihenn_net::GraphEntry* hit = nullptr;
@@ -1766,12 +1774,14 @@ extern "C" int unihenn_eval_network(const unihenn_ctx* c, unihenn_net* net, cons
                 hit = &net->graphs[0];
                 for (auto& g : net->graphs)
                     if (g.last_use < hit->last_use) hit = &g;
+                // it may still run on a caller's stream
+                UH_CHECK_HIP(hipDeviceSynchronize());
                 if (hit->exec) (void)hipGraphExecDestroy(hit->exec);
                 hit->exec = nullptr;
             }
             Exec ex{net, c, (int)in->batch, net->gstream, {}, -1, ins, (int)in->n_limbs};
             for (size_t i = 0; i < net->out_regs.size(); ++i) ex.bound[net->out_regs[i]] = out[i].data;
-            UH_CHECK_HIP(hipStreamBeginCapture(net->gstream, hipStreamCaptureModeThreadLocal));
+            UH_CHECK_HIP(begin_capture(net));
             int rc2 = ex.run(0, net->steps.size());
             hipGraph_t graph_obj = nullptr;
             hipError_t e = hipStreamEndCapture(net->gstream, &graph_obj);
@@ -1794,12 +1804,7 @@ extern "C" int unihenn_eval_network(const unihenn_ctx* c, unihenn_net* net, cons
             hit->key_version = net->key_version;
         }
         hit->last_use = ++net->graph_clock;
-        hipGraphExec_t gexec = hit->exec;
-        UH_CHECK_HIP(hipEventRecord(net->ev_in, cs));
-        UH_CHECK_HIP(hipStreamWaitEvent(net->gstream, net->ev_in, 0));
-        UH_CHECK_HIP(hipGraphLaunch(gexec, net->gstream));
-        UH_CHECK_HIP(hipEventRecord(net->ev_out, net->gstream));
-        UH_CHECK_HIP(hipStreamWaitEvent(cs, net->ev_out, 0));
+        UH_CHECK_HIP(hipGraphLaunch(hit->exec, cs));
     }
     for (size_t i = 0; i < net->out_regs.size(); ++i) {
         out[i].n_limbs = 1;
@@ -1846,6 +1851,135 @@ extern "C" int unihenn_conv(const unihenn_ctx* c, unihenn_net* net, uint32_t lay
         out[o].scale = r.scale;
     }
     if (interval_out) *interval_out = (uint32_t)L.interval_out;
+    return UNIHENN_OK;
+}
+
+// ---------------------------------------------------------------- layer stages
+// Stage k is layer k of the plan (stage 0 also reduces the inputs to the
+// network's level).  A group of batch slots of the net's registers runs its
+// stages in order; groups at different stages interleave on the net's stream,
+// each launch touching only its own slots.
+extern "C" int unihenn_net_stages(const unihenn_net* net, uint32_t* n_stages)
+{
+    if (!net || !n_stages) return uh_fail(UNIHENN_EINVAL, "null argument");
+    *n_stages = (uint32_t)net->layers.size();
+    return UNIHENN_OK;
+}
+
+extern "C" int unihenn_net_memory(const unihenn_net* net, size_t* fixed_bytes, size_t* per_slot_bytes)
+{
+    if (!net || !fixed_bytes || !per_slot_bytes) return uh_fail(UNIHENN_EINVAL, "null argument");
+    // every physical register holds max_batch slots of 2 * limbs rows; the
+    // workspace is laid out for max_batch slots too
+    size_t slot_words = 0;
+    std::vector<char> seen(net->phys_off.size(), 0);
+    for (const VReg& r : net->regs)
+        if (r.phys >= 0 && !seen[r.phys]) {
+            seen[r.phys] = 1;
+            slot_words += (size_t)2 * r.limbs() * net->ctx->n;
+        }
+    slot_words += (net->ws_words + net->max_batch - 1) / net->max_batch;
+    *per_slot_bytes = sizeof(u64) * slot_words;
+    *fixed_bytes = sizeof(u64) * net->pt_words;
+    return UNIHENN_OK;
+}
+
+extern "C" int unihenn_eval_stage(const unihenn_ctx* c, unihenn_net* net, uint32_t stage, uint32_t slot,
+                                  uint32_t batch, const unihenn_ct* in, unihenn_ct* out, void* stream)
+{
+    if (!c || !net) return uh_fail(UNIHENN_EINVAL, "null argument");
+    if (net->ctx != c) return uh_fail(UNIHENN_EINVAL, "net made for another context");
+    const uint32_t ns = (uint32_t)net->layers.size();
+    if (stage >= ns) return uh_fail(UNIHENN_EINVAL, "stage out of range");
+    if (batch < 1 || (size_t)slot + batch > (size_t)net->max_batch)
+        return uh_fail(UNIHENN_EINVAL, "slots [slot, slot + batch) exceed max_batch");
+    std::vector<const u64*> ins;
+    int in_limbs = 0;
+    if (stage == 0) {
+        if (!in || !in->data) return uh_fail(UNIHENN_EINVAL, "stage 0 needs the input ciphertexts");
+        if ((int)in->n_limbs < net->in_limbs) return uh_fail(UNIHENN_ELEVEL, "input has fewer limbs than the depth needs");
+        if ((int)in->n_limbs > c->n_data) return uh_fail(UNIHENN_ELEVEL, "bad input limb count");
+        if (in->scale != c->scale) return uh_fail(UNIHENN_ESCALE, "input scale differs from the encoding scale");
+        for (int i = 0; i < net->n_inputs; ++i) {
+            if (!in[i].data || in[i].batch != batch || in[i].n_limbs != in->n_limbs || in[i].scale != in->scale)
+                return uh_fail(UNIHENN_EINVAL, "input " + std::to_string(i) + " differs in batch, limbs or scale");
+            ins.push_back(in[i].data);
+        }
+        in_limbs = (int)in->n_limbs;
+    }
+    if (stage + 1 == ns) {
+        if (!out) return uh_fail(UNIHENN_EINVAL, "the last stage needs the output buffers");
+        for (size_t i = 0; i < net->out_regs.size(); ++i)
+            if (!out[i].data) return uh_fail(UNIHENN_EINVAL, "null output buffer");
+    }
+    int rc = check_keys(net);
+    if (rc) return rc;
+    std::vector<u64*> outs;
+    if (stage + 1 == ns)
+        for (size_t i = 0; i < net->out_regs.size(); ++i) outs.push_back(out[i].data);
+    const size_t b = stage == 0 ? 0 : net->layers[stage].step_begin;
+    const bool graph = (net->mode & UNIHENN_EVAL_GRAPH) && !stats_enabled();
+    hipStream_t cs = (hipStream_t)stream;
+    if (!graph) {
+        Exec ex{net, c, (int)batch, cs, {}, -1, ins, in_limbs, slot};
+        for (size_t i = 0; i < outs.size(); ++i) ex.bound[net->out_regs[i]] = outs[i];
+        rc = ex.run(b, net->layers[stage].step_end);
+        if (rc) return rc;
+    } else {
+        // one captured graph per stage, slot range and buffer set (up to 256, least recently used replaced)
+        if (!net->gstream) UH_CHECK_HIP(hipStreamCreateWithFlags(&net->gstream, hipStreamNonBlocking));
+        unihenn_net::GraphEntry* hit = nullptr;
+        for (auto& g : net->stage_graphs)
+            if (g.exec && g.stage == (int)stage && g.slot == (int)slot && g.batch == (int)batch && g.in == ins &&
+                g.in_limbs == in_limbs && g.outs == outs && g.mode == net->mode && g.key_version == net->key_version)
+                hit = &g;
+        if (!hit) {
+            if (net->stage_graphs.size() < 256) {
+                net->stage_graphs.emplace_back();
+                hit = &net->stage_graphs.back();
+            } else {
+                hit = &net->stage_graphs[0];
+                for (auto& g : net->stage_graphs)
+                    if (g.last_use < hit->last_use) hit = &g;
+                UH_CHECK_HIP(hipDeviceSynchronize());
+                if (hit->exec) (void)hipGraphExecDestroy(hit->exec);
+                hit->exec = nullptr;
+            }
+            Exec ex{net, c, (int)batch, net->gstream, {}, -1, ins, in_limbs, slot};
+            for (size_t i = 0; i < outs.size(); ++i) ex.bound[net->out_regs[i]] = outs[i];
+            UH_CHECK_HIP(begin_capture(net));
+            int rc2 = ex.run(b, net->layers[stage].step_end);
+            hipGraph_t graph_obj = nullptr;
+            hipError_t e = hipStreamEndCapture(net->gstream, &graph_obj);
+            if (rc2) {
+                if (graph_obj) (void)hipGraphDestroy(graph_obj);
+                return rc2;
+            }
+            if (e != hipSuccess) return uh_fail(UNIHENN_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+            e = hipGraphInstantiate(&hit->exec, graph_obj, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph_obj);
+            if (e != hipSuccess) {
+                hit->exec = nullptr;
+                return uh_fail(UNIHENN_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+            }
+            hit->stage = (int)stage;
+            hit->slot = (int)slot;
+            hit->batch = (int)batch;
+            hit->in = ins;
+            hit->in_limbs = in_limbs;
+            hit->outs = outs;
+            hit->mode = net->mode;
+            hit->key_version = net->key_version;
+        }
+        hit->last_use = ++net->graph_clock;
+        UH_CHECK_HIP(hipGraphLaunch(hit->exec, cs));
+    }
+    if (stage + 1 == ns)
+        for (size_t i = 0; i < net->out_regs.size(); ++i) {
+            out[i].n_limbs = 1;
+            out[i].batch = batch;
+            out[i].scale = net->regs[net->out_regs[i]].scale;
+        }
     return UNIHENN_OK;
 }
 

@@ -1,0 +1,86 @@
+"""Layer stages (unihenn_eval_stage): groups of batch slots that run the
+network's layers one at a time, interleaved with other groups at other
+layers, give the same ciphertexts as whole evaluations, bit for bit, and as
+the oracle; slots are reused by later groups."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle.run import OracleSession, build_net, run_encrypted
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(name, log_n, n_cts, lazy=False):
+    import paper_2402_03060_amd as P
+    cfg = W.config(name)
+    cfg["log_n"] = log_n
+    sess = OracleSession(cfg)
+    onet = build_net(cfg, sess.ck.slots)
+    S = cfg["samples_per_ct"]
+    xs = W.gen_inputs(cfg["input"], S * n_cts)
+    cts, expected = [], []
+    for b in range(n_cts):
+        ct, outs, _ = run_encrypted(sess, onet, xs[b * S:(b + 1) * S], enc_seed=W.SEED_ENCRYPT + b, lazy=lazy)
+        cts.append(ct)
+        expected.append([o.data for o in outs])
+    ctx = P.Context(cfg["log_n"], cfg["prime_bits"], cfg["special_bits"], 2.0 ** cfg["log_scale"])
+    net = P.Net(ctx, cfg["input"], cfg["layers"], onet.params, samples=S, stride=cfg["sample_stride"], max_batch=4,
+                lazy=lazy)
+    net.bind_keys({r: ctx.import_evk(sess.key_coeff[r]) for r in net.rotations()}, ctx.import_evk(sess.rlk_coeff))
+    gin = ctx.import_ct(np.stack([c.data for c in cts]), cts[0].scale)
+    return ctx, net, gin, expected
+
+
+@pytest.mark.parametrize("lazy", [False, True])
+def test_interleaved_stage_groups_equal_whole_evaluations(lazy):
+    import torch
+    import paper_2402_03060_amd as P
+    ctx, net, gin, expected = _setup("lenet1", 11, 4, lazy=lazy)
+    ns = net.stages()
+    assert ns == len(W.config("lenet1")["layers"])
+    for mode in (P.EVAL_PLAIN, P.EVAL_HOISTED, P.EVAL_HOISTED | P.EVAL_GRAPH):
+        net.set_mode(mode)
+        whole = [ctx.export_ct(o) for o in net.eval(gin)]
+        # group A: ciphertexts 0, 1 in slots 0..1; group B: ciphertext 2 in
+        # slot 2, started two layers later; group C: ciphertext 3 in slot 0
+        # once A is done (slot reuse)
+        groups = {"A": (0, 2, 0), "B": (2, 1, 2), "C": (0, 1, 3)}   # slot, batch, first ciphertext
+        ins = {g: P.Ciphertext(gin.data[i:i + n].contiguous(), gin.scale) for g, (_, n, i) in groups.items()}
+        outs = {g: net.alloc_outputs(n) for g, (_, n, _) in groups.items()}
+        order = ["A0", "A1", "B0", "A2", "B1", "B2", "A3"] + [f"{a}{k}" for k in range(3, ns) for a in "B"] + \
+                [f"A{k}" for k in range(4, ns)] + [f"C{k}" for k in range(ns)]
+        seen = {"A": -1, "B": -1, "C": -1}
+        for tag in order:
+            g, k = tag[0], int(tag[1:])
+            assert k == seen[g] + 1
+            seen[g] = k
+            slot, n, _ = groups[g]
+            net.eval_stage(k, slot, n, ct=ins[g] if k == 0 else None, outs=outs[g] if k == ns - 1 else None)
+        torch.cuda.synchronize()
+        assert all(v == ns - 1 for v in seen.values())
+        for g, (_, n, first) in groups.items():
+            got = [ctx.export_ct(o) for o in outs[g]]
+            for j in range(n):
+                for o in range(len(got)):
+                    assert np.array_equal(got[o][j], whole[o][first + j]), (mode, g, j, o)
+                    assert np.array_equal(got[o][j], expected[first + j][o]), (mode, g, j, o)
+
+
+def test_stage_arguments_checked():
+    import paper_2402_03060_amd as P
+    ctx, net, gin, _ = _setup("conv1", 11, 1)
+    ns = net.stages()
+    with pytest.raises(P.UnihennError) as ei:
+        net.eval_stage(ns, 0, 1)
+    assert ei.value.code == P.EINVAL
+    with pytest.raises(P.UnihennError) as ei:
+        net.eval_stage(0, 3, 2, ct=P.Ciphertext(gin.data.repeat(2, 1, 1, 1).contiguous(), gin.scale))
+    assert ei.value.code == P.EINVAL           # slots 3..4 exceed max_batch 4
+    with pytest.raises(P.UnihennError) as ei:
+        net.eval_stage(0, 0, 1)                 # stage 0 without its input
+    assert ei.value.code == P.EINVAL
+    fixed, per_slot = net.memory()
+    assert fixed > 0 and per_slot > 0
