@@ -55,6 +55,7 @@ class ModelSpec:
     slot_bytes: int           # HBM one admitted request holds (its slot, input and outputs)
     n_stages: int = 1         # layers; a request is done after that many rounds
     group_max: int = 0        # most requests one round starts (0: all free slots)
+    max_wait_s: float = 0.0   # while other models have work waiting, a partial group waits up to this
 
 
 @dataclass
@@ -79,6 +80,8 @@ class RunStats:
     joins: int = 0            # groups started while another group of their model was in flight
     max_in_flight_bytes: int = 0
     max_host_queue: int = 0
+    backlog_at_last_arrival: int = 0   # requests arrived but not finished when the last one arrived
+    group_sizes: dict = field(default_factory=dict)   # model -> sizes of the groups started
 
     def summary(self) -> dict:
         allv = np.array([v for vs in self.latencies.values() for v in vs]) if self.completed else np.zeros(1)
@@ -88,11 +91,13 @@ class RunStats:
                "p99_ms": round(1e3 * float(np.percentile(allv, 99)), 3),
                "groups": self.batches, "rounds": self.rounds, "joins": self.joins,
                "max_host_queue": self.max_host_queue, "max_in_flight_bytes": self.max_in_flight_bytes,
+               "backlog_at_last_arrival": self.backlog_at_last_arrival,
                "per_model": {}}
         for m, vs in self.latencies.items():
             a = np.array(vs)
             out["per_model"][m] = {"n": len(vs), "p50_ms": round(1e3 * float(np.percentile(a, 50)), 3),
-                                   "p99_ms": round(1e3 * float(np.percentile(a, 99)), 3)}
+                                   "p99_ms": round(1e3 * float(np.percentile(a, 99)), 3),
+                                   "mean_group": round(float(np.mean(self.group_sizes.get(m, [0]))), 2)}
         return out
 
 
@@ -160,6 +165,16 @@ class Scheduler:
     def _release_slots(self, m: str, a: int, k: int):
         self.free[m].append(a // self._block(m))
 
+    def _start_now(self, m: str, now: float) -> bool:
+        """Start a group of m's admitted requests now: when it would be full,
+        when its oldest request has waited max_wait_s, or when no other model
+        has requests waiting (nothing to give the GPU time to).  Fuller groups
+        cost less GPU time per request, which goes to the other models."""
+        spec = self.models[m]
+        if len(self.ready[m]) >= self._block(m) or now - self.ready[m][0].arrival >= spec.max_wait_s:
+            return True
+        return not any(self.host[x] or self.ready[x] for x in self.models if x != m)
+
     def plan_round(self, m: str, now: float):
         """The next round of model m: a new group of its admitted requests
         (first come, first served, in one free slot range), then one layer of
@@ -167,7 +182,7 @@ class Scheduler:
         [(group, stage)])."""
         spec = self.models[m]
         new = None
-        if self.ready[m]:
+        if self.ready[m] and self._start_now(m, now):
             slot, k = self._take_slots(m, len(self.ready[m]))
             if k:
                 new = Group(m, slot, [self.ready[m].popleft() for _ in range(k)])
@@ -207,6 +222,8 @@ def serve(scheduler: Scheduler, executor, requests: list, clock=time.perf_counte
         now = clock() - t0
         while pending and pending[0].arrival <= now:
             scheduler.arrive(pending.popleft())
+            if not pending:
+                stats.backlog_at_last_arrival = len(requests) - stats.completed
         stats.max_host_queue = max(stats.max_host_queue, scheduler.queued())
         for m in scheduler.models:
             h = scheduler.busy[m]
@@ -231,6 +248,7 @@ def serve(scheduler: Scheduler, executor, requests: list, clock=time.perf_counte
             if new is not None:
                 stats.batches += 1
                 stats.joins += in_flight > 0
+                stats.group_sizes.setdefault(m, []).append(new.size)
             stats.rounds += 1
             scheduler.busy[m] = executor.run_round(m, new, steps)
         if poll_s:
@@ -268,6 +286,7 @@ class GpuExecutor:
         self.torch = torch
         self.m = models          # name -> dict(net, ctx, pool (ciphertext batch tensor), ...)
         self.keep_results = keep_results
+        self.batch_time = {}     # name -> seconds for a full group through every layer (warmup)
         for name, d in models.items():
             ctx, net = d["ctx"], d["net"]
             pool = d["pool"]      # Ciphertext [P][2][nl][N]
@@ -309,6 +328,15 @@ class GpuExecutor:
                     g = Group(m, a, [Request(-1, m, 0.0, payload=i % d["pool"].batch) for i in range(b)])
                     for k in range(d["n_stages"]):
                         self.run_round(m, g if k == 0 else None, [(g, k)]).synchronize()
+            # batch time: a full group through every layer (replays), median of 3
+            g = Group(m, 0, [Request(-1, m, 0.0, payload=i % d["pool"].batch) for i in range(blk)])
+            ts = []
+            for _ in range(3):
+                t0 = time.perf_counter()
+                for k in range(d["n_stages"]):
+                    self.run_round(m, g if k == 0 else None, [(g, k)]).synchronize()
+                ts.append(time.perf_counter() - t0)
+            self.batch_time[m] = sorted(ts)[1]
 
     def done(self, handle) -> bool:
         return handle.query()
@@ -372,13 +400,16 @@ SERVE_MIX = {"conv1": 0.5, "cnn1d": 0.3, "cifar_cnn": 0.2}
 
 
 def serving_benchmark(P, W, n_requests: int, tuning_cache: str | None = None, hbm_budget: int | None = None,
-                      levels=(0.5, 0.8, 1.0), log=print, lazy: bool = True, fc_doubling: bool = True) -> dict:
+                      levels=(0.5, 0.8, 0.9, 1.0), log=print, lazy: bool = True, fc_doubling: bool = True,
+                      wait_batches: float = 3.0) -> dict:
     """Three models of different ring sizes behind the server: saturation
     throughput (a burst of requests queued at t = 0), then Poisson arrivals
     (seed 4, mix 50/30/20) at the given fractions of it.  The admission budget
     defaults to the bytes of every model's slots (the memory reserved for
     requests).  The models run the deferred-ModDown plan with the doubling FC
-    sum unless lazy / fc_doubling say otherwise."""
+    sum unless lazy / fc_doubling say otherwise.  While other models have
+    work waiting, a partial group waits up to wait_batches of its model's
+    batch time (a full group through every layer) to fill."""
     import torch
     plan = " + ".join([n for n, on in (("deferred ModDown", lazy), ("doubling FC sum", fc_doubling)) if on]) \
         or "default"
@@ -388,7 +419,10 @@ def serving_benchmark(P, W, n_requests: int, tuning_cache: str | None = None, hb
     ex = GpuExecutor(models)
     specs = {m: d["spec"] for m, d in models.items()}
     ex.warmup(specs)
-    log("warmed up: a graph per layer, block and group size captured")
+    for m, spec in specs.items():
+        spec.max_wait_s = wait_batches * ex.batch_time[m]
+    log("warmed up: a graph per layer, block and group size captured; batch times " +
+        ", ".join(f"{m} {1e3 * t:.2f} ms" for m, t in ex.batch_time.items()))
     if hbm_budget is None:
         hbm_budget = sum(s.slots * s.slot_bytes for s in specs.values())
     payloads = {m: list(range(16)) for m in models}
@@ -397,7 +431,9 @@ def serving_benchmark(P, W, n_requests: int, tuning_cache: str | None = None, hb
                           "samples_per_ct": d["cfg"]["samples_per_ct"], "request_bytes": d["spec"].slot_bytes}
                       for m, d in models.items()},
            "plan": plan, "batching": "continuous at layer boundaries", "mix": SERVE_MIX,
-           "arrival_seed": W.SEED_ARRIVALS, "hbm_budget_bytes": hbm_budget, "requests_per_level": n_requests}
+           "arrival_seed": W.SEED_ARRIVALS, "hbm_budget_bytes": hbm_budget, "requests_per_level": n_requests,
+           "batch_time_ms": {m: round(1e3 * t, 3) for m, t in ex.batch_time.items()},
+           "max_wait_batches": wait_batches}
     burst = poisson_requests(SERVE_MIX, 1e9, min(n_requests, 3000), W.SEED_ARRIVALS, payloads)
     st = serve(Scheduler(specs, hbm_budget), ex, burst)
     torch.cuda.synchronize()
@@ -427,7 +463,9 @@ def main():
     import sys
     ap = argparse.ArgumentParser(description="serving measurement: saturation, then Poisson load levels")
     ap.add_argument("--requests", type=int, default=10000, help="requests per load level")
-    ap.add_argument("--levels", default="0.5,0.8,1.0")
+    ap.add_argument("--levels", default="0.5,0.8,0.9,1.0")
+    ap.add_argument("--wait-batches", type=float, default=3.0,
+                    help="longest wait of a partial group, in batch times, while other models have work")
     ap.add_argument("--default-plan", action="store_true",
                     help="the default plan instead of deferred ModDown + doubling FC sum")
     ap.add_argument("--tuning-cache", default=os.path.join(os.path.dirname(os.path.abspath(__file__)),
@@ -438,7 +476,7 @@ def main():
     import workloads as W
     out = serving_benchmark(P, W, a.requests, tuning_cache=a.tuning_cache,
                             levels=tuple(float(x) for x in a.levels.split(",")),
-                            lazy=not a.default_plan, fc_doubling=not a.default_plan,
+                            lazy=not a.default_plan, fc_doubling=not a.default_plan, wait_batches=a.wait_batches,
                             log=lambda m: print("[serve] " + m, file=sys.stderr, flush=True))
     print(json.dumps(out))
 

@@ -279,3 +279,20 @@ def test_budget_is_first_come_first_served():
     st, _, _, _ = _run(reqs, 1000)
     assert st.completed == 3
     assert reqs[2].admitted >= reqs[1].admitted
+
+
+def test_partial_group_waits_only_while_others_have_work():
+    """Model a alone: a single request starts at once.  With model c's
+    requests waiting, a's partial group waits up to max_wait_s to fill."""
+    import dataclasses
+    models = dict(MODELS)
+    models["a"] = dataclasses.replace(MODELS["a"], max_wait_s=5e-4)
+    st, _, _, _ = _run([Request(0, "a", 0.0, 0)], 10 ** 9, models)
+    assert st.group_sizes["a"] == [1]
+    reqs = [Request(i, "c", 0.0, 0) for i in range(6)] + [Request(6 + i, "a", 1e-4 * (i + 1), 0) for i in range(3)]
+    st, _, _, _ = _run(reqs, 10 ** 9, models)
+    assert st.completed == len(reqs)
+    assert st.group_sizes["a"][0] >= 2          # waited for company
+    for r in reqs:
+        if r.model == "a":
+            assert r.started - r.arrival <= 5e-4 + 1e-4
