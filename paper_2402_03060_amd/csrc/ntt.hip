@@ -16,6 +16,7 @@
 // words (16 KiB) of LDS and 256 threads; the radix-8 kernels take the tile
 // size (2^11 or 2^12 words, with 2^8 or 2^9 threads) as a launch parameter.
 #include <cstring>
+#include <type_traits>
 
 #include "kernels.h"
 
@@ -243,6 +244,21 @@ __device__ __forceinline__ int row_arith(const DevCtx& ctx, u64 q, int lazy_smal
     return (lazy_small && q < (1ull << 40)) ? 1 : 0;
 }
 
+// An IO type with a nested Pre (operands of its store epilogue) has them
+// loaded with the pass's input, so that their latency hides behind the
+// butterflies: pre1 / pre2 fetch them for one word / two adjacent words, and
+// store_pre / store2_pre complete the stores from them.
+template <class IO, class = void>
+struct IoPre {
+    static constexpr bool on = false;
+    struct type {};
+};
+template <class IO>
+struct IoPre<IO, std::void_t<typename IO::Pre>> {
+    static constexpr bool on = true;
+    using type = typename IO::Pre;
+};
+
 template <int LOG_R, int TILE_LOG, bool STRIDED, bool INV, bool LAST, int AR, class IO>
 __device__ __forceinline__ void ntt_r8_body(u64* __restrict__ s, const IO& io, const Modulus& M,
                                             const u64* __restrict__ tw, const u64* __restrict__ tw_sh, int log_n,
@@ -275,6 +291,7 @@ __device__ __forceinline__ void ntt_r8_body(u64* __restrict__ s, const IO& io, c
 #define GIDX(u) (STRIDED ? col + ((u) << log_stride) : (col << LOG_R) + (u))
 #define LIDX(u) (STRIDED ? ((u) << log_cols) + c : c * RP + (u) + ((u) >> 3))
     V x[8];
+    typename IoPre<IO>::type pre;
 #pragma clang loop unroll(full)
     for (int rho = 0; rho < ROUNDS; ++rho) {
         // bits held this round: [lo, lo + 3)
@@ -290,6 +307,20 @@ __device__ __forceinline__ void ntt_r8_body(u64* __restrict__ s, const IO& io, c
             } else {
 #pragma clang loop unroll(full)
                 for (int m = 0; m < 8; ++m) xi[m] = io.load(GIDX(ub | (m << lo)));
+            }
+            if constexpr (IoPre<IO>::on) {
+                // the words this thread stores in the last round
+                constexpr int rl = ROUNDS - 1;
+                const int lo_l = INV ? (3 * rl < LOG_R - 3 ? 3 * rl : LOG_R - 3)
+                                     : (LOG_R - 3 - 3 * rl > 0 ? LOG_R - 3 - 3 * rl : 0);
+                const int ub_l = ((g >> lo_l) << (lo_l + 3)) | (g & ((1 << lo_l) - 1));
+                if (!STRIDED && lo_l == 0) {
+#pragma clang loop unroll(full)
+                    for (int h = 0; h < 4; ++h) io.pre2(GIDX(ub_l) + 2 * h, pre, h);
+                } else {
+#pragma clang loop unroll(full)
+                    for (int m = 0; m < 8; ++m) io.pre1(GIDX(ub_l | (m << lo_l)), pre, m);
+                }
             }
 #pragma clang loop unroll(full)
             for (int m = 0; m < 8; ++m) {
@@ -386,10 +417,16 @@ __device__ __forceinline__ void ntt_r8_body(u64* __restrict__ s, const IO& io, c
                 }
                 if (!STRIDED && lo == 0) {
 #pragma clang loop unroll(full)
-                    for (int h = 0; h < 4; ++h) io.store2(GIDX(ub) + 2 * h, xo[2 * h], xo[2 * h + 1]);
+                    for (int h = 0; h < 4; ++h) {
+                        if constexpr (IoPre<IO>::on) io.store2_pre(GIDX(ub) + 2 * h, xo[2 * h], xo[2 * h + 1], pre, h);
+                        else io.store2(GIDX(ub) + 2 * h, xo[2 * h], xo[2 * h + 1]);
+                    }
                 } else {
 #pragma clang loop unroll(full)
-                    for (int m = 0; m < 8; ++m) io.store(GIDX(ub | (m << lo)), xo[m]);
+                    for (int m = 0; m < 8; ++m) {
+                        if constexpr (IoPre<IO>::on) io.store_pre(GIDX(ub | (m << lo)), xo[m], pre, m);
+                        else io.store(GIDX(ub | (m << lo)), xo[m]);
+                    }
                 }
             }
         }
@@ -505,6 +542,38 @@ struct FinishIO {
             a1 = addend(g + 1);
         }
         *reinterpret_cast<ulonglong2*>(out + g) = make_ulonglong2(finish(t0, xv.x, a0), finish(t1, xv.y, a1));
+    }
+    // epilogue operands fetched with the input (IoPre)
+    struct Pre {
+        u64 x[8], a[8];
+    };
+    __device__ __forceinline__ void pre1(int g, Pre& p, int m) const
+    {
+        p.x[m] = x[g];
+        p.a[m] = addend(g);
+    }
+    __device__ __forceinline__ void pre2(int g, Pre& p, int h) const
+    {
+        const ulonglong2 xv = *reinterpret_cast<const ulonglong2*>(x + g);
+        p.x[2 * h] = xv.x;
+        p.x[2 * h + 1] = xv.y;
+        if (add && perm == 1) {
+            const ulonglong2 av = *reinterpret_cast<const ulonglong2*>(add + g);
+            p.a[2 * h] = av.x;
+            p.a[2 * h + 1] = av.y;
+        } else {
+            p.a[2 * h] = addend(g);
+            p.a[2 * h + 1] = addend(g + 1);
+        }
+    }
+    __device__ __forceinline__ void store_pre(int g, u64 t, const Pre& p, int m) const
+    {
+        out[g] = finish(t, p.x[m], p.a[m]);
+    }
+    __device__ __forceinline__ void store2_pre(int g, u64 t0, u64 t1, const Pre& p, int h) const
+    {
+        *reinterpret_cast<ulonglong2*>(out + g) =
+            make_ulonglong2(finish(t0, p.x[2 * h], p.a[2 * h]), finish(t1, p.x[2 * h + 1], p.a[2 * h + 1]));
     }
 };
 
