@@ -55,7 +55,7 @@ class ModelSpec:
     slot_bytes: int           # HBM one admitted request holds (its slot, input and outputs)
     n_stages: int = 1         # layers; a request is done after that many rounds
     group_max: int = 0        # most requests one round starts (0: all free slots)
-    max_wait_s: float = 0.0   # while other models have work waiting, a partial group waits up to this
+    max_wait_s: float = 0.0   # while another model is backlogged, a partial group waits up to this
 
 
 @dataclass
@@ -165,15 +165,19 @@ class Scheduler:
     def _release_slots(self, m: str, a: int, k: int):
         self.free[m].append(a // self._block(m))
 
+    def _backlogged(self, m: str) -> bool:
+        """Model m has at least a full group of requests waiting."""
+        return len(self.host[m]) + len(self.ready[m]) >= self._block(m)
+
     def _start_now(self, m: str, now: float) -> bool:
         """Start a group of m's admitted requests now: when it would be full,
         when its oldest request has waited max_wait_s, or when no other model
-        has requests waiting (nothing to give the GPU time to).  Fuller groups
-        cost less GPU time per request, which goes to the other models."""
+        is backlogged (nothing to give the GPU time to).  Fuller groups cost
+        less GPU time per request, which goes to the backlogged models."""
         spec = self.models[m]
         if len(self.ready[m]) >= self._block(m) or now - self.ready[m][0].arrival >= spec.max_wait_s:
             return True
-        return not any(self.host[x] or self.ready[x] for x in self.models if x != m)
+        return not any(self._backlogged(x) for x in self.models if x != m)
 
     def plan_round(self, m: str, now: float):
         """The next round of model m: a new group of its admitted requests
@@ -407,9 +411,9 @@ def serving_benchmark(P, W, n_requests: int, tuning_cache: str | None = None, hb
     (seed 4, mix 50/30/20) at the given fractions of it.  The admission budget
     defaults to the bytes of every model's slots (the memory reserved for
     requests).  The models run the deferred-ModDown plan with the doubling FC
-    sum unless lazy / fc_doubling say otherwise.  While other models have
-    work waiting, a partial group waits up to wait_batches of its model's
-    batch time (a full group through every layer) to fill."""
+    sum unless lazy / fc_doubling say otherwise.  While another model has a
+    full group waiting, a partial group waits up to wait_batches of its
+    model's batch time (a full group through every layer) to fill."""
     import torch
     plan = " + ".join([n for n, on in (("deferred ModDown", lazy), ("doubling FC sum", fc_doubling)) if on]) \
         or "default"
@@ -465,7 +469,7 @@ def main():
     ap.add_argument("--requests", type=int, default=10000, help="requests per load level")
     ap.add_argument("--levels", default="0.5,0.8,0.9,1.0")
     ap.add_argument("--wait-batches", type=float, default=3.0,
-                    help="longest wait of a partial group, in batch times, while other models have work")
+                    help="longest wait of a partial group, in batch times, while another model is backlogged")
     ap.add_argument("--default-plan", action="store_true",
                     help="the default plan instead of deferred ModDown + doubling FC sum")
     ap.add_argument("--tuning-cache", default=os.path.join(os.path.dirname(os.path.abspath(__file__)),

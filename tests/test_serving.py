@@ -281,9 +281,10 @@ def test_budget_is_first_come_first_served():
     assert reqs[2].admitted >= reqs[1].admitted
 
 
-def test_partial_group_waits_only_while_others_have_work():
+def test_partial_group_waits_only_while_others_are_backlogged():
     """Model a alone: a single request starts at once.  With model c's
-    requests waiting, a's partial group waits up to max_wait_s to fill."""
+    requests queued (a full group of c waiting), a's partial group waits up
+    to max_wait_s to fill."""
     import dataclasses
     models = dict(MODELS)
     models["a"] = dataclasses.replace(MODELS["a"], max_wait_s=5e-4)
@@ -296,3 +297,15 @@ def test_partial_group_waits_only_while_others_have_work():
     for r in reqs:
         if r.model == "a":
             assert r.started - r.arrival <= 5e-4 + 1e-4
+
+
+def test_partial_group_does_not_wait_for_a_short_queue():
+    """Another model with less than a full group waiting is not backlogged:
+    a's single request starts at once."""
+    import dataclasses
+    models = dict(MODELS)
+    models["a"] = dataclasses.replace(MODELS["a"], max_wait_s=5e-3)
+    reqs = [Request(0, "b", 0.0, 0), Request(1, "a", 0.0, 0)]      # b: group of 2, one waiting
+    st, _, _, _ = _run(reqs, 10 ** 9, models)
+    assert st.completed == 2
+    assert reqs[1].started - reqs[1].arrival < 1e-3
