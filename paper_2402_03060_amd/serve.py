@@ -405,7 +405,7 @@ SERVE_MIX = {"conv1": 0.5, "cnn1d": 0.3, "cifar_cnn": 0.2}
 
 def serving_benchmark(P, W, n_requests: int, tuning_cache: str | None = None, hbm_budget: int | None = None,
                       levels=(0.5, 0.8, 0.9, 1.0), log=print, lazy: bool = True, fc_doubling: bool = True,
-                      wait_batches: float = 3.0) -> dict:
+                      wait_batches: float = 3.0, slots: dict | None = None) -> dict:
     """Three models of different ring sizes behind the server: saturation
     throughput (a burst of requests queued at t = 0), then Poisson arrivals
     (seed 4, mix 50/30/20) at the given fractions of it.  The admission budget
@@ -413,18 +413,25 @@ def serving_benchmark(P, W, n_requests: int, tuning_cache: str | None = None, hb
     requests).  The models run the deferred-ModDown plan with the doubling FC
     sum unless lazy / fc_doubling say otherwise.  While another model has a
     full group waiting, a partial group waits up to wait_batches of its
-    model's batch time (a full group through every layer) to fill."""
+    model's batch time (a full group through every layer), and at least half
+    the longest model's batch time, to fill."""
     import torch
     plan = " + ".join([n for n, on in (("deferred ModDown", lazy), ("doubling FC sum", fc_doubling)) if on]) \
         or "default"
-    log("setup serving models " + ", ".join(SERVE_MODELS) + f" ({plan} plan)")
+    slots = dict(SERVE_MODELS, **(slots or {}))
+    log("setup serving models " + ", ".join(f"{m} ({s} slots, groups of {g})" for m, (s, g) in slots.items()) +
+        f" ({plan} plan)")
     models = {m: prepare_model(P, W, m, s, pool_size=16, group_max=g, lazy=lazy, fc_doubling=fc_doubling,
-                               tuning_cache=tuning_cache) for m, (s, g) in SERVE_MODELS.items()}
+                               tuning_cache=tuning_cache) for m, (s, g) in slots.items()}
     ex = GpuExecutor(models)
     specs = {m: d["spec"] for m, d in models.items()}
     ex.warmup(specs)
+    # a model with short batches may wait at least half the longest batch
+    # time: its latency stays far below the slow models' while its fuller
+    # groups free GPU time for them
+    floor_s = 0.5 * max(ex.batch_time.values())
     for m, spec in specs.items():
-        spec.max_wait_s = wait_batches * ex.batch_time[m]
+        spec.max_wait_s = max(wait_batches * ex.batch_time[m], floor_s)
     log("warmed up: a graph per layer, block and group size captured; batch times " +
         ", ".join(f"{m} {1e3 * t:.2f} ms" for m, t in ex.batch_time.items()))
     if hbm_budget is None:
@@ -437,7 +444,8 @@ def serving_benchmark(P, W, n_requests: int, tuning_cache: str | None = None, hb
            "plan": plan, "batching": "continuous at layer boundaries", "mix": SERVE_MIX,
            "arrival_seed": W.SEED_ARRIVALS, "hbm_budget_bytes": hbm_budget, "requests_per_level": n_requests,
            "batch_time_ms": {m: round(1e3 * t, 3) for m, t in ex.batch_time.items()},
-           "max_wait_batches": wait_batches}
+           "max_wait_batches": wait_batches,
+           "max_wait_ms": {m: round(1e3 * sp.max_wait_s, 3) for m, sp in specs.items()}}
     burst = poisson_requests(SERVE_MIX, 1e9, min(n_requests, 3000), W.SEED_ARRIVALS, payloads)
     st = serve(Scheduler(specs, hbm_budget), ex, burst)
     torch.cuda.synchronize()
@@ -470,6 +478,7 @@ def main():
     ap.add_argument("--levels", default="0.5,0.8,0.9,1.0")
     ap.add_argument("--wait-batches", type=float, default=3.0,
                     help="longest wait of a partial group, in batch times, while another model is backlogged")
+    ap.add_argument("--slots", default="", help="per model slots:group, e.g. cifar_cnn=16:8,conv1=32:16")
     ap.add_argument("--default-plan", action="store_true",
                     help="the default plan instead of deferred ModDown + doubling FC sum")
     ap.add_argument("--tuning-cache", default=os.path.join(os.path.dirname(os.path.abspath(__file__)),
@@ -481,6 +490,8 @@ def main():
     out = serving_benchmark(P, W, a.requests, tuning_cache=a.tuning_cache,
                             levels=tuple(float(x) for x in a.levels.split(",")),
                             lazy=not a.default_plan, fc_doubling=not a.default_plan, wait_batches=a.wait_batches,
+                            slots={k: tuple(int(x) for x in v.split(":")) for k, v in
+                                   (kv.split("=") for kv in a.slots.split(",") if kv)},
                             log=lambda m: print("[serve] " + m, file=sys.stderr, flush=True))
     print(json.dumps(out))
 
