@@ -140,6 +140,7 @@ struct GatherArgs {
     const u64* src[UH_FUSE_MAX];
     u32 perm[UH_FUSE_MAX];
     int stride;                      // rows per polynomial in the sources
+    int mod0;                        // modulus index of gathered limb j: mod0 + j
 };
 bool launch_ntt_inv_gather(const unihenn_ctx* c, u64* dcoef, const GatherArgs& ga, int D, int B, int nl,
                            hipStream_t st);

@@ -1034,6 +1034,25 @@ void launch_group_to_ext(const unihenn_ctx* c, const EwGroup& g, int batch, int 
 
 // ModDown of extended sums: the P rows gathered and inverse transformed, then
 // lifted, forward transformed and combined, (x - R) P^-1, in one fused pass
+// last[e][b][c] = INTT of limb `limb` (modulus index `mi`) of polynomial
+// (b, c) of in_e (rows of `limbs` limbs), read straight from in_e by the
+// gathering inverse NTT's first pass; false (nothing launched) when that
+// pass is outside the radix-8 kernels.
+static bool inv_ntt_of_limb(const unihenn_ctx* c, u64* last, const u64* const* in, int E, int B, int limbs,
+                            int limb, int mi, hipStream_t s)
+{
+    if (E > UH_FUSE_MAX || !ntt_fusable(c)) return false;
+    GatherArgs gta;
+    memset(&gta, 0, sizeof(gta));
+    for (int e = 0; e < E; ++e) {
+        gta.src[e] = in[e] + (size_t)limb * c->n;
+        gta.perm[e] = 1;
+    }
+    gta.stride = limbs;
+    gta.mod0 = mi;
+    return launch_ntt_inv_gather(c, last, gta, E, B * 2, 1, s);
+}
+
 void group_moddown(const unihenn_ctx* c, int E, const u64* const* in, u64* const* out, int B, int nl, u64* ws,
                    hipStream_t s)
 {
@@ -1048,11 +1067,13 @@ void group_moddown(const unihenn_ctx* c, int E, const u64* const* in, u64* const
     u64* last = ws;                               // [E][B][2]
     u64* R = ws + (size_t)E * B * 2 * rn;         // [E][B][2][nl]
     const unsigned gx = (c->n + EW_THREADS - 1) / EW_THREADS;
-    {
-        LaunchTimer tm(KF_OTHER, 16.0 * c->n * E * B * 2, s);
-        k_group_last<<<dim3(gx, B * 2, E), EW_THREADS, 0, s>>>(last, g, nl + 1, c->n);
+    if (!inv_ntt_of_limb(c, last, in, E, B, nl + 1, nl, c->n_data, s)) {
+        {
+            LaunchTimer tm(KF_OTHER, 16.0 * c->n * E * B * 2, s);
+            k_group_last<<<dim3(gx, B * 2, E), EW_THREADS, 0, s>>>(last, g, nl + 1, c->n);
+        }
+        launch_ntt_inv(c, last, E * B * 2, rowmap_list({c->n_data}), s);
     }
-    launch_ntt_inv(c, last, E * B * 2, rowmap_list({c->n_data}), s);
     {
         FuseArgs fa;
         memset(&fa, 0, sizeof(fa));
@@ -1092,11 +1113,13 @@ void group_rescale(const unihenn_ctx* c, int E, const u64* const* in, u64* const
     u64* last = ws;                               // [E][B][2]
     u64* R = ws + (size_t)E * B * 2 * rn;         // [E][B][2][l]
     const unsigned gx = (c->n + EW_THREADS - 1) / EW_THREADS;
-    {
-        LaunchTimer tm(KF_OTHER, 16.0 * c->n * E * B * 2, s);
-        k_group_last<<<dim3(gx, B * 2, E), EW_THREADS, 0, s>>>(last, g, nl, c->n);
+    if (!inv_ntt_of_limb(c, last, in, E, B, nl, l, l, s)) {
+        {
+            LaunchTimer tm(KF_OTHER, 16.0 * c->n * E * B * 2, s);
+            k_group_last<<<dim3(gx, B * 2, E), EW_THREADS, 0, s>>>(last, g, nl, c->n);
+        }
+        launch_ntt_inv(c, last, E * B * 2, rowmap_list({l}), s);
     }
-    launch_ntt_inv(c, last, E * B * 2, rowmap_list({l}), s);
     const u64* inv = c->d_inv_last + (size_t)l * c->primes.size() * 2;
     {
         FuseArgs fa;

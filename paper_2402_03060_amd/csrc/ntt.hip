@@ -1075,7 +1075,7 @@ __global__ void __launch_bounds__((1 << TILE_LOG) / 8) k_intt_r8_gather(u64* __r
     const int blk = pb / B, b = pb % B;
     const GatherIO io{ga.src[blk] + ((size_t)b * ga.stride + j) * ctx.n, dcoef + (size_t)row * ctx.n, ga.perm[blk],
                       ctx.log_n};
-    ntt_r8_row<LOG_R, TILE_LOG, false, true, false>(s, io, ctx, j, log_cols, sigma0, lazy_small);
+    ntt_r8_row<LOG_R, TILE_LOG, false, true, false>(s, io, ctx, ga.mod0 + j, log_cols, sigma0, lazy_small);
 }
 
 template <int LOG_R, int TILE_LOG, int TAG>
@@ -1424,9 +1424,10 @@ void launch_ks_rowfused(const unihenn_ctx* c, const GroupArgs& ga, int B, int nl
 }
 
 // Inverse NTT of gathered rows: dcoef row (blk * B + b) * nl + j is limb j
-// of polynomial b of block blk (rows at ga.src[blk] + (b * ga.stride + j) * N),
-// read through the automorphism ga.perm[blk]; the first pass loads them
-// directly.  False when a pass is outside the radix-8 kernels.
+// of polynomial b of block blk (rows at ga.src[blk] + (b * ga.stride + j) * N,
+// modulus index ga.mod0 + j), read through the automorphism ga.perm[blk]; the
+// first pass loads them directly.  False when a pass is outside the radix-8
+// kernels.
 bool launch_ntt_inv_gather(const unihenn_ctx* c, u64* dcoef, const GatherArgs& ga, int D, int B, int nl,
                            hipStream_t st)
 {
@@ -1451,7 +1452,10 @@ bool launch_ntt_inv_gather(const unihenn_ctx* c, u64* dcoef, const GatherArgs& g
     }
     {
         LaunchTimer tm(KF_NTT_INV_COL, 16.0 * c->n * n_rows, st, half * l1);
-        launch_pass_r8(dcoef, c->dev, rowmap_ct(nl), n_rows, c->log_n, l1, 0, true, true, true, tile, 1, st);
+        std::vector<int> mods(nl);
+        for (int j = 0; j < nl; ++j) mods[j] = ga.mod0 + j;
+        launch_pass_r8(dcoef, c->dev, ga.mod0 == 0 ? rowmap_ct(nl) : rowmap_list(mods), n_rows, c->log_n, l1, 0,
+                       true, true, true, tile, 1, st);
     }
     return true;
 }
