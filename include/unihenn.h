@@ -94,6 +94,16 @@ int unihenn_ctx_primes(const unihenn_ctx* ctx, uint64_t* out);
  * Errors: EINVAL (n_limbs outside 1..n_data). */
 int unihenn_to_ntt(const unihenn_ctx* ctx, uint64_t* data, uint32_t n_limbs, uint32_t n_polys, void* stream);
 int unihenn_from_ntt(const unihenn_ctx* ctx, uint64_t* data, uint32_t n_limbs, uint32_t n_polys, void* stream);
+/* Out-of-place import / export of ciphertexts (Section II-B: the client
+ * encrypts and decrypts, the server evaluates; here in NTT form).
+ * unihenn_import_ct copies coeff ([dst->batch][2][dst->n_limbs][N]
+ * coefficients in [0, q_i), device or host memory) into dst->data and
+ * transforms it there; unihenn_export_ct writes the canonical coefficients
+ * of src into coeff (device memory, same layout).  coeff may equal the
+ * ciphertext's data (in place).  The caller owns every buffer.
+ * Errors: EINVAL (null pointers, n_limbs outside 1..n_data, batch 0). */
+int unihenn_import_ct(const unihenn_ctx* ctx, const uint64_t* coeff, unihenn_ct* dst, void* stream);
+int unihenn_export_ct(const unihenn_ctx* ctx, const unihenn_ct* src, uint64_t* coeff, void* stream);
 
 /* Import a switching key given in coefficient form, layout
  * [n_data][2][n_data+1][N] with evk_j = (-a_j s + e_j + [i = j] P t, a_j)
@@ -362,6 +372,14 @@ int unihenn_eval_stage(const unihenn_ctx* ctx, unihenn_net* net, uint32_t stage,
  * per_slot_bytes for each of its max_batch batch slots (registers and the
  * slot's share of the workspace), for admission by HBM footprint. */
 int unihenn_net_memory(const unihenn_net* net, size_t* fixed_bytes, size_t* per_slot_bytes);
+/* Device workspace a net uses for an evaluation of `batch` ciphertexts.  The
+ * net allocates it at unihenn_net_create, laid out for max_batch ciphertexts
+ * (so that captured graphs and the layer stages of every slot range keep one
+ * address), and grows it when the tuner picks larger rotation groups; bytes
+ * (host) receives its current size, the same for every batch up to
+ * max_batch.  Errors: EINVAL (batch outside 1..max_batch, a net of another
+ * context). */
+int unihenn_workspace_size(const unihenn_ctx* ctx, const unihenn_net* net, uint32_t batch, size_t* bytes);
 
 /* Slots of the network output: for sample b and output value v,
  * positions[b * n_values + v] is (output ciphertext index << 32) | slot.

@@ -67,6 +67,8 @@ SIGNATURES = {
     "unihenn_ctx_primes": (C.c_int, [_vp, _P(_u64)]),
     "unihenn_to_ntt": (C.c_int, [_vp, _vp, _u32, _u32, _vp]),
     "unihenn_from_ntt": (C.c_int, [_vp, _vp, _u32, _u32, _vp]),
+    "unihenn_import_ct": (C.c_int, [_vp, _vp, _P(CT), _vp]),
+    "unihenn_export_ct": (C.c_int, [_vp, _P(CT), _vp, _vp]),
     "unihenn_import_evk": (C.c_int, [_vp, _vp, _u32, _vp, _vp]),
     "unihenn_encode": (C.c_int, [_vp, _P(_d), _u32, _d, _u32, C.c_int, _vp, _vp]),
     "unihenn_import_pt": (C.c_int, [_vp, _vp, _u32, C.c_int, _vp, _vp]),
@@ -98,6 +100,7 @@ SIGNATURES = {
     "unihenn_net_stages": (C.c_int, [_vp, _P(_u32)]),
     "unihenn_eval_stage": (C.c_int, [_vp, _vp, _u32, _u32, _u32, _P(CT), _P(CT), _vp]),
     "unihenn_net_memory": (C.c_int, [_vp, _P(_sz), _P(_sz)]),
+    "unihenn_workspace_size": (C.c_int, [_vp, _vp, _u32, _P(_sz)]),
     "unihenn_autotune": (C.c_int, [_vp, _vp, _u32, C.c_char_p, _P(TUNING), _vp]),
     "unihenn_tuning_get": (C.c_int, [_vp, _vp, _P(TUNING)]),
     "unihenn_tuning_set": (C.c_int, [_vp, _vp, _P(TUNING)]),
@@ -236,18 +239,24 @@ class Context:
         _check(lib().unihenn_from_ntt(self.h, t.data_ptr(), n_limbs, n_polys, _stream(stream)))
 
     def import_ct(self, coeff: np.ndarray, scale: float) -> Ciphertext:
-        """coeff: uint64 [batch][2][n_limbs][N] or [2][n_limbs][N] (coefficient form)."""
+        """unihenn_import_ct from host memory; coeff: uint64 [batch][2][n_limbs][N]
+        or [2][n_limbs][N] (coefficient form)."""
         if coeff.ndim == 3:
             coeff = coeff[None]
-        t = device_u64(coeff)
-        self.to_ntt(t, coeff.shape[2], coeff.shape[0] * 2)
-        return Ciphertext(t, scale)
+        coeff = np.ascontiguousarray(coeff, dtype=np.uint64)
+        ct = Ciphertext(torch.empty(coeff.shape, dtype=torch.int64, device="cuda"), scale)
+        d = ct.desc()
+        _check(lib().unihenn_import_ct(self.h, coeff.ctypes.data, C.byref(d), _stream()))
+        torch.cuda.current_stream().synchronize()  # the host buffer is read by the copy
+        return ct
 
     def export_ct(self, ct: Ciphertext) -> np.ndarray:
-        t = ct.data.clone()
-        self.from_ntt(t, ct.n_limbs, ct.batch * 2)
+        """unihenn_export_ct into a device buffer, returned as uint64 host array."""
+        out = torch.empty_like(ct.data)
+        d = ct.desc()
+        _check(lib().unihenn_export_ct(self.h, C.byref(d), out.data_ptr(), _stream()))
         torch.cuda.synchronize()
-        return host_u64(t)
+        return host_u64(out)
 
     def import_evk(self, coeff: np.ndarray) -> torch.Tensor:
         t = device_u64(coeff)
@@ -569,6 +578,13 @@ class Net:
         f, p = C.c_size_t(), C.c_size_t()
         _check(lib().unihenn_net_memory(self.h, C.byref(f), C.byref(p)))
         return f.value, p.value
+
+    def workspace_size(self, batch: int | None = None) -> int:
+        """unihenn_workspace_size: bytes of the workspace the net evaluates in."""
+        b = C.c_size_t()
+        _check(lib().unihenn_workspace_size(self.ctx.h, self.h, self.max_batch if batch is None else batch,
+                                            C.byref(b)))
+        return b.value
 
     def eval_stage(self, stage: int, slot: int, batch: int, ct=None, outs: list[Ciphertext] | None = None,
                    stream=None):

@@ -147,6 +147,35 @@ extern "C" int unihenn_from_ntt(const unihenn_ctx* c, uint64_t* data, uint32_t n
     return UNIHENN_OK;
 }
 
+extern "C" int unihenn_import_ct(const unihenn_ctx* c, const uint64_t* coeff, unihenn_ct* dst, void* stream)
+{
+    if (!c || !coeff || !dst || !dst->data) return uh_fail(UNIHENN_EINVAL, "null argument");
+    if (dst->n_limbs < 1 || (int)dst->n_limbs > c->n_data) return uh_fail(UNIHENN_EINVAL, "bad limb count");
+    if (dst->batch < 1) return uh_fail(UNIHENN_EINVAL, "empty batch");
+    hipStream_t s = (hipStream_t)stream;
+    const uint32_t polys = 2 * dst->batch;
+    if (coeff != dst->data)
+        UH_CHECK_HIP(hipMemcpyAsync(dst->data, coeff, sizeof(u64) * polys * dst->n_limbs * c->n, hipMemcpyDefault, s));
+    launch_ntt_fwd(c, dst->data, (int)(dst->n_limbs * polys), rowmap_ct((int)dst->n_limbs), s);
+    UH_LAUNCH_CHECK();
+    return UNIHENN_OK;
+}
+
+extern "C" int unihenn_export_ct(const unihenn_ctx* c, const unihenn_ct* src, uint64_t* coeff, void* stream)
+{
+    if (!c || !src || !src->data || !coeff) return uh_fail(UNIHENN_EINVAL, "null argument");
+    if (src->n_limbs < 1 || (int)src->n_limbs > c->n_data) return uh_fail(UNIHENN_EINVAL, "bad limb count");
+    if (src->batch < 1) return uh_fail(UNIHENN_EINVAL, "empty batch");
+    hipStream_t s = (hipStream_t)stream;
+    const uint32_t polys = 2 * src->batch;
+    if (coeff != src->data)
+        UH_CHECK_HIP(hipMemcpyAsync(coeff, src->data, sizeof(u64) * polys * src->n_limbs * c->n,
+                                    hipMemcpyDeviceToDevice, s));
+    launch_ntt_inv(c, coeff, (int)(src->n_limbs * polys), rowmap_ct((int)src->n_limbs), s);
+    UH_LAUNCH_CHECK();
+    return UNIHENN_OK;
+}
+
 extern "C" int unihenn_import_evk(const unihenn_ctx* c, const uint64_t* coeff, uint32_t n_data, uint64_t* out,
                                   void* stream)
 {

@@ -1884,6 +1884,15 @@ extern "C" int unihenn_net_memory(const unihenn_net* net, size_t* fixed_bytes, s
     return UNIHENN_OK;
 }
 
+extern "C" int unihenn_workspace_size(const unihenn_ctx* c, const unihenn_net* net, uint32_t batch, size_t* bytes)
+{
+    if (!c || !net || !bytes) return uh_fail(UNIHENN_EINVAL, "null argument");
+    if (net->ctx != c) return uh_fail(UNIHENN_EINVAL, "net made for another context");
+    if (batch < 1 || (int)batch > net->max_batch) return uh_fail(UNIHENN_EINVAL, "batch outside 1..max_batch");
+    *bytes = sizeof(u64) * net->ws_words;
+    return UNIHENN_OK;
+}
+
 extern "C" int unihenn_eval_stage(const unihenn_ctx* c, unihenn_net* net, uint32_t stage, uint32_t slot,
                                   uint32_t batch, const unihenn_ct* in, unihenn_ct* out, void* stream)
 {

@@ -242,3 +242,60 @@ def test_largest_ring_rotation():
         key = P.gen_switch_key(ctx, sk, 96, steps=r)
         got = P.decrypt_slots(ctx, sk, ctx.rotate(ct, r, key, ws), probe)[0]
         assert np.abs(got - np.roll(z, -r)[probe]).max() < 1e-6, r
+
+
+def test_import_export_ct_entry_points(pair):
+    """unihenn_import_ct / unihenn_export_ct: from host and device memory,
+    out of place and in place, equal the in-place transforms and invert each
+    other; bad descriptors are EINVAL with the destination untouched."""
+    import ctypes as C
+    import torch
+    import paper_2402_03060_amd as P
+    from paper_2402_03060_amd import device_u64, host_u64
+    ck, ctx, ring = pair
+    rng = np.random.default_rng(321)
+    nl = len(ctx.primes) - 1
+    a = np.stack([np.stack([np.stack([rng.integers(0, q, ctx.n, dtype=np.uint64) for q in ctx.primes[:nl]])
+                            for _ in range(2)]) for _ in range(3)])
+    ref = device_u64(a)
+    ctx.to_ntt(ref, nl, 6)
+    ct = ctx.import_ct(a, 1.0)                       # host source, out of place
+    assert torch.equal(ct.data, ref)
+    dev = device_u64(a)
+    ct2 = P.Ciphertext(torch.empty_like(dev), 1.0)
+    d2 = ct2.desc()
+    P._check(P.lib().unihenn_import_ct(ctx.h, dev.data_ptr(), C.byref(d2), P._stream()))   # device source
+    d3 = P.Ciphertext(dev, 1.0).desc()
+    P._check(P.lib().unihenn_import_ct(ctx.h, dev.data_ptr(), C.byref(d3), P._stream()))   # in place
+    torch.cuda.synchronize()
+    assert torch.equal(ct2.data, ref) and torch.equal(dev, ref)
+    assert np.array_equal(ctx.export_ct(ct), a)
+    P._check(P.lib().unihenn_export_ct(ctx.h, C.byref(d3), dev.data_ptr(), P._stream()))  # in place
+    torch.cuda.synchronize()
+    assert np.array_equal(host_u64(dev), a)
+    bad = P.Ciphertext(torch.full_like(dev, 7), 1.0)
+    db = bad.desc()
+    db.n_limbs = len(ctx.primes) + 3
+    assert P.lib().unihenn_import_ct(ctx.h, ref.data_ptr(), C.byref(db), P._stream()) == P.EINVAL
+    db = bad.desc()
+    db.batch = 0
+    assert P.lib().unihenn_export_ct(ctx.h, C.byref(db), ref.data_ptr(), P._stream()) == P.EINVAL
+    torch.cuda.synchronize()
+    assert bool((bad.data == 7).all())
+
+
+def test_workspace_size_entry_point():
+    import ctypes as C
+    import workloads as W
+    import paper_2402_03060_amd as P
+    cfg = W.config("conv1")
+    cfg["log_n"] = 11
+    ctx = P.Context(cfg["log_n"], cfg["prime_bits"], cfg["special_bits"], 2.0 ** cfg["log_scale"])
+    net = P.Net(ctx, cfg["input"], cfg["layers"], W.gen_params(cfg["layers"]), max_batch=3)
+    w = net.workspace_size()
+    assert w > 0 and w == net.workspace_size(1)
+    fixed, per_slot = net.memory()
+    assert per_slot * 3 >= w                          # the slots' shares cover the workspace
+    b = C.c_size_t(0)
+    assert P.lib().unihenn_workspace_size(ctx.h, net.h, 4, C.byref(b)) == P.EINVAL
+    assert P.lib().unihenn_workspace_size(ctx.h, net.h, 0, C.byref(b)) == P.EINVAL
