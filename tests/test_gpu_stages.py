@@ -84,3 +84,40 @@ def test_stage_arguments_checked():
     assert ei.value.code == P.EINVAL
     fixed, per_slot = net.memory()
     assert fixed > 0 and per_slot > 0
+
+
+def test_stage_graph_cache_replacement():
+    """More (stage, slot range, size) graphs than the net keeps (256): the
+    least recently used are replaced (after the device drains) and every
+    result still equals the eager stages'."""
+    import torch
+    import paper_2402_03060_amd as P
+    ctx, net, gin, _ = _setup("conv1", 11, 1)
+    cfg = W.config("conv1")
+    cfg["log_n"] = 11
+    slots = 17
+    big = P.Net(ctx, cfg["input"], cfg["layers"], W.gen_params(cfg["layers"]), max_batch=slots)
+    big.bind_keys(*net._bound)
+    ns = big.stages()
+    combos = [(a, n) for n in range(1, slots + 1) for a in range(0, slots - n + 1)]
+    assert len(combos) * ns > 256
+    src = P.Ciphertext(gin.data.repeat(slots, 1, 1, 1).contiguous(), gin.scale)
+
+    def run_all(mode):
+        big.set_mode(mode)
+        res = []
+        for a, n in combos:
+            outs = big.alloc_outputs(n)
+            for k in range(ns):
+                big.eval_stage(k, a, n, ct=P.Ciphertext(src.data[a:a + n], src.scale) if k == 0 else None,
+                               outs=outs if k == ns - 1 else None)
+            res.append([o.data.clone() for o in outs])
+        torch.cuda.synchronize()
+        return res
+
+    eager = run_all(P.EVAL_HOISTED)
+    graph = run_all(P.EVAL_HOISTED | P.EVAL_GRAPH)
+    graph2 = run_all(P.EVAL_HOISTED | P.EVAL_GRAPH)    # replays after replacement
+    for e, g, g2 in zip(eager, graph, graph2):
+        for x, y, z in zip(e, g, g2):
+            assert torch.equal(x, y) and torch.equal(x, z)
