@@ -97,21 +97,35 @@ __global__ void __launch_bounds__(EW_THREADS) k_ks_inner(u64* __restrict__ U, u6
             k1[j] = key[(((size_t)j * 2 + 1) * (nd + 1) + klimb) * n + k];
         }
     }
+    // entry b + 1's digits load while entry b's products run
+    u64 dn[MAXL];
+    auto fetch = [&](int b) {
+#pragma unroll
+        for (int j = 0; j < MAXL; ++j) {
+            if (j < nl) {
+                if (t == j) {
+                    dn[j] = dntt[((size_t)b * d_stride + j) * n + src];
+                } else {
+                    const int s = t < j ? t : t - 1;
+                    dn[j] = modup[(((size_t)b * nl + j) * nl + s) * n + src];
+                }
+            }
+        }
+    };
+    if (b_lo < b_hi) fetch(b_lo);
     for (int b = b_lo; b < b_hi; ++b) {
         WideAcc a0, a1;
         wide_init(a0, 0);
         wide_init(a1, 0);
         int since = 0;
+        u64 dc[MAXL];
+#pragma unroll
+        for (int j = 0; j < MAXL; ++j) dc[j] = dn[j];
+        if (b + 1 < b_hi) fetch(b + 1);
 #pragma unroll
         for (int j = 0; j < MAXL; ++j) {
             if (j < nl) {
-                u64 d;
-                if (t == j) {
-                    d = dntt[((size_t)b * d_stride + j) * n + src];
-                } else {
-                    const int s = t < j ? t : t - 1;
-                    d = modup[(((size_t)b * nl + j) * nl + s) * n + src];
-                }
+                const u64 d = dc[j];
                 wide_mac(a0, d, k0[j]);
                 wide_mac(a1, d, k1[j]);
                 if (++since == period) {
@@ -505,21 +519,36 @@ __global__ void __launch_bounds__(EW_THREADS) k_group_inner(u64* __restrict__ U,
             k1[j] = key[(((size_t)j * 2 + 1) * (nd + 1) + klimb) * n + k];
         }
     }
+    // the digits of batch entry b + 1 are loaded while entry b's products
+    // run, so their latency overlaps the arithmetic
+    u64 dn[MAXL];
+    auto fetch = [&](int b) {
+#pragma unroll
+        for (int j = 0; j < MAXL; ++j) {
+            if (j < nl) {
+                if (t == j) {
+                    dn[j] = dsrc[((size_t)b * ga.dstride + j) * n + srcd];
+                } else {
+                    const int s = t < j ? t : t - 1;
+                    dn[j] = modup[((((size_t)blk * batch + b) * nl + j) * nl + s) * n + src];
+                }
+            }
+        }
+    };
+    if (b_lo < b_hi) fetch(b_lo);
     for (int b = b_lo; b < b_hi; ++b) {
         WideAcc a0, a1;
         wide_init(a0, 0);
         wide_init(a1, 0);
         int since = 0;
+        u64 dc[MAXL];
+#pragma unroll
+        for (int j = 0; j < MAXL; ++j) dc[j] = dn[j];
+        if (b + 1 < b_hi) fetch(b + 1);
 #pragma unroll
         for (int j = 0; j < MAXL; ++j) {
             if (j < nl) {
-                u64 d;
-                if (t == j) {
-                    d = dsrc[((size_t)b * ga.dstride + j) * n + srcd];
-                } else {
-                    const int s = t < j ? t : t - 1;
-                    d = modup[((((size_t)blk * batch + b) * nl + j) * nl + s) * n + src];
-                }
+                const u64 d = dc[j];
                 wide_mac(a0, d, k0[j]);
                 wide_mac(a1, d, k1[j]);
                 if (++since == period) {
