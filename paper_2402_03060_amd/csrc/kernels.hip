@@ -209,16 +209,27 @@ __global__ void __launch_bounds__(EW_THREADS) k_mac(u64* __restrict__ acc, MacTe
         const int b = b0 + u / 2, c = u & 1;
         wide_init(a[u], (accumulate && b < batch) ? acc[(((size_t)b * 2 + c) * nl + i) * n + k] : 0);
     }
-    int since = 0;
-    for (int t = 0; t < n_terms; ++t) {
-        const u64 p = terms.pt[t][(size_t)i * n + k];
+    // term t + 1's words load while term t's products run
+    u64 pn = 0, vn[2 * BCH];
+    auto fetch = [&](int t) {
+        pn = terms.pt[t][(size_t)i * n + k];
         const u64* ct = terms.ct[t];
 #pragma unroll
         for (int u = 0; u < 2 * BCH; ++u) {
             const int b = b0 + u / 2, c = u & 1;
-            const u64 v = b < batch ? ct[(((size_t)b * 2 + c) * nl + i) * n + k] : 0;
-            wide_mac(a[u], p, v);
+            vn[u] = b < batch ? ct[(((size_t)b * 2 + c) * nl + i) * n + k] : 0;
         }
+    };
+    if (n_terms > 0) fetch(0);
+    int since = 0;
+    for (int t = 0; t < n_terms; ++t) {
+        const u64 p = pn;
+        u64 v[2 * BCH];
+#pragma unroll
+        for (int u = 0; u < 2 * BCH; ++u) v[u] = vn[u];
+        if (t + 1 < n_terms) fetch(t + 1);
+#pragma unroll
+        for (int u = 0; u < 2 * BCH; ++u) wide_mac(a[u], p, v[u]);
         if (++since == period) {
 #pragma unroll
             for (int u = 0; u < 2 * BCH; ++u) wide_fold(a[u], M.q, M.qinv_neg);
@@ -911,7 +922,14 @@ __global__ void k_group_sum(SumGroup g, DevCtx ctx, int nl, int accumulate, int 
     const u64 q = ctx.mod[i == pl ? ctx.p_index : i].q;
     const size_t o = r * n + k;
     u64 v = accumulate ? g.out[e][o] : 0;
-    for (int t = 0; t < g.T; ++t) v = add_mod(v, g.in[e * g.T + t][o], q);
+    // four independent loads per step, not one load per dependent addition
+    int t = 0;
+    for (; t + 4 <= g.T; t += 4) {
+        const u64 x0 = g.in[e * g.T + t][o], x1 = g.in[e * g.T + t + 1][o];
+        const u64 x2 = g.in[e * g.T + t + 2][o], x3 = g.in[e * g.T + t + 3][o];
+        v = add_mod(add_mod(v, x0, q), add_mod(x1, add_mod(x2, x3, q), q), q);
+    }
+    for (; t < g.T; ++t) v = add_mod(v, g.in[e * g.T + t][o], q);
     g.out[e][o] = v;
 }
 
@@ -1016,15 +1034,27 @@ __global__ void __launch_bounds__(EW_THREADS) k_mac_group(MacGroup m, DevCtx ctx
     WideAcc a[2 * BCH];
 #pragma unroll
     for (int u = 0; u < 2 * BCH; ++u) wide_init(a[u], 0);
-    int since = 0;
-    for (int t = 0; t < m.T; ++t) {
-        const u64 p = m.pt[e * m.T + t][(size_t)i * n + k];
+    // term t + 1's words load while term t's products run
+    u64 pn = 0, vn[2 * BCH];
+    auto fetch = [&](int t) {
+        pn = m.pt[e * m.T + t][(size_t)i * n + k];
         const u64* ct = m.ct[e * m.T + t];
 #pragma unroll
         for (int u = 0; u < 2 * BCH; ++u) {
             const int b = b0 + u / 2, c = u & 1;
-            wide_mac(a[u], p, b < batch ? ct[(((size_t)b * 2 + c) * nl + i) * n + k] : 0);
+            vn[u] = b < batch ? ct[(((size_t)b * 2 + c) * nl + i) * n + k] : 0;
         }
+    };
+    if (m.T > 0) fetch(0);
+    int since = 0;
+    for (int t = 0; t < m.T; ++t) {
+        const u64 p = pn;
+        u64 v[2 * BCH];
+#pragma unroll
+        for (int u = 0; u < 2 * BCH; ++u) v[u] = vn[u];
+        if (t + 1 < m.T) fetch(t + 1);
+#pragma unroll
+        for (int u = 0; u < 2 * BCH; ++u) wide_mac(a[u], p, v[u]);
         if (++since == period) {
 #pragma unroll
             for (int u = 0; u < 2 * BCH; ++u) wide_fold(a[u], M.q, M.qinv_neg);
