@@ -98,7 +98,7 @@ __global__ void __launch_bounds__(EW_THREADS) k_ks_inner(u64* __restrict__ U, u6
         }
     }
     // entry b + 1's digits load while entry b's products run
-    u64 dn[MAXL];
+    u64 dn[MAXL] = {};
     auto fetch = [&](int b) {
 #pragma unroll
         for (int j = 0; j < MAXL; ++j) {
@@ -532,7 +532,7 @@ __global__ void __launch_bounds__(EW_THREADS) k_group_inner(u64* __restrict__ U,
     }
     // the digits of batch entry b + 1 are loaded while entry b's products
     // run, so their latency overlaps the arithmetic
-    u64 dn[MAXL];
+    u64 dn[MAXL] = {};
     auto fetch = [&](int b) {
 #pragma unroll
         for (int j = 0; j < MAXL; ++j) {
